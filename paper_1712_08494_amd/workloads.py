@@ -1,0 +1,200 @@
+"""Seeded synthetic workloads: parameter sets and initial fields.
+
+This module holds plain numbers and seeded random draws only.  It contains none of the
+arithmetic of the lattice method (no equilibrium, no force, no flux, no solver), so the
+HIP library and the CPU oracle can both be fed from it without sharing any of the
+method's code.  Fields are float64 arrays of shape (nz, ny, nx), x fastest.
+
+The workloads stand in for the paper's quasi-1D / quasi-2D boxes and its 3-D cube
+(Sec. III): cubic boxes with the same ingredients (binary Shan-Chen mixture, monovalent
+salt, permittivity contrast, charged walls or resolved charged spheres, applied field).
+The paper uses no public dataset.
+"""
+from dataclasses import dataclass, field, replace
+from typing import Optional, Tuple
+
+import numpy as np
+
+# Bjerrum length 1.3 lattice units (Sec. III D): eps = 1 / (4 pi l_B) with beta = e = 1.
+EPS_FLUID = 1.0 / (4.0 * np.pi * 1.3)
+
+
+@dataclass
+class EKConfig:
+    nx: int
+    ny: int
+    nz: int
+    walls_z: bool = False
+    precision: str = "fp64"          # "fp64" or "fp32" (populations as deviations)
+    tau: float = 1.0                 # Sec. III A
+    G: float = 3.6                   # fluid/fluid Shan-Chen coupling
+    rho0: float = 1.0                # pseudopotential reference density
+    D: float = 0.01                  # ion diffusivity, Sec. II C
+    beta: float = 1.0
+    dmu_plus: float = 0.0            # Gibbs transfer energies
+    dmu_minus: float = 0.0
+    drho_a: float = 1.0              # bulk rho^a difference between the phases
+    solvation_sign: float = 1.0      # +1: the printed discrete solvation flux
+    eps_a: float = EPS_FLUID
+    eps_b: float = EPS_FLUID
+    eps_p: float = EPS_FLUID / 8.0   # relative permittivities 10 / 80, Sec. III D
+    E_ext: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    body_accel: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    sigma_wall: Tuple[float, float] = (0.0, 0.0)
+    poisson_tol: float = 1e-10       # relative residual of the GPU solve
+    poisson_maxit: int = 20000
+    poisson_tol_oracle: float = 1e-12
+    poisson_maxit_oracle: int = 200000
+    subsample: int = 8               # sub-cells per axis for the solid fraction
+    move_particles: bool = True
+    particle_rho: float = 5.0        # Sec. II E
+    k_hertz: float = 1.0             # Sec. II E
+    eta: float = 1.0 / 6.0           # dynamic viscosity used by lubrication
+    name: str = "custom"
+
+    @property
+    def n_sites(self):
+        return self.nx * self.ny * self.nz
+
+
+@dataclass
+class EKInputs:
+    rho_a: np.ndarray
+    rho_b: np.ndarray
+    n_plus: np.ndarray
+    n_minus: np.ndarray
+    particles: Optional[np.ndarray] = None   # (n, 8): x, y, z, vx, vy, vz, radius, charge
+    extra: dict = field(default_factory=dict)
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _neutralise(n_plus, n_minus, extra_charge=0.0, mask=None):
+    """Rescale n- so that sum(n+) - sum(n-) + extra_charge = 0 in float64."""
+    if mask is None:
+        mask = np.ones_like(n_plus, dtype=bool)
+    tot_p = n_plus[mask].sum() + extra_charge
+    tot_m = n_minus[mask].sum()
+    n_minus = n_minus.copy()
+    n_minus[mask] *= tot_p / tot_m
+    return n_minus
+
+
+# ---------------------------------------------------------------------------------
+# Workload 1: small periodic mixture with noise (parity case).
+# ---------------------------------------------------------------------------------
+def mixture_noise(n=32, seed=1, precision="fp64", G=3.6, shape=None):
+    nx, ny, nz = shape if shape is not None else (n, n, n)
+    cfg = EKConfig(nx, ny, nz, precision=precision, G=G, poisson_tol=1e-10, name=f"mixture_noise_{nx}x{ny}x{nz}")
+    r = _rng(seed)
+    sh = (nz, ny, nx)
+    rho_a = 0.5 + r.uniform(-0.01, 0.01, sh)
+    rho_b = 0.5 + r.uniform(-0.01, 0.01, sh)
+    n_plus = 1e-3 + r.uniform(-1e-5, 1e-5, sh)
+    n_minus = 1e-3 + r.uniform(-1e-5, 1e-5, sh)
+    n_minus = _neutralise(n_plus, n_minus)
+    return cfg, EKInputs(rho_a, rho_b, n_plus, n_minus)
+
+
+# ---------------------------------------------------------------------------------
+# Workload 2: charged walls in z and a flat interface between the two fluids.
+# Phase densities come from a flat-interface calibration of the Shan-Chen mixture
+# (bulk densities of the majority and minority component at G = 5.0, total density
+# about 1.39); see the design notes.
+# ---------------------------------------------------------------------------------
+WALL_G = 5.0
+WALL_RHO_MAJ = 1.2589
+WALL_RHO_MIN = 0.1286
+
+
+def walls_interface(n=128, seed=2, precision="fp32", shape=None, salt=1e-3, sigma=-1e-3, eps_ratio=2.0,
+                    dmu=2.0, width=2.0):
+    nx, ny, nz = shape if shape is not None else (n, n, n)
+    zi = nz // 2
+    drho = WALL_RHO_MAJ - WALL_RHO_MIN
+    cfg = EKConfig(nx, ny, nz, walls_z=True, precision=precision, G=WALL_G, dmu_plus=dmu, dmu_minus=-dmu,
+                   drho_a=drho, eps_a=EPS_FLUID, eps_b=eps_ratio * EPS_FLUID, sigma_wall=(sigma, sigma),
+                   poisson_tol=1e-8, name=f"walls_interface_{nx}x{ny}x{nz}")
+    r = _rng(seed)
+    sh = (nz, ny, nx)
+    z = np.arange(nz, dtype=np.float64)[:, None, None]
+    # fluid a below the interface plane, fluid b above it
+    s = 0.5 * (1.0 + np.tanh((z - (zi - 0.5)) / width))
+    rho_a = WALL_RHO_MAJ + (WALL_RHO_MIN - WALL_RHO_MAJ) * s + 0.0 * np.zeros(sh)
+    rho_b = WALL_RHO_MIN + (WALL_RHO_MAJ - WALL_RHO_MIN) * s + 0.0 * np.zeros(sh)
+    rho_a = rho_a + r.uniform(-1e-4, 1e-4, sh)
+    rho_b = rho_b + r.uniform(-1e-4, 1e-4, sh)
+    n_plus = salt * (1.0 + r.uniform(-1e-3, 1e-3, sh))
+    n_minus = salt * (1.0 + r.uniform(-1e-3, 1e-3, sh))
+    fluid = np.ones(sh, dtype=bool)
+    fluid[0] = False
+    fluid[-1] = False
+    n_plus[~fluid] = 0.0
+    n_minus[~fluid] = 0.0
+    # counter-ions for the two charged walls, spread uniformly over the fluid
+    wall_charge = (sigma + sigma) * nx * ny
+    n_minus = _neutralise(n_plus, n_minus, extra_charge=wall_charge, mask=fluid)
+    return cfg, EKInputs(rho_a, rho_b, n_plus, n_minus)
+
+
+# ---------------------------------------------------------------------------------
+# Workload 3: resolved charged spheres in a periodic binary mixture under a field.
+# ---------------------------------------------------------------------------------
+def place_spheres(rng, count, radius, shape, min_gap=2.0, max_tries=200000):
+    """Uniform random centres, rejection-sampled so that centre distances (minimum
+    image) are at least 2 r + min_gap."""
+    nx, ny, nz = shape
+    L = np.array([nx, ny, nz], dtype=np.float64)
+    centres = []
+    tries = 0
+    while len(centres) < count:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("could not place spheres")
+        c = rng.uniform(0.0, 1.0, 3) * L
+        ok = True
+        for o in centres:
+            d = c - o
+            d -= L * np.round(d / L)
+            if np.dot(d, d) < (2 * radius + min_gap) ** 2:
+                ok = False
+                break
+        if ok:
+            centres.append(c)
+    return np.array(centres)
+
+
+def colloids(n=256, seed=3, precision="fp32", count=200, radius=4.0, shape=None, salt=1e-3,
+             field=(1e-4, 0.0, 0.0), G=3.6):
+    nx, ny, nz = shape if shape is not None else (n, n, n)
+    cfg = EKConfig(nx, ny, nz, precision=precision, G=G, E_ext=tuple(field), poisson_tol=1e-8,
+                   name=f"colloids_{nx}x{ny}x{nz}_{count}")
+    r = _rng(seed)
+    sh = (nz, ny, nx)
+    centres = place_spheres(r, count, radius, (nx, ny, nz))
+    sigma = r.uniform(1e-3, 5e-3, count)
+    Q = 4.0 * np.pi * radius ** 2 * sigma
+    parts = np.zeros((count, 8))
+    parts[:, 0:3] = centres
+    parts[:, 6] = radius
+    parts[:, 7] = Q
+    rho_a = 0.5 + r.uniform(-0.01, 0.01, sh)
+    rho_b = 0.5 + r.uniform(-0.01, 0.01, sh)
+    n_plus = salt * np.ones(sh)
+    n_minus = salt * np.ones(sh) + Q.sum() / float(nx * ny * nz)
+    return cfg, EKInputs(rho_a, rho_b, n_plus, n_minus, particles=parts)
+
+
+# ---------------------------------------------------------------------------------
+# Small deterministic fields used by the pins.
+# ---------------------------------------------------------------------------------
+def uniform(cfg, rho_a=0.5, rho_b=0.5, n_plus=1e-3, n_minus=1e-3):
+    sh = (cfg.nz, cfg.ny, cfg.nx)
+    return EKInputs(np.full(sh, float(rho_a)), np.full(sh, float(rho_b)), np.full(sh, float(n_plus)),
+                    np.full(sh, float(n_minus)))
+
+
+def with_precision(cfg, precision):
+    return replace(cfg, precision=precision)
