@@ -824,9 +824,12 @@ or_state* or_create(const or_params* prm, const double* rho_a, const double* rho
     build_geometry(s);
     /* initial populations f = f~(rho^s, 0) on fluid sites (Reading: fluid at rest) */
     double zero[3] = {0, 0, 0}, feq[OQ];
+    /* Reading: the given ion densities are per unit fluid volume; a site holds them in
+       proportion to its fluid fraction (Sec. II E: at equilibrium the amount of ions at
+       a site is proportional to psi_f), so fully solid sites start empty. */
     for (int64_t i = 0; i < N; ++i) {
-        s->n[0][i] = n_plus[i];
-        s->n[1][i] = n_minus[i];
+        s->n[0][i] = n_plus[i] * s->psif[i];
+        s->n[1][i] = n_minus[i] * s->psif[i];
         if (s->solid[i]) continue;
         const double* rr[2] = {rho_a, rho_b};
         for (int c = 0; c < 2; ++c) {
