@@ -1,0 +1,179 @@
+"""Benchmark of the coupled electrokinetic lattice step on one MI355X.
+
+One step = moments + charge/permittivity + variable-permittivity Poisson solve + total
+force + fused ion/force/collide/stream sweep (+ particles when present), i.e. the whole
+per-timestep sweep of the method.  Default workload: 128^3 lattice with charged walls in
+z and a flat interface between the two fluids (permittivity ratio 2, solvation
+contrast +-2 kT, salt 1e-3), FP32 populations; inputs are seeded synthetic fields.
+
+Prints one JSON line.  Value = lattice-site updates per second (MLUPS) of the whole step
+with all state resident in HBM.  The "roofline" object rates the dominant kernel: its
+algorithmic bytes per launch (per-site compulsory traffic x sites) over its mean launch
+time measured with HIP events on the library's stream.  "cpu_baseline" times the FP64
+CPU oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "coupled-step MLUPS + % HBM roofline; FP32/FP64 speedup at stated error; bwd/fwd ratio"
+
+# Algorithmic (compulsory) bytes per site for one launch of each kernel class; see
+# DESIGN.md "Kernels and their rooflines".  s = bytes of a population / ion value.
+def algorithmic_bytes(kernel, s, colloids=False):
+    if kernel == "fused":
+        # populations read + write (2 x 19 x 2 x s), ions read + write (2 x 2 x s), phi read (8)
+        return 2 * 19 * 2 * s + 2 * 2 * s + 8
+    if kernel == "force":
+        # rho_a, rho_b, psi_a, psi_b, u(3) and ions (2) read, physical velocity (3) written, phi read
+        return 7 * s + 2 * s + 3 * s + 8
+    if kernel == "moments":
+        # populations read (2 x 19 x s), ions read (2 s), moments written (7 s), q and eps written (2 s)
+        return 2 * 19 * s + 2 * s + 7 * s + 2 * s
+    if kernel == "sor":
+        # one colour pass: phi read (8) + half the sites' phi written (4) + eps read (s) + half q read (s/2)
+        return 8 + 4 + s + s / 2
+    raise KeyError(kernel)
+
+
+def build_workload(name, precision, n):
+    from paper_1712_08494_amd import workloads as wl
+    if name == "walls_interface":
+        return wl.walls_interface(n=n, precision=precision)
+    if name == "colloids":
+        return wl.colloids(n=n, precision=precision)
+    if name == "mixture_noise":
+        return wl.mixture_noise(n=n, precision=precision)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def run_gpu(cfg, inp, steps, warmup):
+    import torch
+    from paper_1712_08494_amd import ek
+    sim = ek.EKSim(cfg, inp)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    ob0 = sim.observables()
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = sim.timing()
+    ob1 = sim.observables()
+    sim.close()
+    return t1 - t0, timing, ob0, ob1
+
+
+def cpu_baseline(cfg, inp, target_s=20.0):
+    from oracle import oracle as orc
+    o = orc.Oracle(cfg, inp)
+    threads = orc.num_threads()
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter()
+    steps = 1
+    per = t1 - t0
+    extra = int(max(0, min(20, target_s / max(per, 1e-6) - 1)))
+    if extra:
+        t2 = time.perf_counter()
+        o.step(extra)
+        t3 = time.perf_counter()
+        steps = extra
+        per = (t3 - t2) / extra
+    o.close()
+    return {"value": cfg.n_sites / per / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} step(s) of the same {cfg.nx}x{cfg.ny}x{cfg.nz} workload after one untimed-for-"
+                      f"value step, FP64, {threads} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="walls_interface")
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run used for the FP32/FP64 speedup")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design note, not an implemented path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+
+    cfg, inp = build_workload(args.workload, args.precision, args.n)
+    dt, timing, ob0, ob1 = run_gpu(cfg, inp, args.steps, args.warmup)
+    N = cfg.n_sites
+    mlups = N * args.steps / dt / 1e6
+    s = 4 if args.precision == "fp32" else 8
+    colloids = inp.particles is not None
+
+    # dominant kernel by summed device time
+    cands = {k: timing[k] for k in ("fused", "force", "moments", "sor")}
+    dom = max(cands, key=lambda k: cands[k][0])
+    ms, count = cands[dom]
+    avg_s = ms / 1e3 / max(count, 1)
+    bytes_launch = algorithmic_bytes(dom, s, colloids) * N
+    achieved = bytes_launch / avg_s / 1e9
+    kernel_table = {}
+    for k in ("moments", "poisson", "sor", "force", "fused", "particle"):
+        tms, cnt = timing[k]
+        kernel_table[k] = {"ms_total": round(tms, 3), "launches": int(cnt),
+                           "us_per_launch": round(1e3 * tms / cnt, 3) if cnt else None}
+    sweeps = (ob1["poisson_total"] - ob0["poisson_total"]) / args.steps
+
+    fp64 = None
+    if not args.no_fp64 and args.precision == "fp32":
+        cfg64, inp64 = build_workload(args.workload, "fp64", args.n)
+        dt64, _, _, _ = run_gpu(cfg64, inp64, max(10, args.steps // 2), args.warmup)
+        fp64 = N * max(10, args.steps // 2) / dt64 / 1e6
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, inp, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz}", "sites": N,
+                   "precision": args.precision, "poisson_tol": cfg.poisson_tol,
+                   "poisson_sweeps_per_step": round(sweeps, 2)},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_site": algorithmic_bytes(dom, s, colloids),
+                     "us_per_launch": round(avg_s * 1e6, 3)},
+        "kernels": kernel_table,
+        "fp64_mlups": round(fp64, 2) if fp64 else None,
+        "fp32_fp64_speedup": round(mlups / fp64, 3) if fp64 else None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * ek.h — C ABI of the MI355X (gfx950) coupled electrokinetic lattice library.
+ *
+ * The library advances the coupled lattice method of Rivas, Frijters, Pagonabarraga
+ * and Harting, "Mesoscopic electrohydrodynamic simulations of binary colloidal
+ * suspensions" (arXiv:1712.08494), Sec. II:
+ *   - two fluid components a, b on a D3Q19 lattice with BGK collision and the
+ *     Shan-Chen velocity-shift forcing (Sec. II A, eq. BoltzmannBGKLattice);
+ *   - two monovalent ion species by the link-flux Nernst-Planck scheme on the six
+ *     D3Q7 links (Sec. II B, eq. nernst-planck-disc; Sec. II E, eq. ionic-fluxes-disc-2);
+ *   - Shan-Chen fluid/fluid and solvation couplings, ion friction and the Kelvin
+ *     force (Sec. II C, eqs. shanChenForce, frictionforce, kelvin);
+ *   - the variable-permittivity Poisson equation (Sec. II D, eq. electric_potential);
+ *   - resolved rigid spheres: halfway bounce-back, momentum exchange, solid fraction,
+ *     distributed charge and permittivity (Sec. II E).
+ *
+ * Conventions for every call:
+ *   - Lattice sites are indexed x fastest: i = x + nx * (y + ny * z).
+ *   - Host arrays are double precision; they are borrowed for the duration of the
+ *     call only and never retained.
+ *   - Device memory of a context is allocated by ek_init and released by ek_destroy.
+ *   - All work of a context is enqueued on the HIP stream given to ek_init (which may
+ *     be a stream owned by the caller, e.g. PyTorch's current stream).
+ *   - Calls return an ek_status; no exception or signal crosses the ABI.  On error,
+ *     ek_last_error(ctx) holds a message.  A context is not thread safe; one context
+ *     must not be used from two threads at once.
+ */
+#ifndef EK_H
+#define EK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ek_status;
+#define EK_OK 0
+#define EK_EINVAL (-1)     /* invalid argument or parameter */
+#define EK_ENOMEM (-2)     /* device or host allocation failed */
+#define EK_EHIP (-3)       /* a HIP runtime call failed */
+#define EK_ENOCONV (-4)    /* Poisson solve stopped at maxit above the tolerance */
+#define EK_ENONFINITE (-5) /* a NaN or Inf was found by ek_observables */
+#define EK_ESTATE (-6)     /* call not valid in the context's current state */
+
+#define EK_FP64 0 /* populations, ions, charge and permittivity in double */
+#define EK_FP32 1 /* populations as float deviations from w_d rho_ref, ions in float; phi stays double */
+
+typedef struct ek_params {
+    int32_t nx, ny, nz;         /* lattice size; nx must be even (red-black ordering) */
+    int32_t walls_z;            /* 0: periodic in z; 1: solid charged walls at z = 0 and z = nz-1 */
+    int32_t precision;          /* EK_FP64 or EK_FP32 */
+    int32_t poisson_maxit;      /* maximum Poisson sweeps per solve */
+    int32_t subsample;          /* sub-cells per axis for the particle solid fraction (e.g. 8) */
+    int32_t move_particles;     /* 1: integrate particle motion every step */
+    double tau;                 /* BGK relaxation time of both fluids (> 1/2) */
+    double G;                   /* fluid/fluid Shan-Chen coupling G_ab */
+    double rho0;                /* pseudopotential reference density: psi = rho0 (1 - exp(-rho/rho0)) */
+    double rho_ref[2];          /* FP32 deviation reference densities of a, b; <= 0: initial fluid mean */
+    double D;                   /* ion diffusivity (both species) */
+    double beta;                /* 1 / k_B T */
+    double dmu[2];              /* Gibbs transfer energies of the cation and the anion */
+    double drho_a;              /* bulk difference of rho^a between the phases (solvation scale) */
+    double solvation_sign;      /* +1: the printed discrete solvation flux; -1 flips flux and coupling together */
+    double eps_a, eps_b, eps_p; /* permittivities of fluid a, fluid b and the particles */
+    double E_ext[3];            /* uniform external field */
+    double body_accel[3];       /* uniform body acceleration g (force density rho g) */
+    double sigma_wall[2];       /* surface charge density of the z = 0 and z = nz-1 walls */
+    double poisson_tol;         /* relative residual ||r||_2 <= tol ||s||_2 of the Poisson solve */
+    double sor_omega;           /* over-relaxation factor; <= 0: chosen from the lattice size */
+    double particle_rho;        /* particle mass density (mass = rho_p 4/3 pi r^3) */
+    double k_hertz;             /* Hertz contact stiffness */
+    double eta;                 /* dynamic viscosity used by the lubrication force */
+} ek_params;
+
+typedef struct ek_particle {
+    double x[3];   /* centre (lattice units, site centres at integers) */
+    double v[3];   /* velocity */
+    double radius; /* sphere radius */
+    double charge; /* total charge Q, spread over the covered sites by solid fraction */
+} ek_particle;
+
+typedef struct ek_obs {
+    double sum_rho[2];     /* total mass of a and b over fluid sites */
+    double sum_n[2];       /* total cations, anions over all sites */
+    double sum_q;          /* total charge (ions + particles) */
+    double momentum[3];    /* total fluid momentum sum_d f_d c_d (pre-collision) */
+    double max_u;          /* max |u| of the pre-force barycentric velocity */
+    double source_mean;    /* mean removed from the Poisson source by the last solve */
+    double poisson_rel;    /* relative residual reached by the last solve */
+    int64_t poisson_iters; /* sweeps of the last solve */
+    int64_t poisson_total; /* sweeps summed over all solves since ek_init */
+    int64_t steps;         /* steps taken since ek_init */
+    double drift[3];       /* mean particle displacement since ek_init */
+    double pmomentum[3];   /* total particle momentum */
+    int32_t nonfinite;     /* 1 if a NaN or Inf was found in the populations or ions */
+    int32_t negative_ions; /* number of sites with a negative ion density */
+} ek_obs;
+
+/* Kernel classes timed when timing is on (ek_set_timing). */
+#define EK_T_MOMENTS 0   /* moments, pseudopotentials, charge, permittivity, virtual densities */
+#define EK_T_POISSON 1   /* all Poisson sweeps, residuals and reductions of a solve */
+#define EK_T_FORCE 2     /* total force and physical velocity pass */
+#define EK_T_FUSED 3     /* fused ion update + force + collide + stream pass */
+#define EK_T_PARTICLE 4  /* particle force sums and integration */
+#define EK_T_SOR 5       /* the red-black sweep kernels alone (one entry per colour pass) */
+#define EK_T_COUNT 6
+
+typedef struct ek_timing {
+    double ms[EK_T_COUNT];    /* summed device time per class (HIP events) */
+    int64_t count[EK_T_COUNT];/* launches (or solves for EK_T_POISSON) per class */
+} ek_timing;
+
+/* Field ids for ek_get_field (one double per site, x fastest). */
+#define EK_F_RHO_A 0
+#define EK_F_RHO_B 1
+#define EK_F_N_PLUS 2
+#define EK_F_N_MINUS 3
+#define EK_F_PHI 4
+#define EK_F_UX 5     /* pre-force barycentric velocity */
+#define EK_F_UY 6
+#define EK_F_UZ 7
+#define EK_F_Q 8      /* charge density of the current state */
+#define EK_F_EPS 9    /* permittivity of the current state */
+#define EK_F_PSI_S 10 /* solid fraction */
+#define EK_F_SOLID 11 /* 1 on LB-solid sites */
+#define EK_F_EX 12    /* field E = -grad phi + E_ext of the current potential */
+#define EK_F_EY 13
+#define EK_F_EZ 14
+
+/* D3Q19 velocity set used by ek_get_populations: c[19][3] and weights w[19]
+   (Sec. II A, weights 1/3, 1/18, 1/36).  Returns 19. */
+int32_t ek_lattice(int32_t* c, double* w);
+
+/* Create a context and set up the initial state (Sec. II A-E):
+   - marks LB-solid sites (site centre strictly inside a sphere) and wall layers,
+     counts the solid fraction psi_s by sub-cell centres, spreads each particle's
+     charge in proportion to psi_s so that it sums to Q exactly, and builds the
+     bounce-back link lists;
+   - populations f = f~(rho^s, u = 0) on fluid sites;
+   - ion densities n+- = n_plus, n_minus scaled by the fluid fraction 1 - psi_s;
+   - the initial potential by a Poisson solve from zero.
+   rho_a, rho_b, n_plus, n_minus: host arrays of nx*ny*nz doubles (required).
+   parts: host array of n_parts particles (may be NULL when n_parts == 0).
+   stream: a hipStream_t (NULL for the null stream).
+   Errors: EK_EINVAL (bad sizes, tau <= 1/2, odd nx, non-positive fluid density,
+   overlapping particles), EK_ENOMEM, EK_EHIP, EK_ENOCONV (initial solve). */
+ek_status ek_init(const ek_params* p, const double* rho_a, const double* rho_b, const double* n_plus,
+                  const double* n_minus, const ek_particle* parts, int32_t n_parts, void* stream,
+                  struct ek_ctx** out);
+
+/* Advance nsteps full steps (moments, charge, Poisson, fluxes, forces, collide,
+   stream, particles).  Work is enqueued on the context's stream; the only host
+   synchronisation is the Poisson convergence test.  Returns EK_ENOCONV if any solve
+   stopped at maxit (the step is still taken with the last iterate). */
+ek_status ek_step(struct ek_ctx* ctx, int32_t nsteps);
+
+/* Solve the Poisson equation for the charge and permittivity of the current state
+   (Sec. II D): sum over the six links of eps_face (phi_j - phi_i) = -(q_i + wall
+   charge), eps_face the mean of the two sites, source projected to zero mean, gauge
+   mean(phi) = 0, red-black SOR from the current potential.  iters, rel_res may be
+   NULL.  Returns EK_ENOCONV if the tolerance was not met (phi keeps the last iterate). */
+ek_status ek_poisson(struct ek_ctx* ctx, double tol, int32_t maxit, int32_t* iters, double* rel_res);
+
+/* FP64 totals and diagnostics of the current state (synchronises the stream).
+   Returns EK_ENONFINITE if populations or ion densities hold a NaN or Inf. */
+ek_status ek_observables(struct ek_ctx* ctx, ek_obs* out);
+
+/* Copy one field of the current state to host memory (nx*ny*nz doubles). */
+ek_status ek_get_field(struct ek_ctx* ctx, int32_t field, double* host_out);
+
+/* Copy the populations of component comp (0 = a, 1 = b) to host memory as
+   19 * nx*ny*nz doubles, velocity-major in the order of ek_lattice.  FP32 contexts
+   return f = deviation + w_d rho_ref. */
+ek_status ek_get_populations(struct ek_ctx* ctx, int32_t comp, double* host_out);
+
+/* Copy the particles to host memory as n_parts x 9 doubles: x(3), v(3) and the
+   force F(3) of the last step. */
+ek_status ek_get_particles(struct ek_ctx* ctx, double* host_out);
+
+/* Device bytes held by the context. */
+ek_status ek_device_bytes(const struct ek_ctx* ctx, size_t* bytes);
+
+/* Turn per-kernel-class HIP event timing on (1) or off (0); turning it on clears
+   the accumulated times. */
+ek_status ek_set_timing(struct ek_ctx* ctx, int32_t enable);
+
+/* Accumulated times since timing was turned on (synchronises the stream). */
+ek_status ek_get_timing(struct ek_ctx* ctx, ek_timing* out);
+
+/* Release the context and its device memory (synchronises the stream). */
+ek_status ek_destroy(struct ek_ctx* ctx);
+
+const char* ek_status_str(ek_status s);
+const char* ek_last_error(const struct ek_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EK_H */

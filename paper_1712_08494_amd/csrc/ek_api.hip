@@ -1,0 +1,895 @@
+// Host runtime of the coupled electrokinetic lattice library: context set-up (geometry,
+// device memory, initial state), the step loop, the Poisson convergence control and the
+// export calls of include/ek.h.  All per-step arithmetic runs in the kernels of
+// ek_kernels.hip; the host only orders launches and reads back scalars.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ek.h"
+#include "ek_internal.h"
+#include "ek_lattice.h"
+
+using namespace ek;
+
+namespace ek {
+template <typename T>
+void launch_init_pop_flags(const Scalars& S, T* f, const double* rho, double rref, const uint8_t* flags, hipStream_t st);
+}
+
+struct TimeRec {
+    hipEvent_t a, b;
+    int cls;
+    int count;
+};
+
+struct ek_ctx {
+    ek_params p{};
+    hipStream_t st = nullptr;
+    std::string err;
+    Scalars S{};
+    unsigned N = 0, nblk = 0;
+    size_t esz = 8;
+    std::vector<void*> allocs;
+    size_t bytes = 0;
+    // fields
+    void* f[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [buffer][component]
+    void* n[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [buffer][species]
+    void* mom = nullptr;
+    void* uph = nullptr;
+    void* q = nullptr;
+    void* eps = nullptr;
+    double* phi = nullptr;
+    int cur = 0;
+    // geometry
+    uint8_t* flags = nullptr;
+    void* psif = nullptr;
+    void* qc = nullptr;
+    int32_t* owner = nullptr;
+    int32_t* linkbase = nullptr;
+    double* linkdp = nullptr;
+    int32_t* vlist = nullptr;
+    int nv = 0;
+    long long nlinks = 0;
+    std::vector<uint8_t> hflags;   // host copy (solid marks for export)
+    std::vector<double> hpsis;     // host copy of the solid fraction
+    // particles
+    int np = 0;
+    double* px[2] = {nullptr, nullptr};
+    double* pv[2] = {nullptr, nullptr};
+    double* prad = nullptr;
+    double* pF = nullptr;
+    int pcur = 0;
+    int32_t *plink_off = nullptr, *plink_idx = nullptr, *psite_off = nullptr, *psite_idx = nullptr;
+    std::vector<double> px0, hrad;
+    // scratch
+    double* red = nullptr;
+    double* scal = nullptr;
+    double* hscal = nullptr;  // pinned
+    int* obs_max = nullptr;
+    double* stage = nullptr;
+    // bookkeeping
+    long long steps = 0, ptotal = 0;
+    int last_iters = 0;
+    double last_rel = 0.0, last_mean = 0.0;
+    double omega = 1.0;
+    double rate = -1.0;
+    // timing
+    bool timing = false;
+    std::vector<TimeRec> recs;
+    std::vector<hipEvent_t> pool;
+    double tms[EK_T_COUNT] = {0};
+    long long tcnt[EK_T_COUNT] = {0};
+};
+
+#define EK_HIP(call)                                                                             \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) {                                                                  \
+            c->err = std::string(#call) + ": " + hipGetErrorString(e_);                          \
+            return EK_EHIP;                                                                      \
+        }                                                                                        \
+    } while (0)
+
+static ek_status fail(ek_ctx* c, ek_status s, const std::string& msg) {
+    c->err = msg;
+    return s;
+}
+
+static ek_status dalloc(ek_ctx* c, void** ptr, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        c->err = "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e);
+        return EK_ENOMEM;
+    }
+    c->allocs.push_back(*ptr);
+    c->bytes += bytes;
+    return EK_OK;
+}
+
+#define EK_TRY(x)                   \
+    do {                            \
+        ek_status s_ = (x);         \
+        if (s_ != EK_OK) return s_; \
+    } while (0)
+
+// ------------------------------------------------------------------------------------
+// Timing (HIP events on the context's stream)
+// ------------------------------------------------------------------------------------
+static hipEvent_t get_event(ek_ctx* c) {
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+static void resolve_timing(ek_ctx* c) {
+    if (c->recs.empty()) return;
+    (void)hipEventSynchronize(c->recs.back().b);
+    for (auto& r : c->recs) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, r.a, r.b);
+        c->tms[r.cls] += ms;
+        c->tcnt[r.cls] += r.count;
+        c->pool.push_back(r.a);
+        c->pool.push_back(r.b);
+    }
+    c->recs.clear();
+}
+
+struct Timer {
+    ek_ctx* c;
+    int cls, count;
+    hipEvent_t a{};
+    bool on;
+    Timer(ek_ctx* c_, int cls_, int count_ = 1) : c(c_), cls(cls_), count(count_), on(c_->timing) {
+        if (on) {
+            a = get_event(c);
+            (void)hipEventRecord(a, c->st);
+        }
+    }
+    ~Timer() {
+        if (!on) return;
+        hipEvent_t b = get_event(c);
+        (void)hipEventRecord(b, c->st);
+        c->recs.push_back({a, b, cls, count});
+        if (c->recs.size() > 4096) resolve_timing(c);
+    }
+};
+
+// ------------------------------------------------------------------------------------
+// Fields view for one precision
+// ------------------------------------------------------------------------------------
+template <typename T>
+static Fields<T> fields(ek_ctx* c) {
+    Fields<T> F;
+    for (int k = 0; k < 2; ++k) {
+        F.f[k] = (const T*)c->f[c->cur][k];
+        F.fn[k] = (T*)c->f[c->cur ^ 1][k];
+        F.n[k] = (const T*)c->n[c->cur][k];
+        F.nn[k] = (T*)c->n[c->cur ^ 1][k];
+    }
+    F.mom = (T*)c->mom;
+    F.uph = (T*)c->uph;
+    F.q = (T*)c->q;
+    F.eps = (T*)c->eps;
+    F.phi = c->phi;
+    F.flags = c->flags;
+    F.psif = (const T*)c->psif;
+    F.qc = (const T*)c->qc;
+    F.owner = c->owner;
+    F.linkbase = c->linkbase;
+    F.linkdp = c->linkdp;
+    F.vlist = c->vlist;
+    F.nv = c->nv;
+    F.pv = c->pv[c->pcur];
+    F.red = c->red;
+    F.scal = c->scal;
+    return F;
+}
+
+// ------------------------------------------------------------------------------------
+// Geometry (host, at set-up): wall layers, particle marking, solid fraction by sub-cell
+// counting, charge spreading, boundary lists (Sec. II E).
+// ------------------------------------------------------------------------------------
+static double wrap_dist(double d, int n) {
+    const double L = (double)n;
+    while (d > 0.5 * L) d -= L;
+    while (d < -0.5 * L) d += L;
+    return d;
+}
+
+struct HostGeom {
+    std::vector<uint8_t> flags;
+    std::vector<double> psis, qc;
+    std::vector<int32_t> owner, linkbase, vlist, link_off, link_idx, site_off, site_idx;
+    long long nlinks = 0;
+};
+
+static ek_status build_geometry(ek_ctx* c, const ek_particle* parts, int np, HostGeom& g) {
+    const ek_params& p = c->p;
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const size_t N = c->N;
+    g.flags.assign(N, 0);
+    g.psis.assign(N, 0.0);
+    g.qc.assign(N, 0.0);
+    g.owner.assign(N, -1);
+    auto id = [&](int x, int y, int z) { return (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z); };
+    if (p.walls_z) {
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                g.flags[id(x, y, 0)] |= 1;
+                g.flags[id(x, y, nz - 1)] |= 1;
+                g.psis[id(x, y, 0)] = 1.0;
+                g.psis[id(x, y, nz - 1)] = 1.0;
+            }
+    }
+    const int h = p.subsample > 0 ? p.subsample : 8;
+    std::vector<double> offs(h);
+    for (int a = 0; a < h; ++a) offs[a] = (a + 0.5) / h - 0.5;
+    for (int j = 0; j < np; ++j) {
+        const double X = parts[j].x[0], Y = parts[j].x[1], Z = parts[j].x[2], R = parts[j].radius;
+        if (!(R > 0.0)) return fail(c, EK_EINVAL, "particle radius must be positive");
+        const int lo[3] = {(int)std::floor(X - R) - 1, (int)std::floor(Y - R) - 1, (int)std::floor(Z - R) - 1};
+        const int hi[3] = {(int)std::ceil(X + R) + 1, (int)std::ceil(Y + R) + 1, (int)std::ceil(Z + R) + 1};
+        for (int zz = lo[2]; zz <= hi[2]; ++zz)
+            for (int yy = lo[1]; yy <= hi[1]; ++yy)
+                for (int xx = lo[0]; xx <= hi[0]; ++xx) {
+                    const int x = ((xx % nx) + nx) % nx, y = ((yy % ny) + ny) % ny, z = ((zz % nz) + nz) % nz;
+                    const double dx = wrap_dist((double)x - X, nx), dy = wrap_dist((double)y - Y, ny),
+                                 dz = wrap_dist((double)z - Z, nz);
+                    int cnt = 0;
+                    for (int a = 0; a < h; ++a) {
+                        const double sx = dx + offs[a];
+                        for (int b = 0; b < h; ++b) {
+                            const double sy = dy + offs[b];
+                            const double sxy = sx * sx + sy * sy;
+                            for (int e = 0; e < h; ++e) {
+                                const double sz = dz + offs[e];
+                                if (sxy + sz * sz <= R * R) ++cnt;
+                            }
+                        }
+                    }
+                    const size_t i = id(x, y, z);
+                    const bool wall = p.walls_z && (z == 0 || z == nz - 1);
+                    if (cnt > 0 && !wall) {
+                        if (g.owner[i] >= 0 && g.owner[i] != j)
+                            return fail(c, EK_EINVAL, "particles overlap on the lattice");
+                        g.owner[i] = j;
+                        g.psis[i] = (double)cnt / ((double)h * h * h);
+                    }
+                    if (dx * dx + dy * dy + dz * dz < R * R) g.flags[i] |= 1;
+                }
+    }
+    if (np > 0) {
+        std::vector<double> tot(np, 0.0);
+        for (size_t i = 0; i < N; ++i)
+            if (g.owner[i] >= 0) tot[g.owner[i]] += g.psis[i];
+        for (size_t i = 0; i < N; ++i)
+            if (g.owner[i] >= 0 && tot[g.owner[i]] > 0.0) g.qc[i] = parts[g.owner[i]].charge * g.psis[i] / tot[g.owner[i]];
+    }
+    // neighbour flags, virtual-density list, particle links
+    g.linkbase.assign(np > 0 ? N : 1, 0);
+    long long nl = 0;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const size_t i = id(x, y, z);
+                const bool si = g.flags[i] & 1;
+                bool any_other = false;
+                int links_here = 0;
+                for (int d = 0; d < kQ; ++d) {
+                    if (d == kRest) continue;
+                    const size_t j = id(((x + vx(d)) % nx + nx) % nx, ((y + vy(d)) % ny + ny) % ny,
+                                        ((z + vz(d)) % nz + nz) % nz);
+                    const bool sj = g.flags[j] & 1;
+                    if (sj != si) any_other = true;
+                    if (!si && sj && g.owner[j] >= 0) ++links_here;
+                }
+                if (any_other) g.flags[i] |= si ? 4 : 2;
+                if (si && any_other) g.vlist.push_back((int32_t)i);
+                if (np > 0 && links_here) {
+                    g.linkbase[i] = (int32_t)nl;
+                    nl += links_here;
+                }
+            }
+    g.nlinks = nl;
+    if (np > 0) {
+        // links grouped by particle (counting sort), in the order the fused kernel writes them
+        std::vector<int32_t> lowner(nl > 0 ? nl : 1);
+        long long l = 0;
+        for (size_t i = 0; i < N; ++i) {
+            if ((g.flags[i] & 1) || !(g.flags[i] & 2)) continue;
+            const int x = i % nx, y = (i / nx) % ny, z = i / ((size_t)nx * ny);
+            for (int d = 0; d < kQ; ++d) {
+                if (d == kRest) continue;
+                const size_t j = id(((x + vx(d)) % nx + nx) % nx, ((y + vy(d)) % ny + ny) % ny,
+                                    ((z + vz(d)) % nz + nz) % nz);
+                if ((g.flags[j] & 1) && g.owner[j] >= 0) lowner[l++] = g.owner[j];
+            }
+        }
+        g.link_off.assign(np + 1, 0);
+        for (long long t = 0; t < nl; ++t) g.link_off[lowner[t] + 1]++;
+        for (int j = 0; j < np; ++j) g.link_off[j + 1] += g.link_off[j];
+        g.link_idx.assign(nl > 0 ? nl : 1, 0);
+        std::vector<int32_t> fill(g.link_off.begin(), g.link_off.end() - 1);
+        for (long long t = 0; t < nl; ++t) g.link_idx[fill[lowner[t]]++] = (int32_t)t;
+        g.site_off.assign(np + 1, 0);
+        for (size_t i = 0; i < N; ++i)
+            if (g.owner[i] >= 0) g.site_off[g.owner[i] + 1]++;
+        for (int j = 0; j < np; ++j) g.site_off[j + 1] += g.site_off[j];
+        g.site_idx.assign(std::max<int32_t>(g.site_off[np], 1), 0);
+        std::vector<int32_t> sf(g.site_off.begin(), g.site_off.end() - 1);
+        for (size_t i = 0; i < N; ++i)
+            if (g.owner[i] >= 0) g.site_idx[sf[g.owner[i]]++] = (int32_t)i;
+    }
+    return EK_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Poisson solve with convergence control
+// ------------------------------------------------------------------------------------
+template <typename T>
+static ek_status check_residual(ek_ctx* c, double& rr, double& ss) {
+    Fields<T> F = fields<T>(c);
+    launch_residual<T>(c->S, F, c->nblk, c->st);
+    launch_reduce(c->red, c->nblk, 3, nullptr, c->scal + 1, c->st);
+    EK_HIP(hipMemcpyAsync(c->hscal, c->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    EK_HIP(hipStreamSynchronize(c->st));
+    rr = c->hscal[1];
+    ss = c->hscal[2];
+    c->last_mean = c->hscal[0];
+    return EK_OK;
+}
+
+// Requires q, eps and the source mean of the current state on the device.
+template <typename T>
+static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out, double* rel_out) {
+    Timer tm(c, EK_T_POISSON);
+    Fields<T> F = fields<T>(c);
+    double rr, ss;
+    EK_TRY(check_residual<T>(c, rr, ss));
+    int it = 0;
+    ek_status status = EK_OK;
+    double rel = 0.0;
+    if (!(ss > 0.0)) {
+        launch_phi_finalize(c->S, c->phi, c->scal, 1, c->st);
+    } else {
+        const double target = tol * std::sqrt(ss);
+        double r = std::sqrt(rr);
+        while (r > target && it < maxit) {
+            int k;
+            if (c->rate > 0.0 && c->rate < 1.0)
+                k = (int)std::ceil(1.1 * std::log(target / r) / std::log(c->rate)) + 1;
+            else
+                k = 8;
+            k = std::max(1, std::min(k, 400));
+            k = std::min(k, maxit - it);
+            {
+                Timer ts(c, EK_T_SOR, 2 * k);
+                for (int s = 0; s < k; ++s) {
+                    launch_sor<T>(c->S, F, 0, c->omega, c->st);
+                    launch_sor<T>(c->S, F, 1, c->omega, c->st);
+                }
+            }
+            EK_HIP(hipGetLastError());
+            it += k;
+            EK_TRY(check_residual<T>(c, rr, ss));
+            const double rn = std::sqrt(rr);
+            if (rn < r && rn > 0.0) {
+                const double est = std::pow(rn / r, 1.0 / k);
+                c->rate = c->rate > 0.0 ? std::max(est, 0.5 * (c->rate + est)) : est;
+            }
+            r = rn;
+        }
+        launch_phi_finalize(c->S, c->phi, c->scal, 0, c->st);
+        rel = r / std::sqrt(ss);
+        if (r > target) status = EK_ENOCONV;
+    }
+    launch_phi_ghosts<T>(c->S, F, c->st);
+    EK_HIP(hipGetLastError());
+    c->last_iters = it;
+    c->last_rel = rel;
+    c->ptotal += it;
+    if (iters_out) *iters_out = it;
+    if (rel_out) *rel_out = rel;
+    if (status == EK_ENOCONV) c->err = "Poisson solve stopped at maxit above the tolerance";
+    return status;
+}
+
+template <typename T>
+static void moments_pass(ek_ctx* c) {
+    Timer tm(c, EK_T_MOMENTS);
+    Fields<T> F = fields<T>(c);
+    launch_moments<T>(c->S, F, c->nblk, c->st);
+    launch_virtual<T>(c->S, F, c->st);
+    launch_source_mean(c->S, c->red, c->nblk, c->scal, c->st);
+}
+
+template <typename T>
+static ek_status step_impl(ek_ctx* c, int nsteps) {
+    ek_status worst = EK_OK;
+    for (int s = 0; s < nsteps; ++s) {
+        moments_pass<T>(c);
+        ek_status ps = poisson_solve<T>(c, c->p.poisson_tol, c->p.poisson_maxit, nullptr, nullptr);
+        if (ps == EK_ENOCONV)
+            worst = ps;
+        else if (ps != EK_OK)
+            return ps;
+        Fields<T> F = fields<T>(c);
+        {
+            Timer tm(c, EK_T_FORCE);
+            launch_force<T>(c->S, F, c->st);
+        }
+        {
+            Timer tm(c, EK_T_FUSED);
+            launch_fused<T>(c->S, F, c->st);
+        }
+        if (c->np > 0) {
+            Timer tm(c, EK_T_PARTICLE);
+            launch_particle_sum<T>(c->S, F, c->np, c->plink_off, c->plink_idx, c->psite_off, c->psite_idx, c->pF,
+                                   c->st);
+            launch_particle_move(c->S, c->np, c->px[c->pcur], c->pv[c->pcur], c->prad, c->pF, c->px[c->pcur ^ 1],
+                                 c->pv[c->pcur ^ 1], c->p.particle_rho, c->p.k_hertz, c->p.eta, c->p.move_particles,
+                                 c->st);
+            c->pcur ^= 1;
+        }
+        EK_HIP(hipGetLastError());
+        c->cur ^= 1;
+        c->steps++;
+    }
+    return worst;
+}
+
+// ------------------------------------------------------------------------------------
+// Public ABI
+// ------------------------------------------------------------------------------------
+extern "C" int32_t ek_lattice(int32_t* cvec, double* w) {
+    for (int d = 0; d < kQ; ++d) {
+        if (cvec) {
+            cvec[3 * d] = vx(d);
+            cvec[3 * d + 1] = vy(d);
+            cvec[3 * d + 2] = vz(d);
+        }
+        if (w) w[d] = weight(d);
+    }
+    return kQ;
+}
+
+static double omega_for(const ek_params& p) {
+    const double pi = 3.14159265358979323846;
+    double lam = 1e300;
+    int act = 0;
+    if (p.nx > 1) {
+        lam = std::min(lam, 2.0 - 2.0 * std::cos(2.0 * pi / p.nx));
+        ++act;
+    }
+    if (p.ny > 1) {
+        lam = std::min(lam, 2.0 - 2.0 * std::cos(2.0 * pi / p.ny));
+        ++act;
+    }
+    if (p.walls_z) {
+        if (p.nz - 2 > 1) {
+            lam = std::min(lam, 2.0 - 2.0 * std::cos(pi / (p.nz - 2)));
+            ++act;
+        }
+    } else if (p.nz > 1) {
+        lam = std::min(lam, 2.0 - 2.0 * std::cos(2.0 * pi / p.nz));
+        ++act;
+    }
+    if (act == 0) return 1.0;
+    const double mu = 1.0 - lam / (2.0 * act);
+    return 2.0 / (1.0 + std::sqrt(std::max(0.0, 1.0 - mu * mu)));
+}
+
+template <typename T>
+static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, const double* n_plus,
+                           const double* n_minus, const ek_particle* parts, int np) {
+    const ek_params& p = c->p;
+    const unsigned N = c->N;
+    HostGeom g;
+    EK_TRY(build_geometry(c, parts, np, g));
+    const bool colloids = np > 0;
+    c->S.colloids = colloids;
+    // reference densities for the deviation storage: initial fluid means unless given
+    for (int s = 0; s < 2; ++s) {
+        const double* r = s == 0 ? rho_a : rho_b;
+        double sum = 0.0;
+        long long cnt = 0;
+        for (unsigned i = 0; i < N; ++i) {
+            if (g.flags[i] & 1) continue;
+            if (!(r[i] > 0.0) || !std::isfinite(r[i])) return fail(c, EK_EINVAL, "fluid densities must be positive and finite");
+            sum += r[i];
+            ++cnt;
+        }
+        c->S.rref[s] = p.rho_ref[s] > 0.0 ? p.rho_ref[s] : (cnt > 0 ? sum / cnt : 1.0);
+    }
+    for (unsigned i = 0; i < N; ++i)
+        if (!std::isfinite(n_plus[i]) || !std::isfinite(n_minus[i])) return fail(c, EK_EINVAL, "ion densities must be finite");
+
+    const size_t es = sizeof(T);
+    for (int b = 0; b < 2; ++b)
+        for (int k = 0; k < 2; ++k) {
+            EK_TRY(dalloc(c, &c->f[b][k], (size_t)kQ * N * es));
+            EK_TRY(dalloc(c, &c->n[b][k], (size_t)N * es));
+        }
+    EK_TRY(dalloc(c, &c->mom, 7 * (size_t)N * es));
+    EK_TRY(dalloc(c, &c->uph, 3 * (size_t)N * es));
+    EK_TRY(dalloc(c, &c->q, (size_t)N * es));
+    EK_TRY(dalloc(c, &c->eps, (size_t)N * es));
+    EK_TRY(dalloc(c, (void**)&c->phi, (size_t)N * 8));
+    EK_TRY(dalloc(c, (void**)&c->red, (size_t)c->nblk * kRedSlots * 8));
+    EK_TRY(dalloc(c, (void**)&c->scal, 32 * 8));
+    EK_TRY(dalloc(c, (void**)&c->obs_max, 16 * sizeof(int)));
+    EK_TRY(dalloc(c, (void**)&c->stage, (size_t)N * 8));
+    EK_HIP(hipHostMalloc((void**)&c->hscal, 32 * sizeof(double), hipHostMallocDefault));
+    for (int b = 0; b < 2; ++b)
+        for (int k = 0; k < 2; ++k) {
+            EK_HIP(hipMemsetAsync(c->f[b][k], 0, (size_t)kQ * N * es, c->st));
+            EK_HIP(hipMemsetAsync(c->n[b][k], 0, (size_t)N * es, c->st));
+        }
+    EK_HIP(hipMemsetAsync(c->mom, 0, 7 * (size_t)N * es, c->st));
+    EK_HIP(hipMemsetAsync(c->uph, 0, 3 * (size_t)N * es, c->st));
+    EK_HIP(hipMemsetAsync(c->phi, 0, (size_t)N * 8, c->st));
+    EK_HIP(hipMemsetAsync(c->scal, 0, 32 * 8, c->st));
+    int hmax[16] = {0};
+    hmax[8] = 1;
+    EK_HIP(hipMemcpyAsync(c->obs_max, hmax, sizeof(hmax), hipMemcpyHostToDevice, c->st));
+
+    // geometry upload
+    c->hflags = g.flags;
+    c->hpsis = g.psis;
+    c->nv = (int)g.vlist.size();
+    if (c->nv > 0) {
+        EK_TRY(dalloc(c, (void**)&c->vlist, g.vlist.size() * 4));
+        EK_HIP(hipMemcpyAsync(c->vlist, g.vlist.data(), g.vlist.size() * 4, hipMemcpyHostToDevice, c->st));
+    }
+    if (colloids) {
+        EK_TRY(dalloc(c, (void**)&c->flags, N));
+        EK_HIP(hipMemcpyAsync(c->flags, g.flags.data(), N, hipMemcpyHostToDevice, c->st));
+        EK_TRY(dalloc(c, &c->psif, (size_t)N * es));
+        EK_TRY(dalloc(c, &c->qc, (size_t)N * es));
+        std::vector<double> tmp(N);
+        for (unsigned i = 0; i < N; ++i) tmp[i] = 1.0 - g.psis[i];
+        EK_HIP(hipMemcpyAsync(c->stage, tmp.data(), (size_t)N * 8, hipMemcpyHostToDevice, c->st));
+        launch_upload<T>((T*)c->psif, c->stage, N, c->st);
+        EK_HIP(hipStreamSynchronize(c->st));
+        EK_HIP(hipMemcpyAsync(c->stage, g.qc.data(), (size_t)N * 8, hipMemcpyHostToDevice, c->st));
+        launch_upload<T>((T*)c->qc, c->stage, N, c->st);
+        EK_TRY(dalloc(c, (void**)&c->owner, (size_t)N * 4));
+        EK_HIP(hipMemcpyAsync(c->owner, g.owner.data(), (size_t)N * 4, hipMemcpyHostToDevice, c->st));
+        EK_TRY(dalloc(c, (void**)&c->linkbase, (size_t)N * 4));
+        EK_HIP(hipMemcpyAsync(c->linkbase, g.linkbase.data(), (size_t)N * 4, hipMemcpyHostToDevice, c->st));
+        c->nlinks = g.nlinks;
+        EK_TRY(dalloc(c, (void**)&c->linkdp, (size_t)std::max(1LL, g.nlinks) * 6 * 8));
+        EK_HIP(hipMemsetAsync(c->linkdp, 0, (size_t)std::max(1LL, g.nlinks) * 6 * 8, c->st));
+        EK_TRY(dalloc(c, (void**)&c->plink_off, g.link_off.size() * 4));
+        EK_TRY(dalloc(c, (void**)&c->plink_idx, g.link_idx.size() * 4));
+        EK_TRY(dalloc(c, (void**)&c->psite_off, g.site_off.size() * 4));
+        EK_TRY(dalloc(c, (void**)&c->psite_idx, g.site_idx.size() * 4));
+        EK_HIP(hipMemcpyAsync(c->plink_off, g.link_off.data(), g.link_off.size() * 4, hipMemcpyHostToDevice, c->st));
+        EK_HIP(hipMemcpyAsync(c->plink_idx, g.link_idx.data(), g.link_idx.size() * 4, hipMemcpyHostToDevice, c->st));
+        EK_HIP(hipMemcpyAsync(c->psite_off, g.site_off.data(), g.site_off.size() * 4, hipMemcpyHostToDevice, c->st));
+        EK_HIP(hipMemcpyAsync(c->psite_idx, g.site_idx.data(), g.site_idx.size() * 4, hipMemcpyHostToDevice, c->st));
+        // particles
+        c->np = np;
+        std::vector<double> hx(3 * np), hv(3 * np);
+        c->hrad.resize(np);
+        for (int j = 0; j < np; ++j) {
+            for (int k = 0; k < 3; ++k) {
+                hx[3 * j + k] = parts[j].x[k];
+                hv[3 * j + k] = parts[j].v[k];
+            }
+            c->hrad[j] = parts[j].radius;
+        }
+        c->px0 = hx;
+        for (int b = 0; b < 2; ++b) {
+            EK_TRY(dalloc(c, (void**)&c->px[b], 3 * np * 8));
+            EK_TRY(dalloc(c, (void**)&c->pv[b], 3 * np * 8));
+            EK_HIP(hipMemcpyAsync(c->px[b], hx.data(), 3 * np * 8, hipMemcpyHostToDevice, c->st));
+            EK_HIP(hipMemcpyAsync(c->pv[b], hv.data(), 3 * np * 8, hipMemcpyHostToDevice, c->st));
+        }
+        EK_TRY(dalloc(c, (void**)&c->prad, np * 8));
+        EK_HIP(hipMemcpyAsync(c->prad, c->hrad.data(), np * 8, hipMemcpyHostToDevice, c->st));
+        EK_TRY(dalloc(c, (void**)&c->pF, 3 * np * 8));
+        EK_HIP(hipMemsetAsync(c->pF, 0, 3 * np * 8, c->st));
+        EK_HIP(hipStreamSynchronize(c->st));  // host staging vectors above end with this block
+    }
+    EK_HIP(hipStreamSynchronize(c->st));
+
+    // initial populations and ions
+    Fields<T> F = fields<T>(c);
+    const double* rr[2] = {rho_a, rho_b};
+    for (int s = 0; s < 2; ++s) {
+        EK_HIP(hipMemcpyAsync(c->stage, rr[s], (size_t)N * 8, hipMemcpyHostToDevice, c->st));
+        launch_init_pop_flags<T>(c->S, (T*)c->f[c->cur][s], c->stage, c->S.rref[s], c->flags, c->st);
+        EK_HIP(hipStreamSynchronize(c->st));
+    }
+    const double* nn[2] = {n_plus, n_minus};
+    for (int s = 0; s < 2; ++s) {
+        EK_HIP(hipMemcpyAsync(c->stage, nn[s], (size_t)N * 8, hipMemcpyHostToDevice, c->st));
+        launch_init_ions<T>(c->S, F, (T*)c->n[c->cur][s], c->stage, c->st);
+        EK_HIP(hipStreamSynchronize(c->st));
+    }
+    EK_HIP(hipGetLastError());
+    // initial potential
+    moments_pass<T>(c);
+    ek_status st = poisson_solve<T>(c, p.poisson_tol, p.poisson_maxit, nullptr, nullptr);
+    c->ptotal = 0;
+    return st;
+}
+
+extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const double* rho_b, const double* n_plus,
+                             const double* n_minus, const ek_particle* parts, int32_t n_parts, void* stream,
+                             ek_ctx** out) {
+    if (!out) return EK_EINVAL;
+    *out = nullptr;
+    ek_ctx* c = new ek_ctx();
+    *out = c;
+    if (!p || !rho_a || !rho_b || !n_plus || !n_minus) return fail(c, EK_EINVAL, "null argument");
+    c->p = *p;
+    c->st = (hipStream_t)stream;
+    if (p->nx < 2 || (p->nx & 1) || p->ny < 1 || p->nz < 1) return fail(c, EK_EINVAL, "nx must be even and >= 2; ny, nz >= 1");
+    if (p->walls_z && p->nz < 3) return fail(c, EK_EINVAL, "walls need nz >= 3");
+    const double Nd = (double)p->nx * p->ny * p->nz;
+    if (Nd > 2147483647.0) return fail(c, EK_EINVAL, "lattice too large (more than 2^31 - 1 sites)");
+    if (!(p->tau > 0.5)) return fail(c, EK_EINVAL, "tau must exceed 1/2");
+    if (p->precision != EK_FP32 && p->precision != EK_FP64) return fail(c, EK_EINVAL, "precision must be EK_FP32 or EK_FP64");
+    if (!(p->D > 0.0) || !(p->beta > 0.0) || !(p->rho0 > 0.0)) return fail(c, EK_EINVAL, "D, beta and rho0 must be positive");
+    if (!(p->eps_a > 0.0) || !(p->eps_b > 0.0) || !(p->eps_p > 0.0)) return fail(c, EK_EINVAL, "permittivities must be positive");
+    if ((p->dmu[0] != 0.0 || p->dmu[1] != 0.0) && p->drho_a == 0.0) return fail(c, EK_EINVAL, "drho_a must be non-zero with solvation");
+    if (n_parts < 0 || (n_parts > 0 && !parts)) return fail(c, EK_EINVAL, "bad particle array");
+    if (p->poisson_maxit < 0 || !(p->poisson_tol > 0.0)) return fail(c, EK_EINVAL, "poisson_tol must be > 0, maxit >= 0");
+    c->N = (unsigned)Nd;
+    c->nblk = site_blocks(c->N);
+    Scalars& S = c->S;
+    S.nx = p->nx;
+    S.ny = p->ny;
+    S.nz = p->nz;
+    S.nxy = p->nx * p->ny;
+    S.N = c->N;
+    S.walls = p->walls_z ? 1 : 0;
+    S.kelvin = p->eps_a != p->eps_b;
+    S.z0 = S.walls ? 1 : 0;
+    S.z1 = S.walls ? p->nz - 2 : p->nz - 1;
+    S.ndomain = (unsigned)S.nxy * (unsigned)(S.z1 - S.z0 + 1);
+    S.tau = p->tau;
+    S.inv_tau = 1.0 / p->tau;
+    S.G = p->G;
+    S.rho0 = p->rho0;
+    S.D = p->D;
+    S.beta = p->beta;
+    const double cs2 = 1.0 / 3.0;
+    S.kap_p = p->dmu[0] == 0.0 ? 0.0 : p->solvation_sign * p->beta * p->dmu[0] / (2.0 * p->drho_a);
+    S.kap_m = p->dmu[1] == 0.0 ? 0.0 : p->solvation_sign * p->beta * p->dmu[1] / (2.0 * p->drho_a);
+    S.G_p = p->dmu[0] == 0.0 ? 0.0 : p->solvation_sign * p->dmu[0] / (p->drho_a * cs2);
+    S.G_m = p->dmu[1] == 0.0 ? 0.0 : p->solvation_sign * p->dmu[1] / (p->drho_a * cs2);
+    S.ion_sc = (S.G_p != 0.0 || S.G_m != 0.0);
+    S.eps_a = p->eps_a;
+    S.eps_b = p->eps_b;
+    S.eps_p = p->eps_p;
+    S.eps_bar = 0.5 * (p->eps_a + p->eps_b);
+    for (int k = 0; k < 3; ++k) {
+        S.E_ext[k] = p->E_ext[k];
+        S.g_body[k] = p->body_accel[k];
+    }
+    S.sigma0 = p->sigma_wall[0];
+    S.sigma1 = p->sigma_wall[1];
+    c->omega = p->sor_omega > 0.0 ? p->sor_omega : omega_for(*p);
+    c->esz = p->precision == EK_FP32 ? 4 : 8;
+    if (p->precision == EK_FP32) return init_impl<float>(c, rho_a, rho_b, n_plus, n_minus, parts, n_parts);
+    return init_impl<double>(c, rho_a, rho_b, n_plus, n_minus, parts, n_parts);
+}
+
+extern "C" ek_status ek_step(ek_ctx* c, int32_t nsteps) {
+    if (!c || !c->phi) return EK_ESTATE;
+    if (nsteps < 0) return fail(c, EK_EINVAL, "nsteps must be >= 0");
+    return c->esz == 4 ? step_impl<float>(c, nsteps) : step_impl<double>(c, nsteps);
+}
+
+template <typename T>
+static ek_status poisson_entry(ek_ctx* c, double tol, int maxit, int* iters, double* rel) {
+    moments_pass<T>(c);
+    return poisson_solve<T>(c, tol, maxit, iters, rel);
+}
+
+extern "C" ek_status ek_poisson(ek_ctx* c, double tol, int32_t maxit, int32_t* iters, double* rel_res) {
+    if (!c || !c->phi) return EK_ESTATE;
+    if (!(tol > 0.0) || maxit < 0) return fail(c, EK_EINVAL, "tol must be > 0 and maxit >= 0");
+    int it = 0;
+    double rel = 0.0;
+    ek_status s = c->esz == 4 ? poisson_entry<float>(c, tol, maxit, &it, &rel) : poisson_entry<double>(c, tol, maxit, &it, &rel);
+    if (iters) *iters = it;
+    if (rel_res) *rel_res = rel;
+    return s;
+}
+
+template <typename T>
+static ek_status observe_impl(ek_ctx* c, ek_obs* o) {
+    Fields<T> F = fields<T>(c);
+    launch_observe<T>(c->S, F, c->nblk, c->st);
+    launch_reduce(c->red, c->nblk, 11, c->obs_max, c->scal + 8, c->st);
+    EK_HIP(hipMemcpyAsync(c->hscal, c->scal, 20 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    EK_HIP(hipStreamSynchronize(c->st));
+    const double* v = c->hscal + 8;
+    std::memset(o, 0, sizeof(*o));
+    o->sum_rho[0] = v[0];
+    o->sum_rho[1] = v[1];
+    o->sum_n[0] = v[2];
+    o->sum_n[1] = v[3];
+    o->sum_q = v[4];
+    o->momentum[0] = v[5];
+    o->momentum[1] = v[6];
+    o->momentum[2] = v[7];
+    o->max_u = v[8] < 0.0 ? 0.0 : v[8];
+    o->nonfinite = v[9] > 0.0;
+    o->negative_ions = (int32_t)v[10];
+    o->source_mean = c->last_mean;
+    o->poisson_rel = c->last_rel;
+    o->poisson_iters = c->last_iters;
+    o->poisson_total = c->ptotal;
+    o->steps = c->steps;
+    if (c->np > 0) {
+        std::vector<double> hx(3 * c->np), hv(3 * c->np);
+        EK_HIP(hipMemcpyAsync(hx.data(), c->px[c->pcur], 3 * c->np * 8, hipMemcpyDeviceToHost, c->st));
+        EK_HIP(hipMemcpyAsync(hv.data(), c->pv[c->pcur], 3 * c->np * 8, hipMemcpyDeviceToHost, c->st));
+        EK_HIP(hipStreamSynchronize(c->st));
+        const double pi = 3.14159265358979323846;
+        for (int j = 0; j < c->np; ++j) {
+            const double m = c->p.particle_rho * (4.0 / 3.0) * pi * c->hrad[j] * c->hrad[j] * c->hrad[j];
+            for (int k = 0; k < 3; ++k) {
+                o->drift[k] += (hx[3 * j + k] - c->px0[3 * j + k]) / c->np;
+                o->pmomentum[k] += m * hv[3 * j + k];
+            }
+        }
+    }
+    return o->nonfinite ? fail(c, EK_ENONFINITE, "non-finite populations or ion densities") : EK_OK;
+}
+
+extern "C" ek_status ek_observables(ek_ctx* c, ek_obs* out) {
+    if (!c || !c->phi) return EK_ESTATE;
+    if (!out) return fail(c, EK_EINVAL, "null output");
+    return c->esz == 4 ? observe_impl<float>(c, out) : observe_impl<double>(c, out);
+}
+
+template <typename T>
+static ek_status field_impl(ek_ctx* c, int which, double* host) {
+    const unsigned N = c->N;
+    Fields<T> F = fields<T>(c);
+    if (which == EK_F_PSI_S || which == EK_F_SOLID) {
+        for (unsigned i = 0; i < N; ++i) host[i] = which == EK_F_PSI_S ? c->hpsis[i] : (double)(c->hflags[i] & 1);
+        return EK_OK;
+    }
+    if (which == EK_F_PHI) {
+        EK_HIP(hipMemcpyAsync(host, c->phi, (size_t)N * 8, hipMemcpyDeviceToHost, c->st));
+        EK_HIP(hipStreamSynchronize(c->st));
+        return EK_OK;
+    }
+    if (which == EK_F_N_PLUS || which == EK_F_N_MINUS) {
+        launch_to_double<T>((const T*)c->n[c->cur][which - EK_F_N_PLUS], c->stage, N, 0.0, c->st);
+    } else if (which >= EK_F_EX && which <= EK_F_EZ) {
+        launch_field_e<T>(c->S, F, which - EK_F_EX, c->stage, c->st);
+    } else {
+        launch_moments<T>(c->S, F, c->nblk, c->st);
+        launch_virtual<T>(c->S, F, c->st);
+        const T* src = nullptr;
+        switch (which) {
+            case EK_F_RHO_A: src = (const T*)c->mom; break;
+            case EK_F_RHO_B: src = (const T*)c->mom + N; break;
+            case EK_F_UX: src = (const T*)c->mom + 4 * (size_t)N; break;
+            case EK_F_UY: src = (const T*)c->mom + 5 * (size_t)N; break;
+            case EK_F_UZ: src = (const T*)c->mom + 6 * (size_t)N; break;
+            case EK_F_Q: src = (const T*)c->q; break;
+            case EK_F_EPS: src = (const T*)c->eps; break;
+            default: return fail(c, EK_EINVAL, "unknown field id");
+        }
+        launch_to_double<T>(src, c->stage, N, 0.0, c->st);
+    }
+    EK_HIP(hipGetLastError());
+    EK_HIP(hipMemcpyAsync(host, c->stage, (size_t)N * 8, hipMemcpyDeviceToHost, c->st));
+    EK_HIP(hipStreamSynchronize(c->st));
+    return EK_OK;
+}
+
+extern "C" ek_status ek_get_field(ek_ctx* c, int32_t which, double* host_out) {
+    if (!c || !c->phi) return EK_ESTATE;
+    if (!host_out) return fail(c, EK_EINVAL, "null output");
+    if (which < 0 || which > EK_F_EZ) return fail(c, EK_EINVAL, "unknown field id");
+    return c->esz == 4 ? field_impl<float>(c, which, host_out) : field_impl<double>(c, which, host_out);
+}
+
+template <typename T>
+static ek_status pops_impl(ek_ctx* c, int comp, double* host) {
+    const unsigned N = c->N;
+    for (int d = 0; d < kQ; ++d) {
+        launch_to_double<T>((const T*)c->f[c->cur][comp] + (size_t)d * N, c->stage, N, weight(d) * c->S.rref[comp], c->st);
+        EK_HIP(hipMemcpyAsync(host + (size_t)d * N, c->stage, (size_t)N * 8, hipMemcpyDeviceToHost, c->st));
+        EK_HIP(hipStreamSynchronize(c->st));
+    }
+    return EK_OK;
+}
+
+extern "C" ek_status ek_get_populations(ek_ctx* c, int32_t comp, double* host_out) {
+    if (!c || !c->phi) return EK_ESTATE;
+    if (!host_out || comp < 0 || comp > 1) return fail(c, EK_EINVAL, "bad component or null output");
+    return c->esz == 4 ? pops_impl<float>(c, comp, host_out) : pops_impl<double>(c, comp, host_out);
+}
+
+extern "C" ek_status ek_get_particles(ek_ctx* c, double* out) {
+    if (!c || !c->phi) return EK_ESTATE;
+    if (c->np == 0) return EK_OK;
+    if (!out) return fail(c, EK_EINVAL, "null output");
+    std::vector<double> hx(3 * c->np), hv(3 * c->np), hf(3 * c->np);
+    EK_HIP(hipMemcpyAsync(hx.data(), c->px[c->pcur], 3 * c->np * 8, hipMemcpyDeviceToHost, c->st));
+    EK_HIP(hipMemcpyAsync(hv.data(), c->pv[c->pcur], 3 * c->np * 8, hipMemcpyDeviceToHost, c->st));
+    EK_HIP(hipMemcpyAsync(hf.data(), c->pF, 3 * c->np * 8, hipMemcpyDeviceToHost, c->st));
+    EK_HIP(hipStreamSynchronize(c->st));
+    for (int j = 0; j < c->np; ++j)
+        for (int k = 0; k < 3; ++k) {
+            out[9 * j + k] = hx[3 * j + k];
+            out[9 * j + 3 + k] = hv[3 * j + k];
+            out[9 * j + 6 + k] = hf[3 * j + k];
+        }
+    return EK_OK;
+}
+
+extern "C" ek_status ek_device_bytes(const ek_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return EK_EINVAL;
+    *bytes = c->bytes;
+    return EK_OK;
+}
+
+extern "C" ek_status ek_set_timing(ek_ctx* c, int32_t enable) {
+    if (!c) return EK_EINVAL;
+    resolve_timing(c);
+    c->timing = enable != 0;
+    for (int k = 0; k < EK_T_COUNT; ++k) {
+        c->tms[k] = 0.0;
+        c->tcnt[k] = 0;
+    }
+    return EK_OK;
+}
+
+extern "C" ek_status ek_get_timing(ek_ctx* c, ek_timing* out) {
+    if (!c || !out) return EK_EINVAL;
+    resolve_timing(c);
+    for (int k = 0; k < EK_T_COUNT; ++k) {
+        out->ms[k] = c->tms[k];
+        out->count[k] = c->tcnt[k];
+    }
+    return EK_OK;
+}
+
+extern "C" ek_status ek_destroy(ek_ctx* c) {
+    if (!c) return EK_OK;
+    if (c->phi) (void)hipStreamSynchronize(c->st);
+    resolve_timing(c);
+    for (auto e : c->pool) (void)hipEventDestroy(e);
+    for (void* a : c->allocs) (void)hipFree(a);
+    if (c->hscal) (void)hipHostFree(c->hscal);
+    delete c;
+    return EK_OK;
+}
+
+extern "C" const char* ek_status_str(ek_status s) {
+    switch (s) {
+        case EK_OK: return "ok";
+        case EK_EINVAL: return "invalid argument";
+        case EK_ENOMEM: return "out of memory";
+        case EK_EHIP: return "HIP runtime error";
+        case EK_ENOCONV: return "Poisson solve did not converge";
+        case EK_ENONFINITE: return "non-finite value";
+        case EK_ESTATE: return "invalid state";
+        default: return "unknown status";
+    }
+}
+
+extern "C" const char* ek_last_error(const ek_ctx* c) { return c ? c->err.c_str() : "null context"; }

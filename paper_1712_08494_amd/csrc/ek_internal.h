@@ -1,0 +1,87 @@
+// Internal declarations shared by the kernels (ek_kernels.hip) and the host runtime
+// (ek_api.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ek {
+
+constexpr int kBlock = 256;   // threads per site-kernel workgroup (4 wave64)
+constexpr int kRedSlots = 12; // doubles per workgroup in reduction scratch
+
+// Scalar parameters of a context, passed by value to every kernel.
+struct Scalars {
+    int nx, ny, nz;
+    int nxy;
+    unsigned N;
+    int walls;        // solid layers at z = 0 and z = nz-1
+    int colloids;     // per-site geometry arrays present
+    int kelvin;       // eps_a != eps_b: Kelvin force active
+    int ion_sc;       // solvation Shan-Chen coupling active
+    int z0, z1;       // Poisson domain in z (inclusive)
+    unsigned ndomain; // sites in the Poisson domain
+    double tau, inv_tau, G, rho0, D, beta;
+    double kap_p, kap_m;   // s beta dmu+- / (2 drho_a)
+    double G_p, G_m;       // s dmu+- / (drho_a c_s^2)
+    double eps_a, eps_b, eps_p, eps_bar;
+    double E_ext[3];
+    double g_body[3];
+    double sigma0, sigma1;
+    double rref[2];        // deviation reference densities
+};
+
+// Device pointers of a context for one precision.
+template <typename T>
+struct Fields {
+    const T* f[2];      // populations of a, b at time t (19 N each, velocity-major)
+    T* fn[2];           // populations at t+1
+    const T* n[2];      // n+, n- at time t
+    T* nn[2];           // n+, n- at t+1
+    T* mom;             // 7 N: rho_a, rho_b, psi_a, psi_b, ux, uy, uz (pre-force)
+    T* uph;             // 3 N: physical velocity
+    T* q;               // charge density
+    T* eps;             // permittivity
+    double* phi;        // potential (double)
+    const uint8_t* flags;    // bit0 solid, bit1 fluid next to a solid, bit2 solid next to fluid
+    const T* psif;           // fluid fraction
+    const T* qc;             // particle charge per site
+    const int32_t* owner;    // particle owning a site, -1 none
+    const int32_t* linkbase; // first particle link of a fluid site
+    double* linkdp;          // 6 doubles per particle link: (component, xyz) momentum handed over
+    const int32_t* vlist;    // solid sites next to fluid (virtual densities)
+    int nv;
+    const double* pv;        // particle velocities (3 per particle)
+    double* red;             // reduction scratch
+    double* scal;            // device scalars: [0] source mean, [1..3] rr, ss, sum phi
+};
+
+unsigned site_blocks(unsigned n);
+
+template <typename T> void launch_moments(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
+template <typename T> void launch_virtual(const Scalars& S, const Fields<T>& F, hipStream_t st);
+void launch_source_mean(const Scalars& S, double* red, unsigned nblk, double* scal, hipStream_t st);
+template <typename T> void launch_sor(const Scalars& S, const Fields<T>& F, int color, double omega, hipStream_t st);
+template <typename T> void launch_residual(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
+void launch_reduce(const double* red, unsigned nblk, int nvals, const int* is_max, double* out, hipStream_t st);
+void launch_phi_finalize(const Scalars& S, double* phi, const double* scal, int zero, hipStream_t st);
+template <typename T> void launch_phi_ghosts(const Scalars& S, const Fields<T>& F, hipStream_t st);
+template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hipStream_t st);
+template <typename T> void launch_fused(const Scalars& S, const Fields<T>& F, hipStream_t st);
+template <typename T>
+void launch_particle_sum(const Scalars& S, const Fields<T>& F, int np, const int32_t* link_off,
+                         const int32_t* link_idx, const int32_t* site_off, const int32_t* site_idx, double* pF,
+                         hipStream_t st);
+void launch_particle_move(const Scalars& S, int np, const double* x, const double* v, const double* r,
+                          const double* pF, double* xn, double* vn, double rho_p, double k_h, double eta, int move,
+                          hipStream_t st);
+template <typename T> void launch_observe(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
+template <typename T>
+void launch_init_pop_flags(const Scalars& S, T* f, const double* rho, double rref, const uint8_t* flags, hipStream_t st);
+template <typename T> void launch_init_ions(const Scalars& S, const Fields<T>& F, T* n, const double* src, hipStream_t st);
+template <typename T> void launch_to_double(const T* src, double* dst, unsigned n, double add, hipStream_t st);
+template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, int k, double* dst, hipStream_t st);
+template <typename T> void launch_upload(T* dst, const double* src, unsigned n, hipStream_t st);
+
+}  // namespace ek

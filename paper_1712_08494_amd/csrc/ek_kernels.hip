@@ -1,0 +1,930 @@
+// HIP kernels (gfx950 / CDNA4) of the coupled electrokinetic lattice step.
+//
+// One step (Rivas et al., arXiv:1712.08494, Sec. II), all stages reading time-t fields:
+//   k_moments  : rho^s, pre-force velocity, Shan-Chen pseudopotentials, charge and
+//                permittivity; FP64 partial sums of the charge          (Sec. II A-C, II E)
+//   k_virtual  : virtual fluid densities on solid sites next to fluid    (Sec. II E)
+//   k_sor      : red-black over-relaxed sweeps of the variable-eps Poisson equation
+//   k_residual : FP64 residual / source / potential sums                 (Sec. II D)
+//   k_force    : total force and physical velocity u = u' + sum Phi / 2 rho
+//   k_fused    : link-flux Nernst-Planck update of both ion species, Shan-Chen +
+//                friction + Kelvin forces, BGK collide with velocity shift, push
+//                streaming with halfway bounce-back and momentum exchange
+//                                                                      (Sec. II A-C, II E)
+//   k_particle_*: particle force sums and integration                    (Sec. II E)
+//
+// Everything here is HBM-bandwidth bound stencil work: no MFMA.  Site kernels map one
+// thread to one site (x fastest, coalesced SoA access) and remap workgroups so that each
+// of the eight XCDs sweeps a contiguous slab of the lattice (its z-neighbour planes stay
+// in that XCD's L2).  Reductions are wave64 shuffles + LDS + a fixed-order final pass,
+// so results are deterministic run to run.
+#include "ek_internal.h"
+#include "ek_lattice.h"
+
+namespace ek {
+
+// ------------------------------------------------------------------------------------
+// Indexing helpers
+// ------------------------------------------------------------------------------------
+unsigned site_blocks(unsigned n) {
+    unsigned b = (n + kBlock - 1) / kBlock;
+    return (b + 7u) & ~7u;  // a multiple of the 8 XCDs, see xcd_linear()
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (XCD = blockIdx % 8).  Give XCD k
+// the contiguous block range [k * nb/8, (k+1) * nb/8) so its L2 holds a slab of planes.
+__device__ __forceinline__ unsigned xcd_linear() {
+    const unsigned nb = gridDim.x;  // multiple of 8 (site_blocks)
+    const unsigned b = blockIdx.x;
+    const unsigned lb = (b & 7u) * (nb >> 3) + (b >> 3);
+    return lb * blockDim.x + threadIdx.x;
+}
+
+struct Nbr {
+    int xm, xp, ym, yp, zm, zp;  // index offsets to the -1/+1 neighbour along each axis (periodic)
+};
+
+__device__ __forceinline__ Nbr make_nbr(int x, int y, int z, const Scalars& S) {
+    Nbr o;
+    o.xm = x == 0 ? S.nx - 1 : -1;
+    o.xp = x == S.nx - 1 ? -(S.nx - 1) : 1;
+    o.ym = y == 0 ? (S.ny - 1) * S.nx : -S.nx;
+    o.yp = y == S.ny - 1 ? -(S.ny - 1) * S.nx : S.nx;
+    o.zm = z == 0 ? (S.nz - 1) * S.nxy : -S.nxy;
+    o.zp = z == S.nz - 1 ? -(S.nz - 1) * S.nxy : S.nxy;
+    return o;
+}
+
+__device__ __forceinline__ int offset_of(const Nbr& o, int d) {
+    return (vx(d) < 0 ? o.xm : (vx(d) > 0 ? o.xp : 0)) + (vy(d) < 0 ? o.ym : (vy(d) > 0 ? o.yp : 0)) +
+           (vz(d) < 0 ? o.zm : (vz(d) > 0 ? o.zp : 0));
+}
+
+__device__ __forceinline__ int wrapc(int a, int n) {
+    return n == 1 ? 0 : (a < 0 ? a + n : (a >= n ? a - n : a));
+}
+
+__device__ __forceinline__ double phi_at(const double* phi, int x, int y, int z, const Scalars& S) {
+    return phi[wrapc(x, S.nx) + S.nx * (wrapc(y, S.ny) + S.ny * wrapc(z, S.nz))];
+}
+
+// Component k of E = -grad(phi) + E_ext at site (x, y, z): central differences, one-sided
+// for the normal component on the wall layers.
+__device__ __forceinline__ double efield(int k, int x, int y, int z, const double* phi, const Scalars& S) {
+    double e;
+    if (k == 0) {
+        e = -0.5 * (phi_at(phi, x + 1, y, z, S) - phi_at(phi, x - 1, y, z, S));
+    } else if (k == 1) {
+        e = -0.5 * (phi_at(phi, x, y + 1, z, S) - phi_at(phi, x, y - 1, z, S));
+    } else {
+        if (S.walls && z == 0)
+            e = -(phi_at(phi, x, y, 1, S) - phi_at(phi, x, y, 0, S));
+        else if (S.walls && z == S.nz - 1)
+            e = -(phi_at(phi, x, y, z, S) - phi_at(phi, x, y, z - 1, S));
+        else
+            e = -0.5 * (phi_at(phi, x, y, z + 1, S) - phi_at(phi, x, y, z - 1, S));
+    }
+    return e + S.E_ext[k];
+}
+
+__device__ __forceinline__ double efield_sq(int x, int y, int z, const double* phi, const Scalars& S) {
+    double a = efield(0, x, y, z, phi, S), b = efield(1, x, y, z, phi, S), c = efield(2, x, y, z, phi, S);
+    return a * a + b * b + c * c;
+}
+
+__device__ __forceinline__ bool wall_layer(int z, const Scalars& S) { return S.walls && (z == 0 || z == S.nz - 1); }
+
+template <typename T>
+__device__ __forceinline__ bool solid_at(unsigned j, int zj, const Scalars& S, const Fields<T>& F) {
+    return S.colloids ? (F.flags[j] & 1u) != 0 : wall_layer(zj, S);
+}
+
+template <typename T>
+__device__ __forceinline__ T psif_at(unsigned j, int zj, const Scalars& S, const Fields<T>& F) {
+    return S.colloids ? F.psif[j] : (wall_layer(zj, S) ? T(0) : T(1));
+}
+
+template <typename T> __device__ __forceinline__ T expT(T v);
+template <> __device__ __forceinline__ float expT<float>(float v) { return expf(v); }
+template <> __device__ __forceinline__ double expT<double>(double v) { return exp(v); }
+
+template <typename T> __device__ __forceinline__ T pseudo(T rho, const Scalars& S) {
+    // psi = rho0 (1 - exp(-rho / rho0)), Sec. II C
+    const T r0 = T(S.rho0);
+    return r0 * (T(1) - expT<T>(-rho / r0));
+}
+
+// Fluid permittivity (eq. dielectric_constant) mixed with the particle permittivity
+// by the solid fraction (Sec. II E).
+template <typename T> __device__ __forceinline__ T eps_fluid(T ra, T rb, const Scalars& S) {
+    const T rt = ra + rb;
+    const T c = rt > T(0) ? (rb - ra) / rt : T(0);
+    return T(0.5) * (T(S.eps_a) * (T(1) - c) + T(S.eps_b) * (T(1) + c));
+}
+
+// ------------------------------------------------------------------------------------
+// FP64 block reduction of NV values (sums, or maxima where is_max) into red[blockIdx].
+// ------------------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NV], const bool (&is_max)[NV], double* red) {
+    __shared__ double sm[NV][kBlock / 64];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double a = v[k];
+#pragma unroll
+        for (int s = 32; s > 0; s >>= 1) {
+            double b = __shfl_down(a, s, 64);
+            a = is_max[k] ? fmax(a, b) : a + b;
+        }
+        v[k] = a;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sm[k][wid] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double a = sm[k][0];
+            for (int w = 1; w < kBlock / 64; ++w) a = is_max[k] ? fmax(a, sm[k][w]) : a + sm[k][w];
+            red[(size_t)blockIdx.x * kRedSlots + k] = a;
+        }
+    }
+}
+
+// Sums (or maxima) of nvals values over nblk partial records, fixed order: deterministic.
+__global__ void k_reduce(const double* __restrict__ red, unsigned nblk, int nvals, const int* is_max_d,
+                         double* __restrict__ out) {
+    __shared__ double sm[kRedSlots][kBlock];
+    int is_max[kRedSlots];
+    for (int k = 0; k < kRedSlots; ++k) is_max[k] = (k < nvals && is_max_d) ? is_max_d[k] : 0;
+    for (int k = 0; k < nvals; ++k) {
+        double a = is_max[k] ? -1e300 : 0.0;
+        for (unsigned b = threadIdx.x; b < nblk; b += blockDim.x) {
+            double v = red[(size_t)b * kRedSlots + k];
+            a = is_max[k] ? fmax(a, v) : a + v;
+        }
+        sm[k][threadIdx.x] = a;
+    }
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < nvals; ++k)
+                sm[k][threadIdx.x] = is_max[k] ? fmax(sm[k][threadIdx.x], sm[k][threadIdx.x + s])
+                                               : sm[k][threadIdx.x] + sm[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < nvals; ++k) out[k] = sm[k][0];
+}
+
+void launch_reduce(const double* red, unsigned nblk, int nvals, const int* is_max, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, red, nblk, nvals, is_max, out);
+}
+
+// ------------------------------------------------------------------------------------
+// Step 1: moments, pseudopotentials, charge and permittivity.
+// Populations are stored as deviations g_d = f_d - w_d rho_ref (both precisions), so
+//   rho = rho_ref + sum_d g_d,  rho u = sum_d g_d c_d   (sum_d w_d c_d = 0).
+// ------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_moments(Scalars S, Fields<T> F) {
+    const unsigned i = xcd_linear();
+    const bool valid = i < S.N;
+    double qsum = 0.0;
+    if (valid) {
+        const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+        const bool solid = solid_at(i, z, S, F);
+        T ra = 0, rb = 0, ux = 0, uy = 0, uz = 0, pa = 0, pb = 0;
+        if (!solid) {
+            T sa = 0, sb = 0, mx = 0, my = 0, mz = 0;
+#pragma unroll
+            for (int d = 0; d < kQ; ++d) {
+                const T a = F.f[0][(size_t)d * S.N + i];
+                const T b = F.f[1][(size_t)d * S.N + i];
+                sa += a;
+                sb += b;
+                const T s = a + b;
+                if (vx(d) > 0) mx += s;
+                if (vx(d) < 0) mx -= s;
+                if (vy(d) > 0) my += s;
+                if (vy(d) < 0) my -= s;
+                if (vz(d) > 0) mz += s;
+                if (vz(d) < 0) mz -= s;
+            }
+            ra = T(S.rref[0]) + sa;
+            rb = T(S.rref[1]) + sb;
+            const T rt = ra + rb;
+            ux = mx / rt;
+            uy = my / rt;
+            uz = mz / rt;
+            pa = pseudo<T>(ra, S);
+            pb = pseudo<T>(rb, S);
+        }
+        F.mom[i] = ra;
+        F.mom[(size_t)S.N + i] = rb;
+        F.mom[2 * (size_t)S.N + i] = pa;
+        F.mom[3 * (size_t)S.N + i] = pb;
+        F.mom[4 * (size_t)S.N + i] = ux;
+        F.mom[5 * (size_t)S.N + i] = uy;
+        F.mom[6 * (size_t)S.N + i] = uz;
+        const T qc = S.colloids ? F.qc[i] : T(0);
+        const T q = F.n[0][i] - F.n[1][i] + qc;
+        const T psis = T(1) - psif_at(i, z, S, F);
+        const T ef = eps_fluid<T>(ra, rb, S);
+        F.q[i] = q;
+        F.eps[i] = T(S.eps_p) * psis + ef * (T(1) - psis);
+        if (z >= S.z0 && z <= S.z1) qsum = (double)q;
+        (void)x;
+    }
+    double v[1] = {qsum};
+    const bool mx[1] = {false};
+    block_reduce_store<1>(v, mx, F.red);
+}
+
+template <typename T> void launch_moments(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_moments<T>, dim3(nblk), dim3(kBlock), 0, st, S, F);
+}
+
+// Virtual densities (Sec. II E, after Jansen et al.): a solid site with a fluid D3Q19
+// neighbour carries the mean density of its fluid neighbours, used only by the
+// Shan-Chen sums (and the permittivity of partly covered sites).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_virtual(Scalars S, Fields<T> F) {
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if ((int)t >= F.nv) return;
+    const unsigned i = (unsigned)F.vlist[t];
+    const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+    const Nbr o = make_nbr(x, y, z, S);
+    T sa = 0, sb = 0;
+    int cnt = 0;
+#pragma unroll
+    for (int d = 0; d < kQ; ++d) {
+        if (d == kRest) continue;
+        const unsigned j = i + offset_of(o, d);
+        const int zj = wrapc(z + vz(d), S.nz);
+        if (solid_at(j, zj, S, F)) continue;
+        sa += F.mom[j];
+        sb += F.mom[(size_t)S.N + j];
+        ++cnt;
+    }
+    if (cnt == 0) return;
+    const T ra = sa / T(cnt), rb = sb / T(cnt);
+    F.mom[i] = ra;
+    F.mom[(size_t)S.N + i] = rb;
+    F.mom[2 * (size_t)S.N + i] = pseudo<T>(ra, S);
+    F.mom[3 * (size_t)S.N + i] = pseudo<T>(rb, S);
+    const T psis = T(1) - psif_at(i, z, S, F);
+    F.eps[i] = T(S.eps_p) * psis + eps_fluid<T>(ra, rb, S) * (T(1) - psis);
+}
+
+template <typename T> void launch_virtual(const Scalars& S, const Fields<T>& F, hipStream_t st) {
+    if (F.nv <= 0) return;
+    hipLaunchKernelGGL(k_virtual<T>, dim3((F.nv + kBlock - 1) / kBlock), dim3(kBlock), 0, st, S, F);
+}
+
+// Mean of the Poisson source over the domain: (sum q + wall charges) / sites.
+__global__ void k_source_mean(Scalars S, const double* __restrict__ red, unsigned nblk, double* scal) {
+    __shared__ double sm[kBlock];
+    double a = 0.0;
+    for (unsigned b = threadIdx.x; b < nblk; b += blockDim.x) a += red[(size_t)b * kRedSlots];
+    sm[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double tot = sm[0];
+        if (S.walls) tot += (S.sigma0 + S.sigma1) * (double)S.nxy;
+        scal[0] = tot / (double)S.ndomain;
+    }
+}
+
+void launch_source_mean(const Scalars& S, double* red, unsigned nblk, double* scal, hipStream_t st) {
+    hipLaunchKernelGGL(k_source_mean, dim3(1), dim3(kBlock), 0, st, S, red, nblk, scal);
+}
+
+// ------------------------------------------------------------------------------------
+// Poisson (Sec. II D): sum_{Q6} eps_f (phi_j - phi_i) = -s_i, eps_f = (eps_i + eps_j)/2,
+// s = q + wall charge in the layer next to a wall - mean.  Links leaving the domain (the
+// wall faces) carry no flux; links of an axis of length 1 join a site to itself and
+// contribute nothing, so they are skipped.
+// ------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void poisson_row(unsigned i, int x, int y, int z, const Scalars& S, const Fields<T>& F,
+                                            double& diag, double& offsum, double& src) {
+    const double ei = (double)F.eps[i];
+    diag = 0.0;
+    offsum = 0.0;
+    if (S.nx > 1) {
+        const unsigned a = i + (x == 0 ? S.nx - 1 : -1), b = i + (x == S.nx - 1 ? -(S.nx - 1) : 1);
+        const double ea = 0.5 * (ei + (double)F.eps[a]), eb = 0.5 * (ei + (double)F.eps[b]);
+        diag += ea + eb;
+        offsum += ea * F.phi[a] + eb * F.phi[b];
+    }
+    if (S.ny > 1) {
+        const unsigned a = i + (y == 0 ? (S.ny - 1) * S.nx : -S.nx), b = i + (y == S.ny - 1 ? -(S.ny - 1) * S.nx : S.nx);
+        const double ea = 0.5 * (ei + (double)F.eps[a]), eb = 0.5 * (ei + (double)F.eps[b]);
+        diag += ea + eb;
+        offsum += ea * F.phi[a] + eb * F.phi[b];
+    }
+    if (S.nz > 1) {
+        if (!(S.walls && z == S.z0)) {
+            const unsigned a = i + (z == 0 ? (S.nz - 1) * S.nxy : -S.nxy);
+            const double ea = 0.5 * (ei + (double)F.eps[a]);
+            diag += ea;
+            offsum += ea * F.phi[a];
+        }
+        if (!(S.walls && z == S.z1)) {
+            const unsigned b = i + (z == S.nz - 1 ? -(S.nz - 1) * S.nxy : S.nxy);
+            const double eb = 0.5 * (ei + (double)F.eps[b]);
+            diag += eb;
+            offsum += eb * F.phi[b];
+        }
+    }
+    double s = (double)F.q[i];
+    if (S.walls && z == S.z0) s += S.sigma0;
+    if (S.walls && z == S.z1) s += S.sigma1;
+    src = s - F.scal[0];
+}
+
+// One colour of a red-black sweep; thread -> site of that colour ((x + y + z) % 2 == color).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sor(Scalars S, Fields<T> F, int color, double omega) {
+    const unsigned t = xcd_linear();
+    const unsigned half = (unsigned)(S.nx >> 1);
+    const unsigned rows = (unsigned)S.ny * (unsigned)(S.z1 - S.z0 + 1);
+    if (t >= half * rows) return;
+    const unsigned row = t / half, m = t % half;
+    const int y = row % S.ny, z = S.z0 + row / S.ny;
+    const int x = 2 * m + ((color + y + z) & 1);
+    const unsigned i = x + S.nx * (y + S.ny * z);
+    double diag, offsum, src;
+    poisson_row<T>(i, x, y, z, S, F, diag, offsum, src);
+    if (diag <= 0.0) return;
+    const double gs = (offsum + src) / diag;
+    F.phi[i] = F.phi[i] + omega * (gs - F.phi[i]);
+}
+
+template <typename T> void launch_sor(const Scalars& S, const Fields<T>& F, int color, double omega, hipStream_t st) {
+    const unsigned n = (unsigned)(S.nx / 2) * S.ny * (S.z1 - S.z0 + 1);
+    hipLaunchKernelGGL(k_sor<T>, dim3(site_blocks(n)), dim3(kBlock), 0, st, S, F, color, omega);
+}
+
+// Residual r = s + A phi: FP64 partial sums of r.r, s.s and phi over the domain.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual(Scalars S, Fields<T> F) {
+    const unsigned i = xcd_linear();
+    double v[3] = {0.0, 0.0, 0.0};
+    if (i < S.N) {
+        const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+        if (z >= S.z0 && z <= S.z1) {
+            double diag, offsum, src;
+            poisson_row<T>(i, x, y, z, S, F, diag, offsum, src);
+            const double res = src + offsum - diag * F.phi[i];
+            v[0] = res * res;
+            v[1] = src * src;
+            v[2] = F.phi[i];
+        }
+    }
+    const bool mx[3] = {false, false, false};
+    block_reduce_store<3>(v, mx, F.red);
+}
+
+template <typename T> void launch_residual(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_residual<T>, dim3(nblk), dim3(kBlock), 0, st, S, F);
+}
+
+// Gauge mean(phi) = 0 over the domain (scal[3] = sum of phi), or phi = 0 when zero != 0.
+__global__ __launch_bounds__(kBlock) void k_phi_finalize(Scalars S, double* phi, const double* scal, int zero) {
+    const unsigned i = xcd_linear();
+    if (i >= S.N) return;
+    const int z = (i / S.nx) / S.ny;
+    if (z < S.z0 || z > S.z1) return;
+    phi[i] = zero ? 0.0 : phi[i] - scal[3] / (double)S.ndomain;
+}
+
+void launch_phi_finalize(const Scalars& S, double* phi, const double* scal, int zero, hipStream_t st) {
+    hipLaunchKernelGGL(k_phi_finalize, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, phi, scal, zero);
+}
+
+// Wall layers: Gauss's law at the charged wall face, phi_wall = phi_adjacent + sigma / eps_adjacent.
+template <typename T>
+__global__ void k_phi_ghosts(Scalars S, Fields<T> F) {
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (unsigned)S.nxy) return;
+    const unsigned a1 = t + S.nxy, a0 = t;
+    const unsigned b1 = t + (unsigned)(S.nz - 2) * S.nxy, b0 = t + (unsigned)(S.nz - 1) * S.nxy;
+    F.phi[a0] = F.phi[a1] + S.sigma0 / (double)F.eps[a1];
+    F.phi[b0] = F.phi[b1] + S.sigma1 / (double)F.eps[b1];
+}
+
+template <typename T> void launch_phi_ghosts(const Scalars& S, const Fields<T>& F, hipStream_t st) {
+    if (!S.walls) return;
+    hipLaunchKernelGGL(k_phi_ghosts<T>, dim3((S.nxy + kBlock - 1) / kBlock), dim3(kBlock), 0, st, S, F);
+}
+
+// ------------------------------------------------------------------------------------
+// Link fluxes (Sec. II B, II E eq. ionic-fluxes-disc-2), for the link lo -> hi along axis k:
+//   J = -D psi_f(lo) psi_f(hi) [ (n~_hi - n~_lo) - (beta/4)(q~_lo + q~_hi)(E_lo + E_hi)_k
+//                              + s (beta dmu / 2 drho_a)(n~_lo + n~_hi)(rho^a_hi - rho^a_lo) ]
+// n~ = n / psi_f, q~ = z e n~.  Both end sites evaluate a link with identical operands in
+// identical order, so the two see bit-identical fluxes and the update conserves ions.
+// ------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void link_flux(T nplo, T nmlo, T nphi, T nmhi, T pflo, T pfhi, T Elo, T Ehi, T ralo,
+                                          T rahi, const Scalars& S, T& Jp, T& Jm) {
+#pragma clang fp contract(off)
+    if (pflo > T(0) && pfhi > T(0)) {
+        const T tpl = nplo / pflo, tph = nphi / pfhi, tml = nmlo / pflo, tmh = nmhi / pfhi;
+        const T es = Elo + Ehi;
+        const T dra = rahi - ralo;
+        const T qb = T(0.25) * T(S.beta);
+        const T bp = (tph - tpl) - qb * (tpl + tph) * es + T(S.kap_p) * (tpl + tph) * dra;
+        const T bm = (tmh - tml) + qb * (tml + tmh) * es + T(S.kap_m) * (tml + tmh) * dra;
+        const T w = -T(S.D) * pflo * pfhi;
+        Jp = w * bp;
+        Jm = w * bm;
+    } else {
+        Jp = T(0);
+        Jm = T(0);
+    }
+}
+
+// Donor-cell advection across lo -> hi (only between LB-fluid sites).
+template <typename T>
+__device__ __forceinline__ T advect(T nlo, T nhi, T ulo, T uhi) {
+#pragma clang fp contract(off)
+    return nlo * (ulo > T(0) ? ulo : T(0)) - nhi * (uhi < T(0) ? -uhi : T(0));
+}
+
+// The six links of site i: friction sums (sum over species of J on the +k and -k link,
+// per axis) and, when update is set, the new ion densities.
+template <typename T, bool kUpdate>
+__device__ __forceinline__ void site_links(unsigned i, int x, int y, int z, const Nbr& o, bool solid_i,
+                                           const Scalars& S, const Fields<T>& F, T (&jsum)[3], T& np_new,
+                                           T& nm_new) {
+    const T np_i = F.n[0][i], nm_i = F.n[1][i];
+    const T pf_i = psif_at(i, z, S, F);
+    const T ra_i = F.mom[i];
+    T out_p = T(0), out_m = T(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int offm = k == 0 ? o.xm : (k == 1 ? o.ym : o.zm);
+        const int offp = k == 0 ? o.xp : (k == 1 ? o.yp : o.zp);
+        const unsigned lo = i + offm, hi = i + offp;
+        const int zlo = k == 2 ? wrapc(z - 1, S.nz) : z, zhi = k == 2 ? wrapc(z + 1, S.nz) : z;
+        const int xlo = k == 0 ? wrapc(x - 1, S.nx) : x, xhi = k == 0 ? wrapc(x + 1, S.nx) : x;
+        const int ylo = k == 1 ? wrapc(y - 1, S.ny) : y, yhi = k == 1 ? wrapc(y + 1, S.ny) : y;
+        const T E_i = (T)efield(k, x, y, z, F.phi, S);
+        const T E_lo = (T)efield(k, xlo, ylo, zlo, F.phi, S);
+        const T E_hi = (T)efield(k, xhi, yhi, zhi, F.phi, S);
+        const T np_lo = F.n[0][lo], nm_lo = F.n[1][lo], np_hi = F.n[0][hi], nm_hi = F.n[1][hi];
+        const T pf_lo = psif_at(lo, zlo, S, F), pf_hi = psif_at(hi, zhi, S, F);
+        const T ra_lo = F.mom[lo], ra_hi = F.mom[hi];
+        T Jp_lo, Jm_lo, Jp_hi, Jm_hi;
+        link_flux<T>(np_lo, nm_lo, np_i, nm_i, pf_lo, pf_i, E_lo, E_i, ra_lo, ra_i, S, Jp_lo, Jm_lo);
+        link_flux<T>(np_i, nm_i, np_hi, nm_hi, pf_i, pf_hi, E_i, E_hi, ra_i, ra_hi, S, Jp_hi, Jm_hi);
+        jsum[k] = ((Jp_hi + Jp_lo) + Jm_hi) + Jm_lo;
+        if (kUpdate) {
+            T Ap_lo = 0, Am_lo = 0, Ap_hi = 0, Am_hi = 0;
+            if (!solid_i) {
+                const T u_i = F.uph[(size_t)k * S.N + i];
+                if (!solid_at(lo, zlo, S, F)) {
+                    const T u_lo = F.uph[(size_t)k * S.N + lo];
+                    Ap_lo = advect<T>(np_lo, np_i, u_lo, u_i);
+                    Am_lo = advect<T>(nm_lo, nm_i, u_lo, u_i);
+                }
+                if (!solid_at(hi, zhi, S, F)) {
+                    const T u_hi = F.uph[(size_t)k * S.N + hi];
+                    Ap_hi = advect<T>(np_i, np_hi, u_i, u_hi);
+                    Am_hi = advect<T>(nm_i, nm_hi, u_i, u_hi);
+                }
+            }
+            out_p += (Jp_hi + Ap_hi) - (Jp_lo + Ap_lo);
+            out_m += (Jm_hi + Am_hi) - (Jm_lo + Am_lo);
+        }
+    }
+    if (kUpdate) {
+        np_new = np_i - out_p;
+        nm_new = nm_i - out_m;
+    }
+}
+
+// Forces on both fluid components at fluid site i (Sec. II C):
+//   Phi^a = -psi^a sum_d w_d [G psi^b + G_a+ n+ + G_a- n-](i+d) c_d + (rho^a/rho) F
+//   Phi^b = -psi^b sum_d w_d  G psi^a(i+d) c_d                      + (rho^b/rho) F
+//   F = (1/(2 beta D)) sum_{Q6} sum_+- J c_d  -  ((eps_f - eps_bar)/4) sum_{Q6} E^2(i+d) c_d  +  rho g
+// Ion pseudopotentials count on LB-fluid neighbours only; solid neighbours next to fluid
+// carry virtual densities.
+template <typename T>
+__device__ __forceinline__ void site_forces(unsigned i, int x, int y, int z, const Nbr& o, T ra, T rb,
+                                            const T (&jsum)[3], const Scalars& S, const Fields<T>& F, T (&Pa)[3],
+                                            T (&Pb)[3]) {
+    const T psa = F.mom[2 * (size_t)S.N + i], psb = F.mom[3 * (size_t)S.N + i];
+    T sa[3] = {0, 0, 0}, sb[3] = {0, 0, 0};
+    const T G = T(S.G);
+#pragma unroll
+    for (int d = 0; d < kQ; ++d) {
+        if (d == kRest) continue;
+        const unsigned j = i + offset_of(o, d);
+        const T w = T(weight(d));
+        const T pa_j = F.mom[2 * (size_t)S.N + j], pb_j = F.mom[3 * (size_t)S.N + j];
+        T ion = T(0);
+        if (S.ion_sc) {
+            const int zj = wrapc(z + vz(d), S.nz);
+            if (!solid_at(j, zj, S, F)) ion = T(S.G_p) * F.n[0][j] + T(S.G_m) * F.n[1][j];
+        }
+        const T ta = w * (G * pb_j + ion);
+        const T tb = w * (G * pa_j);
+        if (vx(d) > 0) { sa[0] += ta; sb[0] += tb; }
+        if (vx(d) < 0) { sa[0] -= ta; sb[0] -= tb; }
+        if (vy(d) > 0) { sa[1] += ta; sb[1] += tb; }
+        if (vy(d) < 0) { sa[1] -= ta; sb[1] -= tb; }
+        if (vz(d) > 0) { sa[2] += ta; sb[2] += tb; }
+        if (vz(d) < 0) { sa[2] -= ta; sb[2] -= tb; }
+    }
+    T FK[3] = {0, 0, 0};
+    if (S.kelvin) {
+        const T fac = T(-0.25) * (eps_fluid<T>(ra, rb, S) - T(S.eps_bar));
+        const int xm = wrapc(x - 1, S.nx), xp = wrapc(x + 1, S.nx);
+        const int ym = wrapc(y - 1, S.ny), yp = wrapc(y + 1, S.ny);
+        const int zm = wrapc(z - 1, S.nz), zp = wrapc(z + 1, S.nz);
+        FK[0] = fac * (T)(efield_sq(xp, y, z, F.phi, S) - efield_sq(xm, y, z, F.phi, S));
+        FK[1] = fac * (T)(efield_sq(x, yp, z, F.phi, S) - efield_sq(x, ym, z, F.phi, S));
+        FK[2] = fac * (T)(efield_sq(x, y, zp, F.phi, S) - efield_sq(x, y, zm, F.phi, S));
+    }
+    const T rt = ra + rb;
+    const T ifr = T(0.5) / (T(S.beta) * T(S.D));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const T Frest = jsum[k] * ifr + FK[k] + rt * T(S.g_body[k]);
+        Pa[k] = -psa * sa[k] + (ra / rt) * Frest;
+        Pb[k] = -psb * sb[k] + (rb / rt) * Frest;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Total force and physical velocity u = u' + (Phi^a + Phi^b) / (2 rho) of every fluid
+// site (needed by the donor-cell ion advection of the neighbours).
+// ------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_force(Scalars S, Fields<T> F) {
+    const unsigned i = xcd_linear();
+    if (i >= S.N) return;
+    const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+    if (solid_at(i, z, S, F)) {
+        F.uph[i] = T(0);
+        F.uph[(size_t)S.N + i] = T(0);
+        F.uph[2 * (size_t)S.N + i] = T(0);
+        return;
+    }
+    const Nbr o = make_nbr(x, y, z, S);
+    T jsum[3], dummy_p, dummy_m;
+    site_links<T, false>(i, x, y, z, o, false, S, F, jsum, dummy_p, dummy_m);
+    const T ra = F.mom[i], rb = F.mom[(size_t)S.N + i];
+    T Pa[3], Pb[3];
+    site_forces<T>(i, x, y, z, o, ra, rb, jsum, S, F, Pa, Pb);
+    const T rt2 = T(2) * (ra + rb);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) F.uph[(size_t)k * S.N + i] = F.mom[(size_t)(4 + k) * S.N + i] + (Pa[k] + Pb[k]) / rt2;
+}
+
+template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hipStream_t st) {
+    hipLaunchKernelGGL(k_force<T>, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F);
+}
+
+// ------------------------------------------------------------------------------------
+// Fused sweep: ion update (all sites), then for fluid sites forces, BGK collision with
+// the velocity shift u_e^s = u' + tau Phi^s / rho^s (Sec. II A) and push streaming.
+// A population headed into a solid site returns half-way (Sec. II E):
+//   g_{d*}(i, t+1) = g*_d(i) - 6 w_d rho^s(i) (c_d . v)      (w_d = w_{d*})
+// and, for a particle site, the momentum (2 f*_d - 6 w_d rho^s (c_d . v)) c_d is written
+// to the link's record (deterministic per-particle sum later).
+// ------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fused(Scalars S, Fields<T> F) {
+    const unsigned i = xcd_linear();
+    if (i >= S.N) return;
+    const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+    const Nbr o = make_nbr(x, y, z, S);
+    const bool solid_i = solid_at(i, z, S, F);
+    T jsum[3], np_new, nm_new;
+    site_links<T, true>(i, x, y, z, o, solid_i, S, F, jsum, np_new, nm_new);
+    F.nn[0][i] = np_new;
+    F.nn[1][i] = nm_new;
+    if (solid_i) return;
+
+    // moments of the time-t populations (same arithmetic as k_moments)
+    T g[2][kQ];
+    T sa = 0, sb = 0, mx = 0, my = 0, mz = 0;
+#pragma unroll
+    for (int d = 0; d < kQ; ++d) {
+        g[0][d] = F.f[0][(size_t)d * S.N + i];
+        g[1][d] = F.f[1][(size_t)d * S.N + i];
+        sa += g[0][d];
+        sb += g[1][d];
+        const T s = g[0][d] + g[1][d];
+        if (vx(d) > 0) mx += s;
+        if (vx(d) < 0) mx -= s;
+        if (vy(d) > 0) my += s;
+        if (vy(d) < 0) my -= s;
+        if (vz(d) > 0) mz += s;
+        if (vz(d) < 0) mz -= s;
+    }
+    const T ra = T(S.rref[0]) + sa, rb = T(S.rref[1]) + sb;
+    const T rt = ra + rb;
+    const T u0[3] = {mx / rt, my / rt, mz / rt};
+    T Pa[3], Pb[3];
+    site_forces<T>(i, x, y, z, o, ra, rb, jsum, S, F, Pa, Pb);
+
+    const bool near = S.colloids ? (F.flags[i] & 2u) != 0 : (S.walls && (z == 1 || z == S.nz - 2));
+    int link = near && S.colloids ? F.linkbase[i] : 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const T rs = c == 0 ? ra : rb;
+        const T dr = c == 0 ? sa : sb;
+        const T P0 = c == 0 ? Pa[0] : Pb[0], P1 = c == 0 ? Pa[1] : Pb[1], P2 = c == 0 ? Pa[2] : Pb[2];
+        const T tau = T(S.tau);
+        const T ue0 = u0[0] + tau * P0 / rs, ue1 = u0[1] + tau * P1 / rs, ue2 = u0[2] + tau * P2 / rs;
+        const T usq = ue0 * ue0 + ue1 * ue1 + ue2 * ue2;
+        int lk = link;
+#pragma unroll
+        for (int d = 0; d < kQ; ++d) {
+            const T cu = T(vx(d)) * ue0 + T(vy(d)) * ue1 + T(vz(d)) * ue2;
+            const T w = T(weight(d));
+            const T geq = w * (dr + rs * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq));
+            const T gs = g[c][d] - (g[c][d] - geq) * T(S.inv_tau);
+            const unsigned j = i + offset_of(o, d);
+            bool bounce = false;
+            if (d != kRest && near) bounce = solid_at(j, wrapc(z + vz(d), S.nz), S, F);
+            if (bounce) {
+                T cv = T(0);
+                int own = -1;
+                if (S.colloids) {
+                    own = F.owner[j];
+                    if (own >= 0)
+                        cv = T(vx(d)) * T(F.pv[3 * own]) + T(vy(d)) * T(F.pv[3 * own + 1]) +
+                             T(vz(d)) * T(F.pv[3 * own + 2]);
+                }
+                const T corr = T(6) * w * rs * cv;
+                F.fn[c][(size_t)opposite(d) * S.N + i] = gs - corr;
+                if (own >= 0) {
+                    const double dp = 2.0 * ((double)gs + weight(d) * S.rref[c]) - (double)corr;
+                    double* rec = F.linkdp + (size_t)lk * 6 + 3 * c;
+                    rec[0] = dp * vx(d);
+                    rec[1] = dp * vy(d);
+                    rec[2] = dp * vz(d);
+                    ++lk;
+                }
+            } else {
+                F.fn[c][(size_t)d * S.N + j] = gs;
+            }
+        }
+    }
+}
+
+template <typename T> void launch_fused(const Scalars& S, const Fields<T>& F, hipStream_t st) {
+    hipLaunchKernelGGL(k_fused<T>, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F);
+}
+
+// ------------------------------------------------------------------------------------
+// Particles (Sec. II E): momentum from the particle's links plus q_c E over its sites,
+// one workgroup per particle, fixed-order sums.
+// ------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_particle_sum(Scalars S, Fields<T> F, const int32_t* link_off,
+                                                         const int32_t* link_idx, const int32_t* site_off,
+                                                         const int32_t* site_idx, double* pF) {
+    const int p = blockIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = link_off[p] + threadIdx.x; t < link_off[p + 1]; t += blockDim.x) {
+        const double* rec = F.linkdp + (size_t)link_idx[t] * 6;
+        v[0] += rec[0] + rec[3];
+        v[1] += rec[1] + rec[4];
+        v[2] += rec[2] + rec[5];
+    }
+    for (int t = site_off[p] + threadIdx.x; t < site_off[p + 1]; t += blockDim.x) {
+        const unsigned i = (unsigned)site_idx[t];
+        const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+        const double qv = (double)F.qc[i];
+        v[0] += qv * efield(0, x, y, z, F.phi, S);
+        v[1] += qv * efield(1, x, y, z, F.phi, S);
+        v[2] += qv * efield(2, x, y, z, F.phi, S);
+    }
+    __shared__ double sm[3][kBlock];
+    for (int k = 0; k < 3; ++k) sm[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 3; ++k) sm[k][threadIdx.x] += sm[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) pF[3 * p + k] = sm[k][0];
+}
+
+template <typename T>
+void launch_particle_sum(const Scalars& S, const Fields<T>& F, int np, const int32_t* link_off, const int32_t* link_idx,
+                         const int32_t* site_off, const int32_t* site_idx, double* pF, hipStream_t st) {
+    if (np <= 0) return;
+    hipLaunchKernelGGL(k_particle_sum<T>, dim3(np), dim3(kBlock), 0, st, S, F, link_off, link_idx, site_off, site_idx,
+                       pF);
+}
+
+__device__ __forceinline__ double min_image(double d, int n) {
+    const double L = (double)n;
+    while (d > 0.5 * L) d -= L;
+    while (d < -0.5 * L) d += L;
+    return d;
+}
+
+// Hertz contact (+k_H delta^{3/2} n, repulsive) and lubrication, then symplectic Euler.
+__global__ void k_particle_move(Scalars S, int np, const double* __restrict__ x, const double* __restrict__ v,
+                                const double* __restrict__ rad, double* __restrict__ pF, double* __restrict__ xn,
+                                double* __restrict__ vn, double rho_p, double k_h, double eta, int move) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= np) return;
+    double F[3] = {pF[3 * a], pF[3 * a + 1], pF[3 * a + 2]};
+    const int L[3] = {S.nx, S.ny, S.nz};
+    for (int b = 0; b < np; ++b) {
+        if (b == a) continue;
+        double dv[3], d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            dv[k] = min_image(x[3 * a + k] - x[3 * b + k], L[k]);
+            d2 += dv[k] * dv[k];
+        }
+        const double dist = sqrt(d2);
+        if (dist == 0.0) continue;
+        const double nh[3] = {dv[0] / dist, dv[1] / dist, dv[2] / dist};
+        const double delta = rad[a] + rad[b] - dist;
+        if (delta > 0.0) {
+            const double fh = k_h * pow(delta, 1.5);
+            for (int k = 0; k < 3; ++k) F[k] += fh * nh[k];
+        }
+        const double gap = dist - rad[a] - rad[b];
+        if (gap < 2.0 / 3.0 && gap > 0.0) {
+            const double rp = 0.5 * (rad[a] + rad[b]);
+            double nv = 0.0;
+            for (int k = 0; k < 3; ++k) nv += nh[k] * (v[3 * a + k] - v[3 * b + k]);
+            const double fl = -1.5 * M_PI * eta * rp * rp * nv * (1.0 / gap - 1.0);
+            for (int k = 0; k < 3; ++k) F[k] += fl * nh[k];
+        }
+    }
+    const double m = rho_p * (4.0 / 3.0) * M_PI * rad[a] * rad[a] * rad[a];
+    for (int k = 0; k < 3; ++k) {
+        pF[3 * a + k] = F[k];
+        const double vv = move ? v[3 * a + k] + F[k] / m : v[3 * a + k];
+        vn[3 * a + k] = vv;
+        xn[3 * a + k] = move ? x[3 * a + k] + vv : x[3 * a + k];
+    }
+}
+
+void launch_particle_move(const Scalars& S, int np, const double* x, const double* v, const double* r,
+                          const double* pF, double* xn, double* vn, double rho_p, double k_h, double eta, int move,
+                          hipStream_t st) {
+    if (np <= 0) return;
+    hipLaunchKernelGGL(k_particle_move, dim3((np + 63) / 64), dim3(64), 0, st, S, np, x, v, r, const_cast<double*>(pF),
+                       xn, vn, rho_p, k_h, eta, move);
+}
+
+// ------------------------------------------------------------------------------------
+// Observables: FP64 partial sums of mass, ions, charge, momentum; max |u|; counts of
+// non-finite values and negative ion densities.
+// ------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_observe(Scalars S, Fields<T> F) {
+    const unsigned i = xcd_linear();
+    double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < S.N) {
+        const int z = (i / S.nx) / S.ny;
+        const double np_ = (double)F.n[0][i], nm_ = (double)F.n[1][i];
+        v[2] = np_;
+        v[3] = nm_;
+        v[4] = np_ - nm_ + (S.colloids ? (double)F.qc[i] : 0.0);
+        int bad = !isfinite(np_) || !isfinite(nm_);
+        v[10] = (np_ < 0.0) + (nm_ < 0.0);
+        if (!solid_at(i, z, S, F)) {
+            double sa = 0, sb = 0, m[3] = {0, 0, 0};
+#pragma unroll
+            for (int d = 0; d < kQ; ++d) {
+                const double a = (double)F.f[0][(size_t)d * S.N + i], b = (double)F.f[1][(size_t)d * S.N + i];
+                bad |= !isfinite(a) || !isfinite(b);
+                sa += a;
+                sb += b;
+                m[0] += (a + b) * vx(d);
+                m[1] += (a + b) * vy(d);
+                m[2] += (a + b) * vz(d);
+            }
+            const double ra = S.rref[0] + sa, rb = S.rref[1] + sb;
+            v[0] = ra;
+            v[1] = rb;
+            v[5] = m[0];
+            v[6] = m[1];
+            v[7] = m[2];
+            v[8] = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) / (ra + rb);
+        }
+        v[9] = bad;
+    }
+    const bool mx[11] = {false, false, false, false, false, false, false, false, true, false, false};
+    block_reduce_store<11>(v, mx, F.red);
+}
+
+template <typename T> void launch_observe(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_observe<T>, dim3(nblk), dim3(kBlock), 0, st, S, F);
+}
+
+// ------------------------------------------------------------------------------------
+// Initialisation and export
+// ------------------------------------------------------------------------------------
+// f = f~(rho, u = 0) = w_d rho on fluid sites, stored as g_d = w_d (rho - rho_ref).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init_pop(Scalars S, T* f, const double* rho, double rref,
+                                                      const uint8_t* flags) {
+    const unsigned i = xcd_linear();
+    if (i >= S.N) return;
+    const int z = (i / S.nx) / S.ny;
+    const bool solid = S.colloids ? (flags[i] & 1u) != 0 : wall_layer(z, S);
+    const double dr = solid ? 0.0 : rho[i] - rref;
+#pragma unroll
+    for (int d = 0; d < kQ; ++d) f[(size_t)d * S.N + i] = (T)(weight(d) * dr);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init_ions(Scalars S, Fields<T> F, T* n, const double* src) {
+    const unsigned i = xcd_linear();
+    if (i >= S.N) return;
+    const int z = (i / S.nx) / S.ny;
+    n[i] = (T)(src[i] * (double)psif_at(i, z, S, F));
+}
+
+template <typename T>
+void launch_init_ions(const Scalars& S, const Fields<T>& F, T* n, const double* src, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_ions<T>, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F, n, src);
+}
+
+template <typename T>
+__global__ void k_to_double(const T* __restrict__ src, double* __restrict__ dst, unsigned n, double add) {
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (double)src[i] + add;
+}
+
+template <typename T> void launch_to_double(const T* src, double* dst, unsigned n, double add, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_double<T>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, src, dst, n, add);
+}
+
+template <typename T>
+__global__ void k_upload(T* __restrict__ dst, const double* __restrict__ src, unsigned n) {
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (T)src[i];
+}
+
+template <typename T> void launch_upload(T* dst, const double* src, unsigned n, hipStream_t st) {
+    hipLaunchKernelGGL(k_upload<T>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, dst, src, n);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_field_e(Scalars S, Fields<T> F, int k, double* dst) {
+    const unsigned i = xcd_linear();
+    if (i >= S.N) return;
+    const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+    dst[i] = efield(k, x, y, z, F.phi, S);
+}
+
+template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, int k, double* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_field_e<T>, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F, k, dst);
+}
+
+// explicit instantiations
+#define EK_INST(T)                                                                                              \
+    template void launch_moments<T>(const Scalars&, const Fields<T>&, unsigned, hipStream_t);                  \
+    template void launch_virtual<T>(const Scalars&, const Fields<T>&, hipStream_t);                            \
+    template void launch_sor<T>(const Scalars&, const Fields<T>&, int, double, hipStream_t);                   \
+    template void launch_residual<T>(const Scalars&, const Fields<T>&, unsigned, hipStream_t);                 \
+    template void launch_phi_ghosts<T>(const Scalars&, const Fields<T>&, hipStream_t);                         \
+    template void launch_force<T>(const Scalars&, const Fields<T>&, hipStream_t);                              \
+    template void launch_fused<T>(const Scalars&, const Fields<T>&, hipStream_t);                              \
+    template void launch_particle_sum<T>(const Scalars&, const Fields<T>&, int, const int32_t*, const int32_t*, \
+                                         const int32_t*, const int32_t*, double*, hipStream_t);                \
+    template void launch_observe<T>(const Scalars&, const Fields<T>&, unsigned, hipStream_t);                  \
+    template void launch_init_ions<T>(const Scalars&, const Fields<T>&, T*, const double*, hipStream_t);       \
+    template void launch_to_double<T>(const T*, double*, unsigned, double, hipStream_t);                       \
+    template void launch_field_e<T>(const Scalars&, const Fields<T>&, int, double*, hipStream_t);              \
+    template void launch_upload<T>(T*, const double*, unsigned, hipStream_t);
+
+EK_INST(float)
+EK_INST(double)
+
+// population initialisation needs the flags pointer, exposed separately
+template <typename T>
+void launch_init_pop_flags(const Scalars& S, T* f, const double* rho, double rref, const uint8_t* flags, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_pop<T>, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, f, rho, rref, flags);
+}
+template void launch_init_pop_flags<float>(const Scalars&, float*, const double*, double, const uint8_t*, hipStream_t);
+template void launch_init_pop_flags<double>(const Scalars&, double*, const double*, double, const uint8_t*,
+                                            hipStream_t);
+
+}  // namespace ek

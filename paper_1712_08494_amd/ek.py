@@ -1,0 +1,265 @@
+"""Python binding of ``libek.so`` (the C ABI in ``include/ek.h``).
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels.
+The binding fails loudly when the library is not built; there is no fallback.
+PyTorch supplies the HIP stream the context runs on (its current stream by default).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libek.so")
+
+EK_OK, EK_EINVAL, EK_ENOMEM, EK_EHIP, EK_ENOCONV, EK_ENONFINITE, EK_ESTATE = 0, -1, -2, -3, -4, -5, -6
+EK_FP64, EK_FP32 = 0, 1
+FIELDS = {"rho_a": 0, "rho_b": 1, "n_plus": 2, "n_minus": 3, "phi": 4, "ux": 5, "uy": 6, "uz": 7, "q": 8,
+          "eps": 9, "psi_s": 10, "solid": 11, "Ex": 12, "Ey": 13, "Ez": 14}
+TIMING_CLASSES = ["moments", "poisson", "force", "fused", "particle", "sor"]
+
+
+class EKParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("walls_z", ctypes.c_int32), ("precision", ctypes.c_int32), ("poisson_maxit", ctypes.c_int32),
+        ("subsample", ctypes.c_int32), ("move_particles", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("G", ctypes.c_double), ("rho0", ctypes.c_double),
+        ("rho_ref", ctypes.c_double * 2), ("D", ctypes.c_double), ("beta", ctypes.c_double),
+        ("dmu", ctypes.c_double * 2), ("drho_a", ctypes.c_double), ("solvation_sign", ctypes.c_double),
+        ("eps_a", ctypes.c_double), ("eps_b", ctypes.c_double), ("eps_p", ctypes.c_double),
+        ("E_ext", ctypes.c_double * 3), ("body_accel", ctypes.c_double * 3), ("sigma_wall", ctypes.c_double * 2),
+        ("poisson_tol", ctypes.c_double), ("sor_omega", ctypes.c_double), ("particle_rho", ctypes.c_double),
+        ("k_hertz", ctypes.c_double), ("eta", ctypes.c_double),
+    ]
+
+
+class EKParticle(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_double * 3), ("v", ctypes.c_double * 3), ("radius", ctypes.c_double),
+                ("charge", ctypes.c_double)]
+
+
+class EKObs(ctypes.Structure):
+    _fields_ = [
+        ("sum_rho", ctypes.c_double * 2), ("sum_n", ctypes.c_double * 2), ("sum_q", ctypes.c_double),
+        ("momentum", ctypes.c_double * 3), ("max_u", ctypes.c_double), ("source_mean", ctypes.c_double),
+        ("poisson_rel", ctypes.c_double), ("poisson_iters", ctypes.c_int64), ("poisson_total", ctypes.c_int64),
+        ("steps", ctypes.c_int64), ("drift", ctypes.c_double * 3), ("pmomentum", ctypes.c_double * 3),
+        ("nonfinite", ctypes.c_int32), ("negative_ions", ctypes.c_int32),
+    ]
+
+
+class EKTiming(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 6), ("count", ctypes.c_int64 * 6)]
+
+
+EXPORTS = ["ek_lattice", "ek_init", "ek_step", "ek_poisson", "ek_observables", "ek_get_field",
+           "ek_get_populations", "ek_get_particles", "ek_device_bytes", "ek_set_timing", "ek_get_timing",
+           "ek_destroy", "ek_status_str", "ek_last_error"]
+
+_lib = None
+
+
+class EKError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def load(path=LIB_PATH):
+    """Load libek.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with paper_1712_08494_amd.build.build()")
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    vp = ctypes.c_void_p
+    L.ek_lattice.argtypes = [ctypes.POINTER(ctypes.c_int32), dp]
+    L.ek_lattice.restype = ctypes.c_int32
+    L.ek_init.argtypes = [ctypes.POINTER(EKParams), dp, dp, dp, dp, ctypes.POINTER(EKParticle), ctypes.c_int32, vp,
+                          ctypes.POINTER(vp)]
+    L.ek_init.restype = ctypes.c_int32
+    L.ek_step.argtypes = [vp, ctypes.c_int32]
+    L.ek_step.restype = ctypes.c_int32
+    L.ek_poisson.argtypes = [vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), dp]
+    L.ek_poisson.restype = ctypes.c_int32
+    L.ek_observables.argtypes = [vp, ctypes.POINTER(EKObs)]
+    L.ek_observables.restype = ctypes.c_int32
+    L.ek_get_field.argtypes = [vp, ctypes.c_int32, dp]
+    L.ek_get_field.restype = ctypes.c_int32
+    L.ek_get_populations.argtypes = [vp, ctypes.c_int32, dp]
+    L.ek_get_populations.restype = ctypes.c_int32
+    L.ek_get_particles.argtypes = [vp, dp]
+    L.ek_get_particles.restype = ctypes.c_int32
+    L.ek_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.ek_device_bytes.restype = ctypes.c_int32
+    L.ek_set_timing.argtypes = [vp, ctypes.c_int32]
+    L.ek_set_timing.restype = ctypes.c_int32
+    L.ek_get_timing.argtypes = [vp, ctypes.POINTER(EKTiming)]
+    L.ek_get_timing.restype = ctypes.c_int32
+    L.ek_destroy.argtypes = [vp]
+    L.ek_destroy.restype = ctypes.c_int32
+    L.ek_status_str.argtypes = [ctypes.c_int32]
+    L.ek_status_str.restype = ctypes.c_char_p
+    L.ek_last_error.argtypes = [vp]
+    L.ek_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def lattice():
+    """The library's D3Q19 velocities (19x3) and weights (19)."""
+    L = load()
+    c = np.zeros((19, 3), dtype=np.int32)
+    w = np.zeros(19)
+    L.ek_lattice(c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return c, w
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def params_from_config(cfg):
+    """Pack a workloads.EKConfig into the ek_params struct."""
+    p = EKParams()
+    p.nx, p.ny, p.nz = cfg.nx, cfg.ny, cfg.nz
+    p.walls_z = int(bool(cfg.walls_z))
+    p.precision = EK_FP32 if cfg.precision == "fp32" else EK_FP64
+    p.poisson_maxit = int(cfg.poisson_maxit)
+    p.subsample = int(cfg.subsample)
+    p.move_particles = int(bool(cfg.move_particles))
+    p.tau, p.G, p.rho0 = cfg.tau, cfg.G, cfg.rho0
+    p.rho_ref[0] = p.rho_ref[1] = 0.0
+    p.D, p.beta = cfg.D, cfg.beta
+    p.dmu[0], p.dmu[1] = cfg.dmu_plus, cfg.dmu_minus
+    p.drho_a, p.solvation_sign = cfg.drho_a, cfg.solvation_sign
+    p.eps_a, p.eps_b, p.eps_p = cfg.eps_a, cfg.eps_b, cfg.eps_p
+    for k in range(3):
+        p.E_ext[k] = cfg.E_ext[k]
+        p.body_accel[k] = cfg.body_accel[k]
+    p.sigma_wall[0], p.sigma_wall[1] = cfg.sigma_wall
+    p.poisson_tol = cfg.poisson_tol
+    p.sor_omega = 0.0
+    p.particle_rho, p.k_hertz, p.eta = cfg.particle_rho, cfg.k_hertz, cfg.eta
+    return p
+
+
+def current_stream_handle():
+    """Raw hipStream_t of PyTorch's current stream on the current device."""
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class EKSim:
+    """A simulation context on the GPU.  Fields come back as (nz, ny, nx) float64 arrays."""
+
+    def __init__(self, cfg, inputs, stream=None, params=None):
+        L = load()
+        self.cfg = cfg
+        self.shape = (cfg.nz, cfg.ny, cfg.nx)
+        self.N = cfg.nx * cfg.ny * cfg.nz
+        self._p = params if params is not None else params_from_config(cfg)
+        ra, rb = _c64(inputs.rho_a), _c64(inputs.rho_b)
+        npl, nmi = _c64(inputs.n_plus), _c64(inputs.n_minus)
+        parts = inputs.particles
+        self.np = 0 if parts is None else int(parts.shape[0])
+        arr = (EKParticle * max(self.np, 1))()
+        for j in range(self.np):
+            for k in range(3):
+                arr[j].x[k] = parts[j, k]
+                arr[j].v[k] = parts[j, 3 + k]
+            arr[j].radius = parts[j, 6]
+            arr[j].charge = parts[j, 7]
+        if stream is None:
+            stream = current_stream_handle()
+        self._stream = stream
+        h = ctypes.c_void_p()
+        st = L.ek_init(ctypes.byref(self._p), _dp(ra), _dp(rb), _dp(npl), _dp(nmi),
+                       arr if self.np else None, self.np, stream, ctypes.byref(h))
+        self._h = h
+        if st != EK_OK:
+            msg = self.last_error()
+            self.close()
+            raise EKError(st, "ek_init: " + msg)
+
+    def last_error(self):
+        if not self._h:
+            return ""
+        return load().ek_last_error(self._h).decode()
+
+    def _check(self, st, what, allow=()):
+        if st != EK_OK and st not in allow:
+            raise EKError(st, f"{what}: {self.last_error()}")
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().ek_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1, allow_noconv=False):
+        return self._check(load().ek_step(self._h, int(n)), "ek_step", (EK_ENOCONV,) if allow_noconv else ())
+
+    def poisson(self, tol, maxit):
+        it = ctypes.c_int32(0)
+        rel = ctypes.c_double(0.0)
+        st = load().ek_poisson(self._h, float(tol), int(maxit), ctypes.byref(it), ctypes.byref(rel))
+        self._check(st, "ek_poisson", (EK_ENOCONV,))
+        return st, it.value, rel.value
+
+    def observables(self):
+        o = EKObs()
+        st = load().ek_observables(self._h, ctypes.byref(o))
+        self._check(st, "ek_observables", (EK_ENONFINITE,))
+        return {
+            "status": st,
+            "sum_rho_a": o.sum_rho[0], "sum_rho_b": o.sum_rho[1], "sum_n_plus": o.sum_n[0],
+            "sum_n_minus": o.sum_n[1], "sum_q": o.sum_q, "mom_x": o.momentum[0], "mom_y": o.momentum[1],
+            "mom_z": o.momentum[2], "max_u": o.max_u, "source_mean": o.source_mean, "poisson_rel": o.poisson_rel,
+            "poisson_iters": o.poisson_iters, "poisson_total": o.poisson_total, "steps": o.steps,
+            "drift_x": o.drift[0], "drift_y": o.drift[1], "drift_z": o.drift[2], "pmom_x": o.pmomentum[0],
+            "pmom_y": o.pmomentum[1], "pmom_z": o.pmomentum[2], "nonfinite": o.nonfinite,
+            "negative_ions": o.negative_ions,
+        }
+
+    def field(self, name):
+        out = np.zeros(self.N)
+        self._check(load().ek_get_field(self._h, FIELDS[name], _dp(out)), "ek_get_field")
+        return out.reshape(self.shape)
+
+    def populations(self, comp):
+        """(19, nz, ny, nx) in the library's velocity order (see lattice())."""
+        out = np.zeros(19 * self.N)
+        self._check(load().ek_get_populations(self._h, int(comp), _dp(out)), "ek_get_populations")
+        return out.reshape((19,) + self.shape)
+
+    def particles(self):
+        out = np.zeros((max(self.np, 1), 9))
+        self._check(load().ek_get_particles(self._h, _dp(out)), "ek_get_particles")
+        return out[: self.np]
+
+    def device_bytes(self):
+        b = ctypes.c_size_t(0)
+        load().ek_device_bytes(self._h, ctypes.byref(b))
+        return b.value
+
+    def set_timing(self, on):
+        self._check(load().ek_set_timing(self._h, int(bool(on))), "ek_set_timing")
+
+    def timing(self):
+        t = EKTiming()
+        self._check(load().ek_get_timing(self._h, ctypes.byref(t)), "ek_get_timing")
+        return {name: (t.ms[k], t.count[k]) for k, name in enumerate(TIMING_CLASSES)}

@@ -1,0 +1,180 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on the same
+seeded inputs, field by field, plus properties that hold at any size."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1712_08494_amd import ek
+from paper_1712_08494_amd import workloads as wl
+from tests.parity import TOL, compare, max_rel, oracle_from_sim, phi_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    ek.load()
+    torch.cuda.init()
+    yield
+
+
+def _pair(cfg, inp):
+    return ek.EKSim(cfg, inp), orc.Oracle(cfg, inp)
+
+
+def _announce(msg):
+    print(msg, flush=True)
+
+
+# --------------------------------------------------------------------------------
+# Mixture with noise (32^3 periodic, G = 3.6, SOR to 1e-10): FP64 and FP32.
+# --------------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mixture_noise_32(precision):
+    cfg, inp = wl.mixture_noise(n=32, precision=precision)
+    _announce(f"mixture_noise 32^3 {precision}")
+    sim, o = _pair(cfg, inp)
+    compare(sim, o, precision, "t=0")
+    for t in (10, 40):
+        sim.step(t)
+        o.step(t)
+        errs = compare(sim, o, precision, f"after {t}")
+        _announce(f"  {precision} errors {errs}")
+
+
+def test_ragged_tile_periodic():
+    """Odd sizes that leave partial workgroups and partial XCD slabs."""
+    cfg, inp = wl.mixture_noise(shape=(10, 7, 5), precision="fp64", G=4.4)
+    _announce("ragged 10x7x5 fp64")
+    sim, o = _pair(cfg, inp)
+    sim.step(25)
+    o.step(25)
+    compare(sim, o, "fp64", "ragged")
+
+
+# --------------------------------------------------------------------------------
+# Charged walls and an interface with solvation and permittivity contrast.
+# --------------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_walls_interface_small(precision):
+    cfg, inp = wl.walls_interface(shape=(16, 12, 32), precision=precision)
+    _announce(f"walls_interface 16x12x32 {precision}")
+    sim, o = _pair(cfg, inp)
+    compare(sim, o, precision, "t=0")
+    sim.step(30)
+    o.step(30)
+    errs = compare(sim, o, precision, "after 30")
+    _announce(f"  errors {errs}")
+
+
+# --------------------------------------------------------------------------------
+# Resolved charged spheres under a field.
+# --------------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_colloids_small(precision):
+    cfg, inp = wl.colloids(shape=(32, 32, 32), count=6, radius=3.5, precision=precision, field=(1e-3, 0, 0),
+                           seed=7)
+    _announce(f"colloids 32^3 x6 {precision}")
+    sim, o = _pair(cfg, inp)
+    np.testing.assert_array_equal(sim.field("solid"), o.field("solid"))
+    np.testing.assert_allclose(sim.field("psi_s"), o.field("psi_s"), rtol=0, atol=0)
+    compare(sim, o, precision, "t=0")
+    sim.step(20)
+    o.step(20)
+    errs = compare(sim, o, precision, "after 20")
+    pg, po = sim.particles(), o.particles()
+    tol = 1e-4 if precision == "fp32" else 1e-9
+    # positions, velocities and the last step's force
+    np.testing.assert_allclose(pg[:, 0:3], po[:, 0:3], rtol=0, atol=1e-9)
+    vscale = np.abs(po[:, 3:6]).max()
+    assert np.abs(pg[:, 3:6] - po[:, 3:6]).max() <= tol * vscale
+    fscale = np.abs(po[:, 6:9]).max()
+    assert np.abs(pg[:, 6:9] - po[:, 6:9]).max() <= tol * fscale
+    _announce(f"  errors {errs}")
+
+
+def test_body_force_walls_fp64():
+    cfg = wl.EKConfig(4, 2, 18, walls_z=True, body_accel=(1e-6, 0, 0), G=0.0, name="poiseuille")
+    inp = wl.uniform(cfg, 0.5, 0.5, 0.0, 0.0)
+    _announce("poiseuille 4x2x18 fp64")
+    sim, o = _pair(cfg, inp)
+    sim.step(500)
+    o.step(500)
+    compare(sim, o, "fp64", "poiseuille")
+    np.testing.assert_allclose(sim.field("ux"), o.field("ux"), rtol=1e-9, atol=1e-15)
+
+
+# --------------------------------------------------------------------------------
+# Full size of the benchmark workload (128^3 walls + interface, FP32): one step from the
+# library's state, against the oracle taking the same step from that state.
+# --------------------------------------------------------------------------------
+def test_walls_interface_128_one_step():
+    cfg, inp = wl.walls_interface(n=128, precision="fp32")
+    _announce("walls_interface 128^3 fp32: 3 steps then one-step parity")
+    sim = ek.EKSim(cfg, inp)
+    sim.step(3)
+    o = oracle_from_sim(cfg, inp, sim)
+    sim.step(1)
+    o.step(1)
+    errs = compare(sim, o, "fp32", "128^3 one step")
+    _announce(f"  errors {errs}")
+
+
+# --------------------------------------------------------------------------------
+# Properties at any size
+# --------------------------------------------------------------------------------
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_conservation(precision, tol):
+    cfg, inp = wl.walls_interface(shape=(32, 32, 64), precision=precision)
+    sim = ek.EKSim(cfg, inp)
+    a = sim.observables()
+    sim.step(50)
+    b = sim.observables()
+    for k in ["sum_rho_a", "sum_rho_b", "sum_n_plus", "sum_n_minus"]:
+        assert abs(b[k] - a[k]) <= tol * abs(a[k]), (k, a[k], b[k])
+    assert b["nonfinite"] == 0 and b["negative_ions"] == 0
+
+
+def test_deterministic_bitwise():
+    cfg, inp = wl.colloids(shape=(32, 32, 32), count=4, radius=3.0, precision="fp32", seed=11)
+    out = []
+    for _ in range(2):
+        sim = ek.EKSim(cfg, inp)
+        sim.step(10)
+        out.append([sim.field(k) for k in ("rho_a", "n_plus", "phi")] + [sim.particles()])
+        sim.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
+def test_poisson_entry_and_noconv():
+    cfg, inp = wl.mixture_noise(n=16, precision="fp64")
+    sim = ek.EKSim(cfg, inp)
+    st, it, rel = sim.poisson(1e-12, 5000)
+    assert st == ek.EK_OK and rel <= 1e-12
+    o = orc.Oracle(cfg, inp)
+    assert phi_err(sim.field("phi"), o.field("phi")) < 1e-9
+    sim.step(1)
+    st, it, rel = sim.poisson(1e-14, 1)
+    assert st == ek.EK_ENOCONV and it == 1 and rel > 1e-14
+
+
+def test_invalid_parameters():
+    cfg, inp = wl.mixture_noise(n=8, precision="fp64")
+    cfg.tau = 0.5
+    with pytest.raises(ek.EKError) as e:
+        ek.EKSim(cfg, inp)
+    assert e.value.status == ek.EK_EINVAL
+    cfg2, inp2 = wl.mixture_noise(shape=(7, 4, 4), precision="fp64")
+    with pytest.raises(ek.EKError):
+        ek.EKSim(cfg2, inp2)
+
+
+def test_nonfinite_detected():
+    cfg, inp = wl.mixture_noise(n=8, precision="fp64")
+    inp.n_plus[0, 0, 0] = np.nan
+    with pytest.raises(ek.EKError):
+        ek.EKSim(cfg, inp)
