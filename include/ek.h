@@ -44,6 +44,10 @@ typedef int32_t ek_status;
 #define EK_ENONFINITE (-5) /* a NaN or Inf was found by ek_observables */
 #define EK_ESTATE (-6)     /* call not valid in the context's current state */
 
+#define EK_POISSON_AUTO 0 /* multigrid when every axis divides by 4, else SOR */
+#define EK_POISSON_SOR 1  /* red-black successive over-relaxation */
+#define EK_POISSON_MG 2   /* geometric multigrid V-cycles (EINVAL if the lattice cannot be coarsened) */
+
 #define EK_FP64 0 /* populations, ions, charge and permittivity in double */
 #define EK_FP32 1 /* populations as float deviations from w_d rho_ref, ions in float; phi stays double */
 
@@ -51,7 +55,8 @@ typedef struct ek_params {
     int32_t nx, ny, nz;         /* lattice size; nx must be even (red-black ordering) */
     int32_t walls_z;            /* 0: periodic in z; 1: solid charged walls at z = 0 and z = nz-1 */
     int32_t precision;          /* EK_FP64 or EK_FP32 */
-    int32_t poisson_maxit;      /* maximum Poisson sweeps per solve */
+    int32_t poisson_maxit;      /* maximum Poisson iterations per solve (SOR sweeps or V-cycles) */
+    int32_t poisson_solver;     /* EK_POISSON_AUTO, EK_POISSON_SOR or EK_POISSON_MG */
     int32_t subsample;          /* sub-cells per axis for the particle solid fraction (e.g. 8) */
     int32_t move_particles;     /* 1: integrate particle motion every step */
     double tau;                 /* BGK relaxation time of both fluids (> 1/2) */
@@ -89,8 +94,9 @@ typedef struct ek_obs {
     double max_u;          /* max |u| of the pre-force barycentric velocity */
     double source_mean;    /* mean removed from the Poisson source by the last solve */
     double poisson_rel;    /* relative residual reached by the last solve */
-    int64_t poisson_iters; /* sweeps of the last solve */
-    int64_t poisson_total; /* sweeps summed over all solves since ek_init */
+    int64_t poisson_iters; /* iterations (SOR sweeps or V-cycles) of the last solve */
+    int64_t poisson_total; /* iterations summed over all solves since ek_init */
+    int32_t poisson_mg_levels; /* multigrid levels in use (0: SOR) */
     int64_t steps;         /* steps taken since ek_init */
     double drift[3];       /* mean particle displacement since ek_init */
     double pmomentum[3];   /* total particle momentum */
@@ -159,8 +165,9 @@ ek_status ek_step(struct ek_ctx* ctx, int32_t nsteps);
 /* Solve the Poisson equation for the charge and permittivity of the current state
    (Sec. II D): sum over the six links of eps_face (phi_j - phi_i) = -(q_i + wall
    charge), eps_face the mean of the two sites, source projected to zero mean, gauge
-   mean(phi) = 0, red-black SOR from the current potential.  iters, rel_res may be
-   NULL.  Returns EK_ENOCONV if the tolerance was not met (phi keeps the last iterate). */
+   mean(phi) = 0, starting from the current potential with the context's solver
+   (multigrid V-cycles or red-black SOR).  iters, rel_res may be NULL.  Returns
+   EK_ENOCONV if the tolerance was not met (phi keeps the last iterate). */
 ek_status ek_poisson(struct ek_ctx* ctx, double tol, int32_t maxit, int32_t* iters, double* rel_res);
 
 /* FP64 totals and diagnostics of the current state (synchronises the stream).

@@ -77,6 +77,9 @@ struct ek_ctx {
     double last_rel = 0.0, last_mean = 0.0;
     double omega = 1.0;
     double rate = -1.0;
+    // multigrid (levels[0] is the lattice itself and holds no arrays)
+    std::vector<MGLevel> mg;
+    double mg_coarse_omega = 1.0;
     // timing
     bool timing = false;
     std::vector<TimeRec> recs;
@@ -350,6 +353,47 @@ static ek_status check_residual(ek_ctx* c, double& rr, double& ss) {
     return EK_OK;
 }
 
+// One V-cycle on the lattice (level 0) with the coarse levels in c->mg.
+template <typename T>
+static void vcycle(ek_ctx* c, const Fields<T>& F) {
+    const int nl = (int)c->mg.size();
+    const int pre = 2, post = 2;
+    for (int l = 0; l < nl; ++l) {  // downward leg: smooth, restrict
+        for (int s = 0; s < pre; ++s)
+            for (int color = 0; color < 2; ++color) {
+                if (l == 0)
+                    launch_sor<T>(c->S, F, color, 1.0, c->st);
+                else
+                    launch_mg_smooth(c->mg[l - 1], color, 1.0, c->st);
+            }
+        if (l == 0)
+            launch_mg_restrict_fine<T>(c->S, F, c->mg[0], c->st);
+        else
+            launch_mg_restrict(c->mg[l - 1], c->mg[l], c->st);
+    }
+    launch_mg_coarse_solve(c->mg[nl - 1], 40, c->mg_coarse_omega, c->st);
+    for (int l = nl - 1; l >= 0; --l) {  // upward leg: interpolate, smooth
+        if (l == 0)
+            launch_mg_prolong_fine<T>(c->S, F, c->mg[0], c->st);
+        else
+            launch_mg_prolong(c->mg[l], c->mg[l - 1], c->st);
+        for (int s = 0; s < post; ++s)
+            for (int color = 0; color < 2; ++color) {
+                if (l == 0)
+                    launch_sor<T>(c->S, F, color, 1.0, c->st);
+                else
+                    launch_mg_smooth(c->mg[l - 1], color, 1.0, c->st);
+            }
+    }
+}
+
+// Coarse-level face coefficients for the current permittivity.
+template <typename T>
+static void mg_build(ek_ctx* c, const Fields<T>& F) {
+    launch_mg_coarsen_fine<T>(c->S, F, c->mg[0], c->st);
+    for (size_t l = 1; l < c->mg.size(); ++l) launch_mg_coarsen(c->mg[l - 1], c->mg[l], c->st);
+}
+
 // Requires q, eps and the source mean of the current state on the device.
 template <typename T>
 static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out, double* rel_out) {
@@ -365,7 +409,28 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
     } else {
         const double target = tol * std::sqrt(ss);
         double r = std::sqrt(rr);
-        while (r > target && it < maxit) {
+        const bool use_mg = !c->mg.empty();
+        if (use_mg && r > target) mg_build<T>(c, F);
+        while (use_mg && r > target && it < maxit) {
+            int k = 1;
+            if (c->rate > 0.0 && c->rate < 1.0) k = (int)std::ceil(std::log(target / r) / std::log(c->rate));
+            k = std::max(1, std::min(k, 8));
+            k = std::min(k, maxit - it);
+            {
+                Timer ts(c, EK_T_SOR, k);
+                for (int s = 0; s < k; ++s) vcycle<T>(c, F);
+            }
+            EK_HIP(hipGetLastError());
+            it += k;
+            EK_TRY(check_residual<T>(c, rr, ss));
+            const double rn = std::sqrt(rr);
+            if (rn < r && rn > 0.0) {
+                const double est = std::pow(rn / r, 1.0 / k);
+                c->rate = c->rate > 0.0 ? std::max(est, 0.5 * (c->rate + est)) : est;
+            }
+            r = rn;
+        }
+        while (!use_mg && r > target && it < maxit) {
             int k;
             if (c->rate > 0.0 && c->rate < 1.0)
                 k = (int)std::ceil(1.1 * std::log(target / r) / std::log(c->rate)) + 1;
@@ -531,6 +596,14 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     EK_TRY(dalloc(c, (void**)&c->obs_max, 16 * sizeof(int)));
     EK_TRY(dalloc(c, (void**)&c->stage, (size_t)N * 8));
     EK_HIP(hipHostMalloc((void**)&c->hscal, 32 * sizeof(double), hipHostMallocDefault));
+    for (auto& L : c->mg) {
+        EK_TRY(dalloc(c, (void**)&L.phi, (size_t)L.n * 8));
+        EK_TRY(dalloc(c, (void**)&L.s, (size_t)L.n * 8));
+        EK_TRY(dalloc(c, (void**)&L.ax, (size_t)L.n * 8));
+        EK_TRY(dalloc(c, (void**)&L.ay, (size_t)L.n * 8));
+        EK_TRY(dalloc(c, (void**)&L.az, (size_t)L.n * 8));
+        EK_HIP(hipMemsetAsync(L.phi, 0, (size_t)L.n * 8, c->st));
+    }
     for (int b = 0; b < 2; ++b)
         for (int k = 0; k < 2; ++k) {
             EK_HIP(hipMemsetAsync(c->f[b][k], 0, (size_t)kQ * N * es, c->st));
@@ -684,6 +757,32 @@ extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const doub
     S.sigma0 = p->sigma_wall[0];
     S.sigma1 = p->sigma_wall[1];
     c->omega = p->sor_omega > 0.0 ? p->sor_omega : omega_for(*p);
+    if (p->poisson_solver < 0 || p->poisson_solver > 2) return fail(c, EK_EINVAL, "unknown poisson_solver");
+    if (p->poisson_solver != EK_POISSON_SOR) {
+        // Coarsen by two while every axis of the current level divides by 4 (so that the
+        // coarse level keeps even axes for red-black ordering) and the level is large.
+        int dims[3] = {p->nx, p->ny, p->nz};
+        while (dims[0] % 4 == 0 && dims[1] % 4 == 0 && dims[2] % 4 == 0 && dims[0] * dims[1] * dims[2] > 512) {
+            for (int k = 0; k < 3; ++k) dims[k] /= 2;
+            MGLevel L{};
+            L.nx = dims[0];
+            L.ny = dims[1];
+            L.nz = dims[2];
+            L.n = (unsigned)(dims[0] * dims[1] * dims[2]);
+            c->mg.push_back(L);
+        }
+        if (c->mg.empty() && p->poisson_solver == EK_POISSON_MG)
+            return fail(c, EK_EINVAL, "multigrid needs every axis divisible by 4");
+        if (!c->mg.empty()) {
+            // SOR factor of the coarsest level (uniform-coefficient estimate)
+            ek_params q = *p;
+            q.nx = c->mg.back().nx;
+            q.ny = c->mg.back().ny;
+            q.nz = c->mg.back().nz;
+            q.walls_z = 0;
+            c->mg_coarse_omega = std::min(1.9, omega_for(q));
+        }
+    }
     c->esz = p->precision == EK_FP32 ? 4 : 8;
     if (p->precision == EK_FP32) return init_impl<float>(c, rho_a, rho_b, n_plus, n_minus, parts, n_parts);
     return init_impl<double>(c, rho_a, rho_b, n_plus, n_minus, parts, n_parts);
@@ -736,6 +835,7 @@ static ek_status observe_impl(ek_ctx* c, ek_obs* o) {
     o->poisson_rel = c->last_rel;
     o->poisson_iters = c->last_iters;
     o->poisson_total = c->ptotal;
+    o->poisson_mg_levels = c->mg.empty() ? 0 : (int32_t)c->mg.size() + 1;
     o->steps = c->steps;
     if (c->np > 0) {
         std::vector<double> hx(3 * c->np), hv(3 * c->np);

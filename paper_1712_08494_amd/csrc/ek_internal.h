@@ -57,7 +57,29 @@ struct Fields {
     double* scal;            // device scalars: [0] source mean, [1..3] rr, ss, sum phi
 };
 
+// One coarse level of the Poisson multigrid: cell-centred, periodic in all axes, with
+// the operator held as face coefficients (a zero face decouples two cells, which is how
+// the wall layers enter the coarse levels).
+struct MGLevel {
+    int nx, ny, nz;
+    unsigned n;
+    double* phi;  // correction on this level
+    double* s;    // restricted residual (right-hand side)
+    double* ax;   // coefficient of the face to the +x neighbour
+    double* ay;
+    double* az;
+};
+
 unsigned site_blocks(unsigned n);
+
+template <typename T> void launch_mg_coarsen_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st);
+void launch_mg_coarsen(const MGLevel& f, const MGLevel& c, hipStream_t st);
+void launch_mg_smooth(const MGLevel& L, int color, double omega, hipStream_t st);
+template <typename T> void launch_mg_restrict_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st);
+void launch_mg_restrict(const MGLevel& f, const MGLevel& c, hipStream_t st);
+template <typename T> void launch_mg_prolong_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st);
+void launch_mg_prolong(const MGLevel& c, const MGLevel& f, hipStream_t st);
+void launch_mg_coarse_solve(const MGLevel& L, int iters, double omega, hipStream_t st);
 
 template <typename T> void launch_moments(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
 template <typename T> void launch_virtual(const Scalars& S, const Fields<T>& F, hipStream_t st);

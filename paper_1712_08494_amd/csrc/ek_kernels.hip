@@ -428,6 +428,226 @@ template <typename T> void launch_phi_ghosts(const Scalars& S, const Fields<T>& 
 }
 
 // ------------------------------------------------------------------------------------
+// Geometric multigrid for the same Poisson operator.  Cell-centred coarsening by 2 per
+// axis; a coarse face coefficient is half the sum of the four fine faces it covers (the
+// finite-volume flux of a cell twice as wide); the residual is restricted by summing the
+// eight children; the correction is interpolated trilinearly (weights 3/4, 1/4 per axis),
+// falling back to the parent across a zero face.  Smoothing is red-black Gauss-Seidel.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ unsigned lid(const MGLevel& L, int x, int y, int z) {
+    return (unsigned)x + (unsigned)L.nx * ((unsigned)y + (unsigned)L.ny * (unsigned)z);
+}
+
+// Fine-level face coefficient between (x, y, z) and its +k neighbour: zero unless both
+// cells are in the Poisson domain.
+template <typename T>
+__device__ __forceinline__ double fine_face(int k, int x, int y, int z, const Scalars& S, const Fields<T>& F) {
+    if (z < S.z0 || z > S.z1) return 0.0;
+    int xn = x, yn = y, zn = z;
+    if (k == 0) xn = wrapc(x + 1, S.nx);
+    if (k == 1) yn = wrapc(y + 1, S.ny);
+    if (k == 2) {
+        zn = wrapc(z + 1, S.nz);
+        if (zn < S.z0 || zn > S.z1) return 0.0;
+    }
+    const unsigned i = x + S.nx * (y + S.ny * z), j = xn + S.nx * (yn + S.ny * zn);
+    return 0.5 * ((double)F.eps[i] + (double)F.eps[j]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mg_coarsen_fine(Scalars S, Fields<T> F, MGLevel C) {
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C.n) return;
+    const int I = t % C.nx, r = t / C.nx, J = r % C.ny, K = r / C.ny;
+    double ax = 0, ay = 0, az = 0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            ax += fine_face<T>(0, 2 * I + 1, 2 * J + a, 2 * K + b, S, F);
+            ay += fine_face<T>(1, 2 * I + a, 2 * J + 1, 2 * K + b, S, F);
+            az += fine_face<T>(2, 2 * I + a, 2 * J + b, 2 * K + 1, S, F);
+        }
+    C.ax[t] = 0.5 * ax;
+    C.ay[t] = 0.5 * ay;
+    C.az[t] = 0.5 * az;
+}
+
+template <typename T> void launch_mg_coarsen_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st) {
+    hipLaunchKernelGGL(k_mg_coarsen_fine<T>, dim3((c.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, S, F, c);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mg_coarsen(MGLevel Fl, MGLevel C) {
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C.n) return;
+    const int I = t % C.nx, r = t / C.nx, J = r % C.ny, K = r / C.ny;
+    double ax = 0, ay = 0, az = 0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            ax += Fl.ax[lid(Fl, 2 * I + 1, 2 * J + a, 2 * K + b)];
+            ay += Fl.ay[lid(Fl, 2 * I + a, 2 * J + 1, 2 * K + b)];
+            az += Fl.az[lid(Fl, 2 * I + a, 2 * J + b, 2 * K + 1)];
+        }
+    C.ax[t] = 0.5 * ax;
+    C.ay[t] = 0.5 * ay;
+    C.az[t] = 0.5 * az;
+}
+
+void launch_mg_coarsen(const MGLevel& f, const MGLevel& c, hipStream_t st) {
+    hipLaunchKernelGGL(k_mg_coarsen, dim3((c.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, f, c);
+}
+
+// Row of a coarse level: diagonal, off-diagonal sum, at cell (x, y, z).
+__device__ __forceinline__ void mg_row(const MGLevel& L, int x, int y, int z, double& diag, double& off) {
+    const int xm = wrapc(x - 1, L.nx), xp = wrapc(x + 1, L.nx);
+    const int ym = wrapc(y - 1, L.ny), yp = wrapc(y + 1, L.ny);
+    const int zm = wrapc(z - 1, L.nz), zp = wrapc(z + 1, L.nz);
+    const unsigned i = lid(L, x, y, z);
+    const double a0 = L.ax[i], a1 = L.ax[lid(L, xm, y, z)];
+    const double b0 = L.ay[i], b1 = L.ay[lid(L, x, ym, z)];
+    const double c0 = L.az[i], c1 = L.az[lid(L, x, y, zm)];
+    diag = a0 + a1 + b0 + b1 + c0 + c1;
+    off = a0 * L.phi[lid(L, xp, y, z)] + a1 * L.phi[lid(L, xm, y, z)] + b0 * L.phi[lid(L, x, yp, z)] +
+          b1 * L.phi[lid(L, x, ym, z)] + c0 * L.phi[lid(L, x, y, zp)] + c1 * L.phi[lid(L, x, y, zm)];
+}
+
+__global__ __launch_bounds__(kBlock) void k_mg_smooth(MGLevel L, int color, double omega) {
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned half = (unsigned)(L.nx >> 1);
+    if (t >= half * (unsigned)L.ny * (unsigned)L.nz) return;
+    const unsigned row = t / half, m = t % half;
+    const int y = row % L.ny, z = row / L.ny;
+    const int x = 2 * m + ((color + y + z) & 1);
+    double diag, off;
+    mg_row(L, x, y, z, diag, off);
+    if (diag <= 0.0) return;
+    const unsigned i = lid(L, x, y, z);
+    L.phi[i] = L.phi[i] + omega * ((off + L.s[i]) / diag - L.phi[i]);
+}
+
+void launch_mg_smooth(const MGLevel& L, int color, double omega, hipStream_t st) {
+    const unsigned n = L.n / 2;
+    hipLaunchKernelGGL(k_mg_smooth, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, L, color, omega);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mg_restrict_fine(Scalars S, Fields<T> F, MGLevel C) {
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C.n) return;
+    const int I = t % C.nx, r = t / C.nx, J = r % C.ny, K = r / C.ny;
+    double sum = 0.0;
+    for (int c = 0; c < 2; ++c)
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) {
+                const int x = 2 * I + a, y = 2 * J + b, z = 2 * K + c;
+                if (z < S.z0 || z > S.z1) continue;
+                const unsigned i = x + S.nx * (y + S.ny * z);
+                double diag, offsum, src;
+                poisson_row<T>(i, x, y, z, S, F, diag, offsum, src);
+                sum += src + offsum - diag * F.phi[i];
+            }
+    C.s[t] = sum;
+    C.phi[t] = 0.0;
+}
+
+template <typename T> void launch_mg_restrict_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st) {
+    hipLaunchKernelGGL(k_mg_restrict_fine<T>, dim3((c.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, S, F, c);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(MGLevel Fl, MGLevel C) {
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C.n) return;
+    const int I = t % C.nx, r = t / C.nx, J = r % C.ny, K = r / C.ny;
+    double sum = 0.0;
+    for (int c = 0; c < 2; ++c)
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) {
+                const int x = 2 * I + a, y = 2 * J + b, z = 2 * K + c;
+                double diag, off;
+                mg_row(Fl, x, y, z, diag, off);
+                const unsigned i = lid(Fl, x, y, z);
+                sum += Fl.s[i] + off - diag * Fl.phi[i];
+            }
+    C.s[t] = sum;
+    C.phi[t] = 0.0;
+}
+
+void launch_mg_restrict(const MGLevel& f, const MGLevel& c, hipStream_t st) {
+    hipLaunchKernelGGL(k_mg_restrict, dim3((c.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, f, c);
+}
+
+// Trilinear interpolation of the coarse correction at the fine cell (x, y, z).
+__device__ __forceinline__ double mg_interp(const MGLevel& C, int x, int y, int z) {
+    const int I = x >> 1, J = y >> 1, K = z >> 1;
+    const int dx = (x & 1) ? 1 : -1, dy = (y & 1) ? 1 : -1, dz = (z & 1) ? 1 : -1;
+    const int In = wrapc(I + dx, C.nx), Jn = wrapc(J + dy, C.ny), Kn = wrapc(K + dz, C.nz);
+    const double fx = C.ax[lid(C, dx > 0 ? I : In, J, K)];
+    const double fy = C.ay[lid(C, I, dy > 0 ? J : Jn, K)];
+    const double fz = C.az[lid(C, I, J, dz > 0 ? K : Kn)];
+    const double wx = fx > 0.0 ? 0.25 : 0.0, wy = fy > 0.0 ? 0.25 : 0.0, wz = fz > 0.0 ? 0.25 : 0.0;
+    const int xs[2] = {I, In}, ys[2] = {J, Jn}, zs[2] = {K, Kn};
+    const double wxs[2] = {1.0 - wx, wx}, wys[2] = {1.0 - wy, wy}, wzs[2] = {1.0 - wz, wz};
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) v += wxs[a] * wys[b] * wzs[c] * C.phi[lid(C, xs[a], ys[b], zs[c])];
+    return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mg_prolong_fine(Scalars S, Fields<T> F, MGLevel C) {
+    const unsigned i = xcd_linear();
+    if (i >= S.N) return;
+    const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+    if (z < S.z0 || z > S.z1) return;
+    F.phi[i] += mg_interp(C, x, y, z);
+}
+
+template <typename T> void launch_mg_prolong_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st) {
+    hipLaunchKernelGGL(k_mg_prolong_fine<T>, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F, c);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mg_prolong(MGLevel C, MGLevel Fl) {
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Fl.n) return;
+    const int x = i % Fl.nx, r = i / Fl.nx, y = r % Fl.ny, z = r / Fl.ny;
+    Fl.phi[i] += mg_interp(C, x, y, z);
+}
+
+void launch_mg_prolong(const MGLevel& c, const MGLevel& f, hipStream_t st) {
+    hipLaunchKernelGGL(k_mg_prolong, dim3((f.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c, f);
+}
+
+// Coarsest level: red-black SOR sweeps inside one workgroup (the level is tiny).
+__global__ __launch_bounds__(kBlock) void k_mg_coarse_solve(MGLevel L, int iters, double omega) {
+    const unsigned half = L.n / 2;
+    for (unsigned t = threadIdx.x; t < L.n; t += blockDim.x) L.phi[t] = 0.0;
+    __syncthreads();
+    for (int it = 0; it < iters; ++it) {
+        for (int color = 0; color < 2; ++color) {
+            for (unsigned t = threadIdx.x; t < half; t += blockDim.x) {
+                const unsigned hx = (unsigned)(L.nx >> 1);
+                const unsigned row = t / hx, m = t % hx;
+                const int y = row % L.ny, z = row / L.ny;
+                const int x = 2 * m + ((color + y + z) & 1);
+                double diag, off;
+                mg_row(L, x, y, z, diag, off);
+                if (diag > 0.0) {
+                    const unsigned i = lid(L, x, y, z);
+                    L.phi[i] = L.phi[i] + omega * ((off + L.s[i]) / diag - L.phi[i]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+void launch_mg_coarse_solve(const MGLevel& L, int iters, double omega, hipStream_t st) {
+    hipLaunchKernelGGL(k_mg_coarse_solve, dim3(1), dim3(kBlock), 0, st, L, iters, omega);
+}
+
+// ------------------------------------------------------------------------------------
 // Link fluxes (Sec. II B, II E eq. ionic-fluxes-disc-2), for the link lo -> hi along axis k:
 //   J = -D psi_f(lo) psi_f(hi) [ (n~_hi - n~_lo) - (beta/4)(q~_lo + q~_hi)(E_lo + E_hi)_k
 //                              + s (beta dmu / 2 drho_a)(n~_lo + n~_hi)(rho^a_hi - rho^a_lo) ]
@@ -913,7 +1133,10 @@ template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, 
     template void launch_init_ions<T>(const Scalars&, const Fields<T>&, T*, const double*, hipStream_t);       \
     template void launch_to_double<T>(const T*, double*, unsigned, double, hipStream_t);                       \
     template void launch_field_e<T>(const Scalars&, const Fields<T>&, int, double*, hipStream_t);              \
-    template void launch_upload<T>(T*, const double*, unsigned, hipStream_t);
+    template void launch_upload<T>(T*, const double*, unsigned, hipStream_t);                               \
+    template void launch_mg_coarsen_fine<T>(const Scalars&, const Fields<T>&, const MGLevel&, hipStream_t);    \
+    template void launch_mg_restrict_fine<T>(const Scalars&, const Fields<T>&, const MGLevel&, hipStream_t);   \
+    template void launch_mg_prolong_fine<T>(const Scalars&, const Fields<T>&, const MGLevel&, hipStream_t);
 
 EK_INST(float)
 EK_INST(double)

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libek.so")
 
 EK_OK, EK_EINVAL, EK_ENOMEM, EK_EHIP, EK_ENOCONV, EK_ENONFINITE, EK_ESTATE = 0, -1, -2, -3, -4, -5, -6
 EK_FP64, EK_FP32 = 0, 1
+POISSON_SOLVERS = {"auto": 0, "sor": 1, "mg": 2}
 FIELDS = {"rho_a": 0, "rho_b": 1, "n_plus": 2, "n_minus": 3, "phi": 4, "ux": 5, "uy": 6, "uz": 7, "q": 8,
           "eps": 9, "psi_s": 10, "solid": 11, "Ex": 12, "Ey": 13, "Ez": 14}
 TIMING_CLASSES = ["moments", "poisson", "force", "fused", "particle", "sor"]
@@ -23,7 +24,7 @@ class EKParams(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("walls_z", ctypes.c_int32), ("precision", ctypes.c_int32), ("poisson_maxit", ctypes.c_int32),
-        ("subsample", ctypes.c_int32), ("move_particles", ctypes.c_int32),
+        ("poisson_solver", ctypes.c_int32), ("subsample", ctypes.c_int32), ("move_particles", ctypes.c_int32),
         ("tau", ctypes.c_double), ("G", ctypes.c_double), ("rho0", ctypes.c_double),
         ("rho_ref", ctypes.c_double * 2), ("D", ctypes.c_double), ("beta", ctypes.c_double),
         ("dmu", ctypes.c_double * 2), ("drho_a", ctypes.c_double), ("solvation_sign", ctypes.c_double),
@@ -44,7 +45,7 @@ class EKObs(ctypes.Structure):
         ("sum_rho", ctypes.c_double * 2), ("sum_n", ctypes.c_double * 2), ("sum_q", ctypes.c_double),
         ("momentum", ctypes.c_double * 3), ("max_u", ctypes.c_double), ("source_mean", ctypes.c_double),
         ("poisson_rel", ctypes.c_double), ("poisson_iters", ctypes.c_int64), ("poisson_total", ctypes.c_int64),
-        ("steps", ctypes.c_int64), ("drift", ctypes.c_double * 3), ("pmomentum", ctypes.c_double * 3),
+        ("poisson_mg_levels", ctypes.c_int32), ("steps", ctypes.c_int64), ("drift", ctypes.c_double * 3), ("pmomentum", ctypes.c_double * 3),
         ("nonfinite", ctypes.c_int32), ("negative_ions", ctypes.c_int32),
     ]
 
@@ -73,6 +74,10 @@ def load(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} not found: build it with paper_1712_08494_amd.build.build()")
+    # PyTorch ships its own HIP runtime with the same soname as the system one; importing
+    # it first makes libek bind to that already-loaded runtime, so the process holds a
+    # single HIP runtime (two would each try to own the device).
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     dp = ctypes.POINTER(ctypes.c_double)
     vp = ctypes.c_void_p
@@ -133,6 +138,7 @@ def params_from_config(cfg):
     p.walls_z = int(bool(cfg.walls_z))
     p.precision = EK_FP32 if cfg.precision == "fp32" else EK_FP64
     p.poisson_maxit = int(cfg.poisson_maxit)
+    p.poisson_solver = POISSON_SOLVERS[cfg.poisson_solver]
     p.subsample = int(cfg.subsample)
     p.move_particles = int(bool(cfg.move_particles))
     p.tau, p.G, p.rho0 = cfg.tau, cfg.G, cfg.rho0
@@ -229,7 +235,8 @@ class EKSim:
             "sum_rho_a": o.sum_rho[0], "sum_rho_b": o.sum_rho[1], "sum_n_plus": o.sum_n[0],
             "sum_n_minus": o.sum_n[1], "sum_q": o.sum_q, "mom_x": o.momentum[0], "mom_y": o.momentum[1],
             "mom_z": o.momentum[2], "max_u": o.max_u, "source_mean": o.source_mean, "poisson_rel": o.poisson_rel,
-            "poisson_iters": o.poisson_iters, "poisson_total": o.poisson_total, "steps": o.steps,
+            "poisson_iters": o.poisson_iters, "poisson_total": o.poisson_total,
+            "poisson_mg_levels": o.poisson_mg_levels, "steps": o.steps,
             "drift_x": o.drift[0], "drift_y": o.drift[1], "drift_z": o.drift[2], "pmom_x": o.pmomentum[0],
             "pmom_y": o.pmomentum[1], "pmom_z": o.pmomentum[2], "nonfinite": o.nonfinite,
             "negative_ions": o.negative_ions,
