@@ -102,6 +102,7 @@ typedef struct ek_obs {
     double pmomentum[3];   /* total particle momentum */
     int32_t nonfinite;     /* 1 if a NaN or Inf was found in the populations or ions */
     int32_t negative_ions; /* number of sites with a negative ion density */
+    double poisson_rel0;   /* relative residual of the starting guess of the last solve */
 } ek_obs;
 
 /* Kernel classes timed when timing is on (ek_set_timing). */
@@ -157,8 +158,9 @@ ek_status ek_init(const ek_params* p, const double* rho_a, const double* rho_b, 
                   struct ek_ctx** out);
 
 /* Advance nsteps full steps (moments, charge, Poisson, fluxes, forces, collide,
-   stream, particles).  Work is enqueued on the context's stream; the only host
-   synchronisation is the Poisson convergence test.  Returns EK_ENOCONV if any solve
+   stream, particles).  Each solve starts from the potential extrapolated linearly in
+   time from the two previous steps.  Work is enqueued on the context's stream; the only
+   host synchronisation is the Poisson convergence test.  Returns EK_ENOCONV if any solve
    stopped at maxit (the step is still taken with the last iterate). */
 ek_status ek_step(struct ek_ctx* ctx, int32_t nsteps);
 

@@ -43,6 +43,7 @@ struct ek_ctx {
     void* q = nullptr;
     void* eps = nullptr;
     double* phi = nullptr;
+    double* phi_prev = nullptr;  // potential of the previous step (time extrapolation)
     int cur = 0;
     // geometry
     uint8_t* flags = nullptr;
@@ -74,7 +75,7 @@ struct ek_ctx {
     // bookkeeping
     long long steps = 0, ptotal = 0;
     int last_iters = 0;
-    double last_rel = 0.0, last_mean = 0.0;
+    double last_rel = 0.0, last_mean = 0.0, last_rel0 = 0.0;
     double omega = 1.0;
     double rate = -1.0;
     // multigrid (levels[0] is the lattice itself and holds no arrays)
@@ -401,6 +402,7 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
     Fields<T> F = fields<T>(c);
     double rr, ss;
     EK_TRY(check_residual<T>(c, rr, ss));
+    c->last_rel0 = ss > 0.0 ? std::sqrt(rr / ss) : 0.0;
     int it = 0;
     ek_status status = EK_OK;
     double rel = 0.0;
@@ -484,6 +486,7 @@ static ek_status step_impl(ek_ctx* c, int nsteps) {
     ek_status worst = EK_OK;
     for (int s = 0; s < nsteps; ++s) {
         moments_pass<T>(c);
+        launch_phi_extrapolate(c->S, c->phi, c->phi_prev, c->st);
         ek_status ps = poisson_solve<T>(c, c->p.poisson_tol, c->p.poisson_maxit, nullptr, nullptr);
         if (ps == EK_ENOCONV)
             worst = ps;
@@ -586,11 +589,12 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
             EK_TRY(dalloc(c, &c->f[b][k], (size_t)kQ * N * es));
             EK_TRY(dalloc(c, &c->n[b][k], (size_t)N * es));
         }
-    EK_TRY(dalloc(c, &c->mom, 7 * (size_t)N * es));
+    EK_TRY(dalloc(c, &c->mom, 8 * (size_t)N * es));
     EK_TRY(dalloc(c, &c->uph, 3 * (size_t)N * es));
     EK_TRY(dalloc(c, &c->q, (size_t)N * es));
     EK_TRY(dalloc(c, &c->eps, (size_t)N * es));
     EK_TRY(dalloc(c, (void**)&c->phi, (size_t)N * 8));
+    EK_TRY(dalloc(c, (void**)&c->phi_prev, (size_t)N * 8));
     EK_TRY(dalloc(c, (void**)&c->red, (size_t)c->nblk * kRedSlots * 8));
     EK_TRY(dalloc(c, (void**)&c->scal, 32 * 8));
     EK_TRY(dalloc(c, (void**)&c->obs_max, 16 * sizeof(int)));
@@ -609,7 +613,7 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
             EK_HIP(hipMemsetAsync(c->f[b][k], 0, (size_t)kQ * N * es, c->st));
             EK_HIP(hipMemsetAsync(c->n[b][k], 0, (size_t)N * es, c->st));
         }
-    EK_HIP(hipMemsetAsync(c->mom, 0, 7 * (size_t)N * es, c->st));
+    EK_HIP(hipMemsetAsync(c->mom, 0, 8 * (size_t)N * es, c->st));
     EK_HIP(hipMemsetAsync(c->uph, 0, 3 * (size_t)N * es, c->st));
     EK_HIP(hipMemsetAsync(c->phi, 0, (size_t)N * 8, c->st));
     EK_HIP(hipMemsetAsync(c->scal, 0, 32 * 8, c->st));
@@ -696,6 +700,7 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     // initial potential
     moments_pass<T>(c);
     ek_status st = poisson_solve<T>(c, p.poisson_tol, p.poisson_maxit, nullptr, nullptr);
+    EK_HIP(hipMemcpyAsync(c->phi_prev, c->phi, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
     c->ptotal = 0;
     return st;
 }
@@ -833,6 +838,7 @@ static ek_status observe_impl(ek_ctx* c, ek_obs* o) {
     o->negative_ions = (int32_t)v[10];
     o->source_mean = c->last_mean;
     o->poisson_rel = c->last_rel;
+    o->poisson_rel0 = c->last_rel0;
     o->poisson_iters = c->last_iters;
     o->poisson_total = c->ptotal;
     o->poisson_mg_levels = c->mg.empty() ? 0 : (int32_t)c->mg.size() + 1;
@@ -881,17 +887,18 @@ static ek_status field_impl(ek_ctx* c, int which, double* host) {
         launch_moments<T>(c->S, F, c->nblk, c->st);
         launch_virtual<T>(c->S, F, c->st);
         const T* src = nullptr;
+        double add = 0.0;
         switch (which) {
-            case EK_F_RHO_A: src = (const T*)c->mom; break;
-            case EK_F_RHO_B: src = (const T*)c->mom + N; break;
-            case EK_F_UX: src = (const T*)c->mom + 4 * (size_t)N; break;
-            case EK_F_UY: src = (const T*)c->mom + 5 * (size_t)N; break;
-            case EK_F_UZ: src = (const T*)c->mom + 6 * (size_t)N; break;
+            case EK_F_RHO_A: src = (const T*)c->mom; add = c->S.rref[0]; break;
+            case EK_F_RHO_B: src = (const T*)c->mom + N; add = c->S.rref[1]; break;
+            case EK_F_UX: src = (const T*)c->mom + 5 * (size_t)N; break;
+            case EK_F_UY: src = (const T*)c->mom + 6 * (size_t)N; break;
+            case EK_F_UZ: src = (const T*)c->mom + 7 * (size_t)N; break;
             case EK_F_Q: src = (const T*)c->q; break;
             case EK_F_EPS: src = (const T*)c->eps; break;
             default: return fail(c, EK_EINVAL, "unknown field id");
         }
-        launch_to_double<T>(src, c->stage, N, 0.0, c->st);
+        launch_to_double<T>(src, c->stage, N, add, c->st);
     }
     EK_HIP(hipGetLastError());
     EK_HIP(hipMemcpyAsync(host, c->stage, (size_t)N * 8, hipMemcpyDeviceToHost, c->st));

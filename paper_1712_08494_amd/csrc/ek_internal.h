@@ -39,7 +39,7 @@ struct Fields {
     T* fn[2];           // populations at t+1
     const T* n[2];      // n+, n- at time t
     T* nn[2];           // n+, n- at t+1
-    T* mom;             // 7 N: rho_a, rho_b, psi_a, psi_b, ux, uy, uz (pre-force)
+    T* mom;             // 8 N: rho_a - rho_ref_a, rho_b - rho_ref_b, psi_a, psi_b, chi_a, ux, uy, uz
     T* uph;             // 3 N: physical velocity
     T* q;               // charge density
     T* eps;             // permittivity
@@ -88,6 +88,7 @@ template <typename T> void launch_sor(const Scalars& S, const Fields<T>& F, int 
 template <typename T> void launch_residual(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
 void launch_reduce(const double* red, unsigned nblk, int nvals, const int* is_max, double* out, hipStream_t st);
 void launch_phi_finalize(const Scalars& S, double* phi, const double* scal, int zero, hipStream_t st);
+void launch_phi_extrapolate(const Scalars& S, double* phi, double* phi_prev, hipStream_t st);
 template <typename T> void launch_phi_ghosts(const Scalars& S, const Fields<T>& F, hipStream_t st);
 template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hipStream_t st);
 template <typename T> void launch_fused(const Scalars& S, const Fields<T>& F, hipStream_t st);

@@ -94,6 +94,26 @@ __device__ __forceinline__ double efield_sq(int x, int y, int z, const double* p
 
 __device__ __forceinline__ bool wall_layer(int z, const Scalars& S) { return S.walls && (z == 0 || z == S.nz - 1); }
 
+// Geometry modes, a template parameter of the site kernels so that unused cases cost
+// nothing: kPeriodic (no solid site), kWalls (wall layers only, decided by z),
+// kColloids (per-site flags and fluid fractions; wall layers are marked there too).
+constexpr int kPeriodic = 0, kWalls = 1, kColloids = 2;
+
+template <typename T, int G>
+__device__ __forceinline__ bool is_solid(unsigned j, int zj, const Scalars& S, const Fields<T>& F) {
+    if (G == kPeriodic) return false;
+    if (G == kWalls) return zj == 0 || zj == S.nz - 1;
+    return (F.flags[j] & 1u) != 0;
+}
+
+template <typename T, int G>
+__device__ __forceinline__ T fluid_fraction(unsigned j, int zj, const Scalars& S, const Fields<T>& F) {
+    if (G == kPeriodic) return T(1);
+    if (G == kWalls) return (zj == 0 || zj == S.nz - 1) ? T(0) : T(1);
+    return F.psif[j];
+}
+
+// run-time dispatch helpers (used outside the hot kernels)
 template <typename T>
 __device__ __forceinline__ bool solid_at(unsigned j, int zj, const Scalars& S, const Fields<T>& F) {
     return S.colloids ? (F.flags[j] & 1u) != 0 : wall_layer(zj, S);
@@ -188,16 +208,26 @@ void launch_reduce(const double* red, unsigned nblk, int nvals, const int* is_ma
 // Step 1: moments, pseudopotentials, charge and permittivity.
 // Populations are stored as deviations g_d = f_d - w_d rho_ref (both precisions), so
 //   rho = rho_ref + sum_d g_d,  rho u = sum_d g_d c_d   (sum_d w_d c_d = 0).
+// Moment slots (N values each): 0 rho_a - rho_ref_a, 1 rho_b - rho_ref_b, 2 psi_a,
+// 3 psi_b, 4 chi_a = G psi_b + G_a+ n+ + G_a- n- (the Shan-Chen source felt by fluid a;
+// ions count on LB-fluid sites only), 5..7 pre-force velocity.  Solid sites hold
+// rho = 0 (or the virtual density, written by k_virtual).
 // ------------------------------------------------------------------------------------
-template <typename T>
+constexpr int kMomSlots = 8;
+
+// Occupancy requested for the force and fused kernels (waves per SIMD): four keeps FP32
+// at 128 VGPRs with at most a handful of spills; FP64 needs the registers of two.
+template <typename T> constexpr int kHotOcc = sizeof(T) == 4 ? 4 : 2;
+
+template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_moments(Scalars S, Fields<T> F) {
     const unsigned i = xcd_linear();
     const bool valid = i < S.N;
     double qsum = 0.0;
     if (valid) {
-        const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
-        const bool solid = solid_at(i, z, S, F);
-        T ra = 0, rb = 0, ux = 0, uy = 0, uz = 0, pa = 0, pb = 0;
+        const int z = (i / S.nx) / S.ny;
+        const bool solid = is_solid<T, G>(i, z, S, F);
+        T da = T(-S.rref[0]), db = T(-S.rref[1]), ux = 0, uy = 0, uz = 0, pa = 0, pb = 0;
         if (!solid) {
             T sa = 0, sb = 0, mx = 0, my = 0, mz = 0;
 #pragma unroll
@@ -214,8 +244,9 @@ __global__ __launch_bounds__(kBlock) void k_moments(Scalars S, Fields<T> F) {
                 if (vz(d) > 0) mz += s;
                 if (vz(d) < 0) mz -= s;
             }
-            ra = T(S.rref[0]) + sa;
-            rb = T(S.rref[1]) + sb;
+            da = sa;
+            db = sb;
+            const T ra = T(S.rref[0]) + sa, rb = T(S.rref[1]) + sb;
             const T rt = ra + rb;
             ux = mx / rt;
             uy = my / rt;
@@ -223,21 +254,24 @@ __global__ __launch_bounds__(kBlock) void k_moments(Scalars S, Fields<T> F) {
             pa = pseudo<T>(ra, S);
             pb = pseudo<T>(rb, S);
         }
-        F.mom[i] = ra;
-        F.mom[(size_t)S.N + i] = rb;
-        F.mom[2 * (size_t)S.N + i] = pa;
-        F.mom[3 * (size_t)S.N + i] = pb;
-        F.mom[4 * (size_t)S.N + i] = ux;
-        F.mom[5 * (size_t)S.N + i] = uy;
-        F.mom[6 * (size_t)S.N + i] = uz;
-        const T qc = S.colloids ? F.qc[i] : T(0);
-        const T q = F.n[0][i] - F.n[1][i] + qc;
-        const T psis = T(1) - psif_at(i, z, S, F);
-        const T ef = eps_fluid<T>(ra, rb, S);
+        const T npl = F.n[0][i], nmi = F.n[1][i];
+        const T chi = T(S.G) * pb + (solid ? T(0) : T(S.G_p) * npl + T(S.G_m) * nmi);
+        const size_t N = S.N;
+        F.mom[i] = da;
+        F.mom[N + i] = db;
+        F.mom[2 * N + i] = pa;
+        F.mom[3 * N + i] = pb;
+        F.mom[4 * N + i] = chi;
+        F.mom[5 * N + i] = ux;
+        F.mom[6 * N + i] = uy;
+        F.mom[7 * N + i] = uz;
+        const T qc = G == kColloids ? F.qc[i] : T(0);
+        const T q = npl - nmi + qc;
+        const T psis = T(1) - fluid_fraction<T, G>(i, z, S, F);
+        const T ra = T(S.rref[0]) + da, rb = T(S.rref[1]) + db;
         F.q[i] = q;
-        F.eps[i] = T(S.eps_p) * psis + ef * (T(1) - psis);
+        F.eps[i] = T(S.eps_p) * psis + eps_fluid<T>(ra, rb, S) * (T(1) - psis);
         if (z >= S.z0 && z <= S.z1) qsum = (double)q;
-        (void)x;
     }
     double v[1] = {qsum};
     const bool mx[1] = {false};
@@ -245,7 +279,12 @@ __global__ __launch_bounds__(kBlock) void k_moments(Scalars S, Fields<T> F) {
 }
 
 template <typename T> void launch_moments(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st) {
-    hipLaunchKernelGGL(k_moments<T>, dim3(nblk), dim3(kBlock), 0, st, S, F);
+    if (S.colloids)
+        hipLaunchKernelGGL((k_moments<T, kColloids>), dim3(nblk), dim3(kBlock), 0, st, S, F);
+    else if (S.walls)
+        hipLaunchKernelGGL((k_moments<T, kWalls>), dim3(nblk), dim3(kBlock), 0, st, S, F);
+    else
+        hipLaunchKernelGGL((k_moments<T, kPeriodic>), dim3(nblk), dim3(kBlock), 0, st, S, F);
 }
 
 // Virtual densities (Sec. II E, after Jansen et al.): a solid site with a fluid D3Q19
@@ -271,11 +310,15 @@ __global__ __launch_bounds__(kBlock) void k_virtual(Scalars S, Fields<T> F) {
         ++cnt;
     }
     if (cnt == 0) return;
-    const T ra = sa / T(cnt), rb = sb / T(cnt);
-    F.mom[i] = ra;
-    F.mom[(size_t)S.N + i] = rb;
-    F.mom[2 * (size_t)S.N + i] = pseudo<T>(ra, S);
-    F.mom[3 * (size_t)S.N + i] = pseudo<T>(rb, S);
+    const size_t N = S.N;
+    const T da = sa / T(cnt), db = sb / T(cnt);
+    const T ra = T(S.rref[0]) + da, rb = T(S.rref[1]) + db;
+    const T pb = pseudo<T>(rb, S);
+    F.mom[i] = da;
+    F.mom[N + i] = db;
+    F.mom[2 * N + i] = pseudo<T>(ra, S);
+    F.mom[3 * N + i] = pb;
+    F.mom[4 * N + i] = T(S.G) * pb;
     const T psis = T(1) - psif_at(i, z, S, F);
     F.eps[i] = T(S.eps_p) * psis + eps_fluid<T>(ra, rb, S) * (T(1) - psis);
 }
@@ -409,6 +452,22 @@ __global__ __launch_bounds__(kBlock) void k_phi_finalize(Scalars S, double* phi,
 
 void launch_phi_finalize(const Scalars& S, double* phi, const double* scal, int zero, hipStream_t st) {
     hipLaunchKernelGGL(k_phi_finalize, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, phi, scal, zero);
+}
+
+// Warm start of the next solve by linear extrapolation in time,
+// phi <- 2 phi(t-1) - phi(t-2), keeping phi(t-1) for the following step.
+__global__ __launch_bounds__(kBlock) void k_phi_extrapolate(Scalars S, double* phi, double* phi_prev) {
+    const unsigned i = xcd_linear();
+    if (i >= S.N) return;
+    const int z = (i / S.nx) / S.ny;
+    if (z < S.z0 || z > S.z1) return;
+    const double p = phi[i];
+    phi[i] = 2.0 * p - phi_prev[i];
+    phi_prev[i] = p;
+}
+
+void launch_phi_extrapolate(const Scalars& S, double* phi, double* phi_prev, hipStream_t st) {
+    hipLaunchKernelGGL(k_phi_extrapolate, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, phi, phi_prev);
 }
 
 // Wall layers: Gauss's law at the charged wall face, phi_wall = phi_adjacent + sigma / eps_adjacent.
@@ -655,23 +714,16 @@ void launch_mg_coarse_solve(const MGLevel& L, int iters, double omega, hipStream
 // identical order, so the two see bit-identical fluxes and the update conserves ions.
 // ------------------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void link_flux(T nplo, T nmlo, T nphi, T nmhi, T pflo, T pfhi, T Elo, T Ehi, T ralo,
-                                          T rahi, const Scalars& S, T& Jp, T& Jm) {
+__device__ __forceinline__ void link_flux(T tpl, T tml, T tph, T tmh, T w, T Elo, T Ehi, T ralo, T rahi,
+                                          const Scalars& S, T& Jp, T& Jm) {
 #pragma clang fp contract(off)
-    if (pflo > T(0) && pfhi > T(0)) {
-        const T tpl = nplo / pflo, tph = nphi / pfhi, tml = nmlo / pflo, tmh = nmhi / pfhi;
-        const T es = Elo + Ehi;
-        const T dra = rahi - ralo;
-        const T qb = T(0.25) * T(S.beta);
-        const T bp = (tph - tpl) - qb * (tpl + tph) * es + T(S.kap_p) * (tpl + tph) * dra;
-        const T bm = (tmh - tml) + qb * (tml + tmh) * es + T(S.kap_m) * (tml + tmh) * dra;
-        const T w = -T(S.D) * pflo * pfhi;
-        Jp = w * bp;
-        Jm = w * bm;
-    } else {
-        Jp = T(0);
-        Jm = T(0);
-    }
+    const T es = Elo + Ehi;
+    const T dra = rahi - ralo;
+    const T qb = T(0.25) * T(S.beta);
+    const T bp = (tph - tpl) - qb * (tpl + tph) * es + T(S.kap_p) * (tpl + tph) * dra;
+    const T bm = (tmh - tml) + qb * (tml + tmh) * es + T(S.kap_m) * (tml + tmh) * dra;
+    Jp = w * bp;
+    Jm = w * bm;
 }
 
 // Donor-cell advection across lo -> hi (only between LB-fluid sites).
@@ -681,47 +733,105 @@ __device__ __forceinline__ T advect(T nlo, T nhi, T ulo, T uhi) {
     return nlo * (ulo > T(0) ? ulo : T(0)) - nhi * (uhi < T(0) ? -uhi : T(0));
 }
 
-// The six links of site i: friction sums (sum over species of J on the +k and -k link,
-// per axis) and, when update is set, the new ion densities.
-template <typename T, bool kUpdate>
-__device__ __forceinline__ void site_links(unsigned i, int x, int y, int z, const Nbr& o, bool solid_i,
-                                           const Scalars& S, const Fields<T>& F, T (&jsum)[3], T& np_new,
-                                           T& nm_new) {
+// Potential values around a site shared by the field evaluations of one site: the six
+// axis neighbours (a[k][0] at -e_k, a[k][1] at +e_k) and the six second neighbours.
+struct PhiStar {
+    double c;
+    double a[3][2];
+    double b[3][2];
+};
+
+__device__ __forceinline__ PhiStar load_phi_star(unsigned i, int x, int y, int z, const Nbr& o, const Scalars& S,
+                                                 const double* phi) {
+    PhiStar P;
+    P.c = phi[i];
+    P.a[0][0] = phi[i + o.xm];
+    P.a[0][1] = phi[i + o.xp];
+    P.a[1][0] = phi[i + o.ym];
+    P.a[1][1] = phi[i + o.yp];
+    P.a[2][0] = phi[i + o.zm];
+    P.a[2][1] = phi[i + o.zp];
+    const int row = S.nx * (y + S.ny * z);
+    P.b[0][0] = phi[wrapc(x - 2, S.nx) + row];
+    P.b[0][1] = phi[wrapc(x + 2, S.nx) + row];
+    const int zr = S.nx * S.ny * z;
+    P.b[1][0] = phi[x + S.nx * wrapc(y - 2, S.ny) + zr];
+    P.b[1][1] = phi[x + S.nx * wrapc(y + 2, S.ny) + zr];
+    const int xy = x + S.nx * y;
+    P.b[2][0] = phi[xy + S.nxy * wrapc(z - 2, S.nz)];
+    P.b[2][1] = phi[xy + S.nxy * wrapc(z + 2, S.nz)];
+    return P;
+}
+
+// Field component k at the site (E0), at its -e_k neighbour (El) and at its +e_k
+// neighbour (Eh); the normal component on a wall layer is one-sided.
+__device__ __forceinline__ void field_line(int k, int z, const PhiStar& P, const Scalars& S, double& El, double& E0,
+                                           double& Eh) {
+    E0 = -0.5 * (P.a[k][1] - P.a[k][0]) + S.E_ext[k];
+    if (k == 2 && S.walls && z - 1 == 0)
+        El = -(P.c - P.a[2][0]) + S.E_ext[2];
+    else
+        El = -0.5 * (P.c - P.b[k][0]) + S.E_ext[k];
+    if (k == 2 && S.walls && z + 1 == S.nz - 1)
+        Eh = -(P.a[2][1] - P.c) + S.E_ext[2];
+    else
+        Eh = -0.5 * (P.b[k][1] - P.c) + S.E_ext[k];
+}
+
+// The six links of (non-wall) site i: friction sums (sum over species of J on the +k and
+// -k link, per axis), and when kUpdate the new ion densities.  El/Eh of every axis are
+// returned for the Kelvin force.
+template <typename T, int G, bool kUpdate>
+__device__ __forceinline__ void site_links(unsigned i, int z, const Nbr& o, bool solid_i, const PhiStar& P,
+                                           const Scalars& S, const Fields<T>& F, T (&jsum)[3], double (&El)[3],
+                                           double (&Eh)[3], T& np_new, T& nm_new) {
     const T np_i = F.n[0][i], nm_i = F.n[1][i];
-    const T pf_i = psif_at(i, z, S, F);
     const T ra_i = F.mom[i];
+    const T pf_i = fluid_fraction<T, G>(i, z, S, F);
+    const T inv_i = G == kColloids ? (pf_i > T(0) ? T(1) / pf_i : T(0)) : T(1);
+    const T tp_i = np_i * inv_i, tm_i = nm_i * inv_i;
     T out_p = T(0), out_m = T(0);
+    T u_i[3];
+    if (kUpdate && !solid_i) {
+        u_i[0] = F.uph[i];
+        u_i[1] = F.uph[(size_t)S.N + i];
+        u_i[2] = F.uph[2 * (size_t)S.N + i];
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int offm = k == 0 ? o.xm : (k == 1 ? o.ym : o.zm);
         const int offp = k == 0 ? o.xp : (k == 1 ? o.yp : o.zp);
         const unsigned lo = i + offm, hi = i + offp;
         const int zlo = k == 2 ? wrapc(z - 1, S.nz) : z, zhi = k == 2 ? wrapc(z + 1, S.nz) : z;
-        const int xlo = k == 0 ? wrapc(x - 1, S.nx) : x, xhi = k == 0 ? wrapc(x + 1, S.nx) : x;
-        const int ylo = k == 1 ? wrapc(y - 1, S.ny) : y, yhi = k == 1 ? wrapc(y + 1, S.ny) : y;
-        const T E_i = (T)efield(k, x, y, z, F.phi, S);
-        const T E_lo = (T)efield(k, xlo, ylo, zlo, F.phi, S);
-        const T E_hi = (T)efield(k, xhi, yhi, zhi, F.phi, S);
+        double E0;
+        field_line(k, z, P, S, El[k], E0, Eh[k]);
+        const T Ei = (T)E0, Elo = (T)El[k], Ehi = (T)Eh[k];
         const T np_lo = F.n[0][lo], nm_lo = F.n[1][lo], np_hi = F.n[0][hi], nm_hi = F.n[1][hi];
-        const T pf_lo = psif_at(lo, zlo, S, F), pf_hi = psif_at(hi, zhi, S, F);
         const T ra_lo = F.mom[lo], ra_hi = F.mom[hi];
+        const T pf_lo = fluid_fraction<T, G>(lo, zlo, S, F), pf_hi = fluid_fraction<T, G>(hi, zhi, S, F);
+        T inv_lo = T(1), inv_hi = T(1);
+        if (G == kColloids) {
+            inv_lo = pf_lo > T(0) ? T(1) / pf_lo : T(0);
+            inv_hi = pf_hi > T(0) ? T(1) / pf_hi : T(0);
+        }
+        const T wlo = (pf_lo > T(0) && pf_i > T(0)) ? -T(S.D) * pf_lo * pf_i : T(0);
+        const T whi = (pf_i > T(0) && pf_hi > T(0)) ? -T(S.D) * pf_i * pf_hi : T(0);
         T Jp_lo, Jm_lo, Jp_hi, Jm_hi;
-        link_flux<T>(np_lo, nm_lo, np_i, nm_i, pf_lo, pf_i, E_lo, E_i, ra_lo, ra_i, S, Jp_lo, Jm_lo);
-        link_flux<T>(np_i, nm_i, np_hi, nm_hi, pf_i, pf_hi, E_i, E_hi, ra_i, ra_hi, S, Jp_hi, Jm_hi);
+        link_flux<T>(np_lo * inv_lo, nm_lo * inv_lo, tp_i, tm_i, wlo, Elo, Ei, ra_lo, ra_i, S, Jp_lo, Jm_lo);
+        link_flux<T>(tp_i, tm_i, np_hi * inv_hi, nm_hi * inv_hi, whi, Ei, Ehi, ra_i, ra_hi, S, Jp_hi, Jm_hi);
         jsum[k] = ((Jp_hi + Jp_lo) + Jm_hi) + Jm_lo;
         if (kUpdate) {
             T Ap_lo = 0, Am_lo = 0, Ap_hi = 0, Am_hi = 0;
             if (!solid_i) {
-                const T u_i = F.uph[(size_t)k * S.N + i];
-                if (!solid_at(lo, zlo, S, F)) {
+                if (!is_solid<T, G>(lo, zlo, S, F)) {
                     const T u_lo = F.uph[(size_t)k * S.N + lo];
-                    Ap_lo = advect<T>(np_lo, np_i, u_lo, u_i);
-                    Am_lo = advect<T>(nm_lo, nm_i, u_lo, u_i);
+                    Ap_lo = advect<T>(np_lo, np_i, u_lo, u_i[k]);
+                    Am_lo = advect<T>(nm_lo, nm_i, u_lo, u_i[k]);
                 }
-                if (!solid_at(hi, zhi, S, F)) {
+                if (!is_solid<T, G>(hi, zhi, S, F)) {
                     const T u_hi = F.uph[(size_t)k * S.N + hi];
-                    Ap_hi = advect<T>(np_i, np_hi, u_i, u_hi);
-                    Am_hi = advect<T>(nm_i, nm_hi, u_i, u_hi);
+                    Ap_hi = advect<T>(np_i, np_hi, u_i[k], u_hi);
+                    Am_hi = advect<T>(nm_i, nm_hi, u_i[k], u_hi);
                 }
             }
             out_p += (Jp_hi + Ap_hi) - (Jp_lo + Ap_lo);
@@ -735,31 +845,23 @@ __device__ __forceinline__ void site_links(unsigned i, int x, int y, int z, cons
 }
 
 // Forces on both fluid components at fluid site i (Sec. II C):
-//   Phi^a = -psi^a sum_d w_d [G psi^b + G_a+ n+ + G_a- n-](i+d) c_d + (rho^a/rho) F
-//   Phi^b = -psi^b sum_d w_d  G psi^a(i+d) c_d                      + (rho^b/rho) F
+//   Phi^a = -psi^a sum_d w_d chi_a(i+d) c_d + (rho^a/rho) F,   chi_a = G psi^b + G_a+ n+ + G_a- n-
+//   Phi^b = -psi^b sum_d w_d G psi^a(i+d) c_d + (rho^b/rho) F
 //   F = (1/(2 beta D)) sum_{Q6} sum_+- J c_d  -  ((eps_f - eps_bar)/4) sum_{Q6} E^2(i+d) c_d  +  rho g
-// Ion pseudopotentials count on LB-fluid neighbours only; solid neighbours next to fluid
-// carry virtual densities.
 template <typename T>
-__device__ __forceinline__ void site_forces(unsigned i, int x, int y, int z, const Nbr& o, T ra, T rb,
-                                            const T (&jsum)[3], const Scalars& S, const Fields<T>& F, T (&Pa)[3],
-                                            T (&Pb)[3]) {
-    const T psa = F.mom[2 * (size_t)S.N + i], psb = F.mom[3 * (size_t)S.N + i];
+__device__ __forceinline__ void site_forces(unsigned i, const Nbr& o, T ra, T rb, const T (&jsum)[3],
+                                            const double (&El)[3], const double (&Eh)[3], const Scalars& S,
+                                            const Fields<T>& F, const double* phi, T (&Pa)[3], T (&Pb)[3]) {
+    const size_t N = S.N;
+    const T psa = F.mom[2 * N + i], psb = F.mom[3 * N + i];
     T sa[3] = {0, 0, 0}, sb[3] = {0, 0, 0};
-    const T G = T(S.G);
 #pragma unroll
     for (int d = 0; d < kQ; ++d) {
         if (d == kRest) continue;
         const unsigned j = i + offset_of(o, d);
         const T w = T(weight(d));
-        const T pa_j = F.mom[2 * (size_t)S.N + j], pb_j = F.mom[3 * (size_t)S.N + j];
-        T ion = T(0);
-        if (S.ion_sc) {
-            const int zj = wrapc(z + vz(d), S.nz);
-            if (!solid_at(j, zj, S, F)) ion = T(S.G_p) * F.n[0][j] + T(S.G_m) * F.n[1][j];
-        }
-        const T ta = w * (G * pb_j + ion);
-        const T tb = w * (G * pa_j);
+        const T ta = w * F.mom[4 * N + j];
+        const T tb = w * F.mom[2 * N + j];
         if (vx(d) > 0) { sa[0] += ta; sb[0] += tb; }
         if (vx(d) < 0) { sa[0] -= ta; sb[0] -= tb; }
         if (vy(d) > 0) { sa[1] += ta; sb[1] += tb; }
@@ -767,15 +869,31 @@ __device__ __forceinline__ void site_forces(unsigned i, int x, int y, int z, con
         if (vz(d) > 0) { sa[2] += ta; sb[2] += tb; }
         if (vz(d) < 0) { sa[2] -= ta; sb[2] -= tb; }
     }
+    const T G = T(S.G);
     T FK[3] = {0, 0, 0};
     if (S.kelvin) {
+        // full field vectors at the six neighbours: the component along the link comes
+        // from the axis line, the two others from the twelve face-diagonal potentials
+        const double ex = S.E_ext[0], ey = S.E_ext[1], ez = S.E_ext[2];
+        auto dg = [&](int sx, int sy, int sz) {
+            int off = (sx < 0 ? o.xm : (sx > 0 ? o.xp : 0)) + (sy < 0 ? o.ym : (sy > 0 ? o.yp : 0)) +
+                      (sz < 0 ? o.zm : (sz > 0 ? o.zp : 0));
+            return phi[i + off];
+        };
+        const double pxpy = dg(1, 1, 0), pxmy = dg(1, -1, 0), mxpy = dg(-1, 1, 0), mxmy = dg(-1, -1, 0);
+        const double pxpz = dg(1, 0, 1), pxmz = dg(1, 0, -1), mxpz = dg(-1, 0, 1), mxmz = dg(-1, 0, -1);
+        const double pypz = dg(0, 1, 1), pymz = dg(0, 1, -1), mypz = dg(0, -1, 1), mymz = dg(0, -1, -1);
+        auto sq = [](double a, double b, double c) { return a * a + b * b + c * c; };
+        const double e2_px = sq(Eh[0], -0.5 * (pxpy - pxmy) + ey, -0.5 * (pxpz - pxmz) + ez);
+        const double e2_mx = sq(El[0], -0.5 * (mxpy - mxmy) + ey, -0.5 * (mxpz - mxmz) + ez);
+        const double e2_py = sq(-0.5 * (pxpy - mxpy) + ex, Eh[1], -0.5 * (pypz - pymz) + ez);
+        const double e2_my = sq(-0.5 * (pxmy - mxmy) + ex, El[1], -0.5 * (mypz - mymz) + ez);
+        const double e2_pz = sq(-0.5 * (pxpz - mxpz) + ex, -0.5 * (pypz - mypz) + ey, Eh[2]);
+        const double e2_mz = sq(-0.5 * (pxmz - mxmz) + ex, -0.5 * (pymz - mymz) + ey, El[2]);
         const T fac = T(-0.25) * (eps_fluid<T>(ra, rb, S) - T(S.eps_bar));
-        const int xm = wrapc(x - 1, S.nx), xp = wrapc(x + 1, S.nx);
-        const int ym = wrapc(y - 1, S.ny), yp = wrapc(y + 1, S.ny);
-        const int zm = wrapc(z - 1, S.nz), zp = wrapc(z + 1, S.nz);
-        FK[0] = fac * (T)(efield_sq(xp, y, z, F.phi, S) - efield_sq(xm, y, z, F.phi, S));
-        FK[1] = fac * (T)(efield_sq(x, yp, z, F.phi, S) - efield_sq(x, ym, z, F.phi, S));
-        FK[2] = fac * (T)(efield_sq(x, y, zp, F.phi, S) - efield_sq(x, y, zm, F.phi, S));
+        FK[0] = fac * (T)(e2_px - e2_mx);
+        FK[1] = fac * (T)(e2_py - e2_my);
+        FK[2] = fac * (T)(e2_pz - e2_mz);
     }
     const T rt = ra + rb;
     const T ifr = T(0.5) / (T(S.beta) * T(S.D));
@@ -783,7 +901,7 @@ __device__ __forceinline__ void site_forces(unsigned i, int x, int y, int z, con
     for (int k = 0; k < 3; ++k) {
         const T Frest = jsum[k] * ifr + FK[k] + rt * T(S.g_body[k]);
         Pa[k] = -psa * sa[k] + (ra / rt) * Frest;
-        Pb[k] = -psb * sb[k] + (rb / rt) * Frest;
+        Pb[k] = -psb * (G * sb[k]) + (rb / rt) * Frest;
     }
 }
 
@@ -791,30 +909,39 @@ __device__ __forceinline__ void site_forces(unsigned i, int x, int y, int z, con
 // Total force and physical velocity u = u' + (Phi^a + Phi^b) / (2 rho) of every fluid
 // site (needed by the donor-cell ion advection of the neighbours).
 // ------------------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_force(Scalars S, Fields<T> F) {
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock, kHotOcc<T>) void k_force(Scalars S, Fields<T> F) {
     const unsigned i = xcd_linear();
     if (i >= S.N) return;
     const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
-    if (solid_at(i, z, S, F)) {
+    const size_t N = S.N;
+    if (is_solid<T, G>(i, z, S, F)) {
         F.uph[i] = T(0);
-        F.uph[(size_t)S.N + i] = T(0);
-        F.uph[2 * (size_t)S.N + i] = T(0);
+        F.uph[N + i] = T(0);
+        F.uph[2 * N + i] = T(0);
         return;
     }
     const Nbr o = make_nbr(x, y, z, S);
-    T jsum[3], dummy_p, dummy_m;
-    site_links<T, false>(i, x, y, z, o, false, S, F, jsum, dummy_p, dummy_m);
-    const T ra = F.mom[i], rb = F.mom[(size_t)S.N + i];
+    const PhiStar P = load_phi_star(i, x, y, z, o, S, F.phi);
+    T jsum[3], dp, dm;
+    double El[3], Eh[3];
+    site_links<T, G, false>(i, z, o, false, P, S, F, jsum, El, Eh, dp, dm);
+    const T ra = T(S.rref[0]) + F.mom[i], rb = T(S.rref[1]) + F.mom[N + i];
     T Pa[3], Pb[3];
-    site_forces<T>(i, x, y, z, o, ra, rb, jsum, S, F, Pa, Pb);
+    site_forces<T>(i, o, ra, rb, jsum, El, Eh, S, F, F.phi, Pa, Pb);
     const T rt2 = T(2) * (ra + rb);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) F.uph[(size_t)k * S.N + i] = F.mom[(size_t)(4 + k) * S.N + i] + (Pa[k] + Pb[k]) / rt2;
+    for (int k = 0; k < 3; ++k) F.uph[(size_t)k * N + i] = F.mom[(size_t)(5 + k) * N + i] + (Pa[k] + Pb[k]) / rt2;
 }
 
 template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hipStream_t st) {
-    hipLaunchKernelGGL(k_force<T>, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F);
+    const dim3 g(site_blocks(S.N)), b(kBlock);
+    if (S.colloids)
+        hipLaunchKernelGGL((k_force<T, kColloids>), g, b, 0, st, S, F);
+    else if (S.walls)
+        hipLaunchKernelGGL((k_force<T, kWalls>), g, b, 0, st, S, F);
+    else
+        hipLaunchKernelGGL((k_force<T, kPeriodic>), g, b, 0, st, S, F);
 }
 
 // ------------------------------------------------------------------------------------
@@ -823,75 +950,71 @@ template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hi
 // A population headed into a solid site returns half-way (Sec. II E):
 //   g_{d*}(i, t+1) = g*_d(i) - 6 w_d rho^s(i) (c_d . v)      (w_d = w_{d*})
 // and, for a particle site, the momentum (2 f*_d - 6 w_d rho^s (c_d . v)) c_d is written
-// to the link's record (deterministic per-particle sum later).
+// to the link's record (deterministic per-particle sum later).  The collision reads each
+// population only when tau != 1: at tau = 1 the post-collision state is the equilibrium
+// of the moments (already in the moment slots), and populations are streamed as written.
 // ------------------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fused(Scalars S, Fields<T> F) {
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock, kHotOcc<T>) void k_fused(Scalars S, Fields<T> F) {
     const unsigned i = xcd_linear();
     if (i >= S.N) return;
     const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+    if (G == kWalls && (z == 0 || z == S.nz - 1)) return;  // wall layers hold no ions and no fluid
+    const size_t N = S.N;
     const Nbr o = make_nbr(x, y, z, S);
-    const bool solid_i = solid_at(i, z, S, F);
+    const bool solid_i = is_solid<T, G>(i, z, S, F);
+    const PhiStar P = load_phi_star(i, x, y, z, o, S, F.phi);
     T jsum[3], np_new, nm_new;
-    site_links<T, true>(i, x, y, z, o, solid_i, S, F, jsum, np_new, nm_new);
+    double El[3], Eh[3];
+    site_links<T, G, true>(i, z, o, solid_i, P, S, F, jsum, El, Eh, np_new, nm_new);
     F.nn[0][i] = np_new;
     F.nn[1][i] = nm_new;
     if (solid_i) return;
 
-    // moments of the time-t populations (same arithmetic as k_moments)
-    T g[2][kQ];
-    T sa = 0, sb = 0, mx = 0, my = 0, mz = 0;
-#pragma unroll
-    for (int d = 0; d < kQ; ++d) {
-        g[0][d] = F.f[0][(size_t)d * S.N + i];
-        g[1][d] = F.f[1][(size_t)d * S.N + i];
-        sa += g[0][d];
-        sb += g[1][d];
-        const T s = g[0][d] + g[1][d];
-        if (vx(d) > 0) mx += s;
-        if (vx(d) < 0) mx -= s;
-        if (vy(d) > 0) my += s;
-        if (vy(d) < 0) my -= s;
-        if (vz(d) > 0) mz += s;
-        if (vz(d) < 0) mz -= s;
-    }
-    const T ra = T(S.rref[0]) + sa, rb = T(S.rref[1]) + sb;
-    const T rt = ra + rb;
-    const T u0[3] = {mx / rt, my / rt, mz / rt};
+    const T da = F.mom[i], db = F.mom[N + i];
+    const T ra = T(S.rref[0]) + da, rb = T(S.rref[1]) + db;
+    const T u0 = F.mom[5 * N + i], u1 = F.mom[6 * N + i], u2 = F.mom[7 * N + i];
     T Pa[3], Pb[3];
-    site_forces<T>(i, x, y, z, o, ra, rb, jsum, S, F, Pa, Pb);
+    site_forces<T>(i, o, ra, rb, jsum, El, Eh, S, F, F.phi, Pa, Pb);
 
-    const bool near = S.colloids ? (F.flags[i] & 2u) != 0 : (S.walls && (z == 1 || z == S.nz - 2));
-    int link = near && S.colloids ? F.linkbase[i] : 0;
+    const bool near = G == kColloids ? (F.flags[i] & 2u) != 0 : (G == kWalls && (z == 1 || z == S.nz - 2));
+    const int link = (G == kColloids && near) ? F.linkbase[i] : 0;
+    const bool tau1 = S.tau == 1.0;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const T rs = c == 0 ? ra : rb;
-        const T dr = c == 0 ? sa : sb;
+        const T dr = c == 0 ? da : db;
         const T P0 = c == 0 ? Pa[0] : Pb[0], P1 = c == 0 ? Pa[1] : Pb[1], P2 = c == 0 ? Pa[2] : Pb[2];
         const T tau = T(S.tau);
-        const T ue0 = u0[0] + tau * P0 / rs, ue1 = u0[1] + tau * P1 / rs, ue2 = u0[2] + tau * P2 / rs;
+        const T ue0 = u0 + tau * P0 / rs, ue1 = u1 + tau * P1 / rs, ue2 = u2 + tau * P2 / rs;
         const T usq = ue0 * ue0 + ue1 * ue1 + ue2 * ue2;
+        const T* fc = F.f[c];
+        T* fo = F.fn[c];
         int lk = link;
 #pragma unroll
         for (int d = 0; d < kQ; ++d) {
             const T cu = T(vx(d)) * ue0 + T(vy(d)) * ue1 + T(vz(d)) * ue2;
             const T w = T(weight(d));
             const T geq = w * (dr + rs * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq));
-            const T gs = g[c][d] - (g[c][d] - geq) * T(S.inv_tau);
+            T gs = geq;
+            if (!tau1) {
+                const T g = fc[(size_t)d * N + i];
+                gs = g - (g - geq) * T(S.inv_tau);
+            }
             const unsigned j = i + offset_of(o, d);
             bool bounce = false;
-            if (d != kRest && near) bounce = solid_at(j, wrapc(z + vz(d), S.nz), S, F);
+            if (G != kPeriodic && d != kRest && near) bounce = is_solid<T, G>(j, wrapc(z + vz(d), S.nz), S, F);
             if (bounce) {
                 T cv = T(0);
                 int own = -1;
-                if (S.colloids) {
+                if (G == kColloids) {
                     own = F.owner[j];
                     if (own >= 0)
                         cv = T(vx(d)) * T(F.pv[3 * own]) + T(vy(d)) * T(F.pv[3 * own + 1]) +
                              T(vz(d)) * T(F.pv[3 * own + 2]);
                 }
                 const T corr = T(6) * w * rs * cv;
-                F.fn[c][(size_t)opposite(d) * S.N + i] = gs - corr;
+                fo[(size_t)opposite(d) * N + i] = gs - corr;
                 if (own >= 0) {
                     const double dp = 2.0 * ((double)gs + weight(d) * S.rref[c]) - (double)corr;
                     double* rec = F.linkdp + (size_t)lk * 6 + 3 * c;
@@ -901,14 +1024,20 @@ __global__ __launch_bounds__(kBlock) void k_fused(Scalars S, Fields<T> F) {
                     ++lk;
                 }
             } else {
-                F.fn[c][(size_t)d * S.N + j] = gs;
+                fo[(size_t)d * N + j] = gs;
             }
         }
     }
 }
 
 template <typename T> void launch_fused(const Scalars& S, const Fields<T>& F, hipStream_t st) {
-    hipLaunchKernelGGL(k_fused<T>, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F);
+    const dim3 g(site_blocks(S.N)), b(kBlock);
+    if (S.colloids)
+        hipLaunchKernelGGL((k_fused<T, kColloids>), g, b, 0, st, S, F);
+    else if (S.walls)
+        hipLaunchKernelGGL((k_fused<T, kWalls>), g, b, 0, st, S, F);
+    else
+        hipLaunchKernelGGL((k_fused<T, kPeriodic>), g, b, 0, st, S, F);
 }
 
 // ------------------------------------------------------------------------------------

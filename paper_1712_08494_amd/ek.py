@@ -46,7 +46,7 @@ class EKObs(ctypes.Structure):
         ("momentum", ctypes.c_double * 3), ("max_u", ctypes.c_double), ("source_mean", ctypes.c_double),
         ("poisson_rel", ctypes.c_double), ("poisson_iters", ctypes.c_int64), ("poisson_total", ctypes.c_int64),
         ("poisson_mg_levels", ctypes.c_int32), ("steps", ctypes.c_int64), ("drift", ctypes.c_double * 3), ("pmomentum", ctypes.c_double * 3),
-        ("nonfinite", ctypes.c_int32), ("negative_ions", ctypes.c_int32),
+        ("nonfinite", ctypes.c_int32), ("negative_ions", ctypes.c_int32), ("poisson_rel0", ctypes.c_double),
     ]
 
 
@@ -239,7 +239,7 @@ class EKSim:
             "poisson_mg_levels": o.poisson_mg_levels, "steps": o.steps,
             "drift_x": o.drift[0], "drift_y": o.drift[1], "drift_z": o.drift[2], "pmom_x": o.pmomentum[0],
             "pmom_y": o.pmomentum[1], "pmom_z": o.pmomentum[2], "nonfinite": o.nonfinite,
-            "negative_ions": o.negative_ions,
+            "negative_ions": o.negative_ions, "poisson_rel0": o.poisson_rel0,
         }
 
     def field(self, name):

@@ -110,6 +110,56 @@ WALL_RHO_MAJ = 1.2589
 WALL_RHO_MIN = 0.1286
 
 
+def _bisect(f, lo, hi, it=200):
+    flo = f(lo)
+    for _ in range(it):
+        mid = 0.5 * (lo + hi)
+        fm = f(mid)
+        if (fm > 0) == (flo > 0):
+            lo, flo = mid, fm
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def pb_column(nz, zi, rho_a_z, salt, sigma, eps_a, eps_b, dmu_p, dmu_m, drho, sign=1.0):
+    """Equilibrium ion profiles n+(z), n-(z) of a column with charged walls (planes at
+    z = 1/2 and nz - 3/2) and a sharp interface at z = zi between fluid a (below) and b
+    (above), from closed-form Poisson-Boltzmann pieces (beta = e = 1):
+      - ions are Boltzmann distributed in the potential psi and the solvation energy
+        U+- = sign * dmu+- rho^a / drho_a, so the two bulks differ by the Donnan step
+        psi_b - psi_a = U+_a - U+_b;
+      - at the interface each side follows tanh((psi - psi_bulk)/4) ~ exp(-kappa |z - zi|),
+        kappa^2 = 2 n / eps, with psi and eps psi' continuous (one scalar root);
+      - at each wall the Gouy-Chapman solution with sinh(psi0 / 2) = sigma / sqrt(8 eps n).
+    The pieces are superposed; they overlap negligibly when the walls are far from the
+    interface compared with the Debye length.  Returns arrays of length nz (wall layers 0)."""
+    z = np.arange(nz, dtype=np.float64)
+    U_p = sign * dmu_p * rho_a_z / drho
+    U_m = sign * dmu_m * rho_a_z / drho
+    Ua_p, Ub_p = sign * dmu_p * rho_a_z[1] / drho, sign * dmu_p * rho_a_z[-2] / drho
+    Ua_m, Ub_m = sign * dmu_m * rho_a_z[1] / drho, sign * dmu_m * rho_a_z[-2] / drho
+    psi_a = 0.0
+    psi_b = Ua_p - Ub_p  # equals Ub_m - Ua_m when dmu+ = -dmu-
+    ka, kb = np.sqrt(2 * salt / eps_a), np.sqrt(2 * salt / eps_b)
+    g = lambda p0: eps_a * ka * np.sinh((p0 - psi_a) / 2) + eps_b * kb * np.sinh((p0 - psi_b) / 2)
+    lo, hi = min(psi_a, psi_b), max(psi_a, psi_b)
+    psi0 = _bisect(g, lo, hi) if hi > lo else psi_a
+    dz = z - zi
+    dev = np.where(dz < 0,
+                   4 * np.arctanh(np.tanh((psi0 - psi_a) / 4) * np.exp(-ka * np.abs(dz))),
+                   4 * np.arctanh(np.tanh((psi0 - psi_b) / 4) * np.exp(-kb * np.abs(dz))))
+    bulk = np.where(dz < 0, psi_a, psi_b)
+    for zw, k, e in ((0.5, ka, eps_a), (nz - 1.5, kb, eps_b)):
+        p0 = 2 * np.arcsinh(sigma / np.sqrt(8 * e * salt))
+        dev = dev + 4 * np.arctanh(np.tanh(p0 / 4) * np.exp(-k * np.abs(z - zw)))
+    psi = bulk + dev
+    n_p = salt * np.exp(-(psi - psi_a) - (U_p - Ua_p))
+    n_m = salt * np.exp(+(psi - psi_a) - (U_m - Ua_m))
+    n_p[0] = n_p[-1] = n_m[0] = n_m[-1] = 0.0
+    return n_p, n_m
+
+
 def walls_interface(n=128, seed=2, precision="fp32", shape=None, salt=1e-3, sigma=-1e-3, eps_ratio=2.0,
                     dmu=2.0, width=2.0):
     nx, ny, nz = shape if shape is not None else (n, n, n)
@@ -120,21 +170,23 @@ def walls_interface(n=128, seed=2, precision="fp32", shape=None, salt=1e-3, sigm
                    poisson_tol=1e-8, name=f"walls_interface_{nx}x{ny}x{nz}")
     r = _rng(seed)
     sh = (nz, ny, nx)
-    z = np.arange(nz, dtype=np.float64)[:, None, None]
+    z = np.arange(nz, dtype=np.float64)
     # fluid a below the interface plane, fluid b above it
     s = 0.5 * (1.0 + np.tanh((z - (zi - 0.5)) / width))
-    rho_a = WALL_RHO_MAJ + (WALL_RHO_MIN - WALL_RHO_MAJ) * s + 0.0 * np.zeros(sh)
-    rho_b = WALL_RHO_MIN + (WALL_RHO_MAJ - WALL_RHO_MIN) * s + 0.0 * np.zeros(sh)
-    rho_a = rho_a + r.uniform(-1e-4, 1e-4, sh)
-    rho_b = rho_b + r.uniform(-1e-4, 1e-4, sh)
-    n_plus = salt * (1.0 + r.uniform(-1e-3, 1e-3, sh))
-    n_minus = salt * (1.0 + r.uniform(-1e-3, 1e-3, sh))
+    ra_z = WALL_RHO_MAJ + (WALL_RHO_MIN - WALL_RHO_MAJ) * s
+    rb_z = WALL_RHO_MIN + (WALL_RHO_MAJ - WALL_RHO_MIN) * s
+    rho_a = ra_z[:, None, None] + r.uniform(-1e-4, 1e-4, sh)
+    rho_b = rb_z[:, None, None] + r.uniform(-1e-4, 1e-4, sh)
+    # ions start at the equilibrium double layers (walls and interface)
+    np_z, nm_z = pb_column(nz, zi - 0.5, ra_z, salt, sigma, cfg.eps_a, cfg.eps_b, dmu, -dmu, drho)
+    n_plus = np_z[:, None, None] * (1.0 + r.uniform(-1e-4, 1e-4, sh))
+    n_minus = nm_z[:, None, None] * (1.0 + r.uniform(-1e-4, 1e-4, sh))
     fluid = np.ones(sh, dtype=bool)
     fluid[0] = False
     fluid[-1] = False
     n_plus[~fluid] = 0.0
     n_minus[~fluid] = 0.0
-    # counter-ions for the two charged walls, spread uniformly over the fluid
+    # exact neutrality with the two charged walls
     wall_charge = (sigma + sigma) * nx * ny
     n_minus = _neutralise(n_plus, n_minus, extra_charge=wall_charge, mask=fluid)
     return cfg, EKInputs(rho_a, rho_b, n_plus, n_minus)

@@ -90,7 +90,10 @@ def test_colloids_small(precision):
     o.step(20)
     errs = compare(sim, o, precision, "after 20")
     pg, po = sim.particles(), o.particles()
-    tol = 1e-4 if precision == "fp32" else 1e-8
+    # The net force on a sphere is a small difference of O(1) link momenta (about 700
+    # links of magnitude 0.03 give a net force near 0.02): FP32 rounding of the
+    # populations is amplified by that cancellation, hence 2e-3 in FP32.
+    tol = 2e-3 if precision == "fp32" else 1e-8
     # displacement, velocity and the last step's force, relative to their largest component
     disp_g, disp_o = pg[:, 0:3] - inp.particles[:, 0:3], po[:, 0:3] - inp.particles[:, 0:3]
     perr = {"x": np.abs(disp_g - disp_o).max() / np.abs(disp_o).max(),
