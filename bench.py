@@ -24,22 +24,32 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "coupled-step MLUPS + % HBM roofline; FP32/FP64 speedup at stated error; bwd/fwd ratio"
 
-# Algorithmic (compulsory) bytes per site for one launch of each kernel class; see
-# DESIGN.md "Kernels and their rooflines".  s = bytes of a population / ion value.
-def algorithmic_bytes(kernel, s, colloids=False):
+# Algorithmic bytes per lattice site for one launch of each kernel (the data the kernel
+# must move to do its job, each array counted once); s = bytes of one population / ion /
+# moment value (4 in FP32, 8 in FP64).  The potential is always FP64.
+def algorithmic_bytes(kernel, s, tau_one=True):
     if kernel == "fused":
-        # populations read + write (2 x 19 x 2 x s), ions read + write (2 x 2 x s), phi read (8)
-        return 2 * 19 * 2 * s + 2 * 2 * s + 8
+        # populations written (2 x 19), read too when tau != 1; ions read + written (2 x 2);
+        # potential read (8); moment slots read (8); physical velocity read (3)
+        pops = 2 * 19 * s * (1 if tau_one else 2)
+        return pops + 4 * s + 8 + 8 * s + 3 * s
     if kernel == "force":
-        # rho_a, rho_b, psi_a, psi_b, u(3) and ions (2) read, physical velocity (3) written, phi read
-        return 7 * s + 2 * s + 3 * s + 8
+        # moment slots read (8), ions read (2), potential read (8), physical velocity written (3)
+        return 8 * s + 2 * s + 8 + 3 * s
     if kernel == "moments":
-        # populations read (2 x 19 x s), ions read (2 s), moments written (7 s), q and eps written (2 s)
-        return 2 * 19 * s + 2 * s + 7 * s + 2 * s
-    if kernel == "sor":
-        # one colour pass: phi read (8) + half the sites' phi written (4) + eps read (s) + half q read (s/2)
+        # populations read (2 x 19), ions read (2), moment slots written (8), charge and permittivity written (2)
+        return 2 * 19 * s + 2 * s + 8 * s + 2 * s
+    if kernel == "smooth":
+        # one red-black colour pass over the lattice: potential read (8) and half of it
+        # written (4), permittivity read (s), charge read for half the sites (s / 2)
         return 8 + 4 + s + s / 2
     raise KeyError(kernel)
+
+
+# The method's own compulsory traffic per site and step (populations, ions and
+# potential, each read and written once): what a single perfectly fused pass would move.
+def step_bytes(s):
+    return 2 * 19 * 2 * s + 2 * 2 * s + 8
 
 
 def build_workload(name, precision, n):
@@ -131,20 +141,25 @@ def main():
     N = cfg.n_sites
     mlups = N * args.steps / dt / 1e6
     s = 4 if args.precision == "fp32" else 8
-    colloids = inp.particles is not None
 
     # dominant kernel by summed device time
-    cands = {k: timing[k] for k in ("fused", "force", "moments", "sor")}
+    tau_one = cfg.tau == 1.0
+    cands = {k: timing[k] for k in ("fused", "force", "moments", "smooth")}
     dom = max(cands, key=lambda k: cands[k][0])
     ms, count = cands[dom]
     avg_s = ms / 1e3 / max(count, 1)
-    bytes_launch = algorithmic_bytes(dom, s, colloids) * N
-    achieved = bytes_launch / avg_s / 1e9
+    bpsite = algorithmic_bytes(dom, s, tau_one)
+    achieved = bpsite * N / avg_s / 1e9
     kernel_table = {}
-    for k in ("moments", "poisson", "sor", "force", "fused", "particle"):
+    for k in ("moments", "poisson", "iter", "smooth", "force", "fused", "particle"):
         tms, cnt = timing[k]
-        kernel_table[k] = {"ms_total": round(tms, 3), "launches": int(cnt),
-                           "us_per_launch": round(1e3 * tms / cnt, 3) if cnt else None}
+        row = {"ms_total": round(tms, 3), "launches": int(cnt),
+               "us_per_launch": round(1e3 * tms / cnt, 3) if cnt else None}
+        if k in ("fused", "force", "moments", "smooth") and cnt:
+            b = algorithmic_bytes(k, s, tau_one)
+            row["bytes_per_site"] = b
+            row["GBps"] = round(b * N / (tms / 1e3 / cnt) / 1e9, 1)
+        kernel_table[k] = row
     sweeps = (ob1["poisson_total"] - ob0["poisson_total"]) / args.steps
 
     fp64 = None
@@ -174,11 +189,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz}", "sites": N,
                    "precision": args.precision, "poisson_tol": cfg.poisson_tol,
-                   "poisson_sweeps_per_step": round(sweeps, 2)},
+                   "poisson_solver": "multigrid" if ob1["poisson_mg_levels"] else "sor",
+                   "poisson_iterations_per_step": round(sweeps, 2),
+                   "poisson_start_residual": ob1["poisson_rel0"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_site": algorithmic_bytes(dom, s, colloids),
-                     "us_per_launch": round(avg_s * 1e6, 3)},
+                     "bytes_per_site": bpsite, "us_per_launch": round(avg_s * 1e6, 3)},
+        "step_bytes_per_site": step_bytes(s),
+        "step_effective_GBps": round(step_bytes(s) * N * args.steps / dt / 1e9, 1),
         "kernels": kernel_table,
         "fp64_mlups": round(fp64, 2) if fp64 else None,
         "fp32_fp64_speedup": round(mlups / fp64, 3) if fp64 else None,

@@ -111,8 +111,9 @@ typedef struct ek_obs {
 #define EK_T_FORCE 2     /* total force and physical velocity pass */
 #define EK_T_FUSED 3     /* fused ion update + force + collide + stream pass */
 #define EK_T_PARTICLE 4  /* particle force sums and integration */
-#define EK_T_SOR 5       /* the red-black sweep kernels alone (one entry per colour pass) */
-#define EK_T_COUNT 6
+#define EK_T_ITER 5      /* Poisson iterations: SOR sweep chunks (count = sweeps) or V-cycles (count = cycles) */
+#define EK_T_SMOOTH 6    /* each red-black colour pass on the lattice itself (SOR sweep or multigrid smoothing) */
+#define EK_T_COUNT 7
 
 typedef struct ek_timing {
     double ms[EK_T_COUNT];    /* summed device time per class (HIP events) */

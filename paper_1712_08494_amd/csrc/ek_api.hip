@@ -354,37 +354,39 @@ static ek_status check_residual(ek_ctx* c, double& rr, double& ss) {
     return EK_OK;
 }
 
-// One V-cycle on the lattice (level 0) with the coarse levels in c->mg.
+// One V-cycle on the lattice (grid 0) with the coarse grids c->mg[0..nl-1] (grid g >= 1 is
+// c->mg[g - 1]).  The last one or two grids are handled by the single-workgroup tail
+// kernel (the coarsest solve, and the sweeps of the grid above it when small enough).
 template <typename T>
 static void vcycle(ek_ctx* c, const Fields<T>& F) {
     const int nl = (int)c->mg.size();
-    const int pre = 2, post = 2;
-    for (int l = 0; l < nl; ++l) {  // downward leg: smooth, restrict
-        for (int s = 0; s < pre; ++s)
-            for (int color = 0; color < 2; ++color) {
-                if (l == 0)
-                    launch_sor<T>(c->S, F, color, 1.0, c->st);
-                else
-                    launch_mg_smooth(c->mg[l - 1], color, 1.0, c->st);
+    const int tail_mid = (nl >= 2 && c->mg[nl - 2].n <= 4096 && c->mg[nl - 1].n <= 512) ? 1 : 0;
+    const int last_gpu = nl - 1 - tail_mid;  // finest grid handled by the tail, minus one
+    auto smooth = [&](int g) {
+        for (int color = 0; color < 2; ++color) {
+            if (g == 0) {
+                Timer tm(c, EK_T_SMOOTH);
+                launch_sor<T>(c->S, F, color, 1.0, c->st);
+            } else {
+                launch_mg_smooth(c->mg[g - 1], color, 1.0, c->st);
             }
-        if (l == 0)
+        }
+    };
+    const int sweeps = 2;
+    for (int g = 0; g <= last_gpu; ++g) {  // downward leg: smooth grid g, restrict to grid g+1
+        for (int s = 0; s < sweeps; ++s) smooth(g);
+        if (g == 0)
             launch_mg_restrict_fine<T>(c->S, F, c->mg[0], c->st);
         else
-            launch_mg_restrict(c->mg[l - 1], c->mg[l], c->st);
+            launch_mg_restrict(c->mg[g - 1], c->mg[g], c->st);
     }
-    launch_mg_coarse_solve(c->mg[nl - 1], 40, c->mg_coarse_omega, c->st);
-    for (int l = nl - 1; l >= 0; --l) {  // upward leg: interpolate, smooth
-        if (l == 0)
+    launch_mg_tail(tail_mid ? c->mg[nl - 2] : c->mg[nl - 1], c->mg[nl - 1], tail_mid, 30, c->mg_coarse_omega, c->st);
+    for (int g = last_gpu; g >= 0; --g) {  // upward leg: interpolate from grid g+1, smooth grid g
+        if (g == 0)
             launch_mg_prolong_fine<T>(c->S, F, c->mg[0], c->st);
         else
-            launch_mg_prolong(c->mg[l], c->mg[l - 1], c->st);
-        for (int s = 0; s < post; ++s)
-            for (int color = 0; color < 2; ++color) {
-                if (l == 0)
-                    launch_sor<T>(c->S, F, color, 1.0, c->st);
-                else
-                    launch_mg_smooth(c->mg[l - 1], color, 1.0, c->st);
-            }
+            launch_mg_prolong(c->mg[g], c->mg[g - 1], c->st);
+        for (int s = 0; s < sweeps; ++s) smooth(g);
     }
 }
 
@@ -419,7 +421,7 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
             k = std::max(1, std::min(k, 8));
             k = std::min(k, maxit - it);
             {
-                Timer ts(c, EK_T_SOR, k);
+                Timer ts(c, EK_T_ITER, k);
                 for (int s = 0; s < k; ++s) vcycle<T>(c, F);
             }
             EK_HIP(hipGetLastError());
@@ -441,11 +443,12 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
             k = std::max(1, std::min(k, 400));
             k = std::min(k, maxit - it);
             {
-                Timer ts(c, EK_T_SOR, 2 * k);
-                for (int s = 0; s < k; ++s) {
-                    launch_sor<T>(c->S, F, 0, c->omega, c->st);
-                    launch_sor<T>(c->S, F, 1, c->omega, c->st);
-                }
+                Timer ts(c, EK_T_ITER, k);
+                for (int s = 0; s < k; ++s)
+                    for (int color = 0; color < 2; ++color) {
+                        Timer tm(c, EK_T_SMOOTH);
+                        launch_sor<T>(c->S, F, color, c->omega, c->st);
+                    }
             }
             EK_HIP(hipGetLastError());
             it += k;
@@ -776,8 +779,10 @@ extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const doub
             L.n = (unsigned)(dims[0] * dims[1] * dims[2]);
             c->mg.push_back(L);
         }
+        // the coarsest grid is solved inside one workgroup's LDS (at most 4608 cells)
+        if (!c->mg.empty() && c->mg.back().n > 4608) c->mg.clear();
         if (c->mg.empty() && p->poisson_solver == EK_POISSON_MG)
-            return fail(c, EK_EINVAL, "multigrid needs every axis divisible by 4");
+            return fail(c, EK_EINVAL, "multigrid needs every axis divisible by 4 and a coarsest grid of at most 4608 cells");
         if (!c->mg.empty()) {
             // SOR factor of the coarsest level (uniform-coefficient estimate)
             ek_params q = *p;

@@ -175,33 +175,38 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], const bool (
 }
 
 // Sums (or maxima) of nvals values over nblk partial records, fixed order: deterministic.
-__global__ void k_reduce(const double* __restrict__ red, unsigned nblk, int nvals, const int* is_max_d,
-                         double* __restrict__ out) {
-    __shared__ double sm[kRedSlots][kBlock];
-    int is_max[kRedSlots];
-    for (int k = 0; k < kRedSlots; ++k) is_max[k] = (k < nvals && is_max_d) ? is_max_d[k] : 0;
+constexpr int kRedThreads = 1024;
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ red, unsigned nblk, int nvals,
+                                                        const int* is_max_d, double* __restrict__ out) {
+    __shared__ double sm[kRedThreads];
     for (int k = 0; k < nvals; ++k) {
-        double a = is_max[k] ? -1e300 : 0.0;
-        for (unsigned b = threadIdx.x; b < nblk; b += blockDim.x) {
-            double v = red[(size_t)b * kRedSlots + k];
-            a = is_max[k] ? fmax(a, v) : a + v;
+        const bool mx = is_max_d ? is_max_d[k] != 0 : false;
+        double a = mx ? -1e300 : 0.0;
+        unsigned b = threadIdx.x;
+        for (; b + 3 * kRedThreads < nblk; b += 4 * kRedThreads) {
+            const double v0 = red[(size_t)b * kRedSlots + k], v1 = red[(size_t)(b + kRedThreads) * kRedSlots + k];
+            const double v2 = red[(size_t)(b + 2 * kRedThreads) * kRedSlots + k];
+            const double v3 = red[(size_t)(b + 3 * kRedThreads) * kRedSlots + k];
+            a = mx ? fmax(fmax(a, v0), fmax(v1, fmax(v2, v3))) : a + ((v0 + v1) + (v2 + v3));
         }
-        sm[k][threadIdx.x] = a;
-    }
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < nvals; ++k)
-                sm[k][threadIdx.x] = is_max[k] ? fmax(sm[k][threadIdx.x], sm[k][threadIdx.x + s])
-                                               : sm[k][threadIdx.x] + sm[k][threadIdx.x + s];
+        for (; b < nblk; b += kRedThreads) {
+            const double v = red[(size_t)b * kRedSlots + k];
+            a = mx ? fmax(a, v) : a + v;
+        }
+        sm[threadIdx.x] = a;
+        __syncthreads();
+        for (int s2 = kRedThreads / 2; s2 > 0; s2 >>= 1) {
+            if ((int)threadIdx.x < s2) sm[threadIdx.x] = mx ? fmax(sm[threadIdx.x], sm[threadIdx.x + s2]) : sm[threadIdx.x] + sm[threadIdx.x + s2];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = sm[0];
         __syncthreads();
     }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < nvals; ++k) out[k] = sm[k][0];
 }
 
 void launch_reduce(const double* red, unsigned nblk, int nvals, const int* is_max, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, red, nblk, nvals, is_max, out);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, st, red, nblk, nvals, is_max, out);
 }
 
 // ------------------------------------------------------------------------------------
@@ -329,14 +334,19 @@ template <typename T> void launch_virtual(const Scalars& S, const Fields<T>& F, 
 }
 
 // Mean of the Poisson source over the domain: (sum q + wall charges) / sites.
-__global__ void k_source_mean(Scalars S, const double* __restrict__ red, unsigned nblk, double* scal) {
-    __shared__ double sm[kBlock];
+__global__ __launch_bounds__(kRedThreads) void k_source_mean(Scalars S, const double* __restrict__ red, unsigned nblk,
+                                                             double* scal) {
+    __shared__ double sm[kRedThreads];
     double a = 0.0;
-    for (unsigned b = threadIdx.x; b < nblk; b += blockDim.x) a += red[(size_t)b * kRedSlots];
+    unsigned b = threadIdx.x;
+    for (; b + 3 * kRedThreads < nblk; b += 4 * kRedThreads)
+        a += (red[(size_t)b * kRedSlots] + red[(size_t)(b + kRedThreads) * kRedSlots]) +
+             (red[(size_t)(b + 2 * kRedThreads) * kRedSlots] + red[(size_t)(b + 3 * kRedThreads) * kRedSlots]);
+    for (; b < nblk; b += kRedThreads) a += red[(size_t)b * kRedSlots];
     sm[threadIdx.x] = a;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    for (int s2 = kRedThreads / 2; s2 > 0; s2 >>= 1) {
+        if ((int)threadIdx.x < s2) sm[threadIdx.x] += sm[threadIdx.x + s2];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -347,7 +357,7 @@ __global__ void k_source_mean(Scalars S, const double* __restrict__ red, unsigne
 }
 
 void launch_source_mean(const Scalars& S, double* red, unsigned nblk, double* scal, hipStream_t st) {
-    hipLaunchKernelGGL(k_source_mean, dim3(1), dim3(kBlock), 0, st, S, red, nblk, scal);
+    hipLaunchKernelGGL(k_source_mean, dim3(1), dim3(kRedThreads), 0, st, S, red, nblk, scal);
 }
 
 // ------------------------------------------------------------------------------------
@@ -678,32 +688,111 @@ void launch_mg_prolong(const MGLevel& c, const MGLevel& f, hipStream_t st) {
     hipLaunchKernelGGL(k_mg_prolong, dim3((f.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c, f);
 }
 
-// Coarsest level: red-black SOR sweeps inside one workgroup (the level is tiny).
-__global__ __launch_bounds__(kBlock) void k_mg_coarse_solve(MGLevel L, int iters, double omega) {
-    const unsigned half = L.n / 2;
-    for (unsigned t = threadIdx.x; t < L.n; t += blockDim.x) L.phi[t] = 0.0;
-    __syncthreads();
-    for (int it = 0; it < iters; ++it) {
+// The last two levels in one workgroup: on the smaller of them ("mid", at most
+// kTailMid cells) two red-black Gauss-Seidel sweeps, restriction to the coarsest level
+// (at most kTailCoarse cells), red-black SOR sweeps there, interpolation back and two
+// more sweeps.  Potentials and right-hand sides live in LDS; face coefficients are read
+// from global memory (they stay in L2).  When has_mid is 0 only the coarsest solve runs.
+constexpr int kTailThreads = 512;
+constexpr unsigned kTailMid = 4096, kTailCoarse = 512;
+
+struct LdsLevel {
+    const MGLevel* L;
+    double* phi;
+    const double* s;
+};
+
+__device__ __forceinline__ void tail_row(const MGLevel& L, const double* phi, int x, int y, int z, double& diag,
+                                         double& off) {
+    const int xm = wrapc(x - 1, L.nx), xp = wrapc(x + 1, L.nx);
+    const int ym = wrapc(y - 1, L.ny), yp = wrapc(y + 1, L.ny);
+    const int zm = wrapc(z - 1, L.nz), zp = wrapc(z + 1, L.nz);
+    const unsigned i = lid(L, x, y, z);
+    const double a0 = L.ax[i], a1 = L.ax[lid(L, xm, y, z)];
+    const double b0 = L.ay[i], b1 = L.ay[lid(L, x, ym, z)];
+    const double c0 = L.az[i], c1 = L.az[lid(L, x, y, zm)];
+    diag = a0 + a1 + b0 + b1 + c0 + c1;
+    off = a0 * phi[lid(L, xp, y, z)] + a1 * phi[lid(L, xm, y, z)] + b0 * phi[lid(L, x, yp, z)] +
+          b1 * phi[lid(L, x, ym, z)] + c0 * phi[lid(L, x, y, zp)] + c1 * phi[lid(L, x, y, zm)];
+}
+
+__device__ void tail_sweeps(const MGLevel& L, double* phi, const double* rhs, int sweeps, double omega) {
+    const unsigned half = L.n / 2, hx = (unsigned)(L.nx >> 1);
+    for (int it = 0; it < sweeps; ++it)
         for (int color = 0; color < 2; ++color) {
             for (unsigned t = threadIdx.x; t < half; t += blockDim.x) {
-                const unsigned hx = (unsigned)(L.nx >> 1);
                 const unsigned row = t / hx, m = t % hx;
                 const int y = row % L.ny, z = row / L.ny;
                 const int x = 2 * m + ((color + y + z) & 1);
                 double diag, off;
-                mg_row(L, x, y, z, diag, off);
+                tail_row(L, phi, x, y, z, diag, off);
                 if (diag > 0.0) {
                     const unsigned i = lid(L, x, y, z);
-                    L.phi[i] = L.phi[i] + omega * ((off + L.s[i]) / diag - L.phi[i]);
+                    phi[i] = phi[i] + omega * ((off + rhs[i]) / diag - phi[i]);
                 }
             }
             __syncthreads();
         }
+}
+
+__global__ __launch_bounds__(kTailThreads) void k_mg_tail(MGLevel M, MGLevel C, int has_mid, int coarse_iters,
+                                                         double coarse_omega) {
+    extern __shared__ double lds[];
+    // with a mid grid: [phi_c | s_c] in 2 x kTailCoarse, then [phi_m | s_m] in 2 x kTailMid;
+    // coarsest only: [phi_c | s_c] may use the whole allocation (C.n <= kTailCoarse + kTailMid)
+    double* phic = lds;
+    double* sc = lds + (has_mid ? kTailCoarse : C.n);
+    double* phim = lds + 2 * kTailCoarse;
+    double* sm = phim + kTailMid;
+    if (has_mid) {
+        for (unsigned t = threadIdx.x; t < M.n; t += blockDim.x) {
+            phim[t] = 0.0;
+            sm[t] = M.s[t];
+        }
+        __syncthreads();
+        tail_sweeps(M, phim, sm, 2, 1.0);
+        // restriction: sum of the eight children's residuals
+        for (unsigned t = threadIdx.x; t < C.n; t += blockDim.x) {
+            const int I = t % C.nx, r = t / C.nx, J = r % C.ny, K = r / C.ny;
+            double sum = 0.0;
+            for (int c = 0; c < 2; ++c)
+                for (int b = 0; b < 2; ++b)
+                    for (int a = 0; a < 2; ++a) {
+                        const int x = 2 * I + a, y = 2 * J + b, z = 2 * K + c;
+                        double diag, off;
+                        tail_row(M, phim, x, y, z, diag, off);
+                        const unsigned i = lid(M, x, y, z);
+                        sum += sm[i] + off - diag * phim[i];
+                    }
+            sc[t] = sum;
+            phic[t] = 0.0;
+        }
+    } else {
+        for (unsigned t = threadIdx.x; t < C.n; t += blockDim.x) {
+            sc[t] = C.s[t];
+            phic[t] = 0.0;
+        }
+    }
+    __syncthreads();
+    tail_sweeps(C, phic, sc, coarse_iters, coarse_omega);
+    if (has_mid) {
+        MGLevel Cl = C;
+        Cl.phi = phic;  // interpolate from the LDS copy
+        for (unsigned t = threadIdx.x; t < M.n; t += blockDim.x) {
+            const int x = t % M.nx, r = t / M.nx, y = r % M.ny, z = r / M.ny;
+            phim[t] += mg_interp(Cl, x, y, z);
+        }
+        __syncthreads();
+        tail_sweeps(M, phim, sm, 2, 1.0);
+        for (unsigned t = threadIdx.x; t < M.n; t += blockDim.x) M.phi[t] = phim[t];
+    } else {
+        for (unsigned t = threadIdx.x; t < C.n; t += blockDim.x) C.phi[t] = phic[t];
     }
 }
 
-void launch_mg_coarse_solve(const MGLevel& L, int iters, double omega, hipStream_t st) {
-    hipLaunchKernelGGL(k_mg_coarse_solve, dim3(1), dim3(kBlock), 0, st, L, iters, omega);
+void launch_mg_tail(const MGLevel& mid, const MGLevel& coarse, int has_mid, int iters, double omega, hipStream_t st) {
+    const size_t lds = (2 * kTailCoarse + 2 * kTailMid) * sizeof(double);
+    hipLaunchKernelGGL(k_mg_tail, dim3(1), dim3(kTailThreads), lds, st, mid, coarse, has_mid, iters, omega);
 }
 
 // ------------------------------------------------------------------------------------

@@ -17,7 +17,7 @@ EK_FP64, EK_FP32 = 0, 1
 POISSON_SOLVERS = {"auto": 0, "sor": 1, "mg": 2}
 FIELDS = {"rho_a": 0, "rho_b": 1, "n_plus": 2, "n_minus": 3, "phi": 4, "ux": 5, "uy": 6, "uz": 7, "q": 8,
           "eps": 9, "psi_s": 10, "solid": 11, "Ex": 12, "Ey": 13, "Ez": 14}
-TIMING_CLASSES = ["moments", "poisson", "force", "fused", "particle", "sor"]
+TIMING_CLASSES = ["moments", "poisson", "force", "fused", "particle", "iter", "smooth"]
 
 
 class EKParams(ctypes.Structure):
@@ -51,7 +51,7 @@ class EKObs(ctypes.Structure):
 
 
 class EKTiming(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 6), ("count", ctypes.c_int64 * 6)]
+    _fields_ = [("ms", ctypes.c_double * 7), ("count", ctypes.c_int64 * 7)]
 
 
 EXPORTS = ["ek_lattice", "ek_init", "ek_step", "ek_poisson", "ek_observables", "ek_get_field",
