@@ -192,8 +192,10 @@ ek_status ek_get_particles(struct ek_ctx* ctx, double* host_out);
 /* Device bytes held by the context. */
 ek_status ek_device_bytes(const struct ek_ctx* ctx, size_t* bytes);
 
-/* Turn per-kernel-class HIP event timing on (1) or off (0); turning it on clears
-   the accumulated times. */
+/* Per-kernel HIP event timing: 0 off, 1 kernel classes (a few events per step),
+   2 classes plus every lattice-level red-black pass (EK_T_SMOOTH; adds events
+   between small kernels, so use it for per-launch figures, not for step rates).
+   Any call clears the accumulated times. */
 ek_status ek_set_timing(struct ek_ctx* ctx, int32_t enable);
 
 /* Accumulated times since timing was turned on (synchronises the stream). */

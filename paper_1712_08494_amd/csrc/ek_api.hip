@@ -81,8 +81,8 @@ struct ek_ctx {
     // multigrid (levels[0] is the lattice itself and holds no arrays)
     std::vector<MGLevel> mg;
     double mg_coarse_omega = 1.0;
-    // timing
-    bool timing = false;
+    // timing: 0 off, 1 kernel classes, 2 classes and every lattice-level smoothing pass
+    int timing = 0;
     std::vector<TimeRec> recs;
     std::vector<hipEvent_t> pool;
     double tms[EK_T_COUNT] = {0};
@@ -154,7 +154,8 @@ struct Timer {
     int cls, count;
     hipEvent_t a{};
     bool on;
-    Timer(ek_ctx* c_, int cls_, int count_ = 1) : c(c_), cls(cls_), count(count_), on(c_->timing) {
+    Timer(ek_ctx* c_, int cls_, int count_ = 1)
+        : c(c_), cls(cls_), count(count_), on(c_->timing >= (cls_ == EK_T_SMOOTH ? 2 : 1)) {
         if (on) {
             a = get_event(c);
             (void)hipEventRecord(a, c->st);
@@ -380,7 +381,7 @@ static void vcycle(ek_ctx* c, const Fields<T>& F) {
         else
             launch_mg_restrict(c->mg[g - 1], c->mg[g], c->st);
     }
-    launch_mg_tail(tail_mid ? c->mg[nl - 2] : c->mg[nl - 1], c->mg[nl - 1], tail_mid, 30, c->mg_coarse_omega, c->st);
+    launch_mg_tail(tail_mid ? c->mg[nl - 2] : c->mg[nl - 1], c->mg[nl - 1], tail_mid, 20, c->mg_coarse_omega, c->st);
     for (int g = last_gpu; g >= 0; --g) {  // upward leg: interpolate from grid g+1, smooth grid g
         if (g == 0)
             launch_mg_prolong_fine<T>(c->S, F, c->mg[0], c->st);
@@ -962,7 +963,7 @@ extern "C" ek_status ek_device_bytes(const ek_ctx* c, size_t* bytes) {
 extern "C" ek_status ek_set_timing(ek_ctx* c, int32_t enable) {
     if (!c) return EK_EINVAL;
     resolve_timing(c);
-    c->timing = enable != 0;
+    c->timing = enable < 0 ? 0 : (enable > 2 ? 2 : enable);
     for (int k = 0; k < EK_T_COUNT; ++k) {
         c->tms[k] = 0.0;
         c->tcnt[k] = 0;

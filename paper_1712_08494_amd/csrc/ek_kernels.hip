@@ -691,32 +691,57 @@ void launch_mg_prolong(const MGLevel& c, const MGLevel& f, hipStream_t st) {
 // The last two levels in one workgroup: on the smaller of them ("mid", at most
 // kTailMid cells) two red-black Gauss-Seidel sweeps, restriction to the coarsest level
 // (at most kTailCoarse cells), red-black SOR sweeps there, interpolation back and two
-// more sweeps.  Potentials and right-hand sides live in LDS; face coefficients are read
-// from global memory (they stay in L2).  When has_mid is 0 only the coarsest solve runs.
-constexpr int kTailThreads = 512;
+// more sweeps.  Potentials, right-hand sides and face coefficients all live in LDS (the
+// mid grid's coefficients as float: this grid only carries a coarse-grid correction,
+// the lattice-level residual stays FP64).  When has_mid is 0 only the coarsest solve
+// runs, and the coarsest grid may use the whole allocation.
+constexpr int kTailThreads = 1024;
 constexpr unsigned kTailMid = 4096, kTailCoarse = 512;
+constexpr unsigned kTailCoarseOnly = kTailMid + kTailCoarse;
 
-struct LdsLevel {
-    const MGLevel* L;
+template <typename C>
+struct TailGrid {
+    int nx, ny, nz;
+    unsigned n;
     double* phi;
-    const double* s;
+    const double* rhs;
+    const C* ax;
+    const C* ay;
+    const C* az;
+    C* idiag;  // 1 / diagonal (0 for a decoupled cell)
 };
 
-__device__ __forceinline__ void tail_row(const MGLevel& L, const double* phi, int x, int y, int z, double& diag,
-                                         double& off) {
+template <typename C>
+__device__ __forceinline__ unsigned tid3(const TailGrid<C>& L, int x, int y, int z) {
+    return (unsigned)x + (unsigned)L.nx * ((unsigned)y + (unsigned)L.ny * (unsigned)z);
+}
+
+template <typename C>
+__device__ __forceinline__ void tail_row(const TailGrid<C>& L, int x, int y, int z, double& diag, double& off) {
     const int xm = wrapc(x - 1, L.nx), xp = wrapc(x + 1, L.nx);
     const int ym = wrapc(y - 1, L.ny), yp = wrapc(y + 1, L.ny);
     const int zm = wrapc(z - 1, L.nz), zp = wrapc(z + 1, L.nz);
-    const unsigned i = lid(L, x, y, z);
-    const double a0 = L.ax[i], a1 = L.ax[lid(L, xm, y, z)];
-    const double b0 = L.ay[i], b1 = L.ay[lid(L, x, ym, z)];
-    const double c0 = L.az[i], c1 = L.az[lid(L, x, y, zm)];
+    const unsigned i = tid3(L, x, y, z);
+    const double a0 = L.ax[i], a1 = L.ax[tid3(L, xm, y, z)];
+    const double b0 = L.ay[i], b1 = L.ay[tid3(L, x, ym, z)];
+    const double c0 = L.az[i], c1 = L.az[tid3(L, x, y, zm)];
     diag = a0 + a1 + b0 + b1 + c0 + c1;
-    off = a0 * phi[lid(L, xp, y, z)] + a1 * phi[lid(L, xm, y, z)] + b0 * phi[lid(L, x, yp, z)] +
-          b1 * phi[lid(L, x, ym, z)] + c0 * phi[lid(L, x, y, zp)] + c1 * phi[lid(L, x, y, zm)];
+    off = a0 * L.phi[tid3(L, xp, y, z)] + a1 * L.phi[tid3(L, xm, y, z)] + b0 * L.phi[tid3(L, x, yp, z)] +
+          b1 * L.phi[tid3(L, x, ym, z)] + c0 * L.phi[tid3(L, x, y, zp)] + c1 * L.phi[tid3(L, x, y, zm)];
 }
 
-__device__ void tail_sweeps(const MGLevel& L, double* phi, const double* rhs, int sweeps, double omega) {
+template <typename C>
+__device__ void tail_inverse_diagonal(const TailGrid<C>& L) {
+    for (unsigned t = threadIdx.x; t < L.n; t += blockDim.x) {
+        const int x = t % L.nx, r = t / L.nx, y = r % L.ny, z = r / L.ny;
+        double diag, off;
+        tail_row(L, x, y, z, diag, off);
+        L.idiag[t] = diag > 0.0 ? (C)(1.0 / diag) : (C)0;
+    }
+}
+
+template <typename C>
+__device__ void tail_sweeps(const TailGrid<C>& L, int sweeps, double omega) {
     const unsigned half = L.n / 2, hx = (unsigned)(L.nx >> 1);
     for (int it = 0; it < sweeps; ++it)
         for (int color = 0; color < 2; ++color) {
@@ -725,74 +750,121 @@ __device__ void tail_sweeps(const MGLevel& L, double* phi, const double* rhs, in
                 const int y = row % L.ny, z = row / L.ny;
                 const int x = 2 * m + ((color + y + z) & 1);
                 double diag, off;
-                tail_row(L, phi, x, y, z, diag, off);
-                if (diag > 0.0) {
-                    const unsigned i = lid(L, x, y, z);
-                    phi[i] = phi[i] + omega * ((off + rhs[i]) / diag - phi[i]);
-                }
+                tail_row(L, x, y, z, diag, off);
+                const unsigned i = tid3(L, x, y, z);
+                L.phi[i] = L.phi[i] + omega * ((off + L.rhs[i]) * (double)L.idiag[i] - L.phi[i]);
             }
             __syncthreads();
         }
 }
 
-__global__ __launch_bounds__(kTailThreads) void k_mg_tail(MGLevel M, MGLevel C, int has_mid, int coarse_iters,
+template <typename C>
+__device__ void tail_load_coeffs(const MGLevel& G, C* ax, C* ay, C* az) {
+    for (unsigned t = threadIdx.x; t < G.n; t += blockDim.x) {
+        ax[t] = (C)G.ax[t];
+        ay[t] = (C)G.ay[t];
+        az[t] = (C)G.az[t];
+    }
+}
+
+__global__ __launch_bounds__(kTailThreads) void k_mg_tail(MGLevel M, MGLevel Cg, int has_mid, int coarse_iters,
                                                          double coarse_omega) {
     extern __shared__ double lds[];
-    // with a mid grid: [phi_c | s_c] in 2 x kTailCoarse, then [phi_m | s_m] in 2 x kTailMid;
-    // coarsest only: [phi_c | s_c] may use the whole allocation (C.n <= kTailCoarse + kTailMid)
-    double* phic = lds;
-    double* sc = lds + (has_mid ? kTailCoarse : C.n);
-    double* phim = lds + 2 * kTailCoarse;
-    double* sm = phim + kTailMid;
     if (has_mid) {
+        double* phim = lds;
+        double* sm = phim + kTailMid;
+        double* phic = sm + kTailMid;
+        double* sc = phic + kTailCoarse;
+        double* cax = sc + kTailCoarse;
+        double* cay = cax + kTailCoarse;
+        double* caz = cay + kTailCoarse;
+        double* cid = caz + kTailCoarse;
+        float* max_ = (float*)(cid + kTailCoarse);
+        float* may = max_ + kTailMid;
+        float* maz = may + kTailMid;
+        float* mid_ = maz + kTailMid;
+        tail_load_coeffs(M, max_, may, maz);
+        tail_load_coeffs(Cg, cax, cay, caz);
         for (unsigned t = threadIdx.x; t < M.n; t += blockDim.x) {
             phim[t] = 0.0;
             sm[t] = M.s[t];
         }
         __syncthreads();
-        tail_sweeps(M, phim, sm, 2, 1.0);
+        const TailGrid<float> Lm{M.nx, M.ny, M.nz, M.n, phim, sm, max_, may, maz, mid_};
+        const TailGrid<double> Lc{Cg.nx, Cg.ny, Cg.nz, Cg.n, phic, sc, cax, cay, caz, cid};
+        tail_inverse_diagonal(Lm);
+        tail_inverse_diagonal(Lc);
+        __syncthreads();
+        tail_sweeps(Lm, 2, 1.0);
         // restriction: sum of the eight children's residuals
-        for (unsigned t = threadIdx.x; t < C.n; t += blockDim.x) {
-            const int I = t % C.nx, r = t / C.nx, J = r % C.ny, K = r / C.ny;
+        for (unsigned t = threadIdx.x; t < Cg.n; t += blockDim.x) {
+            const int I = t % Cg.nx, r = t / Cg.nx, J = r % Cg.ny, K = r / Cg.ny;
             double sum = 0.0;
             for (int c = 0; c < 2; ++c)
                 for (int b = 0; b < 2; ++b)
                     for (int a = 0; a < 2; ++a) {
                         const int x = 2 * I + a, y = 2 * J + b, z = 2 * K + c;
                         double diag, off;
-                        tail_row(M, phim, x, y, z, diag, off);
-                        const unsigned i = lid(M, x, y, z);
+                        tail_row(Lm, x, y, z, diag, off);
+                        const unsigned i = tid3(Lm, x, y, z);
                         sum += sm[i] + off - diag * phim[i];
                     }
             sc[t] = sum;
             phic[t] = 0.0;
         }
-    } else {
-        for (unsigned t = threadIdx.x; t < C.n; t += blockDim.x) {
-            sc[t] = C.s[t];
-            phic[t] = 0.0;
-        }
-    }
-    __syncthreads();
-    tail_sweeps(C, phic, sc, coarse_iters, coarse_omega);
-    if (has_mid) {
-        MGLevel Cl = C;
-        Cl.phi = phic;  // interpolate from the LDS copy
+        __syncthreads();
+        tail_sweeps(Lc, coarse_iters, coarse_omega);
+        // trilinear interpolation of the coarse correction (parent only across a zero face)
         for (unsigned t = threadIdx.x; t < M.n; t += blockDim.x) {
             const int x = t % M.nx, r = t / M.nx, y = r % M.ny, z = r / M.ny;
-            phim[t] += mg_interp(Cl, x, y, z);
+            const int I = x >> 1, J = y >> 1, K = z >> 1;
+            const int dx = (x & 1) ? 1 : -1, dy = (y & 1) ? 1 : -1, dz = (z & 1) ? 1 : -1;
+            const int In = wrapc(I + dx, Cg.nx), Jn = wrapc(J + dy, Cg.ny), Kn = wrapc(K + dz, Cg.nz);
+            const double fx = cax[tid3(Lc, dx > 0 ? I : In, J, K)];
+            const double fy = cay[tid3(Lc, I, dy > 0 ? J : Jn, K)];
+            const double fz = caz[tid3(Lc, I, J, dz > 0 ? K : Kn)];
+            const double wx = fx > 0.0 ? 0.25 : 0.0, wy = fy > 0.0 ? 0.25 : 0.0, wz = fz > 0.0 ? 0.25 : 0.0;
+            const int xs[2] = {I, In}, ys[2] = {J, Jn}, zs[2] = {K, Kn};
+            const double wxs[2] = {1.0 - wx, wx}, wys[2] = {1.0 - wy, wy}, wzs[2] = {1.0 - wz, wz};
+            double v = 0.0;
+            for (int c = 0; c < 2; ++c)
+                for (int b = 0; b < 2; ++b)
+                    for (int a = 0; a < 2; ++a) v += wxs[a] * wys[b] * wzs[c] * phic[tid3(Lc, xs[a], ys[b], zs[c])];
+            phim[t] += v;
         }
         __syncthreads();
-        tail_sweeps(M, phim, sm, 2, 1.0);
+        tail_sweeps(Lm, 2, 1.0);
         for (unsigned t = threadIdx.x; t < M.n; t += blockDim.x) M.phi[t] = phim[t];
     } else {
-        for (unsigned t = threadIdx.x; t < C.n; t += blockDim.x) C.phi[t] = phic[t];
+        double* phic = lds;
+        double* sc = phic + kTailCoarseOnly;
+        float* cax = (float*)(sc + kTailCoarseOnly);
+        float* cay = cax + kTailCoarseOnly;
+        float* caz = cay + kTailCoarseOnly;
+        float* cid = caz + kTailCoarseOnly;
+        tail_load_coeffs(Cg, cax, cay, caz);
+        for (unsigned t = threadIdx.x; t < Cg.n; t += blockDim.x) {
+            sc[t] = Cg.s[t];
+            phic[t] = 0.0;
+        }
+        __syncthreads();
+        const TailGrid<float> Lc{Cg.nx, Cg.ny, Cg.nz, Cg.n, phic, sc, cax, cay, caz, cid};
+        tail_inverse_diagonal(Lc);
+        __syncthreads();
+        tail_sweeps(Lc, coarse_iters, coarse_omega);
+        for (unsigned t = threadIdx.x; t < Cg.n; t += blockDim.x) Cg.phi[t] = phic[t];
     }
 }
 
+size_t mg_tail_lds_bytes() {
+    const size_t with_mid = 2 * kTailMid * 8 + 6 * kTailCoarse * 8 + 4 * kTailMid * 4;
+    const size_t coarse_only = 2 * kTailCoarseOnly * 8 + 4 * kTailCoarseOnly * 4;
+    return with_mid > coarse_only ? with_mid : coarse_only;
+}
+
 void launch_mg_tail(const MGLevel& mid, const MGLevel& coarse, int has_mid, int iters, double omega, hipStream_t st) {
-    const size_t lds = (2 * kTailCoarse + 2 * kTailMid) * sizeof(double);
-    hipLaunchKernelGGL(k_mg_tail, dim3(1), dim3(kTailThreads), lds, st, mid, coarse, has_mid, iters, omega);
+    hipLaunchKernelGGL(k_mg_tail, dim3(1), dim3(kTailThreads), mg_tail_lds_bytes(), st, mid, coarse, has_mid, iters,
+                       omega);
 }
 
 // ------------------------------------------------------------------------------------

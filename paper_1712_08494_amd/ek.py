@@ -264,7 +264,7 @@ class EKSim:
         return b.value
 
     def set_timing(self, on):
-        self._check(load().ek_set_timing(self._h, int(bool(on))), "ek_set_timing")
+        self._check(load().ek_set_timing(self._h, int(on)), "ek_set_timing")
 
     def timing(self):
         t = EKTiming()
