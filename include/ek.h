@@ -153,7 +153,8 @@ int32_t ek_lattice(int32_t* c, double* w);
    parts: host array of n_parts particles (may be NULL when n_parts == 0).
    stream: a hipStream_t (NULL for the null stream).
    Errors: EK_EINVAL (bad sizes, tau <= 1/2, odd nx, non-positive fluid density,
-   overlapping particles), EK_ENOMEM, EK_EHIP, EK_ENOCONV (initial solve). */
+   overlapping particles), EK_ENOMEM, EK_EHIP, EK_ENOCONV (initial solve).  On failure
+   *out still holds a context for ek_last_error; release it with ek_destroy. */
 ek_status ek_init(const ek_params* p, const double* rho_a, const double* rho_b, const double* n_plus,
                   const double* n_minus, const ek_particle* parts, int32_t n_parts, void* stream,
                   struct ek_ctx** out);
@@ -206,6 +207,50 @@ ek_status ek_destroy(struct ek_ctx* ctx);
 
 const char* ek_status_str(ek_status s);
 const char* ek_last_error(const struct ek_ctx* ctx);
+
+/* ---------------------------------------------------------------------------------
+ * Batched replicas: many independent lattices (a parameter sweep) advanced together,
+ * one graph launch per step for all of them.  Every replica is a full context of the
+ * method above (Sec. II), periodic, without particles, with a lattice the multigrid
+ * can coarsen (every axis divisible by 4); all share one precision.  Each stage of a
+ * step (moments, Poisson V-cycles per grid level, force pass, fused sweep) is a single
+ * launch over the work of all replicas; the whole step is captured once into a HIP
+ * graph (one per buffer parity), so a step is one host call and no host
+ * synchronisation.  Each step runs exactly `cycles` multigrid V-cycles from the
+ * extrapolated potential; the relative residual each replica reaches is recorded on
+ * the device (ek_batch_residuals) instead of steering the step.
+ * The batch owns a HIP stream of its own (default priority); calls that return data
+ * synchronise it.
+ * --------------------------------------------------------------------------------- */
+struct ek_batch;
+
+/* params, rho_a, rho_b, n_plus, n_minus: arrays of n_rep entries (host, borrowed for the
+   call; field arrays as in ek_init).  cycles: V-cycles per step (1..64).
+   Errors: EK_EINVAL (walls, mixed precision, lattice not coarsenable, bad cycles), or
+   any ek_init error of a replica (message names the replica).  On failure *out still
+   holds a batch for ek_batch_last_error; release it with ek_batch_destroy. */
+ek_status ek_batch_init(const ek_params* params, int32_t n_rep, const double* const* rho_a,
+                        const double* const* rho_b, const double* const* n_plus, const double* const* n_minus,
+                        int32_t cycles, struct ek_batch** out);
+
+/* Enqueue nsteps steps of every replica (one graph launch each); returns without waiting. */
+ek_status ek_batch_step(struct ek_batch* b, int32_t nsteps);
+
+/* Wait for the batch's stream. */
+ek_status ek_batch_sync(struct ek_batch* b);
+
+/* Relative Poisson residual of every replica after the last step (last) and the largest
+   over all steps so far (worst); either may be NULL.  Synchronises. */
+ek_status ek_batch_residuals(struct ek_batch* b, double* last, double* worst);
+
+/* Borrow replica r's context for the export calls (ek_get_field, ek_get_populations,
+   ek_observables).  It stays owned by the batch: ek_step, ek_poisson and ek_destroy
+   return EK_ESTATE on it. */
+ek_status ek_batch_replica(struct ek_batch* b, int32_t r, struct ek_ctx** ctx);
+
+/* Release the batch, its replicas and its stream. */
+ek_status ek_batch_destroy(struct ek_batch* b);
+const char* ek_batch_last_error(const struct ek_batch* b);
 
 #ifdef __cplusplus
 }

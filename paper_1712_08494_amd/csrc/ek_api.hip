@@ -72,6 +72,7 @@ struct ek_ctx {
     double* hscal = nullptr;  // pinned
     int* obs_max = nullptr;
     double* stage = nullptr;
+    double* stage2 = nullptr;
     // bookkeeping
     long long steps = 0, ptotal = 0;
     int last_iters = 0;
@@ -87,6 +88,7 @@ struct ek_ctx {
     std::vector<hipEvent_t> pool;
     double tms[EK_T_COUNT] = {0};
     long long tcnt[EK_T_COUNT] = {0};
+    bool in_batch = false;  // owned by a batch: stepping goes through the batch
 };
 
 #define EK_HIP(call)                                                                             \
@@ -694,12 +696,14 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
         launch_init_pop_flags<T>(c->S, (T*)c->f[c->cur][s], c->stage, c->S.rref[s], c->flags, c->st);
         EK_HIP(hipStreamSynchronize(c->st));
     }
-    const double* nn[2] = {n_plus, n_minus};
-    for (int s = 0; s < 2; ++s) {
-        EK_HIP(hipMemcpyAsync(c->stage, nn[s], (size_t)N * 8, hipMemcpyHostToDevice, c->st));
-        launch_init_ions<T>(c->S, F, (T*)c->n[c->cur][s], c->stage, c->st);
-        EK_HIP(hipStreamSynchronize(c->st));
-    }
+    // ions: stored as mean density and ionic charge (staging holds n+ then n-)
+    double* stage2 = nullptr;
+    EK_TRY(dalloc(c, (void**)&stage2, (size_t)N * 8));
+    EK_HIP(hipMemcpyAsync(c->stage, n_plus, (size_t)N * 8, hipMemcpyHostToDevice, c->st));
+    EK_HIP(hipMemcpyAsync(stage2, n_minus, (size_t)N * 8, hipMemcpyHostToDevice, c->st));
+    launch_init_ions<T>(c->S, F, (T*)c->n[c->cur][0], (T*)c->n[c->cur][1], c->stage, stage2, c->st);
+    EK_HIP(hipStreamSynchronize(c->st));
+    c->stage2 = stage2;
     EK_HIP(hipGetLastError());
     // initial potential
     moments_pass<T>(c);
@@ -801,6 +805,7 @@ extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const doub
 
 extern "C" ek_status ek_step(ek_ctx* c, int32_t nsteps) {
     if (!c || !c->phi) return EK_ESTATE;
+    if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: step it with ek_batch_step");
     if (nsteps < 0) return fail(c, EK_EINVAL, "nsteps must be >= 0");
     return c->esz == 4 ? step_impl<float>(c, nsteps) : step_impl<double>(c, nsteps);
 }
@@ -813,6 +818,7 @@ static ek_status poisson_entry(ek_ctx* c, double tol, int maxit, int* iters, dou
 
 extern "C" ek_status ek_poisson(ek_ctx* c, double tol, int32_t maxit, int32_t* iters, double* rel_res) {
     if (!c || !c->phi) return EK_ESTATE;
+    if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: its potential is solved by ek_batch_step");
     if (!(tol > 0.0) || maxit < 0) return fail(c, EK_EINVAL, "tol must be > 0 and maxit >= 0");
     int it = 0;
     double rel = 0.0;
@@ -886,7 +892,8 @@ static ek_status field_impl(ek_ctx* c, int which, double* host) {
         return EK_OK;
     }
     if (which == EK_F_N_PLUS || which == EK_F_N_MINUS) {
-        launch_to_double<T>((const T*)c->n[c->cur][which - EK_F_N_PLUS], c->stage, N, 0.0, c->st);
+        launch_ion_species<T>((const T*)c->n[c->cur][0], (const T*)c->n[c->cur][1], c->stage, N,
+                              which == EK_F_N_PLUS ? 1.0 : -1.0, c->st);
     } else if (which >= EK_F_EX && which <= EK_F_EZ) {
         launch_field_e<T>(c->S, F, which - EK_F_EX, c->stage, c->st);
     } else {
@@ -983,6 +990,7 @@ extern "C" ek_status ek_get_timing(ek_ctx* c, ek_timing* out) {
 
 extern "C" ek_status ek_destroy(ek_ctx* c) {
     if (!c) return EK_OK;
+    if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: released by ek_batch_destroy");
     if (c->phi) (void)hipStreamSynchronize(c->st);
     resolve_timing(c);
     for (auto e : c->pool) (void)hipEventDestroy(e);
@@ -1006,3 +1014,281 @@ extern "C" const char* ek_status_str(ek_status s) {
 }
 
 extern "C" const char* ek_last_error(const ek_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+// ------------------------------------------------------------------------------------
+// Batched replicas
+// ------------------------------------------------------------------------------------
+struct BatchTable {
+    BlockRef* d = nullptr;
+    unsigned n = 0;
+};
+
+struct ek_batch {
+    std::vector<ek_ctx*> reps;
+    hipStream_t st = nullptr;
+    std::string err;
+    size_t esz = 4;
+    int cycles = 4;
+    int max_grid = 0;  // largest grid index over replicas
+    int max_gpu = 0;   // largest grid handled by full-GPU launches
+    void* desc[2] = {nullptr, nullptr};
+    BatchTable site, color;
+    std::vector<BatchTable> cells, cells_gpu, colors_gpu, into;  // indexed by grid
+    std::vector<void*> allocs;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    int parity = 0;
+    long long steps = 0;
+    double* hres = nullptr;
+};
+
+#define EB_HIP(call)                                                                 \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            b->err = std::string(#call) + ": " + hipGetErrorString(e_);              \
+            return EK_EHIP;                                                          \
+        }                                                                            \
+    } while (0)
+
+static ek_status batch_table(ek_batch* b, const std::vector<BlockRef>& h, BatchTable& t) {
+    t.n = (unsigned)h.size();
+    if (h.empty()) return EK_OK;
+    EB_HIP(hipMalloc((void**)&t.d, h.size() * sizeof(BlockRef)));
+    b->allocs.push_back(t.d);
+    EB_HIP(hipMemcpy(t.d, h.data(), h.size() * sizeof(BlockRef), hipMemcpyHostToDevice));
+    return EK_OK;
+}
+
+static int last_gpu_grid(const ek_ctx* c) {
+    const int nl = (int)c->mg.size();
+    const int tail_mid = (nl >= 2 && c->mg[nl - 2].n <= 4096 && c->mg[nl - 1].n <= 512) ? 1 : 0;
+    return nl - 1 - tail_mid;
+}
+
+template <typename T>
+static RepDesc<T> make_desc(ek_ctx* c, int parity) {
+    const int saved = c->cur;
+    c->cur = parity;
+    RepDesc<T> d{};
+    d.S = c->S;
+    d.F = fields<T>(c);
+    c->cur = saved;
+    d.phi_prev = c->phi_prev;
+    const int nl = (int)c->mg.size();
+    d.nl = nl;
+    for (int l = 0; l < nl; ++l) d.mg[l] = c->mg[l];
+    d.tail_mid = (nl >= 2 && c->mg[nl - 2].n <= 4096 && c->mg[nl - 1].n <= 512) ? 1 : 0;
+    d.coarse_iters = 20;
+    d.coarse_omega = c->mg_coarse_omega;
+    return d;
+}
+
+// One step of every replica, as launched (and captured) on the batch stream.
+template <typename T>
+static void batch_step_launches(ek_batch* b, int parity) {
+    const RepDesc<T>* D = (const RepDesc<T>*)b->desc[parity];
+    const int nr = (int)b->reps.size();
+    hipStream_t st = b->st;
+    launch_batch<T>(kB_MOMENTS, D, b->site.d, b->site.n, 0, 0, st);
+    launch_batch_source_mean<T>(D, nr, st);
+    launch_batch<T>(kB_EXTRAPOLATE, D, b->site.d, b->site.n, 0, 0, st);
+    launch_batch<T>(kB_COARSEN_FINE, D, b->cells[1].d, b->cells[1].n, 1, 0, st);
+    for (int g = 2; g <= b->max_grid; ++g) launch_batch<T>(kB_COARSEN, D, b->cells[g].d, b->cells[g].n, g, 0, st);
+    for (int cyc = 0; cyc < b->cycles; ++cyc) {
+        for (int g = 0; g <= b->max_gpu; ++g) {
+            for (int sweep = 0; sweep < 2; ++sweep)
+                for (int color = 0; color < 2; ++color) {
+                    if (g == 0)
+                        launch_batch<T>(kB_SOR, D, b->color.d, b->color.n, 0, color, st);
+                    else
+                        launch_batch<T>(kB_SMOOTH, D, b->colors_gpu[g].d, b->colors_gpu[g].n, g, color, st);
+                }
+            if (g == 0)
+                launch_batch<T>(kB_RESTRICT_FINE, D, b->into[1].d, b->into[1].n, 1, 0, st);
+            else
+                launch_batch<T>(kB_RESTRICT, D, b->into[g + 1].d, b->into[g + 1].n, g, 0, st);
+        }
+        launch_batch_tail<T>(D, nr, st);
+        for (int g = b->max_gpu; g >= 0; --g) {
+            if (g == 0)
+                launch_batch<T>(kB_PROLONG_FINE, D, b->site.d, b->site.n, 0, 0, st);
+            else
+                launch_batch<T>(kB_PROLONG, D, b->cells_gpu[g].d, b->cells_gpu[g].n, g, 0, st);
+            for (int sweep = 0; sweep < 2; ++sweep)
+                for (int color = 0; color < 2; ++color) {
+                    if (g == 0)
+                        launch_batch<T>(kB_SOR, D, b->color.d, b->color.n, 0, color, st);
+                    else
+                        launch_batch<T>(kB_SMOOTH, D, b->colors_gpu[g].d, b->colors_gpu[g].n, g, color, st);
+                }
+        }
+    }
+    launch_batch<T>(kB_RESIDUAL, D, b->site.d, b->site.n, 0, 0, st);
+    launch_batch_reduce<T>(D, nr, st);
+    launch_batch<T>(kB_FINALIZE, D, b->site.d, b->site.n, 0, 0, st);
+    launch_batch<T>(kB_FORCE, D, b->site.d, b->site.n, 0, 0, st);
+    launch_batch<T>(kB_FUSED, D, b->site.d, b->site.n, 0, 0, st);
+}
+
+template <typename T>
+static ek_status batch_setup(ek_batch* b) {
+    const int nr = (int)b->reps.size();
+    // descriptors for the two buffer parities
+    for (int par = 0; par < 2; ++par) {
+        std::vector<RepDesc<T>> h(nr);
+        for (int r = 0; r < nr; ++r) h[r] = make_desc<T>(b->reps[r], par);
+        EB_HIP(hipMalloc(&b->desc[par], nr * sizeof(RepDesc<T>)));
+        b->allocs.push_back(b->desc[par]);
+        EB_HIP(hipMemcpy(b->desc[par], h.data(), nr * sizeof(RepDesc<T>), hipMemcpyHostToDevice));
+    }
+    // block tables
+    auto blocks = [](unsigned n) { return (n + kBlock - 1) / kBlock; };
+    std::vector<BlockRef> site, color;
+    b->max_grid = 0;
+    b->max_gpu = 0;
+    for (int r = 0; r < nr; ++r) {
+        const ek_ctx* c = b->reps[r];
+        for (unsigned k = 0; k < blocks(c->N); ++k) site.push_back({r, (int)k});
+        for (unsigned k = 0; k < blocks(c->N / 2); ++k) color.push_back({r, (int)k});
+        b->max_grid = std::max(b->max_grid, (int)c->mg.size());
+        b->max_gpu = std::max(b->max_gpu, last_gpu_grid(c));
+    }
+    EK_TRY(batch_table(b, site, b->site));
+    EK_TRY(batch_table(b, color, b->color));
+    const int G = b->max_grid + 1;
+    b->cells.assign(G, BatchTable{});
+    b->cells_gpu.assign(G, BatchTable{});
+    b->colors_gpu.assign(G, BatchTable{});
+    b->into.assign(G + 1, BatchTable{});
+    for (int g = 1; g < G; ++g) {
+        std::vector<BlockRef> cl, cg, cc, in;
+        for (int r = 0; r < nr; ++r) {
+            const ek_ctx* c = b->reps[r];
+            if ((int)c->mg.size() < g) continue;
+            const unsigned n = c->mg[g - 1].n;
+            const int lg = last_gpu_grid(c);
+            for (unsigned k = 0; k < blocks(n); ++k) cl.push_back({r, (int)k});
+            if (g <= lg) {
+                for (unsigned k = 0; k < blocks(n); ++k) cg.push_back({r, (int)k});
+                for (unsigned k = 0; k < blocks(n / 2); ++k) cc.push_back({r, (int)k});
+            }
+            if (g - 1 <= lg)
+                for (unsigned k = 0; k < blocks(n); ++k) in.push_back({r, (int)k});
+        }
+        EK_TRY(batch_table(b, cl, b->cells[g]));
+        EK_TRY(batch_table(b, cg, b->cells_gpu[g]));
+        EK_TRY(batch_table(b, cc, b->colors_gpu[g]));
+        EK_TRY(batch_table(b, in, b->into[g]));
+    }
+    // capture one step per parity into a graph
+    for (int par = 0; par < 2; ++par) {
+        EB_HIP(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+        batch_step_launches<T>(b, par);
+        EB_HIP(hipStreamEndCapture(b->st, &b->graph[par]));
+        EB_HIP(hipGraphInstantiate(&b->exec[par], b->graph[par], nullptr, nullptr, 0));
+    }
+    return EK_OK;
+}
+
+extern "C" ek_status ek_batch_init(const ek_params* params, int32_t n_rep, const double* const* rho_a,
+                                   const double* const* rho_b, const double* const* n_plus,
+                                   const double* const* n_minus, int32_t cycles, ek_batch** out) {
+    if (!out) return EK_EINVAL;
+    ek_batch* b = new ek_batch();
+    *out = b;
+    if (!params || n_rep <= 0 || !rho_a || !rho_b || !n_plus || !n_minus) {
+        b->err = "bad arguments";
+        return EK_EINVAL;
+    }
+    if (cycles < 1 || cycles > 64) {
+        b->err = "cycles must be in [1, 64]";
+        return EK_EINVAL;
+    }
+    b->cycles = cycles;
+    EB_HIP(hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking));
+    EB_HIP(hipHostMalloc((void**)&b->hres, 2 * 8 * (size_t)n_rep, hipHostMallocDefault));
+    for (int r = 0; r < n_rep; ++r) {
+        const ek_params& p = params[r];
+        if (p.walls_z || p.precision != params[0].precision) {
+            b->err = "batched replicas are periodic and share one precision";
+            return EK_EINVAL;
+        }
+        ek_ctx* c = nullptr;
+        ek_status s = ek_init(&p, rho_a[r], rho_b[r], n_plus[r], n_minus[r], nullptr, 0, b->st, &c);
+        if (s != EK_OK) {
+            b->err = "replica " + std::to_string(r) + ": " + (c ? c->err : std::string("init failed"));
+            if (c) ek_destroy(c);
+            return s;
+        }
+        b->reps.push_back(c);
+        if (c->mg.empty() || (int)c->mg.size() > kMaxLevels) {
+            b->err = "replica " + std::to_string(r) + ": lattice cannot be coarsened for multigrid";
+            return EK_EINVAL;
+        }
+        c->in_batch = true;
+    }
+    b->esz = b->reps[0]->esz;
+    EB_HIP(hipStreamSynchronize(b->st));
+    return b->esz == 4 ? batch_setup<float>(b) : batch_setup<double>(b);
+}
+
+extern "C" ek_status ek_batch_step(ek_batch* b, int32_t nsteps) {
+    if (!b || !b->exec[0]) return EK_ESTATE;
+    for (int s = 0; s < nsteps; ++s) {
+        EB_HIP(hipGraphLaunch(b->exec[b->parity], b->st));
+        b->parity ^= 1;
+        b->steps++;
+    }
+    for (ek_ctx* c : b->reps) {
+        c->cur = b->parity;
+        c->steps = b->steps;
+    }
+    return EK_OK;
+}
+
+extern "C" ek_status ek_batch_sync(ek_batch* b) {
+    if (!b) return EK_EINVAL;
+    EB_HIP(hipStreamSynchronize(b->st));
+    return EK_OK;
+}
+
+extern "C" ek_status ek_batch_residuals(ek_batch* b, double* last, double* worst) {
+    if (!b || b->reps.empty()) return EK_ESTATE;
+    const int nr = (int)b->reps.size();
+    for (int r = 0; r < nr; ++r) {
+        EB_HIP(hipMemcpyAsync(b->hres + 2 * r, b->reps[r]->scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, b->st));
+    }
+    EB_HIP(hipStreamSynchronize(b->st));
+    for (int r = 0; r < nr; ++r) {
+        if (last) last[r] = b->hres[2 * r];
+        if (worst) worst[r] = b->hres[2 * r + 1];
+    }
+    return EK_OK;
+}
+
+extern "C" ek_status ek_batch_replica(ek_batch* b, int32_t r, ek_ctx** ctx) {
+    if (!b || !ctx || r < 0 || r >= (int)b->reps.size()) return EK_EINVAL;
+    *ctx = b->reps[r];
+    return EK_OK;
+}
+
+extern "C" ek_status ek_batch_destroy(ek_batch* b) {
+    if (!b) return EK_OK;
+    if (b->st) (void)hipStreamSynchronize(b->st);
+    for (int par = 0; par < 2; ++par) {
+        if (b->exec[par]) (void)hipGraphExecDestroy(b->exec[par]);
+        if (b->graph[par]) (void)hipGraphDestroy(b->graph[par]);
+    }
+    for (ek_ctx* c : b->reps) {
+        c->in_batch = false;
+        ek_destroy(c);
+    }
+    for (void* a : b->allocs) (void)hipFree(a);
+    if (b->hres) (void)hipHostFree(b->hres);
+    if (b->st) (void)hipStreamDestroy(b->st);
+    delete b;
+    return EK_OK;
+}
+
+extern "C" const char* ek_batch_last_error(const ek_batch* b) { return b ? b->err.c_str() : "null batch"; }

@@ -37,8 +37,8 @@ template <typename T>
 struct Fields {
     const T* f[2];      // populations of a, b at time t (19 N each, velocity-major)
     T* fn[2];           // populations at t+1
-    const T* n[2];      // n+, n- at time t
-    T* nn[2];           // n+, n- at t+1
+    const T* n[2];      // ions at time t: [0] mean density (n+ + n-)/2, [1] ionic charge n+ - n-
+    T* nn[2];           // the same at t+1
     T* mom;             // 8 N: rho_a - rho_ref_a, rho_b - rho_ref_b, psi_a, psi_b, chi_a, ux, uy, uz
     T* uph;             // 3 N: physical velocity
     T* q;               // charge density
@@ -72,6 +72,40 @@ struct MGLevel {
 
 unsigned site_blocks(unsigned n);
 
+// Batched replicas: per-replica descriptors in device memory and block tables mapping
+// each workgroup of a batched launch to (replica, workgroup within the replica).
+constexpr int kMaxLevels = 8;
+
+template <typename T>
+struct RepDesc {
+    Scalars S;
+    Fields<T> F;
+    double* phi_prev;
+    MGLevel mg[kMaxLevels];  // grid g >= 1 is mg[g - 1]
+    int nl;                  // number of coarse grids
+    int tail_mid;            // the tail kernel also handles grid nl - 1 (mg[nl - 2])
+    int coarse_iters;
+    double coarse_omega;
+};
+
+struct BlockRef {
+    int rep;
+    int blk;
+};
+
+enum BatchOp {
+    kB_MOMENTS, kB_EXTRAPOLATE, kB_RESIDUAL, kB_FINALIZE, kB_FORCE, kB_FUSED, kB_PROLONG_FINE,  // site tables
+    kB_SOR,                                                                                    // colour table
+    kB_COARSEN_FINE, kB_COARSEN, kB_RESTRICT_FINE, kB_RESTRICT, kB_SMOOTH, kB_PROLONG            // level tables
+};
+
+template <typename T>
+void launch_batch(BatchOp op, const RepDesc<T>* D, const BlockRef* tab, unsigned nblocks, int grid, int color,
+                  hipStream_t st);
+template <typename T> void launch_batch_source_mean(const RepDesc<T>* D, int n_rep, hipStream_t st);
+template <typename T> void launch_batch_reduce(const RepDesc<T>* D, int n_rep, hipStream_t st);
+template <typename T> void launch_batch_tail(const RepDesc<T>* D, int n_rep, hipStream_t st);
+
 template <typename T> void launch_mg_coarsen_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st);
 void launch_mg_coarsen(const MGLevel& f, const MGLevel& c, hipStream_t st);
 void launch_mg_smooth(const MGLevel& L, int color, double omega, hipStream_t st);
@@ -102,7 +136,11 @@ void launch_particle_move(const Scalars& S, int np, const double* x, const doubl
 template <typename T> void launch_observe(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
 template <typename T>
 void launch_init_pop_flags(const Scalars& S, T* f, const double* rho, double rref, const uint8_t* flags, hipStream_t st);
-template <typename T> void launch_init_ions(const Scalars& S, const Fields<T>& F, T* n, const double* src, hipStream_t st);
+template <typename T>
+void launch_init_ions(const Scalars& S, const Fields<T>& F, T* ion_s, T* ion_c, const double* np_, const double* nm_,
+                      hipStream_t st);
+template <typename T>
+void launch_ion_species(const T* ion_s, const T* ion_c, double* dst, unsigned n, double sign, hipStream_t st);
 template <typename T> void launch_to_double(const T* src, double* dst, unsigned n, double add, hipStream_t st);
 template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, int k, double* dst, hipStream_t st);
 template <typename T> void launch_upload(T* dst, const double* src, unsigned n, hipStream_t st);

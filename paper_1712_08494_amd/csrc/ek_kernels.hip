@@ -146,7 +146,8 @@ template <typename T> __device__ __forceinline__ T eps_fluid(T ra, T rb, const S
 // FP64 block reduction of NV values (sums, or maxima where is_max) into red[blockIdx].
 // ------------------------------------------------------------------------------------
 template <int NV>
-__device__ __forceinline__ void block_reduce_store(double (&v)[NV], const bool (&is_max)[NV], double* red) {
+__device__ __forceinline__ void block_reduce_store(double (&v)[NV], const bool (&is_max)[NV], double* red,
+                                                   unsigned slot) {
     __shared__ double sm[NV][kBlock / 64];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -169,7 +170,7 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], const bool (
         for (int k = 0; k < NV; ++k) {
             double a = sm[k][0];
             for (int w = 1; w < kBlock / 64; ++w) a = is_max[k] ? fmax(a, sm[k][w]) : a + sm[k][w];
-            red[(size_t)blockIdx.x * kRedSlots + k] = a;
+            red[(size_t)slot * kRedSlots + k] = a;
         }
     }
 }
@@ -224,12 +225,11 @@ constexpr int kMomSlots = 8;
 // at 128 VGPRs with at most a handful of spills; FP64 needs the registers of two.
 template <typename T> constexpr int kHotOcc = sizeof(T) == 4 ? 4 : 2;
 
+// returns this site's contribution to the FP64 charge sum of the Poisson domain
 template <typename T, int G>
-__global__ __launch_bounds__(kBlock) void k_moments(Scalars S, Fields<T> F) {
-    const unsigned i = xcd_linear();
-    const bool valid = i < S.N;
+__device__ __forceinline__ double moments_body(const Scalars& S, const Fields<T>& F, unsigned i) {
     double qsum = 0.0;
-    if (valid) {
+    if (i < S.N) {
         const int z = (i / S.nx) / S.ny;
         const bool solid = is_solid<T, G>(i, z, S, F);
         T da = T(-S.rref[0]), db = T(-S.rref[1]), ux = 0, uy = 0, uz = 0, pa = 0, pb = 0;
@@ -259,7 +259,8 @@ __global__ __launch_bounds__(kBlock) void k_moments(Scalars S, Fields<T> F) {
             pa = pseudo<T>(ra, S);
             pb = pseudo<T>(rb, S);
         }
-        const T npl = F.n[0][i], nmi = F.n[1][i];
+        const T ion_s = F.n[0][i], ion_c = F.n[1][i];
+        const T npl = ion_s + T(0.5) * ion_c, nmi = ion_s - T(0.5) * ion_c;
         const T chi = T(S.G) * pb + (solid ? T(0) : T(S.G_p) * npl + T(S.G_m) * nmi);
         const size_t N = S.N;
         F.mom[i] = da;
@@ -271,16 +272,21 @@ __global__ __launch_bounds__(kBlock) void k_moments(Scalars S, Fields<T> F) {
         F.mom[6 * N + i] = uy;
         F.mom[7 * N + i] = uz;
         const T qc = G == kColloids ? F.qc[i] : T(0);
-        const T q = npl - nmi + qc;
+        const T q = ion_c + qc;
         const T psis = T(1) - fluid_fraction<T, G>(i, z, S, F);
         const T ra = T(S.rref[0]) + da, rb = T(S.rref[1]) + db;
         F.q[i] = q;
         F.eps[i] = T(S.eps_p) * psis + eps_fluid<T>(ra, rb, S) * (T(1) - psis);
         if (z >= S.z0 && z <= S.z1) qsum = (double)q;
     }
-    double v[1] = {qsum};
+    return qsum;
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_moments(Scalars S, Fields<T> F) {
+    double v[1] = {moments_body<T, G>(S, F, xcd_linear())};
     const bool mx[1] = {false};
-    block_reduce_store<1>(v, mx, F.red);
+    block_reduce_store<1>(v, mx, F.red, blockIdx.x);
 }
 
 template <typename T> void launch_moments(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st) {
@@ -334,8 +340,7 @@ template <typename T> void launch_virtual(const Scalars& S, const Fields<T>& F, 
 }
 
 // Mean of the Poisson source over the domain: (sum q + wall charges) / sites.
-__global__ __launch_bounds__(kRedThreads) void k_source_mean(Scalars S, const double* __restrict__ red, unsigned nblk,
-                                                             double* scal) {
+__device__ void source_mean_body(const Scalars& S, const double* __restrict__ red, unsigned nblk, double* scal) {
     __shared__ double sm[kRedThreads];
     double a = 0.0;
     unsigned b = threadIdx.x;
@@ -354,6 +359,11 @@ __global__ __launch_bounds__(kRedThreads) void k_source_mean(Scalars S, const do
         if (S.walls) tot += (S.sigma0 + S.sigma1) * (double)S.nxy;
         scal[0] = tot / (double)S.ndomain;
     }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_source_mean(Scalars S, const double* __restrict__ red, unsigned nblk,
+                                                             double* scal) {
+    source_mean_body(S, red, nblk, scal);
 }
 
 void launch_source_mean(const Scalars& S, double* red, unsigned nblk, double* scal, hipStream_t st) {
@@ -406,8 +416,7 @@ __device__ __forceinline__ void poisson_row(unsigned i, int x, int y, int z, con
 
 // One colour of a red-black sweep; thread -> site of that colour ((x + y + z) % 2 == color).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sor(Scalars S, Fields<T> F, int color, double omega) {
-    const unsigned t = xcd_linear();
+__device__ __forceinline__ void sor_body(const Scalars& S, const Fields<T>& F, unsigned t, int color, double omega) {
     const unsigned half = (unsigned)(S.nx >> 1);
     const unsigned rows = (unsigned)S.ny * (unsigned)(S.z1 - S.z0 + 1);
     if (t >= half * rows) return;
@@ -422,6 +431,11 @@ __global__ __launch_bounds__(kBlock) void k_sor(Scalars S, Fields<T> F, int colo
     F.phi[i] = F.phi[i] + omega * (gs - F.phi[i]);
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sor(Scalars S, Fields<T> F, int color, double omega) {
+    sor_body<T>(S, F, xcd_linear(), color, omega);
+}
+
 template <typename T> void launch_sor(const Scalars& S, const Fields<T>& F, int color, double omega, hipStream_t st) {
     const unsigned n = (unsigned)(S.nx / 2) * S.ny * (S.z1 - S.z0 + 1);
     hipLaunchKernelGGL(k_sor<T>, dim3(site_blocks(n)), dim3(kBlock), 0, st, S, F, color, omega);
@@ -429,9 +443,8 @@ template <typename T> void launch_sor(const Scalars& S, const Fields<T>& F, int 
 
 // Residual r = s + A phi: FP64 partial sums of r.r, s.s and phi over the domain.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_residual(Scalars S, Fields<T> F) {
-    const unsigned i = xcd_linear();
-    double v[3] = {0.0, 0.0, 0.0};
+__device__ __forceinline__ void residual_body(const Scalars& S, const Fields<T>& F, unsigned i, double (&v)[3]) {
+    v[0] = v[1] = v[2] = 0.0;
     if (i < S.N) {
         const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
         if (z >= S.z0 && z <= S.z1) {
@@ -443,8 +456,14 @@ __global__ __launch_bounds__(kBlock) void k_residual(Scalars S, Fields<T> F) {
             v[2] = F.phi[i];
         }
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual(Scalars S, Fields<T> F) {
+    double v[3];
+    residual_body<T>(S, F, xcd_linear(), v);
     const bool mx[3] = {false, false, false};
-    block_reduce_store<3>(v, mx, F.red);
+    block_reduce_store<3>(v, mx, F.red, blockIdx.x);
 }
 
 template <typename T> void launch_residual(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st) {
@@ -452,12 +471,15 @@ template <typename T> void launch_residual(const Scalars& S, const Fields<T>& F,
 }
 
 // Gauge mean(phi) = 0 over the domain (scal[3] = sum of phi), or phi = 0 when zero != 0.
-__global__ __launch_bounds__(kBlock) void k_phi_finalize(Scalars S, double* phi, const double* scal, int zero) {
-    const unsigned i = xcd_linear();
+__device__ __forceinline__ void finalize_body(const Scalars& S, double* phi, const double* scal, int zero, unsigned i) {
     if (i >= S.N) return;
     const int z = (i / S.nx) / S.ny;
     if (z < S.z0 || z > S.z1) return;
     phi[i] = zero ? 0.0 : phi[i] - scal[3] / (double)S.ndomain;
+}
+
+__global__ __launch_bounds__(kBlock) void k_phi_finalize(Scalars S, double* phi, const double* scal, int zero) {
+    finalize_body(S, phi, scal, zero, xcd_linear());
 }
 
 void launch_phi_finalize(const Scalars& S, double* phi, const double* scal, int zero, hipStream_t st) {
@@ -466,14 +488,17 @@ void launch_phi_finalize(const Scalars& S, double* phi, const double* scal, int 
 
 // Warm start of the next solve by linear extrapolation in time,
 // phi <- 2 phi(t-1) - phi(t-2), keeping phi(t-1) for the following step.
-__global__ __launch_bounds__(kBlock) void k_phi_extrapolate(Scalars S, double* phi, double* phi_prev) {
-    const unsigned i = xcd_linear();
+__device__ __forceinline__ void extrapolate_body(const Scalars& S, double* phi, double* phi_prev, unsigned i) {
     if (i >= S.N) return;
     const int z = (i / S.nx) / S.ny;
     if (z < S.z0 || z > S.z1) return;
     const double p = phi[i];
     phi[i] = 2.0 * p - phi_prev[i];
     phi_prev[i] = p;
+}
+
+__global__ __launch_bounds__(kBlock) void k_phi_extrapolate(Scalars S, double* phi, double* phi_prev) {
+    extrapolate_body(S, phi, phi_prev, xcd_linear());
 }
 
 void launch_phi_extrapolate(const Scalars& S, double* phi, double* phi_prev, hipStream_t st) {
@@ -524,8 +549,7 @@ __device__ __forceinline__ double fine_face(int k, int x, int y, int z, const Sc
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mg_coarsen_fine(Scalars S, Fields<T> F, MGLevel C) {
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void coarsen_fine_body(const Scalars& S, const Fields<T>& F, const MGLevel& C, unsigned t) {
     if (t >= C.n) return;
     const int I = t % C.nx, r = t / C.nx, J = r % C.ny, K = r / C.ny;
     double ax = 0, ay = 0, az = 0;
@@ -540,12 +564,16 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarsen_fine(Scalars S, Fields<T>
     C.az[t] = 0.5 * az;
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mg_coarsen_fine(Scalars S, Fields<T> F, MGLevel C) {
+    coarsen_fine_body<T>(S, F, C, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 template <typename T> void launch_mg_coarsen_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st) {
     hipLaunchKernelGGL(k_mg_coarsen_fine<T>, dim3((c.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, S, F, c);
 }
 
-__global__ __launch_bounds__(kBlock) void k_mg_coarsen(MGLevel Fl, MGLevel C) {
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void coarsen_body(const MGLevel& Fl, const MGLevel& C, unsigned t) {
     if (t >= C.n) return;
     const int I = t % C.nx, r = t / C.nx, J = r % C.ny, K = r / C.ny;
     double ax = 0, ay = 0, az = 0;
@@ -558,6 +586,10 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarsen(MGLevel Fl, MGLevel C) {
     C.ax[t] = 0.5 * ax;
     C.ay[t] = 0.5 * ay;
     C.az[t] = 0.5 * az;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mg_coarsen(MGLevel Fl, MGLevel C) {
+    coarsen_body(Fl, C, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 void launch_mg_coarsen(const MGLevel& f, const MGLevel& c, hipStream_t st) {
@@ -578,8 +610,7 @@ __device__ __forceinline__ void mg_row(const MGLevel& L, int x, int y, int z, do
           b1 * L.phi[lid(L, x, ym, z)] + c0 * L.phi[lid(L, x, y, zp)] + c1 * L.phi[lid(L, x, y, zm)];
 }
 
-__global__ __launch_bounds__(kBlock) void k_mg_smooth(MGLevel L, int color, double omega) {
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void smooth_body(const MGLevel& L, int color, double omega, unsigned t) {
     const unsigned half = (unsigned)(L.nx >> 1);
     if (t >= half * (unsigned)L.ny * (unsigned)L.nz) return;
     const unsigned row = t / half, m = t % half;
@@ -592,14 +623,17 @@ __global__ __launch_bounds__(kBlock) void k_mg_smooth(MGLevel L, int color, doub
     L.phi[i] = L.phi[i] + omega * ((off + L.s[i]) / diag - L.phi[i]);
 }
 
+__global__ __launch_bounds__(kBlock) void k_mg_smooth(MGLevel L, int color, double omega) {
+    smooth_body(L, color, omega, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 void launch_mg_smooth(const MGLevel& L, int color, double omega, hipStream_t st) {
     const unsigned n = L.n / 2;
     hipLaunchKernelGGL(k_mg_smooth, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, L, color, omega);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mg_restrict_fine(Scalars S, Fields<T> F, MGLevel C) {
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void restrict_fine_body(const Scalars& S, const Fields<T>& F, const MGLevel& C, unsigned t) {
     if (t >= C.n) return;
     const int I = t % C.nx, r = t / C.nx, J = r % C.ny, K = r / C.ny;
     double sum = 0.0;
@@ -617,12 +651,16 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict_fine(Scalars S, Fields<T
     C.phi[t] = 0.0;
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mg_restrict_fine(Scalars S, Fields<T> F, MGLevel C) {
+    restrict_fine_body<T>(S, F, C, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 template <typename T> void launch_mg_restrict_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st) {
     hipLaunchKernelGGL(k_mg_restrict_fine<T>, dim3((c.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, S, F, c);
 }
 
-__global__ __launch_bounds__(kBlock) void k_mg_restrict(MGLevel Fl, MGLevel C) {
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void restrict_body(const MGLevel& Fl, const MGLevel& C, unsigned t) {
     if (t >= C.n) return;
     const int I = t % C.nx, r = t / C.nx, J = r % C.ny, K = r / C.ny;
     double sum = 0.0;
@@ -637,6 +675,10 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(MGLevel Fl, MGLevel C) {
             }
     C.s[t] = sum;
     C.phi[t] = 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(MGLevel Fl, MGLevel C) {
+    restrict_body(Fl, C, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 void launch_mg_restrict(const MGLevel& f, const MGLevel& c, hipStream_t st) {
@@ -665,23 +707,30 @@ __device__ __forceinline__ double mg_interp(const MGLevel& C, int x, int y, int 
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mg_prolong_fine(Scalars S, Fields<T> F, MGLevel C) {
-    const unsigned i = xcd_linear();
+__device__ __forceinline__ void prolong_fine_body(const Scalars& S, const Fields<T>& F, const MGLevel& C, unsigned i) {
     if (i >= S.N) return;
     const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
     if (z < S.z0 || z > S.z1) return;
     F.phi[i] += mg_interp(C, x, y, z);
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mg_prolong_fine(Scalars S, Fields<T> F, MGLevel C) {
+    prolong_fine_body<T>(S, F, C, xcd_linear());
+}
+
 template <typename T> void launch_mg_prolong_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st) {
     hipLaunchKernelGGL(k_mg_prolong_fine<T>, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F, c);
 }
 
-__global__ __launch_bounds__(kBlock) void k_mg_prolong(MGLevel C, MGLevel Fl) {
-    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void prolong_body(const MGLevel& C, const MGLevel& Fl, unsigned i) {
     if (i >= Fl.n) return;
     const int x = i % Fl.nx, r = i / Fl.nx, y = r % Fl.ny, z = r / Fl.ny;
     Fl.phi[i] += mg_interp(C, x, y, z);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mg_prolong(MGLevel C, MGLevel Fl) {
+    prolong_body(C, Fl, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 void launch_mg_prolong(const MGLevel& c, const MGLevel& f, hipStream_t st) {
@@ -767,8 +816,7 @@ __device__ void tail_load_coeffs(const MGLevel& G, C* ax, C* ay, C* az) {
     }
 }
 
-__global__ __launch_bounds__(kTailThreads) void k_mg_tail(MGLevel M, MGLevel Cg, int has_mid, int coarse_iters,
-                                                         double coarse_omega) {
+__device__ void tail_body(const MGLevel& M, const MGLevel& Cg, int has_mid, int coarse_iters, double coarse_omega) {
     extern __shared__ double lds[];
     if (has_mid) {
         double* phim = lds;
@@ -856,6 +904,11 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MGLevel M, MGLevel Cg,
     }
 }
 
+__global__ __launch_bounds__(kTailThreads) void k_mg_tail(MGLevel M, MGLevel Cg, int has_mid, int coarse_iters,
+                                                         double coarse_omega) {
+    tail_body(M, Cg, has_mid, coarse_iters, coarse_omega);
+}
+
 size_t mg_tail_lds_bytes() {
     const size_t with_mid = 2 * kTailMid * 8 + 6 * kTailCoarse * 8 + 4 * kTailMid * 4;
     const size_t coarse_only = 2 * kTailCoarseOnly * 8 + 4 * kTailCoarseOnly * 4;
@@ -874,17 +927,28 @@ void launch_mg_tail(const MGLevel& mid, const MGLevel& coarse, int has_mid, int 
 // n~ = n / psi_f, q~ = z e n~.  Both end sites evaluate a link with identical operands in
 // identical order, so the two see bit-identical fluxes and the update conserves ions.
 // ------------------------------------------------------------------------------------
+// The same flux written for the stored variables s = (n+ + n-)/2 and c = n+ - n-
+// (an exact linear recombination of the two species' fluxes):
+//   J_s = (J+ + J-)/2 = w [ (s~_hi - s~_lo) - (beta/4)(c~_lo + c~_hi)/2 Es
+//                           + ((k+ + k-) S + (k+ - k-) C/2) dra / 2 ]
+//   J_c =  J+ - J-    = w [ (c~_hi - c~_lo) - (beta/4) 2 (s~_lo + s~_hi) Es
+//                           + ((k+ - k-) S + (k+ + k-) C/2) dra ]
+// with S = s~_lo + s~_hi, C = c~_lo + c~_hi, Es = (E_lo + E_hi)_k, dra the rho^a
+// difference, w = -D psi_f(lo) psi_f(hi), k+- = s beta dmu+- / (2 drho_a).  The charge
+// flux is rounded relative to its own terms, not to the salt concentration.
 template <typename T>
-__device__ __forceinline__ void link_flux(T tpl, T tml, T tph, T tmh, T w, T Elo, T Ehi, T ralo, T rahi,
-                                          const Scalars& S, T& Jp, T& Jm) {
+__device__ __forceinline__ void link_flux(T sl, T cl, T sh, T ch, T w, T Elo, T Ehi, T ralo, T rahi,
+                                          const Scalars& S, T& Js, T& Jc) {
 #pragma clang fp contract(off)
     const T es = Elo + Ehi;
     const T dra = rahi - ralo;
     const T qb = T(0.25) * T(S.beta);
-    const T bp = (tph - tpl) - qb * (tpl + tph) * es + T(S.kap_p) * (tpl + tph) * dra;
-    const T bm = (tmh - tml) + qb * (tml + tmh) * es + T(S.kap_m) * (tml + tmh) * dra;
-    Jp = w * bp;
-    Jm = w * bm;
+    const T ss = sl + sh, cs = cl + ch;
+    const T ksum = T(S.kap_p) + T(S.kap_m), kdif = T(S.kap_p) - T(S.kap_m);
+    const T bs = (sh - sl) - qb * (T(0.5) * cs) * es + T(0.5) * (ksum * ss + kdif * (T(0.5) * cs)) * dra;
+    const T bc = (ch - cl) - qb * (T(2) * ss) * es + (kdif * ss + ksum * (T(0.5) * cs)) * dra;
+    Js = w * bs;
+    Jc = w * bc;
 }
 
 // Donor-cell advection across lo -> hi (only between LB-fluid sites).
@@ -946,12 +1010,12 @@ template <typename T, int G, bool kUpdate>
 __device__ __forceinline__ void site_links(unsigned i, int z, const Nbr& o, bool solid_i, const PhiStar& P,
                                            const Scalars& S, const Fields<T>& F, T (&jsum)[3], double (&El)[3],
                                            double (&Eh)[3], T& np_new, T& nm_new) {
-    const T np_i = F.n[0][i], nm_i = F.n[1][i];
+    const T s_i = F.n[0][i], c_i = F.n[1][i];
     const T ra_i = F.mom[i];
     const T pf_i = fluid_fraction<T, G>(i, z, S, F);
     const T inv_i = G == kColloids ? (pf_i > T(0) ? T(1) / pf_i : T(0)) : T(1);
-    const T tp_i = np_i * inv_i, tm_i = nm_i * inv_i;
-    T out_p = T(0), out_m = T(0);
+    const T ts_i = s_i * inv_i, tc_i = c_i * inv_i;
+    T out_s = T(0), out_c = T(0);
     T u_i[3];
     if (kUpdate && !solid_i) {
         u_i[0] = F.uph[i];
@@ -967,7 +1031,7 @@ __device__ __forceinline__ void site_links(unsigned i, int z, const Nbr& o, bool
         double E0;
         field_line(k, z, P, S, El[k], E0, Eh[k]);
         const T Ei = (T)E0, Elo = (T)El[k], Ehi = (T)Eh[k];
-        const T np_lo = F.n[0][lo], nm_lo = F.n[1][lo], np_hi = F.n[0][hi], nm_hi = F.n[1][hi];
+        const T s_lo = F.n[0][lo], c_lo = F.n[1][lo], s_hi = F.n[0][hi], c_hi = F.n[1][hi];
         const T ra_lo = F.mom[lo], ra_hi = F.mom[hi];
         const T pf_lo = fluid_fraction<T, G>(lo, zlo, S, F), pf_hi = fluid_fraction<T, G>(hi, zhi, S, F);
         T inv_lo = T(1), inv_hi = T(1);
@@ -977,31 +1041,31 @@ __device__ __forceinline__ void site_links(unsigned i, int z, const Nbr& o, bool
         }
         const T wlo = (pf_lo > T(0) && pf_i > T(0)) ? -T(S.D) * pf_lo * pf_i : T(0);
         const T whi = (pf_i > T(0) && pf_hi > T(0)) ? -T(S.D) * pf_i * pf_hi : T(0);
-        T Jp_lo, Jm_lo, Jp_hi, Jm_hi;
-        link_flux<T>(np_lo * inv_lo, nm_lo * inv_lo, tp_i, tm_i, wlo, Elo, Ei, ra_lo, ra_i, S, Jp_lo, Jm_lo);
-        link_flux<T>(tp_i, tm_i, np_hi * inv_hi, nm_hi * inv_hi, whi, Ei, Ehi, ra_i, ra_hi, S, Jp_hi, Jm_hi);
-        jsum[k] = ((Jp_hi + Jp_lo) + Jm_hi) + Jm_lo;
+        T Js_lo, Jc_lo, Js_hi, Jc_hi;
+        link_flux<T>(s_lo * inv_lo, c_lo * inv_lo, ts_i, tc_i, wlo, Elo, Ei, ra_lo, ra_i, S, Js_lo, Jc_lo);
+        link_flux<T>(ts_i, tc_i, s_hi * inv_hi, c_hi * inv_hi, whi, Ei, Ehi, ra_i, ra_hi, S, Js_hi, Jc_hi);
+        jsum[k] = T(2) * (Js_hi + Js_lo);  // sum over both species of J on the two links
         if (kUpdate) {
-            T Ap_lo = 0, Am_lo = 0, Ap_hi = 0, Am_hi = 0;
+            T As_lo = 0, Ac_lo = 0, As_hi = 0, Ac_hi = 0;
             if (!solid_i) {
                 if (!is_solid<T, G>(lo, zlo, S, F)) {
                     const T u_lo = F.uph[(size_t)k * S.N + lo];
-                    Ap_lo = advect<T>(np_lo, np_i, u_lo, u_i[k]);
-                    Am_lo = advect<T>(nm_lo, nm_i, u_lo, u_i[k]);
+                    As_lo = advect<T>(s_lo, s_i, u_lo, u_i[k]);
+                    Ac_lo = advect<T>(c_lo, c_i, u_lo, u_i[k]);
                 }
                 if (!is_solid<T, G>(hi, zhi, S, F)) {
                     const T u_hi = F.uph[(size_t)k * S.N + hi];
-                    Ap_hi = advect<T>(np_i, np_hi, u_i[k], u_hi);
-                    Am_hi = advect<T>(nm_i, nm_hi, u_i[k], u_hi);
+                    As_hi = advect<T>(s_i, s_hi, u_i[k], u_hi);
+                    Ac_hi = advect<T>(c_i, c_hi, u_i[k], u_hi);
                 }
             }
-            out_p += (Jp_hi + Ap_hi) - (Jp_lo + Ap_lo);
-            out_m += (Jm_hi + Am_hi) - (Jm_lo + Am_lo);
+            out_s += (Js_hi + As_hi) - (Js_lo + As_lo);
+            out_c += (Jc_hi + Ac_hi) - (Jc_lo + Ac_lo);
         }
     }
     if (kUpdate) {
-        np_new = np_i - out_p;
-        nm_new = nm_i - out_m;
+        np_new = s_i - out_s;  // mean ion density
+        nm_new = c_i - out_c;  // ionic charge
     }
 }
 
@@ -1071,8 +1135,7 @@ __device__ __forceinline__ void site_forces(unsigned i, const Nbr& o, T ra, T rb
 // site (needed by the donor-cell ion advection of the neighbours).
 // ------------------------------------------------------------------------------------
 template <typename T, int G>
-__global__ __launch_bounds__(kBlock, kHotOcc<T>) void k_force(Scalars S, Fields<T> F) {
-    const unsigned i = xcd_linear();
+__device__ __forceinline__ void force_body(const Scalars& S, const Fields<T>& F, unsigned i) {
     if (i >= S.N) return;
     const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
     const size_t N = S.N;
@@ -1093,6 +1156,11 @@ __global__ __launch_bounds__(kBlock, kHotOcc<T>) void k_force(Scalars S, Fields<
     const T rt2 = T(2) * (ra + rb);
 #pragma unroll
     for (int k = 0; k < 3; ++k) F.uph[(size_t)k * N + i] = F.mom[(size_t)(5 + k) * N + i] + (Pa[k] + Pb[k]) / rt2;
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock, kHotOcc<T>) void k_force(Scalars S, Fields<T> F) {
+    force_body<T, G>(S, F, xcd_linear());
 }
 
 template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hipStream_t st) {
@@ -1116,8 +1184,7 @@ template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hi
 // of the moments (already in the moment slots), and populations are streamed as written.
 // ------------------------------------------------------------------------------------
 template <typename T, int G>
-__global__ __launch_bounds__(kBlock, kHotOcc<T>) void k_fused(Scalars S, Fields<T> F) {
-    const unsigned i = xcd_linear();
+__device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F, unsigned i) {
     if (i >= S.N) return;
     const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
     if (G == kWalls && (z == 0 || z == S.nz - 1)) return;  // wall layers hold no ions and no fluid
@@ -1128,8 +1195,8 @@ __global__ __launch_bounds__(kBlock, kHotOcc<T>) void k_fused(Scalars S, Fields<
     T jsum[3], np_new, nm_new;
     double El[3], Eh[3];
     site_links<T, G, true>(i, z, o, solid_i, P, S, F, jsum, El, Eh, np_new, nm_new);
-    F.nn[0][i] = np_new;
-    F.nn[1][i] = nm_new;
+    F.nn[0][i] = np_new;  // mean ion density
+    F.nn[1][i] = nm_new;  // ionic charge
     if (solid_i) return;
 
     const T da = F.mom[i], db = F.mom[N + i];
@@ -1189,6 +1256,11 @@ __global__ __launch_bounds__(kBlock, kHotOcc<T>) void k_fused(Scalars S, Fields<
             }
         }
     }
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock, kHotOcc<T>) void k_fused(Scalars S, Fields<T> F) {
+    fused_body<T, G>(S, F, xcd_linear());
 }
 
 template <typename T> void launch_fused(const Scalars& S, const Fields<T>& F, hipStream_t st) {
@@ -1311,7 +1383,8 @@ __global__ __launch_bounds__(kBlock) void k_observe(Scalars S, Fields<T> F) {
     double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < S.N) {
         const int z = (i / S.nx) / S.ny;
-        const double np_ = (double)F.n[0][i], nm_ = (double)F.n[1][i];
+        const double is_ = (double)F.n[0][i], ic_ = (double)F.n[1][i];
+        const double np_ = is_ + 0.5 * ic_, nm_ = is_ - 0.5 * ic_;
         v[2] = np_;
         v[3] = nm_;
         v[4] = np_ - nm_ + (S.colloids ? (double)F.qc[i] : 0.0);
@@ -1340,7 +1413,7 @@ __global__ __launch_bounds__(kBlock) void k_observe(Scalars S, Fields<T> F) {
         v[9] = bad;
     }
     const bool mx[11] = {false, false, false, false, false, false, false, false, true, false, false};
-    block_reduce_store<11>(v, mx, F.red);
+    block_reduce_store<11>(v, mx, F.red, blockIdx.x);
 }
 
 template <typename T> void launch_observe(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st) {
@@ -1363,17 +1436,38 @@ __global__ __launch_bounds__(kBlock) void k_init_pop(Scalars S, T* f, const doub
     for (int d = 0; d < kQ; ++d) f[(size_t)d * S.N + i] = (T)(weight(d) * dr);
 }
 
+// Ions are stored as the mean density s = (n+ + n-)/2 and the ionic charge c = n+ - n-
+// (both scaled by the fluid fraction at set-up), so that the charge keeps its own
+// relative precision in FP32 however large the salt concentration.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_init_ions(Scalars S, Fields<T> F, T* n, const double* src) {
+__global__ __launch_bounds__(kBlock) void k_init_ions(Scalars S, Fields<T> F, T* ion_s, T* ion_c, const double* np_,
+                                                      const double* nm_) {
     const unsigned i = xcd_linear();
     if (i >= S.N) return;
     const int z = (i / S.nx) / S.ny;
-    n[i] = (T)(src[i] * (double)psif_at(i, z, S, F));
+    const double pf = (double)psif_at(i, z, S, F);
+    ion_s[i] = (T)(0.5 * (np_[i] + nm_[i]) * pf);
+    ion_c[i] = (T)((np_[i] - nm_[i]) * pf);
 }
 
 template <typename T>
-void launch_init_ions(const Scalars& S, const Fields<T>& F, T* n, const double* src, hipStream_t st) {
-    hipLaunchKernelGGL(k_init_ions<T>, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F, n, src);
+void launch_init_ions(const Scalars& S, const Fields<T>& F, T* ion_s, T* ion_c, const double* np_, const double* nm_,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_init_ions<T>, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F, ion_s, ion_c, np_, nm_);
+}
+
+// n+ (sign = +1) or n- (sign = -1) in double from the stored mean and charge
+template <typename T>
+__global__ void k_ion_species(const T* __restrict__ ion_s, const T* __restrict__ ion_c, double* __restrict__ dst,
+                              unsigned n, double sign) {
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (double)ion_s[i] + sign * 0.5 * (double)ion_c[i];
+}
+
+template <typename T>
+void launch_ion_species(const T* ion_s, const T* ion_c, double* dst, unsigned n, double sign, hipStream_t st) {
+    hipLaunchKernelGGL(k_ion_species<T>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, ion_s, ion_c, dst, n,
+                       sign);
 }
 
 template <typename T>
@@ -1420,7 +1514,9 @@ template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, 
     template void launch_particle_sum<T>(const Scalars&, const Fields<T>&, int, const int32_t*, const int32_t*, \
                                          const int32_t*, const int32_t*, double*, hipStream_t);                \
     template void launch_observe<T>(const Scalars&, const Fields<T>&, unsigned, hipStream_t);                  \
-    template void launch_init_ions<T>(const Scalars&, const Fields<T>&, T*, const double*, hipStream_t);       \
+    template void launch_init_ions<T>(const Scalars&, const Fields<T>&, T*, T*, const double*, const double*,  \
+                                      hipStream_t);                                                             \
+    template void launch_ion_species<T>(const T*, const T*, double*, unsigned, double, hipStream_t);           \
     template void launch_to_double<T>(const T*, double*, unsigned, double, hipStream_t);                       \
     template void launch_field_e<T>(const Scalars&, const Fields<T>&, int, double*, hipStream_t);              \
     template void launch_upload<T>(T*, const double*, unsigned, hipStream_t);                               \
@@ -1430,6 +1526,161 @@ template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, 
 
 EK_INST(float)
 EK_INST(double)
+
+
+// ------------------------------------------------------------------------------------
+// Batched replicas: the same bodies, one launch per stage for every replica.  Each
+// workgroup finds its replica and its workgroup index inside that replica in a block
+// table; the replica's parameters and pointers come from a descriptor in device memory
+// (uniform per workgroup, so they are read through the scalar cache).  Batched
+// replicas are periodic without particles.
+// ------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_moments(const RepDesc<T>* __restrict__ D, const BlockRef* __restrict__ tab) {
+    const BlockRef e = tab[blockIdx.x];
+    const RepDesc<T>& R = D[e.rep];
+    double v[1] = {moments_body<T, kPeriodic>(R.S, R.F, (unsigned)e.blk * kBlock + threadIdx.x)};
+    const bool mx[1] = {false};
+    block_reduce_store<1>(v, mx, R.F.red, e.blk);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_residual(const RepDesc<T>* __restrict__ D, const BlockRef* __restrict__ tab) {
+    const BlockRef e = tab[blockIdx.x];
+    const RepDesc<T>& R = D[e.rep];
+    double v[3];
+    residual_body<T>(R.S, R.F, (unsigned)e.blk * kBlock + threadIdx.x, v);
+    const bool mx[3] = {false, false, false};
+    block_reduce_store<3>(v, mx, R.F.red, e.blk);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock, kHotOcc<T>) void kb_force(const RepDesc<T>* __restrict__ D,
+                                                               const BlockRef* __restrict__ tab) {
+    const BlockRef e = tab[blockIdx.x];
+    const RepDesc<T>& R = D[e.rep];
+    force_body<T, kPeriodic>(R.S, R.F, (unsigned)e.blk * kBlock + threadIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock, kHotOcc<T>) void kb_fused(const RepDesc<T>* __restrict__ D,
+                                                               const BlockRef* __restrict__ tab) {
+    const BlockRef e = tab[blockIdx.x];
+    const RepDesc<T>& R = D[e.rep];
+    fused_body<T, kPeriodic>(R.S, R.F, (unsigned)e.blk * kBlock + threadIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_misc(const RepDesc<T>* __restrict__ D, const BlockRef* __restrict__ tab,
+                                                  int op, int grid, int color) {
+    const BlockRef e = tab[blockIdx.x];
+    const RepDesc<T>& R = D[e.rep];
+    const unsigned t = (unsigned)e.blk * kBlock + threadIdx.x;
+    switch (op) {
+        case kB_EXTRAPOLATE: extrapolate_body(R.S, R.F.phi, R.phi_prev, t); break;
+        case kB_FINALIZE: finalize_body(R.S, R.F.phi, R.F.scal, 0, t); break;
+        case kB_PROLONG_FINE: prolong_fine_body<T>(R.S, R.F, R.mg[0], t); break;
+        case kB_SOR: sor_body<T>(R.S, R.F, t, color, 1.0); break;
+        case kB_COARSEN_FINE:
+            if (t < R.mg[0].n) coarsen_fine_body<T>(R.S, R.F, R.mg[0], t);
+            break;
+        case kB_COARSEN:
+            if (t < R.mg[grid - 1].n) coarsen_body(R.mg[grid - 2], R.mg[grid - 1], t);
+            break;
+        case kB_RESTRICT_FINE:
+            if (t < R.mg[0].n) restrict_fine_body<T>(R.S, R.F, R.mg[0], t);
+            break;
+        case kB_RESTRICT:
+            if (t < R.mg[grid].n) restrict_body(R.mg[grid - 1], R.mg[grid], t);
+            break;
+        case kB_SMOOTH:
+            if (t < R.mg[grid - 1].n / 2) smooth_body(R.mg[grid - 1], color, 1.0, t);
+            break;
+        case kB_PROLONG:
+            if (t < R.mg[grid - 1].n) prolong_body(R.mg[grid], R.mg[grid - 1], t);
+            break;
+        default: break;
+    }
+}
+
+template <typename T>
+void launch_batch(BatchOp op, const RepDesc<T>* D, const BlockRef* tab, unsigned nblocks, int grid, int color,
+                  hipStream_t st) {
+    if (nblocks == 0) return;
+    const dim3 g(nblocks), b(kBlock);
+    switch (op) {
+        case kB_MOMENTS: hipLaunchKernelGGL(kb_moments<T>, g, b, 0, st, D, tab); break;
+        case kB_RESIDUAL: hipLaunchKernelGGL(kb_residual<T>, g, b, 0, st, D, tab); break;
+        case kB_FORCE: hipLaunchKernelGGL(kb_force<T>, g, b, 0, st, D, tab); break;
+        case kB_FUSED: hipLaunchKernelGGL(kb_fused<T>, g, b, 0, st, D, tab); break;
+        default: hipLaunchKernelGGL(kb_misc<T>, g, b, 0, st, D, tab, (int)op, grid, color); break;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void kb_source_mean(const RepDesc<T>* __restrict__ D) {
+    const RepDesc<T>& R = D[blockIdx.x];
+    source_mean_body(R.S, R.F.red, (R.S.N + kBlock - 1) / kBlock, R.F.scal);
+}
+
+template <typename T> void launch_batch_source_mean(const RepDesc<T>* D, int n_rep, hipStream_t st) {
+    hipLaunchKernelGGL(kb_source_mean<T>, dim3(n_rep), dim3(kRedThreads), 0, st, D);
+}
+
+// Per replica: residual sums -> scal[1..3], relative residual -> scal[4], its running
+// maximum -> scal[5].
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void kb_reduce(const RepDesc<T>* __restrict__ D) {
+    const RepDesc<T>& R = D[blockIdx.x];
+    const unsigned nblk = (R.S.N + kBlock - 1) / kBlock;
+    __shared__ double sm[kRedThreads];
+    double tot[3];
+    for (int k = 0; k < 3; ++k) {
+        double a = 0.0;
+        for (unsigned b = threadIdx.x; b < nblk; b += kRedThreads) a += R.F.red[(size_t)b * kRedSlots + k];
+        sm[threadIdx.x] = a;
+        __syncthreads();
+        for (int s2 = kRedThreads / 2; s2 > 0; s2 >>= 1) {
+            if ((int)threadIdx.x < s2) sm[threadIdx.x] += sm[threadIdx.x + s2];
+            __syncthreads();
+        }
+        tot[k] = sm[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double* sc = R.F.scal;
+        sc[1] = tot[0];
+        sc[2] = tot[1];
+        sc[3] = tot[2];
+        const double rel = tot[1] > 0.0 ? sqrt(tot[0] / tot[1]) : 0.0;
+        sc[4] = rel;
+        sc[5] = fmax(sc[5], rel);
+    }
+}
+
+template <typename T> void launch_batch_reduce(const RepDesc<T>* D, int n_rep, hipStream_t st) {
+    hipLaunchKernelGGL(kb_reduce<T>, dim3(n_rep), dim3(kRedThreads), 0, st, D);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) void kb_tail(const RepDesc<T>* __restrict__ D) {
+    const RepDesc<T>& R = D[blockIdx.x];
+    const int nl = R.nl;
+    tail_body(R.tail_mid ? R.mg[nl - 2] : R.mg[nl - 1], R.mg[nl - 1], R.tail_mid, R.coarse_iters, R.coarse_omega);
+}
+
+template <typename T> void launch_batch_tail(const RepDesc<T>* D, int n_rep, hipStream_t st) {
+    hipLaunchKernelGGL(kb_tail<T>, dim3(n_rep), dim3(kTailThreads), mg_tail_lds_bytes(), st, D);
+}
+
+#define EK_BATCH_INST(T)                                                                                          \
+    template void launch_batch<T>(BatchOp, const RepDesc<T>*, const BlockRef*, unsigned, int, int, hipStream_t); \
+    template void launch_batch_source_mean<T>(const RepDesc<T>*, int, hipStream_t);                             \
+    template void launch_batch_reduce<T>(const RepDesc<T>*, int, hipStream_t);                                  \
+    template void launch_batch_tail<T>(const RepDesc<T>*, int, hipStream_t);
+
+EK_BATCH_INST(float)
+EK_BATCH_INST(double)
 
 // population initialisation needs the flags pointer, exposed separately
 template <typename T>

@@ -56,7 +56,8 @@ class EKTiming(ctypes.Structure):
 
 EXPORTS = ["ek_lattice", "ek_init", "ek_step", "ek_poisson", "ek_observables", "ek_get_field",
            "ek_get_populations", "ek_get_particles", "ek_device_bytes", "ek_set_timing", "ek_get_timing",
-           "ek_destroy", "ek_status_str", "ek_last_error"]
+           "ek_destroy", "ek_status_str", "ek_last_error", "ek_batch_init", "ek_batch_step", "ek_batch_sync",
+           "ek_batch_residuals", "ek_batch_replica", "ek_batch_destroy", "ek_batch_last_error"]
 
 _lib = None
 
@@ -110,6 +111,22 @@ def load(path=LIB_PATH):
     L.ek_status_str.restype = ctypes.c_char_p
     L.ek_last_error.argtypes = [vp]
     L.ek_last_error.restype = ctypes.c_char_p
+    pdp = ctypes.POINTER(dp)
+    L.ek_batch_init.argtypes = [ctypes.POINTER(EKParams), ctypes.c_int32, pdp, pdp, pdp, pdp, ctypes.c_int32,
+                                ctypes.POINTER(vp)]
+    L.ek_batch_init.restype = ctypes.c_int32
+    L.ek_batch_step.argtypes = [vp, ctypes.c_int32]
+    L.ek_batch_step.restype = ctypes.c_int32
+    L.ek_batch_sync.argtypes = [vp]
+    L.ek_batch_sync.restype = ctypes.c_int32
+    L.ek_batch_residuals.argtypes = [vp, dp, dp]
+    L.ek_batch_residuals.restype = ctypes.c_int32
+    L.ek_batch_replica.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(vp)]
+    L.ek_batch_replica.restype = ctypes.c_int32
+    L.ek_batch_destroy.argtypes = [vp]
+    L.ek_batch_destroy.restype = ctypes.c_int32
+    L.ek_batch_last_error.argtypes = [vp]
+    L.ek_batch_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -270,3 +287,76 @@ class EKSim:
         t = EKTiming()
         self._check(load().ek_get_timing(self._h, ctypes.byref(t)), "ek_get_timing")
         return {name: (t.ms[k], t.count[k]) for k, name in enumerate(TIMING_CLASSES)}
+
+
+class _Borrowed(EKSim):
+    """A replica context owned by a batch: export calls only."""
+
+    def __init__(self, handle, cfg):
+        self._h = handle
+        self.cfg = cfg
+        self.shape = (cfg.nz, cfg.ny, cfg.nx)
+        self.N = cfg.nx * cfg.ny * cfg.nz
+        self.np = 0
+
+    def close(self):
+        self._h = None
+
+
+class EKBatch:
+    """Many periodic replicas advanced together, one graph launch per step."""
+
+    def __init__(self, cfgs, inputs, cycles=4):
+        L = load()
+        n = len(cfgs)
+        self.cfgs = list(cfgs)
+        params = (EKParams * n)()
+        for r, c in enumerate(cfgs):
+            params[r] = params_from_config(c)
+        self._keep = []
+        ptrs = []
+        for name in ("rho_a", "rho_b", "n_plus", "n_minus"):
+            arrs = [_c64(getattr(inp, name)) for inp in inputs]
+            self._keep.append(arrs)
+            ptrs.append((ctypes.POINTER(ctypes.c_double) * n)(*[_dp(a) for a in arrs]))
+        h = ctypes.c_void_p()
+        st = L.ek_batch_init(params, n, ptrs[0], ptrs[1], ptrs[2], ptrs[3], int(cycles), ctypes.byref(h))
+        self._h = h
+        self.n = n
+        self._keep = None
+        if st != EK_OK:
+            msg = L.ek_batch_last_error(h).decode() if h else ""
+            self.close()
+            raise EKError(st, "ek_batch_init: " + msg)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().ek_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        st = load().ek_batch_step(self._h, int(n))
+        if st != EK_OK:
+            raise EKError(st, "ek_batch_step: " + load().ek_batch_last_error(self._h).decode())
+
+    def sync(self):
+        load().ek_batch_sync(self._h)
+
+    def residuals(self):
+        last = np.zeros(self.n)
+        worst = np.zeros(self.n)
+        load().ek_batch_residuals(self._h, _dp(last), _dp(worst))
+        return last, worst
+
+    def replica(self, r):
+        h = ctypes.c_void_p()
+        st = load().ek_batch_replica(self._h, int(r), ctypes.byref(h))
+        if st != EK_OK:
+            raise EKError(st, "ek_batch_replica")
+        return _Borrowed(h, self.cfgs[r])

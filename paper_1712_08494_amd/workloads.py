@@ -241,6 +241,44 @@ def colloids(n=256, seed=3, precision="fp32", count=200, radius=4.0, shape=None,
 
 
 # ---------------------------------------------------------------------------------
+# Workload 4: a sweep of independent droplet replicas of uneven size.
+# ---------------------------------------------------------------------------------
+def droplet(L, seed=4, precision="fp32", field=1e-4, salt=1e-3, G=3.6, dmu=-4.0, width=2.0, shape=None):
+    """A drop of fluid b (radius L/5) in fluid a, centred in a periodic cube: inside
+    (rho_a, rho_b) = (0.1, 0.9), outside swapped, tanh profile of width 2; both ion
+    species Boltzmann-partitioned by the solvation energy dmu rho_a / drho_a (same
+    energy for both, so the fluid stays neutral), mean salt `salt`; field along z."""
+    nx, ny, nz = shape if shape is not None else (L, L, L)
+    drho = 0.8
+    cfg = EKConfig(nx, ny, nz, precision=precision, G=G, dmu_plus=dmu, dmu_minus=dmu, drho_a=drho,
+                   E_ext=(0.0, 0.0, field), poisson_tol=1e-8, name=f"droplet_{nx}x{ny}x{nz}")
+    r = _rng(seed)
+    sh = (nz, ny, nx)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    d = np.sqrt((x - nx / 2 + 0.5) ** 2 + (y - ny / 2 + 0.5) ** 2 + (z - nz / 2 + 0.5) ** 2)
+    inside = 0.5 * (1.0 - np.tanh((d - min(nx, ny, nz) / 5.0) / width))
+    rho_a = 0.9 - 0.8 * inside + r.uniform(-1e-3, 1e-3, sh)
+    rho_b = 0.1 + 0.8 * inside + r.uniform(-1e-3, 1e-3, sh)
+    boltz = np.exp(-(dmu / drho) * rho_a)
+    n = salt * boltz / boltz.mean()
+    return cfg, EKInputs(rho_a, rho_b, n.copy(), n.copy())
+
+
+def replica_sweep(count=64, seed=4, precision="fp32", sizes=(32, 48, 64)):
+    """Replica sizes drawn from `sizes`; field E_z log-uniform in [1e-5, 1e-3], salt
+    log-uniform in [1e-4, 1e-2], G uniform in [3.0, 4.2]."""
+    r = _rng(seed)
+    out = []
+    for k in range(count):
+        L = int(r.choice(sizes))
+        field = float(10 ** r.uniform(-5, -3))
+        salt = float(10 ** r.uniform(-4, -2))
+        G = float(r.uniform(3.0, 4.2))
+        out.append(droplet(L, seed=seed * 1000 + k, precision=precision, field=field, salt=salt, G=G))
+    return out
+
+
+# ---------------------------------------------------------------------------------
 # Small deterministic fields used by the pins.
 # ---------------------------------------------------------------------------------
 def uniform(cfg, rho_a=0.5, rho_b=0.5, n_plus=1e-3, n_minus=1e-3):
