@@ -120,6 +120,48 @@ def cpu_baseline(cfg, inp, target_s=20.0):
                       f"untimed step), FP64, Poisson CG to 1e-12, {threads} OpenMP threads"}
 
 
+def run_batched(count, steps, cycles, seed=4):
+    """The replica sweep (droplets of sizes 32^3, 48^3, 64^3 with swept field, salt and
+    coupling; FP32) as one batch with one graph launch per step, and the same replicas
+    stepped one context after another."""
+    import torch
+    from paper_1712_08494_amd import ek
+    from paper_1712_08494_amd import workloads as wl
+    reps = wl.replica_sweep(count=count, seed=seed, precision="fp32")
+    cfgs = [c for c, _ in reps]
+    sites = sum(c.n_sites for c in cfgs)
+    log(f"batched: {count} replicas, {sites} sites, {cycles} V-cycles per step")
+    b = ek.EKBatch(cfgs, [i for _, i in reps], cycles=cycles)
+    b.step(3)
+    b.residuals()  # restart the worst-residual tracker after the start-up steps
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    tb = time.perf_counter() - t0
+    last, worst = b.residuals()
+    b.close()
+    log(f"batched: {1e3 * tb / steps:.3f} ms per step of all replicas")
+    sims = [ek.EKSim(c, i) for c, i in reps]
+    for sm in sims:
+        sm.step(3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for sm in sims:
+            sm.step(1)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    its = sum(sm.observables()["poisson_total"] for sm in sims) / (len(sims) * (steps + 3))
+    for sm in sims:
+        sm.close()
+    log(f"serial: {1e3 * ts / steps:.3f} ms per step of all replicas")
+    return {"workload": f"{count} droplet replicas of 32^3/48^3/64^3 (FP32)", "sites": sites, "steps": steps,
+            "v_cycles_per_step": cycles, "mlups": round(sites * steps / tb / 1e6, 2),
+            "serial_mlups": round(sites * steps / ts / 1e6, 2), "batched_over_serial": round(ts / tb, 3),
+            "serial_v_cycles_per_step": round(its, 2), "worst_rel_residual": float(worst.max()),
+            "last_rel_residual": float(last.max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +173,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run used for the FP32/FP64 speedup")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-serial replica sweep")
+    ap.add_argument("--batched-replicas", type=int, default=64)
+    ap.add_argument("--batched-steps", type=int, default=50)
+    ap.add_argument("--batched-cycles", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -178,6 +224,10 @@ def main():
         fp64 = N * max(10, args.steps // 2) / dt64 / 1e6
         log(f"gpu fp64: {1e3 * dt64 / max(10, args.steps // 2):.3f} ms/step")
 
+    batched = None
+    if not args.no_batched:
+        batched = run_batched(args.batched_replicas, args.batched_steps, args.batched_cycles)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, inp, args.cpu_seconds)
@@ -208,6 +258,7 @@ def main():
         "kernels": kernel_table,
         "fp64_mlups": round(fp64, 2) if fp64 else None,
         "fp32_fp64_speedup": round(mlups / fp64, 3) if fp64 else None,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

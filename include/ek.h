@@ -62,7 +62,8 @@ typedef struct ek_params {
     double tau;                 /* BGK relaxation time of both fluids (> 1/2) */
     double G;                   /* fluid/fluid Shan-Chen coupling G_ab */
     double rho0;                /* pseudopotential reference density: psi = rho0 (1 - exp(-rho/rho0)) */
-    double rho_ref[2];          /* FP32 deviation reference densities of a, b; <= 0: initial fluid mean */
+    double rho_ref[2];          /* FP32 deviation reference densities of a, b; <= 0: the harmonic mean
+                                   2 lo hi / (lo + hi) of the initial fluid range [lo, hi] */
     double D;                   /* ion diffusivity (both species) */
     double beta;                /* 1 / k_B T */
     double dmu[2];              /* Gibbs transfer energies of the cation and the anion */
@@ -240,7 +241,8 @@ ek_status ek_batch_step(struct ek_batch* b, int32_t nsteps);
 ek_status ek_batch_sync(struct ek_batch* b);
 
 /* Relative Poisson residual of every replica after the last step (last) and the largest
-   over all steps so far (worst); either may be NULL.  Synchronises. */
+   over the steps since the previous call (worst; the running maximum restarts with each
+   call); either may be NULL.  Synchronises. */
 ek_status ek_batch_residuals(struct ek_batch* b, double* last, double* worst);
 
 /* Borrow replica r's context for the export calls (ek_get_field, ek_get_populations,

@@ -573,18 +573,22 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     EK_TRY(build_geometry(c, parts, np, g));
     const bool colloids = np > 0;
     c->S.colloids = colloids;
-    // reference densities for the deviation storage: initial fluid means unless given
+    // Reference densities for the deviation storage, unless given.  A stored deviation
+    // rho - r carries a rounding error proportional to |rho - r|, so the relative error
+    // of rho scales with |rho - r| / rho.  Over the initial range [lo, hi] of a component
+    // the worst case of that ratio is smallest for the harmonic mean r = 2 lo hi / (lo + hi):
+    // near the mean for a nearly uniform fluid, near the minority value of a demixed one
+    // (where a plain mean would cost the minority phase two decades of precision).
     for (int s = 0; s < 2; ++s) {
         const double* r = s == 0 ? rho_a : rho_b;
-        double sum = 0.0;
-        long long cnt = 0;
+        double lo = INFINITY, hi = 0.0;
         for (unsigned i = 0; i < N; ++i) {
             if (g.flags[i] & 1) continue;
             if (!(r[i] > 0.0) || !std::isfinite(r[i])) return fail(c, EK_EINVAL, "fluid densities must be positive and finite");
-            sum += r[i];
-            ++cnt;
+            lo = std::min(lo, r[i]);
+            hi = std::max(hi, r[i]);
         }
-        c->S.rref[s] = p.rho_ref[s] > 0.0 ? p.rho_ref[s] : (cnt > 0 ? sum / cnt : 1.0);
+        c->S.rref[s] = p.rho_ref[s] > 0.0 ? p.rho_ref[s] : (hi > 0.0 ? 2.0 * lo * hi / (lo + hi) : 1.0);
     }
     for (unsigned i = 0; i < N; ++i)
         if (!std::isfinite(n_plus[i]) || !std::isfinite(n_minus[i])) return fail(c, EK_EINVAL, "ion densities must be finite");
@@ -1263,7 +1267,10 @@ extern "C" ek_status ek_batch_residuals(ek_batch* b, double* last, double* worst
     for (int r = 0; r < nr; ++r) {
         if (last) last[r] = b->hres[2 * r];
         if (worst) worst[r] = b->hres[2 * r + 1];
+        // the running maximum restarts with each read (outside any captured graph)
+        EB_HIP(hipMemsetAsync(b->reps[r]->scal + 5, 0, sizeof(double), b->st));
     }
+    EB_HIP(hipStreamSynchronize(b->st));
     return EK_OK;
 }
 
