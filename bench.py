@@ -52,6 +52,47 @@ def step_bytes(s):
     return 2 * 19 * 2 * s + 2 * 2 * s + 8
 
 
+# HBM traffic of the dominant kernel, from rocprofv3 counter runs (FETCH_SIZE, then
+# WRITE_SIZE, each scaled by what the same counter reads for a device copy of known size).
+# The summary records a hash of the kernel source it was taken on; once the source has
+# changed the figure no longer describes the kernel and is reported as null.
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1712_08494_amd", "csrc", "ek_kernels.hip")
+
+
+def traffic_summary_path(kernel, workload, n, precision):
+    return os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{n}_{precision}_hbm_traffic.md")
+
+
+def measured_traffic(kernel, workload, n, precision):
+    import hashlib
+    path = traffic_summary_path(kernel, workload, n, precision)
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].strip().split(": ", 1)
+                rec[k.strip("`")] = v.strip().strip("`")
+    with open(KERNEL_SOURCE, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    if rec.get("kernel_source_sha256") != sha:
+        return None, "kernel source changed since the counters were taken"
+    return float(rec["hbm_bytes_per_launch"]), path
+
+
+def copy_calibration(mib, repeats=3):
+    """Device-to-device copies of a known size, for scaling the HBM byte counters."""
+    import torch
+    x = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(repeats):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {repeats} copies of {mib} MiB")
+
+
 def build_workload(name, precision, n):
     from paper_1712_08494_amd import workloads as wl
     if name == "walls_interface":
@@ -86,6 +127,8 @@ def run_gpu(cfg, inp, steps, warmup, detail_steps=20):
         sim.set_timing(2)
         sim.step(detail_steps)
         timing["smooth"] = sim.timing()["smooth"]
+    else:
+        timing["smooth"] = (0.0, 0)
     sim.close()
     return t1 - t0, timing, ob0, ob1
 
@@ -177,6 +220,10 @@ def main():
     ap.add_argument("--batched-replicas", type=int, default=64)
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--batched-cycles", type=int, default=4)
+    ap.add_argument("--detail-steps", type=int, default=20,
+                    help="steps after the timed region with per-smoothing-pass events")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this size three times (byte-counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -190,7 +237,7 @@ def main():
 
     cfg, inp = build_workload(args.workload, args.precision, args.n)
     log(f"gpu {args.precision}: {cfg.name}, {args.warmup} warm-up + {args.steps} timed steps")
-    dt, timing, ob0, ob1 = run_gpu(cfg, inp, args.steps, args.warmup)
+    dt, timing, ob0, ob1 = run_gpu(cfg, inp, args.steps, args.warmup, args.detail_steps)
     log(f"gpu {args.precision}: {1e3 * dt / args.steps:.3f} ms/step")
     N = cfg.n_sites
     mlups = N * args.steps / dt / 1e6
@@ -215,6 +262,10 @@ def main():
             row["GBps"] = round(b * N / (tms / 1e3 / cnt) / 1e9, 1)
         kernel_table[k] = row
     sweeps = (ob1["poisson_total"] - ob0["poisson_total"]) / args.steps
+
+    if args.copy_calibration_mib:
+        copy_calibration(args.copy_calibration_mib)
+    traffic, traffic_src = measured_traffic(dom, args.workload, args.n, args.precision)
 
     fp64 = None
     if not args.no_fp64 and args.precision == "fp32":
@@ -251,7 +302,10 @@ def main():
                    "poisson_iterations_per_step": round(sweeps, 2),
                    "poisson_start_residual": ob1["poisson_rel0"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": round(traffic) if traffic else None, "traffic_unit": "bytes per launch",
+                     "traffic_bytes_per_site": round(traffic / N, 1) if traffic else None,
+                     "traffic_source": os.path.relpath(traffic_src, ROOT) if traffic else traffic_src,
                      "bytes_per_site": bpsite, "us_per_launch": round(avg_s * 1e6, 3)},
         "step_bytes_per_site": step_bytes(s),
         "step_effective_GBps": round(step_bytes(s) * N * args.steps / dt / 1e9, 1),
