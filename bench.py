@@ -205,6 +205,106 @@ def run_batched(count, steps, cycles, seed=4):
             "last_rel_residual": float(last.max())}
 
 
+def droplet_deformation(ra, rb, background=0.1):
+    """(b - a)/(b + a) from the second moments of the b excess about the box centre, a
+    along y and b along z; works on numpy arrays and on torch tensors."""
+    nz, ny, _ = rb.shape
+    if hasattr(rb, "device"):
+        import torch
+        z = torch.arange(nz, dtype=rb.dtype, device=rb.device)[:, None, None] - (nz - 1) / 2
+        y = torch.arange(ny, dtype=rb.dtype, device=rb.device)[None, :, None] - (ny - 1) / 2
+        sq = torch.sqrt
+        total = torch.sum
+    else:
+        import numpy as np
+        z = np.arange(nz)[:, None, None] - (nz - 1) / 2
+        y = np.arange(ny)[None, :, None] - (ny - 1) / 2
+        sq, total = np.sqrt, np.sum
+    w = rb - background
+    a = sq(total(w * y * y))
+    b = sq(total(w * z * z))
+    return (b - a) / (b + a)
+
+
+def run_adjoint(n=96, steps=500, every=50, fd=True):
+    """Reverse mode on the differentiation workload: a charged droplet (radius 20 in a
+    periodic 96^3 box, permittivity ratio 4, E_z = 5e-4, FP64), 500 steps with a
+    checkpoint every 50, and the gradient of its deformation with respect to (E_z,
+    eps_b/eps_a, G) by the adjoint sweep, next to central differences of GPU runs."""
+    import torch
+    from dataclasses import replace
+    from paper_1712_08494_amd import ek
+    from paper_1712_08494_amd import workloads as wl
+    cfg, inp = wl.droplet(n, seed=5, precision="fp64", field=5e-4, salt=1e-3, G=3.6, radius=20)
+    cfg.eps_b = 4.0 * cfg.eps_a
+    cfg.poisson_tol = 1e-10
+    N = cfg.n_sites
+    log(f"adjoint: droplet {n}^3, {steps} steps, checkpoints every {every}")
+    sim = ek.EKSim(cfg, inp)
+    sim.step(2)
+    sim.close()  # warm the library and the allocator
+    sim = ek.EKSim(cfg, inp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    sim.close()
+    sim = ek.EKSim(cfg, inp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.forward_checkpointed(steps, every)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    dev = torch.device("cuda")
+    ra = torch.from_numpy(sim.field("rho_a")).to(dev).requires_grad_(True)
+    rb = torch.from_numpy(sim.field("rho_b")).to(dev).requires_grad_(True)
+    D = droplet_deformation(ra, rb)
+    D.backward()
+    adj_f = torch.zeros((2, 19, N), dtype=torch.float64, device=dev)
+    adj_f[0] = ra.grad.reshape(1, N)
+    adj_f[1] = rb.grad.reshape(1, N)
+    adj_n = torch.zeros((2, N), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grad, _, _ = sim.adjoint(adj_f, adj_n, initial=False)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    sim.close()
+    g = {"E_z": grad["E_ext"][2], "eps_ratio": grad["eps_b"] * cfg.eps_a, "G": grad["G"]}
+    log(f"adjoint: forward {t_fwd:.2f} s (plain {t_plain:.2f} s), backward {t_bwd:.2f} s")
+    out = {"workload": f"droplet {n}^3 radius 20, eps ratio 4, E_z 5e-4, FP64, {steps} steps, checkpoint every "
+                       f"{every}, Poisson tolerance {cfg.poisson_tol:g}",
+           "objective": "deformation (b - a)/(b + a) from second moments of the b excess",
+           "D": float(D.detach()), "fwd_ms": round(1e3 * t_fwd, 1), "fwd_plain_ms": round(1e3 * t_plain, 1),
+           "bwd_ms": round(1e3 * t_bwd, 1), "bwd_fwd_ratio": round(t_bwd / t_fwd, 3),
+           "grad": {k: float(v) for k, v in g.items()}}
+    if fd:
+        def D_at(**kw):
+            s2 = ek.EKSim(replace(cfg, **kw), inp)
+            s2.step(steps)
+            v = float(droplet_deformation(s2.field("rho_a"), s2.field("rho_b")))
+            s2.close()
+            return v
+        fds, rels = {}, {}
+        for key, base, rel_h in (("E_z", cfg.E_ext[2], 1e-2), ("eps_ratio", 4.0, 1e-4), ("G", cfg.G, 1e-4)):
+            h = rel_h * base
+            vals = []
+            for sgn in (1, -1):
+                if key == "E_z":
+                    vals.append(D_at(E_ext=(0.0, 0.0, base + sgn * h)))
+                elif key == "eps_ratio":
+                    vals.append(D_at(eps_b=(base + sgn * h) * cfg.eps_a))
+                else:
+                    vals.append(D_at(G=base + sgn * h))
+            fds[key] = (vals[0] - vals[1]) / (2 * h)
+            rels[key] = abs(g[key] - fds[key]) / abs(fds[key]) if fds[key] != 0 else None
+            log(f"adjoint: dD/d{key} {g[key]:.6e} vs central difference (relative step {rel_h:g}) {fds[key]:.6e}")
+        out["fd"] = fds
+        out["fd_rel_err"] = rels
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +320,7 @@ def main():
     ap.add_argument("--batched-replicas", type=int, default=64)
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--batched-cycles", type=int, default=4)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode leg")
     ap.add_argument("--detail-steps", type=int, default=20,
                     help="steps after the timed region with per-smoothing-pass events")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -279,6 +380,10 @@ def main():
     if not args.no_batched:
         batched = run_batched(args.batched_replicas, args.batched_steps, args.batched_cycles)
 
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = run_adjoint()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, inp, args.cpu_seconds)
@@ -313,6 +418,7 @@ def main():
         "fp64_mlups": round(fp64, 2) if fp64 else None,
         "fp32_fp64_speedup": round(mlups / fp64, 3) if fp64 else None,
         "batched": batched,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -210,6 +210,38 @@ const char* ek_status_str(ek_status s);
 const char* ek_last_error(const struct ek_ctx* ctx);
 
 /* ---------------------------------------------------------------------------------
+ * Reverse mode: gradients of a scalar objective L of the state after T steps, with
+ * respect to the state before them and to the external field, the two fluid
+ * permittivities and the Shan-Chen coupling (Sec. II A-D).  The adjoint is the exact
+ * transpose of the discrete step (streaming, collision with the velocity shift, the
+ * Shan-Chen, ion-solvation, friction and Kelvin forces, the link fluxes with donor-cell
+ * advection, the central-difference field and the Poisson equation, whose potential is
+ * the implicit solution: its adjoint is one more solve with the same symmetric operator).
+ * FP64 contexts on periodic lattices without particles only (EK_EINVAL otherwise).
+ * --------------------------------------------------------------------------------- */
+
+/* Advance nsteps steps (as ek_step) keeping a device checkpoint of the state every
+   `every` steps and at the end, for a later ek_adjoint; replaces the checkpoints of any
+   earlier call.  Device memory: (nsteps / every + 2) x 42 N doubles.
+   Errors: EK_EINVAL (bad counts, unsupported context), EK_ENOMEM, EK_ENOCONV as ek_step. */
+ek_status ek_forward_ckpt(struct ek_ctx* ctx, int32_t nsteps, int32_t every);
+
+/* Reverse the last ek_forward_ckpt run.  Inputs (device pointers, FP64, read only):
+     adj_f  2 x 19 x N: dL/df of components a then b at the end of the run, each
+            velocity-major in the ek_lattice order, x fastest
+     adj_n  2 x N: dL/dn+ then dL/dn- at the end of the run
+   Outputs: grad (host, 6 doubles) = dL/d[E_ext x, E_ext y, E_ext z, eps_a, eps_b, G];
+   adj_f0, adj_n0 (device, optional, NULL to skip): the same sensitivities for the
+   state at the start of the run.  Each segment of `every` steps is recomputed from its
+   checkpoint (device memory `every` x 41 N doubles) and reversed step by step; every
+   reverse step solves the adjoint Poisson equation to the context's Poisson tolerance.
+   On return the context holds the state at the end of the run again.  Synchronises.
+   Errors: EK_ESTATE (no checkpointed run), EK_EINVAL, EK_ENOMEM, EK_ENOCONV (an
+   adjoint solve stopped at maxit; the gradient is still returned). */
+ek_status ek_adjoint(struct ek_ctx* ctx, const double* adj_f, const double* adj_n, double* grad, double* adj_f0,
+                     double* adj_n0);
+
+/* ---------------------------------------------------------------------------------
  * Batched replicas: many independent lattices (a parameter sweep) advanced together,
  * one graph launch per step for all of them.  Every replica is a full context of the
  * method above (Sec. II), periodic, without particles, with a lattice the multigrid

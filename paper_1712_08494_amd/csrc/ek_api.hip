@@ -89,7 +89,27 @@ struct ek_ctx {
     double tms[EK_T_COUNT] = {0};
     long long tcnt[EK_T_COUNT] = {0};
     bool in_batch = false;  // owned by a batch: stepping goes through the batch
+    // reverse mode (periodic FP64 contexts): checkpoints of the last checkpointed forward
+    // run and the adjoint fields
+    struct {
+        int T = 0, K = 0, nck = 0;  // steps, checkpoint interval, checkpoints (every K steps and the end)
+        double* ck = nullptr;       // nck x kCkVals N doubles
+        size_t ck_cap = 0;          // checkpoints the allocation holds
+        std::vector<double> ck_rate;
+        std::vector<long long> ck_steps, ck_ptotal;
+        double* seg = nullptr;      // K x kSegVals N doubles: the states of one segment
+        int seg_cap = 0;
+        double* buf = nullptr;      // adjoint fields (kAdjVals N doubles)
+        double* gred = nullptr;     // gradient partials per workgroup
+        bool valid = false;
+    } adj;
 };
+
+// Checkpoint: populations of a and b (2 x 19 N), stored ions (2 N), the potential and the
+// previous potential (the warm start of the next solve).  Segment state: populations, ions
+// and the potential solved in that step.  Adjoint fields: dL/df (two parities x two
+// components x 19 N), dL/dn (two parities x 2 N) and the intermediates of AdjFields.
+constexpr size_t kCkVals = 2 * kQ + 4, kSegVals = 2 * kQ + 3, kAdjVals = 4 * kQ + 4 + 6 + 3 + 3 + 2 + 3 + 2 + 1 + 1 + 1;
 
 #define EK_HIP(call)                                                                             \
     do {                                                                                         \
@@ -122,6 +142,17 @@ static ek_status dalloc(ek_ctx* c, void** ptr, size_t bytes) {
         ek_status s_ = (x);         \
         if (s_ != EK_OK) return s_; \
     } while (0)
+
+static void dfree(ek_ctx* c, void* ptr, size_t bytes) {
+    if (!ptr) return;
+    for (size_t k = 0; k < c->allocs.size(); ++k)
+        if (c->allocs[k] == ptr) {
+            c->allocs.erase(c->allocs.begin() + (long)k);
+            break;
+        }
+    (void)hipFree(ptr);
+    c->bytes -= bytes;
+}
 
 // ------------------------------------------------------------------------------------
 // Timing (HIP events on the context's stream)
@@ -874,6 +905,228 @@ static ek_status observe_impl(ek_ctx* c, ek_obs* o) {
         }
     }
     return o->nonfinite ? fail(c, EK_ENONFINITE, "non-finite populations or ion densities") : EK_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Reverse mode: checkpointed forward run and the adjoint sweep (periodic FP64 contexts).
+// ------------------------------------------------------------------------------------
+static ek_status adj_check(ek_ctx* c) {
+    if (!c || !c->phi) return EK_ESTATE;
+    if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: no reverse mode");
+    if (c->esz != 8) return fail(c, EK_EINVAL, "reverse mode needs an FP64 context");
+    if (c->S.walls || c->np > 0) return fail(c, EK_EINVAL, "reverse mode covers periodic lattices without particles");
+    return EK_OK;
+}
+
+static ek_status copy_d(ek_ctx* c, void* dst, const void* src, size_t n) {
+    EK_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+    return EK_OK;
+}
+
+static ek_status save_ck(ek_ctx* c, int slot) {
+    const size_t N = c->N;
+    double* b = c->adj.ck + (size_t)slot * kCkVals * N;
+    EK_TRY(copy_d(c, b, c->f[c->cur][0], kQ * N));
+    EK_TRY(copy_d(c, b + kQ * N, c->f[c->cur][1], kQ * N));
+    EK_TRY(copy_d(c, b + 2 * kQ * N, c->n[c->cur][0], N));
+    EK_TRY(copy_d(c, b + (2 * kQ + 1) * N, c->n[c->cur][1], N));
+    EK_TRY(copy_d(c, b + (2 * kQ + 2) * N, c->phi, N));
+    EK_TRY(copy_d(c, b + (2 * kQ + 3) * N, c->phi_prev, N));
+    c->adj.ck_rate[slot] = c->rate;
+    c->adj.ck_steps[slot] = c->steps;
+    c->adj.ck_ptotal[slot] = c->ptotal;
+    return EK_OK;
+}
+
+static ek_status load_ck(ek_ctx* c, int slot) {
+    const size_t N = c->N;
+    const double* b = c->adj.ck + (size_t)slot * kCkVals * N;
+    EK_TRY(copy_d(c, c->f[c->cur][0], b, kQ * N));
+    EK_TRY(copy_d(c, c->f[c->cur][1], b + kQ * N, kQ * N));
+    EK_TRY(copy_d(c, c->n[c->cur][0], b + 2 * kQ * N, N));
+    EK_TRY(copy_d(c, c->n[c->cur][1], b + (2 * kQ + 1) * N, N));
+    EK_TRY(copy_d(c, c->phi, b + (2 * kQ + 2) * N, N));
+    EK_TRY(copy_d(c, c->phi_prev, b + (2 * kQ + 3) * N, N));
+    c->rate = c->adj.ck_rate[slot];
+    c->steps = c->adj.ck_steps[slot];
+    c->ptotal = c->adj.ck_ptotal[slot];
+    return EK_OK;
+}
+
+extern "C" ek_status ek_forward_ckpt(ek_ctx* c, int32_t nsteps, int32_t every) {
+    EK_TRY(adj_check(c));
+    if (nsteps < 1 || every < 1) return fail(c, EK_EINVAL, "nsteps and every must be >= 1");
+    auto& A = c->adj;
+    const int nseg = (nsteps + every - 1) / every;
+    const size_t need = (size_t)nseg + 1;
+    const size_t N = c->N;
+    if (A.ck_cap < need) {
+        dfree(c, A.ck, A.ck_cap * kCkVals * N * sizeof(double));
+        A.ck = nullptr;
+        A.ck_cap = 0;
+        EK_TRY(dalloc(c, (void**)&A.ck, need * kCkVals * N * sizeof(double)));
+        A.ck_cap = need;
+    }
+    A.ck_rate.assign(need, 0.0);
+    A.ck_steps.assign(need, 0);
+    A.ck_ptotal.assign(need, 0);
+    A.valid = false;
+    ek_status worst = EK_OK;
+    for (int g = 0; g < nseg; ++g) {
+        EK_TRY(save_ck(c, g));
+        const ek_status st = step_impl<double>(c, std::min(every, nsteps - g * every));
+        if (st == EK_ENOCONV)
+            worst = st;
+        else if (st != EK_OK)
+            return st;
+    }
+    EK_TRY(save_ck(c, nseg));
+    A.T = nsteps;
+    A.K = every;
+    A.nck = (int)need;
+    A.valid = true;
+    return worst;
+}
+
+extern "C" ek_status ek_adjoint(ek_ctx* c, const double* adj_f, const double* adj_n, double* grad, double* adj_f0,
+                                double* adj_n0) {
+    EK_TRY(adj_check(c));
+    auto& A = c->adj;
+    if (!A.valid) return fail(c, EK_ESTATE, "no checkpointed forward run (ek_forward_ckpt) to reverse");
+    if (!adj_f || !adj_n || !grad) return fail(c, EK_EINVAL, "adj_f, adj_n and grad are required");
+    const size_t N = c->N;
+    if (A.seg_cap < A.K) {
+        dfree(c, A.seg, (size_t)A.seg_cap * kSegVals * N * sizeof(double));
+        A.seg = nullptr;
+        A.seg_cap = 0;
+        EK_TRY(dalloc(c, (void**)&A.seg, (size_t)A.K * kSegVals * N * sizeof(double)));
+        A.seg_cap = A.K;
+    }
+    if (!A.buf) {
+        EK_TRY(dalloc(c, (void**)&A.buf, kAdjVals * N * sizeof(double)));
+        EK_TRY(dalloc(c, (void**)&A.gred, (size_t)c->nblk * kRedSlots * sizeof(double)));
+    }
+    // adjoint field layout inside A.buf
+    double* p = A.buf;
+    double* lf[2][2];
+    double* ln[2][2];
+    for (int par = 0; par < 2; ++par)
+        for (int k = 0; k < 2; ++k) {
+            lf[par][k] = p;
+            p += kQ * N;
+        }
+    for (int par = 0; par < 2; ++par)
+        for (int k = 0; k < 2; ++k) {
+            ln[par][k] = p;
+            p += N;
+        }
+    AdjFields AF{};
+    AF.aS = p; p += 6 * N;
+    AF.aF = p; p += 3 * N;
+    AF.aE = p; p += 3 * N;
+    AF.arho = p; p += 2 * N;
+    AF.au = p; p += 3 * N;
+    AF.an = p; p += 2 * N;
+    AF.aeps = p; p += N;
+    AF.rhs = p; p += N;
+    double* mu = p; p += N;
+    AF.mu = mu;
+    AF.gred = A.gred;
+
+    EK_HIP(hipMemsetAsync(A.gred, 0, (size_t)c->nblk * kRedSlots * sizeof(double), c->st));
+    EK_HIP(hipMemsetAsync(mu, 0, N * sizeof(double), c->st));
+    EK_TRY(copy_d(c, lf[0][0], adj_f, kQ * N));
+    EK_TRY(copy_d(c, lf[0][1], adj_f + kQ * N, kQ * N));
+    EK_TRY(copy_d(c, ln[0][0], adj_n, N));
+    EK_TRY(copy_d(c, ln[0][1], adj_n + N, N));
+    const double rate_fwd = c->rate;
+    int la = 0;
+    ek_status worst = EK_OK;
+    const int nseg = A.nck - 1;
+    for (int g = nseg - 1; g >= 0; --g) {
+        const int t0 = g * A.K, n = std::min(A.K, A.T - t0);
+        // recompute the segment, keeping each step's state and the potential solved in it
+        EK_TRY(load_ck(c, g));
+        for (int k = 0; k < n; ++k) {
+            double* b = A.seg + (size_t)k * kSegVals * N;
+            EK_TRY(copy_d(c, b, c->f[c->cur][0], kQ * N));
+            EK_TRY(copy_d(c, b + kQ * N, c->f[c->cur][1], kQ * N));
+            EK_TRY(copy_d(c, b + 2 * kQ * N, c->n[c->cur][0], N));
+            EK_TRY(copy_d(c, b + (2 * kQ + 1) * N, c->n[c->cur][1], N));
+            const ek_status st = step_impl<double>(c, 1);
+            if (st != EK_OK && st != EK_ENOCONV) return st;
+            EK_TRY(copy_d(c, b + (2 * kQ + 2) * N, c->phi, N));
+        }
+        // reverse the steps of the segment
+        for (int k = n - 1; k >= 0; --k) {
+            double* b = A.seg + (size_t)k * kSegVals * N;
+            Fields<double> F = fields<double>(c);
+            F.f[0] = b;
+            F.f[1] = b + kQ * N;
+            F.n[0] = b + 2 * kQ * N;
+            F.n[1] = b + (2 * kQ + 1) * N;
+            F.phi = b + (2 * kQ + 2) * N;
+            {
+                Timer tm(c, EK_T_MOMENTS);
+                launch_moments<double>(c->S, F, c->nblk, c->st);
+            }
+            {
+                Timer tm(c, EK_T_FORCE);
+                launch_force<double>(c->S, F, c->st);
+            }
+            for (int k2 = 0; k2 < 2; ++k2) {
+                AF.lf[k2] = lf[la][k2];
+                AF.lfo[k2] = lf[la ^ 1][k2];
+                AF.ln[k2] = ln[la][k2];
+                AF.lno[k2] = ln[la ^ 1][k2];
+            }
+            launch_adj_force(c->S, F, AF, c->st);
+            launch_adj_links(c->S, F, AF, c->st);
+            launch_adj_rhs(c->S, F, AF, c->st);
+            launch_source_mean(c->S, c->red, c->nblk, c->scal, c->st);
+            EK_HIP(hipGetLastError());
+            // adjoint Poisson equation M mu = dL/dphi with the same solver: the source and
+            // the unknown are swapped in for the charge and the potential
+            void* q_fwd = c->q;
+            double* phi_fwd = c->phi;
+            c->q = AF.rhs;
+            c->phi = mu;
+            const ek_status ps = poisson_solve<double>(c, c->p.poisson_tol, c->p.poisson_maxit, nullptr, nullptr);
+            c->q = q_fwd;
+            c->phi = phi_fwd;
+            if (ps == EK_ENOCONV)
+                worst = ps;
+            else if (ps != EK_OK)
+                return ps;
+            launch_adj_final(c->S, F, AF, c->st);
+            EK_HIP(hipGetLastError());
+            la ^= 1;
+        }
+    }
+    // parameter gradient: fixed-order sum of the per-workgroup partials
+    launch_reduce(A.gred, c->nblk, kAdjSlots, nullptr, c->stage, c->st);
+    double g[kAdjSlots];
+    EK_HIP(hipMemcpyAsync(g, c->stage, sizeof(g), hipMemcpyDeviceToHost, c->st));
+    if (adj_f0) {
+        EK_TRY(copy_d(c, adj_f0, lf[la][0], kQ * N));
+        EK_TRY(copy_d(c, adj_f0 + kQ * N, lf[la][1], kQ * N));
+    }
+    if (adj_n0) {
+        EK_TRY(copy_d(c, adj_n0, ln[la][0], N));
+        EK_TRY(copy_d(c, adj_n0 + N, ln[la][1], N));
+    }
+    // leave the context at the end of the forward run
+    EK_TRY(load_ck(c, A.nck - 1));
+    c->rate = rate_fwd;
+    EK_HIP(hipStreamSynchronize(c->st));
+    grad[0] = g[kAdjEx];
+    grad[1] = g[kAdjEx + 1];
+    grad[2] = g[kAdjEx + 2];
+    grad[3] = g[kAdjEa] + 0.5 * g[kAdjEbar];
+    grad[4] = g[kAdjEb] + 0.5 * g[kAdjEbar];
+    grad[5] = g[kAdjG];
+    if (worst == EK_ENOCONV) c->err = "an adjoint Poisson solve stopped at maxit above the tolerance";
+    return worst;
 }
 
 extern "C" ek_status ek_observables(ek_ctx* c, ek_obs* out) {

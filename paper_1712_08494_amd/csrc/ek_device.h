@@ -1,0 +1,107 @@
+// Device helpers shared by the step kernels (ek_kernels.hip) and the adjoint kernels
+// (ek_adjoint.hip): workgroup-to-site mapping, periodic neighbour offsets, the
+// central-difference field and the deterministic FP64 block reduction.
+#pragma once
+
+#include "ek_internal.h"
+#include "ek_lattice.h"
+
+namespace ek {
+
+// Workgroups are dispatched round-robin over the 8 XCDs (XCD = blockIdx % 8).  Give XCD k
+// the contiguous block range [k * nb/8, (k+1) * nb/8) so its L2 holds a slab of planes.
+__device__ __forceinline__ unsigned xcd_linear() {
+    const unsigned nb = gridDim.x;  // multiple of 8 (site_blocks)
+    const unsigned b = blockIdx.x;
+    const unsigned lb = (b & 7u) * (nb >> 3) + (b >> 3);
+    return lb * blockDim.x + threadIdx.x;
+}
+
+struct Nbr {
+    int xm, xp, ym, yp, zm, zp;  // index offsets to the -1/+1 neighbour along each axis (periodic)
+};
+
+__device__ __forceinline__ Nbr make_nbr(int x, int y, int z, const Scalars& S) {
+    Nbr o;
+    o.xm = x == 0 ? S.nx - 1 : -1;
+    o.xp = x == S.nx - 1 ? -(S.nx - 1) : 1;
+    o.ym = y == 0 ? (S.ny - 1) * S.nx : -S.nx;
+    o.yp = y == S.ny - 1 ? -(S.ny - 1) * S.nx : S.nx;
+    o.zm = z == 0 ? (S.nz - 1) * S.nxy : -S.nxy;
+    o.zp = z == S.nz - 1 ? -(S.nz - 1) * S.nxy : S.nxy;
+    return o;
+}
+
+__device__ __forceinline__ int offset_of(const Nbr& o, int d) {
+    return (vx(d) < 0 ? o.xm : (vx(d) > 0 ? o.xp : 0)) + (vy(d) < 0 ? o.ym : (vy(d) > 0 ? o.yp : 0)) +
+           (vz(d) < 0 ? o.zm : (vz(d) > 0 ? o.zp : 0));
+}
+
+__device__ __forceinline__ int wrapc(int a, int n) {
+    return n == 1 ? 0 : (a < 0 ? a + n : (a >= n ? a - n : a));
+}
+
+__device__ __forceinline__ double phi_at(const double* phi, int x, int y, int z, const Scalars& S) {
+    return phi[wrapc(x, S.nx) + S.nx * (wrapc(y, S.ny) + S.ny * wrapc(z, S.nz))];
+}
+
+// Component k of E = -grad(phi) + E_ext at site (x, y, z): central differences, one-sided
+// for the normal component on the wall layers.
+__device__ __forceinline__ double efield(int k, int x, int y, int z, const double* phi, const Scalars& S) {
+    double e;
+    if (k == 0) {
+        e = -0.5 * (phi_at(phi, x + 1, y, z, S) - phi_at(phi, x - 1, y, z, S));
+    } else if (k == 1) {
+        e = -0.5 * (phi_at(phi, x, y + 1, z, S) - phi_at(phi, x, y - 1, z, S));
+    } else {
+        if (S.walls && z == 0)
+            e = -(phi_at(phi, x, y, 1, S) - phi_at(phi, x, y, 0, S));
+        else if (S.walls && z == S.nz - 1)
+            e = -(phi_at(phi, x, y, z, S) - phi_at(phi, x, y, z - 1, S));
+        else
+            e = -0.5 * (phi_at(phi, x, y, z + 1, S) - phi_at(phi, x, y, z - 1, S));
+    }
+    return e + S.E_ext[k];
+}
+
+__device__ __forceinline__ double efield_sq(int x, int y, int z, const double* phi, const Scalars& S) {
+    double a = efield(0, x, y, z, phi, S), b = efield(1, x, y, z, phi, S), c = efield(2, x, y, z, phi, S);
+    return a * a + b * b + c * c;
+}
+
+__device__ __forceinline__ bool wall_layer(int z, const Scalars& S) { return S.walls && (z == 0 || z == S.nz - 1); }
+
+// ------------------------------------------------------------------------------------
+// FP64 block reduction of NV values (sums, or maxima where is_max) into red[blockIdx].
+// ------------------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NV], const bool (&is_max)[NV], double* red,
+                                                   unsigned slot) {
+    __shared__ double sm[NV][kBlock / 64];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double a = v[k];
+#pragma unroll
+        for (int s = 32; s > 0; s >>= 1) {
+            double b = __shfl_down(a, s, 64);
+            a = is_max[k] ? fmax(a, b) : a + b;
+        }
+        v[k] = a;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sm[k][wid] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double a = sm[k][0];
+            for (int w = 1; w < kBlock / 64; ++w) a = is_max[k] ? fmax(a, sm[k][w]) : a + sm[k][w];
+            red[(size_t)slot * kRedSlots + k] = a;
+        }
+    }
+}
+
+}  // namespace ek

@@ -72,6 +72,30 @@ struct MGLevel {
 
 unsigned site_blocks(unsigned n);
 
+// Reverse-mode (adjoint) fields of a periodic FP64 context for one reverse step: the
+// sensitivities of a scalar objective L to the step's inputs and intermediates.  All
+// arrays are N-major doubles.
+struct AdjFields {
+    const double* lf[2];  // dL/df at t+1 of components a, b (19 N each, velocity-major)
+    double* lfo[2];       // dL/df at t
+    const double* ln[2];  // dL/dn+, dL/dn- at t+1
+    double* lno[2];       // the same at t
+    double* aS;           // 6 N: dL/d(sum_d w_d chi_a(i+d) c_d), dL/d(sum_d w_d psi_a(i+d) c_d)
+    double* aF;           // 3 N: dL/d(non-Shan-Chen force: friction + Kelvin + body)
+    double* aE;           // 3 N: dL/dE
+    double* arho;         // 2 N: dL/drho^a, dL/drho^b (partial sums)
+    double* au;           // 3 N: dL/du' (pre-force velocity)
+    double* an;           // 2 N: dL/dn+, dL/dn- at t (partial sums)
+    double* aeps;         // N: dL/deps (partial sum)
+    double* rhs;          // N: dL/dphi, the right-hand side of the adjoint Poisson equation
+    const double* mu;     // N: adjoint potential, M mu = dL/dphi projected to zero mean
+    double* gred;         // kRedSlots doubles per workgroup: parameter-gradient partials
+};
+
+// Slots of AdjFields::gred: dL/dE_ext (x, y, z), dL/deps_a and dL/deps_b through the site
+// permittivity, dL/d(eps_bar) of the Kelvin force, dL/dG.
+constexpr int kAdjEx = 0, kAdjEa = 3, kAdjEb = 4, kAdjEbar = 5, kAdjG = 6, kAdjSlots = 7;
+
 // Batched replicas: per-replica descriptors in device memory and block tables mapping
 // each workgroup of a batched launch to (replica, workgroup within the replica).
 constexpr int kMaxLevels = 8;
@@ -144,5 +168,10 @@ void launch_ion_species(const T* ion_s, const T* ion_c, double* dst, unsigned n,
 template <typename T> void launch_to_double(const T* src, double* dst, unsigned n, double add, hipStream_t st);
 template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, int k, double* dst, hipStream_t st);
 template <typename T> void launch_upload(T* dst, const double* src, unsigned n, hipStream_t st);
+
+void launch_adj_force(const Scalars& S, const Fields<double>& F, const AdjFields& A, hipStream_t st);
+void launch_adj_links(const Scalars& S, const Fields<double>& F, const AdjFields& A, hipStream_t st);
+void launch_adj_rhs(const Scalars& S, const Fields<double>& F, const AdjFields& A, hipStream_t st);
+void launch_adj_final(const Scalars& S, const Fields<double>& F, const AdjFields& A, hipStream_t st);
 
 }  // namespace ek

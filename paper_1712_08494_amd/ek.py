@@ -57,7 +57,8 @@ class EKTiming(ctypes.Structure):
 EXPORTS = ["ek_lattice", "ek_init", "ek_step", "ek_poisson", "ek_observables", "ek_get_field",
            "ek_get_populations", "ek_get_particles", "ek_device_bytes", "ek_set_timing", "ek_get_timing",
            "ek_destroy", "ek_status_str", "ek_last_error", "ek_batch_init", "ek_batch_step", "ek_batch_sync",
-           "ek_batch_residuals", "ek_batch_replica", "ek_batch_destroy", "ek_batch_last_error"]
+           "ek_batch_residuals", "ek_batch_replica", "ek_batch_destroy", "ek_batch_last_error",
+           "ek_forward_ckpt", "ek_adjoint"]
 
 _lib = None
 
@@ -127,6 +128,10 @@ def load(path=LIB_PATH):
     L.ek_batch_destroy.restype = ctypes.c_int32
     L.ek_batch_last_error.argtypes = [vp]
     L.ek_batch_last_error.restype = ctypes.c_char_p
+    L.ek_forward_ckpt.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.ek_forward_ckpt.restype = ctypes.c_int32
+    L.ek_adjoint.argtypes = [vp, vp, vp, dp, vp, vp]
+    L.ek_adjoint.restype = ctypes.c_int32
     _lib = L
     return L
 
@@ -288,6 +293,31 @@ class EKSim:
         self._check(load().ek_get_timing(self._h, ctypes.byref(t)), "ek_get_timing")
         return {name: (t.ms[k], t.count[k]) for k, name in enumerate(TIMING_CLASSES)}
 
+    def forward_checkpointed(self, nsteps, every, allow_noconv=False):
+        """nsteps steps keeping a checkpoint every `every` steps, for adjoint()."""
+        return self._check(load().ek_forward_ckpt(self._h, int(nsteps), int(every)), "ek_forward_ckpt",
+                           (EK_ENOCONV,) if allow_noconv else ())
+
+    def adjoint(self, adj_f, adj_n, initial=True):
+        """Reverse the last forward_checkpointed run.  adj_f (2, 19, N) and adj_n (2, N) are
+        float64 tensors on the GPU holding dL/d(populations) and dL/d(n+, n-) at its end.
+        Returns (gradient dict, dL/df at the start or None, dL/dn at the start or None)."""
+        import torch
+        for t in (adj_f, adj_n):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise TypeError("adj_f and adj_n must be contiguous float64 GPU tensors")
+        if adj_f.numel() != 2 * 19 * self.N or adj_n.numel() != 2 * self.N:
+            raise ValueError("adj_f must hold 2 x 19 x N values and adj_n 2 x N")
+        f0 = torch.empty_like(adj_f) if initial else None
+        n0 = torch.empty_like(adj_n) if initial else None
+        g = np.zeros(6)
+        st = load().ek_adjoint(self._h, ctypes.c_void_p(adj_f.data_ptr()), ctypes.c_void_p(adj_n.data_ptr()), _dp(g),
+                               ctypes.c_void_p(f0.data_ptr()) if initial else None,
+                               ctypes.c_void_p(n0.data_ptr()) if initial else None)
+        self._check(st, "ek_adjoint", (EK_ENOCONV,))
+        grad = {"E_ext": g[0:3].copy(), "eps_a": g[3], "eps_b": g[4], "G": g[5]}
+        return grad, f0, n0
+
 
 class _Borrowed(EKSim):
     """A replica context owned by a batch: export calls only."""
@@ -360,3 +390,49 @@ class EKBatch:
         if st != EK_OK:
             raise EKError(st, "ek_batch_replica")
         return _Borrowed(h, self.cfgs[r])
+
+
+def _ek_run_function():
+    import torch
+
+    class EKRun(torch.autograd.Function):
+        """T steps of the method as a differentiable function of (E_z, eps_b / eps_a, G).
+        forward(params, cfg, inputs, nsteps, every) runs a checkpointed forward pass of an
+        FP64 periodic context built from cfg with those three parameters replaced, and
+        returns the fluid densities rho^a, rho^b at the end as (nz, ny, nx) GPU tensors;
+        backward runs the library's adjoint sweep."""
+
+        @staticmethod
+        def forward(ctx, params, cfg, inputs, nsteps, every):
+            from dataclasses import replace
+            ez, ratio, G = (float(v) for v in params.detach().cpu().tolist())
+            c2 = replace(cfg, E_ext=(cfg.E_ext[0], cfg.E_ext[1], ez), eps_b=ratio * cfg.eps_a, G=G, precision="fp64")
+            sim = EKSim(c2, inputs)
+            sim.forward_checkpointed(nsteps, every)
+            ctx.sim, ctx.eps_a = sim, cfg.eps_a
+            dev = torch.device("cuda")
+            return (torch.from_numpy(sim.field("rho_a")).to(dev), torch.from_numpy(sim.field("rho_b")).to(dev))
+
+        @staticmethod
+        def backward(ctx, g_ra, g_rb):
+            sim = ctx.sim
+            N = sim.N
+            dev = torch.device("cuda")
+            adj_f = torch.zeros((2, 19, N), dtype=torch.float64, device=dev)
+            # rho^s = sum_d f^s_d: the same sensitivity for every population of a component
+            if g_ra is not None:
+                adj_f[0] = g_ra.reshape(1, N).to(torch.float64)
+            if g_rb is not None:
+                adj_f[1] = g_rb.reshape(1, N).to(torch.float64)
+            adj_n = torch.zeros((2, N), dtype=torch.float64, device=dev)
+            grad, _, _ = sim.adjoint(adj_f, adj_n, initial=False)
+            sim.close()
+            out = torch.tensor([grad["E_ext"][2], grad["eps_b"] * ctx.eps_a, grad["G"]], dtype=torch.float64)
+            return out, None, None, None, None
+
+    return EKRun
+
+
+def ek_run(params, cfg, inputs, nsteps, every):
+    """Differentiable run: see EKRun (params = tensor([E_z, eps_b / eps_a, G]))."""
+    return _ek_run_function().apply(params, cfg, inputs, nsteps, every)

@@ -243,8 +243,8 @@ def colloids(n=256, seed=3, precision="fp32", count=200, radius=4.0, shape=None,
 # ---------------------------------------------------------------------------------
 # Workload 4: a sweep of independent droplet replicas of uneven size.
 # ---------------------------------------------------------------------------------
-def droplet(L, seed=4, precision="fp32", field=1e-4, salt=1e-3, G=3.6, dmu=-4.0, width=2.0, shape=None):
-    """A drop of fluid b (radius L/5) in fluid a, centred in a periodic cube: inside
+def droplet(L, seed=4, precision="fp32", field=1e-4, salt=1e-3, G=3.6, dmu=-4.0, width=2.0, shape=None, radius=None):
+    """A drop of fluid b (radius L/5 unless given) in fluid a, centred in a periodic cube: inside
     (rho_a, rho_b) = (0.1, 0.9), outside swapped, tanh profile of width 2; both ion
     species Boltzmann-partitioned by the solvation energy dmu rho_a / drho_a (same
     energy for both, so the fluid stays neutral), mean salt `salt`; field along z."""
@@ -256,7 +256,8 @@ def droplet(L, seed=4, precision="fp32", field=1e-4, salt=1e-3, G=3.6, dmu=-4.0,
     sh = (nz, ny, nx)
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     d = np.sqrt((x - nx / 2 + 0.5) ** 2 + (y - ny / 2 + 0.5) ** 2 + (z - nz / 2 + 0.5) ** 2)
-    inside = 0.5 * (1.0 - np.tanh((d - min(nx, ny, nz) / 5.0) / width))
+    R = min(nx, ny, nz) / 5.0 if radius is None else float(radius)
+    inside = 0.5 * (1.0 - np.tanh((d - R) / width))
     rho_a = 0.9 - 0.8 * inside + r.uniform(-1e-3, 1e-3, sh)
     rho_b = 0.1 + 0.8 * inside + r.uniform(-1e-3, 1e-3, sh)
     boltz = np.exp(-(dmu / drho) * rho_a)

@@ -1,0 +1,233 @@
+"""Reverse mode (ek_forward_ckpt / ek_adjoint) against central finite differences of the
+forward runs, on the GPU and on the FP64 oracle.
+
+The state test is the classic adjoint identity: for L = <lam_f, f(T)> + <lam_n, n(T)>
+with random lam, dL along a random perturbation of the initial densities and ions equals
+<dL/dx(0), dx(0)>.  The library builds the initial populations as f_d = w_d rho (at rest),
+so the density component of dL/dx(0) is sum_d w_d dL/df_d.  The cases switch the pieces
+of the step on one after another, so a failing transpose names its term."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1712_08494_amd import ek
+from paper_1712_08494_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    ek.load()
+    yield
+
+
+def _case(name, n=16, seed=21):
+    """Periodic FP64 mixture with small noise, drifting under a uniform body force; the
+    named physics switched on.  The donor-cell advection is piecewise linear in the
+    velocity (upwind switch at u = 0), so finite differences are only meaningful where no
+    link velocity changes sign: the drift keeps every component of the velocity one-signed
+    while the noise and the ion forces stay an order of magnitude smaller."""
+    cfg, inp = wl.mixture_noise(shape=(n, n, n), precision="fp64", G=0.0)
+    cfg.poisson_tol = 1e-13
+    cfg.name = name
+    cfg.body_accel = (3e-3, 2.5e-3, 2e-3)
+    r = np.random.Generator(np.random.PCG64(seed))
+    sh = inp.rho_a.shape
+    inp.rho_a = 0.5 + 2e-4 * r.uniform(-1, 1, sh)
+    inp.rho_b = 0.5 + 2e-4 * r.uniform(-1, 1, sh)
+    # a charge pattern so that potential and field are not trivial
+    inp.n_plus = 1e-3 * (1.0 + 0.05 * r.uniform(-1, 1, sh))
+    inp.n_minus = 1e-3 * (1.0 + 0.05 * r.uniform(-1, 1, sh))
+    inp.n_minus *= inp.n_plus.sum() / inp.n_minus.sum()
+    if name in ("shan_chen", "solvation", "kelvin", "tau"):
+        cfg.G = 3.0
+    if name in ("solvation", "kelvin", "tau"):
+        cfg.dmu_plus, cfg.dmu_minus, cfg.drho_a = 2.0, -1.0, 0.5
+    if name in ("kelvin", "tau"):
+        cfg.eps_b = 2.0 * cfg.eps_a
+        cfg.E_ext = (2e-4, -1e-4, 5e-4)
+    if name == "tau":
+        cfg.tau = 0.8
+    return cfg, inp
+
+
+def _objective(sim, lam_f, lam_n):
+    f = np.stack([sim.populations(0), sim.populations(1)]).reshape(2, 19, -1)
+    n = np.stack([sim.field("n_plus"), sim.field("n_minus")]).reshape(2, -1)
+    return float(np.sum(lam_f * f) + np.sum(lam_n * n))
+
+
+def _run(cfg, inp, T):
+    sim = ek.EKSim(cfg, inp)
+    sim.step(T)
+    return sim
+
+
+def _perturbed(inp, d, h):
+    out = wl.EKInputs(inp.rho_a + h * d[0], inp.rho_b + h * d[1], inp.n_plus + h * d[2], inp.n_minus + h * d[3])
+    return out
+
+
+CASES = ["bgk", "shan_chen", "solvation", "kelvin", "tau"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_state_adjoint_dot_product(name):
+    import torch
+    cfg, inp = _case(name)
+    T, K = 5, 2
+    print(f"adjoint dot-product test: {name} 16^3, {T} steps, checkpoints every {K}", flush=True)
+    N = cfg.n_sites
+    r = np.random.Generator(np.random.PCG64(7))
+    lam_f = r.standard_normal((2, 19, N))
+    lam_n = r.standard_normal((2, N)) * 1e2
+    sim = ek.EKSim(cfg, inp)
+    sim.forward_checkpointed(T, K)
+    umin = min(sim.field(k).min() for k in ("ux", "uy", "uz"))
+    print(f"  smallest velocity component at the end: {umin:.3e}", flush=True)
+    dev = torch.device("cuda")
+    grad, f0, n0 = sim.adjoint(torch.from_numpy(lam_f).to(dev), torch.from_numpy(lam_n).to(dev))
+    L_end = _objective(sim, lam_f, lam_n)  # the context is back at the end state
+    sim.close()
+    _, w = ek.lattice()
+    f0 = f0.cpu().numpy().reshape(2, 19, N)
+    n0 = n0.cpu().numpy().reshape(2, N)
+    g_rho = np.einsum("d,cdn->cn", w, f0)
+    sh = inp.rho_a.shape
+    d = [r.uniform(-1, 1, sh) * 1e-3, r.uniform(-1, 1, sh) * 1e-3, r.uniform(-1, 1, sh) * 1e-5,
+         r.uniform(-1, 1, sh) * 1e-5]
+    pred = float(np.sum(g_rho[0] * d[0].ravel()) + np.sum(g_rho[1] * d[1].ravel()) + np.sum(n0[0] * d[2].ravel()) +
+                 np.sum(n0[1] * d[3].ravel()))
+    h = 1e-3
+    Lp = _objective(_run(cfg, _perturbed(inp, d, h), T), lam_f, lam_n)
+    Lm = _objective(_run(cfg, _perturbed(inp, d, -h), T), lam_f, lam_n)
+    L0 = _objective(_run(cfg, inp, T), lam_f, lam_n)
+    fd = (Lp - Lm) / (2 * h)
+    rel = abs(pred - fd) / abs(fd)
+    print(f"  <dL/dx0, dx> = {pred:.12e}  central FD = {fd:.12e}  rel {rel:.2e}", flush=True)
+    assert abs(L_end - L0) <= 1e-12 * abs(L0)
+    assert rel < 1e-6
+
+    # parameter gradients
+    for key, idx in (("E_z", None), ("eps_b", "eps_b"), ("G", "G")):
+        if key == "E_z" and name not in ("kelvin", "tau"):
+            continue
+        if key == "eps_b" and name not in ("kelvin", "tau"):
+            continue
+        if key == "G" and cfg.G == 0.0:
+            continue
+
+        def with_param(v):
+            from dataclasses import replace
+            if key == "E_z":
+                return replace(cfg, E_ext=(cfg.E_ext[0], cfg.E_ext[1], v))
+            return replace(cfg, **{idx: v})
+
+        base = cfg.E_ext[2] if key == "E_z" else getattr(cfg, idx)
+        # L is nearly quadratic in E_z (linear migration, quadratic Kelvin force) and weakly
+        # sensitive to it: a larger step keeps the difference above rounding
+        hp = (1e-2 if key == "E_z" else 1e-4) * abs(base)
+        Lp = _objective(_run(with_param(base + hp), inp, T), lam_f, lam_n)
+        Lm = _objective(_run(with_param(base - hp), inp, T), lam_f, lam_n)
+        fdp = (Lp - Lm) / (2 * hp)
+        ad = grad["E_ext"][2] if key == "E_z" else grad[idx]
+        relp = abs(ad - fdp) / abs(fdp)
+        print(f"  dL/d{key}: adjoint {ad:.10e}  FD {fdp:.10e}  rel {relp:.2e}", flush=True)
+        assert relp < 1e-5, (key, ad, fdp)
+
+
+def _deformation(ra, rb, background):
+    """Droplet deformation (b - a)/(b + a) from the second moments of the b excess about
+    the box centre: a along y, b along z."""
+    nz, ny, nx = rb.shape
+    z = np.arange(nz)[:, None, None] - (nz - 1) / 2
+    y = np.arange(ny)[None, :, None] - (ny - 1) / 2
+    w = rb - background
+    a = np.sqrt(np.sum(w * y * y))
+    b = np.sqrt(np.sum(w * z * z))
+    return (b - a) / (b + a)
+
+
+def _droplet(n, field):
+    cfg, inp = wl.droplet(n, seed=5, precision="fp64", field=field, salt=1e-3, G=3.6)
+    cfg.eps_b = 4.0 * cfg.eps_a
+    cfg.poisson_tol = 1e-13
+    return cfg, inp
+
+
+def test_droplet_deformation_gradient_vs_oracle():
+    """dD/d(E_z, eps_b/eps_a, G) of a charged droplet (permittivity ratio 4) after 32
+    steps: the adjoint through the autograd wrapper against central differences of the
+    FP64 oracle.  Over so few steps the deformation responds weakly to the field, so the
+    field is 1e-2 (the full-size run uses 5e-4 over 500 steps), and a uniform drift keeps
+    the outer fluid off the upwind switch of the donor-cell advection at u = 0, where
+    finite differences are not derivatives."""
+    import torch
+    n, T, K = 16, 32, 8
+    cfg, inp = _droplet(n, 1e-2)
+    cfg.body_accel = (1e-3, 8e-4, 6e-4)
+    print(f"droplet {n}^3, {T} steps: adjoint vs oracle finite differences", flush=True)
+    p0 = np.array([cfg.E_ext[2], cfg.eps_b / cfg.eps_a, cfg.G])
+    params = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    ra, rb = ek.ek_run(params, cfg, inp, T, K)
+    nz = n
+    z = torch.arange(nz, dtype=torch.float64, device=ra.device)[:, None, None] - (nz - 1) / 2
+    y = torch.arange(n, dtype=torch.float64, device=ra.device)[None, :, None] - (n - 1) / 2
+    w = rb - 0.1
+    a = torch.sqrt(torch.sum(w * y * y))
+    b = torch.sqrt(torch.sum(w * z * z))
+    D = (b - a) / (b + a)
+    D.backward()
+    g = params.grad.numpy()
+
+    def oracle_D(p):
+        from dataclasses import replace
+        c2 = replace(cfg, E_ext=(cfg.E_ext[0], cfg.E_ext[1], p[0]), eps_b=p[1] * cfg.eps_a, G=p[2],
+                     poisson_tol=1e-13)
+        o = orc.Oracle(c2, inp)
+        o.step(T)
+        return _deformation(o.field("rho_a"), o.field("rho_b"), 0.1)
+
+    D0 = oracle_D(p0)
+    Dv = float(D.detach())
+    print(f"  D = {Dv:.12e} (library), {D0:.12e} (oracle)", flush=True)
+    assert abs(D0 - Dv) < 1e-8 * abs(D0) + 1e-12, (D0, Dv)
+    for k, name in enumerate(("E_z", "eps_b/eps_a", "G")):
+        fds = []
+        for rel_h in (1e-4, 1e-3):
+            h = rel_h * abs(p0[k])
+            pp, pm = p0.copy(), p0.copy()
+            pp[k] += h
+            pm[k] -= h
+            fds.append((oracle_D(pp) - oracle_D(pm)) / (2 * h))
+        rels = [abs(g[k] - fd) / abs(fd) for fd in fds]
+        print(f"  dD/d{name}: adjoint {g[k]:.10e}  oracle FD (h 1e-4) {fds[0]:.10e} rel {rels[0]:.2e}, "
+              f"(h 1e-3) {fds[1]:.10e} rel {rels[1]:.2e}", flush=True)
+        assert min(rels) < 1e-5, (name, g[k], fds)
+
+
+def test_adjoint_rejects_unsupported():
+    import torch
+    cfg, inp = wl.walls_interface(shape=(16, 16, 16), precision="fp64")
+    sim = ek.EKSim(cfg, inp)
+    with pytest.raises(ek.EKError) as e:
+        sim.forward_checkpointed(2, 1)
+    assert e.value.status == ek.EK_EINVAL
+    sim.close()
+    cfg, inp = _case("bgk", n=8)
+    cfg.precision = "fp32"
+    sim = ek.EKSim(cfg, inp)
+    with pytest.raises(ek.EKError):
+        sim.forward_checkpointed(2, 1)
+    sim.close()
+    cfg.precision = "fp64"
+    sim = ek.EKSim(cfg, inp)
+    z = torch.zeros(2 * 19 * cfg.n_sites, dtype=torch.float64, device="cuda")
+    with pytest.raises(ek.EKError) as e:
+        sim.adjoint(z, torch.zeros(2 * cfg.n_sites, dtype=torch.float64, device="cuda"))
+    assert e.value.status == ek.EK_ESTATE
+    sim.close()
