@@ -208,15 +208,15 @@ def run_batched(count, steps, cycles, seed=4):
 def droplet_deformation(ra, rb, background=0.1):
     """(b - a)/(b + a) from the second moments of the b excess about the box centre, a
     along y and b along z; works on numpy arrays and on torch tensors."""
+    import numpy as np
     nz, ny, _ = rb.shape
-    if hasattr(rb, "device"):
+    if not isinstance(rb, np.ndarray):
         import torch
         z = torch.arange(nz, dtype=rb.dtype, device=rb.device)[:, None, None] - (nz - 1) / 2
         y = torch.arange(ny, dtype=rb.dtype, device=rb.device)[None, :, None] - (ny - 1) / 2
         sq = torch.sqrt
         total = torch.sum
     else:
-        import numpy as np
         z = np.arange(nz)[:, None, None] - (nz - 1) / 2
         y = np.arange(ny)[None, :, None] - (ny - 1) / 2
         sq, total = np.sqrt, np.sum
@@ -262,8 +262,9 @@ def run_adjoint(n=96, steps=500, every=50, fd=True):
     D = droplet_deformation(ra, rb)
     D.backward()
     adj_f = torch.zeros((2, 19, N), dtype=torch.float64, device=dev)
-    adj_f[0] = ra.grad.reshape(1, N)
-    adj_f[1] = rb.grad.reshape(1, N)
+    for comp, t in ((0, ra), (1, rb)):
+        if t.grad is not None:
+            adj_f[comp] = t.grad.reshape(1, N)
     adj_n = torch.zeros((2, N), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

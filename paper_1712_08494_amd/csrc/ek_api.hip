@@ -82,6 +82,9 @@ struct ek_ctx {
     // multigrid (levels[0] is the lattice itself and holds no arrays)
     std::vector<MGLevel> mg;
     double mg_coarse_omega = 1.0;
+    // V-cycle shape: red-black sweeps before and after the coarse correction on the
+    // lattice and on the coarse grids, and sweeps on the coarsest grid
+    int mg_fine_pre = 2, mg_fine_post = 2, mg_pre = 3, mg_post = 3, mg_coarsest = 20;
     // timing: 0 off, 1 kernel classes, 2 classes and every lattice-level smoothing pass
     int timing = 0;
     std::vector<TimeRec> recs;
@@ -406,21 +409,23 @@ static void vcycle(ek_ctx* c, const Fields<T>& F) {
             }
         }
     };
-    const int sweeps = 2;
     for (int g = 0; g <= last_gpu; ++g) {  // downward leg: smooth grid g, restrict to grid g+1
-        for (int s = 0; s < sweeps; ++s) smooth(g);
+        const int pre = g == 0 ? c->mg_fine_pre : c->mg_pre;
+        for (int s = 0; s < pre; ++s) smooth(g);
         if (g == 0)
             launch_mg_restrict_fine<T>(c->S, F, c->mg[0], c->st);
         else
             launch_mg_restrict(c->mg[g - 1], c->mg[g], c->st);
     }
-    launch_mg_tail(tail_mid ? c->mg[nl - 2] : c->mg[nl - 1], c->mg[nl - 1], tail_mid, 20, c->mg_coarse_omega, c->st);
+    launch_mg_tail(tail_mid ? c->mg[nl - 2] : c->mg[nl - 1], c->mg[nl - 1], tail_mid, c->mg_coarsest,
+                   c->mg_coarse_omega, c->st);
     for (int g = last_gpu; g >= 0; --g) {  // upward leg: interpolate from grid g+1, smooth grid g
         if (g == 0)
             launch_mg_prolong_fine<T>(c->S, F, c->mg[0], c->st);
         else
             launch_mg_prolong(c->mg[g], c->mg[g - 1], c->st);
-        for (int s = 0; s < sweeps; ++s) smooth(g);
+        const int post = g == 0 ? c->mg_fine_post : c->mg_post;
+        for (int s = 0; s < post; ++s) smooth(g);
     }
 }
 
@@ -1127,6 +1132,24 @@ extern "C" ek_status ek_adjoint(ek_ctx* c, const double* adj_f, const double* ad
     grad[5] = g[kAdjG];
     if (worst == EK_ENOCONV) c->err = "an adjoint Poisson solve stopped at maxit above the tolerance";
     return worst;
+}
+
+extern "C" ek_status ek_set_multigrid(ek_ctx* c, int32_t fine_pre, int32_t fine_post, int32_t coarse_pre,
+                                      int32_t coarse_post, int32_t coarsest_sweeps) {
+    if (!c || !c->phi) return EK_ESTATE;
+    if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: its cycle is fixed by the batch");
+    const int v[5] = {fine_pre, fine_post, coarse_pre, coarse_post, coarsest_sweeps};
+    for (int k = 0; k < 5; ++k)
+        if (v[k] < 0 || v[k] > 64) return fail(c, EK_EINVAL, "sweep counts must be in 0..64");
+    if (fine_pre + fine_post == 0 || coarsest_sweeps == 0)
+        return fail(c, EK_EINVAL, "the lattice needs a sweep per cycle and the coarsest grid at least one");
+    c->mg_fine_pre = fine_pre;
+    c->mg_fine_post = fine_post;
+    c->mg_pre = coarse_pre;
+    c->mg_post = coarse_post;
+    c->mg_coarsest = coarsest_sweeps;
+    c->rate = -1.0;  // the convergence rate is re-estimated
+    return EK_OK;
 }
 
 extern "C" ek_status ek_observables(ek_ctx* c, ek_obs* out) {

@@ -58,7 +58,7 @@ EXPORTS = ["ek_lattice", "ek_init", "ek_step", "ek_poisson", "ek_observables", "
            "ek_get_populations", "ek_get_particles", "ek_device_bytes", "ek_set_timing", "ek_get_timing",
            "ek_destroy", "ek_status_str", "ek_last_error", "ek_batch_init", "ek_batch_step", "ek_batch_sync",
            "ek_batch_residuals", "ek_batch_replica", "ek_batch_destroy", "ek_batch_last_error",
-           "ek_forward_ckpt", "ek_adjoint"]
+           "ek_forward_ckpt", "ek_adjoint", "ek_set_multigrid"]
 
 _lib = None
 
@@ -132,6 +132,8 @@ def load(path=LIB_PATH):
     L.ek_forward_ckpt.restype = ctypes.c_int32
     L.ek_adjoint.argtypes = [vp, vp, vp, dp, vp, vp]
     L.ek_adjoint.restype = ctypes.c_int32
+    L.ek_set_multigrid.argtypes = [vp] + [ctypes.c_int32] * 5
+    L.ek_set_multigrid.restype = ctypes.c_int32
     _lib = L
     return L
 
@@ -292,6 +294,11 @@ class EKSim:
         t = EKTiming()
         self._check(load().ek_get_timing(self._h, ctypes.byref(t)), "ek_get_timing")
         return {name: (t.ms[k], t.count[k]) for k, name in enumerate(TIMING_CLASSES)}
+
+    def set_multigrid(self, fine_pre=2, fine_post=2, coarse_pre=3, coarse_post=3, coarsest=20):
+        """V-cycle shape: sweeps before/after the correction on the lattice and the coarse grids."""
+        self._check(load().ek_set_multigrid(self._h, fine_pre, fine_post, coarse_pre, coarse_post, coarsest),
+                    "ek_set_multigrid")
 
     def forward_checkpointed(self, nsteps, every, allow_noconv=False):
         """nsteps steps keeping a checkpoint every `every` steps, for adjoint()."""
