@@ -287,20 +287,26 @@ def run_adjoint(n=96, steps=500, every=50, fd=True):
             v = float(droplet_deformation(s2.field("rho_a"), s2.field("rho_b")))
             s2.close()
             return v
+        # central differences at several relative steps: the step the workload names
+        # (1e-4) and smaller ones, which show where the difference quotient settles
         fds, rels = {}, {}
-        for key, base, rel_h in (("E_z", cfg.E_ext[2], 1e-2), ("eps_ratio", 4.0, 1e-4), ("G", cfg.G, 1e-4)):
-            h = rel_h * base
-            vals = []
-            for sgn in (1, -1):
-                if key == "E_z":
-                    vals.append(D_at(E_ext=(0.0, 0.0, base + sgn * h)))
-                elif key == "eps_ratio":
-                    vals.append(D_at(eps_b=(base + sgn * h) * cfg.eps_a))
-                else:
-                    vals.append(D_at(G=base + sgn * h))
-            fds[key] = (vals[0] - vals[1]) / (2 * h)
-            rels[key] = abs(g[key] - fds[key]) / abs(fds[key]) if fds[key] != 0 else None
-            log(f"adjoint: dD/d{key} {g[key]:.6e} vs central difference (relative step {rel_h:g}) {fds[key]:.6e}")
+        for key, base, steps_rel in (("E_z", cfg.E_ext[2], (1e-2, 1e-4)), ("eps_ratio", 4.0, (1e-4, 1e-5)),
+                                     ("G", cfg.G, (1e-4, 1e-5, 1e-6))):
+            fds[key], rels[key] = {}, {}
+            for rel_h in steps_rel:
+                h = rel_h * base
+                vals = []
+                for sgn in (1, -1):
+                    if key == "E_z":
+                        vals.append(D_at(E_ext=(0.0, 0.0, base + sgn * h)))
+                    elif key == "eps_ratio":
+                        vals.append(D_at(eps_b=(base + sgn * h) * cfg.eps_a))
+                    else:
+                        vals.append(D_at(G=base + sgn * h))
+                fd = (vals[0] - vals[1]) / (2 * h)
+                fds[key][f"{rel_h:g}"] = fd
+                rels[key][f"{rel_h:g}"] = abs(g[key] - fd) / abs(fd) if fd != 0 else None
+                log(f"adjoint: dD/d{key} {g[key]:.6e} vs central difference (relative step {rel_h:g}) {fd:.6e}")
         out["fd"] = fds
         out["fd_rel_err"] = rels
     return out
