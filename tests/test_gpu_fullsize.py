@@ -1,0 +1,117 @@
+"""The remaining workloads at their full sizes: 256^3 with 200 resolved charged spheres,
+the 64-replica batched sweep, and the 96^3 differentiation droplet.  Where the oracle
+cannot follow at that size the checks are properties that hold at any size
+(conservation, neutrality, geometry totals, determinism); the 32^3 replicas of the batch are checked against the oracle."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1712_08494_amd import ek
+from paper_1712_08494_amd import workloads as wl
+from tests.parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    ek.load()
+    yield
+
+
+def test_colloids_256_properties():
+    cfg, inp = wl.colloids(n=256, precision="fp32")
+    print(f"colloids 256^3, {inp.particles.shape[0]} spheres of radius 4, FP32", flush=True)
+    parts = inp.particles
+    runs = []
+    for rep in range(2):
+        sim = ek.EKSim(cfg, inp)
+        if rep == 0:
+            psis = sim.field("psi_s")
+            vol = 4.0 / 3.0 * np.pi * parts[:, 6] ** 3
+            # sub-cell counting approximates each sphere's volume (error ~ surface / h)
+            assert abs(psis.sum() - vol.sum()) < 0.03 * vol.sum(), (psis.sum(), vol.sum())
+            o0 = sim.observables()
+            # the colloid charge is spread over its sites and balanced by a uniform anion
+            # excess, of which set-up removes the share inside the spheres (ions start in
+            # proportion to the fluid fraction): the net charge is that share of sum Q
+            solid_share = psis.sum() / cfg.n_sites
+            assert abs(o0["sum_q"] - solid_share * parts[:, 7].sum()) < 1e-3 * parts[:, 7].sum(), o0["sum_q"]
+        sim.step(10)
+        o = sim.observables()
+        p = sim.particles()
+        runs.append((sim.field("n_plus"), sim.field("rho_a"), sim.field("phi"), p))
+        if rep == 0:
+            for k in ("sum_rho_a", "sum_rho_b", "sum_n_plus", "sum_n_minus"):
+                assert abs(o[k] - o0[k]) <= 2e-6 * abs(o0[k]), (k, o0[k], o[k])
+            assert o["nonfinite"] == 0 and o["negative_ions"] == 0
+            # the spheres move (fluid forces) but stay put on the lattice scale over 10 steps
+            assert np.all(np.isfinite(p))
+            d = p[:, 0:3] - parts[:, 0:3]
+            d -= np.array([cfg.nx, cfg.ny, cfg.nz]) * np.round(d / np.array([cfg.nx, cfg.ny, cfg.nz]))
+            assert np.abs(d).max() < 0.5
+        sim.close()
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+
+
+def test_batch_64_replicas_32cubed_vs_oracle():
+    """The benchmark's replica sweep (64 droplets of 32^3, 48^3 and 64^3, FP32, 4 V-cycles per
+    step) for 5 steps; every 32^3 replica against its own FP64 oracle run."""
+    reps = wl.replica_sweep(count=64, seed=4, precision="fp32")
+    print(f"batch of 64 replicas ({sum(c.n_sites for c, _ in reps)} sites)", flush=True)
+    b = ek.EKBatch([c for c, _ in reps], [i for _, i in reps], cycles=4)
+    b.step(5)
+    b.sync()
+    last, worst = b.residuals()
+    print(f"  residuals: last max {last.max():.2e}, worst max {worst.max():.2e}", flush=True)
+    assert np.all(last < 1e-5)
+    small = [r for r, (c, _) in enumerate(reps) if c.nx == 32]
+    assert len(small) >= 5
+    for r in small:
+        cfg, inp = reps[r]
+        o = orc.Oracle(cfg, inp)
+        o.step(5)
+        errs = compare(b.replica(r), o, "fp32", f"replica {r}")
+        print(f"  replica {r} (32^3, E {cfg.E_ext[2]:.1e}, G {cfg.G:.2f}): {errs}", flush=True)
+    b.close()
+
+
+def test_adjoint_droplet_96_short():
+    """The differentiation droplet (96^3, radius 20, permittivity ratio 4, E_z 5e-4, FP64) over
+    60 steps with checkpoints every 20: the adjoint gradient of the deformation against
+    central differences of GPU runs."""
+    import torch
+    from dataclasses import replace
+    import bench
+    cfg, inp = wl.droplet(96, seed=5, precision="fp64", field=5e-4, salt=1e-3, G=3.6, radius=20)
+    cfg.eps_b = 4.0 * cfg.eps_a
+    cfg.poisson_tol = 1e-11
+    T, K = 60, 20
+    print(f"droplet 96^3, {T} steps: adjoint vs finite differences", flush=True)
+    params = torch.tensor([cfg.E_ext[2], 4.0, cfg.G], dtype=torch.float64, requires_grad=True)
+    ra, rb = ek.ek_run(params, cfg, inp, T, K)
+    D = bench.droplet_deformation(ra, rb)
+    D.backward()
+    g = params.grad.numpy()
+
+    def D_at(**kw):
+        s = ek.EKSim(replace(cfg, **kw), inp)
+        s.step(T)
+        v = float(bench.droplet_deformation(s.field("rho_a"), s.field("rho_b")))
+        s.close()
+        return v
+
+    checks = (("E_z", 0, 1e-2, lambda v: dict(E_ext=(0.0, 0.0, v))),
+              ("eps_b/eps_a", 1, 1e-3, lambda v: dict(eps_b=v * cfg.eps_a)),
+              ("G", 2, 1e-4, lambda v: dict(G=v)))
+    p0 = params.detach().numpy()
+    for name, k, rel_h, kw in checks:
+        h = rel_h * p0[k]
+        fd = (D_at(**kw(p0[k] + h)) - D_at(**kw(p0[k] - h))) / (2 * h)
+        rel = abs(g[k] - fd) / abs(fd)
+        print(f"  dD/d{name}: adjoint {g[k]:.8e}  FD {fd:.8e}  rel {rel:.2e}", flush=True)
+        assert rel < 1e-4, (name, g[k], fd)
