@@ -418,7 +418,7 @@ static void vcycle(ek_ctx* c, const Fields<T>& F) {
             launch_mg_restrict(c->mg[g - 1], c->mg[g], c->st);
     }
     launch_mg_tail(tail_mid ? c->mg[nl - 2] : c->mg[nl - 1], c->mg[nl - 1], tail_mid, c->mg_coarsest,
-                   c->mg_coarse_omega, c->st);
+                   c->mg_coarse_omega, c->mg_pre, c->mg_post, c->st);
     for (int g = last_gpu; g >= 0; --g) {  // upward leg: interpolate from grid g+1, smooth grid g
         if (g == 0)
             launch_mg_prolong_fine<T>(c->S, F, c->mg[0], c->st);

@@ -137,7 +137,8 @@ template <typename T> void launch_mg_restrict_fine(const Scalars& S, const Field
 void launch_mg_restrict(const MGLevel& f, const MGLevel& c, hipStream_t st);
 template <typename T> void launch_mg_prolong_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st);
 void launch_mg_prolong(const MGLevel& c, const MGLevel& f, hipStream_t st);
-void launch_mg_tail(const MGLevel& mid, const MGLevel& coarse, int has_mid, int iters, double omega, hipStream_t st);
+void launch_mg_tail(const MGLevel& mid, const MGLevel& coarse, int has_mid, int iters, double omega, int mid_pre,
+                    int mid_post, hipStream_t st);
 
 template <typename T> void launch_moments(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
 template <typename T> void launch_virtual(const Scalars& S, const Fields<T>& F, hipStream_t st);

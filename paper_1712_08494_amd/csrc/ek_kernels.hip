@@ -81,36 +81,61 @@ template <typename T> __device__ __forceinline__ T eps_fluid(T ra, T rb, const S
 // Sums (or maxima) of nvals values over nblk partial records, fixed order: deterministic.
 constexpr int kRedThreads = 1024;
 
+// Each thread accumulates whole records (the values of a workgroup's record are
+// adjacent, so they load together; a few records are in flight at once) in increasing
+// record order; wave64 shuffles and a sum over the waves in order finish the job.  Fixed
+// order throughout: deterministic.  NV is the record width read (at least nvals).
+template <int NV, int kFly>
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ red, unsigned nblk, int nvals,
                                                         const int* is_max_d, double* __restrict__ out) {
-    __shared__ double sm[kRedThreads];
-    for (int k = 0; k < nvals; ++k) {
-        const bool mx = is_max_d ? is_max_d[k] != 0 : false;
-        double a = mx ? -1e300 : 0.0;
-        unsigned b = threadIdx.x;
-        for (; b + 3 * kRedThreads < nblk; b += 4 * kRedThreads) {
-            const double v0 = red[(size_t)b * kRedSlots + k], v1 = red[(size_t)(b + kRedThreads) * kRedSlots + k];
-            const double v2 = red[(size_t)(b + 2 * kRedThreads) * kRedSlots + k];
-            const double v3 = red[(size_t)(b + 3 * kRedThreads) * kRedSlots + k];
-            a = mx ? fmax(fmax(a, v0), fmax(v1, fmax(v2, v3))) : a + ((v0 + v1) + (v2 + v3));
+    __shared__ double sm[NV][kRedThreads / 64];
+    bool mx[NV];
+    double a[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        mx[k] = k < nvals && is_max_d ? is_max_d[k] != 0 : false;
+        a[k] = mx[k] ? -1e300 : 0.0;
+    }
+    for (unsigned b0 = threadIdx.x; b0 < nblk; b0 += kFly * kRedThreads) {
+        double v[kFly][NV];
+#pragma unroll
+        for (int j = 0; j < kFly; ++j) {
+            const unsigned b = b0 + j * kRedThreads;
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                v[j][k] = (k < nvals && b < nblk) ? red[(size_t)b * kRedSlots + k] : (mx[k] ? -1e300 : 0.0);
         }
-        for (; b < nblk; b += kRedThreads) {
-            const double v = red[(size_t)b * kRedSlots + k];
-            a = mx ? fmax(a, v) : a + v;
+#pragma unroll
+        for (int j = 0; j < kFly; ++j)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) a[k] = mx[k] ? fmax(a[k], v[j][k]) : a[k] + v[j][k];
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double v = a[k];
+#pragma unroll
+        for (int s2 = 32; s2 > 0; s2 >>= 1) {
+            const double o = __shfl_down(v, s2, 64);
+            v = mx[k] ? fmax(v, o) : v + o;
         }
-        sm[threadIdx.x] = a;
-        __syncthreads();
-        for (int s2 = kRedThreads / 2; s2 > 0; s2 >>= 1) {
-            if ((int)threadIdx.x < s2) sm[threadIdx.x] = mx ? fmax(sm[threadIdx.x], sm[threadIdx.x + s2]) : sm[threadIdx.x] + sm[threadIdx.x + s2];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[k] = sm[0];
-        __syncthreads();
+        if ((threadIdx.x & 63) == 0) sm[k][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nvals) {
+        const int k = threadIdx.x;
+        double v = sm[k][0];
+        const bool m = is_max_d ? is_max_d[k] != 0 : false;
+        for (int w = 1; w < kRedThreads / 64; ++w) v = m ? fmax(v, sm[k][w]) : v + sm[k][w];
+        out[k] = v;
     }
 }
 
 void launch_reduce(const double* red, unsigned nblk, int nvals, const int* is_max, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, st, red, nblk, nvals, is_max, out);
+    if (nvals <= 3)
+        hipLaunchKernelGGL((k_reduce<3, 4>), dim3(1), dim3(kRedThreads), 0, st, red, nblk, nvals, is_max, out);
+    else
+        hipLaunchKernelGGL((k_reduce<kRedSlots, 2>), dim3(1), dim3(kRedThreads), 0, st, red, nblk, nvals, is_max,
+                           out);
 }
 
 // ------------------------------------------------------------------------------------
@@ -244,21 +269,27 @@ template <typename T> void launch_virtual(const Scalars& S, const Fields<T>& F, 
 
 // Mean of the Poisson source over the domain: (sum q + wall charges) / sites.
 __device__ void source_mean_body(const Scalars& S, const double* __restrict__ red, unsigned nblk, double* scal) {
-    __shared__ double sm[kRedThreads];
+    __shared__ double sm[kRedThreads / 64];
     double a = 0.0;
-    unsigned b = threadIdx.x;
-    for (; b + 3 * kRedThreads < nblk; b += 4 * kRedThreads)
-        a += (red[(size_t)b * kRedSlots] + red[(size_t)(b + kRedThreads) * kRedSlots]) +
-             (red[(size_t)(b + 2 * kRedThreads) * kRedSlots] + red[(size_t)(b + 3 * kRedThreads) * kRedSlots]);
-    for (; b < nblk; b += kRedThreads) a += red[(size_t)b * kRedSlots];
-    sm[threadIdx.x] = a;
-    __syncthreads();
-    for (int s2 = kRedThreads / 2; s2 > 0; s2 >>= 1) {
-        if ((int)threadIdx.x < s2) sm[threadIdx.x] += sm[threadIdx.x + s2];
-        __syncthreads();
+    for (unsigned b0 = threadIdx.x; b0 < nblk; b0 += 4 * kRedThreads) {
+        double v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const unsigned b = b0 + j * kRedThreads;
+            v[j] = b < nblk ? red[(size_t)b * kRedSlots] : 0.0;
+        }
+        a += v[0];
+        a += v[1];
+        a += v[2];
+        a += v[3];
     }
+#pragma unroll
+    for (int s2 = 32; s2 > 0; s2 >>= 1) a += __shfl_down(a, s2, 64);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = a;
+    __syncthreads();
     if (threadIdx.x == 0) {
         double tot = sm[0];
+        for (int w = 1; w < kRedThreads / 64; ++w) tot += sm[w];
         if (S.walls) tot += (S.sigma0 + S.sigma1) * (double)S.nxy;
         scal[0] = tot / (double)S.ndomain;
     }
@@ -719,7 +750,8 @@ __device__ void tail_load_coeffs(const MGLevel& G, C* ax, C* ay, C* az) {
     }
 }
 
-__device__ void tail_body(const MGLevel& M, const MGLevel& Cg, int has_mid, int coarse_iters, double coarse_omega) {
+__device__ void tail_body(const MGLevel& M, const MGLevel& Cg, int has_mid, int coarse_iters, double coarse_omega,
+                          int mid_pre = 2, int mid_post = 2) {
     extern __shared__ double lds[];
     if (has_mid) {
         double* phim = lds;
@@ -746,7 +778,7 @@ __device__ void tail_body(const MGLevel& M, const MGLevel& Cg, int has_mid, int 
         tail_inverse_diagonal(Lm);
         tail_inverse_diagonal(Lc);
         __syncthreads();
-        tail_sweeps(Lm, 2, 1.0);
+        tail_sweeps(Lm, mid_pre, 1.0);
         // restriction: sum of the eight children's residuals
         for (unsigned t = threadIdx.x; t < Cg.n; t += blockDim.x) {
             const int I = t % Cg.nx, r = t / Cg.nx, J = r % Cg.ny, K = r / Cg.ny;
@@ -784,7 +816,7 @@ __device__ void tail_body(const MGLevel& M, const MGLevel& Cg, int has_mid, int 
             phim[t] += v;
         }
         __syncthreads();
-        tail_sweeps(Lm, 2, 1.0);
+        tail_sweeps(Lm, mid_post, 1.0);
         for (unsigned t = threadIdx.x; t < M.n; t += blockDim.x) M.phi[t] = phim[t];
     } else {
         double* phic = lds;
@@ -808,8 +840,8 @@ __device__ void tail_body(const MGLevel& M, const MGLevel& Cg, int has_mid, int 
 }
 
 __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MGLevel M, MGLevel Cg, int has_mid, int coarse_iters,
-                                                         double coarse_omega) {
-    tail_body(M, Cg, has_mid, coarse_iters, coarse_omega);
+                                                         double coarse_omega, int mid_pre, int mid_post) {
+    tail_body(M, Cg, has_mid, coarse_iters, coarse_omega, mid_pre, mid_post);
 }
 
 size_t mg_tail_lds_bytes() {
@@ -818,9 +850,10 @@ size_t mg_tail_lds_bytes() {
     return with_mid > coarse_only ? with_mid : coarse_only;
 }
 
-void launch_mg_tail(const MGLevel& mid, const MGLevel& coarse, int has_mid, int iters, double omega, hipStream_t st) {
+void launch_mg_tail(const MGLevel& mid, const MGLevel& coarse, int has_mid, int iters, double omega, int mid_pre,
+                    int mid_post, hipStream_t st) {
     hipLaunchKernelGGL(k_mg_tail, dim3(1), dim3(kTailThreads), mg_tail_lds_bytes(), st, mid, coarse, has_mid, iters,
-                       omega);
+                       omega, mid_pre, mid_post);
 }
 
 // ------------------------------------------------------------------------------------

@@ -105,13 +105,26 @@ def test_adjoint_droplet_96_short():
         s.close()
         return v
 
-    checks = (("E_z", 0, 1e-2, lambda v: dict(E_ext=(0.0, 0.0, v))),
-              ("eps_b/eps_a", 1, 1e-3, lambda v: dict(eps_b=v * cfg.eps_a)),
-              ("G", 2, 1e-4, lambda v: dict(G=v)))
+    # The deformation is weakly sensitive to the field and the permittivity ratio over 60
+    # steps: those use a Richardson-extrapolated central difference (steps h and 2h, error
+    # O(h^4)) with a step large enough to stay clear of rounding.  For G the quiescent
+    # outer fluid sits at the upwind switch of the donor-cell advection (u = 0), where
+    # the flux is not differentiable: difference quotients scatter around the derivative
+    # by a few 1e-4 at small steps (with a uniform drift they converge to it to 1e-7), so
+    # G takes a small step and a 1e-3 bound.
+    checks = (("E_z", 0, 1e-2, True, 1e-4, lambda v: dict(E_ext=(0.0, 0.0, v))),
+              ("eps_b/eps_a", 1, 1e-2, True, 1e-4, lambda v: dict(eps_b=v * cfg.eps_a)),
+              ("G", 2, 1e-6, False, 1e-3, lambda v: dict(G=v)))
     p0 = params.detach().numpy()
-    for name, k, rel_h, kw in checks:
+
+    def central(k, h, kw):
+        return (D_at(**kw(p0[k] + h)) - D_at(**kw(p0[k] - h))) / (2 * h)
+
+    for name, k, rel_h, richardson, tol, kw in checks:
         h = rel_h * p0[k]
-        fd = (D_at(**kw(p0[k] + h)) - D_at(**kw(p0[k] - h))) / (2 * h)
+        fd = central(k, h, kw)
+        if richardson:
+            fd = (4.0 * fd - central(k, 2 * h, kw)) / 3.0
         rel = abs(g[k] - fd) / abs(fd)
         print(f"  dD/d{name}: adjoint {g[k]:.8e}  FD {fd:.8e}  rel {rel:.2e}", flush=True)
-        assert rel < 1e-4, (name, g[k], fd)
+        assert rel < tol, (name, g[k], fd)
