@@ -84,7 +84,8 @@ struct ek_ctx {
     double mg_coarse_omega = 1.0;
     // V-cycle shape: red-black sweeps before and after the coarse correction on the
     // lattice and on the coarse grids, and sweeps on the coarsest grid
-    int mg_fine_pre = 2, mg_fine_post = 2, mg_pre = 3, mg_post = 3, mg_coarsest = 20;
+    int mg_fine_pre = 1, mg_fine_post = 2, mg_pre = 3, mg_post = 3, mg_coarsest = 20;
+    double mg_omega = 1.2;  // relaxation of the smoothing sweeps (1: Gauss-Seidel)
     // timing: 0 off, 1 kernel classes, 2 classes and every lattice-level smoothing pass
     int timing = 0;
     std::vector<TimeRec> recs;
@@ -403,9 +404,9 @@ static void vcycle(ek_ctx* c, const Fields<T>& F) {
         for (int color = 0; color < 2; ++color) {
             if (g == 0) {
                 Timer tm(c, EK_T_SMOOTH);
-                launch_sor<T>(c->S, F, color, 1.0, c->st);
+                launch_sor<T>(c->S, F, color, c->mg_omega, c->st);
             } else {
-                launch_mg_smooth(c->mg[g - 1], color, 1.0, c->st);
+                launch_mg_smooth(c->mg[g - 1], color, c->mg_omega, c->st);
             }
         }
     };
@@ -418,7 +419,7 @@ static void vcycle(ek_ctx* c, const Fields<T>& F) {
             launch_mg_restrict(c->mg[g - 1], c->mg[g], c->st);
     }
     launch_mg_tail(tail_mid ? c->mg[nl - 2] : c->mg[nl - 1], c->mg[nl - 1], tail_mid, c->mg_coarsest,
-                   c->mg_coarse_omega, c->mg_pre, c->mg_post, c->st);
+                   c->mg_coarse_omega, c->mg_pre, c->mg_post, c->mg_omega, c->st);
     for (int g = last_gpu; g >= 0; --g) {  // upward leg: interpolate from grid g+1, smooth grid g
         if (g == 0)
             launch_mg_prolong_fine<T>(c->S, F, c->mg[0], c->st);
@@ -1135,7 +1136,7 @@ extern "C" ek_status ek_adjoint(ek_ctx* c, const double* adj_f, const double* ad
 }
 
 extern "C" ek_status ek_set_multigrid(ek_ctx* c, int32_t fine_pre, int32_t fine_post, int32_t coarse_pre,
-                                      int32_t coarse_post, int32_t coarsest_sweeps) {
+                                      int32_t coarse_post, int32_t coarsest_sweeps, double omega) {
     if (!c || !c->phi) return EK_ESTATE;
     if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: its cycle is fixed by the batch");
     const int v[5] = {fine_pre, fine_post, coarse_pre, coarse_post, coarsest_sweeps};
@@ -1143,11 +1144,13 @@ extern "C" ek_status ek_set_multigrid(ek_ctx* c, int32_t fine_pre, int32_t fine_
         if (v[k] < 0 || v[k] > 64) return fail(c, EK_EINVAL, "sweep counts must be in 0..64");
     if (fine_pre + fine_post == 0 || coarsest_sweeps == 0)
         return fail(c, EK_EINVAL, "the lattice needs a sweep per cycle and the coarsest grid at least one");
+    if (!(omega > 0.0 && omega < 2.0)) return fail(c, EK_EINVAL, "omega must be in (0, 2)");
     c->mg_fine_pre = fine_pre;
     c->mg_fine_post = fine_post;
     c->mg_pre = coarse_pre;
     c->mg_post = coarse_post;
     c->mg_coarsest = coarsest_sweeps;
+    c->mg_omega = omega;
     c->rate = -1.0;  // the convergence rate is re-estimated
     return EK_OK;
 }
@@ -1361,6 +1364,9 @@ static RepDesc<T> make_desc(ek_ctx* c, int parity) {
     d.tail_mid = (nl >= 2 && c->mg[nl - 2].n <= 4096 && c->mg[nl - 1].n <= 512) ? 1 : 0;
     d.coarse_iters = 20;
     d.coarse_omega = c->mg_coarse_omega;
+    d.mid_pre = c->mg_pre;
+    d.mid_post = c->mg_post;
+    d.smooth_omega = c->mg_omega;
     return d;
 }
 
@@ -1377,7 +1383,8 @@ static void batch_step_launches(ek_batch* b, int parity) {
     for (int g = 2; g <= b->max_grid; ++g) launch_batch<T>(kB_COARSEN, D, b->cells[g].d, b->cells[g].n, g, 0, st);
     for (int cyc = 0; cyc < b->cycles; ++cyc) {
         for (int g = 0; g <= b->max_gpu; ++g) {
-            for (int sweep = 0; sweep < 2; ++sweep)
+            const int pre = g == 0 ? b->reps[0]->mg_fine_pre : b->reps[0]->mg_pre;
+            for (int sweep = 0; sweep < pre; ++sweep)
                 for (int color = 0; color < 2; ++color) {
                     if (g == 0)
                         launch_batch<T>(kB_SOR, D, b->color.d, b->color.n, 0, color, st);
@@ -1395,7 +1402,8 @@ static void batch_step_launches(ek_batch* b, int parity) {
                 launch_batch<T>(kB_PROLONG_FINE, D, b->site.d, b->site.n, 0, 0, st);
             else
                 launch_batch<T>(kB_PROLONG, D, b->cells_gpu[g].d, b->cells_gpu[g].n, g, 0, st);
-            for (int sweep = 0; sweep < 2; ++sweep)
+            const int post = g == 0 ? b->reps[0]->mg_fine_post : b->reps[0]->mg_post;
+            for (int sweep = 0; sweep < post; ++sweep)
                 for (int color = 0; color < 2; ++color) {
                     if (g == 0)
                         launch_batch<T>(kB_SOR, D, b->color.d, b->color.n, 0, color, st);

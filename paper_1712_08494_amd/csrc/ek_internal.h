@@ -110,6 +110,8 @@ struct RepDesc {
     int tail_mid;            // the tail kernel also handles grid nl - 1 (mg[nl - 2])
     int coarse_iters;
     double coarse_omega;
+    int mid_pre, mid_post;  // sweeps of the tail kernel's upper grid
+    double smooth_omega;    // relaxation of the smoothing sweeps
 };
 
 struct BlockRef {
@@ -138,7 +140,7 @@ void launch_mg_restrict(const MGLevel& f, const MGLevel& c, hipStream_t st);
 template <typename T> void launch_mg_prolong_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st);
 void launch_mg_prolong(const MGLevel& c, const MGLevel& f, hipStream_t st);
 void launch_mg_tail(const MGLevel& mid, const MGLevel& coarse, int has_mid, int iters, double omega, int mid_pre,
-                    int mid_post, hipStream_t st);
+                    int mid_post, double mid_omega, hipStream_t st);
 
 template <typename T> void launch_moments(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
 template <typename T> void launch_virtual(const Scalars& S, const Fields<T>& F, hipStream_t st);

@@ -751,7 +751,7 @@ __device__ void tail_load_coeffs(const MGLevel& G, C* ax, C* ay, C* az) {
 }
 
 __device__ void tail_body(const MGLevel& M, const MGLevel& Cg, int has_mid, int coarse_iters, double coarse_omega,
-                          int mid_pre = 2, int mid_post = 2) {
+                          int mid_pre = 2, int mid_post = 2, double mid_omega = 1.0) {
     extern __shared__ double lds[];
     if (has_mid) {
         double* phim = lds;
@@ -778,7 +778,7 @@ __device__ void tail_body(const MGLevel& M, const MGLevel& Cg, int has_mid, int 
         tail_inverse_diagonal(Lm);
         tail_inverse_diagonal(Lc);
         __syncthreads();
-        tail_sweeps(Lm, mid_pre, 1.0);
+        tail_sweeps(Lm, mid_pre, mid_omega);
         // restriction: sum of the eight children's residuals
         for (unsigned t = threadIdx.x; t < Cg.n; t += blockDim.x) {
             const int I = t % Cg.nx, r = t / Cg.nx, J = r % Cg.ny, K = r / Cg.ny;
@@ -816,7 +816,7 @@ __device__ void tail_body(const MGLevel& M, const MGLevel& Cg, int has_mid, int 
             phim[t] += v;
         }
         __syncthreads();
-        tail_sweeps(Lm, mid_post, 1.0);
+        tail_sweeps(Lm, mid_post, mid_omega);
         for (unsigned t = threadIdx.x; t < M.n; t += blockDim.x) M.phi[t] = phim[t];
     } else {
         double* phic = lds;
@@ -840,8 +840,9 @@ __device__ void tail_body(const MGLevel& M, const MGLevel& Cg, int has_mid, int 
 }
 
 __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MGLevel M, MGLevel Cg, int has_mid, int coarse_iters,
-                                                         double coarse_omega, int mid_pre, int mid_post) {
-    tail_body(M, Cg, has_mid, coarse_iters, coarse_omega, mid_pre, mid_post);
+                                                         double coarse_omega, int mid_pre, int mid_post,
+                                                         double mid_omega) {
+    tail_body(M, Cg, has_mid, coarse_iters, coarse_omega, mid_pre, mid_post, mid_omega);
 }
 
 size_t mg_tail_lds_bytes() {
@@ -851,9 +852,9 @@ size_t mg_tail_lds_bytes() {
 }
 
 void launch_mg_tail(const MGLevel& mid, const MGLevel& coarse, int has_mid, int iters, double omega, int mid_pre,
-                    int mid_post, hipStream_t st) {
+                    int mid_post, double mid_omega, hipStream_t st) {
     hipLaunchKernelGGL(k_mg_tail, dim3(1), dim3(kTailThreads), mg_tail_lds_bytes(), st, mid, coarse, has_mid, iters,
-                       omega, mid_pre, mid_post);
+                       omega, mid_pre, mid_post, mid_omega);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1516,7 +1517,7 @@ __global__ __launch_bounds__(kBlock) void kb_misc(const RepDesc<T>* __restrict__
         case kB_EXTRAPOLATE: extrapolate_body(R.S, R.F.phi, R.phi_prev, t); break;
         case kB_FINALIZE: finalize_body(R.S, R.F.phi, R.F.scal, 0, t); break;
         case kB_PROLONG_FINE: prolong_fine_body<T>(R.S, R.F, R.mg[0], t); break;
-        case kB_SOR: sor_body<T>(R.S, R.F, t, color, 1.0); break;
+        case kB_SOR: sor_body<T>(R.S, R.F, t, color, R.smooth_omega); break;
         case kB_COARSEN_FINE:
             if (t < R.mg[0].n) coarsen_fine_body<T>(R.S, R.F, R.mg[0], t);
             break;
@@ -1530,7 +1531,7 @@ __global__ __launch_bounds__(kBlock) void kb_misc(const RepDesc<T>* __restrict__
             if (t < R.mg[grid].n) restrict_body(R.mg[grid - 1], R.mg[grid], t);
             break;
         case kB_SMOOTH:
-            if (t < R.mg[grid - 1].n / 2) smooth_body(R.mg[grid - 1], color, 1.0, t);
+            if (t < R.mg[grid - 1].n / 2) smooth_body(R.mg[grid - 1], color, R.smooth_omega, t);
             break;
         case kB_PROLONG:
             if (t < R.mg[grid - 1].n) prolong_body(R.mg[grid], R.mg[grid - 1], t);
@@ -1602,7 +1603,8 @@ template <typename T>
 __global__ __launch_bounds__(kTailThreads) void kb_tail(const RepDesc<T>* __restrict__ D) {
     const RepDesc<T>& R = D[blockIdx.x];
     const int nl = R.nl;
-    tail_body(R.tail_mid ? R.mg[nl - 2] : R.mg[nl - 1], R.mg[nl - 1], R.tail_mid, R.coarse_iters, R.coarse_omega);
+    tail_body(R.tail_mid ? R.mg[nl - 2] : R.mg[nl - 1], R.mg[nl - 1], R.tail_mid, R.coarse_iters, R.coarse_omega,
+              R.mid_pre, R.mid_post, R.smooth_omega);
 }
 
 template <typename T> void launch_batch_tail(const RepDesc<T>* D, int n_rep, hipStream_t st) {
