@@ -177,13 +177,16 @@ ek_status ek_poisson(struct ek_ctx* ctx, double tol, int32_t maxit, int32_t* ite
 
 /* Shape of the multigrid V-cycle (contexts whose lattice the multigrid coarsens): red-black
    Gauss-Seidel sweeps before and after the coarse-grid correction on the lattice itself
-   (fine_pre, fine_post) and on the coarser grids (coarse_pre, coarse_post), and red-black
-   SOR sweeps on the coarsest grid; omega relaxes the smoothing sweeps (1 is Gauss-Seidel).
-   Defaults 1, 2, 3, 3, 20, 1.2.  Counts in 0..64, omega in (0, 2); the lattice needs at least
-   one sweep per cycle.  The solve still runs to the Poisson tolerance; the shape only trades
-   work per cycle against cycles.  Errors: EK_EINVAL, EK_ESTATE. */
+   (fine_pre, fine_post), on the coarse grids smoothed by separate launches (coarse_pre,
+   coarse_post) and on the upper grid of the last two, which one workgroup handles in LDS
+   (tail_pre, tail_post); red-black SOR sweeps on the coarsest grid; omega relaxes the
+   smoothing sweeps (1 is Gauss-Seidel).  Defaults 1, 2, 1, 2, 3, 3, 20, 1.2.  Counts in
+   0..64, omega in (0, 2); the lattice needs at least one sweep per cycle.  The solve still
+   runs to the Poisson tolerance; the shape only trades work per cycle against cycles.
+   Errors: EK_EINVAL, EK_ESTATE. */
 ek_status ek_set_multigrid(struct ek_ctx* ctx, int32_t fine_pre, int32_t fine_post, int32_t coarse_pre,
-                           int32_t coarse_post, int32_t coarsest_sweeps, double omega);
+                           int32_t coarse_post, int32_t tail_pre, int32_t tail_post, int32_t coarsest_sweeps,
+                           double omega);
 
 /* FP64 totals and diagnostics of the current state (synchronises the stream).
    Returns EK_ENONFINITE if populations or ion densities hold a NaN or Inf. */

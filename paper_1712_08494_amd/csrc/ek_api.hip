@@ -84,7 +84,8 @@ struct ek_ctx {
     double mg_coarse_omega = 1.0;
     // V-cycle shape: red-black sweeps before and after the coarse correction on the
     // lattice and on the coarse grids, and sweeps on the coarsest grid
-    int mg_fine_pre = 1, mg_fine_post = 2, mg_pre = 3, mg_post = 3, mg_coarsest = 20;
+    int mg_fine_pre = 1, mg_fine_post = 2, mg_pre = 1, mg_post = 2, mg_coarsest = 20;
+    int mg_tail_pre = 3, mg_tail_post = 3;  // sweeps on the upper grid of the single-workgroup tail
     double mg_omega = 1.2;  // relaxation of the smoothing sweeps (1: Gauss-Seidel)
     // timing: 0 off, 1 kernel classes, 2 classes and every lattice-level smoothing pass
     int timing = 0;
@@ -419,7 +420,7 @@ static void vcycle(ek_ctx* c, const Fields<T>& F) {
             launch_mg_restrict(c->mg[g - 1], c->mg[g], c->st);
     }
     launch_mg_tail(tail_mid ? c->mg[nl - 2] : c->mg[nl - 1], c->mg[nl - 1], tail_mid, c->mg_coarsest,
-                   c->mg_coarse_omega, c->mg_pre, c->mg_post, c->mg_omega, c->st);
+                   c->mg_coarse_omega, c->mg_tail_pre, c->mg_tail_post, c->mg_omega, c->st);
     for (int g = last_gpu; g >= 0; --g) {  // upward leg: interpolate from grid g+1, smooth grid g
         if (g == 0)
             launch_mg_prolong_fine<T>(c->S, F, c->mg[0], c->st);
@@ -1136,11 +1137,12 @@ extern "C" ek_status ek_adjoint(ek_ctx* c, const double* adj_f, const double* ad
 }
 
 extern "C" ek_status ek_set_multigrid(ek_ctx* c, int32_t fine_pre, int32_t fine_post, int32_t coarse_pre,
-                                      int32_t coarse_post, int32_t coarsest_sweeps, double omega) {
+                                      int32_t coarse_post, int32_t tail_pre, int32_t tail_post,
+                                      int32_t coarsest_sweeps, double omega) {
     if (!c || !c->phi) return EK_ESTATE;
     if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: its cycle is fixed by the batch");
-    const int v[5] = {fine_pre, fine_post, coarse_pre, coarse_post, coarsest_sweeps};
-    for (int k = 0; k < 5; ++k)
+    const int v[7] = {fine_pre, fine_post, coarse_pre, coarse_post, tail_pre, tail_post, coarsest_sweeps};
+    for (int k = 0; k < 7; ++k)
         if (v[k] < 0 || v[k] > 64) return fail(c, EK_EINVAL, "sweep counts must be in 0..64");
     if (fine_pre + fine_post == 0 || coarsest_sweeps == 0)
         return fail(c, EK_EINVAL, "the lattice needs a sweep per cycle and the coarsest grid at least one");
@@ -1149,6 +1151,8 @@ extern "C" ek_status ek_set_multigrid(ek_ctx* c, int32_t fine_pre, int32_t fine_
     c->mg_fine_post = fine_post;
     c->mg_pre = coarse_pre;
     c->mg_post = coarse_post;
+    c->mg_tail_pre = tail_pre;
+    c->mg_tail_post = tail_post;
     c->mg_coarsest = coarsest_sweeps;
     c->mg_omega = omega;
     c->rate = -1.0;  // the convergence rate is re-estimated
@@ -1364,8 +1368,8 @@ static RepDesc<T> make_desc(ek_ctx* c, int parity) {
     d.tail_mid = (nl >= 2 && c->mg[nl - 2].n <= 4096 && c->mg[nl - 1].n <= 512) ? 1 : 0;
     d.coarse_iters = 20;
     d.coarse_omega = c->mg_coarse_omega;
-    d.mid_pre = c->mg_pre;
-    d.mid_post = c->mg_post;
+    d.mid_pre = c->mg_tail_pre;
+    d.mid_post = c->mg_tail_post;
     d.smooth_omega = c->mg_omega;
     return d;
 }

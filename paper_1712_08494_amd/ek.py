@@ -132,7 +132,7 @@ def load(path=LIB_PATH):
     L.ek_forward_ckpt.restype = ctypes.c_int32
     L.ek_adjoint.argtypes = [vp, vp, vp, dp, vp, vp]
     L.ek_adjoint.restype = ctypes.c_int32
-    L.ek_set_multigrid.argtypes = [vp] + [ctypes.c_int32] * 5 + [ctypes.c_double]
+    L.ek_set_multigrid.argtypes = [vp] + [ctypes.c_int32] * 7 + [ctypes.c_double]
     L.ek_set_multigrid.restype = ctypes.c_int32
     _lib = L
     return L
@@ -295,11 +295,13 @@ class EKSim:
         self._check(load().ek_get_timing(self._h, ctypes.byref(t)), "ek_get_timing")
         return {name: (t.ms[k], t.count[k]) for k, name in enumerate(TIMING_CLASSES)}
 
-    def set_multigrid(self, fine_pre=1, fine_post=2, coarse_pre=3, coarse_post=3, coarsest=20, omega=1.2):
-        """V-cycle shape: sweeps before/after the correction on the lattice and the coarse
-        grids, coarsest-grid sweeps, and the relaxation of the smoothing sweeps."""
-        self._check(load().ek_set_multigrid(self._h, fine_pre, fine_post, coarse_pre, coarse_post, coarsest,
-                                            float(omega)), "ek_set_multigrid")
+    def set_multigrid(self, fine_pre=1, fine_post=2, coarse_pre=1, coarse_post=2, tail_pre=3, tail_post=3,
+                      coarsest=20, omega=1.2):
+        """V-cycle shape: sweeps before/after the correction on the lattice, on the launched
+        coarse grids and on the tail kernel's upper grid, coarsest-grid sweeps, and the
+        relaxation of the smoothing sweeps."""
+        self._check(load().ek_set_multigrid(self._h, fine_pre, fine_post, coarse_pre, coarse_post, tail_pre,
+                                            tail_post, coarsest, float(omega)), "ek_set_multigrid")
 
     def forward_checkpointed(self, nsteps, every, allow_noconv=False):
         """nsteps steps keeping a checkpoint every `every` steps, for adjoint()."""
