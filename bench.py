@@ -309,6 +309,10 @@ def run_adjoint(n=96, steps=500, every=50, fd=True):
                 log(f"adjoint: dD/d{key} {g[key]:.6e} vs central difference (relative step {rel_h:g}) {fd:.6e}")
         out["fd"] = fds
         out["fd_rel_err"] = rels
+        out["fd_note"] = ("the donor-cell ion flux n max(u, 0) is not differentiable where a link velocity is 0, "
+                          "and the resting fluid around the drop sits there: difference quotients in G scatter "
+                          "around the adjoint value instead of converging (with a uniform drift they converge to "
+                          "it within 1e-7, see the reverse-mode tests)")
     return out
 
 

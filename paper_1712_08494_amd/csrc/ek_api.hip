@@ -1049,82 +1049,88 @@ extern "C" ek_status ek_adjoint(ek_ctx* c, const double* adj_f, const double* ad
     const double rate_fwd = c->rate;
     int la = 0;
     ek_status worst = EK_OK;
-    const int nseg = A.nck - 1;
-    for (int g = nseg - 1; g >= 0; --g) {
-        const int t0 = g * A.K, n = std::min(A.K, A.T - t0);
-        // recompute the segment, keeping each step's state and the potential solved in it
-        EK_TRY(load_ck(c, g));
-        for (int k = 0; k < n; ++k) {
-            double* b = A.seg + (size_t)k * kSegVals * N;
-            EK_TRY(copy_d(c, b, c->f[c->cur][0], kQ * N));
-            EK_TRY(copy_d(c, b + kQ * N, c->f[c->cur][1], kQ * N));
-            EK_TRY(copy_d(c, b + 2 * kQ * N, c->n[c->cur][0], N));
-            EK_TRY(copy_d(c, b + (2 * kQ + 1) * N, c->n[c->cur][1], N));
-            const ek_status st = step_impl<double>(c, 1);
-            if (st != EK_OK && st != EK_ENOCONV) return st;
-            EK_TRY(copy_d(c, b + (2 * kQ + 2) * N, c->phi, N));
-        }
-        // reverse the steps of the segment
-        for (int k = n - 1; k >= 0; --k) {
-            double* b = A.seg + (size_t)k * kSegVals * N;
-            Fields<double> F = fields<double>(c);
-            F.f[0] = b;
-            F.f[1] = b + kQ * N;
-            F.n[0] = b + 2 * kQ * N;
-            F.n[1] = b + (2 * kQ + 1) * N;
-            F.phi = b + (2 * kQ + 2) * N;
-            {
-                Timer tm(c, EK_T_MOMENTS);
-                launch_moments<double>(c->S, F, c->nblk, c->st);
-            }
-            {
-                Timer tm(c, EK_T_FORCE);
-                launch_force<double>(c->S, F, c->st);
-            }
-            for (int k2 = 0; k2 < 2; ++k2) {
-                AF.lf[k2] = lf[la][k2];
-                AF.lfo[k2] = lf[la ^ 1][k2];
-                AF.ln[k2] = ln[la][k2];
-                AF.lno[k2] = ln[la ^ 1][k2];
-            }
-            launch_adj_force(c->S, F, AF, c->st);
-            launch_adj_links(c->S, F, AF, c->st);
-            launch_adj_rhs(c->S, F, AF, c->st);
-            launch_source_mean(c->S, c->red, c->nblk, c->scal, c->st);
-            EK_HIP(hipGetLastError());
-            // adjoint Poisson equation M mu = dL/dphi with the same solver: the source and
-            // the unknown are swapped in for the charge and the potential
-            void* q_fwd = c->q;
-            double* phi_fwd = c->phi;
-            c->q = AF.rhs;
-            c->phi = mu;
-            const ek_status ps = poisson_solve<double>(c, c->p.poisson_tol, c->p.poisson_maxit, nullptr, nullptr);
-            c->q = q_fwd;
-            c->phi = phi_fwd;
-            if (ps == EK_ENOCONV)
-                worst = ps;
-            else if (ps != EK_OK)
-                return ps;
-            launch_adj_final(c->S, F, AF, c->st);
-            EK_HIP(hipGetLastError());
-            la ^= 1;
-        }
-    }
-    // parameter gradient: fixed-order sum of the per-workgroup partials
-    launch_reduce(A.gred, c->nblk, kAdjSlots, nullptr, c->stage, c->st);
     double g[kAdjSlots];
-    EK_HIP(hipMemcpyAsync(g, c->stage, sizeof(g), hipMemcpyDeviceToHost, c->st));
-    if (adj_f0) {
-        EK_TRY(copy_d(c, adj_f0, lf[la][0], kQ * N));
-        EK_TRY(copy_d(c, adj_f0 + kQ * N, lf[la][1], kQ * N));
-    }
-    if (adj_n0) {
-        EK_TRY(copy_d(c, adj_n0, ln[la][0], N));
-        EK_TRY(copy_d(c, adj_n0 + N, ln[la][1], N));
-    }
-    // leave the context at the end of the forward run
-    EK_TRY(load_ck(c, A.nck - 1));
+    auto sweep = [&]() -> ek_status {
+        const int nseg = A.nck - 1;
+        for (int g = nseg - 1; g >= 0; --g) {
+            const int t0 = g * A.K, n = std::min(A.K, A.T - t0);
+            // recompute the segment, keeping each step's state and the potential solved in it
+            EK_TRY(load_ck(c, g));
+            for (int k = 0; k < n; ++k) {
+                double* b = A.seg + (size_t)k * kSegVals * N;
+                EK_TRY(copy_d(c, b, c->f[c->cur][0], kQ * N));
+                EK_TRY(copy_d(c, b + kQ * N, c->f[c->cur][1], kQ * N));
+                EK_TRY(copy_d(c, b + 2 * kQ * N, c->n[c->cur][0], N));
+                EK_TRY(copy_d(c, b + (2 * kQ + 1) * N, c->n[c->cur][1], N));
+                const ek_status st = step_impl<double>(c, 1);
+                if (st != EK_OK && st != EK_ENOCONV) return st;
+                EK_TRY(copy_d(c, b + (2 * kQ + 2) * N, c->phi, N));
+            }
+            // reverse the steps of the segment
+            for (int k = n - 1; k >= 0; --k) {
+                double* b = A.seg + (size_t)k * kSegVals * N;
+                Fields<double> F = fields<double>(c);
+                F.f[0] = b;
+                F.f[1] = b + kQ * N;
+                F.n[0] = b + 2 * kQ * N;
+                F.n[1] = b + (2 * kQ + 1) * N;
+                F.phi = b + (2 * kQ + 2) * N;
+                {
+                    Timer tm(c, EK_T_MOMENTS);
+                    launch_moments<double>(c->S, F, c->nblk, c->st);
+                }
+                {
+                    Timer tm(c, EK_T_FORCE);
+                    launch_force<double>(c->S, F, c->st);
+                }
+                for (int k2 = 0; k2 < 2; ++k2) {
+                    AF.lf[k2] = lf[la][k2];
+                    AF.lfo[k2] = lf[la ^ 1][k2];
+                    AF.ln[k2] = ln[la][k2];
+                    AF.lno[k2] = ln[la ^ 1][k2];
+                }
+                launch_adj_force(c->S, F, AF, c->st);
+                launch_adj_links(c->S, F, AF, c->st);
+                launch_adj_rhs(c->S, F, AF, c->st);
+                launch_source_mean(c->S, c->red, c->nblk, c->scal, c->st);
+                EK_HIP(hipGetLastError());
+                // adjoint Poisson equation M mu = dL/dphi with the same solver: the source and
+                // the unknown are swapped in for the charge and the potential
+                void* q_fwd = c->q;
+                double* phi_fwd = c->phi;
+                c->q = AF.rhs;
+                c->phi = mu;
+                const ek_status ps = poisson_solve<double>(c, c->p.poisson_tol, c->p.poisson_maxit, nullptr, nullptr);
+                c->q = q_fwd;
+                c->phi = phi_fwd;
+                if (ps == EK_ENOCONV)
+                    worst = ps;
+                else if (ps != EK_OK)
+                    return ps;
+                launch_adj_final(c->S, F, AF, c->st);
+                EK_HIP(hipGetLastError());
+                la ^= 1;
+            }
+        }
+        // parameter gradient: fixed-order sum of the per-workgroup partials
+        launch_reduce(A.gred, c->nblk, kAdjSlots, nullptr, c->stage, c->st);
+        EK_HIP(hipMemcpyAsync(g, c->stage, sizeof(g), hipMemcpyDeviceToHost, c->st));
+        if (adj_f0) {
+            EK_TRY(copy_d(c, adj_f0, lf[la][0], kQ * N));
+            EK_TRY(copy_d(c, adj_f0 + kQ * N, lf[la][1], kQ * N));
+        }
+        if (adj_n0) {
+            EK_TRY(copy_d(c, adj_n0, ln[la][0], N));
+            EK_TRY(copy_d(c, adj_n0 + N, ln[la][1], N));
+        }
+        return EK_OK;
+    };
+    const ek_status sst = sweep();
+    // leave the context at the end of the forward run, also after a failed sweep
+    const ek_status lst = load_ck(c, A.nck - 1);
     c->rate = rate_fwd;
+    if (sst != EK_OK) return sst;
+    EK_TRY(lst);
     EK_HIP(hipStreamSynchronize(c->st));
     grad[0] = g[kAdjEx];
     grad[1] = g[kAdjEx + 1];
