@@ -78,6 +78,10 @@ typedef struct ek_params {
     double particle_rho;        /* particle mass density (mass = rho_p 4/3 pi r^3) */
     double k_hertz;             /* Hertz contact stiffness */
     double eta;                 /* dynamic viscosity used by the lubrication force */
+    int32_t phi_history;        /* warm start of each Poisson solve from the potentials of the last steps:
+                                   1 the previous one, 2 linear and 3 quadratic extrapolation in time;
+                                   0 adaptive: the order (2 or 3) whose last measured start residual was
+                                   smaller, the other re-probed every 64 steps (deterministic) */
 } ek_params;
 
 typedef struct ek_particle {
@@ -235,7 +239,7 @@ const char* ek_last_error(const struct ek_ctx* ctx);
 
 /* Advance nsteps steps (as ek_step) keeping a device checkpoint of the state every
    `every` steps and at the end, for a later ek_adjoint; replaces the checkpoints of any
-   earlier call.  Device memory: (nsteps / every + 2) x 42 N doubles.
+   earlier call.  Device memory: (nsteps / every + 2) x 43 N doubles.
    Errors: EK_EINVAL (bad counts, unsupported context), EK_ENOMEM, EK_ENOCONV as ek_step. */
 ek_status ek_forward_ckpt(struct ek_ctx* ctx, int32_t nsteps, int32_t every);
 

@@ -44,6 +44,12 @@ struct ek_ctx {
     void* eps = nullptr;
     double* phi = nullptr;
     double* phi_prev = nullptr;  // potential of the previous step (time extrapolation)
+    double* phi_prev2 = nullptr; // potential two steps back
+    int phi_history = 0;         // potentials the warm start extrapolates from (1, 2 or 3; 0 adaptive)
+    // adaptive warm start: the last start residual measured with linear (2) and quadratic
+    // (3) extrapolation, the order in use and the steps since the other one was probed
+    double rel0_of[4] = {0, 0, 0, 0};
+    int ws_order = 2, ws_since = 0;
     int cur = 0;
     // geometry
     uint8_t* flags = nullptr;
@@ -102,6 +108,8 @@ struct ek_ctx {
         size_t ck_cap = 0;          // checkpoints the allocation holds
         std::vector<double> ck_rate;
         std::vector<long long> ck_steps, ck_ptotal;
+        std::vector<int> ck_ws;          // adaptive warm start: order, steps since the probe
+        std::vector<double> ck_rel0;     // its last start residuals of orders 2 and 3
         double* seg = nullptr;      // K x kSegVals N doubles: the states of one segment
         int seg_cap = 0;
         double* buf = nullptr;      // adjoint fields (kAdjVals N doubles)
@@ -111,10 +119,10 @@ struct ek_ctx {
 };
 
 // Checkpoint: populations of a and b (2 x 19 N), stored ions (2 N), the potential and the
-// previous potential (the warm start of the next solve).  Segment state: populations, ions
+// two previous potentials (the warm start of the next solve).  Segment state: populations, ions
 // and the potential solved in that step.  Adjoint fields: dL/df (two parities x two
 // components x 19 N), dL/dn (two parities x 2 N) and the intermediates of AdjFields.
-constexpr size_t kCkVals = 2 * kQ + 4, kSegVals = 2 * kQ + 3, kAdjVals = 4 * kQ + 4 + 6 + 3 + 3 + 2 + 3 + 2 + 1 + 1 + 1;
+constexpr size_t kCkVals = 2 * kQ + 5, kSegVals = 2 * kQ + 3, kAdjVals = 4 * kQ + 4 + 6 + 3 + 3 + 2 + 3 + 2 + 1 + 1 + 1;
 
 #define EK_HIP(call)                                                                             \
     do {                                                                                         \
@@ -530,8 +538,28 @@ static ek_status step_impl(ek_ctx* c, int nsteps) {
     ek_status worst = EK_OK;
     for (int s = 0; s < nsteps; ++s) {
         moments_pass<T>(c);
-        launch_phi_extrapolate(c->S, c->phi, c->phi_prev, c->st);
+        int order = c->phi_history;
+        bool probe = false;
+        if (order == 0) {  // adaptive: keep the order with the smaller start residual, re-probe the other
+            order = c->ws_order;
+            const int other = 5 - c->ws_order;
+            if (c->rel0_of[c->ws_order] > 0.0 && (c->rel0_of[other] == 0.0 || c->ws_since >= 64)) {
+                order = other;
+                probe = true;
+            }
+        }
+        launch_phi_extrapolate(c->S, c->phi, c->phi_prev, c->phi_prev2, order, c->st);
         ek_status ps = poisson_solve<T>(c, c->p.poisson_tol, c->p.poisson_maxit, nullptr, nullptr);
+        if (c->phi_history == 0 && c->steps >= 2) {
+            c->rel0_of[order] = c->last_rel0;
+            const int other = 5 - order;
+            if (probe) {
+                c->ws_since = 0;
+                if (c->rel0_of[order] < c->rel0_of[other]) c->ws_order = order;
+            } else {
+                ++c->ws_since;
+            }
+        }
         if (ps == EK_ENOCONV)
             worst = ps;
         else if (ps != EK_OK)
@@ -643,6 +671,7 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     EK_TRY(dalloc(c, &c->eps, (size_t)N * es));
     EK_TRY(dalloc(c, (void**)&c->phi, (size_t)N * 8));
     EK_TRY(dalloc(c, (void**)&c->phi_prev, (size_t)N * 8));
+    EK_TRY(dalloc(c, (void**)&c->phi_prev2, (size_t)N * 8));
     EK_TRY(dalloc(c, (void**)&c->red, (size_t)c->nblk * kRedSlots * 8));
     EK_TRY(dalloc(c, (void**)&c->scal, 32 * 8));
     EK_TRY(dalloc(c, (void**)&c->obs_max, 16 * sizeof(int)));
@@ -751,6 +780,7 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     moments_pass<T>(c);
     ek_status st = poisson_solve<T>(c, p.poisson_tol, p.poisson_maxit, nullptr, nullptr);
     EK_HIP(hipMemcpyAsync(c->phi_prev, c->phi, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
+    EK_HIP(hipMemcpyAsync(c->phi_prev2, c->phi, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
     c->ptotal = 0;
     return st;
 }
@@ -776,6 +806,8 @@ extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const doub
     if ((p->dmu[0] != 0.0 || p->dmu[1] != 0.0) && p->drho_a == 0.0) return fail(c, EK_EINVAL, "drho_a must be non-zero with solvation");
     if (n_parts < 0 || (n_parts > 0 && !parts)) return fail(c, EK_EINVAL, "bad particle array");
     if (p->poisson_maxit < 0 || !(p->poisson_tol > 0.0)) return fail(c, EK_EINVAL, "poisson_tol must be > 0, maxit >= 0");
+    if (p->phi_history < 0 || p->phi_history > 3) return fail(c, EK_EINVAL, "phi_history must be in 0..3");
+    c->phi_history = p->phi_history;
     c->N = (unsigned)Nd;
     c->nblk = site_blocks(c->N);
     Scalars& S = c->S;
@@ -939,9 +971,14 @@ static ek_status save_ck(ek_ctx* c, int slot) {
     EK_TRY(copy_d(c, b + (2 * kQ + 1) * N, c->n[c->cur][1], N));
     EK_TRY(copy_d(c, b + (2 * kQ + 2) * N, c->phi, N));
     EK_TRY(copy_d(c, b + (2 * kQ + 3) * N, c->phi_prev, N));
+    EK_TRY(copy_d(c, b + (2 * kQ + 4) * N, c->phi_prev2, N));
     c->adj.ck_rate[slot] = c->rate;
     c->adj.ck_steps[slot] = c->steps;
     c->adj.ck_ptotal[slot] = c->ptotal;
+    c->adj.ck_ws[2 * slot] = c->ws_order;
+    c->adj.ck_ws[2 * slot + 1] = c->ws_since;
+    c->adj.ck_rel0[2 * slot] = c->rel0_of[2];
+    c->adj.ck_rel0[2 * slot + 1] = c->rel0_of[3];
     return EK_OK;
 }
 
@@ -954,9 +991,14 @@ static ek_status load_ck(ek_ctx* c, int slot) {
     EK_TRY(copy_d(c, c->n[c->cur][1], b + (2 * kQ + 1) * N, N));
     EK_TRY(copy_d(c, c->phi, b + (2 * kQ + 2) * N, N));
     EK_TRY(copy_d(c, c->phi_prev, b + (2 * kQ + 3) * N, N));
+    EK_TRY(copy_d(c, c->phi_prev2, b + (2 * kQ + 4) * N, N));
     c->rate = c->adj.ck_rate[slot];
     c->steps = c->adj.ck_steps[slot];
     c->ptotal = c->adj.ck_ptotal[slot];
+    c->ws_order = c->adj.ck_ws[2 * slot];
+    c->ws_since = c->adj.ck_ws[2 * slot + 1];
+    c->rel0_of[2] = c->adj.ck_rel0[2 * slot];
+    c->rel0_of[3] = c->adj.ck_rel0[2 * slot + 1];
     return EK_OK;
 }
 
@@ -977,6 +1019,8 @@ extern "C" ek_status ek_forward_ckpt(ek_ctx* c, int32_t nsteps, int32_t every) {
     A.ck_rate.assign(need, 0.0);
     A.ck_steps.assign(need, 0);
     A.ck_ptotal.assign(need, 0);
+    A.ck_ws.assign(2 * need, 0);
+    A.ck_rel0.assign(2 * need, 0.0);
     A.valid = false;
     ek_status worst = EK_OK;
     for (int g = 0; g < nseg; ++g) {

@@ -149,7 +149,8 @@ template <typename T> void launch_sor(const Scalars& S, const Fields<T>& F, int 
 template <typename T> void launch_residual(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
 void launch_reduce(const double* red, unsigned nblk, int nvals, const int* is_max, double* out, hipStream_t st);
 void launch_phi_finalize(const Scalars& S, double* phi, const double* scal, int zero, hipStream_t st);
-void launch_phi_extrapolate(const Scalars& S, double* phi, double* phi_prev, hipStream_t st);
+void launch_phi_extrapolate(const Scalars& S, double* phi, double* prev, double* prev2, int history,
+                            hipStream_t st);
 template <typename T> void launch_phi_ghosts(const Scalars& S, const Fields<T>& F, hipStream_t st);
 template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hipStream_t st);
 template <typename T> void launch_fused(const Scalars& S, const Fields<T>& F, hipStream_t st);

@@ -431,12 +431,28 @@ __device__ __forceinline__ void extrapolate_body(const Scalars& S, double* phi, 
     phi_prev[i] = p;
 }
 
-__global__ __launch_bounds__(kBlock) void k_phi_extrapolate(Scalars S, double* phi, double* phi_prev) {
-    extrapolate_body(S, phi, phi_prev, xcd_linear());
+// Start of the next solve from the last potentials phi(t-1), phi(t-2), phi(t-3) (held in
+// phi, prev, prev2): the previous one, or the linear or quadratic extrapolation in time;
+// the history shifts by one step.
+__global__ __launch_bounds__(kBlock) void k_phi_extrapolate(Scalars S, double* phi, double* prev, double* prev2,
+                                                            int history) {
+    const unsigned i = xcd_linear();
+    if (i >= S.N) return;
+    const int z = (i / S.nx) / S.ny;
+    if (z < S.z0 || z > S.z1) return;
+    const double p1 = phi[i], p2 = prev[i];
+    double v = p1;
+    if (history == 2) v = 2.0 * p1 - p2;
+    if (history >= 3) v = 3.0 * (p1 - p2) + prev2[i];
+    phi[i] = v;
+    prev2[i] = p2;
+    prev[i] = p1;
 }
 
-void launch_phi_extrapolate(const Scalars& S, double* phi, double* phi_prev, hipStream_t st) {
-    hipLaunchKernelGGL(k_phi_extrapolate, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, phi, phi_prev);
+void launch_phi_extrapolate(const Scalars& S, double* phi, double* prev, double* prev2, int history,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_phi_extrapolate, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, phi, prev, prev2,
+                       history);
 }
 
 // Wall layers: Gauss's law at the charged wall face, phi_wall = phi_adjacent + sigma / eps_adjacent.
