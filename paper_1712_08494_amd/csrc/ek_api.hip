@@ -93,6 +93,16 @@ struct ek_ctx {
     int mg_fine_pre = 1, mg_fine_post = 2, mg_pre = 1, mg_post = 2, mg_coarsest = 20;
     int mg_tail_pre = 3, mg_tail_post = 3;  // sweeps on the upper grid of the single-workgroup tail
     double mg_omega = 1.2;  // relaxation of the smoothing sweeps (1: Gauss-Seidel)
+    // One V-cycle captured as a HIP graph and replayed for each cycle of a solve (one host
+    // call instead of ~40 launches).  It is captured with the context's own charge and
+    // potential buffers and used only while they are the ones in place; per-sweep timing
+    // (level 2) and a changed cycle shape fall back to direct launches / a new capture.
+    hipStream_t cap_st = nullptr;
+    hipGraph_t vc_graph = nullptr;
+    hipGraphExec_t vc_exec = nullptr;
+    void* q_own = nullptr;
+    double* phi_own = nullptr;
+    bool vc_off = false;
     // timing: 0 off, 1 kernel classes, 2 classes and every lattice-level smoothing pass
     int timing = 0;
     std::vector<TimeRec> recs;
@@ -439,6 +449,42 @@ static void vcycle(ek_ctx* c, const Fields<T>& F) {
     }
 }
 
+static void vcycle_graph_drop(ek_ctx* c) {
+    if (c->vc_exec) (void)hipGraphExecDestroy(c->vc_exec);
+    if (c->vc_graph) (void)hipGraphDestroy(c->vc_graph);
+    c->vc_exec = nullptr;
+    c->vc_graph = nullptr;
+}
+
+// k V-cycles: graph replays when possible, direct launches otherwise.
+template <typename T>
+static ek_status run_cycles(ek_ctx* c, Fields<T>& F, int k) {
+    const bool own = c->phi == c->phi_own && c->q == c->q_own;
+    if (c->timing < 2 && own && !c->vc_off && !c->vc_exec) {
+        if (!c->cap_st) EK_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
+        hipStream_t st = c->st;
+        c->st = c->cap_st;
+        bool ok = hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            vcycle<T>(c, F);
+            ok = hipStreamEndCapture(c->cap_st, &c->vc_graph) == hipSuccess;
+        }
+        c->st = st;
+        if (ok) ok = hipGraphInstantiate(&c->vc_exec, c->vc_graph, nullptr, nullptr, 0) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            vcycle_graph_drop(c);
+            c->vc_off = true;  // this runtime cannot capture the cycle: launch it directly from now on
+        }
+    }
+    if (c->vc_exec && c->timing < 2 && own) {
+        for (int s = 0; s < k; ++s) EK_HIP(hipGraphLaunch(c->vc_exec, c->st));
+    } else {
+        for (int s = 0; s < k; ++s) vcycle<T>(c, F);
+    }
+    return EK_OK;
+}
+
 // Coarse-level face coefficients for the current permittivity.
 template <typename T>
 static void mg_build(ek_ctx* c, const Fields<T>& F) {
@@ -471,7 +517,7 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
             k = std::min(k, maxit - it);
             {
                 Timer ts(c, EK_T_ITER, k);
-                for (int s = 0; s < k; ++s) vcycle<T>(c, F);
+                EK_TRY(run_cycles<T>(c, F, k));
             }
             EK_HIP(hipGetLastError());
             it += k;
@@ -672,6 +718,8 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     EK_TRY(dalloc(c, (void**)&c->phi, (size_t)N * 8));
     EK_TRY(dalloc(c, (void**)&c->phi_prev, (size_t)N * 8));
     EK_TRY(dalloc(c, (void**)&c->phi_prev2, (size_t)N * 8));
+    c->phi_own = c->phi;
+    c->q_own = c->q;
     EK_TRY(dalloc(c, (void**)&c->red, (size_t)c->nblk * kRedSlots * 8));
     EK_TRY(dalloc(c, (void**)&c->scal, 32 * 8));
     EK_TRY(dalloc(c, (void**)&c->obs_max, 16 * sizeof(int)));
@@ -1205,7 +1253,8 @@ extern "C" ek_status ek_set_multigrid(ek_ctx* c, int32_t fine_pre, int32_t fine_
     c->mg_tail_post = tail_post;
     c->mg_coarsest = coarsest_sweeps;
     c->mg_omega = omega;
-    c->rate = -1.0;  // the convergence rate is re-estimated
+    c->rate = -1.0;
+    vcycle_graph_drop(c);  // the captured cycle has the old shape  // the convergence rate is re-estimated
     return EK_OK;
 }
 
@@ -1330,6 +1379,8 @@ extern "C" ek_status ek_destroy(ek_ctx* c) {
     if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: released by ek_batch_destroy");
     if (c->phi) (void)hipStreamSynchronize(c->st);
     resolve_timing(c);
+    vcycle_graph_drop(c);
+    if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
     for (auto e : c->pool) (void)hipEventDestroy(e);
     for (void* a : c->allocs) (void)hipFree(a);
     if (c->hscal) (void)hipHostFree(c->hscal);

@@ -582,20 +582,74 @@ void launch_mg_smooth(const MGLevel& L, int color, double omega, hipStream_t st)
     hipLaunchKernelGGL(k_mg_smooth, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, L, color, omega);
 }
 
+// Residuals of the eight lattice cells under coarse cell t, summed.  The eight rows
+// share their stencil points: the 2x2x2 block and the four neighbours across each of its
+// six faces (32 sites), loaded once each.  Rows as in poisson_row, same operand order.
 template <typename T>
 __device__ __forceinline__ void restrict_fine_body(const Scalars& S, const Fields<T>& F, const MGLevel& C, unsigned t) {
     if (t >= C.n) return;
     const int I = t % C.nx, r = t / C.nx, J = r % C.ny, K = r / C.ny;
+    int xs[4], ys[4], zs[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        xs[k] = wrapc(2 * I - 1 + k, S.nx);
+        ys[k] = wrapc(2 * J - 1 + k, S.ny);
+        zs[k] = wrapc(2 * K - 1 + k, S.nz);
+    }
+    auto at = [&](int a, int b, int c) {
+        return (unsigned)xs[a] + (unsigned)S.nx * ((unsigned)ys[b] + (unsigned)S.ny * (unsigned)zs[c]);
+    };
+    double P[4][4][4], E[4][4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int outer = (a == 0 || a == 3) + (b == 0 || b == 3) + (c == 0 || c == 3);
+                if (outer <= 1) {
+                    const unsigned g = at(a, b, c);
+                    P[c][b][a] = F.phi[g];
+                    E[c][b][a] = (double)F.eps[g];
+                }
+            }
+    const double mean = F.scal[0];
     double sum = 0.0;
-    for (int c = 0; c < 2; ++c)
-        for (int b = 0; b < 2; ++b)
-            for (int a = 0; a < 2; ++a) {
-                const int x = 2 * I + a, y = 2 * J + b, z = 2 * K + c;
+#pragma unroll
+    for (int c = 1; c < 3; ++c)
+#pragma unroll
+        for (int b = 1; b < 3; ++b)
+#pragma unroll
+            for (int a = 1; a < 3; ++a) {
+                const int z = zs[c];
                 if (z < S.z0 || z > S.z1) continue;
-                const unsigned i = x + S.nx * (y + S.ny * z);
-                double diag, offsum, src;
-                poisson_row<T>(i, x, y, z, S, F, diag, offsum, src);
-                sum += src + offsum - diag * F.phi[i];
+                const double ei = E[c][b][a];
+                double diag = 0.0, off = 0.0;
+                {
+                    const double ea = 0.5 * (ei + E[c][b][a - 1]), eb = 0.5 * (ei + E[c][b][a + 1]);
+                    diag += ea + eb;
+                    off += ea * P[c][b][a - 1] + eb * P[c][b][a + 1];
+                }
+                {
+                    const double ea = 0.5 * (ei + E[c][b - 1][a]), eb = 0.5 * (ei + E[c][b + 1][a]);
+                    diag += ea + eb;
+                    off += ea * P[c][b - 1][a] + eb * P[c][b + 1][a];
+                }
+                if (!(S.walls && z == S.z0)) {
+                    const double ea = 0.5 * (ei + E[c - 1][b][a]);
+                    diag += ea;
+                    off += ea * P[c - 1][b][a];
+                }
+                if (!(S.walls && z == S.z1)) {
+                    const double eb = 0.5 * (ei + E[c + 1][b][a]);
+                    diag += eb;
+                    off += eb * P[c + 1][b][a];
+                }
+                double src = (double)F.q[at(a, b, c)];
+                if (S.walls && z == S.z0) src += S.sigma0;
+                if (S.walls && z == S.z1) src += S.sigma1;
+                src -= mean;
+                sum += src + off - diag * P[c][b][a];
             }
     C.s[t] = sum;
     C.phi[t] = 0.0;
@@ -656,12 +710,30 @@ __device__ __forceinline__ double mg_interp(const MGLevel& C, int x, int y, int 
     return v;
 }
 
+// The same interpolation onto the lattice.  Coarse faces of the first coarse grid are
+// zero only where it wraps across the wall layers in z (every other face averages
+// positive permittivities), so the weights follow from the indices and no coefficient
+// is read.
 template <typename T>
 __device__ __forceinline__ void prolong_fine_body(const Scalars& S, const Fields<T>& F, const MGLevel& C, unsigned i) {
     if (i >= S.N) return;
     const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
     if (z < S.z0 || z > S.z1) return;
-    F.phi[i] += mg_interp(C, x, y, z);
+    const int I = x >> 1, J = y >> 1, K = z >> 1;
+    const int dx = (x & 1) ? 1 : -1, dy = (y & 1) ? 1 : -1, dz = (z & 1) ? 1 : -1;
+    const int In = wrapc(I + dx, C.nx), Jn = wrapc(J + dy, C.ny), Kn = wrapc(K + dz, C.nz);
+    const bool zwrap = S.walls && (K + dz < 0 || K + dz >= C.nz);
+    const double wx = 0.25, wy = 0.25, wz = zwrap ? 0.0 : 0.25;
+    const int xs[2] = {I, In}, ys[2] = {J, Jn}, zs[2] = {K, Kn};
+    const double wxs[2] = {1.0 - wx, wx}, wys[2] = {1.0 - wy, wy}, wzs[2] = {1.0 - wz, wz};
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) v += wxs[a] * wys[b] * wzs[c] * C.phi[lid(C, xs[a], ys[b], zs[c])];
+    F.phi[i] += v;
 }
 
 template <typename T>
