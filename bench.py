@@ -434,7 +434,8 @@ def main():
                      "traffic_source": os.path.relpath(traffic_src, ROOT) if traffic else traffic_src,
                      "bytes_per_site": bpsite, "us_per_launch": round(avg_s * 1e6, 3),
                      "timed_over": "the timed region" if dom != "smooth" else
-                     f"{args.detail_steps} steps after the timed region, an event pair per launch"},
+                     f"{args.detail_steps} steps after the timed region, an event pair per group of back-to-back "
+                     "lattice passes"},
         "roofline_fused": {"kernel": "fused", "achieved": round(f_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(f_ach / HBM_PEAK_GBS, 4), "bytes_per_site": f_b,
                            "us_per_launch": round(f_avg * 1e6, 3),

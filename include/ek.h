@@ -117,7 +117,8 @@ typedef struct ek_obs {
 #define EK_T_FUSED 3     /* fused ion update + force + collide + stream pass */
 #define EK_T_PARTICLE 4  /* particle force sums and integration */
 #define EK_T_ITER 5      /* Poisson iterations: SOR sweep chunks (count = sweeps) or V-cycles (count = cycles) */
-#define EK_T_SMOOTH 6    /* each red-black colour pass on the lattice itself (SOR sweep or multigrid smoothing) */
+#define EK_T_SMOOTH 6    /* red-black colour passes on the lattice itself (SOR or multigrid smoothing): one event
+                            pair per group of back-to-back passes, count = passes */
 #define EK_T_COUNT 7
 
 typedef struct ek_timing {
@@ -212,8 +213,10 @@ ek_status ek_get_particles(struct ek_ctx* ctx, double* host_out);
 ek_status ek_device_bytes(const struct ek_ctx* ctx, size_t* bytes);
 
 /* Per-kernel HIP event timing: 0 off, 1 kernel classes (a few events per step),
-   2 classes plus every lattice-level red-black pass (EK_T_SMOOTH; adds events
-   between small kernels, so use it for per-launch figures, not for step rates).
+   2 classes plus the lattice-level red-black passes (EK_T_SMOOTH, one event pair per
+   group of back-to-back passes; it adds events between small kernels and launches
+   the multigrid cycle without its graph, so use it for per-launch figures, not for
+   step rates).
    Any call clears the accumulated times. */
 ek_status ek_set_timing(struct ek_ctx* ctx, int32_t enable);
 

@@ -421,17 +421,24 @@ static void vcycle(ek_ctx* c, const Fields<T>& F) {
     const int last_gpu = nl - 1 - tail_mid;  // finest grid handled by the tail, minus one
     auto smooth = [&](int g) {
         for (int color = 0; color < 2; ++color) {
-            if (g == 0) {
-                Timer tm(c, EK_T_SMOOTH);
+            if (g == 0)
                 launch_sor<T>(c->S, F, color, c->mg_omega, c->st);
-            } else {
+            else
                 launch_mg_smooth(c->mg[g - 1], color, c->mg_omega, c->st);
-            }
         }
+    };
+    // the lattice sweeps of one leg run back to back: one event pair times the group
+    auto smooth_lattice = [&](int sweeps) {
+        if (sweeps <= 0) return;
+        Timer tm(c, EK_T_SMOOTH, 2 * sweeps);
+        for (int s = 0; s < sweeps; ++s) smooth(0);
     };
     for (int g = 0; g <= last_gpu; ++g) {  // downward leg: smooth grid g, restrict to grid g+1
         const int pre = g == 0 ? c->mg_fine_pre : c->mg_pre;
-        for (int s = 0; s < pre; ++s) smooth(g);
+        if (g == 0)
+            smooth_lattice(pre);
+        else
+            for (int s = 0; s < pre; ++s) smooth(g);
         if (g == 0)
             launch_mg_restrict_fine<T>(c->S, F, c->mg[0], c->st);
         else
@@ -445,7 +452,10 @@ static void vcycle(ek_ctx* c, const Fields<T>& F) {
         else
             launch_mg_prolong(c->mg[g], c->mg[g - 1], c->st);
         const int post = g == 0 ? c->mg_fine_post : c->mg_post;
-        for (int s = 0; s < post; ++s) smooth(g);
+        if (g == 0)
+            smooth_lattice(post);
+        else
+            for (int s = 0; s < post; ++s) smooth(g);
     }
 }
 
@@ -539,11 +549,9 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
             k = std::min(k, maxit - it);
             {
                 Timer ts(c, EK_T_ITER, k);
+                Timer tm(c, EK_T_SMOOTH, 2 * k);  // the k sweeps run back to back
                 for (int s = 0; s < k; ++s)
-                    for (int color = 0; color < 2; ++color) {
-                        Timer tm(c, EK_T_SMOOTH);
-                        launch_sor<T>(c->S, F, color, c->omega, c->st);
-                    }
+                    for (int color = 0; color < 2; ++color) launch_sor<T>(c->S, F, color, c->omega, c->st);
             }
             EK_HIP(hipGetLastError());
             it += k;
