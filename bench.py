@@ -104,15 +104,22 @@ def build_workload(name, precision, n):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_gpu(cfg, inp, steps, warmup, detail_steps=20):
+def run_gpu(cfg, inp, steps, warmup, detail_steps=20, autotune=0):
     """Warm-up, then `steps` timed steps with kernel-class HIP events (a few per step),
     then `detail_steps` more with an event pair around every lattice-level smoothing
     pass as well (those events sit between small kernels, so they are kept out of the
-    timed region)."""
+    timed region).  With autotune > 0 the library's V-cycle autotuner runs after the
+    warm-up (that many trial steps per candidate shape, state restored) and its choice
+    is returned."""
     import torch
     from paper_1712_08494_amd import ek
     sim = ek.EKSim(cfg, inp)
     sim.step(warmup)
+    tuned = None
+    if autotune:
+        best, shapes, ms = sim.autotune_multigrid(autotune)
+        tuned = {"shape": list(shapes[best][0]), "omega": shapes[best][1], "index": best,
+                 "ms_per_step": [round(t, 4) for t in ms]}
     torch.cuda.synchronize()
     ob0 = sim.observables()
     sim.set_timing(1)
@@ -130,7 +137,7 @@ def run_gpu(cfg, inp, steps, warmup, detail_steps=20):
     else:
         timing["smooth"] = (0.0, 0)
     sim.close()
-    return t1 - t0, timing, ob0, ob1
+    return t1 - t0, timing, ob0, ob1, tuned
 
 
 def log(msg):
@@ -334,6 +341,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode leg")
     ap.add_argument("--detail-steps", type=int, default=20,
                     help="steps after the timed region with per-smoothing-pass events")
+    ap.add_argument("--autotune", type=int, default=0,
+                    help="after the warm-up, let the library pick the V-cycle shape (trial steps per candidate)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size three times (byte-counter scale)")
     args = ap.parse_args()
@@ -349,7 +358,9 @@ def main():
 
     cfg, inp = build_workload(args.workload, args.precision, args.n)
     log(f"gpu {args.precision}: {cfg.name}, {args.warmup} warm-up + {args.steps} timed steps")
-    dt, timing, ob0, ob1 = run_gpu(cfg, inp, args.steps, args.warmup, args.detail_steps)
+    dt, timing, ob0, ob1, tuned = run_gpu(cfg, inp, args.steps, args.warmup, args.detail_steps, args.autotune)
+    if tuned:
+        log(f"autotuned V-cycle: {tuned}")
     log(f"gpu {args.precision}: {1e3 * dt / args.steps:.3f} ms/step")
     N = cfg.n_sites
     mlups = N * args.steps / dt / 1e6
@@ -393,7 +404,7 @@ def main():
     if not args.no_fp64 and args.precision == "fp32":
         cfg64, inp64 = build_workload(args.workload, "fp64", args.n)
         log("gpu fp64 run for the FP32/FP64 speedup")
-        dt64, _, _, _ = run_gpu(cfg64, inp64, max(10, args.steps // 2), args.warmup, detail_steps=0)
+        dt64, _, _, _, _ = run_gpu(cfg64, inp64, max(10, args.steps // 2), args.warmup, detail_steps=0)
         fp64 = N * max(10, args.steps // 2) / dt64 / 1e6
         log(f"gpu fp64: {1e3 * dt64 / max(10, args.steps // 2):.3f} ms/step")
 
@@ -426,7 +437,7 @@ def main():
                    "precision": args.precision, "poisson_tol": cfg.poisson_tol,
                    "poisson_solver": "multigrid" if ob1["poisson_mg_levels"] else "sor",
                    "poisson_iterations_per_step": round(sweeps, 2),
-                   "poisson_start_residual": ob1["poisson_rel0"]},
+                   "poisson_start_residual": ob1["poisson_rel0"], "multigrid_autotune": tuned},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": round(traffic) if traffic else None, "traffic_unit": "bytes per launch",

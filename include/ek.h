@@ -193,6 +193,31 @@ ek_status ek_set_multigrid(struct ek_ctx* ctx, int32_t fine_pre, int32_t fine_po
                            int32_t coarse_post, int32_t tail_pre, int32_t tail_post, int32_t coarsest_sweeps,
                            double omega);
 
+/* Candidate V-cycle shapes of ek_autotune_multigrid, the default first: writes, if not
+   NULL, 7 counts per candidate to shapes (the first seven arguments of ek_set_multigrid
+   after the context, in order) and its omega to omegas.  Returns the number of candidates
+   (at most 16).  Needs no context or GPU. */
+int32_t ek_autotune_candidates(int32_t* shapes, double* omegas);
+
+/* Pick the V-cycle shape that steps this context fastest.  From the current state every
+   candidate runs one untimed step (which captures its cycle graph and estimates its
+   convergence rate), then trial_steps timed steps (HIP events on the context's stream),
+   each time from the same saved copy of the state, in two rounds over the candidates
+   (each candidate's faster round counts).  The state (populations, ions, potential and
+   its two predecessors, particles, step counters, warm-start bookkeeping) is restored
+   afterwards and the fastest shape set as by ek_set_multigrid; a candidate earlier in
+   the list (the default first) within 1 % of the fastest is preferred to it.  A step runs a
+   whole number of V-cycles, so a window of a few steps can favour a shape that happens
+   to save a cycle on those steps; about 100 trial steps follow the long-run rate.  best (host, may be NULL) receives its index in the
+   ek_autotune_candidates order, ms_per_step (host, may be NULL, room for every candidate)
+   each candidate's mean milliseconds per step.  Device memory: a copy of the state
+   (about (2 x 19 + 2) N element sizes + 24 N bytes), held only during the call.  The Poisson
+   tolerance of the context applies; a solve that stops at maxit counts with its time.
+   Synchronises.  Errors: EK_EINVAL (trial_steps outside 1..1000, a context solved by SOR),
+   EK_ESTATE (replica of a batch), EK_ENOMEM, EK_EHIP; on an error the shape in place
+   before the call is kept. */
+ek_status ek_autotune_multigrid(struct ek_ctx* ctx, int32_t trial_steps, int32_t* best, double* ms_per_step);
+
 /* FP64 totals and diagnostics of the current state (synchronises the stream).
    Returns EK_ENONFINITE if populations or ion densities hold a NaN or Inf. */
 ek_status ek_observables(struct ek_ctx* ctx, ek_obs* out);

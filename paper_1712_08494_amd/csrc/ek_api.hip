@@ -103,6 +103,7 @@ struct ek_ctx {
     void* q_own = nullptr;
     double* phi_own = nullptr;
     bool vc_off = false;
+    void* tune_buf = nullptr;  // state copy of the autotuner (held only while it runs)
     // timing: 0 off, 1 kernel classes, 2 classes and every lattice-level smoothing pass
     int timing = 0;
     std::vector<TimeRec> recs;
@@ -1242,6 +1243,31 @@ extern "C" ek_status ek_adjoint(ek_ctx* c, const double* adj_f, const double* ad
     return worst;
 }
 
+// The shapes the autotuner tries, the default first.
+struct CycleShape {
+    int v[7];  // fine pre/post, launched coarse grids pre/post, tail grid pre/post, coarsest sweeps
+    double omega;
+};
+static const CycleShape kCycleShapes[] = {
+    {{1, 2, 1, 2, 3, 3, 20}, 1.2}, {{1, 2, 3, 3, 3, 3, 20}, 1.2}, {{1, 2, 1, 2, 4, 4, 20}, 1.2},
+    {{1, 2, 2, 2, 3, 3, 20}, 1.2}, {{1, 2, 1, 2, 3, 3, 20}, 1.1}, {{2, 2, 1, 2, 3, 3, 20}, 1.2},
+    {{2, 2, 2, 2, 2, 2, 20}, 1.0},
+};
+constexpr int kNumCycleShapes = (int)(sizeof(kCycleShapes) / sizeof(kCycleShapes[0]));
+
+static void apply_shape(ek_ctx* c, const CycleShape& sh) {
+    c->mg_fine_pre = sh.v[0];
+    c->mg_fine_post = sh.v[1];
+    c->mg_pre = sh.v[2];
+    c->mg_post = sh.v[3];
+    c->mg_tail_pre = sh.v[4];
+    c->mg_tail_post = sh.v[5];
+    c->mg_coarsest = sh.v[6];
+    c->mg_omega = sh.omega;
+    c->rate = -1.0;        // the convergence rate of the new shape is estimated afresh
+    vcycle_graph_drop(c);  // the captured cycle has the old shape
+}
+
 extern "C" ek_status ek_set_multigrid(ek_ctx* c, int32_t fine_pre, int32_t fine_post, int32_t coarse_pre,
                                       int32_t coarse_post, int32_t tail_pre, int32_t tail_post,
                                       int32_t coarsest_sweeps, double omega) {
@@ -1253,17 +1279,153 @@ extern "C" ek_status ek_set_multigrid(ek_ctx* c, int32_t fine_pre, int32_t fine_
     if (fine_pre + fine_post == 0 || coarsest_sweeps == 0)
         return fail(c, EK_EINVAL, "the lattice needs a sweep per cycle and the coarsest grid at least one");
     if (!(omega > 0.0 && omega < 2.0)) return fail(c, EK_EINVAL, "omega must be in (0, 2)");
-    c->mg_fine_pre = fine_pre;
-    c->mg_fine_post = fine_post;
-    c->mg_pre = coarse_pre;
-    c->mg_post = coarse_post;
-    c->mg_tail_pre = tail_pre;
-    c->mg_tail_post = tail_post;
-    c->mg_coarsest = coarsest_sweeps;
-    c->mg_omega = omega;
-    c->rate = -1.0;
-    vcycle_graph_drop(c);  // the captured cycle has the old shape  // the convergence rate is re-estimated
+    CycleShape sh{{fine_pre, fine_post, coarse_pre, coarse_post, tail_pre, tail_post, coarsest_sweeps}, omega};
+    apply_shape(c, sh);
     return EK_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Autotuner of the V-cycle shape: every candidate runs the same steps from the same saved
+// state, timed with HIP events on the context's stream; the state is put back and the
+// fastest shape kept.
+// ------------------------------------------------------------------------------------
+namespace {
+struct HostState {
+    int cur, pcur, ws_order, ws_since, last_iters;
+    double rate, rel0_of[4], last_rel, last_mean, last_rel0;
+    long long steps, ptotal;
+};
+}  // namespace
+
+// Device state copy: populations and ions of the current buffers, the three potentials,
+// particle positions, velocities and last forces.
+static ek_status tune_copy(ek_ctx* c, bool save, HostState& h) {
+    const size_t N = c->N, pop = (size_t)kQ * N * c->esz, ion = N * c->esz, pb = (size_t)3 * c->np * 8;
+    char* b = (char*)c->tune_buf;
+    if (save) {
+        h = HostState{c->cur, c->pcur, c->ws_order, c->ws_since, c->last_iters, c->rate, {0, 0, 0, 0},
+                      c->last_rel, c->last_mean, c->last_rel0, c->steps, c->ptotal};
+        for (int k = 0; k < 4; ++k) h.rel0_of[k] = c->rel0_of[k];
+    } else {
+        c->cur = h.cur;
+        c->pcur = h.pcur;
+        c->ws_order = h.ws_order;
+        c->ws_since = h.ws_since;
+        c->last_iters = h.last_iters;
+        c->rate = h.rate;
+        for (int k = 0; k < 4; ++k) c->rel0_of[k] = h.rel0_of[k];
+        c->last_rel = h.last_rel;
+        c->last_mean = h.last_mean;
+        c->last_rel0 = h.last_rel0;
+        c->steps = h.steps;
+        c->ptotal = h.ptotal;
+    }
+    void* dev[] = {c->f[c->cur][0], c->f[c->cur][1], c->n[c->cur][0], c->n[c->cur][1], c->phi, c->phi_prev,
+                   c->phi_prev2, c->np ? c->px[c->pcur] : nullptr, c->np ? c->pv[c->pcur] : nullptr,
+                   c->np ? c->pF : nullptr};
+    const size_t len[] = {pop, pop, ion, ion, N * 8, N * 8, N * 8, pb, pb, pb};
+    for (int k = 0; k < 10; ++k) {
+        if (!dev[k] || !len[k]) continue;
+        if (save)
+            EK_HIP(hipMemcpyAsync(b, dev[k], len[k], hipMemcpyDeviceToDevice, c->st));
+        else
+            EK_HIP(hipMemcpyAsync(dev[k], b, len[k], hipMemcpyDeviceToDevice, c->st));
+        b += (len[k] + 255) & ~(size_t)255;
+    }
+    return EK_OK;
+}
+
+static size_t tune_bytes(const ek_ctx* c) {
+    const size_t N = c->N, pb = (size_t)3 * c->np * 8;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    return 2 * up(kQ * N * c->esz) + 2 * up(N * c->esz) + 3 * up(N * 8) + 3 * up(pb);
+}
+
+template <typename T>
+static ek_status autotune_impl(ek_ctx* c, int trial, int* best, double* ms_out) {
+    if (!c->tune_buf) EK_TRY(dalloc(c, &c->tune_buf, tune_bytes(c)));
+    const CycleShape orig{{c->mg_fine_pre, c->mg_fine_post, c->mg_pre, c->mg_post, c->mg_tail_pre, c->mg_tail_post,
+                           c->mg_coarsest},
+                          c->mg_omega};
+    HostState h{};
+    EK_TRY(tune_copy(c, true, h));
+    hipEvent_t ev[2];
+    EK_HIP(hipEventCreate(&ev[0]));
+    EK_HIP(hipEventCreate(&ev[1]));
+    const int timing = c->timing;
+    c->timing = 0;
+    double per[kNumCycleShapes];
+    for (int k = 0; k < kNumCycleShapes; ++k) per[k] = 1e300;
+    ek_status st = EK_OK;
+    // Two rounds over the candidates, each candidate's best round counts (clock and
+    // thermal drift during the sweep hit every candidate alike).  Each trial: the saved
+    // state, one untimed step that captures the cycle graph and estimates the cycle's
+    // convergence rate, the saved state again (keeping that rate), the timed steps.
+    for (int round = 0; round < 2 && st == EK_OK; ++round)
+        for (int k = 0; k < kNumCycleShapes && st == EK_OK; ++k) {
+            apply_shape(c, kCycleShapes[k]);
+            st = tune_copy(c, false, h);
+            c->rate = -1.0;
+            if (st == EK_OK) st = step_impl<T>(c, 1);
+            if (st == EK_ENOCONV) st = EK_OK;
+            const double rate = c->rate;
+            if (st == EK_OK) st = tune_copy(c, false, h);
+            if (st != EK_OK) break;
+            c->rate = rate;
+            (void)hipEventRecord(ev[0], c->st);
+            st = step_impl<T>(c, trial);
+            if (st == EK_ENOCONV) st = EK_OK;
+            (void)hipEventRecord(ev[1], c->st);
+            if (hipEventSynchronize(ev[1]) != hipSuccess) st = EK_EHIP;
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+            per[k] = std::min(per[k], (double)ms / trial);
+        }
+    // the fastest, unless an earlier candidate (the default first) is within 1 % of it
+    int arg = 0;
+    for (int k = 1; k < kNumCycleShapes; ++k)
+        if (per[k] < per[arg]) arg = k;
+    for (int k = 0; k < arg; ++k)
+        if (per[k] <= 1.01 * per[arg]) {
+            arg = k;
+            break;
+        }
+    if (ms_out)
+        for (int k = 0; k < kNumCycleShapes; ++k) ms_out[k] = per[k];
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    c->timing = timing;
+    const CycleShape& b = st == EK_OK ? kCycleShapes[arg] : orig;
+    apply_shape(c, b);
+    const ek_status rs = tune_copy(c, false, h);
+    bool same = b.omega == orig.omega;
+    for (int j = 0; j < 7; ++j) same = same && b.v[j] == orig.v[j];
+    if (!same) c->rate = -1.0;  // the restored rate belongs to the old shape
+    EK_HIP(hipStreamSynchronize(c->st));
+    dfree(c, c->tune_buf, tune_bytes(c));
+    c->tune_buf = nullptr;
+    if (st != EK_OK) return st;
+    EK_TRY(rs);
+    if (best) *best = arg;
+    return EK_OK;
+}
+
+extern "C" int32_t ek_autotune_candidates(int32_t* shapes, double* omegas) {
+    for (int k = 0; k < kNumCycleShapes; ++k) {
+        if (shapes)
+            for (int j = 0; j < 7; ++j) shapes[7 * k + j] = kCycleShapes[k].v[j];
+        if (omegas) omegas[k] = kCycleShapes[k].omega;
+    }
+    return kNumCycleShapes;
+}
+
+extern "C" ek_status ek_autotune_multigrid(ek_ctx* c, int32_t trial_steps, int32_t* best, double* ms_per_step) {
+    if (!c || !c->phi) return EK_ESTATE;
+    if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: its cycle is fixed by the batch");
+    if (c->mg.empty()) return fail(c, EK_EINVAL, "this lattice is solved by SOR: there is no V-cycle to tune");
+    if (trial_steps < 1 || trial_steps > 1000) return fail(c, EK_EINVAL, "trial_steps must be in 1..1000");
+    return c->esz == 4 ? autotune_impl<float>(c, trial_steps, best, ms_per_step)
+                       : autotune_impl<double>(c, trial_steps, best, ms_per_step);
 }
 
 extern "C" ek_status ek_observables(ek_ctx* c, ek_obs* out) {

@@ -58,7 +58,8 @@ EXPORTS = ["ek_lattice", "ek_init", "ek_step", "ek_poisson", "ek_observables", "
            "ek_get_populations", "ek_get_particles", "ek_device_bytes", "ek_set_timing", "ek_get_timing",
            "ek_destroy", "ek_status_str", "ek_last_error", "ek_batch_init", "ek_batch_step", "ek_batch_sync",
            "ek_batch_residuals", "ek_batch_replica", "ek_batch_destroy", "ek_batch_last_error",
-           "ek_forward_ckpt", "ek_adjoint", "ek_set_multigrid"]
+           "ek_forward_ckpt", "ek_adjoint", "ek_set_multigrid", "ek_autotune_candidates",
+           "ek_autotune_multigrid"]
 
 _lib = None
 
@@ -134,6 +135,11 @@ def load(path=LIB_PATH):
     L.ek_adjoint.restype = ctypes.c_int32
     L.ek_set_multigrid.argtypes = [vp] + [ctypes.c_int32] * 7 + [ctypes.c_double]
     L.ek_set_multigrid.restype = ctypes.c_int32
+    L.ek_autotune_candidates.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+    L.ek_autotune_candidates.restype = ctypes.c_int32
+    L.ek_autotune_multigrid.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_double)]
+    L.ek_autotune_multigrid.restype = ctypes.c_int32
     _lib = L
     return L
 
@@ -145,6 +151,17 @@ def lattice():
     w = np.zeros(19)
     L.ek_lattice(c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return c, w
+
+
+def autotune_candidates():
+    """The V-cycle shapes the autotuner tries, the default first: (7 sweep counts in the
+    argument order of set_multigrid, omega)."""
+    L = load()
+    n = L.ek_autotune_candidates(None, None)
+    shapes = (ctypes.c_int32 * (7 * n))()
+    om = (ctypes.c_double * n)()
+    L.ek_autotune_candidates(shapes, om)
+    return [(tuple(shapes[7 * k:7 * k + 7]), om[k]) for k in range(n)]
 
 
 def _dp(a):
@@ -303,6 +320,19 @@ class EKSim:
         relaxation of the smoothing sweeps."""
         self._check(load().ek_set_multigrid(self._h, fine_pre, fine_post, coarse_pre, coarse_post, tail_pre,
                                             tail_post, coarsest, float(omega)), "ek_set_multigrid")
+
+    def autotune_multigrid(self, trial_steps=100):
+        """Time every candidate V-cycle shape over trial_steps steps from the current state,
+        restore the state and keep the fastest shape.  Returns (best index, the candidates
+        as (sweep counts, omega), milliseconds per step of each).  A step runs a whole
+        number of cycles, so a window of a few steps can favour a shape that happens to
+        save a cycle there; about 100 steps track the long-run rate."""
+        cands = autotune_candidates()
+        best = ctypes.c_int32(-1)
+        ms = (ctypes.c_double * len(cands))()
+        self._check(load().ek_autotune_multigrid(self._h, int(trial_steps), ctypes.byref(best), ms),
+                    "ek_autotune_multigrid")
+        return best.value, cands, list(ms)
 
     def forward_checkpointed(self, nsteps, every, allow_noconv=False):
         """nsteps steps keeping a checkpoint every `every` steps, for adjoint()."""

@@ -1,0 +1,77 @@
+"""ek_autotune_multigrid leaves the state as it found it and applies the V-cycle shape it
+reports: a run tuned part-way equals, bit for bit, a run that is given that shape with
+ek_set_multigrid at the same step."""
+import numpy as np
+import pytest
+
+from paper_1712_08494_amd import ek
+from paper_1712_08494_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    ek.load()
+    yield
+
+
+def _state(sim):
+    out = [sim.populations(0), sim.populations(1)]
+    out += [sim.field(k) for k in ("n_plus", "n_minus", "phi")]
+    p = sim.particles()
+    if p is not None and len(p):
+        out.append(np.asarray(p))
+    return out
+
+
+def _case(name):
+    if name == "walls_fp32":
+        return wl.walls_interface(shape=(64, 64, 64), precision="fp32")
+    return wl.colloids(shape=(64, 64, 64), count=6, precision="fp64")
+
+
+@pytest.mark.parametrize("name", ["walls_fp32", "colloids_fp64"])
+def test_autotune_restores_state_and_applies_shape(name):
+    cfg, inp = _case(name)
+    print(f"autotune {name} 64^3", flush=True)
+    a = ek.EKSim(cfg, inp)
+    a.step(4)
+    before = _state(a)
+    o0 = a.observables()
+    best, cands, ms = a.autotune_multigrid(trial_steps=3)
+    print("  " + ", ".join(f"{c}: {t:.3f} ms" for c, t in zip(cands, ms)) + f"  -> {best}", flush=True)
+    assert 0 <= best < len(cands)
+    assert all(np.isfinite(t) and t > 0 for t in ms)
+    assert ms[best] == min(ms)
+    for x, y in zip(before, _state(a)):
+        assert np.array_equal(x, y)
+    o1 = a.observables()
+    for k in ("steps", "poisson_total", "poisson_iters", "poisson_rel"):
+        assert o1[k] == o0[k], (k, o0[k], o1[k])
+
+    a.step(4)
+    b = ek.EKSim(cfg, inp)
+    b.step(4)
+    if best != 0:
+        counts, omega = cands[best]
+        b.set_multigrid(*counts, omega=omega)
+    b.step(4)
+    for x, y in zip(_state(a), _state(b)):
+        assert np.array_equal(x, y)
+    assert a.observables()["poisson_total"] == b.observables()["poisson_total"]
+    a.close()
+    b.close()
+
+
+def test_autotune_rejects_sor_contexts():
+    cfg, inp = wl.mixture_noise(n=16, precision="fp64")
+    cfg.poisson_solver = "sor"
+    sim = ek.EKSim(cfg, inp)
+    with pytest.raises(ek.EKError) as e:
+        sim.autotune_multigrid(2)
+    assert e.value.status == ek.EK_EINVAL
+    sim.close()
