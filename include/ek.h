@@ -185,7 +185,7 @@ ek_status ek_poisson(struct ek_ctx* ctx, double tol, int32_t maxit, int32_t* ite
    (fine_pre, fine_post), on the coarse grids smoothed by separate launches (coarse_pre,
    coarse_post) and on the upper grid of the last two, which one workgroup handles in LDS
    (tail_pre, tail_post); red-black SOR sweeps on the coarsest grid; omega relaxes the
-   smoothing sweeps (1 is Gauss-Seidel).  Defaults 1, 2, 1, 2, 3, 3, 20, 1.2.  Counts in
+   smoothing sweeps (1 is Gauss-Seidel).  Defaults 1, 2, 1, 2, 3, 3, 10, 1.2.  Counts in
    0..64, omega in (0, 2); the lattice needs at least one sweep per cycle.  The solve still
    runs to the Poisson tolerance; the shape only trades work per cycle against cycles.
    Errors: EK_EINVAL, EK_ESTATE. */

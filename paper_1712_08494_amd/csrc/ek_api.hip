@@ -90,7 +90,7 @@ struct ek_ctx {
     double mg_coarse_omega = 1.0;
     // V-cycle shape: red-black sweeps before and after the coarse correction on the
     // lattice and on the coarse grids, and sweeps on the coarsest grid
-    int mg_fine_pre = 1, mg_fine_post = 2, mg_pre = 1, mg_post = 2, mg_coarsest = 20;
+    int mg_fine_pre = 1, mg_fine_post = 2, mg_pre = 1, mg_post = 2, mg_coarsest = 10;
     int mg_tail_pre = 3, mg_tail_post = 3;  // sweeps on the upper grid of the single-workgroup tail
     double mg_omega = 1.2;  // relaxation of the smoothing sweeps (1: Gauss-Seidel)
     // One V-cycle captured as a HIP graph and replayed for each cycle of a solve (one host
@@ -920,12 +920,14 @@ extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const doub
         if (c->mg.empty() && p->poisson_solver == EK_POISSON_MG)
             return fail(c, EK_EINVAL, "multigrid needs every axis divisible by 4 and a coarsest grid of at most 4608 cells");
         if (!c->mg.empty()) {
-            // SOR factor of the coarsest level (uniform-coefficient estimate)
+            // SOR factor of the coarsest level (uniform-coefficient estimate).  With walls the
+            // coarse grids have zero faces where z wraps, so all their nz cells form a closed
+            // column, as the nz - 2 fluid layers do on the lattice: its smoothest mode sets
+            // the factor.
             ek_params q = *p;
             q.nx = c->mg.back().nx;
             q.ny = c->mg.back().ny;
-            q.nz = c->mg.back().nz;
-            q.walls_z = 0;
+            q.nz = c->mg.back().nz + (p->walls_z ? 2 : 0);
             c->mg_coarse_omega = std::min(1.9, omega_for(q));
         }
     }
@@ -1249,9 +1251,9 @@ struct CycleShape {
     double omega;
 };
 static const CycleShape kCycleShapes[] = {
-    {{1, 2, 1, 2, 3, 3, 20}, 1.2}, {{1, 2, 3, 3, 3, 3, 20}, 1.2}, {{1, 2, 1, 2, 4, 4, 20}, 1.2},
-    {{1, 2, 2, 2, 3, 3, 20}, 1.2}, {{1, 2, 1, 2, 3, 3, 20}, 1.1}, {{2, 2, 1, 2, 3, 3, 20}, 1.2},
-    {{2, 2, 2, 2, 2, 2, 20}, 1.0},
+    {{1, 2, 1, 2, 3, 3, 10}, 1.2}, {{1, 2, 1, 2, 2, 2, 10}, 1.2}, {{1, 2, 1, 2, 4, 4, 8}, 1.2},
+    {{1, 2, 1, 1, 3, 3, 10}, 1.2}, {{1, 2, 2, 2, 3, 3, 10}, 1.2}, {{1, 2, 1, 2, 3, 3, 10}, 1.3},
+    {{1, 2, 1, 2, 3, 3, 20}, 1.2}, {{2, 2, 1, 2, 3, 3, 10}, 1.2},
 };
 constexpr int kNumCycleShapes = (int)(sizeof(kCycleShapes) / sizeof(kCycleShapes[0]));
 
@@ -1637,7 +1639,7 @@ static RepDesc<T> make_desc(ek_ctx* c, int parity) {
     d.nl = nl;
     for (int l = 0; l < nl; ++l) d.mg[l] = c->mg[l];
     d.tail_mid = (nl >= 2 && c->mg[nl - 2].n <= 4096 && c->mg[nl - 1].n <= 512) ? 1 : 0;
-    d.coarse_iters = 20;
+    d.coarse_iters = c->mg_coarsest;
     d.coarse_omega = c->mg_coarse_omega;
     d.mid_pre = c->mg_tail_pre;
     d.mid_post = c->mg_tail_post;

@@ -759,14 +759,13 @@ void launch_mg_prolong(const MGLevel& c, const MGLevel& f, hipStream_t st) {
     hipLaunchKernelGGL(k_mg_prolong, dim3((f.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c, f);
 }
 
-// The last two levels in one workgroup: on the smaller of them ("mid", at most
-// kTailMid cells) two red-black Gauss-Seidel sweeps, restriction to the coarsest level
-// (at most kTailCoarse cells), red-black SOR sweeps there, interpolation back and two
-// more sweeps.  Potentials, right-hand sides and face coefficients all live in LDS (the
-// mid grid's coefficients as float: this grid only carries a coarse-grid correction,
-// the lattice-level residual stays FP64).  When has_mid is 0 only the coarsest solve
-// runs, and the coarsest grid may use the whole allocation.
-constexpr int kTailThreads = 1024;
+// The last two levels in one workgroup: on the upper of them ("mid", at most kTailMid
+// cells) red-black Gauss-Seidel sweeps, restriction to the coarsest level (at most
+// kTailCoarse cells), red-black SOR sweeps there, interpolation back and more sweeps on
+// the mid grid.  The mid grid's face coefficients are float (this grid only carries a
+// coarse-grid correction; the lattice-level residual stays FP64).  When has_mid is 0 only
+// the coarsest solve runs, and the coarsest grid may use the whole LDS allocation.
+constexpr int kTailThreads = 512;
 constexpr unsigned kTailMid = 4096, kTailCoarse = 512;
 constexpr unsigned kTailCoarseOnly = kTailMid + kTailCoarse;
 
@@ -838,74 +837,249 @@ __device__ void tail_load_coeffs(const MGLevel& G, C* ax, C* ay, C* az) {
     }
 }
 
-__device__ void tail_body(const MGLevel& M, const MGLevel& Cg, int has_mid, int coarse_iters, double coarse_omega,
+// Exact floor(a / d) for a, d < 2^20 from a precomputed 1/d: (a + 0.5)/d lies at least
+// 0.5/d from an integer, far more than the rounding of two FP64 operations.
+__device__ __forceinline__ unsigned div_exact(unsigned a, double inv_d) {
+    return (unsigned)(((double)a + 0.5) * inv_d);
+}
+
+// Cell h of colour c of a red-black grid (h < n/2, even nx): coordinates.
+__device__ __forceinline__ void rb_cell(unsigned h, int c, unsigned hx, double inv_hx, int ny, double inv_ny, int& x,
+                                        int& y, int& z) {
+    const unsigned row = div_exact(h, inv_hx), m = h - row * hx;
+    z = (int)div_exact(row, inv_ny);
+    y = (int)row - z * ny;
+    x = 2 * (int)m + ((c + y + z) & 1);
+}
+
+// Periodic neighbour indices of cell i = (x, y, z), packed (+1 side | -1 side << 16).
+struct PackedNbr {
+    unsigned x, y, z;
+};
+
+__device__ __forceinline__ PackedNbr packed_nbr(unsigned i, int x, int y, int z, int nx, int ny, int nz) {
+    const unsigned nxu = (unsigned)nx, nxy = (unsigned)(nx * ny), n = nxy * (unsigned)nz;
+    const unsigned xm = x == 0 ? i + nxu - 1 : i - 1, xp = x == nx - 1 ? i + 1 - nxu : i + 1;
+    const unsigned ym = y == 0 ? i + nxy - nxu : i - nxu, yp = y == ny - 1 ? i + nxu - nxy : i + nxu;
+    const unsigned zm = z == 0 ? i + n - nxy : i - nxy, zp = z == nz - 1 ? i + nxy - n : i + nxy;
+    return PackedNbr{xp | (xm << 16), yp | (ym << 16), zp | (zm << 16)};
+}
+
+// An owned cell of the mid grid with its row in registers.
+struct MidRow {
+    unsigned i;  // cell index (n when the slot is empty)
+    PackedNbr nb;
+    float a0, a1, b0, b1, c0, c1;  // faces to +x, -x, +y, -y, +z, -z
+    float idiag;                   // 1 / diagonal (0 for a decoupled cell)
+    double rhs, phi;
+};
+
+// The tail with a mid grid.  Every cell is owned by one thread (cell h of each colour by
+// thread h % NT), which keeps its row (neighbour indices, coefficients, inverse diagonal,
+// right-hand side) and its potential in registers for the whole call; LDS holds the
+// potentials the neighbours read, and the residuals for the restriction.  Loads are
+// coalesced through LDS.  The arithmetic and its order are those of the row-by-row form
+// (tail_row, tail_sweeps), so the result does not depend on the thread count.
+template <int NT>
+__device__ __forceinline__ void tail_mid_body(const MGLevel M, const MGLevel Cg, int coarse_iters, double coarse_omega, int mid_pre,
+                              int mid_post, double mid_omega) {
+    extern __shared__ double lds[];
+    constexpr int kSlots = kTailMid / 2 / NT;
+    double* phim = lds;
+    double* res = phim + kTailMid;  // right-hand side while loading, then the residuals
+    double* phic = res + kTailMid;
+    double* sc = phic + kTailCoarse;
+    double* cax = sc + kTailCoarse;
+    double* cay = cax + kTailCoarse;
+    double* caz = cay + kTailCoarse;
+    float* fax = (float*)(caz + kTailCoarse);
+    float* fay = fax + kTailMid;
+    float* faz = fay + kTailMid;
+    for (unsigned t = threadIdx.x; t < M.n; t += NT) {
+        fax[t] = (float)M.ax[t];
+        fay[t] = (float)M.ay[t];
+        faz[t] = (float)M.az[t];
+        res[t] = M.s[t];
+    }
+    for (unsigned t = threadIdx.x; t < Cg.n; t += NT) {
+        cax[t] = Cg.ax[t];
+        cay[t] = Cg.ay[t];
+        caz[t] = Cg.az[t];
+    }
+    __syncthreads();
+    const unsigned halfm = M.n / 2, hxm = (unsigned)(M.nx >> 1);
+    const double inv_hxm = 1.0 / hxm, inv_nym = 1.0 / M.ny;
+    MidRow R[2][kSlots];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            MidRow& r = R[c][k];
+            const unsigned h = threadIdx.x + k * NT;
+            r.i = M.n;
+            if (h < halfm) {
+                int x, y, z;
+                rb_cell(h, c, hxm, inv_hxm, M.ny, inv_nym, x, y, z);
+                const unsigned i = (unsigned)x + (unsigned)M.nx * ((unsigned)y + (unsigned)M.ny * (unsigned)z);
+                r.i = i;
+                r.nb = packed_nbr(i, x, y, z, M.nx, M.ny, M.nz);
+                r.a0 = fax[i];
+                r.a1 = fax[r.nb.x >> 16];
+                r.b0 = fay[i];
+                r.b1 = fay[r.nb.y >> 16];
+                r.c0 = faz[i];
+                r.c1 = faz[r.nb.z >> 16];
+                const double a0 = r.a0, a1 = r.a1, b0 = r.b0, b1 = r.b1, c0 = r.c0, c1 = r.c1;
+                const double diag = a0 + a1 + b0 + b1 + c0 + c1;
+                r.idiag = diag > 0.0 ? (float)(1.0 / diag) : 0.0f;
+                r.rhs = res[i];
+                r.phi = 0.0;
+                phim[i] = 0.0;
+            }
+        }
+    __syncthreads();
+    // (both lambdas must inline: the row array has to stay in registers)
+    auto off_of = [&](const MidRow& r) __attribute__((always_inline)) {
+        const double a0 = r.a0, a1 = r.a1, b0 = r.b0, b1 = r.b1, c0 = r.c0, c1 = r.c1;
+        return a0 * phim[r.nb.x & 0xffffu] + a1 * phim[r.nb.x >> 16] + b0 * phim[r.nb.y & 0xffffu] +
+               b1 * phim[r.nb.y >> 16] + c0 * phim[r.nb.z & 0xffffu] + c1 * phim[r.nb.z >> 16];
+    };
+    auto mid_sweeps = [&](int sweeps) __attribute__((always_inline)) {
+        for (int it = 0; it < sweeps; ++it)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+#pragma unroll
+                for (int k = 0; k < kSlots; ++k) {
+                    MidRow& r = R[c][k];
+                    if (r.i < M.n) {
+                        const double off = off_of(r);
+                        r.phi = r.phi + mid_omega * ((off + r.rhs) * (double)r.idiag - r.phi);
+                        phim[r.i] = r.phi;
+                    }
+                }
+                __syncthreads();
+            }
+    };
+    mid_sweeps(mid_pre);
+    // residuals of the owned cells (the right-hand side in res is no longer needed: every
+    // owner holds its own), then the coarse right-hand side: the sum over eight children
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            const MidRow& r = R[c][k];
+            if (r.i < M.n) {
+                const double a0 = r.a0, a1 = r.a1, b0 = r.b0, b1 = r.b1, c0 = r.c0, c1 = r.c1;
+                const double diag = a0 + a1 + b0 + b1 + c0 + c1;
+                const double off = off_of(r);
+                res[r.i] = r.rhs + off - diag * r.phi;
+            }
+        }
+    __syncthreads();
+    const unsigned mnx = (unsigned)M.nx, mnxy = (unsigned)(M.nx * M.ny);
+    const unsigned cnx = (unsigned)Cg.nx, cnxy = (unsigned)(Cg.nx * Cg.ny);
+    const double inv_cnx = 1.0 / cnx, inv_cny = 1.0 / Cg.ny;
+    for (unsigned t = threadIdx.x; t < Cg.n; t += NT) {
+        const unsigned r = div_exact(t, inv_cnx), I = t - r * cnx;
+        const unsigned K = div_exact(r, inv_cny), J = r - K * (unsigned)Cg.ny;
+        const unsigned b = 2 * I + mnx * 2 * J + mnxy * 2 * K;
+        double sum = 0.0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+                for (int a = 0; a < 2; ++a) sum += res[b + a + mnx * bb + mnxy * c];
+        sc[t] = sum;
+        phic[t] = 0.0;
+    }
+    __syncthreads();
+    // coarsest grid: thread h < n/2 owns cell h of each colour
+    const unsigned halfc = Cg.n / 2, hxc = cnx >> 1;
+    const double inv_hxc = 1.0 / hxc;
+    unsigned ci[2];
+    PackedNbr cn[2];
+    double cidg[2], crhs[2], cphi[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        ci[c] = Cg.n;
+        const unsigned h = threadIdx.x;
+        if (h < halfc) {
+            int x, y, z;
+            rb_cell(h, c, hxc, inv_hxc, Cg.ny, inv_cny, x, y, z);
+            const unsigned i = (unsigned)x + cnx * (unsigned)y + cnxy * (unsigned)z;
+            ci[c] = i;
+            cn[c] = packed_nbr(i, x, y, z, Cg.nx, Cg.ny, Cg.nz);
+            const double a0 = cax[i], a1 = cax[cn[c].x >> 16], b0 = cay[i], b1 = cay[cn[c].y >> 16];
+            const double c0 = caz[i], c1 = caz[cn[c].z >> 16];
+            const double diag = a0 + a1 + b0 + b1 + c0 + c1;
+            cidg[c] = diag > 0.0 ? 1.0 / diag : 0.0;
+            crhs[c] = sc[i];
+            cphi[c] = 0.0;
+        }
+    }
+    for (int it = 0; it < coarse_iters; ++it)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if (ci[c] < Cg.n) {
+                const unsigned i = ci[c];
+                const PackedNbr& q = cn[c];
+                const double a0 = cax[i], a1 = cax[q.x >> 16], b0 = cay[i], b1 = cay[q.y >> 16];
+                const double c0 = caz[i], c1 = caz[q.z >> 16];
+                const double off = a0 * phic[q.x & 0xffffu] + a1 * phic[q.x >> 16] + b0 * phic[q.y & 0xffffu] +
+                                   b1 * phic[q.y >> 16] + c0 * phic[q.z & 0xffffu] + c1 * phic[q.z >> 16];
+                cphi[c] = cphi[c] + coarse_omega * ((off + crhs[c]) * cidg[c] - cphi[c]);
+                phic[i] = cphi[c];
+            }
+            __syncthreads();
+        }
+    // trilinear interpolation of the coarse correction onto the owned cells (parent only
+    // across a zero face)
+    const double inv_mnx = 1.0 / mnx, inv_mny = 1.0 / M.ny;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            MidRow& r = R[c][k];
+            if (r.i < M.n) {
+                const unsigned row = div_exact(r.i, inv_mnx);
+                const int x = (int)(r.i - row * mnx);
+                const int z = (int)div_exact(row, inv_mny), y = (int)row - z * M.ny;
+                const int I = x >> 1, J = y >> 1, K = z >> 1;
+                const int dx = (x & 1) ? 1 : -1, dy = (y & 1) ? 1 : -1, dz = (z & 1) ? 1 : -1;
+                const unsigned In = wrapc(I + dx, Cg.nx), Jn = cnx * wrapc(J + dy, Cg.ny), Kn = cnxy * wrapc(K + dz, Cg.nz);
+                const unsigned I0 = I, J0 = cnx * J, K0 = cnxy * K;
+                const double fx = cax[(dx > 0 ? I0 : In) + J0 + K0];
+                const double fy = cay[I0 + (dy > 0 ? J0 : Jn) + K0];
+                const double fz = caz[I0 + J0 + (dz > 0 ? K0 : Kn)];
+                const double wx = fx > 0.0 ? 0.25 : 0.0, wy = fy > 0.0 ? 0.25 : 0.0, wz = fz > 0.0 ? 0.25 : 0.0;
+                const unsigned xs[2] = {I0, In}, ys[2] = {J0, Jn}, zs[2] = {K0, Kn};
+                const double wxs[2] = {1.0 - wx, wx}, wys[2] = {1.0 - wy, wy}, wzs[2] = {1.0 - wz, wz};
+                double v = 0.0;
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int a = 0; a < 2; ++a) v += wxs[a] * wys[b] * wzs[cc] * phic[xs[a] + ys[b] + zs[cc]];
+                r.phi += v;
+                phim[r.i] = r.phi;
+            }
+        }
+    __syncthreads();
+    mid_sweeps(mid_post);
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k)
+            if (R[c][k].i < M.n) M.phi[R[c][k].i] = R[c][k].phi;
+}
+
+__device__ __forceinline__ void tail_body(const MGLevel& M, const MGLevel& Cg, int has_mid, int coarse_iters, double coarse_omega,
                           int mid_pre = 2, int mid_post = 2, double mid_omega = 1.0) {
     extern __shared__ double lds[];
     if (has_mid) {
-        double* phim = lds;
-        double* sm = phim + kTailMid;
-        double* phic = sm + kTailMid;
-        double* sc = phic + kTailCoarse;
-        double* cax = sc + kTailCoarse;
-        double* cay = cax + kTailCoarse;
-        double* caz = cay + kTailCoarse;
-        double* cid = caz + kTailCoarse;
-        float* max_ = (float*)(cid + kTailCoarse);
-        float* may = max_ + kTailMid;
-        float* maz = may + kTailMid;
-        float* mid_ = maz + kTailMid;
-        tail_load_coeffs(M, max_, may, maz);
-        tail_load_coeffs(Cg, cax, cay, caz);
-        for (unsigned t = threadIdx.x; t < M.n; t += blockDim.x) {
-            phim[t] = 0.0;
-            sm[t] = M.s[t];
-        }
-        __syncthreads();
-        const TailGrid<float> Lm{M.nx, M.ny, M.nz, M.n, phim, sm, max_, may, maz, mid_};
-        const TailGrid<double> Lc{Cg.nx, Cg.ny, Cg.nz, Cg.n, phic, sc, cax, cay, caz, cid};
-        tail_inverse_diagonal(Lm);
-        tail_inverse_diagonal(Lc);
-        __syncthreads();
-        tail_sweeps(Lm, mid_pre, mid_omega);
-        // restriction: sum of the eight children's residuals
-        for (unsigned t = threadIdx.x; t < Cg.n; t += blockDim.x) {
-            const int I = t % Cg.nx, r = t / Cg.nx, J = r % Cg.ny, K = r / Cg.ny;
-            double sum = 0.0;
-            for (int c = 0; c < 2; ++c)
-                for (int b = 0; b < 2; ++b)
-                    for (int a = 0; a < 2; ++a) {
-                        const int x = 2 * I + a, y = 2 * J + b, z = 2 * K + c;
-                        double diag, off;
-                        tail_row(Lm, x, y, z, diag, off);
-                        const unsigned i = tid3(Lm, x, y, z);
-                        sum += sm[i] + off - diag * phim[i];
-                    }
-            sc[t] = sum;
-            phic[t] = 0.0;
-        }
-        __syncthreads();
-        tail_sweeps(Lc, coarse_iters, coarse_omega);
-        // trilinear interpolation of the coarse correction (parent only across a zero face)
-        for (unsigned t = threadIdx.x; t < M.n; t += blockDim.x) {
-            const int x = t % M.nx, r = t / M.nx, y = r % M.ny, z = r / M.ny;
-            const int I = x >> 1, J = y >> 1, K = z >> 1;
-            const int dx = (x & 1) ? 1 : -1, dy = (y & 1) ? 1 : -1, dz = (z & 1) ? 1 : -1;
-            const int In = wrapc(I + dx, Cg.nx), Jn = wrapc(J + dy, Cg.ny), Kn = wrapc(K + dz, Cg.nz);
-            const double fx = cax[tid3(Lc, dx > 0 ? I : In, J, K)];
-            const double fy = cay[tid3(Lc, I, dy > 0 ? J : Jn, K)];
-            const double fz = caz[tid3(Lc, I, J, dz > 0 ? K : Kn)];
-            const double wx = fx > 0.0 ? 0.25 : 0.0, wy = fy > 0.0 ? 0.25 : 0.0, wz = fz > 0.0 ? 0.25 : 0.0;
-            const int xs[2] = {I, In}, ys[2] = {J, Jn}, zs[2] = {K, Kn};
-            const double wxs[2] = {1.0 - wx, wx}, wys[2] = {1.0 - wy, wy}, wzs[2] = {1.0 - wz, wz};
-            double v = 0.0;
-            for (int c = 0; c < 2; ++c)
-                for (int b = 0; b < 2; ++b)
-                    for (int a = 0; a < 2; ++a) v += wxs[a] * wys[b] * wzs[c] * phic[tid3(Lc, xs[a], ys[b], zs[c])];
-            phim[t] += v;
-        }
-        __syncthreads();
-        tail_sweeps(Lm, mid_post, mid_omega);
-        for (unsigned t = threadIdx.x; t < M.n; t += blockDim.x) M.phi[t] = phim[t];
+        tail_mid_body<kTailThreads>(M, Cg, coarse_iters, coarse_omega, mid_pre, mid_post, mid_omega);
     } else {
         double* phic = lds;
         double* sc = phic + kTailCoarseOnly;
@@ -934,7 +1108,7 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MGLevel M, MGLevel Cg,
 }
 
 size_t mg_tail_lds_bytes() {
-    const size_t with_mid = 2 * kTailMid * 8 + 6 * kTailCoarse * 8 + 4 * kTailMid * 4;
+    const size_t with_mid = 2 * kTailMid * 8 + 5 * kTailCoarse * 8 + 3 * kTailMid * 4;
     const size_t coarse_only = 2 * kTailCoarseOnly * 8 + 4 * kTailCoarseOnly * 4;
     return with_mid > coarse_only ? with_mid : coarse_only;
 }

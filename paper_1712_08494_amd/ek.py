@@ -314,7 +314,7 @@ class EKSim:
         return {name: (t.ms[k], t.count[k]) for k, name in enumerate(TIMING_CLASSES)}
 
     def set_multigrid(self, fine_pre=1, fine_post=2, coarse_pre=1, coarse_post=2, tail_pre=3, tail_post=3,
-                      coarsest=20, omega=1.2):
+                      coarsest=10, omega=1.2):
         """V-cycle shape: sweeps before/after the correction on the lattice, on the launched
         coarse grids and on the tail kernel's upper grid, coarsest-grid sweeps, and the
         relaxation of the smoothing sweeps."""
