@@ -84,7 +84,7 @@ __device__ __forceinline__ void block_sum_add(double (&v)[NV], double* gred, int
         for (int k = 0; k < NV; ++k) {
             double a = sm[k][0];
             for (int w = 1; w < kBlock / 64; ++w) a += sm[k][w];
-            gred[(size_t)blockIdx.x * kRedSlots + base + k] += a;
+            gred[(size_t)(base + k) * gridDim.x + blockIdx.x] += a;
         }
     }
 }
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_rhs(Scalars S, Fields<double> F,
         v[0] = l;
     }
     const bool mx[1] = {false};
-    block_reduce_store<1>(v, mx, F.red, blockIdx.x);
+    block_reduce_store<1>(v, mx, F.red, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------------------------

@@ -402,8 +402,9 @@ static ek_status build_geometry(ek_ctx* c, const ek_particle* parts, int np, Hos
 template <typename T>
 static ek_status check_residual(ek_ctx* c, double& rr, double& ss) {
     Fields<T> F = fields<T>(c);
-    launch_residual<T>(c->S, F, c->nblk, c->st);
-    launch_reduce(c->red, c->nblk, 3, nullptr, c->scal + 1, c->st);
+    const unsigned nres = residual_blocks(c->N);
+    launch_residual<T>(c->S, F, nres, c->st);
+    launch_reduce(c->red, nres, 3, nullptr, c->scal + 1, c->st);
     EK_HIP(hipMemcpyAsync(c->hscal, c->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, c->st));
     EK_HIP(hipStreamSynchronize(c->st));
     rr = c->hscal[1];
@@ -515,7 +516,7 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
     ek_status status = EK_OK;
     double rel = 0.0;
     if (!(ss > 0.0)) {
-        launch_phi_finalize(c->S, c->phi, c->scal, 1, c->st);
+        launch_phi_finalize<T>(c->S, F, 1, c->st);
     } else {
         const double target = tol * std::sqrt(ss);
         double r = std::sqrt(rr);
@@ -564,11 +565,10 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
             }
             r = rn;
         }
-        launch_phi_finalize(c->S, c->phi, c->scal, 0, c->st);
+        launch_phi_finalize<T>(c->S, F, 0, c->st);
         rel = r / std::sqrt(ss);
         if (r > target) status = EK_ENOCONV;
     }
-    launch_phi_ghosts<T>(c->S, F, c->st);
     EK_HIP(hipGetLastError());
     c->last_iters = it;
     c->last_rel = rel;

@@ -72,11 +72,13 @@ __device__ __forceinline__ double efield_sq(int x, int y, int z, const double* p
 __device__ __forceinline__ bool wall_layer(int z, const Scalars& S) { return S.walls && (z == 0 || z == S.nz - 1); }
 
 // ------------------------------------------------------------------------------------
-// FP64 block reduction of NV values (sums, or maxima where is_max) into red[blockIdx].
+// FP64 block reduction of NV values (sums, or maxima where is_max) into record `slot` of
+// nrec records, stored value-major (value k of record b at red[k * nrec + b]) so that a
+// reducer reads each value's records contiguously.
 // ------------------------------------------------------------------------------------
 template <int NV>
 __device__ __forceinline__ void block_reduce_store(double (&v)[NV], const bool (&is_max)[NV], double* red,
-                                                   unsigned slot) {
+                                                   unsigned slot, unsigned nrec) {
     __shared__ double sm[NV][kBlock / 64];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -99,7 +101,7 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], const bool (
         for (int k = 0; k < NV; ++k) {
             double a = sm[k][0];
             for (int w = 1; w < kBlock / 64; ++w) a = is_max[k] ? fmax(a, sm[k][w]) : a + sm[k][w];
-            red[(size_t)slot * kRedSlots + k] = a;
+            red[(size_t)k * nrec + slot] = a;
         }
     }
 }

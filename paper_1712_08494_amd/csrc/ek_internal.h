@@ -10,6 +10,7 @@ namespace ek {
 
 constexpr int kBlock = 256;   // threads per site-kernel workgroup (4 wave64)
 constexpr int kRedSlots = 12; // doubles per workgroup in reduction scratch
+constexpr int kResSites = 4;   // sites per thread of the residual kernel
 
 // Scalar parameters of a context, passed by value to every kernel.
 struct Scalars {
@@ -71,6 +72,7 @@ struct MGLevel {
 };
 
 unsigned site_blocks(unsigned n);
+unsigned residual_blocks(unsigned n);  // workgroups of the residual kernel for n sites
 
 // Reverse-mode (adjoint) fields of a periodic FP64 context for one reverse step: the
 // sensitivities of a scalar objective L to the step's inputs and intermediates.  All
@@ -148,10 +150,10 @@ void launch_source_mean(const Scalars& S, double* red, unsigned nblk, double* sc
 template <typename T> void launch_sor(const Scalars& S, const Fields<T>& F, int color, double omega, hipStream_t st);
 template <typename T> void launch_residual(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
 void launch_reduce(const double* red, unsigned nblk, int nvals, const int* is_max, double* out, hipStream_t st);
-void launch_phi_finalize(const Scalars& S, double* phi, const double* scal, int zero, hipStream_t st);
+// gauge mean(phi) = 0 (phi = 0 when zero != 0) and the wall layers of the potential
+template <typename T> void launch_phi_finalize(const Scalars& S, const Fields<T>& F, int zero, hipStream_t st);
 void launch_phi_extrapolate(const Scalars& S, double* phi, double* prev, double* prev2, int history,
                             hipStream_t st);
-template <typename T> void launch_phi_ghosts(const Scalars& S, const Fields<T>& F, hipStream_t st);
 template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hipStream_t st);
 template <typename T> void launch_fused(const Scalars& S, const Fields<T>& F, hipStream_t st);
 template <typename T>

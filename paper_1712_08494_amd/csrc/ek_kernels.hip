@@ -81,10 +81,10 @@ template <typename T> __device__ __forceinline__ T eps_fluid(T ra, T rb, const S
 // Sums (or maxima) of nvals values over nblk partial records, fixed order: deterministic.
 constexpr int kRedThreads = 1024;
 
-// Each thread accumulates whole records (the values of a workgroup's record are
-// adjacent, so they load together; a few records are in flight at once) in increasing
-// record order; wave64 shuffles and a sum over the waves in order finish the job.  Fixed
-// order throughout: deterministic.  NV is the record width read (at least nvals).
+// Each thread accumulates whole records (value k of record b at red[k * nblk + b]; a few
+// records are in flight at once) in increasing record order; wave64 shuffles and a sum
+// over the waves in order finish the job.  Fixed order throughout: deterministic.  NV is
+// the number of values read (at least nvals).
 template <int NV, int kFly>
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ red, unsigned nblk, int nvals,
                                                         const int* is_max_d, double* __restrict__ out) {
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict
             const unsigned b = b0 + j * kRedThreads;
 #pragma unroll
             for (int k = 0; k < NV; ++k)
-                v[j][k] = (k < nvals && b < nblk) ? red[(size_t)b * kRedSlots + k] : (mx[k] ? -1e300 : 0.0);
+                v[j][k] = (k < nvals && b < nblk) ? red[(size_t)k * nblk + b] : (mx[k] ? -1e300 : 0.0);
         }
 #pragma unroll
         for (int j = 0; j < kFly; ++j)
@@ -214,7 +214,7 @@ template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_moments(Scalars S, Fields<T> F) {
     double v[1] = {moments_body<T, G>(S, F, xcd_linear())};
     const bool mx[1] = {false};
-    block_reduce_store<1>(v, mx, F.red, blockIdx.x);
+    block_reduce_store<1>(v, mx, F.red, blockIdx.x, gridDim.x);
 }
 
 template <typename T> void launch_moments(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st) {
@@ -276,7 +276,7 @@ __device__ void source_mean_body(const Scalars& S, const double* __restrict__ re
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const unsigned b = b0 + j * kRedThreads;
-            v[j] = b < nblk ? red[(size_t)b * kRedSlots] : 0.0;
+            v[j] = b < nblk ? red[b] : 0.0;
         }
         a += v[0];
         a += v[1];
@@ -392,13 +392,27 @@ __device__ __forceinline__ void residual_body(const Scalars& S, const Fields<T>&
     }
 }
 
+// Each thread takes kResSites sites, kBlock apart (a workgroup covers kResSites x kBlock
+// consecutive sites), and sums them in order before the block reduction: fewer records
+// for the reducer to read.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_residual(Scalars S, Fields<T> F) {
-    double v[3];
-    residual_body<T>(S, F, xcd_linear(), v);
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned lb = (b & 7u) * (nb >> 3) + (b >> 3);  // XCD-contiguous ranges, as xcd_linear
+    double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < kResSites; ++j) {
+        double v[3];
+        residual_body<T>(S, F, (lb * kResSites + j) * kBlock + threadIdx.x, v);
+        acc[0] += v[0];
+        acc[1] += v[1];
+        acc[2] += v[2];
+    }
     const bool mx[3] = {false, false, false};
-    block_reduce_store<3>(v, mx, F.red, blockIdx.x);
+    block_reduce_store<3>(acc, mx, F.red, blockIdx.x, gridDim.x);
 }
+
+unsigned residual_blocks(unsigned n) { return site_blocks((n + kResSites - 1) / kResSites); }
 
 template <typename T> void launch_residual(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st) {
     hipLaunchKernelGGL(k_residual<T>, dim3(nblk), dim3(kBlock), 0, st, S, F);
@@ -412,12 +426,22 @@ __device__ __forceinline__ void finalize_body(const Scalars& S, double* phi, con
     phi[i] = zero ? 0.0 : phi[i] - scal[3] / (double)S.ndomain;
 }
 
-__global__ __launch_bounds__(kBlock) void k_phi_finalize(Scalars S, double* phi, const double* scal, int zero) {
-    finalize_body(S, phi, scal, zero, xcd_linear());
+// The gauge, and with walls the wall layers from the gauged potential next to them (Gauss's
+// law at the charged wall face): phi_wall = phi_adjacent + sigma / eps_adjacent.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_phi_finalize(Scalars S, Fields<T> F, int zero) {
+    const unsigned i = xcd_linear();
+    if (i >= S.N) return;
+    const int z = (i / S.nx) / S.ny;
+    if (z < S.z0 || z > S.z1) return;
+    const double p = zero ? 0.0 : F.phi[i] - F.scal[3] / (double)S.ndomain;
+    F.phi[i] = p;
+    if (S.walls && z == S.z0) F.phi[i - S.nxy] = p + S.sigma0 / (double)F.eps[i];
+    if (S.walls && z == S.z1) F.phi[i + S.nxy] = p + S.sigma1 / (double)F.eps[i];
 }
 
-void launch_phi_finalize(const Scalars& S, double* phi, const double* scal, int zero, hipStream_t st) {
-    hipLaunchKernelGGL(k_phi_finalize, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, phi, scal, zero);
+template <typename T> void launch_phi_finalize(const Scalars& S, const Fields<T>& F, int zero, hipStream_t st) {
+    hipLaunchKernelGGL(k_phi_finalize<T>, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F, zero);
 }
 
 // Warm start of the next solve by linear extrapolation in time,
@@ -453,22 +477,6 @@ void launch_phi_extrapolate(const Scalars& S, double* phi, double* prev, double*
                             hipStream_t st) {
     hipLaunchKernelGGL(k_phi_extrapolate, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, phi, prev, prev2,
                        history);
-}
-
-// Wall layers: Gauss's law at the charged wall face, phi_wall = phi_adjacent + sigma / eps_adjacent.
-template <typename T>
-__global__ void k_phi_ghosts(Scalars S, Fields<T> F) {
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (unsigned)S.nxy) return;
-    const unsigned a1 = t + S.nxy, a0 = t;
-    const unsigned b1 = t + (unsigned)(S.nz - 2) * S.nxy, b0 = t + (unsigned)(S.nz - 1) * S.nxy;
-    F.phi[a0] = F.phi[a1] + S.sigma0 / (double)F.eps[a1];
-    F.phi[b0] = F.phi[b1] + S.sigma1 / (double)F.eps[b1];
-}
-
-template <typename T> void launch_phi_ghosts(const Scalars& S, const Fields<T>& F, hipStream_t st) {
-    if (!S.walls) return;
-    hipLaunchKernelGGL(k_phi_ghosts<T>, dim3((S.nxy + kBlock - 1) / kBlock), dim3(kBlock), 0, st, S, F);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1612,7 +1620,7 @@ __global__ __launch_bounds__(kBlock) void k_observe(Scalars S, Fields<T> F) {
         v[9] = bad;
     }
     const bool mx[11] = {false, false, false, false, false, false, false, false, true, false, false};
-    block_reduce_store<11>(v, mx, F.red, blockIdx.x);
+    block_reduce_store<11>(v, mx, F.red, blockIdx.x, gridDim.x);
 }
 
 template <typename T> void launch_observe(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st) {
@@ -1707,7 +1715,7 @@ template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, 
     template void launch_virtual<T>(const Scalars&, const Fields<T>&, hipStream_t);                            \
     template void launch_sor<T>(const Scalars&, const Fields<T>&, int, double, hipStream_t);                   \
     template void launch_residual<T>(const Scalars&, const Fields<T>&, unsigned, hipStream_t);                 \
-    template void launch_phi_ghosts<T>(const Scalars&, const Fields<T>&, hipStream_t);                         \
+    template void launch_phi_finalize<T>(const Scalars&, const Fields<T>&, int, hipStream_t);                  \
     template void launch_force<T>(const Scalars&, const Fields<T>&, hipStream_t);                              \
     template void launch_fused<T>(const Scalars&, const Fields<T>&, hipStream_t);                              \
     template void launch_particle_sum<T>(const Scalars&, const Fields<T>&, int, const int32_t*, const int32_t*, \
@@ -1740,7 +1748,7 @@ __global__ __launch_bounds__(kBlock) void kb_moments(const RepDesc<T>* __restric
     const RepDesc<T>& R = D[e.rep];
     double v[1] = {moments_body<T, kPeriodic>(R.S, R.F, (unsigned)e.blk * kBlock + threadIdx.x)};
     const bool mx[1] = {false};
-    block_reduce_store<1>(v, mx, R.F.red, e.blk);
+    block_reduce_store<1>(v, mx, R.F.red, e.blk, (R.S.N + kBlock - 1) / kBlock);
 }
 
 template <typename T>
@@ -1750,7 +1758,7 @@ __global__ __launch_bounds__(kBlock) void kb_residual(const RepDesc<T>* __restri
     double v[3];
     residual_body<T>(R.S, R.F, (unsigned)e.blk * kBlock + threadIdx.x, v);
     const bool mx[3] = {false, false, false};
-    block_reduce_store<3>(v, mx, R.F.red, e.blk);
+    block_reduce_store<3>(v, mx, R.F.red, e.blk, (R.S.N + kBlock - 1) / kBlock);
 }
 
 template <typename T>
@@ -1836,7 +1844,7 @@ __global__ __launch_bounds__(kRedThreads) void kb_reduce(const RepDesc<T>* __res
     double tot[3];
     for (int k = 0; k < 3; ++k) {
         double a = 0.0;
-        for (unsigned b = threadIdx.x; b < nblk; b += kRedThreads) a += R.F.red[(size_t)b * kRedSlots + k];
+        for (unsigned b = threadIdx.x; b < nblk; b += kRedThreads) a += R.F.red[(size_t)k * nblk + b];
         sm[threadIdx.x] = a;
         __syncthreads();
         for (int s2 = kRedThreads / 2; s2 > 0; s2 >>= 1) {
