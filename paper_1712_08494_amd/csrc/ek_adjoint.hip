@@ -43,13 +43,6 @@ __device__ __forceinline__ void species_at(const Fields<double>& F, unsigned j, 
     n[1] = s - 0.5 * c;
 }
 
-__device__ __forceinline__ void site_xyz(unsigned j, const Scalars& S, int& x, int& y, int& z) {
-    x = j % S.nx;
-    const unsigned r = j / S.nx;
-    y = r % S.ny;
-    z = r / S.ny;
-}
-
 __device__ __forceinline__ double efield_at(int k, unsigned j, const double* phi, const Scalars& S) {
     int x, y, z;
     site_xyz(j, S, x, y, z);

@@ -878,6 +878,10 @@ extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const doub
     S.z0 = S.walls ? 1 : 0;
     S.z1 = S.walls ? p->nz - 2 : p->nz - 1;
     S.ndomain = (unsigned)S.nxy * (unsigned)(S.z1 - S.z0 + 1);
+    S.inv_nx = 1.0 / S.nx;
+    S.inv_ny = 1.0 / S.ny;
+    S.inv_nxy = 1.0 / S.nxy;
+    S.inv_hx = S.nx >= 2 ? 1.0 / (S.nx / 2) : 0.0;
     S.tau = p->tau;
     S.inv_tau = 1.0 / p->tau;
     S.G = p->G;
@@ -913,6 +917,9 @@ extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const doub
             L.ny = dims[1];
             L.nz = dims[2];
             L.n = (unsigned)(dims[0] * dims[1] * dims[2]);
+            L.inv_nx = 1.0 / L.nx;
+            L.inv_ny = 1.0 / L.ny;
+            L.inv_hx = 1.0 / (L.nx / 2);
             c->mg.push_back(L);
         }
         // the coarsest grid is solved inside one workgroup's LDS (at most 4608 cells)

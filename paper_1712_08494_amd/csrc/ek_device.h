@@ -37,6 +37,31 @@ __device__ __forceinline__ int offset_of(const Nbr& o, int d) {
            (vz(d) < 0 ? o.zm : (vz(d) > 0 ? o.zp : 0));
 }
 
+// Exact floor(a / d) from a precomputed 1/d (FP64), for a, d < 2^32: (a + 1/2)/d lies at
+// least 1/(2d) from an integer, far more than the rounding of the two FP64 operations.  A
+// few FP64 instructions instead of an integer division's long sequence.
+__device__ __forceinline__ unsigned div_exact(unsigned a, double inv_d) {
+    return (unsigned)(((double)a + 0.5) * inv_d);
+}
+
+// Coordinates of lattice site i.
+__device__ __forceinline__ void site_xyz(unsigned i, const Scalars& S, int& x, int& y, int& z) {
+    const unsigned r = div_exact(i, S.inv_nx);
+    x = (int)(i - r * (unsigned)S.nx);
+    z = (int)div_exact(i, S.inv_nxy);
+    y = (int)(r - (unsigned)z * (unsigned)S.ny);
+}
+
+__device__ __forceinline__ int site_z(unsigned i, const Scalars& S) { return (int)div_exact(i, S.inv_nxy); }
+
+// Coordinates of cell t of a multigrid level.
+__device__ __forceinline__ void level_xyz(unsigned t, const MGLevel& L, int& x, int& y, int& z) {
+    const unsigned r = div_exact(t, L.inv_nx);
+    x = (int)(t - r * (unsigned)L.nx);
+    z = (int)div_exact(r, L.inv_ny);
+    y = (int)(r - (unsigned)z * (unsigned)L.ny);
+}
+
 __device__ __forceinline__ int wrapc(int a, int n) {
     return n == 1 ? 0 : (a < 0 ? a + n : (a >= n ? a - n : a));
 }

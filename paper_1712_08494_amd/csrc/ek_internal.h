@@ -23,6 +23,7 @@ struct Scalars {
     int ion_sc;       // solvation Shan-Chen coupling active
     int z0, z1;       // Poisson domain in z (inclusive)
     unsigned ndomain; // sites in the Poisson domain
+    double inv_nx, inv_ny, inv_nxy, inv_hx;  // 1/nx, 1/ny, 1/(nx ny), 1/(nx/2): exact index division
     double tau, inv_tau, G, rho0, D, beta;
     double kap_p, kap_m;   // s beta dmu+- / (2 drho_a)
     double G_p, G_m;       // s dmu+- / (drho_a c_s^2)
@@ -69,6 +70,7 @@ struct MGLevel {
     double* ax;   // coefficient of the face to the +x neighbour
     double* ay;
     double* az;
+    double inv_nx, inv_ny, inv_hx;  // 1/nx, 1/ny, 1/(nx/2) for div_exact
 };
 
 unsigned site_blocks(unsigned n);

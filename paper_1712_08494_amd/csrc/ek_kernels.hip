@@ -158,7 +158,7 @@ template <typename T, int G>
 __device__ __forceinline__ double moments_body(const Scalars& S, const Fields<T>& F, unsigned i) {
     double qsum = 0.0;
     if (i < S.N) {
-        const int z = (i / S.nx) / S.ny;
+        const int z = site_z(i, S);
         const bool solid = is_solid<T, G>(i, z, S, F);
         T da = T(-S.rref[0]), db = T(-S.rref[1]), ux = 0, uy = 0, uz = 0, pa = 0, pb = 0;
         if (!solid) {
@@ -234,7 +234,8 @@ __global__ __launch_bounds__(kBlock) void k_virtual(Scalars S, Fields<T> F) {
     const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
     if ((int)t >= F.nv) return;
     const unsigned i = (unsigned)F.vlist[t];
-    const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+    int x, y, z;
+    site_xyz(i, S, x, y, z);
     const Nbr o = make_nbr(x, y, z, S);
     T sa = 0, sb = 0;
     int cnt = 0;
@@ -354,8 +355,9 @@ __device__ __forceinline__ void sor_body(const Scalars& S, const Fields<T>& F, u
     const unsigned half = (unsigned)(S.nx >> 1);
     const unsigned rows = (unsigned)S.ny * (unsigned)(S.z1 - S.z0 + 1);
     if (t >= half * rows) return;
-    const unsigned row = t / half, m = t % half;
-    const int y = row % S.ny, z = S.z0 + row / S.ny;
+    const unsigned row = div_exact(t, S.inv_hx), m = t - row * half;
+    const unsigned zr = div_exact(row, S.inv_ny);
+    const int y = (int)(row - zr * (unsigned)S.ny), z = S.z0 + (int)zr;
     const int x = 2 * m + ((color + y + z) & 1);
     const unsigned i = x + S.nx * (y + S.ny * z);
     double diag, offsum, src;
@@ -380,7 +382,8 @@ template <typename T>
 __device__ __forceinline__ void residual_body(const Scalars& S, const Fields<T>& F, unsigned i, double (&v)[3]) {
     v[0] = v[1] = v[2] = 0.0;
     if (i < S.N) {
-        const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+        int x, y, z;
+    site_xyz(i, S, x, y, z);
         if (z >= S.z0 && z <= S.z1) {
             double diag, offsum, src;
             poisson_row<T>(i, x, y, z, S, F, diag, offsum, src);
@@ -421,7 +424,7 @@ template <typename T> void launch_residual(const Scalars& S, const Fields<T>& F,
 // Gauge mean(phi) = 0 over the domain (scal[3] = sum of phi), or phi = 0 when zero != 0.
 __device__ __forceinline__ void finalize_body(const Scalars& S, double* phi, const double* scal, int zero, unsigned i) {
     if (i >= S.N) return;
-    const int z = (i / S.nx) / S.ny;
+    const int z = site_z(i, S);
     if (z < S.z0 || z > S.z1) return;
     phi[i] = zero ? 0.0 : phi[i] - scal[3] / (double)S.ndomain;
 }
@@ -432,7 +435,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_phi_finalize(Scalars S, Fields<T> F, int zero) {
     const unsigned i = xcd_linear();
     if (i >= S.N) return;
-    const int z = (i / S.nx) / S.ny;
+    const int z = site_z(i, S);
     if (z < S.z0 || z > S.z1) return;
     const double p = zero ? 0.0 : F.phi[i] - F.scal[3] / (double)S.ndomain;
     F.phi[i] = p;
@@ -448,7 +451,7 @@ template <typename T> void launch_phi_finalize(const Scalars& S, const Fields<T>
 // phi <- 2 phi(t-1) - phi(t-2), keeping phi(t-1) for the following step.
 __device__ __forceinline__ void extrapolate_body(const Scalars& S, double* phi, double* phi_prev, unsigned i) {
     if (i >= S.N) return;
-    const int z = (i / S.nx) / S.ny;
+    const int z = site_z(i, S);
     if (z < S.z0 || z > S.z1) return;
     const double p = phi[i];
     phi[i] = 2.0 * p - phi_prev[i];
@@ -462,7 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_phi_extrapolate(Scalars S, double* p
                                                             int history) {
     const unsigned i = xcd_linear();
     if (i >= S.N) return;
-    const int z = (i / S.nx) / S.ny;
+    const int z = site_z(i, S);
     if (z < S.z0 || z > S.z1) return;
     const double p1 = phi[i], p2 = prev[i];
     double v = p1;
@@ -509,7 +512,8 @@ __device__ __forceinline__ double fine_face(int k, int x, int y, int z, const Sc
 template <typename T>
 __device__ __forceinline__ void coarsen_fine_body(const Scalars& S, const Fields<T>& F, const MGLevel& C, unsigned t) {
     if (t >= C.n) return;
-    const int I = t % C.nx, r = t / C.nx, J = r % C.ny, K = r / C.ny;
+    int I, J, K;
+    level_xyz(t, C, I, J, K);
     double ax = 0, ay = 0, az = 0;
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
@@ -533,7 +537,8 @@ template <typename T> void launch_mg_coarsen_fine(const Scalars& S, const Fields
 
 __device__ __forceinline__ void coarsen_body(const MGLevel& Fl, const MGLevel& C, unsigned t) {
     if (t >= C.n) return;
-    const int I = t % C.nx, r = t / C.nx, J = r % C.ny, K = r / C.ny;
+    int I, J, K;
+    level_xyz(t, C, I, J, K);
     double ax = 0, ay = 0, az = 0;
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
@@ -571,8 +576,8 @@ __device__ __forceinline__ void mg_row(const MGLevel& L, int x, int y, int z, do
 __device__ __forceinline__ void smooth_body(const MGLevel& L, int color, double omega, unsigned t) {
     const unsigned half = (unsigned)(L.nx >> 1);
     if (t >= half * (unsigned)L.ny * (unsigned)L.nz) return;
-    const unsigned row = t / half, m = t % half;
-    const int y = row % L.ny, z = row / L.ny;
+    const unsigned row = div_exact(t, L.inv_hx), m = t - row * half;
+    const int z = (int)div_exact(row, L.inv_ny), y = (int)row - z * L.ny;
     const int x = 2 * m + ((color + y + z) & 1);
     double diag, off;
     mg_row(L, x, y, z, diag, off);
@@ -596,7 +601,8 @@ void launch_mg_smooth(const MGLevel& L, int color, double omega, hipStream_t st)
 template <typename T>
 __device__ __forceinline__ void restrict_fine_body(const Scalars& S, const Fields<T>& F, const MGLevel& C, unsigned t) {
     if (t >= C.n) return;
-    const int I = t % C.nx, r = t / C.nx, J = r % C.ny, K = r / C.ny;
+    int I, J, K;
+    level_xyz(t, C, I, J, K);
     int xs[4], ys[4], zs[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -674,7 +680,8 @@ template <typename T> void launch_mg_restrict_fine(const Scalars& S, const Field
 
 __device__ __forceinline__ void restrict_body(const MGLevel& Fl, const MGLevel& C, unsigned t) {
     if (t >= C.n) return;
-    const int I = t % C.nx, r = t / C.nx, J = r % C.ny, K = r / C.ny;
+    int I, J, K;
+    level_xyz(t, C, I, J, K);
     double sum = 0.0;
     for (int c = 0; c < 2; ++c)
         for (int b = 0; b < 2; ++b)
@@ -725,7 +732,8 @@ __device__ __forceinline__ double mg_interp(const MGLevel& C, int x, int y, int 
 template <typename T>
 __device__ __forceinline__ void prolong_fine_body(const Scalars& S, const Fields<T>& F, const MGLevel& C, unsigned i) {
     if (i >= S.N) return;
-    const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+    int x, y, z;
+    site_xyz(i, S, x, y, z);
     if (z < S.z0 || z > S.z1) return;
     const int I = x >> 1, J = y >> 1, K = z >> 1;
     const int dx = (x & 1) ? 1 : -1, dy = (y & 1) ? 1 : -1, dz = (z & 1) ? 1 : -1;
@@ -755,7 +763,8 @@ template <typename T> void launch_mg_prolong_fine(const Scalars& S, const Fields
 
 __device__ __forceinline__ void prolong_body(const MGLevel& C, const MGLevel& Fl, unsigned i) {
     if (i >= Fl.n) return;
-    const int x = i % Fl.nx, r = i / Fl.nx, y = r % Fl.ny, z = r / Fl.ny;
+    int x, y, z;
+    level_xyz(i, Fl, x, y, z);
     Fl.phi[i] += mg_interp(C, x, y, z);
 }
 
@@ -843,12 +852,6 @@ __device__ void tail_load_coeffs(const MGLevel& G, C* ax, C* ay, C* az) {
         ay[t] = (C)G.ay[t];
         az[t] = (C)G.az[t];
     }
-}
-
-// Exact floor(a / d) for a, d < 2^20 from a precomputed 1/d: (a + 0.5)/d lies at least
-// 0.5/d from an integer, far more than the rounding of two FP64 operations.
-__device__ __forceinline__ unsigned div_exact(unsigned a, double inv_d) {
-    return (unsigned)(((double)a + 0.5) * inv_d);
 }
 
 // Cell h of colour c of a red-black grid (h < n/2, even nx): coordinates.
@@ -1344,7 +1347,8 @@ __device__ __forceinline__ void site_forces(unsigned i, const Nbr& o, T ra, T rb
 template <typename T, int G>
 __device__ __forceinline__ void force_body(const Scalars& S, const Fields<T>& F, unsigned i) {
     if (i >= S.N) return;
-    const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+    int x, y, z;
+    site_xyz(i, S, x, y, z);
     const size_t N = S.N;
     if (is_solid<T, G>(i, z, S, F)) {
         F.uph[i] = T(0);
@@ -1393,7 +1397,8 @@ template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hi
 template <typename T, int G>
 __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F, unsigned i) {
     if (i >= S.N) return;
-    const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+    int x, y, z;
+    site_xyz(i, S, x, y, z);
     if (G == kWalls && (z == 0 || z == S.nz - 1)) return;  // wall layers hold no ions and no fluid
     const size_t N = S.N;
     const Nbr o = make_nbr(x, y, z, S);
@@ -1498,7 +1503,8 @@ __global__ __launch_bounds__(kBlock) void k_particle_sum(Scalars S, Fields<T> F,
     }
     for (int t = site_off[p] + threadIdx.x; t < site_off[p + 1]; t += blockDim.x) {
         const unsigned i = (unsigned)site_idx[t];
-        const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+        int x, y, z;
+    site_xyz(i, S, x, y, z);
         const double qv = (double)F.qc[i];
         v[0] += qv * efield(0, x, y, z, F.phi, S);
         v[1] += qv * efield(1, x, y, z, F.phi, S);
@@ -1589,7 +1595,7 @@ __global__ __launch_bounds__(kBlock) void k_observe(Scalars S, Fields<T> F) {
     const unsigned i = xcd_linear();
     double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < S.N) {
-        const int z = (i / S.nx) / S.ny;
+        const int z = site_z(i, S);
         const double is_ = (double)F.n[0][i], ic_ = (double)F.n[1][i];
         const double np_ = is_ + 0.5 * ic_, nm_ = is_ - 0.5 * ic_;
         v[2] = np_;
@@ -1636,7 +1642,7 @@ __global__ __launch_bounds__(kBlock) void k_init_pop(Scalars S, T* f, const doub
                                                       const uint8_t* flags) {
     const unsigned i = xcd_linear();
     if (i >= S.N) return;
-    const int z = (i / S.nx) / S.ny;
+    const int z = site_z(i, S);
     const bool solid = S.colloids ? (flags[i] & 1u) != 0 : wall_layer(z, S);
     const double dr = solid ? 0.0 : rho[i] - rref;
 #pragma unroll
@@ -1651,7 +1657,7 @@ __global__ __launch_bounds__(kBlock) void k_init_ions(Scalars S, Fields<T> F, T*
                                                       const double* nm_) {
     const unsigned i = xcd_linear();
     if (i >= S.N) return;
-    const int z = (i / S.nx) / S.ny;
+    const int z = site_z(i, S);
     const double pf = (double)psif_at(i, z, S, F);
     ion_s[i] = (T)(0.5 * (np_[i] + nm_[i]) * pf);
     ion_c[i] = (T)((np_[i] - nm_[i]) * pf);
@@ -1701,7 +1707,8 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_field_e(Scalars S, Fields<T> F, int k, double* dst) {
     const unsigned i = xcd_linear();
     if (i >= S.N) return;
-    const int x = i % S.nx, r = i / S.nx, y = r % S.ny, z = r / S.ny;
+    int x, y, z;
+    site_xyz(i, S, x, y, z);
     dst[i] = efield(k, x, y, z, F.phi, S);
 }
 
