@@ -144,6 +144,38 @@ def run_gpu(cfg, inp, steps, warmup, detail_steps=20, autotune=0, class_steps=50
     return t1 - t0, timing, ob0, ob1, tuned
 
 
+def S_has_particles(inp):
+    return inp.particles is not None and len(inp.particles) > 0
+
+
+def run_moment_state(workload, precision, n, steps, warmup, mlups_pop):
+    """The same workload with the tau = 1 moment state (density and u_e per site instead of
+    the populations): step rate, device memory, and a bitwise comparison with the
+    population path after a few steps from the same inputs."""
+    import numpy as np
+    from paper_1712_08494_amd import ek
+    cfg, inp = build_workload(workload, precision, n)
+    cfg.moment_state = True
+    log("gpu moment-state run")
+    dt, _, _, _, _ = run_gpu(cfg, inp, steps, warmup, detail_steps=0, class_steps=0)
+    N = cfg.n_sites
+    mlups = N * steps / dt / 1e6
+    log(f"gpu moment state: {1e3 * dt / steps:.3f} ms/step")
+    a = ek.EKSim(cfg, inp)
+    cfg.moment_state = False
+    b = ek.EKSim(cfg, inp)
+    bytes_ms, bytes_pop = a.device_bytes(), b.device_bytes()
+    a.step(5)
+    b.step(5)
+    same = all(np.array_equal(a.field(k), b.field(k)) for k in ("rho_a", "rho_b", "n_plus", "n_minus", "phi"))
+    a.close()
+    b.close()
+    return {"mlups": round(mlups, 2), "ms_per_step": round(1e3 * dt / steps, 4),
+            "speedup_over_populations": round(mlups / mlups_pop, 3),
+            "device_mib": round(bytes_ms / 2**20, 1), "device_mib_populations": round(bytes_pop / 2**20, 1),
+            "bitwise_equal_to_populations_after_5_steps": bool(same)}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -336,6 +368,7 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run used for the FP32/FP64 speedup")
+    ap.add_argument("--no-moment-state", action="store_true", help="skip the tau = 1 moment-state run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-serial replica sweep")
@@ -418,6 +451,10 @@ def main():
         fp64 = N * max(10, args.steps // 2) / dt64 / 1e6
         log(f"gpu fp64: {1e3 * dt64 / max(10, args.steps // 2):.3f} ms/step")
 
+    moment = None
+    if not args.no_moment_state and cfg.tau == 1.0 and not S_has_particles(inp):
+        moment = run_moment_state(args.workload, args.precision, args.n, args.steps, args.warmup, mlups)
+
     batched = None
     if not args.no_batched:
         batched = run_batched(args.batched_replicas, args.batched_steps, args.batched_cycles)
@@ -466,6 +503,7 @@ def main():
         "step_bytes_per_site": step_bytes(s),
         "step_effective_GBps": round(step_bytes(s) * N * args.steps / dt / 1e9, 1),
         "kernels": kernel_table,
+        "moment_state": moment,
         "fp64_mlups": round(fp64, 2) if fp64 else None,
         "fp32_fp64_speedup": round(mlups / fp64, 3) if fp64 else None,
         "batched": batched,

@@ -82,6 +82,15 @@ typedef struct ek_params {
                                    1 the previous one, 2 linear and 3 quadratic extrapolation in time;
                                    0 adaptive: the order (2 or 3) whose last measured start residual was
                                    smaller, the other re-probed every 64 steps (deterministic) */
+    int32_t moment_state;       /* 1: store, per site and component, the density and the equilibrium
+                                   velocity u_e = u' + Phi / rho of the last collision instead of the 19
+                                   populations.  At tau = 1 the post-collision populations are the
+                                   equilibria of exactly these values (Sec. II A, BGK at tau = 1), so the
+                                   step is the same computation with populations gathered from the
+                                   neighbours by the moments pass (halfway bounce-back at the walls): 8
+                                   values per site instead of 38 cross HBM.  Requires tau = 1 and no
+                                   particles; not with ek_forward_ckpt / ek_adjoint or batches.
+                                   ek_get_populations reconstructs the populations.  0: stored populations */
 } ek_params;
 
 typedef struct ek_particle {

@@ -104,6 +104,13 @@ struct ek_ctx {
     double* phi_own = nullptr;
     bool vc_off = false;
     void* tune_buf = nullptr;  // state copy of the autotuner (held only while it runs)
+    // tau = 1 moment state instead of populations (ek_params.moment_state): two buffers of
+    // 8 N values (step parity as the populations), the FP64 initial densities the first
+    // moments pass reads, and whether a step has written a moment state yet
+    bool moment_state = false;
+    void* ms[2] = {nullptr, nullptr};
+    double* rho0 = nullptr;
+    bool ms_first = false;
     // timing: 0 off, 1 kernel classes, 2 classes and every lattice-level smoothing pass
     int timing = 0;
     std::vector<TimeRec> recs;
@@ -255,6 +262,10 @@ static Fields<T> fields(ek_ctx* c) {
     F.pv = c->pv[c->pcur];
     F.red = c->red;
     F.scal = c->scal;
+    F.ms = c->moment_state ? (const T*)c->ms[c->cur] : nullptr;
+    F.msn = c->moment_state ? (T*)c->ms[c->cur ^ 1] : nullptr;
+    F.rho0 = c->rho0;
+    F.ms_first = c->ms_first ? 1 : 0;
     return F;
 }
 
@@ -639,6 +650,7 @@ static ek_status step_impl(ek_ctx* c, int nsteps) {
         }
         EK_HIP(hipGetLastError());
         c->cur ^= 1;
+        c->ms_first = false;  // a moment-state context now holds the state written by this step
         c->steps++;
     }
     return worst;
@@ -717,9 +729,16 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     const size_t es = sizeof(T);
     for (int b = 0; b < 2; ++b)
         for (int k = 0; k < 2; ++k) {
-            EK_TRY(dalloc(c, &c->f[b][k], (size_t)kQ * N * es));
+            if (!c->moment_state) EK_TRY(dalloc(c, &c->f[b][k], (size_t)kQ * N * es));
             EK_TRY(dalloc(c, &c->n[b][k], (size_t)N * es));
         }
+    if (c->moment_state) {
+        for (int b = 0; b < 2; ++b) {
+            EK_TRY(dalloc(c, &c->ms[b], 8 * (size_t)N * es));
+            EK_HIP(hipMemsetAsync(c->ms[b], 0, 8 * (size_t)N * es, c->st));
+        }
+        EK_TRY(dalloc(c, (void**)&c->rho0, 2 * (size_t)N * 8));
+    }
     EK_TRY(dalloc(c, &c->mom, 8 * (size_t)N * es));
     EK_TRY(dalloc(c, &c->uph, 3 * (size_t)N * es));
     EK_TRY(dalloc(c, &c->q, (size_t)N * es));
@@ -744,7 +763,7 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     }
     for (int b = 0; b < 2; ++b)
         for (int k = 0; k < 2; ++k) {
-            EK_HIP(hipMemsetAsync(c->f[b][k], 0, (size_t)kQ * N * es, c->st));
+            if (c->f[b][k]) EK_HIP(hipMemsetAsync(c->f[b][k], 0, (size_t)kQ * N * es, c->st));
             EK_HIP(hipMemsetAsync(c->n[b][k], 0, (size_t)N * es, c->st));
         }
     EK_HIP(hipMemsetAsync(c->mom, 0, 8 * (size_t)N * es, c->st));
@@ -820,10 +839,15 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     Fields<T> F = fields<T>(c);
     const double* rr[2] = {rho_a, rho_b};
     for (int s = 0; s < 2; ++s) {
+        if (c->moment_state) {  // the first moments pass reads w_d rho0 from the densities themselves
+            EK_HIP(hipMemcpyAsync(c->rho0 + (size_t)s * N, rr[s], (size_t)N * 8, hipMemcpyHostToDevice, c->st));
+            continue;
+        }
         EK_HIP(hipMemcpyAsync(c->stage, rr[s], (size_t)N * 8, hipMemcpyHostToDevice, c->st));
         launch_init_pop_flags<T>(c->S, (T*)c->f[c->cur][s], c->stage, c->S.rref[s], c->flags, c->st);
         EK_HIP(hipStreamSynchronize(c->st));
     }
+    EK_HIP(hipStreamSynchronize(c->st));
     // ions: stored as mean density and ionic charge (staging holds n+ then n-)
     double* stage2 = nullptr;
     EK_TRY(dalloc(c, (void**)&stage2, (size_t)N * 8));
@@ -857,6 +881,11 @@ extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const doub
     const double Nd = (double)p->nx * p->ny * p->nz;
     if (Nd > 2147483647.0) return fail(c, EK_EINVAL, "lattice too large (more than 2^31 - 1 sites)");
     if (!(p->tau > 0.5)) return fail(c, EK_EINVAL, "tau must exceed 1/2");
+    if (p->moment_state != 0 && p->moment_state != 1) return fail(c, EK_EINVAL, "moment_state must be 0 or 1");
+    if (p->moment_state && (p->tau != 1.0 || n_parts > 0))
+        return fail(c, EK_EINVAL, "the moment state needs tau = 1 and no particles");
+    c->moment_state = p->moment_state != 0;
+    c->ms_first = c->moment_state;
     if (p->precision != EK_FP32 && p->precision != EK_FP64) return fail(c, EK_EINVAL, "precision must be EK_FP32 or EK_FP64");
     if (!(p->D > 0.0) || !(p->beta > 0.0) || !(p->rho0 > 0.0)) return fail(c, EK_EINVAL, "D, beta and rho0 must be positive");
     if (!(p->eps_a > 0.0) || !(p->eps_b > 0.0) || !(p->eps_p > 0.0)) return fail(c, EK_EINVAL, "permittivities must be positive");
@@ -1020,6 +1049,7 @@ static ek_status adj_check(ek_ctx* c) {
     if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: no reverse mode");
     if (c->esz != 8) return fail(c, EK_EINVAL, "reverse mode needs an FP64 context");
     if (c->S.walls || c->np > 0) return fail(c, EK_EINVAL, "reverse mode covers periodic lattices without particles");
+    if (c->moment_state) return fail(c, EK_EINVAL, "reverse mode needs stored populations (moment_state = 0)");
     return EK_OK;
 }
 
@@ -1300,7 +1330,7 @@ extern "C" ek_status ek_set_multigrid(ek_ctx* c, int32_t fine_pre, int32_t fine_
 // ------------------------------------------------------------------------------------
 namespace {
 struct HostState {
-    int cur, pcur, ws_order, ws_since, last_iters;
+    int cur, pcur, ws_order, ws_since, last_iters, ms_first;
     double rate, rel0_of[4], last_rel, last_mean, last_rel0;
     long long steps, ptotal;
 };
@@ -1312,8 +1342,8 @@ static ek_status tune_copy(ek_ctx* c, bool save, HostState& h) {
     const size_t N = c->N, pop = (size_t)kQ * N * c->esz, ion = N * c->esz, pb = (size_t)3 * c->np * 8;
     char* b = (char*)c->tune_buf;
     if (save) {
-        h = HostState{c->cur, c->pcur, c->ws_order, c->ws_since, c->last_iters, c->rate, {0, 0, 0, 0},
-                      c->last_rel, c->last_mean, c->last_rel0, c->steps, c->ptotal};
+        h = HostState{c->cur, c->pcur, c->ws_order, c->ws_since, c->last_iters, c->ms_first ? 1 : 0, c->rate,
+                      {0, 0, 0, 0}, c->last_rel, c->last_mean, c->last_rel0, c->steps, c->ptotal};
         for (int k = 0; k < 4; ++k) h.rel0_of[k] = c->rel0_of[k];
     } else {
         c->cur = h.cur;
@@ -1321,6 +1351,7 @@ static ek_status tune_copy(ek_ctx* c, bool save, HostState& h) {
         c->ws_order = h.ws_order;
         c->ws_since = h.ws_since;
         c->last_iters = h.last_iters;
+        c->ms_first = h.ms_first != 0;
         c->rate = h.rate;
         for (int k = 0; k < 4; ++k) c->rel0_of[k] = h.rel0_of[k];
         c->last_rel = h.last_rel;
@@ -1329,10 +1360,11 @@ static ek_status tune_copy(ek_ctx* c, bool save, HostState& h) {
         c->steps = h.steps;
         c->ptotal = h.ptotal;
     }
-    void* dev[] = {c->f[c->cur][0], c->f[c->cur][1], c->n[c->cur][0], c->n[c->cur][1], c->phi, c->phi_prev,
-                   c->phi_prev2, c->np ? c->px[c->pcur] : nullptr, c->np ? c->pv[c->pcur] : nullptr,
-                   c->np ? c->pF : nullptr};
-    const size_t len[] = {pop, pop, ion, ion, N * 8, N * 8, N * 8, pb, pb, pb};
+    // populations of the current step, or the moment state (8 N values, in the first slot)
+    void* dev[] = {c->moment_state ? c->ms[c->cur] : c->f[c->cur][0], c->moment_state ? nullptr : c->f[c->cur][1],
+                   c->n[c->cur][0], c->n[c->cur][1], c->phi, c->phi_prev, c->phi_prev2,
+                   c->np ? c->px[c->pcur] : nullptr, c->np ? c->pv[c->pcur] : nullptr, c->np ? c->pF : nullptr};
+    const size_t len[] = {c->moment_state ? 8 * N * c->esz : pop, pop, ion, ion, N * 8, N * 8, N * 8, pb, pb, pb};
     for (int k = 0; k < 10; ++k) {
         if (!dev[k] || !len[k]) continue;
         if (save)
@@ -1494,6 +1526,17 @@ extern "C" ek_status ek_get_field(ek_ctx* c, int32_t which, double* host_out) {
 template <typename T>
 static ek_status pops_impl(ek_ctx* c, int comp, double* host) {
     const unsigned N = c->N;
+    if (c->moment_state) {  // gathered from the moment state into a temporary 19 N buffer
+        double* buf = nullptr;
+        EK_TRY(dalloc(c, (void**)&buf, (size_t)kQ * N * 8));
+        launch_export_pop<T>(c->S, fields<T>(c), comp, buf, c->st);
+        const hipError_t e1 = hipMemcpyAsync(host, buf, (size_t)kQ * N * 8, hipMemcpyDeviceToHost, c->st);
+        const hipError_t e2 = hipStreamSynchronize(c->st);
+        dfree(c, buf, (size_t)kQ * N * 8);
+        EK_HIP(e1);
+        EK_HIP(e2);
+        return EK_OK;
+    }
     for (int d = 0; d < kQ; ++d) {
         launch_to_double<T>((const T*)c->f[c->cur][comp] + (size_t)d * N, c->stage, N, weight(d) * c->S.rref[comp], c->st);
         EK_HIP(hipMemcpyAsync(host + (size_t)d * N, c->stage, (size_t)N * 8, hipMemcpyDeviceToHost, c->st));
@@ -1784,6 +1827,10 @@ extern "C" ek_status ek_batch_init(const ek_params* params, int32_t n_rep, const
         const ek_params& p = params[r];
         if (p.walls_z || p.precision != params[0].precision) {
             b->err = "batched replicas are periodic and share one precision";
+            return EK_EINVAL;
+        }
+        if (p.moment_state) {
+            b->err = "batched replicas store populations (moment_state = 0)";
             return EK_EINVAL;
         }
         ek_ctx* c = nullptr;

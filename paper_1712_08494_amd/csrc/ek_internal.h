@@ -57,6 +57,13 @@ struct Fields {
     const double* pv;        // particle velocities (3 per particle)
     double* red;             // reduction scratch
     double* scal;            // device scalars: [0] source mean, [1..3] rr, ss, sum phi
+    // tau = 1 moment state (null with population storage): per component c, 4 N values
+    // at ms + 4 c N: rho_c - rho_ref_c, then the equilibrium velocity u_e (x, y, z) of
+    // the collision of step t - 1; msn receives those of step t
+    const T* ms;
+    T* msn;
+    const double* rho0;      // initial densities (2 N, FP64): the populations w_d rho0 before the first step
+    int ms_first;            // 1 until the first step has written a moment state
 };
 
 // One coarse level of the Poisson multigrid: cell-centred, periodic in all axes, with
@@ -158,6 +165,8 @@ void launch_phi_extrapolate(const Scalars& S, double* phi, double* prev, double*
                             hipStream_t st);
 template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hipStream_t st);
 template <typename T> void launch_fused(const Scalars& S, const Fields<T>& F, hipStream_t st);
+// populations of component c at time t of a moment-state context (FP64, 19 N, f not g)
+template <typename T> void launch_export_pop(const Scalars& S, const Fields<T>& F, int c, double* out, hipStream_t st);
 template <typename T>
 void launch_particle_sum(const Scalars& S, const Fields<T>& F, int np, const int32_t* link_off,
                          const int32_t* link_idx, const int32_t* site_off, const int32_t* site_idx, double* pF,

@@ -153,9 +153,74 @@ constexpr int kMomSlots = 8;
 // at 128 VGPRs with at most a handful of spills; FP64 needs the registers of two.
 template <typename T> constexpr int kHotOcc = sizeof(T) == 4 ? 4 : 2;
 
-// returns this site's contribution to the FP64 charge sum of the Poisson domain
-template <typename T, int G>
+// Equilibrium of direction d (Sec. II A) in deviation form, f~_d - w_d rho_ref, for the
+// deviation dr = rho - rho_ref, density rs, velocity u and usq = u.u.  The collision
+// (fused sweep) and the moment-state gather evaluate it with this one expression, without
+// multiply-add contraction, so that both round it the same way whatever surrounds it.
+template <typename T>
+__device__ __forceinline__ T usq_of(T u0, T u1, T u2) {
+#pragma clang fp contract(off)
+    return u0 * u0 + u1 * u1 + u2 * u2;
+}
+
+template <typename T>
+__device__ __forceinline__ T geq_dev(int d, T dr, T rs, T u0, T u1, T u2, T usq) {
+#pragma clang fp contract(off)
+    const T cu = T(vx(d)) * u0 + T(vy(d)) * u1 + T(vz(d)) * u2;
+    return T(weight(d)) * (dr + rs * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq));
+}
+
+// tau = 1 moment state.  At tau = 1 the post-collision populations of a site are the
+// equilibria of its density and shifted velocity u_e = u' + Phi / rho (Sec. II A-C), so a
+// site's 4 values per component stand for its 19 post-collision populations.  Streaming
+// then makes the population arriving at site i in direction d (deviation form) the
+// equilibrium of the source site i - c_d or, where that source is a wall layer, the
+// halfway bounce-back of i's own population in the opposite direction (resting walls).
+// Populations are never stored: the moments pass gathers them.
+template <typename T>
+struct MsSite {
+    T dr, rs, u0, u1, u2, usq;
+};
+
+template <typename T>
+__device__ __forceinline__ MsSite<T> ms_site(const Scalars& S, const Fields<T>& F, int c, unsigned j) {
+    const size_t N = S.N;
+    const T* m = F.ms + (size_t)(4 * c) * N;
+    MsSite<T> a;
+    a.dr = m[j];
+    a.u0 = m[N + j];
+    a.u1 = m[2 * N + j];
+    a.u2 = m[3 * N + j];
+    a.rs = T(S.rref[c]) + a.dr;
+    a.usq = usq_of<T>(a.u0, a.u1, a.u2);
+    return a;
+}
+
+// Population (deviation form) arriving at fluid site i, direction d, component c.  PM 1:
+// gathered from the moment state; PM 2: the initial populations w_d (rho0 - rho_ref).
+template <typename T, int PM>
+__device__ __forceinline__ T arriving(const Scalars& S, const Fields<T>& F, int c, int d, unsigned i, int z,
+                                      const Nbr& o, const MsSite<T>& own) {
+    if (PM == 2) return (T)(weight(d) * (F.rho0[(size_t)c * S.N + i] - S.rref[c]));
+    if (d != kRest) {
+        const int od = opposite(d);
+        const int zs = z - vz(d);
+        if (!(S.walls && (zs == 0 || zs == S.nz - 1))) {
+            const MsSite<T> a = ms_site<T>(S, F, c, i + offset_of(o, od));
+            return geq_dev<T>(d, a.dr, a.rs, a.u0, a.u1, a.u2, a.usq);
+        }
+        return geq_dev<T>(od, own.dr, own.rs, own.u0, own.u1, own.u2, own.usq);
+    }
+    return geq_dev<T>(d, own.dr, own.rs, own.u0, own.u1, own.u2, own.usq);
+}
+
+// returns this site's contribution to the FP64 charge sum of the Poisson domain.  PM 0:
+// populations read from storage; 1, 2: see arriving().
+template <typename T, int G, int PM = 0>
 __device__ __forceinline__ double moments_body(const Scalars& S, const Fields<T>& F, unsigned i) {
+    // No multiply-add contraction here: a gathered population must enter the sums rounded
+    // exactly as a stored one does, so both population sources give the same moments.
+#pragma clang fp contract(off)
     double qsum = 0.0;
     if (i < S.N) {
         const int z = site_z(i, S);
@@ -163,10 +228,19 @@ __device__ __forceinline__ double moments_body(const Scalars& S, const Fields<T>
         T da = T(-S.rref[0]), db = T(-S.rref[1]), ux = 0, uy = 0, uz = 0, pa = 0, pb = 0;
         if (!solid) {
             T sa = 0, sb = 0, mx = 0, my = 0, mz = 0;
+            Nbr o{};
+            MsSite<T> own0{}, own1{};
+            if (PM == 1) {
+                int x, y, zz;
+                site_xyz(i, S, x, y, zz);
+                o = make_nbr(x, y, zz, S);
+                own0 = ms_site<T>(S, F, 0, i);
+                own1 = ms_site<T>(S, F, 1, i);
+            }
 #pragma unroll
             for (int d = 0; d < kQ; ++d) {
-                const T a = F.f[0][(size_t)d * S.N + i];
-                const T b = F.f[1][(size_t)d * S.N + i];
+                const T a = PM == 0 ? F.f[0][(size_t)d * S.N + i] : arriving<T, PM>(S, F, 0, d, i, z, o, own0);
+                const T b = PM == 0 ? F.f[1][(size_t)d * S.N + i] : arriving<T, PM>(S, F, 1, d, i, z, o, own1);
                 sa += a;
                 sb += b;
                 const T s = a + b;
@@ -210,20 +284,34 @@ __device__ __forceinline__ double moments_body(const Scalars& S, const Fields<T>
     return qsum;
 }
 
-template <typename T, int G>
+template <typename T, int G, int PM>
 __global__ __launch_bounds__(kBlock) void k_moments(Scalars S, Fields<T> F) {
-    double v[1] = {moments_body<T, G>(S, F, xcd_linear())};
+    double v[1] = {moments_body<T, G, PM>(S, F, xcd_linear())};
     const bool mx[1] = {false};
     block_reduce_store<1>(v, mx, F.red, blockIdx.x, gridDim.x);
 }
 
+// population source of a context: 0 stored populations, 1 moment state, 2 initial densities
+template <typename T> __host__ __device__ inline int pop_mode(const Fields<T>& F) {
+    return F.ms == nullptr ? 0 : (F.ms_first ? 2 : 1);
+}
+
 template <typename T> void launch_moments(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st) {
+    const int pm = pop_mode(F);
     if (S.colloids)
-        hipLaunchKernelGGL((k_moments<T, kColloids>), dim3(nblk), dim3(kBlock), 0, st, S, F);
+        hipLaunchKernelGGL((k_moments<T, kColloids, 0>), dim3(nblk), dim3(kBlock), 0, st, S, F);
+    else if (S.walls && pm == 0)
+        hipLaunchKernelGGL((k_moments<T, kWalls, 0>), dim3(nblk), dim3(kBlock), 0, st, S, F);
+    else if (S.walls && pm == 1)
+        hipLaunchKernelGGL((k_moments<T, kWalls, 1>), dim3(nblk), dim3(kBlock), 0, st, S, F);
     else if (S.walls)
-        hipLaunchKernelGGL((k_moments<T, kWalls>), dim3(nblk), dim3(kBlock), 0, st, S, F);
+        hipLaunchKernelGGL((k_moments<T, kWalls, 2>), dim3(nblk), dim3(kBlock), 0, st, S, F);
+    else if (pm == 0)
+        hipLaunchKernelGGL((k_moments<T, kPeriodic, 0>), dim3(nblk), dim3(kBlock), 0, st, S, F);
+    else if (pm == 1)
+        hipLaunchKernelGGL((k_moments<T, kPeriodic, 1>), dim3(nblk), dim3(kBlock), 0, st, S, F);
     else
-        hipLaunchKernelGGL((k_moments<T, kPeriodic>), dim3(nblk), dim3(kBlock), 0, st, S, F);
+        hipLaunchKernelGGL((k_moments<T, kPeriodic, 2>), dim3(nblk), dim3(kBlock), 0, st, S, F);
 }
 
 // Virtual densities (Sec. II E, after Jansen et al.): a solid site with a fluid D3Q19
@@ -1394,7 +1482,7 @@ template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hi
 // population only when tau != 1: at tau = 1 the post-collision state is the equilibrium
 // of the moments (already in the moment slots), and populations are streamed as written.
 // ------------------------------------------------------------------------------------
-template <typename T, int G>
+template <typename T, int G, bool MS = false>
 __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F, unsigned i) {
     if (i >= S.N) return;
     int x, y, z;
@@ -1427,15 +1515,22 @@ __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F,
         const T P0 = c == 0 ? Pa[0] : Pb[0], P1 = c == 0 ? Pa[1] : Pb[1], P2 = c == 0 ? Pa[2] : Pb[2];
         const T tau = T(S.tau);
         const T ue0 = u0 + tau * P0 / rs, ue1 = u1 + tau * P1 / rs, ue2 = u2 + tau * P2 / rs;
-        const T usq = ue0 * ue0 + ue1 * ue1 + ue2 * ue2;
+        if (MS) {  // tau = 1 moment state: the density and u_e stand for the post-collision populations
+            T* m = F.msn + (size_t)(4 * c) * N;
+            m[i] = dr;
+            m[N + i] = ue0;
+            m[2 * N + i] = ue1;
+            m[3 * N + i] = ue2;
+            continue;
+        }
+        const T usq = usq_of<T>(ue0, ue1, ue2);
         const T* fc = F.f[c];
         T* fo = F.fn[c];
         int lk = link;
 #pragma unroll
         for (int d = 0; d < kQ; ++d) {
-            const T cu = T(vx(d)) * ue0 + T(vy(d)) * ue1 + T(vz(d)) * ue2;
             const T w = T(weight(d));
-            const T geq = w * (dr + rs * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq));
+            const T geq = geq_dev<T>(d, dr, rs, ue0, ue1, ue2, usq);
             T gs = geq;
             if (!tau1) {
                 const T g = fc[(size_t)d * N + i];
@@ -1470,19 +1565,24 @@ __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F,
     }
 }
 
-template <typename T, int G>
+template <typename T, int G, bool MS>
 __global__ __launch_bounds__(kBlock, kHotOcc<T>) void k_fused(Scalars S, Fields<T> F) {
-    fused_body<T, G>(S, F, xcd_linear());
+    fused_body<T, G, MS>(S, F, xcd_linear());
 }
 
 template <typename T> void launch_fused(const Scalars& S, const Fields<T>& F, hipStream_t st) {
     const dim3 g(site_blocks(S.N)), b(kBlock);
+    const bool ms = F.ms != nullptr;  // a moment-state context writes it from the first step on
     if (S.colloids)
-        hipLaunchKernelGGL((k_fused<T, kColloids>), g, b, 0, st, S, F);
+        hipLaunchKernelGGL((k_fused<T, kColloids, false>), g, b, 0, st, S, F);
+    else if (S.walls && ms)
+        hipLaunchKernelGGL((k_fused<T, kWalls, true>), g, b, 0, st, S, F);
     else if (S.walls)
-        hipLaunchKernelGGL((k_fused<T, kWalls>), g, b, 0, st, S, F);
+        hipLaunchKernelGGL((k_fused<T, kWalls, false>), g, b, 0, st, S, F);
+    else if (ms)
+        hipLaunchKernelGGL((k_fused<T, kPeriodic, true>), g, b, 0, st, S, F);
     else
-        hipLaunchKernelGGL((k_fused<T, kPeriodic>), g, b, 0, st, S, F);
+        hipLaunchKernelGGL((k_fused<T, kPeriodic, false>), g, b, 0, st, S, F);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1590,12 +1690,14 @@ void launch_particle_move(const Scalars& S, int np, const double* x, const doubl
 // Observables: FP64 partial sums of mass, ions, charge, momentum; max |u|; counts of
 // non-finite values and negative ion densities.
 // ------------------------------------------------------------------------------------
-template <typename T>
+template <typename T, int PM>
 __global__ __launch_bounds__(kBlock) void k_observe(Scalars S, Fields<T> F) {
+#pragma clang fp contract(off)  // gathered populations rounded as stored ones (see moments_body)
     const unsigned i = xcd_linear();
     double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (i < S.N) {
-        const int z = site_z(i, S);
+        int x, y, z;
+        site_xyz(i, S, x, y, z);
         const double is_ = (double)F.n[0][i], ic_ = (double)F.n[1][i];
         const double np_ = is_ + 0.5 * ic_, nm_ = is_ - 0.5 * ic_;
         v[2] = np_;
@@ -1605,9 +1707,18 @@ __global__ __launch_bounds__(kBlock) void k_observe(Scalars S, Fields<T> F) {
         v[10] = (np_ < 0.0) + (nm_ < 0.0);
         if (!solid_at(i, z, S, F)) {
             double sa = 0, sb = 0, m[3] = {0, 0, 0};
+            const Nbr o = make_nbr(x, y, z, S);
+            MsSite<T> own0{}, own1{};
+            if (PM == 1) {
+                own0 = ms_site<T>(S, F, 0, i);
+                own1 = ms_site<T>(S, F, 1, i);
+            }
 #pragma unroll
             for (int d = 0; d < kQ; ++d) {
-                const double a = (double)F.f[0][(size_t)d * S.N + i], b = (double)F.f[1][(size_t)d * S.N + i];
+                const double a = PM == 0 ? (double)F.f[0][(size_t)d * S.N + i]
+                                         : (double)arriving<T, PM>(S, F, 0, d, i, z, o, own0);
+                const double b = PM == 0 ? (double)F.f[1][(size_t)d * S.N + i]
+                                         : (double)arriving<T, PM>(S, F, 1, d, i, z, o, own1);
                 bad |= !isfinite(a) || !isfinite(b);
                 sa += a;
                 sb += b;
@@ -1630,7 +1741,40 @@ __global__ __launch_bounds__(kBlock) void k_observe(Scalars S, Fields<T> F) {
 }
 
 template <typename T> void launch_observe(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st) {
-    hipLaunchKernelGGL(k_observe<T>, dim3(nblk), dim3(kBlock), 0, st, S, F);
+    const int pm = pop_mode(F);
+    if (pm == 0)
+        hipLaunchKernelGGL((k_observe<T, 0>), dim3(nblk), dim3(kBlock), 0, st, S, F);
+    else if (pm == 1)
+        hipLaunchKernelGGL((k_observe<T, 1>), dim3(nblk), dim3(kBlock), 0, st, S, F);
+    else
+        hipLaunchKernelGGL((k_observe<T, 2>), dim3(nblk), dim3(kBlock), 0, st, S, F);
+}
+
+// Populations of component c at time t (FP64, f_d = g_d + w_d rho_ref, velocity-major) of a
+// moment-state context, gathered as in the moments pass; solid sites hold w_d rho_ref.
+template <typename T, int PM>
+__global__ __launch_bounds__(kBlock) void k_export_pop(Scalars S, Fields<T> F, int c, double* out) {
+#pragma clang fp contract(off)  // as the population export: the stored value plus w_d rho_ref
+    const unsigned i = xcd_linear();
+    if (i >= S.N) return;
+    int x, y, z;
+    site_xyz(i, S, x, y, z);
+    const bool solid = solid_at(i, z, S, F);
+    const Nbr o = make_nbr(x, y, z, S);
+    MsSite<T> own{};
+    if (PM == 1 && !solid) own = ms_site<T>(S, F, c, i);
+#pragma unroll
+    for (int d = 0; d < kQ; ++d) {
+        const double g = solid ? 0.0 : (double)arriving<T, PM>(S, F, c, d, i, z, o, own);
+        out[(size_t)d * S.N + i] = g + weight(d) * S.rref[c];
+    }
+}
+
+template <typename T> void launch_export_pop(const Scalars& S, const Fields<T>& F, int c, double* out, hipStream_t st) {
+    if (pop_mode(F) == 1)
+        hipLaunchKernelGGL((k_export_pop<T, 1>), dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F, c, out);
+    else
+        hipLaunchKernelGGL((k_export_pop<T, 2>), dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F, c, out);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1725,6 +1869,7 @@ template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, 
     template void launch_phi_finalize<T>(const Scalars&, const Fields<T>&, int, hipStream_t);                  \
     template void launch_force<T>(const Scalars&, const Fields<T>&, hipStream_t);                              \
     template void launch_fused<T>(const Scalars&, const Fields<T>&, hipStream_t);                              \
+    template void launch_export_pop<T>(const Scalars&, const Fields<T>&, int, double*, hipStream_t);           \
     template void launch_particle_sum<T>(const Scalars&, const Fields<T>&, int, const int32_t*, const int32_t*, \
                                          const int32_t*, const int32_t*, double*, hipStream_t);                \
     template void launch_observe<T>(const Scalars&, const Fields<T>&, unsigned, hipStream_t);                  \

@@ -32,6 +32,7 @@ class EKParams(ctypes.Structure):
         ("E_ext", ctypes.c_double * 3), ("body_accel", ctypes.c_double * 3), ("sigma_wall", ctypes.c_double * 2),
         ("poisson_tol", ctypes.c_double), ("sor_omega", ctypes.c_double), ("particle_rho", ctypes.c_double),
         ("k_hertz", ctypes.c_double), ("eta", ctypes.c_double), ("phi_history", ctypes.c_int32),
+        ("moment_state", ctypes.c_int32),
     ]
 
 
@@ -196,6 +197,7 @@ def params_from_config(cfg):
     p.sor_omega = 0.0
     p.particle_rho, p.k_hertz, p.eta = cfg.particle_rho, cfg.k_hertz, cfg.eta
     p.phi_history = int(getattr(cfg, "phi_history", 0))
+    p.moment_state = int(bool(getattr(cfg, "moment_state", False)))
     return p
 
 
