@@ -57,9 +57,9 @@ struct Fields {
     const double* pv;        // particle velocities (3 per particle)
     double* red;             // reduction scratch
     double* scal;            // device scalars: [0] source mean, [1..3] rr, ss, sum phi
-    // tau = 1 moment state (null with population storage): per component c, 4 N values
-    // at ms + 4 c N: rho_c - rho_ref_c, then the equilibrium velocity u_e (x, y, z) of
-    // the collision of step t - 1; msn receives those of step t
+    // tau = 1 moment state (null with population storage), site-major: site j's values at
+    // ms + 8 j, component c at + 4 c: rho_c - rho_ref_c, then the equilibrium velocity u_e
+    // (x, y, z) of the collision of step t - 1; msn receives those of step t
     const T* ms;
     T* msn;
     const double* rho0;      // initial densities (2 N, FP64): the populations w_d rho0 before the first step

@@ -182,15 +182,21 @@ struct MsSite {
     T dr, rs, u0, u1, u2, usq;
 };
 
+// The moment state is site-major: the 8 values of site j at ms[8 j .. 8 j + 7] (component
+// c at 4 c: deviation, u_e x, y, z), one aligned 16-byte (FP32) or 32-byte (FP64) vector
+// per component.
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
 template <typename T>
 __device__ __forceinline__ MsSite<T> ms_site(const Scalars& S, const Fields<T>& F, int c, unsigned j) {
-    const size_t N = S.N;
-    const T* m = F.ms + (size_t)(4 * c) * N;
+    const typename Vec4<T>::type v = reinterpret_cast<const typename Vec4<T>::type*>(F.ms)[(size_t)2 * j + c];
     MsSite<T> a;
-    a.dr = m[j];
-    a.u0 = m[N + j];
-    a.u1 = m[2 * N + j];
-    a.u2 = m[3 * N + j];
+    a.dr = v.x;
+    a.u0 = v.y;
+    a.u1 = v.z;
+    a.u2 = v.w;
     a.rs = T(S.rref[c]) + a.dr;
     a.usq = usq_of<T>(a.u0, a.u1, a.u2);
     return a;
@@ -1516,11 +1522,12 @@ __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F,
         const T tau = T(S.tau);
         const T ue0 = u0 + tau * P0 / rs, ue1 = u1 + tau * P1 / rs, ue2 = u2 + tau * P2 / rs;
         if (MS) {  // tau = 1 moment state: the density and u_e stand for the post-collision populations
-            T* m = F.msn + (size_t)(4 * c) * N;
-            m[i] = dr;
-            m[N + i] = ue0;
-            m[2 * N + i] = ue1;
-            m[3 * N + i] = ue2;
+            typename Vec4<T>::type v;
+            v.x = dr;
+            v.y = ue0;
+            v.z = ue1;
+            v.w = ue2;
+            reinterpret_cast<typename Vec4<T>::type*>(F.msn)[(size_t)2 * i + c] = v;
             continue;
         }
         const T usq = usq_of<T>(ue0, ue1, ue2);
