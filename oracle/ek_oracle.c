@@ -90,6 +90,7 @@ typedef struct {
     double sigma_wall[2];     /* surface charge on the z = 0 wall and on the z = nz-1 wall */
     double poisson_tol;
     double particle_rho, k_hertz, eta;
+    int32_t poisson_lagged;   /* 1: each step takes the lagged Fourier scheme of Sec. II D (periodic) */
 } or_params;
 
 typedef struct {
@@ -408,13 +409,13 @@ static void poisson_source(or_state* s, double* b) {
     dom_shift(s, b, mean);
 }
 
-static int poisson_solve(or_state* s, double tol, int maxit, int* iters, double* rel) {
+/* Conjugate gradients for M phi = b (M = -A with the permittivity in s->eps), from the
+   current phi, to ||b + A phi|| <= tol ||b||; gauge mean(phi) = 0.  Returns 0 or -4. */
+static int cg_solve(or_state* s, const double* b, double tol, int maxit, int* iters_out, double* rel_out) {
     int64_t N = s->N;
-    double* b = (double*)malloc(N * sizeof(double));
     double* r = (double*)malloc(N * sizeof(double));
     double* pp = (double*)malloc(N * sizeof(double));
     double* Mp = (double*)malloc(N * sizeof(double));
-    poisson_source(s, b);
     double bnorm = sqrt(dom_dot(s, b, b));
     int it = 0, status = 0;
     double relres = 0.0;
@@ -451,6 +452,19 @@ static int poisson_solve(or_state* s, double tol, int maxit, int* iters, double*
         relres = sqrt(dom_dot(s, r, r)) / bnorm;
         if (relres > tol) status = -4;
     }
+    *iters_out = it;
+    *rel_out = relres;
+    free(r); free(pp); free(Mp);
+    return status;
+}
+
+static int poisson_solve(or_state* s, double tol, int maxit, int* iters, double* rel) {
+    int64_t N = s->N;
+    double* b = (double*)malloc(N * sizeof(double));
+    poisson_source(s, b);
+    int it = 0;
+    double relres = 0.0;
+    int status = cg_solve(s, b, tol, maxit, &it, &relres);
     /* Wall layers: the potential just outside the domain follows from Gauss's law at
        the charged wall face, phi_wall = phi_adjacent + sigma / eps_adjacent. */
     const or_params* p = &s->p;
@@ -467,7 +481,67 @@ static int poisson_solve(or_state* s, double tol, int maxit, int* iters, double*
     s->last_rel = relres;
     if (iters) *iters = it;
     if (rel) *rel = relres;
-    free(b); free(r); free(pp); free(Mp);
+    free(b);
+    return status;
+}
+
+/* The paper's lagged scheme for the variable-permittivity Poisson equation (Sec. II D):
+   the term with the permittivity gradient is taken at the previous potential, which
+   leaves a constant-coefficient Poisson equation for the new one, solved there by a
+   Fourier method.  Discretely (periodic lattices): with eps_f = eps_i + (eps_j - eps_i)/2
+   the finite-volume equation sum_f eps_f (phi_j - phi_i) = -s_i splits into
+     eps_i L phi_i + sum_f (eps_j - eps_i)(phi_j - phi_i) / 2 = -s_i,
+   L phi_i = sum_f (phi_j - phi_i) the 7-point Laplacian, so the new potential solves
+     L phi = r,  r_i = [ -s_i - sum_f (eps_j - eps_i)(phi_old_j - phi_old_i) / 2 ] / eps_i,
+   with the mean of r removed (the zero wavenumber) and mean(phi) = 0.  Readings: the
+   printed equation omits the 1/eps on the gradient term, which the discrete split (and
+   the units) require; the Fourier inversion is of the same 7-point Laplacian, so a
+   potential that satisfies the finite-volume equation is a fixed point of the scheme.
+   The oracle solves L phi = r by its definition, conjugate gradients with unit
+   coefficients to 1e-13, not by Fourier transforms. */
+static int poisson_lagged_solve(or_state* s, int* iters, double* rel) {
+    const or_params* p = &s->p;
+    int64_t N = s->N;
+    double* b = (double*)malloc(N * sizeof(double));
+    double* rhs = (double*)malloc(N * sizeof(double));
+    double* ones = (double*)malloc(N * sizeof(double));
+    poisson_source(s, b);
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                int64_t i = IDX(p, x, y, z);
+                double lag = 0.0;
+                for (int d = 1; d <= 6; ++d) {
+                    int64_t j = IDX(p, wrap(x + OC[d][0], p->nx), wrap(y + OC[d][1], p->ny), wrap(z + OC[d][2], p->nz));
+                    lag += 0.5 * (s->eps[j] - s->eps[i]) * (s->phi[j] - s->phi[i]);
+                }
+                rhs[i] = (-b[i] - lag) / s->eps[i];
+            }
+    int64_t cnt = 0;
+    dom_shift(s, rhs, dom_sum(s, rhs, &cnt) / (double)cnt);
+    /* M phi = -rhs with unit coefficients */
+    for (int64_t i = 0; i < N; ++i) {
+        rhs[i] = -rhs[i];
+        ones[i] = 1.0;
+    }
+    /* a direct solve needs no starting guess: start from zero */
+    for (int64_t i = 0; i < N; ++i) s->phi[i] = 0.0;
+    double* eps = s->eps;
+    s->eps = ones;
+    int it = 0;
+    double relres = 0.0;
+    int status = cg_solve(s, rhs, 1e-13, 100000, &it, &relres);
+    s->eps = eps;
+    /* the accuracy of the step: relative residual of the finite-volume equation */
+    double* r = rhs;
+    apply_A(s, s->phi, r);
+    for (int64_t i = 0; i < N; ++i) r[i] = b[i] + r[i];
+    double bnorm = sqrt(dom_dot(s, b, b));
+    s->last_iters = it;
+    s->last_rel = bnorm > 0.0 ? sqrt(dom_dot(s, r, r)) / bnorm : 0.0;
+    if (iters) *iters = it;
+    if (rel) *rel = s->last_rel;
+    free(b); free(rhs); free(ones);
     return status;
 }
 
@@ -793,6 +867,7 @@ void or_destroy(or_state* s);
 or_state* or_create(const or_params* prm, const double* rho_a, const double* rho_b, const double* n_plus,
                     const double* n_minus, const double* particles, int32_t n_particles) {
     lattice_setup();
+    if (prm->poisson_lagged && prm->walls_z) return NULL; /* the lagged Fourier scheme is periodic */
     or_state* s = (or_state*)calloc(1, sizeof(or_state));
     s->p = *prm;
     set_threads(&s->p);
@@ -861,7 +936,8 @@ void or_destroy(or_state* s) {
 static int step_once(or_state* s) {
     compute_moments(s);
     compute_charge_perm(s);
-    int st = poisson_solve(s, s->p.poisson_tol, s->p.poisson_maxit, NULL, NULL);
+    int st = s->p.poisson_lagged ? poisson_lagged_solve(s, NULL, NULL)
+                                 : poisson_solve(s, s->p.poisson_tol, s->p.poisson_maxit, NULL, NULL);
     compute_field(s);
     compute_link_fluxes(s);
     compute_forces(s);
@@ -889,6 +965,19 @@ int or_step(or_state* s, int32_t nsteps) {
     compute_moments(s);
     compute_charge_perm(s);
     return worst;
+}
+
+/* One lagged Fourier solve (see poisson_lagged_solve) for the current state, from the
+   potential it holds. */
+int or_poisson_lagged(or_state* s, int32_t* iters, double* rel) {
+    set_threads(&s->p);
+    compute_moments(s);
+    compute_charge_perm(s);
+    int it = 0;
+    int st = poisson_lagged_solve(s, &it, rel);
+    compute_field(s);
+    if (iters) *iters = it;
+    return st;
 }
 
 int or_poisson(or_state* s, double tol, int32_t maxit, int32_t* iters, double* rel) {

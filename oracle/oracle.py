@@ -43,6 +43,7 @@ class OrParams(ctypes.Structure):
         ("E_ext", ctypes.c_double * 3), ("body_accel", ctypes.c_double * 3),
         ("sigma_wall", ctypes.c_double * 2), ("poisson_tol", ctypes.c_double),
         ("particle_rho", ctypes.c_double), ("k_hertz", ctypes.c_double), ("eta", ctypes.c_double),
+        ("poisson_lagged", ctypes.c_int32),
     ]
 
 
@@ -76,6 +77,8 @@ def lib():
         L.or_poisson.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_int32), dp]
         L.or_poisson.restype = ctypes.c_int
+        L.or_poisson_lagged.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), dp]
+        L.or_poisson_lagged.restype = ctypes.c_int
         L.or_get_field.argtypes = [ctypes.c_void_p, ctypes.c_int32, dp]
         L.or_get_field.restype = ctypes.c_int
         L.or_get_populations.argtypes = [ctypes.c_void_p, ctypes.c_int32, dp]
@@ -132,6 +135,7 @@ def params_from_config(cfg, n_threads=0):
     p.sigma_wall[0], p.sigma_wall[1] = cfg.sigma_wall
     p.poisson_tol = cfg.poisson_tol_oracle
     p.particle_rho, p.k_hertz, p.eta = cfg.particle_rho, cfg.k_hertz, cfg.eta
+    p.poisson_lagged = int(cfg.poisson_solver == "fft")
     return p
 
 
@@ -170,6 +174,14 @@ class Oracle:
         it = ctypes.c_int32(0)
         rel = ctypes.c_double(0.0)
         st = lib().or_poisson(self._h, float(tol), int(maxit), ctypes.byref(it), ctypes.byref(rel))
+        return st, it.value, rel.value
+
+    def poisson_lagged(self):
+        """One lagged Fourier solve for the current state from its potential; returns
+        (status, CG iterations, relative residual of the finite-volume equation)."""
+        it = ctypes.c_int32(0)
+        rel = ctypes.c_double(0.0)
+        st = lib().or_poisson_lagged(self._h, ctypes.byref(it), ctypes.byref(rel))
         return st, it.value, rel.value
 
     def field(self, name):

@@ -45,7 +45,8 @@ class EKConfig:
     sigma_wall: Tuple[float, float] = (0.0, 0.0)
     poisson_tol: float = 1e-10       # relative residual of the GPU solve
     poisson_maxit: int = 20000
-    poisson_solver: str = "auto"     # "auto" (multigrid where possible), "sor" or "mg"
+    poisson_solver: str = "auto"     # "auto" (multigrid where possible), "sor", "mg", or "fft" (the
+                                     # lagged Fourier scheme, one solve per step, periodic lattices)
     poisson_tol_oracle: float = 1e-12
     poisson_maxit_oracle: int = 200000
     subsample: int = 8               # sub-cells per axis for the solid fraction

@@ -199,6 +199,53 @@ def test_poisson_fourier_eigenvalue():
     np.testing.assert_allclose(o.field("phi"), q / (cfg.eps_a * lam), atol=1e-10 * np.abs(q).max() / (cfg.eps_a * lam), rtol=0)
 
 
+def test_lagged_fourier_single_mode_uniform_eps():
+    """The lagged scheme (Sec. II D) with uniform eps has no gradient term: from any
+    starting potential one solve gives the closed form q / (eps sum_d (2 - 2 cos k_d))."""
+    cfg = wl.EKConfig(16, 8, 12, poisson_solver="fft")
+    kv = (2 * np.pi * 3 / 16, 2 * np.pi / 8, 2 * np.pi * 2 / 12)
+    z, y, x = np.meshgrid(np.arange(12), np.arange(8), np.arange(16), indexing="ij")
+    q = 1e-5 * np.cos(kv[0] * x + kv[1] * y + kv[2] * z)
+    inp = wl.uniform(cfg, 0.5, 0.5, 1e-3, 1e-3)
+    inp.n_plus = 1e-3 + q / 2
+    inp.n_minus = 1e-3 - q / 2
+    o = run(cfg, inp)
+    r = np.random.Generator(np.random.PCG64(3))
+    o.set_state(o.populations(0), o.populations(1), o.field("n_plus"), o.field("n_minus"),
+                r.uniform(-1, 1, q.shape))
+    st, _, rel = o.poisson_lagged()
+    lam = sum(2 - 2 * np.cos(k) for k in kv)
+    exact = q / (cfg.eps_a * lam)
+    assert st == 0 and rel < 1e-11
+    np.testing.assert_allclose(o.field("phi"), exact, atol=1e-10 * np.abs(exact).max(), rtol=0)
+
+
+def test_lagged_fourier_fixed_point_variable_eps():
+    """A potential that solves the finite-volume equation is a fixed point of the lagged
+    scheme, whose gradient term is the finite-volume split of the varying permittivity;
+    from a perturbed potential one solve moves it back towards that solution (a wrong
+    sign or factor in the gradient term breaks both)."""
+    cfg, inp = wl.droplet(16, seed=5, precision="fp64", field=1e-3, salt=1e-3, G=3.6, radius=5)
+    cfg.eps_b = 3.0 * cfg.eps_a
+    cfg.poisson_solver = "fft"
+    cfg.poisson_tol_oracle = 1e-13
+    z, y, x = np.meshgrid(np.arange(16), np.arange(16), np.arange(16), indexing="ij")
+    inp.n_plus = inp.n_plus * (1.0 + 0.2 * np.cos(2 * np.pi * (x + 2 * y) / 16))  # a charge pattern
+    o = run(cfg, inp)
+    phi0 = o.field("phi")
+    assert np.abs(phi0).max() > 0.0
+    fa, fb, npl, nmi = o.populations(0), o.populations(1), o.field("n_plus"), o.field("n_minus")
+    st, _, rel = o.poisson_lagged()
+    assert st == 0 and rel < 1e-10
+    np.testing.assert_allclose(o.field("phi"), phi0, atol=1e-10 * np.abs(phi0).max(), rtol=0)
+    z, y, x = np.meshgrid(np.arange(16), np.arange(16), np.arange(16), indexing="ij")
+    pert = 0.3 * np.abs(phi0).max() * np.sin(2 * np.pi * x / 16) * np.cos(2 * np.pi * z / 16)
+    o.set_state(fa, fb, npl, nmi, phi0 + pert)
+    o.poisson_lagged()
+    err = np.abs(o.field("phi") - phi0).max()
+    assert 1e-6 * np.abs(pert).max() < err < 0.6 * np.abs(pert).max(), err
+
+
 def _gauss_1d(q, eps, walls, sig=(0.0, 0.0)):
     """Potential differences from Gauss's law for a 1-D column: displacement across the
     face above cell z is D_{z+1/2} = D_{z-1/2} + s_z, and phi_{z+1} - phi_z = -D / eps_face."""
