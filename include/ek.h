@@ -47,6 +47,12 @@ typedef int32_t ek_status;
 #define EK_POISSON_AUTO 0 /* multigrid when every axis divides by 4, else SOR */
 #define EK_POISSON_SOR 1  /* red-black successive over-relaxation */
 #define EK_POISSON_MG 2   /* geometric multigrid V-cycles (EINVAL if the lattice cannot be coarsened) */
+#define EK_POISSON_FFT 3  /* the lagged Fourier scheme of Sec. II D, periodic lattices only: each step solves
+                             L phi = r once by FFT, L the 7-point Laplacian and
+                             r = [-s - sum_f (eps_j - eps_i)(phi_old_j - phi_old_i)/2] / eps with the
+                             gradient term at the previous potential (mean(r) and mean(phi) = 0); a
+                             converged finite-volume potential is its fixed point.  The initial potential
+                             and ek_poisson use the converged solver (multigrid or SOR) */
 
 #define EK_FP64 0 /* populations, ions, charge and permittivity in double */
 #define EK_FP32 1 /* populations as float deviations from w_d rho_ref, ions in float; phi stays double */
@@ -56,7 +62,7 @@ typedef struct ek_params {
     int32_t walls_z;            /* 0: periodic in z; 1: solid charged walls at z = 0 and z = nz-1 */
     int32_t precision;          /* EK_FP64 or EK_FP32 */
     int32_t poisson_maxit;      /* maximum Poisson iterations per solve (SOR sweeps or V-cycles) */
-    int32_t poisson_solver;     /* EK_POISSON_AUTO, EK_POISSON_SOR or EK_POISSON_MG */
+    int32_t poisson_solver;     /* EK_POISSON_AUTO, EK_POISSON_SOR, EK_POISSON_MG or EK_POISSON_FFT */
     int32_t subsample;          /* sub-cells per axis for the particle solid fraction (e.g. 8) */
     int32_t move_particles;     /* 1: integrate particle motion every step */
     double tau;                 /* BGK relaxation time of both fluids (> 1/2) */
@@ -107,7 +113,8 @@ typedef struct ek_obs {
     double momentum[3];    /* total fluid momentum sum_d f_d c_d (pre-collision) */
     double max_u;          /* max |u| of the pre-force barycentric velocity */
     double source_mean;    /* mean removed from the Poisson source by the last solve */
-    double poisson_rel;    /* relative residual reached by the last solve */
+    double poisson_rel;    /* relative residual reached by the last solve (-1 after a lagged Fourier step:
+                              not measured) */
     int64_t poisson_iters; /* iterations (SOR sweeps or V-cycles) of the last solve */
     int64_t poisson_total; /* iterations summed over all solves since ek_init */
     int32_t poisson_mg_levels; /* multigrid levels in use (0: SOR) */

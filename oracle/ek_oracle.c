@@ -169,9 +169,11 @@ void or_equilibrium(double rho, const double* u, double* feq) {
 /* so that it sums to Q exactly (the printed normalising volume is a typo).        */
 /* ------------------------------------------------------------------------------ */
 static double min_image(double d, int n) {
+    /* whole periods taken off at once: the same result as stepping by L for finite d,
+       NaN (not an endless loop) for a non-finite one */
     double L = (double)n;
-    while (d > 0.5 * L) d -= L;
-    while (d < -0.5 * L) d += L;
+    if (d > 0.5 * L) d -= L * ceil((d - 0.5 * L) / L);
+    if (d < -0.5 * L) d += L * ceil((-0.5 * L - d) / L);
     return d;
 }
 

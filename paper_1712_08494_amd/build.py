@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libek.so")
-SOURCES = ["ek_kernels.hip", "ek_adjoint.hip", "ek_api.hip"]
+SOURCES = ["ek_kernels.hip", "ek_adjoint.hip", "ek_fft.hip", "ek_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -51,7 +51,7 @@ def build(verbose=False, jobs=2):
         if p.wait() != 0:
             raise RuntimeError("hipcc failed: " + " ".join(c))
     tmp = LIB_PATH + ".tmp"
-    link = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    link = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lhipfft"]
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.check_call(link)

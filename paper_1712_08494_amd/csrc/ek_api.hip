@@ -9,6 +9,8 @@
 #include <string>
 #include <vector>
 
+#include <hipfft/hipfft.h>
+
 #include "ek.h"
 #include "ek_internal.h"
 #include "ek_lattice.h"
@@ -108,6 +110,12 @@ struct ek_ctx {
     // 8 N values (step parity as the populations), the FP64 initial densities the first
     // moments pass reads, and whether a step has written a moment state yet
     bool moment_state = false;
+    // the lagged Fourier Poisson scheme (EK_POISSON_FFT): plans on the context's stream,
+    // the right-hand side (N doubles) and the spectrum (nz ny (nx/2+1) complex doubles)
+    bool fft = false;
+    hipfftHandle fft_fwd = 0, fft_inv = 0;
+    double* fft_rhs = nullptr;
+    double* fft_spec = nullptr;
     void* ms[2] = {nullptr, nullptr};
     double* rho0 = nullptr;
     bool ms_first = false;
@@ -599,11 +607,63 @@ static void moments_pass(ek_ctx* c) {
     launch_source_mean(c->S, c->red, c->nblk, c->scal, c->st);
 }
 
+// The rest of a step after the Poisson solve: forces, the fused sweep, particles, and the
+// swap of the step parity.
+template <typename T>
+static ek_status step_rest(ek_ctx* c) {
+    Fields<T> F = fields<T>(c);
+    {
+        Timer tm(c, EK_T_FORCE);
+        launch_force<T>(c->S, F, c->st);
+    }
+    {
+        Timer tm(c, EK_T_FUSED);
+        launch_fused<T>(c->S, F, c->st);
+    }
+    if (c->np > 0) {
+        Timer tm(c, EK_T_PARTICLE);
+        launch_particle_sum<T>(c->S, F, c->np, c->plink_off, c->plink_idx, c->psite_off, c->psite_idx, c->pF,
+                               c->st);
+        launch_particle_move(c->S, c->np, c->px[c->pcur], c->pv[c->pcur], c->prad, c->pF, c->px[c->pcur ^ 1],
+                             c->pv[c->pcur ^ 1], c->p.particle_rho, c->p.k_hertz, c->p.eta, c->p.move_particles,
+                             c->st);
+        c->pcur ^= 1;
+    }
+    EK_HIP(hipGetLastError());
+    c->cur ^= 1;
+    c->ms_first = false;  // a moment-state context now holds the state written by this step
+    c->steps++;
+    return EK_OK;
+}
+
+// One lagged Fourier solve (ek_fft.hip) from the potential held: right-hand side, forward
+// FFT, spectral division, inverse FFT into the potential.
+template <typename T>
+static ek_status lagged_fourier(ek_ctx* c) {
+    Timer tm(c, EK_T_POISSON);
+    launch_lag_rhs<T>(c->S, fields<T>(c), c->fft_rhs, c->st);
+    if (hipfftExecD2Z(c->fft_fwd, c->fft_rhs, (hipfftDoubleComplex*)c->fft_spec) != HIPFFT_SUCCESS)
+        return fail(c, EK_EHIP, "hipfftExecD2Z failed");
+    launch_lag_scale(c->fft_spec, c->S.nx, c->S.ny, c->S.nz, c->st);
+    if (hipfftExecZ2D(c->fft_inv, (hipfftDoubleComplex*)c->fft_spec, c->phi) != HIPFFT_SUCCESS)
+        return fail(c, EK_EHIP, "hipfftExecZ2D failed");
+    EK_HIP(hipGetLastError());
+    c->last_iters = 1;
+    c->last_rel = -1.0;  // not measured (it would cost a residual pass and a host read-back per step)
+    c->ptotal += 1;
+    return EK_OK;
+}
+
 template <typename T>
 static ek_status step_impl(ek_ctx* c, int nsteps) {
     ek_status worst = EK_OK;
     for (int s = 0; s < nsteps; ++s) {
         moments_pass<T>(c);
+        if (c->fft) {
+            EK_TRY(lagged_fourier<T>(c));
+            EK_TRY(step_rest<T>(c));
+            continue;
+        }
         int order = c->phi_history;
         bool probe = false;
         if (order == 0) {  // adaptive: keep the order with the smaller start residual, re-probe the other
@@ -630,28 +690,7 @@ static ek_status step_impl(ek_ctx* c, int nsteps) {
             worst = ps;
         else if (ps != EK_OK)
             return ps;
-        Fields<T> F = fields<T>(c);
-        {
-            Timer tm(c, EK_T_FORCE);
-            launch_force<T>(c->S, F, c->st);
-        }
-        {
-            Timer tm(c, EK_T_FUSED);
-            launch_fused<T>(c->S, F, c->st);
-        }
-        if (c->np > 0) {
-            Timer tm(c, EK_T_PARTICLE);
-            launch_particle_sum<T>(c->S, F, c->np, c->plink_off, c->plink_idx, c->psite_off, c->psite_idx, c->pF,
-                                   c->st);
-            launch_particle_move(c->S, c->np, c->px[c->pcur], c->pv[c->pcur], c->prad, c->pF, c->px[c->pcur ^ 1],
-                                 c->pv[c->pcur ^ 1], c->p.particle_rho, c->p.k_hertz, c->p.eta, c->p.move_particles,
-                                 c->st);
-            c->pcur ^= 1;
-        }
-        EK_HIP(hipGetLastError());
-        c->cur ^= 1;
-        c->ms_first = false;  // a moment-state context now holds the state written by this step
-        c->steps++;
+        EK_TRY(step_rest<T>(c));
     }
     return worst;
 }
@@ -857,7 +896,16 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     EK_HIP(hipStreamSynchronize(c->st));
     c->stage2 = stage2;
     EK_HIP(hipGetLastError());
-    // initial potential
+    if (c->fft) {
+        EK_TRY(dalloc(c, (void**)&c->fft_rhs, (size_t)N * 8));
+        EK_TRY(dalloc(c, (void**)&c->fft_spec, (size_t)p.nz * p.ny * (p.nx / 2 + 1) * 16));
+        if (hipfftPlan3d(&c->fft_fwd, p.nz, p.ny, p.nx, HIPFFT_D2Z) != HIPFFT_SUCCESS ||
+            hipfftPlan3d(&c->fft_inv, p.nz, p.ny, p.nx, HIPFFT_Z2D) != HIPFFT_SUCCESS ||
+            hipfftSetStream(c->fft_fwd, c->st) != HIPFFT_SUCCESS || hipfftSetStream(c->fft_inv, c->st) != HIPFFT_SUCCESS)
+            return fail(c, EK_EHIP, "hipFFT plan creation failed");
+    }
+    // initial potential (with the lagged Fourier scheme too: its first step needs a solved
+    // potential to lag)
     moments_pass<T>(c);
     ek_status st = poisson_solve<T>(c, p.poisson_tol, p.poisson_maxit, nullptr, nullptr);
     EK_HIP(hipMemcpyAsync(c->phi_prev, c->phi, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
@@ -934,7 +982,10 @@ extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const doub
     S.sigma0 = p->sigma_wall[0];
     S.sigma1 = p->sigma_wall[1];
     c->omega = p->sor_omega > 0.0 ? p->sor_omega : omega_for(*p);
-    if (p->poisson_solver < 0 || p->poisson_solver > 2) return fail(c, EK_EINVAL, "unknown poisson_solver");
+    if (p->poisson_solver < 0 || p->poisson_solver > 3) return fail(c, EK_EINVAL, "unknown poisson_solver");
+    if (p->poisson_solver == EK_POISSON_FFT && p->walls_z)
+        return fail(c, EK_EINVAL, "the lagged Fourier scheme needs a periodic lattice");
+    c->fft = p->poisson_solver == EK_POISSON_FFT;
     if (p->poisson_solver != EK_POISSON_SOR) {
         // Coarsen by two while every axis of the current level divides by 4 (so that the
         // coarse level keeps even axes for red-black ordering) and the level is large.
@@ -1050,6 +1101,7 @@ static ek_status adj_check(ek_ctx* c) {
     if (c->esz != 8) return fail(c, EK_EINVAL, "reverse mode needs an FP64 context");
     if (c->S.walls || c->np > 0) return fail(c, EK_EINVAL, "reverse mode covers periodic lattices without particles");
     if (c->moment_state) return fail(c, EK_EINVAL, "reverse mode needs stored populations (moment_state = 0)");
+    if (c->fft) return fail(c, EK_EINVAL, "reverse mode differentiates a converged Poisson solve, not the lagged one");
     return EK_OK;
 }
 
@@ -1464,6 +1516,7 @@ extern "C" ek_status ek_autotune_multigrid(ek_ctx* c, int32_t trial_steps, int32
     if (!c || !c->phi) return EK_ESTATE;
     if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: its cycle is fixed by the batch");
     if (c->mg.empty()) return fail(c, EK_EINVAL, "this lattice is solved by SOR: there is no V-cycle to tune");
+    if (c->fft) return fail(c, EK_EINVAL, "the lagged Fourier scheme runs no V-cycles in its steps");
     if (trial_steps < 1 || trial_steps > 1000) return fail(c, EK_EINVAL, "trial_steps must be in 1..1000");
     return c->esz == 4 ? autotune_impl<float>(c, trial_steps, best, ms_per_step)
                        : autotune_impl<double>(c, trial_steps, best, ms_per_step);
@@ -1602,6 +1655,8 @@ extern "C" ek_status ek_destroy(ek_ctx* c) {
     if (c->phi) (void)hipStreamSynchronize(c->st);
     resolve_timing(c);
     vcycle_graph_drop(c);
+    if (c->fft_fwd) (void)hipfftDestroy(c->fft_fwd);
+    if (c->fft_inv) (void)hipfftDestroy(c->fft_inv);
     if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
     for (auto e : c->pool) (void)hipEventDestroy(e);
     for (void* a : c->allocs) (void)hipFree(a);
@@ -1829,8 +1884,8 @@ extern "C" ek_status ek_batch_init(const ek_params* params, int32_t n_rep, const
             b->err = "batched replicas are periodic and share one precision";
             return EK_EINVAL;
         }
-        if (p.moment_state) {
-            b->err = "batched replicas store populations (moment_state = 0)";
+        if (p.moment_state || p.poisson_solver == EK_POISSON_FFT) {
+            b->err = "batched replicas store populations and solve with V-cycles";
             return EK_EINVAL;
         }
         ek_ctx* c = nullptr;

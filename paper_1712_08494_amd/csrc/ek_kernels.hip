@@ -1637,10 +1637,13 @@ void launch_particle_sum(const Scalars& S, const Fields<T>& F, int np, const int
                        pF);
 }
 
+// Minimum image of a separation along a periodic axis of length n: the number of periods a
+// loop would take off is computed directly, so a non-finite separation gives NaN instead of
+// a loop that never ends.
 __device__ __forceinline__ double min_image(double d, int n) {
     const double L = (double)n;
-    while (d > 0.5 * L) d -= L;
-    while (d < -0.5 * L) d += L;
+    if (d > 0.5 * L) d -= L * ceil((d - 0.5 * L) / L);
+    if (d < -0.5 * L) d += L * ceil((-0.5 * L - d) / L);
     return d;
 }
 

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libek.so")
 
 EK_OK, EK_EINVAL, EK_ENOMEM, EK_EHIP, EK_ENOCONV, EK_ENONFINITE, EK_ESTATE = 0, -1, -2, -3, -4, -5, -6
 EK_FP64, EK_FP32 = 0, 1
-POISSON_SOLVERS = {"auto": 0, "sor": 1, "mg": 2}
+POISSON_SOLVERS = {"auto": 0, "sor": 1, "mg": 2, "fft": 3}
 FIELDS = {"rho_a": 0, "rho_b": 1, "n_plus": 2, "n_minus": 3, "phi": 4, "ux": 5, "uy": 6, "uz": 7, "q": 8,
           "eps": 9, "psi_s": 10, "solid": 11, "Ex": 12, "Ey": 13, "Ez": 14}
 TIMING_CLASSES = ["moments", "poisson", "force", "fused", "particle", "iter", "smooth"]
