@@ -89,7 +89,10 @@ def test_adjoint_droplet_96_short():
     import bench
     cfg, inp = wl.droplet(96, seed=5, precision="fp64", field=5e-4, salt=1e-3, G=3.6, radius=20)
     cfg.eps_b = 4.0 * cfg.eps_a
-    cfg.poisson_tol = 1e-11
+    # The difference quotients below resolve changes of D near 1e-12 relative; a Poisson
+    # tolerance of 1e-11 leaves solver noise of that order in D (seen as a 1.3e-4 scatter in
+    # the permittivity derivative), so the solves here are converged further.
+    cfg.poisson_tol = 1e-13
     T, K = 60, 20
     print(f"droplet 96^3, {T} steps: adjoint vs finite differences", flush=True)
     params = torch.tensor([cfg.E_ext[2], 4.0, cfg.G], dtype=torch.float64, requires_grad=True)
