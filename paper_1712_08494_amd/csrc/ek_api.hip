@@ -116,6 +116,7 @@ struct ek_ctx {
     hipfftHandle fft_fwd = 0, fft_inv = 0;
     double* fft_rhs = nullptr;
     double* fft_spec = nullptr;
+    double* fft_tab = nullptr;  // per-axis eigenvalue parts (nx/2 + 1 + ny + nz doubles)
     void* ms[2] = {nullptr, nullptr};
     double* rho0 = nullptr;
     bool ms_first = false;
@@ -644,7 +645,7 @@ static ek_status lagged_fourier(ek_ctx* c) {
     launch_lag_rhs<T>(c->S, fields<T>(c), c->fft_rhs, c->st);
     if (hipfftExecD2Z(c->fft_fwd, c->fft_rhs, (hipfftDoubleComplex*)c->fft_spec) != HIPFFT_SUCCESS)
         return fail(c, EK_EHIP, "hipfftExecD2Z failed");
-    launch_lag_scale(c->fft_spec, c->S.nx, c->S.ny, c->S.nz, c->st);
+    launch_lag_scale(c->fft_spec, c->fft_tab, c->S.nx, c->S.ny, c->S.nz, c->st);
     if (hipfftExecZ2D(c->fft_inv, (hipfftDoubleComplex*)c->fft_spec, c->phi) != HIPFFT_SUCCESS)
         return fail(c, EK_EHIP, "hipfftExecZ2D failed");
     EK_HIP(hipGetLastError());
@@ -899,6 +900,8 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     if (c->fft) {
         EK_TRY(dalloc(c, (void**)&c->fft_rhs, (size_t)N * 8));
         EK_TRY(dalloc(c, (void**)&c->fft_spec, (size_t)p.nz * p.ny * (p.nx / 2 + 1) * 16));
+        EK_TRY(dalloc(c, (void**)&c->fft_tab, (size_t)(p.nx / 2 + 1 + p.ny + p.nz) * 8));
+        launch_lag_table(c->fft_tab, p.nx, p.ny, p.nz, c->st);
         if (hipfftPlan3d(&c->fft_fwd, p.nz, p.ny, p.nx, HIPFFT_D2Z) != HIPFFT_SUCCESS ||
             hipfftPlan3d(&c->fft_inv, p.nz, p.ny, p.nx, HIPFFT_Z2D) != HIPFFT_SUCCESS ||
             hipfftSetStream(c->fft_fwd, c->st) != HIPFFT_SUCCESS || hipfftSetStream(c->fft_inv, c->st) != HIPFFT_SUCCESS)

@@ -33,11 +33,24 @@ __global__ __launch_bounds__(kBlock) void k_lag_rhs(Scalars S, Fields<T> F, doub
     rhs[i] = (-s - lag) / ei;
 }
 
+// Per-axis parts of the 7-point Laplacian's eigenvalues, 2 cos(2 pi k / n) - 2, for the
+// nx/2 + 1 wavenumbers along x, then ny along y, then nz along z (set up once per context).
+__global__ void k_lag_table(double* __restrict__ tab, int nx, int ny, int nz) {
+    const int hx1 = nx / 2 + 1;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= hx1 + ny + nz) return;
+    const double twopi = 6.283185307179586476925286766559;
+    const int n = t < hx1 ? nx : (t < hx1 + ny ? ny : nz);
+    const int k = t < hx1 ? t : (t < hx1 + ny ? t - hx1 : t - hx1 - ny);
+    tab[t] = 2.0 * cos(twopi * k / n) - 2.0;
+}
+
 // Spectrum of a real-to-complex transform of an (nz, ny, nx) array, x fastest: nx/2 + 1
 // wavenumbers along x.  Divide by the Laplacian's eigenvalue and by N (the inverse
 // transform is unnormalised); zero wavenumber dropped.
-__global__ __launch_bounds__(kBlock) void k_lag_scale(double2* __restrict__ spec, int nx, int ny, int nz,
-                                                      double inv_hx1, double inv_ny, double inv_n) {
+__global__ __launch_bounds__(kBlock) void k_lag_scale(double2* __restrict__ spec, const double* __restrict__ tab,
+                                                      int nx, int ny, int nz, double inv_hx1, double inv_ny,
+                                                      double inv_n) {
     const unsigned hx1 = (unsigned)(nx / 2 + 1);
     const unsigned total = hx1 * (unsigned)ny * (unsigned)nz;
     const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -48,8 +61,7 @@ __global__ __launch_bounds__(kBlock) void k_lag_scale(double2* __restrict__ spec
         spec[0] = make_double2(0.0, 0.0);
         return;
     }
-    const double twopi = 6.283185307179586476925286766559;
-    const double lam = 2.0 * cos(twopi * kx / nx) + 2.0 * cos(twopi * ky / ny) + 2.0 * cos(twopi * kz / nz) - 6.0;
+    const double lam = tab[kx] + tab[hx1 + ky] + tab[hx1 + ny + kz];
     const double g = inv_n / lam;
     const double2 v = spec[t];
     spec[t] = make_double2(v.x * g, v.y * g);
@@ -59,11 +71,16 @@ template <typename T> void launch_lag_rhs(const Scalars& S, const Fields<T>& F, 
     hipLaunchKernelGGL(k_lag_rhs<T>, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F, rhs);
 }
 
-void launch_lag_scale(double* spec, int nx, int ny, int nz, hipStream_t st) {
+void launch_lag_table(double* tab, int nx, int ny, int nz, hipStream_t st) {
+    const int n = nx / 2 + 1 + ny + nz;
+    hipLaunchKernelGGL(k_lag_table, dim3((n + 63) / 64), dim3(64), 0, st, tab, nx, ny, nz);
+}
+
+void launch_lag_scale(double* spec, const double* tab, int nx, int ny, int nz, hipStream_t st) {
     const unsigned hx1 = (unsigned)(nx / 2 + 1);
     const unsigned total = hx1 * (unsigned)ny * (unsigned)nz;
     hipLaunchKernelGGL(k_lag_scale, dim3((total + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
-                       reinterpret_cast<double2*>(spec), nx, ny, nz, 1.0 / hx1, 1.0 / ny,
+                       reinterpret_cast<double2*>(spec), tab, nx, ny, nz, 1.0 / hx1, 1.0 / ny,
                        1.0 / ((double)nx * ny * nz));
 }
 

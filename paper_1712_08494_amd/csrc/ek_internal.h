@@ -168,7 +168,8 @@ template <typename T> void launch_fused(const Scalars& S, const Fields<T>& F, hi
 // lagged Fourier Poisson scheme (ek_fft.hip): right-hand side r from the potential held,
 // and the spectral division of the forward transform (nz, ny, nx/2+1 complex doubles)
 template <typename T> void launch_lag_rhs(const Scalars& S, const Fields<T>& F, double* rhs, hipStream_t st);
-void launch_lag_scale(double* spec, int nx, int ny, int nz, hipStream_t st);
+void launch_lag_table(double* tab, int nx, int ny, int nz, hipStream_t st);  // nx/2+1+ny+nz doubles
+void launch_lag_scale(double* spec, const double* tab, int nx, int ny, int nz, hipStream_t st);
 // populations of component c at time t of a moment-state context (FP64, 19 N, f not g)
 template <typename T> void launch_export_pop(const Scalars& S, const Fields<T>& F, int c, double* out, hipStream_t st);
 template <typename T>
