@@ -846,13 +846,65 @@ __device__ __forceinline__ void prolong_fine_body(const Scalars& S, const Fields
     F.phi[i] += v;
 }
 
+// The same, one thread per coarse cell for its eight lattice children: the 3x3x3 coarse
+// neighbourhood is loaded once into registers and each child is interpolated with exactly
+// the expression and order of prolong_fine_body (bit-identical); the two x-children of a
+// row are read and written as one 16-byte pair.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mg_prolong_fine(Scalars S, Fields<T> F, MGLevel C) {
-    prolong_fine_body<T>(S, F, C, xcd_linear());
+    const unsigned t = xcd_linear();
+    if (t >= C.n) return;
+    int I, J, K;
+    level_xyz(t, C, I, J, K);
+    double P[3][3][3];  // coarse potential at (I + ox - 1, J + oy - 1, K + oz - 1), periodic
+#pragma unroll
+    for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox)
+                P[oz][oy][ox] = C.phi[lid(C, wrapc(I + ox - 1, C.nx), wrapc(J + oy - 1, C.ny), wrapc(K + oz - 1, C.nz))];
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz) {
+        const int z = 2 * K + cz;
+        if (z < S.z0 || z > S.z1) continue;
+        const int dz = cz ? 1 : -1;
+        const bool zwrap = S.walls && (K + dz < 0 || K + dz >= C.nz);
+        const double wz = zwrap ? 0.0 : 0.25;
+        const double wzs[2] = {1.0 - wz, wz};
+        const int zo[2] = {1, 1 + dz};
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy) {
+            const int y = 2 * J + cy;
+            const int dy = cy ? 1 : -1;
+            const double wys[2] = {0.75, 0.25};
+            const int yo[2] = {1, 1 + dy};
+            double2* row = reinterpret_cast<double2*>(F.phi + ((size_t)z * S.ny + y) * S.nx + 2 * I);
+            double2 f = *row;
+            double vv[2];
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                const int dx = cx ? 1 : -1;
+                const double wxs[2] = {0.75, 0.25};
+                const int xo[2] = {1, 1 + dx};
+                double v = 0.0;
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int a = 0; a < 2; ++a) v += wxs[a] * wys[b] * wzs[c] * P[zo[c]][yo[b]][xo[a]];
+                vv[cx] = v;
+            }
+            f.x += vv[0];
+            f.y += vv[1];
+            *row = f;
+        }
+    }
 }
 
 template <typename T> void launch_mg_prolong_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st) {
-    hipLaunchKernelGGL(k_mg_prolong_fine<T>, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F, c);
+    hipLaunchKernelGGL(k_mg_prolong_fine<T>, dim3(site_blocks(c.n)), dim3(kBlock), 0, st, S, F, c);
 }
 
 __device__ __forceinline__ void prolong_body(const MGLevel& C, const MGLevel& Fl, unsigned i) {
