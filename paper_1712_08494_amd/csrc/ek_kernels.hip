@@ -707,7 +707,8 @@ __device__ __forceinline__ void restrict_fine_body(const Scalars& S, const Field
     auto at = [&](int a, int b, int c) {
         return (unsigned)xs[a] + (unsigned)S.nx * ((unsigned)ys[b] + (unsigned)S.ny * (unsigned)zs[c]);
     };
-    double P[4][4][4], E[4][4][4];
+    double P[4][4][4];
+    T E[4][4][4];  // permittivity in its storage precision (exactly widened where used)
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -718,7 +719,7 @@ __device__ __forceinline__ void restrict_fine_body(const Scalars& S, const Field
                 if (outer <= 1) {
                     const unsigned g = at(a, b, c);
                     P[c][b][a] = F.phi[g];
-                    E[c][b][a] = (double)F.eps[g];
+                    E[c][b][a] = F.eps[g];
                 }
             }
     const double mean = F.scal[0];
@@ -731,25 +732,25 @@ __device__ __forceinline__ void restrict_fine_body(const Scalars& S, const Field
             for (int a = 1; a < 3; ++a) {
                 const int z = zs[c];
                 if (z < S.z0 || z > S.z1) continue;
-                const double ei = E[c][b][a];
+                const double ei = (double)E[c][b][a];
                 double diag = 0.0, off = 0.0;
                 {
-                    const double ea = 0.5 * (ei + E[c][b][a - 1]), eb = 0.5 * (ei + E[c][b][a + 1]);
+                    const double ea = 0.5 * (ei + (double)E[c][b][a - 1]), eb = 0.5 * (ei + (double)E[c][b][a + 1]);
                     diag += ea + eb;
                     off += ea * P[c][b][a - 1] + eb * P[c][b][a + 1];
                 }
                 {
-                    const double ea = 0.5 * (ei + E[c][b - 1][a]), eb = 0.5 * (ei + E[c][b + 1][a]);
+                    const double ea = 0.5 * (ei + (double)E[c][b - 1][a]), eb = 0.5 * (ei + (double)E[c][b + 1][a]);
                     diag += ea + eb;
                     off += ea * P[c][b - 1][a] + eb * P[c][b + 1][a];
                 }
                 if (!(S.walls && z == S.z0)) {
-                    const double ea = 0.5 * (ei + E[c - 1][b][a]);
+                    const double ea = 0.5 * (ei + (double)E[c - 1][b][a]);
                     diag += ea;
                     off += ea * P[c - 1][b][a];
                 }
                 if (!(S.walls && z == S.z1)) {
-                    const double eb = 0.5 * (ei + E[c + 1][b][a]);
+                    const double eb = 0.5 * (ei + (double)E[c + 1][b][a]);
                     diag += eb;
                     off += eb * P[c + 1][b][a];
                 }
@@ -765,11 +766,11 @@ __device__ __forceinline__ void restrict_fine_body(const Scalars& S, const Field
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mg_restrict_fine(Scalars S, Fields<T> F, MGLevel C) {
-    restrict_fine_body<T>(S, F, C, blockIdx.x * blockDim.x + threadIdx.x);
+    restrict_fine_body<T>(S, F, C, xcd_linear());
 }
 
 template <typename T> void launch_mg_restrict_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st) {
-    hipLaunchKernelGGL(k_mg_restrict_fine<T>, dim3((c.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, S, F, c);
+    hipLaunchKernelGGL(k_mg_restrict_fine<T>, dim3(site_blocks(c.n)), dim3(kBlock), 0, st, S, F, c);
 }
 
 __device__ __forceinline__ void restrict_body(const MGLevel& Fl, const MGLevel& C, unsigned t) {
