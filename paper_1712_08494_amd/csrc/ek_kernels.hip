@@ -622,11 +622,11 @@ __device__ __forceinline__ void coarsen_fine_body(const Scalars& S, const Fields
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mg_coarsen_fine(Scalars S, Fields<T> F, MGLevel C) {
-    coarsen_fine_body<T>(S, F, C, blockIdx.x * blockDim.x + threadIdx.x);
+    coarsen_fine_body<T>(S, F, C, xcd_linear());
 }
 
 template <typename T> void launch_mg_coarsen_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st) {
-    hipLaunchKernelGGL(k_mg_coarsen_fine<T>, dim3((c.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, S, F, c);
+    hipLaunchKernelGGL(k_mg_coarsen_fine<T>, dim3(site_blocks(c.n)), dim3(kBlock), 0, st, S, F, c);
 }
 
 __device__ __forceinline__ void coarsen_body(const MGLevel& Fl, const MGLevel& C, unsigned t) {
@@ -646,11 +646,11 @@ __device__ __forceinline__ void coarsen_body(const MGLevel& Fl, const MGLevel& C
 }
 
 __global__ __launch_bounds__(kBlock) void k_mg_coarsen(MGLevel Fl, MGLevel C) {
-    coarsen_body(Fl, C, blockIdx.x * blockDim.x + threadIdx.x);
+    coarsen_body(Fl, C, xcd_linear());
 }
 
 void launch_mg_coarsen(const MGLevel& f, const MGLevel& c, hipStream_t st) {
-    hipLaunchKernelGGL(k_mg_coarsen, dim3((c.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, f, c);
+    hipLaunchKernelGGL(k_mg_coarsen, dim3(site_blocks(c.n)), dim3(kBlock), 0, st, f, c);
 }
 
 // Row of a coarse level: diagonal, off-diagonal sum, at cell (x, y, z).
@@ -681,12 +681,12 @@ __device__ __forceinline__ void smooth_body(const MGLevel& L, int color, double 
 }
 
 __global__ __launch_bounds__(kBlock) void k_mg_smooth(MGLevel L, int color, double omega) {
-    smooth_body(L, color, omega, blockIdx.x * blockDim.x + threadIdx.x);
+    smooth_body(L, color, omega, xcd_linear());
 }
 
 void launch_mg_smooth(const MGLevel& L, int color, double omega, hipStream_t st) {
     const unsigned n = L.n / 2;
-    hipLaunchKernelGGL(k_mg_smooth, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, L, color, omega);
+    hipLaunchKernelGGL(k_mg_smooth, dim3(site_blocks(n)), dim3(kBlock), 0, st, L, color, omega);
 }
 
 // Residuals of the eight lattice cells under coarse cell t, summed.  The eight rows
@@ -792,11 +792,11 @@ __device__ __forceinline__ void restrict_body(const MGLevel& Fl, const MGLevel& 
 }
 
 __global__ __launch_bounds__(kBlock) void k_mg_restrict(MGLevel Fl, MGLevel C) {
-    restrict_body(Fl, C, blockIdx.x * blockDim.x + threadIdx.x);
+    restrict_body(Fl, C, xcd_linear());
 }
 
 void launch_mg_restrict(const MGLevel& f, const MGLevel& c, hipStream_t st) {
-    hipLaunchKernelGGL(k_mg_restrict, dim3((c.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, f, c);
+    hipLaunchKernelGGL(k_mg_restrict, dim3(site_blocks(c.n)), dim3(kBlock), 0, st, f, c);
 }
 
 // Trilinear interpolation of the coarse correction at the fine cell (x, y, z).
@@ -916,11 +916,11 @@ __device__ __forceinline__ void prolong_body(const MGLevel& C, const MGLevel& Fl
 }
 
 __global__ __launch_bounds__(kBlock) void k_mg_prolong(MGLevel C, MGLevel Fl) {
-    prolong_body(C, Fl, blockIdx.x * blockDim.x + threadIdx.x);
+    prolong_body(C, Fl, xcd_linear());
 }
 
 void launch_mg_prolong(const MGLevel& c, const MGLevel& f, hipStream_t st) {
-    hipLaunchKernelGGL(k_mg_prolong, dim3((f.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c, f);
+    hipLaunchKernelGGL(k_mg_prolong, dim3(site_blocks(f.n)), dim3(kBlock), 0, st, c, f);
 }
 
 // The last two levels in one workgroup: on the upper of them ("mid", at most kTailMid
