@@ -429,7 +429,7 @@ def main():
     if args.class_steps < 1:
         raise SystemExit("--class-steps must be at least 1")
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "decomposition is a design note, not an implemented path.", file=sys.stderr)
         sys.exit(2)
 
