@@ -245,8 +245,10 @@ __device__ __forceinline__ double moments_body(const Scalars& S, const Fields<T>
             }
 #pragma unroll
             for (int d = 0; d < kQ; ++d) {
-                const T a = PM == 0 ? F.f[0][(size_t)d * S.N + i] : arriving<T, PM>(S, F, 0, d, i, z, o, own0);
-                const T b = PM == 0 ? F.f[1][(size_t)d * S.N + i] : arriving<T, PM>(S, F, 1, d, i, z, o, own1);
+                const T a = PM == 0 ? __builtin_nontemporal_load(F.f[0] + (size_t)d * S.N + i)
+                                    : arriving<T, PM>(S, F, 0, d, i, z, o, own0);
+                const T b = PM == 0 ? __builtin_nontemporal_load(F.f[1] + (size_t)d * S.N + i)
+                                    : arriving<T, PM>(S, F, 1, d, i, z, o, own1);
                 sa += a;
                 sb += b;
                 const T s = a + b;
@@ -1609,7 +1611,7 @@ __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F,
                              T(vz(d)) * T(F.pv[3 * own + 2]);
                 }
                 const T corr = T(6) * w * rs * cv;
-                fo[(size_t)opposite(d) * N + i] = gs - corr;
+                __builtin_nontemporal_store(gs - corr, fo + (size_t)opposite(d) * N + i);
                 if (own >= 0) {
                     const double dp = 2.0 * ((double)gs + weight(d) * S.rref[c]) - (double)corr;
                     double* rec = F.linkdp + (size_t)lk * 6 + 3 * c;
@@ -1619,7 +1621,7 @@ __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F,
                     ++lk;
                 }
             } else {
-                fo[(size_t)d * N + j] = gs;
+                __builtin_nontemporal_store(gs, fo + (size_t)d * N + j);
             }
         }
     }
