@@ -186,8 +186,14 @@ struct MsSite {
 // c at 4 c: deviation, u_e x, y, z), one aligned 16-byte (FP32) or 32-byte (FP64) vector
 // per component.
 template <typename T> struct Vec4;
-template <> struct Vec4<float> { using type = float4; };
-template <> struct Vec4<double> { using type = double4; };
+template <> struct Vec4<float> {
+    using type = float4;
+    using native = float __attribute__((ext_vector_type(4)));
+};
+template <> struct Vec4<double> {
+    using type = double4;
+    using native = double __attribute__((ext_vector_type(4)));
+};
 
 template <typename T>
 __device__ __forceinline__ MsSite<T> ms_site(const Scalars& S, const Fields<T>& F, int c, unsigned j) {
@@ -1577,12 +1583,8 @@ __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F,
         const T tau = T(S.tau);
         const T ue0 = u0 + tau * P0 / rs, ue1 = u1 + tau * P1 / rs, ue2 = u2 + tau * P2 / rs;
         if (MS) {  // tau = 1 moment state: the density and u_e stand for the post-collision populations
-            typename Vec4<T>::type v;
-            v.x = dr;
-            v.y = ue0;
-            v.z = ue1;
-            v.w = ue2;
-            reinterpret_cast<typename Vec4<T>::type*>(F.msn)[(size_t)2 * i + c] = v;
+            const typename Vec4<T>::native v = {dr, ue0, ue1, ue2};
+            __builtin_nontemporal_store(v, reinterpret_cast<typename Vec4<T>::native*>(F.msn) + (size_t)2 * i + c);
             continue;
         }
         const T usq = usq_of<T>(ue0, ue1, ue2);
@@ -1595,7 +1597,7 @@ __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F,
             const T geq = geq_dev<T>(d, dr, rs, ue0, ue1, ue2, usq);
             T gs = geq;
             if (!tau1) {
-                const T g = fc[(size_t)d * N + i];
+                const T g = __builtin_nontemporal_load(fc + (size_t)d * N + i);
                 gs = g - (g - geq) * T(S.inv_tau);
             }
             const unsigned j = i + offset_of(o, d);
