@@ -214,6 +214,31 @@ def run_fft_compare(n, steps, warmup):
     return out
 
 
+def precision_error(workload, n, steps):
+    """The error the FP32/FP64 speedup is quoted at: the FP32 and FP64 paths from the same
+    inputs after `steps` steps, max relative difference of the fluid densities on fluid
+    sites and of the ion densities where present, and max |dphi| / max |phi|."""
+    import numpy as np
+    from paper_1712_08494_amd import ek
+    out = {}
+    sims = {}
+    for prec in ("fp32", "fp64"):
+        cfg, inp = build_workload(workload, prec, n)
+        sims[prec] = ek.EKSim(cfg, inp)
+        sims[prec].step(steps)
+    a, b = sims["fp32"], sims["fp64"]
+    for name in ("rho_a", "rho_b", "n_plus", "n_minus"):
+        x, y = a.field(name), b.field(name)
+        m = np.abs(y) > 0
+        out[name] = float(f"{np.max(np.abs(x - y)[m] / np.abs(y)[m]):.3e}")
+    px, py = a.field("phi"), b.field("phi")
+    out["phi"] = float(f"{np.abs(px - py).max() / np.abs(py).max():.3e}")
+    out["steps"] = steps
+    for sim in sims.values():
+        sim.close()
+    return out
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -485,12 +510,14 @@ def main():
     f_traffic, f_src = measured_traffic("fused", args.workload, args.n, args.precision)
 
     fp64 = None
+    fp32_error = None
     if not args.no_fp64 and args.precision == "fp32":
         cfg64, inp64 = build_workload(args.workload, "fp64", args.n)
         log("gpu fp64 run for the FP32/FP64 speedup")
         dt64, _, _, _, _ = run_gpu(cfg64, inp64, max(10, args.steps // 2), args.warmup, detail_steps=0, class_steps=0)
         fp64 = N * max(10, args.steps // 2) / dt64 / 1e6
         log(f"gpu fp64: {1e3 * dt64 / max(10, args.steps // 2):.3f} ms/step")
+        fp32_error = precision_error(args.workload, args.n, 50)
 
     moment = None
     if not args.no_moment_state and cfg.tau == 1.0 and not S_has_particles(inp):
@@ -552,6 +579,7 @@ def main():
         "lagged_fourier_poisson": fft,
         "fp64_mlups": round(fp64, 2) if fp64 else None,
         "fp32_fp64_speedup": round(mlups / fp64, 3) if fp64 else None,
+        "fp32_error_vs_fp64": fp32_error,
         "batched": batched,
         "adjoint": adjoint,
         "cpu_baseline": cpu,
