@@ -192,8 +192,9 @@ ek_status ek_step(struct ek_ctx* ctx, int32_t nsteps);
    (Sec. II D): sum over the six links of eps_face (phi_j - phi_i) = -(q_i + wall
    charge), eps_face the mean of the two sites, source projected to zero mean, gauge
    mean(phi) = 0, starting from the current potential with the context's solver
-   (multigrid V-cycles or red-black SOR).  iters, rel_res may be NULL.  Returns
-   EK_ENOCONV if the tolerance was not met (phi keeps the last iterate). */
+   (multigrid V-cycles or red-black SOR; a lattice with an odd periodic y or z axis has no
+   red-black colouring, and its SOR sweeps take three colours).  iters, rel_res may be
+   NULL.  Returns EK_ENOCONV if the tolerance was not met (phi keeps the last iterate). */
 ek_status ek_poisson(struct ek_ctx* ctx, double tol, int32_t maxit, int32_t* iters, double* rel_res);
 
 /* Shape of the multigrid V-cycle (contexts whose lattice the multigrid coarsens): red-black

@@ -103,6 +103,8 @@ struct ek_ctx {
     hipGraph_t vc_graph = nullptr;
     hipGraphExec_t vc_exec = nullptr;
     void* q_own = nullptr;
+    double* phis = nullptr;  // colour-split potential and charge of a multigrid solve
+    void* qs = nullptr;
     double* phi_own = nullptr;
     bool vc_off = false;
     void* tune_buf = nullptr;  // state copy of the autotuner (held only while it runs)
@@ -419,11 +421,11 @@ static ek_status build_geometry(ek_ctx* c, const ek_particle* parts, int np, Hos
 // ------------------------------------------------------------------------------------
 // Poisson solve with convergence control
 // ------------------------------------------------------------------------------------
+// F in site order (split false) and pack: the kernel also fills c->phis, c->qs.
 template <typename T>
-static ek_status check_residual(ek_ctx* c, double& rr, double& ss) {
-    Fields<T> F = fields<T>(c);
+static ek_status check_residual(ek_ctx* c, const Fields<T>& F, bool split, bool pack, double& rr, double& ss) {
     const unsigned nres = residual_blocks(c->N);
-    launch_residual<T>(c->S, F, nres, c->st);
+    launch_residual<T>(c->S, F, nres, split, pack ? c->phis : nullptr, pack ? (T*)c->qs : nullptr, c->st);
     launch_reduce(c->red, nres, 3, nullptr, c->scal + 1, c->st);
     EK_HIP(hipMemcpyAsync(c->hscal, c->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, c->st));
     EK_HIP(hipStreamSynchronize(c->st));
@@ -436,15 +438,18 @@ static ek_status check_residual(ek_ctx* c, double& rr, double& ss) {
 // One V-cycle on the lattice (grid 0) with the coarse grids c->mg[0..nl-1] (grid g >= 1 is
 // c->mg[g - 1]).  The last one or two grids are handled by the single-workgroup tail
 // kernel (the coarsest solve, and the sweeps of the grid above it when small enough).
+// split: F holds the colour-split lattice potential and charge.
 template <typename T>
-static void vcycle(ek_ctx* c, const Fields<T>& F) {
+static void vcycle(ek_ctx* c, const Fields<T>& F, bool split) {
     const int nl = (int)c->mg.size();
     const int tail_mid = (nl >= 2 && c->mg[nl - 2].n <= 4096 && c->mg[nl - 1].n <= 512) ? 1 : 0;
     const int last_gpu = nl - 1 - tail_mid;  // finest grid handled by the tail, minus one
-    auto smooth = [&](int g) {
-        for (int color = 0; color < 2; ++color) {
+    // multigrid grids have even axes: two colours; first = 1 skips the red pass (taken by the
+    // restriction into a launched coarse grid)
+    auto smooth = [&](int g, int first = 0) {
+        for (int color = first; color < 2; ++color) {
             if (g == 0)
-                launch_sor<T>(c->S, F, color, c->mg_omega, c->st);
+                launch_sor<T>(c->S, F, color, c->mg_omega, split, c->st);
             else
                 launch_mg_smooth(c->mg[g - 1], color, c->mg_omega, c->st);
         }
@@ -455,22 +460,25 @@ static void vcycle(ek_ctx* c, const Fields<T>& F) {
         Timer tm(c, EK_T_SMOOTH, 2 * sweeps);
         for (int s = 0; s < sweeps; ++s) smooth(0);
     };
+    // the restriction into a launched coarse grid takes that grid's first red pass
+    const double red = c->mg_pre >= 1 ? c->mg_omega : 0.0;
     for (int g = 0; g <= last_gpu; ++g) {  // downward leg: smooth grid g, restrict to grid g+1
         const int pre = g == 0 ? c->mg_fine_pre : c->mg_pre;
         if (g == 0)
             smooth_lattice(pre);
         else
-            for (int s = 0; s < pre; ++s) smooth(g);
+            for (int s = 0; s < pre; ++s) smooth(g, s == 0 && red > 0.0 ? 1 : 0);
+        const double r = g + 1 <= last_gpu ? red : 0.0;
         if (g == 0)
-            launch_mg_restrict_fine<T>(c->S, F, c->mg[0], c->st);
+            launch_mg_restrict_fine<T>(c->S, F, c->mg[0], split, r, c->st);
         else
-            launch_mg_restrict(c->mg[g - 1], c->mg[g], c->st);
+            launch_mg_restrict(c->mg[g - 1], c->mg[g], r, c->st);
     }
     launch_mg_tail(tail_mid ? c->mg[nl - 2] : c->mg[nl - 1], c->mg[nl - 1], tail_mid, c->mg_coarsest,
                    c->mg_coarse_omega, c->mg_tail_pre, c->mg_tail_post, c->mg_omega, c->st);
     for (int g = last_gpu; g >= 0; --g) {  // upward leg: interpolate from grid g+1, smooth grid g
         if (g == 0)
-            launch_mg_prolong_fine<T>(c->S, F, c->mg[0], c->st);
+            launch_mg_prolong_fine<T>(c->S, F, c->mg[0], split, c->st);
         else
             launch_mg_prolong(c->mg[g], c->mg[g - 1], c->st);
         const int post = g == 0 ? c->mg_fine_post : c->mg_post;
@@ -488,17 +496,20 @@ static void vcycle_graph_drop(ek_ctx* c) {
     c->vc_graph = nullptr;
 }
 
-// k V-cycles: graph replays when possible, direct launches otherwise.
+// k V-cycles: graph replays when possible, direct launches otherwise.  The graph is
+// captured (and replayed) only for the context's own potential and charge, which a
+// multigrid solve holds colour-split (split is then true).
 template <typename T>
-static ek_status run_cycles(ek_ctx* c, Fields<T>& F, int k) {
+static ek_status run_cycles(ek_ctx* c, Fields<T>& F, bool split, int k) {
     const bool own = c->phi == c->phi_own && c->q == c->q_own;
+    if (own != split) return fail(c, EK_ESTATE, "internal: V-cycle layout does not match the captured graph");
     if (c->timing < 2 && own && !c->vc_off && !c->vc_exec) {
         if (!c->cap_st) EK_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
         hipStream_t st = c->st;
         c->st = c->cap_st;
         bool ok = hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
-            vcycle<T>(c, F);
+            vcycle<T>(c, F, split);
             ok = hipStreamEndCapture(c->cap_st, &c->vc_graph) == hipSuccess;
         }
         c->st = st;
@@ -512,7 +523,7 @@ static ek_status run_cycles(ek_ctx* c, Fields<T>& F, int k) {
     if (c->vc_exec && c->timing < 2 && own) {
         for (int s = 0; s < k; ++s) EK_HIP(hipGraphLaunch(c->vc_exec, c->st));
     } else {
-        for (int s = 0; s < k; ++s) vcycle<T>(c, F);
+        for (int s = 0; s < k; ++s) vcycle<T>(c, F, split);
     }
     return EK_OK;
 }
@@ -529,14 +540,22 @@ template <typename T>
 static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out, double* rel_out) {
     Timer tm(c, EK_T_POISSON);
     Fields<T> F = fields<T>(c);
+    // a multigrid solve of the context's own potential runs on colour-split copies of the
+    // potential and charge; the gauge kernel writes the result back in site order
+    const bool split = c->phis && !c->mg.empty() && c->phi == c->phi_own && c->q == c->q_own;
+    Fields<T> FS = F;
+    if (split) {
+        FS.phi = c->phis;
+        FS.q = (T*)c->qs;
+    }
     double rr, ss;
-    EK_TRY(check_residual<T>(c, rr, ss));
+    EK_TRY(check_residual<T>(c, F, false, split, rr, ss));  // from site order, filling the split copies
     c->last_rel0 = ss > 0.0 ? std::sqrt(rr / ss) : 0.0;
     int it = 0;
     ek_status status = EK_OK;
     double rel = 0.0;
     if (!(ss > 0.0)) {
-        launch_phi_finalize<T>(c->S, F, 1, c->st);
+        launch_phi_finalize<T>(c->S, F, 1, nullptr, c->st);
     } else {
         const double target = tol * std::sqrt(ss);
         double r = std::sqrt(rr);
@@ -549,11 +568,11 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
             k = std::min(k, maxit - it);
             {
                 Timer ts(c, EK_T_ITER, k);
-                EK_TRY(run_cycles<T>(c, F, k));
+                EK_TRY(run_cycles<T>(c, FS, split, k));
             }
             EK_HIP(hipGetLastError());
             it += k;
-            EK_TRY(check_residual<T>(c, rr, ss));
+            EK_TRY(check_residual<T>(c, FS, split, false, rr, ss));
             const double rn = std::sqrt(rr);
             if (rn < r && rn > 0.0) {
                 const double est = std::pow(rn / r, 1.0 / k);
@@ -571,13 +590,14 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
             k = std::min(k, maxit - it);
             {
                 Timer ts(c, EK_T_ITER, k);
-                Timer tm(c, EK_T_SMOOTH, 2 * k);  // the k sweeps run back to back
+                Timer tm(c, EK_T_SMOOTH, c->S.ncolor * k);  // the k sweeps run back to back
                 for (int s = 0; s < k; ++s)
-                    for (int color = 0; color < 2; ++color) launch_sor<T>(c->S, F, color, c->omega, c->st);
+                    for (int color = 0; color < c->S.ncolor; ++color)
+                        launch_sor<T>(c->S, F, color, c->omega, false, c->st);
             }
             EK_HIP(hipGetLastError());
             it += k;
-            EK_TRY(check_residual<T>(c, rr, ss));
+            EK_TRY(check_residual<T>(c, FS, split, false, rr, ss));
             const double rn = std::sqrt(rr);
             if (rn < r && rn > 0.0) {
                 const double est = std::pow(rn / r, 1.0 / k);
@@ -585,7 +605,7 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
             }
             r = rn;
         }
-        launch_phi_finalize<T>(c->S, F, 0, c->st);
+        launch_phi_finalize<T>(c->S, F, 0, split ? c->phis : nullptr, c->st);
         rel = r / std::sqrt(ss);
         if (r > target) status = EK_ENOCONV;
     }
@@ -786,6 +806,10 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     EK_TRY(dalloc(c, (void**)&c->phi, (size_t)N * 8));
     EK_TRY(dalloc(c, (void**)&c->phi_prev, (size_t)N * 8));
     EK_TRY(dalloc(c, (void**)&c->phi_prev2, (size_t)N * 8));
+    if (!c->mg.empty()) {
+        EK_TRY(dalloc(c, (void**)&c->phis, (size_t)N * 8));
+        EK_TRY(dalloc(c, &c->qs, (size_t)N * es));
+    }
     c->phi_own = c->phi;
     c->q_own = c->q;
     EK_TRY(dalloc(c, (void**)&c->red, (size_t)c->nblk * kRedSlots * 8));
@@ -958,6 +982,8 @@ extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const doub
     S.z0 = S.walls ? 1 : 0;
     S.z1 = S.walls ? p->nz - 2 : p->nz - 1;
     S.ndomain = (unsigned)S.nxy * (unsigned)(S.z1 - S.z0 + 1);
+    // an odd periodic y or z axis (length >= 3) has no red-black colouring: three colours
+    S.ncolor = ((S.ny >= 3 && (S.ny & 1)) || (!S.walls && S.nz >= 3 && (S.nz & 1))) ? 3 : 2;
     S.inv_nx = 1.0 / S.nx;
     S.inv_ny = 1.0 / S.ny;
     S.inv_nxy = 1.0 / S.nxy;

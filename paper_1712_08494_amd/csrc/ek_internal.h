@@ -23,6 +23,7 @@ struct Scalars {
     int ion_sc;       // solvation Shan-Chen coupling active
     int z0, z1;       // Poisson domain in z (inclusive)
     unsigned ndomain; // sites in the Poisson domain
+    int ncolor;       // colours of a lattice Gauss-Seidel sweep: 2, or 3 with an odd periodic y or z axis
     double inv_nx, inv_ny, inv_nxy, inv_hx;  // 1/nx, 1/ny, 1/(nx ny), 1/(nx/2): exact index division
     double tau, inv_tau, G, rho0, D, beta;
     double kap_p, kap_m;   // s beta dmu+- / (2 drho_a)
@@ -146,9 +147,13 @@ template <typename T> void launch_batch_tail(const RepDesc<T>* D, int n_rep, hip
 template <typename T> void launch_mg_coarsen_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st);
 void launch_mg_coarsen(const MGLevel& f, const MGLevel& c, hipStream_t st);
 void launch_mg_smooth(const MGLevel& L, int color, double omega, hipStream_t st);
-template <typename T> void launch_mg_restrict_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st);
-void launch_mg_restrict(const MGLevel& f, const MGLevel& c, hipStream_t st);
-template <typename T> void launch_mg_prolong_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st);
+template <typename T>
+void launch_mg_restrict_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, bool split, double red_omega,
+                             hipStream_t st);
+// red_omega > 0: the restriction also takes the first red pass of the coarse pre-smoothing
+void launch_mg_restrict(const MGLevel& f, const MGLevel& c, double red_omega, hipStream_t st);
+template <typename T>
+void launch_mg_prolong_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, bool split, hipStream_t st);
 void launch_mg_prolong(const MGLevel& c, const MGLevel& f, hipStream_t st);
 void launch_mg_tail(const MGLevel& mid, const MGLevel& coarse, int has_mid, int iters, double omega, int mid_pre,
                     int mid_post, double mid_omega, hipStream_t st);
@@ -156,11 +161,18 @@ void launch_mg_tail(const MGLevel& mid, const MGLevel& coarse, int has_mid, int 
 template <typename T> void launch_moments(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
 template <typename T> void launch_virtual(const Scalars& S, const Fields<T>& F, hipStream_t st);
 void launch_source_mean(const Scalars& S, double* red, unsigned nblk, double* scal, hipStream_t st);
-template <typename T> void launch_sor(const Scalars& S, const Fields<T>& F, int color, double omega, hipStream_t st);
-template <typename T> void launch_residual(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
+// split: F.phi and F.q hold the colour-split potential and charge (multigrid contexts)
+template <typename T>
+void launch_sor(const Scalars& S, const Fields<T>& F, int color, double omega, bool split, hipStream_t st);
+// From site-order fields (split false) with phis, qs non-null: also writes their colour-split copies
+template <typename T>
+void launch_residual(const Scalars& S, const Fields<T>& F, unsigned nblk, bool split, double* phis, T* qs,
+                     hipStream_t st);
 void launch_reduce(const double* red, unsigned nblk, int nvals, const int* is_max, double* out, hipStream_t st);
 // gauge mean(phi) = 0 (phi = 0 when zero != 0) and the wall layers of the potential
-template <typename T> void launch_phi_finalize(const Scalars& S, const Fields<T>& F, int zero, hipStream_t st);
+// split_src: the colour-split solved potential, or null to gauge F.phi in place
+template <typename T>
+void launch_phi_finalize(const Scalars& S, const Fields<T>& F, int zero, const double* split_src, hipStream_t st);
 void launch_phi_extrapolate(const Scalars& S, double* phi, double* prev, double* prev2, int history,
                             hipStream_t st);
 template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hipStream_t st);

@@ -413,9 +413,21 @@ void launch_source_mean(const Scalars& S, double* red, unsigned nblk, double* sc
 // wall faces) carry no flux; links of an axis of length 1 join a site to itself and
 // contribute nothing, so they are skipped.
 // ------------------------------------------------------------------------------------
-template <typename T>
+//
+// Inside a multigrid solve the lattice potential and charge can be held colour-split (SP):
+// the sites of colour (x + y + z) % 2 = 1 follow those of colour 0, each colour in site
+// order, so a colour pass reads and writes whole cache lines of its own colour.  Axes are
+// even there, site i of colour c sits at c N/2 + i/2, and every neighbour has the other
+// colour.  The permittivity stays in site order.
+template <bool SP>
+__device__ __forceinline__ unsigned cidx(const Scalars& S, unsigned i, int color) {
+    return SP ? (color ? (S.N >> 1) : 0u) + (i >> 1) : i;
+}
+
+template <typename T, bool SP = false>
 __device__ __forceinline__ void poisson_row(unsigned i, int x, int y, int z, const Scalars& S, const Fields<T>& F,
                                             double& diag, double& offsum, double& src) {
+    const int own = SP ? ((x + y + z) & 1) : 0, nb = own ^ 1;
     const double ei = (double)F.eps[i];
     diag = 0.0;
     offsum = 0.0;
@@ -423,92 +435,143 @@ __device__ __forceinline__ void poisson_row(unsigned i, int x, int y, int z, con
         const unsigned a = i + (x == 0 ? S.nx - 1 : -1), b = i + (x == S.nx - 1 ? -(S.nx - 1) : 1);
         const double ea = 0.5 * (ei + (double)F.eps[a]), eb = 0.5 * (ei + (double)F.eps[b]);
         diag += ea + eb;
-        offsum += ea * F.phi[a] + eb * F.phi[b];
+        offsum += ea * F.phi[cidx<SP>(S, a, nb)] + eb * F.phi[cidx<SP>(S, b, nb)];
     }
     if (S.ny > 1) {
         const unsigned a = i + (y == 0 ? (S.ny - 1) * S.nx : -S.nx), b = i + (y == S.ny - 1 ? -(S.ny - 1) * S.nx : S.nx);
         const double ea = 0.5 * (ei + (double)F.eps[a]), eb = 0.5 * (ei + (double)F.eps[b]);
         diag += ea + eb;
-        offsum += ea * F.phi[a] + eb * F.phi[b];
+        offsum += ea * F.phi[cidx<SP>(S, a, nb)] + eb * F.phi[cidx<SP>(S, b, nb)];
     }
     if (S.nz > 1) {
         if (!(S.walls && z == S.z0)) {
             const unsigned a = i + (z == 0 ? (S.nz - 1) * S.nxy : -S.nxy);
             const double ea = 0.5 * (ei + (double)F.eps[a]);
             diag += ea;
-            offsum += ea * F.phi[a];
+            offsum += ea * F.phi[cidx<SP>(S, a, nb)];
         }
         if (!(S.walls && z == S.z1)) {
             const unsigned b = i + (z == S.nz - 1 ? -(S.nz - 1) * S.nxy : S.nxy);
             const double eb = 0.5 * (ei + (double)F.eps[b]);
             diag += eb;
-            offsum += eb * F.phi[b];
+            offsum += eb * F.phi[cidx<SP>(S, b, nb)];
         }
     }
-    double s = (double)F.q[i];
+    double s = (double)F.q[cidx<SP>(S, i, own)];
     if (S.walls && z == S.z0) s += S.sigma0;
     if (S.walls && z == S.z1) s += S.sigma1;
     src = s - F.scal[0];
 }
 
-// One colour of a red-black sweep; thread -> site of that colour ((x + y + z) % 2 == color).
-template <typename T>
-__device__ __forceinline__ void sor_body(const Scalars& S, const Fields<T>& F, unsigned t, int color, double omega) {
-    const unsigned half = (unsigned)(S.nx >> 1);
-    const unsigned rows = (unsigned)S.ny * (unsigned)(S.z1 - S.z0 + 1);
-    if (t >= half * rows) return;
-    const unsigned row = div_exact(t, S.inv_hx), m = t - row * half;
-    const unsigned zr = div_exact(row, S.inv_ny);
-    const int y = (int)(row - zr * (unsigned)S.ny), z = S.z0 + (int)zr;
-    const int x = 2 * m + ((color + y + z) & 1);
-    const unsigned i = x + S.nx * (y + S.ny * z);
+// Colour of a site when a periodic y or z axis has odd length L >= 3.  On such an axis the
+// link from L - 1 back to 0 joins two sites of equal parity, so (x + y + z) % 2 is no
+// colouring.  Per axis the colour is the parity, except 2 for the last index of an odd
+// periodic axis (a proper colouring of an odd cycle with three values); the sum of the
+// three axis colours mod 3 differs between any two neighbours, so the sites of one colour
+// are independent and each pass is well defined.
+__device__ __forceinline__ int color3(const Scalars& S, int x, int y, int z) {
+    const int cy = ((S.ny & 1) && S.ny >= 3 && y == S.ny - 1) ? 2 : (y & 1);
+    const int cz = ((S.nz & 1) && S.nz >= 3 && !S.walls && z == S.nz - 1) ? 2 : (z & 1);
+    return ((x & 1) + cy + cz) % 3;
+}
+
+// One colour of a Gauss-Seidel sweep.  Two colours (the usual red-black ordering): thread
+// -> site of that colour ((x + y + z) % 2 == color).  Three colours: thread -> domain site,
+// threads of other colours return.  sor_site computes the new value and where it goes.
+template <typename T, bool SP = false>
+__device__ __forceinline__ bool sor_site(const Scalars& S, const Fields<T>& F, unsigned t, int color, double omega,
+                                         unsigned& o, double& v) {
+    unsigned i;
+    int x, y, z;
+    if (S.ncolor == 3) {
+        if (t >= S.ndomain) return false;
+        i = t + (unsigned)S.z0 * (unsigned)S.nxy;
+        site_xyz(i, S, x, y, z);
+        if (color3(S, x, y, z) != color) return false;
+    } else {
+        const unsigned half = (unsigned)(S.nx >> 1);
+        const unsigned rows = (unsigned)S.ny * (unsigned)(S.z1 - S.z0 + 1);
+        if (t >= half * rows) return false;
+        const unsigned row = div_exact(t, S.inv_hx), m = t - row * half;
+        const unsigned zr = div_exact(row, S.inv_ny);
+        y = (int)(row - zr * (unsigned)S.ny);
+        z = S.z0 + (int)zr;
+        x = 2 * m + ((color + y + z) & 1);
+        i = x + S.nx * (y + S.ny * z);
+    }
     double diag, offsum, src;
-    poisson_row<T>(i, x, y, z, S, F, diag, offsum, src);
-    if (diag <= 0.0) return;
+    poisson_row<T, SP>(i, x, y, z, S, F, diag, offsum, src);
+    if (diag <= 0.0) return false;
     const double gs = (offsum + src) / diag;
-    F.phi[i] = F.phi[i] + omega * (gs - F.phi[i]);
+    o = cidx<SP>(S, i, color);
+    const double p = F.phi[o];
+    v = p + omega * (gs - p);
+    return true;
+}
+
+template <typename T, bool SP = false>
+__device__ __forceinline__ void sor_body(const Scalars& S, const Fields<T>& F, unsigned t, int color, double omega) {
+    unsigned o;
+    double v;
+    if (sor_site<T, SP>(S, F, t, color, omega, o, v)) F.phi[o] = v;
+}
+
+template <typename T, bool SP>
+__global__ __launch_bounds__(kBlock) void k_sor(Scalars S, Fields<T> F, int color, double omega) {
+    sor_body<T, SP>(S, F, xcd_linear(), color, omega);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sor(Scalars S, Fields<T> F, int color, double omega) {
-    sor_body<T>(S, F, xcd_linear(), color, omega);
-}
-
-template <typename T> void launch_sor(const Scalars& S, const Fields<T>& F, int color, double omega, hipStream_t st) {
-    const unsigned n = (unsigned)(S.nx / 2) * S.ny * (S.z1 - S.z0 + 1);
-    hipLaunchKernelGGL(k_sor<T>, dim3(site_blocks(n)), dim3(kBlock), 0, st, S, F, color, omega);
+void launch_sor(const Scalars& S, const Fields<T>& F, int color, double omega, bool split, hipStream_t st) {
+    const unsigned n = S.ncolor == 3 ? S.ndomain : (unsigned)(S.nx / 2) * S.ny * (S.z1 - S.z0 + 1);
+    if (split)
+        hipLaunchKernelGGL((k_sor<T, true>), dim3(site_blocks(n)), dim3(kBlock), 0, st, S, F, color, omega);
+    else
+        hipLaunchKernelGGL((k_sor<T, false>), dim3(site_blocks(n)), dim3(kBlock), 0, st, S, F, color, omega);
 }
 
 // Residual r = s + A phi: FP64 partial sums of r.r, s.s and phi over the domain.
-template <typename T>
+template <typename T, bool SP = false>
 __device__ __forceinline__ void residual_body(const Scalars& S, const Fields<T>& F, unsigned i, double (&v)[3]) {
     v[0] = v[1] = v[2] = 0.0;
     if (i < S.N) {
         int x, y, z;
-    site_xyz(i, S, x, y, z);
+        site_xyz(i, S, x, y, z);
         if (z >= S.z0 && z <= S.z1) {
             double diag, offsum, src;
-            poisson_row<T>(i, x, y, z, S, F, diag, offsum, src);
-            const double res = src + offsum - diag * F.phi[i];
+            poisson_row<T, SP>(i, x, y, z, S, F, diag, offsum, src);
+            const double p = F.phi[cidx<SP>(S, i, (x + y + z) & 1)];
+            const double res = src + offsum - diag * p;
             v[0] = res * res;
             v[1] = src * src;
-            v[2] = F.phi[i];
+            v[2] = p;
         }
     }
 }
 
 // Each thread takes kResSites sites, kBlock apart (a workgroup covers kResSites x kBlock
 // consecutive sites), and sums them in order before the block reduction: fewer records
-// for the reducer to read.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_residual(Scalars S, Fields<T> F) {
+// for the reducer to read.  From site-order fields (SP false) the kernel can also write
+// the colour-split copies of the potential and charge (phis, qs non-null) for the
+// multigrid solve that follows.
+template <typename T, bool SP>
+__global__ __launch_bounds__(kBlock) void k_residual(Scalars S, Fields<T> F, double* __restrict__ phis,
+                                                     T* __restrict__ qs) {
     const unsigned nb = gridDim.x, b = blockIdx.x;
     const unsigned lb = (b & 7u) * (nb >> 3) + (b >> 3);  // XCD-contiguous ranges, as xcd_linear
     double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < kResSites; ++j) {
+        const unsigned i = (lb * kResSites + j) * kBlock + threadIdx.x;
+        if (!SP && phis && i < S.N) {
+            int x, y, z;
+            site_xyz(i, S, x, y, z);
+            const unsigned o = cidx<true>(S, i, (x + y + z) & 1);
+            phis[o] = F.phi[i];
+            qs[o] = F.q[i];
+        }
         double v[3];
-        residual_body<T>(S, F, (lb * kResSites + j) * kBlock + threadIdx.x, v);
+        residual_body<T, SP>(S, F, i, v);
         acc[0] += v[0];
         acc[1] += v[1];
         acc[2] += v[2];
@@ -519,8 +582,14 @@ __global__ __launch_bounds__(kBlock) void k_residual(Scalars S, Fields<T> F) {
 
 unsigned residual_blocks(unsigned n) { return site_blocks((n + kResSites - 1) / kResSites); }
 
-template <typename T> void launch_residual(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st) {
-    hipLaunchKernelGGL(k_residual<T>, dim3(nblk), dim3(kBlock), 0, st, S, F);
+template <typename T>
+void launch_residual(const Scalars& S, const Fields<T>& F, unsigned nblk, bool split, double* phis, T* qs,
+                     hipStream_t st) {
+    if (split)
+        hipLaunchKernelGGL((k_residual<T, true>), dim3(nblk), dim3(kBlock), 0, st, S, F, (double*)nullptr,
+                           (T*)nullptr);
+    else
+        hipLaunchKernelGGL((k_residual<T, false>), dim3(nblk), dim3(kBlock), 0, st, S, F, phis, qs);
 }
 
 // Gauge mean(phi) = 0 over the domain (scal[3] = sum of phi), or phi = 0 when zero != 0.
@@ -532,21 +601,29 @@ __device__ __forceinline__ void finalize_body(const Scalars& S, double* phi, con
 }
 
 // The gauge, and with walls the wall layers from the gauged potential next to them (Gauss's
-// law at the charged wall face): phi_wall = phi_adjacent + sigma / eps_adjacent.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_phi_finalize(Scalars S, Fields<T> F, int zero) {
+// law at the charged wall face): phi_wall = phi_adjacent + sigma / eps_adjacent.  The
+// solved potential is read from src, colour-split when SP (it is F.phi otherwise).
+template <typename T, bool SP>
+__global__ __launch_bounds__(kBlock) void k_phi_finalize(Scalars S, Fields<T> F, int zero, const double* src) {
     const unsigned i = xcd_linear();
     if (i >= S.N) return;
-    const int z = site_z(i, S);
+    int x, y, z;
+    site_xyz(i, S, x, y, z);
     if (z < S.z0 || z > S.z1) return;
-    const double p = zero ? 0.0 : F.phi[i] - F.scal[3] / (double)S.ndomain;
+    const double p = zero ? 0.0 : src[cidx<SP>(S, i, (x + y + z) & 1)] - F.scal[3] / (double)S.ndomain;
     F.phi[i] = p;
     if (S.walls && z == S.z0) F.phi[i - S.nxy] = p + S.sigma0 / (double)F.eps[i];
     if (S.walls && z == S.z1) F.phi[i + S.nxy] = p + S.sigma1 / (double)F.eps[i];
 }
 
-template <typename T> void launch_phi_finalize(const Scalars& S, const Fields<T>& F, int zero, hipStream_t st) {
-    hipLaunchKernelGGL(k_phi_finalize<T>, dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F, zero);
+template <typename T>
+void launch_phi_finalize(const Scalars& S, const Fields<T>& F, int zero, const double* split_src, hipStream_t st) {
+    if (split_src)
+        hipLaunchKernelGGL((k_phi_finalize<T, true>), dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F, zero,
+                           split_src);
+    else
+        hipLaunchKernelGGL((k_phi_finalize<T, false>), dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F, zero,
+                           (const double*)F.phi);
 }
 
 // Warm start of the next solve by linear extrapolation in time,
@@ -697,11 +774,32 @@ void launch_mg_smooth(const MGLevel& L, int color, double omega, hipStream_t st)
     hipLaunchKernelGGL(k_mg_smooth, dim3(site_blocks(n)), dim3(kBlock), 0, st, L, color, omega);
 }
 
+// Start of a coarse grid's correction: zero, except that with red_omega > 0 the red cells
+// ((I + J + K) even) take the first red pass of the pre-smoothing here.  From a zero
+// correction every neighbour term of that pass vanishes and it reduces to
+// omega s / diag, written as the sweep writes it (same operand order), so the grid's
+// first separate pass can be skipped.
+__device__ __forceinline__ void coarse_start(const MGLevel& C, int I, int J, int K, unsigned t, double s,
+                                             double red_omega) {
+    double v = 0.0;
+    if (red_omega > 0.0 && ((I + J + K) & 1) == 0) {
+        const int xm = wrapc(I - 1, C.nx), ym = wrapc(J - 1, C.ny), zm = wrapc(K - 1, C.nz);
+        const double diag = C.ax[t] + C.ax[lid(C, xm, J, K)] + C.ay[t] + C.ay[lid(C, I, ym, K)] + C.az[t] +
+                            C.az[lid(C, I, J, zm)];
+        if (diag > 0.0) {
+            const double p = 0.0, off = 0.0;
+            v = p + red_omega * ((off + s) / diag - p);
+        }
+    }
+    C.phi[t] = v;
+}
+
 // Residuals of the eight lattice cells under coarse cell t, summed.  The eight rows
 // share their stencil points: the 2x2x2 block and the four neighbours across each of its
 // six faces (32 sites), loaded once each.  Rows as in poisson_row, same operand order.
-template <typename T>
-__device__ __forceinline__ void restrict_fine_body(const Scalars& S, const Fields<T>& F, const MGLevel& C, unsigned t) {
+template <typename T, bool SP = false>
+__device__ __forceinline__ void restrict_fine_body(const Scalars& S, const Fields<T>& F, const MGLevel& C, unsigned t,
+                                                   double red_omega = 0.0) {
     if (t >= C.n) return;
     int I, J, K;
     level_xyz(t, C, I, J, K);
@@ -715,6 +813,7 @@ __device__ __forceinline__ void restrict_fine_body(const Scalars& S, const Field
     auto at = [&](int a, int b, int c) {
         return (unsigned)xs[a] + (unsigned)S.nx * ((unsigned)ys[b] + (unsigned)S.ny * (unsigned)zs[c]);
     };
+    auto col = [&](int a, int b, int c) { return (xs[a] + ys[b] + zs[c]) & 1; };
     double P[4][4][4];
     T E[4][4][4];  // permittivity in its storage precision (exactly widened where used)
 #pragma unroll
@@ -726,7 +825,7 @@ __device__ __forceinline__ void restrict_fine_body(const Scalars& S, const Field
                 const int outer = (a == 0 || a == 3) + (b == 0 || b == 3) + (c == 0 || c == 3);
                 if (outer <= 1) {
                     const unsigned g = at(a, b, c);
-                    P[c][b][a] = F.phi[g];
+                    P[c][b][a] = F.phi[cidx<SP>(S, g, col(a, b, c))];
                     E[c][b][a] = F.eps[g];
                 }
             }
@@ -762,26 +861,33 @@ __device__ __forceinline__ void restrict_fine_body(const Scalars& S, const Field
                     diag += eb;
                     off += eb * P[c + 1][b][a];
                 }
-                double src = (double)F.q[at(a, b, c)];
+                double src = (double)F.q[cidx<SP>(S, at(a, b, c), col(a, b, c))];
                 if (S.walls && z == S.z0) src += S.sigma0;
                 if (S.walls && z == S.z1) src += S.sigma1;
                 src -= mean;
                 sum += src + off - diag * P[c][b][a];
             }
     C.s[t] = sum;
-    C.phi[t] = 0.0;
+    coarse_start(C, I, J, K, t, sum, red_omega);
+}
+
+template <typename T, bool SP>
+__global__ __launch_bounds__(kBlock) void k_mg_restrict_fine(Scalars S, Fields<T> F, MGLevel C, double red_omega) {
+    restrict_fine_body<T, SP>(S, F, C, xcd_linear(), red_omega);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mg_restrict_fine(Scalars S, Fields<T> F, MGLevel C) {
-    restrict_fine_body<T>(S, F, C, xcd_linear());
+void launch_mg_restrict_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, bool split, double red_omega,
+                             hipStream_t st) {
+    if (split)
+        hipLaunchKernelGGL((k_mg_restrict_fine<T, true>), dim3(site_blocks(c.n)), dim3(kBlock), 0, st, S, F, c,
+                           red_omega);
+    else
+        hipLaunchKernelGGL((k_mg_restrict_fine<T, false>), dim3(site_blocks(c.n)), dim3(kBlock), 0, st, S, F, c,
+                           red_omega);
 }
 
-template <typename T> void launch_mg_restrict_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st) {
-    hipLaunchKernelGGL(k_mg_restrict_fine<T>, dim3(site_blocks(c.n)), dim3(kBlock), 0, st, S, F, c);
-}
-
-__device__ __forceinline__ void restrict_body(const MGLevel& Fl, const MGLevel& C, unsigned t) {
+__device__ __forceinline__ void restrict_body(const MGLevel& Fl, const MGLevel& C, unsigned t, double red_omega = 0.0) {
     if (t >= C.n) return;
     int I, J, K;
     level_xyz(t, C, I, J, K);
@@ -796,15 +902,15 @@ __device__ __forceinline__ void restrict_body(const MGLevel& Fl, const MGLevel& 
                 sum += Fl.s[i] + off - diag * Fl.phi[i];
             }
     C.s[t] = sum;
-    C.phi[t] = 0.0;
+    coarse_start(C, I, J, K, t, sum, red_omega);
 }
 
-__global__ __launch_bounds__(kBlock) void k_mg_restrict(MGLevel Fl, MGLevel C) {
-    restrict_body(Fl, C, xcd_linear());
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(MGLevel Fl, MGLevel C, double red_omega) {
+    restrict_body(Fl, C, xcd_linear(), red_omega);
 }
 
-void launch_mg_restrict(const MGLevel& f, const MGLevel& c, hipStream_t st) {
-    hipLaunchKernelGGL(k_mg_restrict, dim3(site_blocks(c.n)), dim3(kBlock), 0, st, f, c);
+void launch_mg_restrict(const MGLevel& f, const MGLevel& c, double red_omega, hipStream_t st) {
+    hipLaunchKernelGGL(k_mg_restrict, dim3(site_blocks(c.n)), dim3(kBlock), 0, st, f, c, red_omega);
 }
 
 // Trilinear interpolation of the coarse correction at the fine cell (x, y, z).
@@ -858,8 +964,9 @@ __device__ __forceinline__ void prolong_fine_body(const Scalars& S, const Fields
 // The same, one thread per coarse cell for its eight lattice children: the 3x3x3 coarse
 // neighbourhood is loaded once into registers and each child is interpolated with exactly
 // the expression and order of prolong_fine_body (bit-identical); the two x-children of a
-// row are read and written as one 16-byte pair.
-template <typename T>
+// row are read and written as one 16-byte pair (colour-split, SP: one value in each
+// colour half).
+template <typename T, bool SP>
 __global__ __launch_bounds__(kBlock) void k_mg_prolong_fine(Scalars S, Fields<T> F, MGLevel C) {
     const unsigned t = xcd_linear();
     if (t >= C.n) return;
@@ -888,8 +995,19 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong_fine(Scalars S, Fields<T>
             const int dy = cy ? 1 : -1;
             const double wys[2] = {0.75, 0.25};
             const int yo[2] = {1, 1 + dy};
-            double2* row = reinterpret_cast<double2*>(F.phi + ((size_t)z * S.ny + y) * S.nx + 2 * I);
-            double2 f = *row;
+            const unsigned i0 = (unsigned)(2 * I) + (unsigned)S.nx * ((unsigned)y + (unsigned)S.ny * (unsigned)z);
+            double2 f;
+            double2* row = nullptr;
+            unsigned o0 = 0, o1 = 0;
+            if (SP) {
+                o0 = cidx<SP>(S, i0, (y + z) & 1);
+                o1 = cidx<SP>(S, i0 + 1, (y + z + 1) & 1);
+                f.x = F.phi[o0];
+                f.y = F.phi[o1];
+            } else {
+                row = reinterpret_cast<double2*>(F.phi + i0);
+                f = *row;
+            }
             double vv[2];
 #pragma unroll
             for (int cx = 0; cx < 2; ++cx) {
@@ -907,14 +1025,24 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong_fine(Scalars S, Fields<T>
             }
             f.x += vv[0];
             f.y += vv[1];
-            *row = f;
+            if (SP) {
+                F.phi[o0] = f.x;
+                F.phi[o1] = f.y;
+            } else {
+                *row = f;
+            }
         }
     }
 }
 
-template <typename T> void launch_mg_prolong_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, hipStream_t st) {
-    hipLaunchKernelGGL(k_mg_prolong_fine<T>, dim3(site_blocks(c.n)), dim3(kBlock), 0, st, S, F, c);
+template <typename T>
+void launch_mg_prolong_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, bool split, hipStream_t st) {
+    if (split)
+        hipLaunchKernelGGL((k_mg_prolong_fine<T, true>), dim3(site_blocks(c.n)), dim3(kBlock), 0, st, S, F, c);
+    else
+        hipLaunchKernelGGL((k_mg_prolong_fine<T, false>), dim3(site_blocks(c.n)), dim3(kBlock), 0, st, S, F, c);
 }
+
 
 __device__ __forceinline__ void prolong_body(const MGLevel& C, const MGLevel& Fl, unsigned i) {
     if (i >= Fl.n) return;
@@ -1931,9 +2059,9 @@ template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, 
 #define EK_INST(T)                                                                                              \
     template void launch_moments<T>(const Scalars&, const Fields<T>&, unsigned, hipStream_t);                  \
     template void launch_virtual<T>(const Scalars&, const Fields<T>&, hipStream_t);                            \
-    template void launch_sor<T>(const Scalars&, const Fields<T>&, int, double, hipStream_t);                   \
-    template void launch_residual<T>(const Scalars&, const Fields<T>&, unsigned, hipStream_t);                 \
-    template void launch_phi_finalize<T>(const Scalars&, const Fields<T>&, int, hipStream_t);                  \
+    template void launch_sor<T>(const Scalars&, const Fields<T>&, int, double, bool, hipStream_t);             \
+    template void launch_residual<T>(const Scalars&, const Fields<T>&, unsigned, bool, double*, T*, hipStream_t); \
+    template void launch_phi_finalize<T>(const Scalars&, const Fields<T>&, int, const double*, hipStream_t);   \
     template void launch_force<T>(const Scalars&, const Fields<T>&, hipStream_t);                              \
     template void launch_fused<T>(const Scalars&, const Fields<T>&, hipStream_t);                              \
     template void launch_export_pop<T>(const Scalars&, const Fields<T>&, int, double*, hipStream_t);           \
@@ -1947,8 +2075,9 @@ template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, 
     template void launch_field_e<T>(const Scalars&, const Fields<T>&, int, double*, hipStream_t);              \
     template void launch_upload<T>(T*, const double*, unsigned, hipStream_t);                               \
     template void launch_mg_coarsen_fine<T>(const Scalars&, const Fields<T>&, const MGLevel&, hipStream_t);    \
-    template void launch_mg_restrict_fine<T>(const Scalars&, const Fields<T>&, const MGLevel&, hipStream_t);   \
-    template void launch_mg_prolong_fine<T>(const Scalars&, const Fields<T>&, const MGLevel&, hipStream_t);
+    template void launch_mg_restrict_fine<T>(const Scalars&, const Fields<T>&, const MGLevel&, bool, double,      \
+                                             hipStream_t);                                                       \
+    template void launch_mg_prolong_fine<T>(const Scalars&, const Fields<T>&, const MGLevel&, bool, hipStream_t);
 
 EK_INST(float)
 EK_INST(double)

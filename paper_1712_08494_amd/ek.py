@@ -194,7 +194,7 @@ def params_from_config(cfg):
         p.body_accel[k] = cfg.body_accel[k]
     p.sigma_wall[0], p.sigma_wall[1] = cfg.sigma_wall
     p.poisson_tol = cfg.poisson_tol
-    p.sor_omega = 0.0
+    p.sor_omega = float(getattr(cfg, "sor_omega", 0.0))
     p.particle_rho, p.k_hertz, p.eta = cfg.particle_rho, cfg.k_hertz, cfg.eta
     p.phi_history = int(getattr(cfg, "phi_history", 0))
     p.moment_state = int(bool(getattr(cfg, "moment_state", False)))

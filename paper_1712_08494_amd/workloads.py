@@ -45,6 +45,7 @@ class EKConfig:
     sigma_wall: Tuple[float, float] = (0.0, 0.0)
     poisson_tol: float = 1e-10       # relative residual of the GPU solve
     poisson_maxit: int = 20000
+    sor_omega: float = 0.0           # SOR relaxation of the "sor" solver; 0: from the lattice size
     poisson_solver: str = "auto"     # "auto" (multigrid where possible), "sor", "mg", or "fft" (the
                                      # lagged Fourier scheme, one solve per step, periodic lattices)
     poisson_tol_oracle: float = 1e-12

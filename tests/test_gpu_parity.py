@@ -56,6 +56,60 @@ def test_ragged_tile_periodic():
     compare(sim, o, "fp64", "ragged")
 
 
+def _sweep_colours(shape):
+    """The lattice Gauss-Seidel colouring: red-black, or three colours when a periodic y or z
+    axis has odd length >= 3 (the axis colour is the parity except 2 on its last index)."""
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    if not ((ny >= 3 and ny % 2) or (nz >= 3 and nz % 2)):
+        return (x + y + z) % 2, 2
+    cy = np.where((ny >= 3) & (ny % 2 == 1) & (y == ny - 1), 2, y % 2)
+    cz = np.where((nz >= 3) & (nz % 2 == 1) & (z == nz - 1), 2, z % 2)
+    return (x % 2 + cy + cz) % 3, 3
+
+
+@pytest.mark.parametrize("shape", [(10, 7, 5), (8, 9, 6), (6, 4, 7), (8, 6, 4)])
+def test_sor_sweep_is_a_proper_colour_ordered_sweep(shape):
+    """One SOR sweep of the library equals a colour-by-colour sweep computed here (periodic,
+    FP64), and the colouring leaves no two neighbours in one pass: with an odd periodic axis
+    two colours cannot, so the library sweeps three."""
+    nx, ny, nz = shape
+    cfg, inp = wl.mixture_noise(shape=shape, precision="fp64", G=4.4)
+    cfg.poisson_solver = "sor"
+    cfg.sor_omega = 1.25
+    cfg.poisson_tol = 1e-2  # leave the starting potential far from converged
+    _announce(f"one SOR sweep {nx}x{ny}x{nz} fp64")
+    sim = ek.EKSim(cfg, inp)
+    phi0, q, eps = sim.field("phi"), sim.field("q"), sim.field("eps")
+    col, ncol = _sweep_colours(phi0.shape)
+    for ax in range(3):
+        if phi0.shape[ax] > 1:
+            assert not np.any(col == np.roll(col, 1, axis=ax)), "neighbours share a colour"
+    st, iters, _ = sim.poisson(1e-15, 1)
+    assert iters == 1
+    phi1 = sim.field("phi")
+    ref, src = phi0.copy(), q - q.mean()
+    for c in range(ncol):
+        diag, off = np.zeros_like(ref), np.zeros_like(ref)
+        for ax in range(3):
+            if ref.shape[ax] == 1:
+                continue
+            for sh in (1, -1):
+                ef = 0.5 * (eps + np.roll(eps, sh, axis=ax))
+                diag += ef
+                off += ef * np.roll(ref, sh, axis=ax)
+        m = col == c
+        ref[m] += cfg.sor_omega * ((off + src)[m] / diag[m] - ref[m])
+    ref -= ref.mean()
+    scale = np.abs(phi1).max()
+    change = np.abs(phi1 - phi0).max() / scale
+    err = np.abs(phi1 - ref).max() / scale
+    _announce(f"  {ncol} colours: sweep changed phi by {change:.2e}, differs from the ordered sweep by {err:.2e}")
+    assert change > 1e-6
+    assert err < 1e-12
+    sim.close()
+
+
 # --------------------------------------------------------------------------------
 # Charged walls and an interface with solvation and permittivity contrast.
 # --------------------------------------------------------------------------------
