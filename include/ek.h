@@ -194,7 +194,10 @@ ek_status ek_step(struct ek_ctx* ctx, int32_t nsteps);
    mean(phi) = 0, starting from the current potential with the context's solver
    (multigrid V-cycles or red-black SOR; a lattice with an odd periodic y or z axis has no
    red-black colouring, and its SOR sweeps take three colours).  iters, rel_res may be
-   NULL.  Returns EK_ENOCONV if the tolerance was not met (phi keeps the last iterate). */
+   NULL.  Returns EK_ENOCONV if the tolerance was not met (phi keeps the last iterate).
+   Multigrid solves of a context's own potential work on colour-split copies of the
+   potential and charge; with EK_POISSON_SITE_ORDER=1 in the environment at ek_init the
+   context keeps them in site order instead (a diagnostic: the results are bit-identical). */
 ek_status ek_poisson(struct ek_ctx* ctx, double tol, int32_t maxit, int32_t* iters, double* rel_res);
 
 /* Shape of the multigrid V-cycle (contexts whose lattice the multigrid coarsens): red-black

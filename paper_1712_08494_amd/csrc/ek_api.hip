@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -107,6 +108,7 @@ struct ek_ctx {
     void* qs = nullptr;
     double* phi_own = nullptr;
     bool vc_off = false;
+    bool vc_split = false;  // layout the captured V-cycle graph works on
     void* tune_buf = nullptr;  // state copy of the autotuner (held only while it runs)
     // tau = 1 moment state instead of populations (ek_params.moment_state): two buffers of
     // 8 N values (step parity as the populations), the FP64 initial densities the first
@@ -497,12 +499,12 @@ static void vcycle_graph_drop(ek_ctx* c) {
 }
 
 // k V-cycles: graph replays when possible, direct launches otherwise.  The graph is
-// captured (and replayed) only for the context's own potential and charge, which a
-// multigrid solve holds colour-split (split is then true).
+// captured (and replayed) only for the context's own potential and charge, in the layout
+// (colour-split or site order) it was captured with.
 template <typename T>
 static ek_status run_cycles(ek_ctx* c, Fields<T>& F, bool split, int k) {
     const bool own = c->phi == c->phi_own && c->q == c->q_own;
-    if (own != split) return fail(c, EK_ESTATE, "internal: V-cycle layout does not match the captured graph");
+    if (c->vc_exec && c->vc_split != split) vcycle_graph_drop(c);
     if (c->timing < 2 && own && !c->vc_off && !c->vc_exec) {
         if (!c->cap_st) EK_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
         hipStream_t st = c->st;
@@ -510,6 +512,7 @@ static ek_status run_cycles(ek_ctx* c, Fields<T>& F, bool split, int k) {
         bool ok = hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
             vcycle<T>(c, F, split);
+            c->vc_split = split;
             ok = hipStreamEndCapture(c->cap_st, &c->vc_graph) == hipSuccess;
         }
         c->st = st;
@@ -806,7 +809,10 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     EK_TRY(dalloc(c, (void**)&c->phi, (size_t)N * 8));
     EK_TRY(dalloc(c, (void**)&c->phi_prev, (size_t)N * 8));
     EK_TRY(dalloc(c, (void**)&c->phi_prev2, (size_t)N * 8));
-    if (!c->mg.empty()) {
+    // EK_POISSON_SITE_ORDER=1 keeps the multigrid solves in site order (a diagnostic switch:
+    // the results are the same, bit for bit)
+    const char* site_order = std::getenv("EK_POISSON_SITE_ORDER");
+    if (!c->mg.empty() && !(site_order && std::atoi(site_order) != 0)) {
         EK_TRY(dalloc(c, (void**)&c->phis, (size_t)N * 8));
         EK_TRY(dalloc(c, &c->qs, (size_t)N * es));
     }

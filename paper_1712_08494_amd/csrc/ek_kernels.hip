@@ -149,9 +149,11 @@ void launch_reduce(const double* red, unsigned nblk, int nvals, const int* is_ma
 // ------------------------------------------------------------------------------------
 constexpr int kMomSlots = 8;
 
-// Occupancy requested for the force and fused kernels (waves per SIMD): four keeps FP32
-// at 128 VGPRs with at most a handful of spills; FP64 needs the registers of two.
+// Occupancy requested for the fused kernel (waves per SIMD): four keeps FP32 at 128 VGPRs
+// without spills; FP64 needs the registers of two.  The force kernel spills at four in
+// FP32 and runs faster at three (170 VGPRs).
 template <typename T> constexpr int kHotOcc = sizeof(T) == 4 ? 4 : 2;
+template <typename T> constexpr int kForceOcc = sizeof(T) == 4 ? 3 : 2;
 
 // Equilibrium of direction d (Sec. II A) in deviation form, f~_d - w_d rho_ref, for the
 // deviation dr = rho - rho_ref, density rs, velocity u and usq = u.u.  The collision
@@ -1653,7 +1655,7 @@ __device__ __forceinline__ void force_body(const Scalars& S, const Fields<T>& F,
 }
 
 template <typename T, int G>
-__global__ __launch_bounds__(kBlock, kHotOcc<T>) void k_force(Scalars S, Fields<T> F) {
+__global__ __launch_bounds__(kBlock, kForceOcc<T>) void k_force(Scalars S, Fields<T> F) {
     force_body<T, G>(S, F, xcd_linear());
 }
 
@@ -2110,7 +2112,7 @@ __global__ __launch_bounds__(kBlock) void kb_residual(const RepDesc<T>* __restri
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock, kHotOcc<T>) void kb_force(const RepDesc<T>* __restrict__ D,
+__global__ __launch_bounds__(kBlock, kForceOcc<T>) void kb_force(const RepDesc<T>* __restrict__ D,
                                                                const BlockRef* __restrict__ tab) {
     const BlockRef e = tab[blockIdx.x];
     const RepDesc<T>& R = D[e.rep];
