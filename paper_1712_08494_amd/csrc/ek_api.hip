@@ -106,6 +106,7 @@ struct ek_ctx {
     void* q_own = nullptr;
     double* phis = nullptr;  // colour-split potential and charge of a multigrid solve
     void* qs = nullptr;
+    double* blk = nullptr;   // black values between the fused interpolation + red pass and the black pass
     double* phi_own = nullptr;
     bool vc_off = false;
     bool vc_split = false;  // layout the captured V-cycle graph works on
@@ -479,11 +480,20 @@ static void vcycle(ek_ctx* c, const Fields<T>& F, bool split) {
     launch_mg_tail(tail_mid ? c->mg[nl - 2] : c->mg[nl - 1], c->mg[nl - 1], tail_mid, c->mg_coarsest,
                    c->mg_coarse_omega, c->mg_tail_pre, c->mg_tail_post, c->mg_omega, c->st);
     for (int g = last_gpu; g >= 0; --g) {  // upward leg: interpolate from grid g+1, smooth grid g
+        const int post = g == 0 ? c->mg_fine_post : c->mg_post;
+        if (g == 0 && split && post >= 1) {
+            // colour-split lattice: the interpolation takes the first red pass, and the black
+            // pass reads the interpolated black values from c->blk
+            launch_mg_prolong_red_fine<T>(c->S, F, c->mg[0], c->mg_omega, c->blk, c->st);
+            Timer tm(c, EK_T_SMOOTH, 2 * post - 1);
+            launch_sor_black_from<T>(c->S, F, c->mg_omega, c->blk, c->st);
+            for (int s = 1; s < post; ++s) smooth(0);
+            continue;
+        }
         if (g == 0)
             launch_mg_prolong_fine<T>(c->S, F, c->mg[0], split, c->st);
         else
             launch_mg_prolong(c->mg[g], c->mg[g - 1], c->st);
-        const int post = g == 0 ? c->mg_fine_post : c->mg_post;
         if (g == 0)
             smooth_lattice(post);
         else
@@ -815,6 +825,7 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     if (!c->mg.empty() && !(site_order && std::atoi(site_order) != 0)) {
         EK_TRY(dalloc(c, (void**)&c->phis, (size_t)N * 8));
         EK_TRY(dalloc(c, &c->qs, (size_t)N * es));
+        EK_TRY(dalloc(c, (void**)&c->blk, (size_t)(N / 2) * 8));
     }
     c->phi_own = c->phi;
     c->q_own = c->q;

@@ -154,6 +154,14 @@ void launch_mg_restrict_fine(const Scalars& S, const Fields<T>& F, const MGLevel
 void launch_mg_restrict(const MGLevel& f, const MGLevel& c, double red_omega, hipStream_t st);
 template <typename T>
 void launch_mg_prolong_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, bool split, hipStream_t st);
+// Colour-split fields: interpolation onto the lattice with the first red pass of the
+// post-smoothing; the interpolated black values go to blk (N/2 doubles), which the black
+// pass launch_sor_black_from reads as the black sites' current values.
+template <typename T>
+void launch_mg_prolong_red_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, double omega, double* blk,
+                                hipStream_t st);
+template <typename T>
+void launch_sor_black_from(const Scalars& S, const Fields<T>& F, double omega, const double* blk, hipStream_t st);
 void launch_mg_prolong(const MGLevel& c, const MGLevel& f, hipStream_t st);
 void launch_mg_tail(const MGLevel& mid, const MGLevel& coarse, int has_mid, int iters, double omega, int mid_pre,
                     int mid_post, double mid_omega, hipStream_t st);

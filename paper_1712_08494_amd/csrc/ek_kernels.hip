@@ -426,9 +426,14 @@ __device__ __forceinline__ unsigned cidx(const Scalars& S, unsigned i, int color
     return SP ? (color ? (S.N >> 1) : 0u) + (i >> 1) : i;
 }
 
-template <typename T, bool SP = false>
-__device__ __forceinline__ void poisson_row(unsigned i, int x, int y, int z, const Scalars& S, const Fields<T>& F,
-                                            double& diag, double& offsum, double& src) {
+// The row with the neighbour potentials supplied by pv(j, colour, ox, oy, oz) for the
+// neighbour j at offset (ox, oy, oz); poisson_row reads them from F.phi.  Evaluated
+// without multiply-add contraction, so that callers supplying the neighbour values
+// differently (loaded, or interpolated on the fly) round the row identically.
+template <typename T, bool SP, typename PV>
+__device__ __forceinline__ void poisson_row_v(unsigned i, int x, int y, int z, const Scalars& S, const Fields<T>& F,
+                                              PV&& pv, double& diag, double& offsum, double& src) {
+#pragma clang fp contract(off)
     const int own = SP ? ((x + y + z) & 1) : 0, nb = own ^ 1;
     const double ei = (double)F.eps[i];
     diag = 0.0;
@@ -437,32 +442,47 @@ __device__ __forceinline__ void poisson_row(unsigned i, int x, int y, int z, con
         const unsigned a = i + (x == 0 ? S.nx - 1 : -1), b = i + (x == S.nx - 1 ? -(S.nx - 1) : 1);
         const double ea = 0.5 * (ei + (double)F.eps[a]), eb = 0.5 * (ei + (double)F.eps[b]);
         diag += ea + eb;
-        offsum += ea * F.phi[cidx<SP>(S, a, nb)] + eb * F.phi[cidx<SP>(S, b, nb)];
+        offsum += ea * pv(a, nb, -1, 0, 0) + eb * pv(b, nb, 1, 0, 0);
     }
     if (S.ny > 1) {
         const unsigned a = i + (y == 0 ? (S.ny - 1) * S.nx : -S.nx), b = i + (y == S.ny - 1 ? -(S.ny - 1) * S.nx : S.nx);
         const double ea = 0.5 * (ei + (double)F.eps[a]), eb = 0.5 * (ei + (double)F.eps[b]);
         diag += ea + eb;
-        offsum += ea * F.phi[cidx<SP>(S, a, nb)] + eb * F.phi[cidx<SP>(S, b, nb)];
+        offsum += ea * pv(a, nb, 0, -1, 0) + eb * pv(b, nb, 0, 1, 0);
     }
     if (S.nz > 1) {
         if (!(S.walls && z == S.z0)) {
             const unsigned a = i + (z == 0 ? (S.nz - 1) * S.nxy : -S.nxy);
             const double ea = 0.5 * (ei + (double)F.eps[a]);
             diag += ea;
-            offsum += ea * F.phi[cidx<SP>(S, a, nb)];
+            offsum += ea * pv(a, nb, 0, 0, -1);
         }
         if (!(S.walls && z == S.z1)) {
             const unsigned b = i + (z == S.nz - 1 ? -(S.nz - 1) * S.nxy : S.nxy);
             const double eb = 0.5 * (ei + (double)F.eps[b]);
             diag += eb;
-            offsum += eb * F.phi[cidx<SP>(S, b, nb)];
+            offsum += eb * pv(b, nb, 0, 0, 1);
         }
     }
     double s = (double)F.q[cidx<SP>(S, i, own)];
     if (S.walls && z == S.z0) s += S.sigma0;
     if (S.walls && z == S.z1) s += S.sigma1;
     src = s - F.scal[0];
+}
+
+template <typename T, bool SP = false>
+__device__ __forceinline__ void poisson_row(unsigned i, int x, int y, int z, const Scalars& S, const Fields<T>& F,
+                                            double& diag, double& offsum, double& src) {
+    poisson_row_v<T, SP>(
+        i, x, y, z, S, F, [&](unsigned j, int c, int, int, int) { return F.phi[cidx<SP>(S, j, c)]; }, diag, offsum,
+        src);
+}
+
+// Over-relaxed Gauss-Seidel update, without multiply-add contraction so that every kernel
+// that applies it (separate or fused with the interpolation) rounds it the same way.
+__device__ __forceinline__ double sor_update(double p, double gs, double omega) {
+#pragma clang fp contract(off)
+    return p + omega * (gs - p);
 }
 
 // Colour of a site when a periodic y or z axis has odd length L >= 3.  On such an axis the
@@ -479,10 +499,12 @@ __device__ __forceinline__ int color3(const Scalars& S, int x, int y, int z) {
 
 // One colour of a Gauss-Seidel sweep.  Two colours (the usual red-black ordering): thread
 // -> site of that colour ((x + y + z) % 2 == color).  Three colours: thread -> domain site,
-// threads of other colours return.  sor_site computes the new value and where it goes.
-template <typename T, bool SP = false>
+// threads of other colours return.  sor_site computes the new value and where it goes;
+// with OWN the site's current value is read from own[i / 2] (the black values left by the
+// fused interpolation and red pass) instead of F.phi.
+template <typename T, bool SP = false, bool OWN = false>
 __device__ __forceinline__ bool sor_site(const Scalars& S, const Fields<T>& F, unsigned t, int color, double omega,
-                                         unsigned& o, double& v) {
+                                         unsigned& o, double& v, const double* own = nullptr) {
     unsigned i;
     int x, y, z;
     if (S.ncolor == 3) {
@@ -503,11 +525,15 @@ __device__ __forceinline__ bool sor_site(const Scalars& S, const Fields<T>& F, u
     }
     double diag, offsum, src;
     poisson_row<T, SP>(i, x, y, z, S, F, diag, offsum, src);
-    if (diag <= 0.0) return false;
-    const double gs = (offsum + src) / diag;
     o = cidx<SP>(S, i, color);
-    const double p = F.phi[o];
-    v = p + omega * (gs - p);
+    if (diag <= 0.0) {  // an isolated site keeps its value (with OWN: the one in own)
+        if (!OWN) return false;
+        v = own[i >> 1];
+        return true;
+    }
+    const double gs = (offsum + src) / diag;
+    const double p = OWN ? own[i >> 1] : F.phi[o];
+    v = sor_update(p, gs, omega);
     return true;
 }
 
@@ -521,6 +547,21 @@ __device__ __forceinline__ void sor_body(const Scalars& S, const Fields<T>& F, u
 template <typename T, bool SP>
 __global__ __launch_bounds__(kBlock) void k_sor(Scalars S, Fields<T> F, int color, double omega) {
     sor_body<T, SP>(S, F, xcd_linear(), color, omega);
+}
+
+// The black pass after k_mg_prolong_red_fine: own values from blk.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sor_black_from(Scalars S, Fields<T> F, double omega,
+                                                           const double* __restrict__ blk) {
+    unsigned o;
+    double v;
+    if (sor_site<T, true, true>(S, F, xcd_linear(), 1, omega, o, v, blk)) F.phi[o] = v;
+}
+
+template <typename T>
+void launch_sor_black_from(const Scalars& S, const Fields<T>& F, double omega, const double* blk, hipStream_t st) {
+    const unsigned n = (unsigned)(S.nx / 2) * S.ny * (S.z1 - S.z0 + 1);
+    hipLaunchKernelGGL(k_sor_black_from<T>, dim3(site_blocks(n)), dim3(kBlock), 0, st, S, F, omega, blk);
 }
 
 template <typename T>
@@ -963,6 +1004,35 @@ __device__ __forceinline__ void prolong_fine_body(const Scalars& S, const Fields
     F.phi[i] += v;
 }
 
+// Trilinear correction of one lattice site from the coarse potentials P of the cells
+// (I - 1 .. I + 1) x (J - 1 .. J + 1) x (K - 1 .. K + 1): xo, yo, zo index the site's own
+// coarse cell and its neighbour towards the site, weighted 3/4 and 1/4 (wzs carries the
+// fall-back to the parent across a wall).  The terms and their order are those of
+// prolong_fine_body.
+__device__ __forceinline__ double prolong_corr(const double (&P)[3][3][3], const int (&xo)[2], const int (&yo)[2],
+                                               const int (&zo)[2], const double (&wzs)[2]) {
+#pragma clang fp contract(off)
+    const double wxs[2] = {0.75, 0.25}, wys[2] = {0.75, 0.25};
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) v += wxs[a] * wys[b] * wzs[c] * P[zo[c]][yo[b]][xo[a]];
+    return v;
+}
+
+__device__ __forceinline__ void load_coarse27(const MGLevel& C, int I, int J, int K, double (&P)[3][3][3]) {
+#pragma unroll
+    for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox)
+                P[oz][oy][ox] = C.phi[lid(C, wrapc(I + ox - 1, C.nx), wrapc(J + oy - 1, C.ny), wrapc(K + oz - 1, C.nz))];
+}
+
 // The same, one thread per coarse cell for its eight lattice children: the 3x3x3 coarse
 // neighbourhood is loaded once into registers and each child is interpolated with exactly
 // the expression and order of prolong_fine_body (bit-identical); the two x-children of a
@@ -975,13 +1045,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong_fine(Scalars S, Fields<T>
     int I, J, K;
     level_xyz(t, C, I, J, K);
     double P[3][3][3];  // coarse potential at (I + ox - 1, J + oy - 1, K + oz - 1), periodic
-#pragma unroll
-    for (int oz = 0; oz < 3; ++oz)
-#pragma unroll
-        for (int oy = 0; oy < 3; ++oy)
-#pragma unroll
-            for (int ox = 0; ox < 3; ++ox)
-                P[oz][oy][ox] = C.phi[lid(C, wrapc(I + ox - 1, C.nx), wrapc(J + oy - 1, C.ny), wrapc(K + oz - 1, C.nz))];
+    load_coarse27(C, I, J, K, P);
 #pragma unroll
     for (int cz = 0; cz < 2; ++cz) {
         const int z = 2 * K + cz;
@@ -995,7 +1059,6 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong_fine(Scalars S, Fields<T>
         for (int cy = 0; cy < 2; ++cy) {
             const int y = 2 * J + cy;
             const int dy = cy ? 1 : -1;
-            const double wys[2] = {0.75, 0.25};
             const int yo[2] = {1, 1 + dy};
             const unsigned i0 = (unsigned)(2 * I) + (unsigned)S.nx * ((unsigned)y + (unsigned)S.ny * (unsigned)z);
             double2 f;
@@ -1014,16 +1077,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong_fine(Scalars S, Fields<T>
 #pragma unroll
             for (int cx = 0; cx < 2; ++cx) {
                 const int dx = cx ? 1 : -1;
-                const double wxs[2] = {0.75, 0.25};
                 const int xo[2] = {1, 1 + dx};
-                double v = 0.0;
-#pragma unroll
-                for (int c = 0; c < 2; ++c)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b)
-#pragma unroll
-                        for (int a = 0; a < 2; ++a) v += wxs[a] * wys[b] * wzs[c] * P[zo[c]][yo[b]][xo[a]];
-                vv[cx] = v;
+                vv[cx] = prolong_corr(P, xo, yo, zo, wzs);
             }
             f.x += vv[0];
             f.y += vv[1];
@@ -1043,6 +1098,71 @@ void launch_mg_prolong_fine(const Scalars& S, const Fields<T>& F, const MGLevel&
         hipLaunchKernelGGL((k_mg_prolong_fine<T, true>), dim3(site_blocks(c.n)), dim3(kBlock), 0, st, S, F, c);
     else
         hipLaunchKernelGGL((k_mg_prolong_fine<T, false>), dim3(site_blocks(c.n)), dim3(kBlock), 0, st, S, F, c);
+}
+
+// The interpolation onto the lattice fused with the first red pass of the post-smoothing
+// (colour-split fields).  One thread per coarse cell.  Its four red children take the
+// interpolated correction and then their Gauss-Seidel update; their six black neighbours
+// (three in the block, three around it) are interpolated on the fly from the same 3x3x3
+// coarse registers.  Its four black children's interpolated values go to blk (indexed
+// like the black half), and the black pass that follows reads them from there: written in
+// place they could reach a neighbouring thread that still needs the old values.  Every
+// value is the one the separate interpolation and red pass compute: the same expressions
+// in the same order.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mg_prolong_red_fine(Scalars S, Fields<T> F, MGLevel C, double omega,
+                                                                double* __restrict__ blk) {
+    const unsigned t = xcd_linear();
+    if (t >= C.n) return;
+    int I, J, K;
+    level_xyz(t, C, I, J, K);
+    double P[3][3][3];
+    load_coarse27(C, I, J, K, P);
+    // correction at the lattice site (2I + rx, 2J + ry, 2K + rz), rx, ry, rz in -1..2 (its
+    // coarse cell and the neighbour towards it lie in P); the offsets are compile-time
+    // constants once the loops below unroll, so P stays in registers
+    auto corr_at = [&](int rx, int ry, int rz) {
+        const int dx = (rx & 1) ? 1 : -1, dy = (ry & 1) ? 1 : -1, dz = (rz & 1) ? 1 : -1;
+        const int xo[2] = {1 + (rx >> 1), 1 + (rx >> 1) + dx}, yo[2] = {1 + (ry >> 1), 1 + (ry >> 1) + dy},
+                  zo[2] = {1 + (rz >> 1), 1 + (rz >> 1) + dz};  // >> 1: floor, also for -1
+        const int Kw = wrapc(K + (rz >> 1), C.nz);
+        const bool zwrap = S.walls && (Kw + dz < 0 || Kw + dz >= C.nz);
+        const double wz = zwrap ? 0.0 : 0.25;
+        const double wzs[2] = {1.0 - wz, wz};
+        return prolong_corr(P, xo, yo, zo, wzs);
+    };
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                const int x = 2 * I + cx, y = 2 * J + cy, z = 2 * K + cz;
+                if (z < S.z0 || z > S.z1) continue;
+                const unsigned i = (unsigned)x + (unsigned)S.nx * ((unsigned)y + (unsigned)S.ny * (unsigned)z);
+                const int col = (cx + cy + cz) & 1;
+                const double p = F.phi[cidx<true>(S, i, col)] + corr_at(cx, cy, cz);
+                if (col) {
+                    blk[i >> 1] = p;
+                    continue;
+                }
+                double diag, offsum, src;
+                poisson_row_v<T, true>(
+                    i, x, y, z, S, F,
+                    [&](unsigned j, int c, int ox, int oy, int oz) {
+                        return F.phi[cidx<true>(S, j, c)] + corr_at(cx + ox, cy + oy, cz + oz);
+                    },
+                    diag, offsum, src);
+                double v = p;
+                if (diag > 0.0) v = sor_update(p, (offsum + src) / diag, omega);
+                F.phi[cidx<true>(S, i, 0)] = v;
+            }
+}
+
+template <typename T>
+void launch_mg_prolong_red_fine(const Scalars& S, const Fields<T>& F, const MGLevel& c, double omega, double* blk,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_mg_prolong_red_fine<T>, dim3(site_blocks(c.n)), dim3(kBlock), 0, st, S, F, c, omega, blk);
 }
 
 
@@ -2079,7 +2199,10 @@ template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, 
     template void launch_mg_coarsen_fine<T>(const Scalars&, const Fields<T>&, const MGLevel&, hipStream_t);    \
     template void launch_mg_restrict_fine<T>(const Scalars&, const Fields<T>&, const MGLevel&, bool, double,      \
                                              hipStream_t);                                                       \
-    template void launch_mg_prolong_fine<T>(const Scalars&, const Fields<T>&, const MGLevel&, bool, hipStream_t);
+    template void launch_mg_prolong_fine<T>(const Scalars&, const Fields<T>&, const MGLevel&, bool, hipStream_t); \
+    template void launch_mg_prolong_red_fine<T>(const Scalars&, const Fields<T>&, const MGLevel&, double, double*, \
+                                                hipStream_t);                                                      \
+    template void launch_sor_black_from<T>(const Scalars&, const Fields<T>&, double, const double*, hipStream_t);
 
 EK_INST(float)
 EK_INST(double)
