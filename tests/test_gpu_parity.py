@@ -284,20 +284,26 @@ def test_cycle_graph_matches_direct_launches(precision):
     b.close()
 
 
-@pytest.mark.parametrize("case", ["walls_fp32", "walls_fp64", "colloids_fp32"])
-def test_colour_split_solve_is_bit_identical_to_site_order(case, monkeypatch):
-    """Multigrid solves run on colour-split copies of the potential and charge; the same
-    arithmetic in the same order as the site-order solve (EK_POISSON_SITE_ORDER=1), so the
-    states agree bit for bit, iteration counts included."""
+@pytest.mark.parametrize("case,shape", [("walls_fp32", None), ("walls_fp64", None), ("colloids_fp32", None),
+                                        ("walls_fp32", (2, 1, 1, 3, 3, 3, 10)), ("walls_fp64", (1, 3, 0, 2, 2, 2, 6))])
+def test_colour_split_solve_is_bit_identical_to_site_order(case, shape, monkeypatch):
+    """Multigrid solves run on colour-split copies of the potential and charge, with the
+    lattice interpolation fused with the first red pass after it; the same arithmetic in
+    the same order as the separate site-order launches (EK_POISSON_SITE_ORDER=1), so the
+    states agree bit for bit, iteration counts included (default V-cycle and two other
+    shapes: one and three lattice sweeps after the coarse-grid correction)."""
     if case == "colloids_fp32":
         cfg, inp = wl.colloids(shape=(32, 32, 32), count=4, radius=3.0, precision="fp32", seed=11)
     else:
         cfg, inp = wl.walls_interface(shape=(32, 32, 64), precision=case.split("_")[1])
-    _announce(f"colour-split vs site-order multigrid: {case}")
+    _announce(f"colour-split vs site-order multigrid: {case} {shape or 'default shape'}")
     a = ek.EKSim(cfg, inp)
     monkeypatch.setenv("EK_POISSON_SITE_ORDER", "1")
     b = ek.EKSim(cfg, inp)
     monkeypatch.delenv("EK_POISSON_SITE_ORDER")
+    if shape is not None:
+        for sim in (a, b):
+            sim.set_multigrid(*shape, omega=1.15)
     assert a.device_bytes() > b.device_bytes()
     for k in ("phi", "rho_a", "n_plus", "n_minus"):
         assert np.array_equal(a.field(k), b.field(k)), f"t=0 {k}"
