@@ -110,6 +110,8 @@ struct ek_ctx {
     double* phi_own = nullptr;
     bool vc_off = false;
     bool vc_split = false;  // layout the captured V-cycle graph works on
+    int kring[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // V-cycles of the last own multigrid solves
+    int kpos = 0;
     void* tune_buf = nullptr;  // state copy of the autotuner (held only while it runs)
     // tau = 1 moment state instead of populations (ek_params.moment_state): two buffers of
     // 8 N values (step parity as the populations), the FP64 initial densities the first
@@ -424,6 +426,22 @@ static ek_status build_geometry(ek_ctx* c, const ek_particle* parts, int np, Hos
 // ------------------------------------------------------------------------------------
 // Poisson solve with convergence control
 // ------------------------------------------------------------------------------------
+// The fewest V-cycles any of the last eight own multigrid solves needed (0 until eight are
+// recorded, or after a change of the cycle shape).
+static int cycles_floor(const ek_ctx* c) {
+    int m = c->kring[0];
+    for (int k = 1; k < 8; ++k) m = std::min(m, c->kring[k]);
+    return m;
+}
+static void cycles_record(ek_ctx* c, int k) {
+    c->kring[c->kpos] = k;
+    c->kpos = (c->kpos + 1) % 8;
+}
+static void cycles_forget(ek_ctx* c) {
+    for (int k = 0; k < 8; ++k) c->kring[k] = 0;
+    c->kpos = 0;
+}
+
 // F in site order (split false) and pack: the kernel also fills c->phis, c->qs.
 template <typename T>
 static ek_status check_residual(ek_ctx* c, const Fields<T>& F, bool split, bool pack, double& rr, double& ss) {
@@ -561,19 +579,61 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
         FS.phi = c->phis;
         FS.q = (T*)c->qs;
     }
-    double rr, ss;
-    EK_TRY(check_residual<T>(c, F, false, split, rr, ss));  // from site order, filling the split copies
-    c->last_rel0 = ss > 0.0 ? std::sqrt(rr / ss) : 0.0;
+    const bool use_mg = !c->mg.empty();
+    const bool own = c->phi == c->phi_own && c->q == c->q_own;
+    // the cycle rate: geometric mean over the last k cycles, kept on the slow side
+    auto update_rate = [&](double r_old, double r_new, int k) {
+        if (r_new < r_old && r_new > 0.0) {
+            const double est = std::pow(r_new / r_old, 1.0 / k);
+            c->rate = c->rate > 0.0 ? std::max(est, 0.5 * (c->rate + est)) : est;
+        }
+    };
+    // Multigrid solves of the context's own potential launch the cycles that every one of
+    // the last solves needed (k0) before reading back the first residual: one host round
+    // trip fewer per solve.  The first check's sums go to scal[24..26].
+    const int k0 = own && use_mg ? std::min(cycles_floor(c), maxit) : 0;
+    double rr, ss, r_k0 = 0.0;
     int it = 0;
+    bool built = false;
+    if (k0 > 0) {
+        const unsigned nres = residual_blocks(c->N);
+        launch_residual<T>(c->S, F, nres, false, split ? c->phis : nullptr, split ? (T*)c->qs : nullptr, c->st);
+        launch_reduce(c->red, nres, 3, nullptr, c->scal + 24, c->st);
+        mg_build<T>(c, F);
+        built = true;
+        {
+            Timer ts(c, EK_T_ITER, k0);
+            EK_TRY(run_cycles<T>(c, FS, split, k0));
+        }
+        EK_HIP(hipGetLastError());
+        it = k0;
+        launch_residual<T>(c->S, FS, nres, split, nullptr, nullptr, c->st);
+        launch_reduce(c->red, nres, 3, nullptr, c->scal + 1, c->st);
+        EK_HIP(hipMemcpyAsync(c->hscal, c->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        EK_HIP(hipMemcpyAsync(c->hscal + 24, c->scal + 24, 3 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        EK_HIP(hipStreamSynchronize(c->st));
+        rr = c->hscal[24];
+        ss = c->hscal[25];
+        r_k0 = std::sqrt(c->hscal[1]);
+        c->last_mean = c->hscal[0];
+    } else {
+        EK_TRY(check_residual<T>(c, F, false, split, rr, ss));  // from site order, filling the split copies
+    }
+    c->last_rel0 = ss > 0.0 ? std::sqrt(rr / ss) : 0.0;
     ek_status status = EK_OK;
     double rel = 0.0;
+    int need = 0;  // cycles this solve needed (for the next solves' k0)
     if (!(ss > 0.0)) {
         launch_phi_finalize<T>(c->S, F, 1, nullptr, c->st);
     } else {
         const double target = tol * std::sqrt(ss);
-        double r = std::sqrt(rr);
-        const bool use_mg = !c->mg.empty();
-        if (use_mg && r > target) mg_build<T>(c, F);
+        const double r0 = std::sqrt(rr);
+        double r = r0;
+        if (k0 > 0) {
+            update_rate(r, r_k0, k0);
+            r = r_k0;
+        }
+        if (use_mg && r > target && !built) mg_build<T>(c, F);
         while (use_mg && r > target && it < maxit) {
             int k = 1;
             if (c->rate > 0.0 && c->rate < 1.0) k = (int)std::ceil(std::log(target / r) / std::log(c->rate));
@@ -587,10 +647,7 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
             it += k;
             EK_TRY(check_residual<T>(c, FS, split, false, rr, ss));
             const double rn = std::sqrt(rr);
-            if (rn < r && rn > 0.0) {
-                const double est = std::pow(rn / r, 1.0 / k);
-                c->rate = c->rate > 0.0 ? std::max(est, 0.5 * (c->rate + est)) : est;
-            }
+            update_rate(r, rn, k);
             r = rn;
         }
         while (!use_mg && r > target && it < maxit) {
@@ -612,17 +669,24 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
             it += k;
             EK_TRY(check_residual<T>(c, FS, split, false, rr, ss));
             const double rn = std::sqrt(rr);
-            if (rn < r && rn > 0.0) {
-                const double est = std::pow(rn / r, 1.0 / k);
-                c->rate = c->rate > 0.0 ? std::max(est, 0.5 * (c->rate + est)) : est;
-            }
+            update_rate(r, rn, k);
             r = rn;
         }
         launch_phi_finalize<T>(c->S, F, 0, split ? c->phis : nullptr, c->st);
         rel = r / std::sqrt(ss);
         if (r > target) status = EK_ENOCONV;
+        // cycles needed: the first count at which the solve's mean decay per cycle reaches
+        // the target (at most the cycles run), so that running k0 cycles does not lock k0 in
+        need = it;
+        if (r0 <= target) {
+            need = 0;
+        } else if (it > 0 && r > 0.0 && r < r0) {
+            const double rho = std::pow(r / r0, 1.0 / it);
+            need = std::min(it, std::max(0, (int)std::ceil(std::log(target / r0) / std::log(rho) - 1e-9)));
+        }
     }
     EK_HIP(hipGetLastError());
+    if (own && use_mg) cycles_record(c, need);
     c->last_iters = it;
     c->last_rel = rel;
     c->ptotal += it;
@@ -1402,6 +1466,7 @@ static void apply_shape(ek_ctx* c, const CycleShape& sh) {
     c->mg_coarsest = sh.v[6];
     c->mg_omega = sh.omega;
     c->rate = -1.0;        // the convergence rate of the new shape is estimated afresh
+    cycles_forget(c);      // and so are the cycles a solve needs
     vcycle_graph_drop(c);  // the captured cycle has the old shape
 }
 
@@ -1431,6 +1496,7 @@ struct HostState {
     int cur, pcur, ws_order, ws_since, last_iters, ms_first;
     double rate, rel0_of[4], last_rel, last_mean, last_rel0;
     long long steps, ptotal;
+    int kring[8], kpos;
 };
 }  // namespace
 
@@ -1441,8 +1507,10 @@ static ek_status tune_copy(ek_ctx* c, bool save, HostState& h) {
     char* b = (char*)c->tune_buf;
     if (save) {
         h = HostState{c->cur, c->pcur, c->ws_order, c->ws_since, c->last_iters, c->ms_first ? 1 : 0, c->rate,
-                      {0, 0, 0, 0}, c->last_rel, c->last_mean, c->last_rel0, c->steps, c->ptotal};
+                      {0, 0, 0, 0}, c->last_rel, c->last_mean, c->last_rel0, c->steps, c->ptotal,
+                      {0, 0, 0, 0, 0, 0, 0, 0}, c->kpos};
         for (int k = 0; k < 4; ++k) h.rel0_of[k] = c->rel0_of[k];
+        for (int k = 0; k < 8; ++k) h.kring[k] = c->kring[k];
     } else {
         c->cur = h.cur;
         c->pcur = h.pcur;
@@ -1457,6 +1525,8 @@ static ek_status tune_copy(ek_ctx* c, bool save, HostState& h) {
         c->last_rel0 = h.last_rel0;
         c->steps = h.steps;
         c->ptotal = h.ptotal;
+        for (int k = 0; k < 8; ++k) c->kring[k] = h.kring[k];
+        c->kpos = h.kpos;
     }
     // populations of the current step, or the moment state (8 N values, in the first slot)
     void* dev[] = {c->moment_state ? c->ms[c->cur] : c->f[c->cur][0], c->moment_state ? nullptr : c->f[c->cur][1],
@@ -1539,7 +1609,10 @@ static ek_status autotune_impl(ek_ctx* c, int trial, int* best, double* ms_out) 
     const ek_status rs = tune_copy(c, false, h);
     bool same = b.omega == orig.omega;
     for (int j = 0; j < 7; ++j) same = same && b.v[j] == orig.v[j];
-    if (!same) c->rate = -1.0;  // the restored rate belongs to the old shape
+    if (!same) {  // the restored rate and cycle counts belong to the old shape
+        c->rate = -1.0;
+        cycles_forget(c);
+    }
     EK_HIP(hipStreamSynchronize(c->st));
     dfree(c, c->tune_buf, tune_bytes(c));
     c->tune_buf = nullptr;
