@@ -571,16 +571,16 @@ template <typename T>
 static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out, double* rel_out) {
     Timer tm(c, EK_T_POISSON);
     Fields<T> F = fields<T>(c);
+    const bool use_mg = !c->mg.empty();
+    const bool own = c->phi == c->phi_own && c->q == c->q_own;
     // a multigrid solve of the context's own potential runs on colour-split copies of the
     // potential and charge; the gauge kernel writes the result back in site order
-    const bool split = c->phis && !c->mg.empty() && c->phi == c->phi_own && c->q == c->q_own;
+    const bool split = c->phis && use_mg && own;
     Fields<T> FS = F;
     if (split) {
         FS.phi = c->phis;
         FS.q = (T*)c->qs;
     }
-    const bool use_mg = !c->mg.empty();
-    const bool own = c->phi == c->phi_own && c->q == c->q_own;
     // the cycle rate: geometric mean over the last k cycles, kept on the slow side
     auto update_rate = [&](double r_old, double r_new, int k) {
         if (r_new < r_old && r_new > 0.0) {
