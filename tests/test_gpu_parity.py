@@ -315,3 +315,23 @@ def test_colour_split_solve_is_bit_identical_to_site_order(case, shape, monkeypa
     assert oa["poisson_total"] == ob["poisson_total"] > 0
     a.close()
     b.close()
+
+
+def test_cycle_control_meets_tolerance_every_step():
+    """The multigrid solve launches the cycles recent solves needed before it reads back the
+    start residual; every step must still end below the tolerance, and the count it records
+    is what was needed, so running k0 cycles does not lock k0 in: after the start-up
+    transient the cycles per step fall back (walls 64^3 FP32, tolerance 1e-8)."""
+    cfg, inp = wl.walls_interface(shape=(64, 64, 64), precision="fp32")
+    _announce("cycle control: walls 64^3 fp32, 60 steps")
+    sim = ek.EKSim(cfg, inp)
+    counts = []
+    for _ in range(60):
+        sim.step(1)
+        o = sim.observables()
+        assert 0.0 < o["poisson_rel"] <= cfg.poisson_tol, o["poisson_rel"]
+        counts.append(o["poisson_iters"])
+    _announce(f"  cycles per step: {counts}")
+    assert max(counts[-20:]) <= max(counts[:10])
+    assert min(counts[-20:]) < max(counts[:10])
+    sim.close()
