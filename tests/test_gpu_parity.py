@@ -126,6 +126,19 @@ def test_walls_interface_small(precision, solver):
     _announce(f"  errors {errs}")
 
 
+def test_walls_odd_periodic_axis_three_colour_sor():
+    """Charged walls with an odd periodic y axis (7): no red-black colouring exists, the SOR
+    solver sweeps in three colours; parity with the oracle after 30 steps (FP64)."""
+    cfg, inp = wl.walls_interface(shape=(8, 7, 13), precision="fp64")
+    _announce("walls_interface 8x7x13 fp64 (three-colour SOR)")
+    sim, o = _pair(cfg, inp)
+    compare(sim, o, "fp64", "t=0")
+    sim.step(30)
+    o.step(30)
+    errs = compare(sim, o, "fp64", "after 30")
+    _announce(f"  errors {errs}")
+
+
 # --------------------------------------------------------------------------------
 # Resolved charged spheres under a field.
 # --------------------------------------------------------------------------------
