@@ -532,7 +532,7 @@ static void vcycle_graph_drop(ek_ctx* c) {
 template <typename T>
 static ek_status run_cycles(ek_ctx* c, Fields<T>& F, bool split, int k) {
     const bool own = c->phi == c->phi_own && c->q == c->q_own;
-    if (c->vc_exec && c->vc_split != split) vcycle_graph_drop(c);
+    if (own && c->vc_exec && c->vc_split != split) vcycle_graph_drop(c);  // other solves launch directly
     if (c->timing < 2 && own && !c->vc_off && !c->vc_exec) {
         if (!c->cap_st) EK_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
         hipStream_t st = c->st;
