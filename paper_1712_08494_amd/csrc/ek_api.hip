@@ -144,6 +144,8 @@ struct ek_ctx {
         std::vector<long long> ck_steps, ck_ptotal;
         std::vector<int> ck_ws;          // adaptive warm start: order, steps since the probe
         std::vector<double> ck_rel0;     // its last start residuals of orders 2 and 3
+        std::vector<int> ck_kring;       // cycles the last solves needed (8 per checkpoint) and
+        std::vector<int> ck_kpos;        // the next record's place
         double* seg = nullptr;      // K x kSegVals N doubles: the states of one segment
         int seg_cap = 0;
         double* buf = nullptr;      // adjoint fields (kAdjVals N doubles)
@@ -1237,6 +1239,8 @@ static ek_status save_ck(ek_ctx* c, int slot) {
     c->adj.ck_ws[2 * slot + 1] = c->ws_since;
     c->adj.ck_rel0[2 * slot] = c->rel0_of[2];
     c->adj.ck_rel0[2 * slot + 1] = c->rel0_of[3];
+    for (int k = 0; k < 8; ++k) c->adj.ck_kring[8 * slot + k] = c->kring[k];
+    c->adj.ck_kpos[slot] = c->kpos;
     return EK_OK;
 }
 
@@ -1257,6 +1261,8 @@ static ek_status load_ck(ek_ctx* c, int slot) {
     c->ws_since = c->adj.ck_ws[2 * slot + 1];
     c->rel0_of[2] = c->adj.ck_rel0[2 * slot];
     c->rel0_of[3] = c->adj.ck_rel0[2 * slot + 1];
+    for (int k = 0; k < 8; ++k) c->kring[k] = c->adj.ck_kring[8 * slot + k];
+    c->kpos = c->adj.ck_kpos[slot];
     return EK_OK;
 }
 
@@ -1279,6 +1285,8 @@ extern "C" ek_status ek_forward_ckpt(ek_ctx* c, int32_t nsteps, int32_t every) {
     A.ck_ptotal.assign(need, 0);
     A.ck_ws.assign(2 * need, 0);
     A.ck_rel0.assign(2 * need, 0.0);
+    A.ck_kring.assign(8 * need, 0);
+    A.ck_kpos.assign(need, 0);
     A.valid = false;
     ek_status worst = EK_OK;
     for (int g = 0; g < nseg; ++g) {
