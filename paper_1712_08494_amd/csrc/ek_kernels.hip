@@ -948,12 +948,32 @@ __device__ __forceinline__ void restrict_body(const MGLevel& Fl, const MGLevel& 
     coarse_start(C, I, J, K, t, sum, red_omega);
 }
 
+// The same with one thread per cell of Fl: eight consecutive lanes hold the children of
+// one coarse cell (child a + 2b + 4c), and the sum runs over them in the order of
+// restrict_body.  The launched coarse grids are small (32 k and 4 k coarse cells at 128^3),
+// and eight times the threads hide the loads of the rows far better.
 __global__ __launch_bounds__(kBlock) void k_mg_restrict(MGLevel Fl, MGLevel C, double red_omega) {
-    restrict_body(Fl, C, xcd_linear(), red_omega);
+    const unsigned t = xcd_linear();
+    if (t >= 8u * C.n) return;  // groups of eight lanes leave together (blockDim is a multiple of 8)
+    const unsigned pc = t >> 3, ch = t & 7u;
+    int I, J, K;
+    level_xyz(pc, C, I, J, K);
+    const int x = 2 * I + (int)(ch & 1u), y = 2 * J + (int)((ch >> 1) & 1u), z = 2 * K + (int)(ch >> 2);
+    double diag, off;
+    mg_row(Fl, x, y, z, diag, off);
+    const unsigned i = lid(Fl, x, y, z);
+    const double r = Fl.s[i] + off - diag * Fl.phi[i];
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sum += __shfl(r, k, 8);
+    if (ch == 0) {
+        C.s[pc] = sum;
+        coarse_start(C, I, J, K, pc, sum, red_omega);
+    }
 }
 
 void launch_mg_restrict(const MGLevel& f, const MGLevel& c, double red_omega, hipStream_t st) {
-    hipLaunchKernelGGL(k_mg_restrict, dim3(site_blocks(c.n)), dim3(kBlock), 0, st, f, c, red_omega);
+    hipLaunchKernelGGL(k_mg_restrict, dim3(site_blocks(8u * c.n)), dim3(kBlock), 0, st, f, c, red_omega);
 }
 
 // Trilinear interpolation of the coarse correction at the fine cell (x, y, z).
