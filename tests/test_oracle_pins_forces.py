@@ -1,0 +1,333 @@
+"""More pins of the FP64 oracle: the force terms, the permittivity law and the particle
+couplings, each checked against a closed form, a conservation law or a symmetry that
+does not come from the oracle's own code.
+
+- Virtual densities on solid sites (Sec. II E, after Jansen et al.): a uniform fluid next
+  to a flat wall or a resting neutral sphere feels no Shan-Chen force and stays uniform.
+- Kelvin force (Sec. II C, eq. kelvin): -(eps - eps_bar)/2 grad E^2 in a dielectric column
+  between charged walls, against the continuum field D / eps(z).
+- Solvation coupling of fluid a to the ions (Sec. II C, eq. shanChenForce with
+  G_a+- = dmu+- / (drho_a cs2)): the force -psi^a (dmu / drho_a) grad n on single modes.
+- Fluid-fraction weighted link flux (Sec. II E, eq. ionic-fluxes-disc-2): n = n0 psi_f is a
+  fixed point, and no ion enters a fully covered site.
+- Electric force on a particle (Sec. II E): a charged sphere at rest in a uniform field
+  receives exactly Q E (the self-force of its own charge cancels).
+- Permittivity law (Sec. II B eq. dielectric_constant; Sec. II E): field ratios of a
+  layered dielectric between charged walls, and the interior field of a dielectric sphere
+  (Clausius-Mossotti).
+- Hertz contact and lubrication (Sec. II E, eqs. colloid_interaction, lubrication):
+  direction, Newton's third law and the scaling laws of the printed forces.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1712_08494_amd import workloads as wl
+
+CS2 = 1.0 / 3.0
+
+
+def run(cfg, inp, steps=0):
+    o = orc.Oracle(cfg, inp)
+    if steps:
+        o.step(steps)
+    return o
+
+
+def column(cfg, values):
+    """(nz,) profile broadcast to the lattice shape (nz, ny, nx)."""
+    return np.broadcast_to(np.asarray(values, dtype=float)[:, None, None], (cfg.nz, cfg.ny, cfg.nx)).copy()
+
+
+# --------------------------------------------------------------------------------
+# Virtual densities (Sec. II E): the solid sites next to the fluid carry the mean of
+# their fluid neighbours, so a uniform fluid sees uniform pseudopotentials around it.
+# A sum instead of the mean, or counting solid neighbours, puts a force on the first
+# fluid layer and builds a density layer there.
+# --------------------------------------------------------------------------------
+def test_virtual_density_wall_keeps_uniform_mixture_at_rest():
+    cfg = wl.EKConfig(4, 4, 12, walls_z=True, G=3.0)
+    inp = wl.uniform(cfg, 0.7, 0.3, 0.0, 0.0)
+    o = run(cfg, inp, steps=6)
+    fl = slice(1, cfg.nz - 1)
+    np.testing.assert_allclose(o.field("rho_a")[fl], 0.7, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(o.field("rho_b")[fl], 0.3, rtol=1e-13, atol=0)
+    for k in ("Phi_a_z", "Phi_b_z", "upz"):
+        assert np.abs(o.field(k)[fl]).max() < 1e-14, k
+
+
+def test_virtual_density_sphere_keeps_uniform_mixture_at_rest():
+    cfg = wl.EKConfig(16, 16, 16, G=3.0)
+    inp = wl.uniform(cfg, 0.7, 0.3, 0.0, 0.0)
+    inp.particles = np.array([[8.2, 7.7, 8.4, 0.0, 0.0, 0.0, 3.3, 0.0]])
+    o = run(cfg, inp, steps=4)
+    fluid = o.field("solid") == 0
+    np.testing.assert_allclose(o.field("rho_a")[fluid], 0.7, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(o.field("rho_b")[fluid], 0.3, rtol=1e-13, atol=0)
+    for k in ("Phi_a_x", "Phi_a_y", "Phi_a_z", "Phi_b_x", "Phi_b_y", "Phi_b_z"):
+        assert np.abs(o.field(k)[fluid]).max() < 1e-14, k
+    # a resting uniform fluid pushes equally on every side of the sphere: no net force
+    assert np.abs(o.particles()[0, 6:9]).max() < 1e-13
+
+
+# --------------------------------------------------------------------------------
+# Kelvin force (Sec. II C, eq. kelvin).  Between walls carrying opposite surface charges
+# +-sigma and with no ions, the displacement is uniform, D = sigma, so E(z) = sigma /
+# eps(z) along z, and the Kelvin force density is
+#     F_K = -(eps - eps_bar)/2 d(E^2)/dz = (eps - eps_bar) sigma^2 eps'(z) / eps^3.
+# With G = 0 and no ions it is the only force on the fluid.  The lattice value (central
+# differences, face permittivity the mean of the sites) agrees with it up to O(k^2) of
+# the profile's wavenumber; a flipped sign, a factor 1/2 for 1/4 in the central form, or
+# E^2 taken at the site instead of its neighbours fails.
+# --------------------------------------------------------------------------------
+def test_kelvin_force_in_dielectric_column():
+    nz, sig = 128, 1e-3
+    cfg = wl.EKConfig(2, 1, nz, walls_z=True, G=0.0, eps_a=0.05, eps_b=0.2, sigma_wall=(sig, -sig),
+                      E_ext=(3e-3, 0.0, 0.0))
+    z = np.arange(nz, dtype=float)
+    L = nz - 2
+    ra = 0.5 + 0.35 * np.sin(np.pi * (z - 1.0) / (L - 1) * 1.5)
+    inp = wl.uniform(cfg, 0.5, 0.5, 0.0, 0.0)
+    inp.rho_a = column(cfg, ra)
+    inp.rho_b = column(cfg, 1.0 - ra)
+    o = run(cfg, inp, steps=1)
+    # permittivity (eq. dielectric_constant with rho_a + rho_b = 1): eps = eps_a rho_a + eps_b rho_b
+    eps = cfg.eps_a * ra + cfg.eps_b * (1.0 - ra)
+    deps = -(cfg.eps_b - cfg.eps_a) * 0.35 * np.cos(np.pi * (z - 1.0) / (L - 1) * 1.5) * np.pi / (L - 1) * 1.5
+    ebar = 0.5 * (cfg.eps_a + cfg.eps_b)
+    expect = (eps - ebar) * sig ** 2 * deps / eps ** 3
+    Fz = (o.field("Phi_a_z") + o.field("Phi_b_z"))[:, 0, 0]
+    inner = slice(3, nz - 3)
+    scale = np.abs(expect[inner]).max()
+    assert scale > 0
+    np.testing.assert_allclose(Fz[inner], expect[inner], atol=1e-2 * scale, rtol=0)
+    # nothing varies along x or y: the other components vanish (E_ext adds a constant to E^2)
+    for k in ("Phi_a_x", "Phi_a_y", "Phi_b_x", "Phi_b_y"):
+        assert np.abs(o.field(k)).max() < 1e-22, k
+    # the force is split between the fluids by mass fraction
+    fa = o.field("Phi_a_z")[:, 0, 0]
+    np.testing.assert_allclose(fa[inner], ra[inner] * Fz[inner], rtol=1e-12, atol=1e-30)
+
+
+# --------------------------------------------------------------------------------
+# Solvation coupling of fluid a to the ions (Sec. II C, eq. shanChenForce with
+# G_a+- = dmu+- / (drho_a cs2), pseudopotentials psi+- = n+-).  By the isotropy of the
+# D3Q19 weights, sum_d w_d n(x + c_d) c_d = cs2 times the central difference, so on a
+# single Fourier mode n = A cos(k x + t) the force on fluid a is exactly
+#     Phi^a_ion = -psi^a sum_+- (dmu+- / drho_a) (-A+- sin k sin(k x + t+-)).
+# Fluid b has no ion coupling, and the friction force is shared by mass fraction, so
+# Phi^a - (rho^a / rho^b) Phi^b isolates the coupling.  Different amplitudes, phases and
+# transfer energies for the two species catch a swapped species or a dropped sign.
+# --------------------------------------------------------------------------------
+def test_solvation_coupling_force_on_fluid_a():
+    nx = 16
+    cfg = wl.EKConfig(nx, 2, 2, G=0.0, dmu_plus=2.0, dmu_minus=-1.0, drho_a=0.8)
+    k = 2 * np.pi * 2 / nx
+    x = np.arange(nx, dtype=float)
+    modes = {"n_plus": (2e-5, 0.0), "n_minus": (1e-5, 0.7)}
+    inp = wl.uniform(cfg, 0.6, 0.4, 1e-3, 1e-3)
+    for name, (A, t) in modes.items():
+        setattr(inp, name, np.broadcast_to((1e-3 + A * np.cos(k * x + t))[None, None, :], (2, 2, nx)).copy())
+    o = run(cfg, inp, steps=1)
+    psi_a = 1.0 - np.exp(-0.6)
+    expect = np.zeros(nx)
+    for (A, t), dmu in zip(modes.values(), (cfg.dmu_plus, cfg.dmu_minus)):
+        expect += -psi_a * (dmu / cfg.drho_a) * (-A * np.sin(k) * np.sin(k * x + t))
+    iso = o.field("Phi_a_x") - (0.6 / 0.4) * o.field("Phi_b_x")
+    np.testing.assert_allclose(iso[0, 0, :], expect, atol=1e-9 * np.abs(expect).max(), rtol=0)
+    for c in ("y", "z"):
+        assert np.abs(o.field(f"Phi_a_{c}") - 1.5 * o.field(f"Phi_b_{c}")).max() < 1e-12 * np.abs(expect).max()
+
+
+# --------------------------------------------------------------------------------
+# Fluid-fraction weighted link flux (Sec. II E, eq. ionic-fluxes-disc-2): at equilibrium
+# the ions at a site are proportional to its fluid fraction, so n = n0 psi_f with no field
+# and no solvation is a fixed point (dropping the 1/psi_f of the densities drives a flux
+# across every partly covered site); and the weight psi_f(i) psi_f(i+d) closes every link
+# of a fully covered site, so no ion ever enters one, even under a field.
+# --------------------------------------------------------------------------------
+def test_fluid_fraction_flux_fixed_point_and_closed_solid_sites():
+    cfg = wl.EKConfig(16, 16, 16, G=0.0)
+    inp = wl.uniform(cfg, 0.5, 0.5, 1e-3, 1e-3)
+    inp.particles = np.array([[8.3, 7.6, 8.1, 0.0, 0.0, 0.0, 3.7, 0.0]])
+    o = run(cfg, inp, steps=5)
+    psif = 1.0 - o.field("psi_s")
+    partial = (psif > 0) & (psif < 1)
+    assert partial.sum() > 50
+    for name in ("n_plus", "n_minus"):
+        np.testing.assert_allclose(o.field(name), 1e-3 * psif, atol=1e-18, rtol=0)
+
+    cfg2 = wl.EKConfig(16, 16, 16, G=0.0, E_ext=(2e-3, -1e-3, 5e-4))
+    o2 = orc.Oracle(cfg2, inp)
+    tot0 = o2.observables()
+    o2.step(5)
+    closed = o2.field("psi_s") == 1.0
+    assert closed.sum() > 20
+    for name in ("n_plus", "n_minus"):
+        n = o2.field(name)
+        assert np.all(n[closed] == 0.0), name
+        assert np.abs(n - 1e-3 * psif).max() > 1e-9, name  # the field did move ions
+    tot = o2.observables()
+    for kk in ("sum_n_plus", "sum_n_minus"):
+        assert abs(tot[kk] - tot0[kk]) < 1e-12 * tot0[kk]  # roundoff of the per-site sums
+
+
+# The weight psi_f(i) psi_f(i+d) of a link also fixes how fast a partly covered site
+# relaxes: its ion content n_i = psi_f(i) n~_i exchanges through links weighted by
+# psi_f(i), so the fluid fraction cancels and the concentration n~_i decays at the rate set
+# by its neighbours' open fractions alone.  A sphere of radius 0.45 centred on a site
+# covers part of that site only (it is LB-solid, so no fluid advects there); with ions
+# only in that site and fully fluid neighbours, one step gives n~_i (1 - 6 D) at the site
+# and D psi_f(i) n~_i in each neighbour, exactly: the bulk rate.  Dropping the weight
+# would empty the site 1/psi_f times faster.
+def test_partly_covered_site_relaxes_at_the_bulk_rate():
+    cfg = wl.EKConfig(12, 12, 12, G=0.0, D=0.05)
+    inp = wl.uniform(cfg, 0.5, 0.5, 0.0, 0.0)
+    delta = 1e-6
+    inp.n_plus[6, 6, 6] = delta
+    inp.n_minus[6, 6, 6] = delta
+    inp.particles = np.array([[6.0, 6.0, 6.0, 0.0, 0.0, 0.0, 0.45, 0.0]])
+    o = run(cfg, inp)
+    psif = 1.0 - o.field("psi_s")
+    p = psif[6, 6, 6]
+    assert 0.5 < p < 0.75 and np.count_nonzero(psif < 1.0) == 1
+    assert o.field("n_plus")[6, 6, 6] == delta * p
+    o.step(1)
+    for name in ("n_plus", "n_minus"):
+        n = o.field(name)
+        assert abs(n[6, 6, 6] / p - delta * (1 - 6 * cfg.D)) < 1e-12 * delta
+        for (z, y, x) in ((5, 6, 6), (7, 6, 6), (6, 5, 6), (6, 7, 6), (6, 6, 5), (6, 6, 7)):
+            assert abs(n[z, y, x] - cfg.D * p * delta) < 1e-12 * delta
+
+
+# --------------------------------------------------------------------------------
+# Electric force on a particle (Sec. II E: -Q grad phi with the charge spread over the
+# particle's sites).  With a uniform permittivity the Poisson operator is translation
+# invariant, so the field of the particle's own charge exerts no net force on it; in a
+# resting uniform fluid the momentum exchange cancels too.  The force after one step is
+# exactly Q E_ext, and symplectic Euler moves the sphere by v = Q E / m.
+# --------------------------------------------------------------------------------
+@pytest.mark.parametrize("centre", [(10.0, 10.0, 10.0), (9.7, 10.2, 10.45)])
+def test_particle_electric_force_is_QE(centre):
+    E = (1e-3, -5e-4, 2e-4)
+    cfg = wl.EKConfig(20, 20, 20, G=0.0, E_ext=E, eps_p=wl.EPS_FLUID, particle_rho=5.0)
+    inp = wl.uniform(cfg, 0.6, 0.4, 0.0, 0.0)
+    Q, r = 0.5, 4.0
+    inp.particles = np.array([[*centre, 0.0, 0.0, 0.0, r, Q]])
+    o = run(cfg, inp, steps=1)
+    p = o.particles()[0]
+    np.testing.assert_allclose(p[6:9], Q * np.array(E), rtol=1e-9, atol=0)
+    m = cfg.particle_rho * 4.0 / 3.0 * np.pi * r ** 3
+    np.testing.assert_allclose(p[3:6], Q * np.array(E) / m, rtol=1e-9, atol=0)
+    np.testing.assert_allclose(p[0:3], np.array(centre) + Q * np.array(E) / m, rtol=0, atol=1e-15)
+
+
+# --------------------------------------------------------------------------------
+# Permittivity law (eq. dielectric_constant, and the particle mixing of Sec. II E).
+# Between walls with surface charges +-sigma the displacement D = sigma is uniform, so in
+# a slab of uniform permittivity E = sigma / eps: pure fluid a gives sigma / eps_a, pure b
+# sigma / eps_b, and the 50/50 mixture (c = 0) sigma / ((eps_a + eps_b) / 2).  Swapping the
+# fluids' permittivities inverts the first ratio.
+# --------------------------------------------------------------------------------
+def test_layered_dielectric_field_ratios():
+    nz, sig = 62, 2e-3
+    cfg = wl.EKConfig(2, 1, nz, walls_z=True, G=0.0, eps_a=0.05, eps_b=0.15, sigma_wall=(sig, -sig))
+    z = np.arange(nz)
+    tiny = 1e-12
+    ra = np.where(z < 21, 1.0 - tiny, np.where(z < 41, 0.5, tiny))
+    inp = wl.uniform(cfg, 0.5, 0.5, 0.0, 0.0)
+    inp.rho_a = column(cfg, ra)
+    inp.rho_b = column(cfg, 1.0 - ra)
+    o = run(cfg, inp)
+    Ez = o.field("Ez")[:, 0, 0]
+    Ea, Em, Eb = Ez[5:17], Ez[25:37], Ez[45:57]
+    np.testing.assert_allclose(Ea, sig / cfg.eps_a, rtol=1e-8)
+    np.testing.assert_allclose(Eb, sig / cfg.eps_b, rtol=1e-8)
+    np.testing.assert_allclose(Em, sig / (0.5 * (cfg.eps_a + cfg.eps_b)), rtol=1e-8)
+    assert abs(Ea.mean() / Eb.mean() - cfg.eps_b / cfg.eps_a) < 1e-7
+
+
+# The particle permittivity enters by the solid fraction, eps = eps_p psi_s + eps_f (1 - psi_s).
+# A dielectric sphere in a uniform far field E0 = D / eps_f has the uniform interior field
+# 3 eps_f / (2 eps_f + eps_p) E0 (Clausius-Mossotti).  With eps_p = eps_f / 8 that is 1.41 E0;
+# exchanging the two weights turns the sphere into a high-permittivity inclusion in a
+# low-permittivity medium (0.3 E0).  On the lattice the staircase interface with face
+# permittivities taken as site means carries a first-order error: the interior field comes
+# out 10 % high at radius 5 and 6 % high at radius 10 (oracle runs at 32^3 and 64^3), so the
+# bound is 12 %; walls 16 sites away and periodic images 32 apart add under 1 %.
+def test_dielectric_sphere_interior_field():
+    sig = 1e-3
+    cfg = wl.EKConfig(32, 32, 34, walls_z=True, G=0.0, sigma_wall=(sig, -sig), eps_p=wl.EPS_FLUID / 8.0)
+    inp = wl.uniform(cfg, 0.5, 0.5, 0.0, 0.0)
+    inp.particles = np.array([[15.5, 15.5, 16.5, 0.0, 0.0, 0.0, 5.0, 0.0]])
+    o = run(cfg, inp)
+    E0 = sig / wl.EPS_FLUID
+    Ez = o.field("Ez")
+    inner = Ez[15:19, 14:18, 14:18]  # the 4x4x4 sites nearest the centre
+    expect = 3.0 * wl.EPS_FLUID / (2.0 * wl.EPS_FLUID + cfg.eps_p)
+    ratio = inner / E0
+    assert abs(ratio.mean() - expect) < 0.12 * expect, ratio.mean()
+    assert ratio.std() < 0.03 * expect  # uniform inside
+    eps = o.field("eps")
+    psis = o.field("psi_s")
+    assert np.all(eps[psis == 1.0] == cfg.eps_p)
+
+
+# --------------------------------------------------------------------------------
+# Hertz contact (eq. colloid_interaction): k_H delta^{3/2} along the line of centres,
+# repulsive, equal and opposite on the two spheres.  The step is run with and without the
+# stiffness from the same state, so the difference of the particle forces is the contact
+# force alone.  Four times the overlap gives eight times the force.
+# --------------------------------------------------------------------------------
+def _pair_force_difference(cfg, parts, **on):
+    from dataclasses import replace
+    inp = wl.uniform(cfg, 0.5, 0.5, 0.0, 0.0)
+    inp.particles = parts
+    with_f = run(replace(cfg, **on), inp, steps=1).particles()[:, 6:9]
+    off = {k: 0.0 for k in on}
+    without = run(replace(cfg, **off), inp, steps=1).particles()[:, 6:9]
+    return with_f - without
+
+
+def test_hertz_contact_force():
+    cfg = wl.EKConfig(24, 16, 16, G=0.0, move_particles=False)
+    sep = np.array([5.9, 0.2, -0.1])
+    out = []
+    for delta_scale in (1.0, 4.0):
+        d = np.linalg.norm(sep)
+        delta = 0.02 * delta_scale
+        s = sep * (6.0 - delta) / d
+        parts = np.array([[8.0, 8.0, 8.0, 0, 0, 0, 3.0, 0.0], [8.0 + s[0], 8.0 + s[1], 8.0 + s[2], 0, 0, 0, 3.0, 0.0]])
+        dF = _pair_force_difference(cfg, parts, k_hertz=1.0)
+        nhat = -s / np.linalg.norm(s)  # from particle 1 to particle 0
+        np.testing.assert_allclose(dF[0], 1.0 * delta ** 1.5 * nhat, rtol=1e-9, atol=1e-18)
+        np.testing.assert_allclose(dF[1], -dF[0], rtol=1e-12, atol=1e-18)
+        out.append(np.linalg.norm(dF[0]))
+    assert abs(out[1] / out[0] - 8.0) < 1e-9
+
+
+# Lubrication (eq. lubrication): along the line of centres, opposing the normal relative
+# velocity, proportional to eta r_p^2 and to 1/h - 1 in the gap h, absent for tangential
+# relative motion and beyond h = 2/3.
+def test_lubrication_force():
+    cfg = wl.EKConfig(24, 16, 16, G=0.0, move_particles=False, k_hertz=0.0)
+    nhat = np.array([1.0, 0.0, 0.0])
+    res = {}
+    for gap in (0.25, 0.5, 0.8):
+        for name, (v0, v1) in {"normal": ((0.01, 0.0, 0.0), (-0.004, 0.0, 0.0)),
+                               "tangential": ((0.0, 0.01, 0.002), (0.0, -0.003, 0.0))}.items():
+            x1 = 8.0 + 6.0 + gap
+            parts = np.array([[8.0, 8.0, 8.0, *v0, 3.0, 0.0], [x1, 8.0, 8.0, *v1, 3.0, 0.0]])
+            res[gap, name] = _pair_force_difference(cfg, parts, eta=1.0 / 6.0)
+    for gap in (0.25, 0.5):
+        # particle 0 approaches particle 1 (relative velocity 0.014 towards it): pushed back (-x)
+        dF = res[gap, "normal"]
+        assert dF[0, 0] < 0 and np.abs(dF[0, 1:]).max() == 0.0
+        np.testing.assert_allclose(dF[1], -dF[0], rtol=1e-12)
+        mag = 1.5 * np.pi * (1.0 / 6.0) * 9.0 * 0.014 * (1.0 / gap - 1.0)
+        np.testing.assert_allclose(-dF[0, 0], mag, rtol=1e-9)
+        assert np.abs(res[gap, "tangential"]).max() == 0.0
+    ratio = res[0.25, "normal"][0, 0] / res[0.5, "normal"][0, 0]
+    assert abs(ratio - (1 / 0.25 - 1) / (1 / 0.5 - 1)) < 1e-9
+    assert np.abs(res[0.8, "normal"]).max() == 0.0  # beyond the 2/3 cut-off
+    _ = nhat
