@@ -1,16 +1,19 @@
 """Benchmark of the coupled electrokinetic lattice step on one MI355X.
 
 One step = moments + charge/permittivity + variable-permittivity Poisson solve + total
-force + fused ion/force/collide/stream sweep (+ particles when present), i.e. the whole
-per-timestep sweep of the method.  Default workload: 128^3 lattice with charged walls in
-z and a flat interface between the two fluids (permittivity ratio 2, solvation
-contrast +-2 kT, salt 1e-3), FP32 populations; inputs are seeded synthetic fields.
+force + fused ion/force/collide/stream sweep + particle update: the whole per-timestep
+sweep of the method.  Headline workload: a 256^3 periodic binary mixture with 200
+resolved charged spheres (radius 4, surface charge uniform in [1e-3, 5e-3]) in the
+applied field E_x = 1e-4, FP32 populations; inputs are seeded synthetic fields.
 
-Prints one JSON line.  Value = lattice-site updates per second (MLUPS) of the whole step
-with all state resident in HBM.  The "roofline" object rates the dominant kernel: its
-algorithmic bytes per launch (per-site compulsory traffic x sites) over its mean launch
-time measured with HIP events on the library's stream.  "cpu_baseline" times the FP64
-CPU oracle on a bounded sample of the same workload.
+Prints one JSON line.  value = lattice-site updates per second (MLUPS) of the whole step
+with all state resident in HBM.  "roofline" rates the kernel with the largest device time
+per step, chosen among every kernel of the step (HIP events around each launch, on the
+library's stream): its algorithmic bytes per launch over its mean launch time.
+"roofline_step" rates the whole step: the method's compulsory bytes per site update
+(populations, ions and potential once each way, the solid mask, and 24 B for each executed
+lattice sweep of the Poisson solve) at the step rate.  "cpu_baseline" times the FP64 CPU
+oracle on a bounded sample of the same workload, with all host cores and with one.
 """
 import argparse
 import json
@@ -24,38 +27,39 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "coupled-step MLUPS + % HBM roofline; FP32/FP64 speedup at stated error; bwd/fwd ratio"
 
-# Algorithmic bytes per lattice site for one launch of each kernel (the data the kernel
-# must move to do its job, each array counted once); s = bytes of one population / ion /
-# moment value (4 in FP32, 8 in FP64).  The potential is always FP64.
-def algorithmic_bytes(kernel, s, tau_one=True):
-    if kernel == "fused":
-        # populations written (2 x 19), read too when tau != 1; ions read + written (2 x 2);
-        # potential read (8); moment slots read (8); physical velocity read (3)
-        pops = 2 * 19 * s * (1 if tau_one else 2)
-        return pops + 4 * s + 8 + 8 * s + 3 * s
-    if kernel == "force":
-        # moment slots read (8), ions read (2), potential read (8), physical velocity written (3)
-        return 8 * s + 2 * s + 8 + 3 * s
-    if kernel == "moments":
-        # populations read (2 x 19), ions read (2), moment slots written (8), charge and permittivity written (2)
-        return 2 * 19 * s + 2 * s + 8 * s + 2 * s
-    if kernel == "smooth":
-        # one red-black colour pass over the lattice: potential read (8) and half of it
-        # written (4), permittivity read (s), charge read for half the sites (s / 2)
-        return 8 + 4 + s + s / 2
-    raise KeyError(kernel)
+
+# Algorithmic bytes per lattice site of one launch: the part of the method's compulsory
+# traffic that the kernel carries (s = bytes of a population or ion value, 4 in FP32 and 8
+# in FP64; the potential is FP64; `mask` = 1 byte of solid mask where there are solids).
+# Intermediates that a kernel writes and the next reads (moment slots, charge,
+# permittivity, physical velocity, multigrid levels) are not algorithmic.
+def algorithmic_bytes(kernel, s, tau_one=True, mask=0):
+    pops = 2 * 19 * s
+    if kernel == "k_fused":      # populations written (and read when tau != 1), ions read + written, potential read
+        return pops * (1 if tau_one else 2) + 4 * s + 8 + mask
+    if kernel == "k_moments":    # populations read
+        return pops + mask
+    if kernel in ("k_sor", "k_sor_black_from", "k_mg_prolong_red_fine"):
+        # one red-black colour pass over the lattice: half of a sweep's potential read +
+        # write (16), charge (s) and permittivity (s)
+        return (16 + 2 * s) / 2
+    return 0.0
 
 
-# The method's own compulsory traffic per site and step (populations, ions and
-# potential, each read and written once): what a single perfectly fused pass would move.
-def step_bytes(s):
-    return 2 * 19 * 2 * s + 2 * 2 * s + 8
+def step_bytes(s, mask=0):
+    """The method's compulsory traffic per site update outside the Poisson solve."""
+    return 2 * 19 * 2 * s + 2 * 2 * s + 8 + mask
 
 
-# HBM traffic of the dominant kernel, from rocprofv3 counter runs (FETCH_SIZE, then
-# WRITE_SIZE, each scaled by what the same counter reads for a device copy of known size).
-# The summary records a hash of the kernel source it was taken on; once the source has
-# changed the figure no longer describes the kernel and is reported as null.
+def sweep_bytes(s):
+    """Compulsory traffic of one executed lattice sweep of the Poisson solve."""
+    return 16 + 2 * s
+
+
+# HBM traffic of a kernel, from rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, each
+# scaled by what the same counter reads for a device copy of known size).  The summary
+# records a hash of the kernel source it was taken on; once the source has changed the
+# figure no longer describes the kernel and is reported as null.
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1712_08494_amd", "csrc", "ek_kernels.hip")
 
 
@@ -93,25 +97,27 @@ def copy_calibration(mib, repeats=3):
     log(f"copy calibration: {repeats} copies of {mib} MiB")
 
 
-def build_workload(name, precision, n):
+def build_workload(name, precision, n, **kw):
     from paper_1712_08494_amd import workloads as wl
     if name == "walls_interface":
         return wl.walls_interface(n=n, precision=precision)
     if name == "colloids":
-        return wl.colloids(n=n, precision=precision)
+        return wl.colloids(n=n, precision=precision, **kw)
     if name == "mixture_noise":
         return wl.mixture_noise(n=n, precision=precision)
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_gpu(cfg, inp, steps, warmup, detail_steps=20, autotune=0, class_steps=50):
-    """Warm-up, then `steps` timed steps with no events inside; then `class_steps` steps
-    with an event pair around each kernel class (a few per step), and `detail_steps`
-    more with an event pair around every group of lattice-level smoothing passes as
-    well.  Events between kernels of a few microseconds stretch the step, so they stay
-    out of the timed region.  With autotune > 0 the library's V-cycle autotuner runs
-    after the warm-up (that many trial steps per candidate shape, state restored) and
-    its choice is returned."""
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_gpu(cfg, inp, steps, warmup, kernel_steps=20, autotune=0):
+    """Warm-up, then `steps` timed steps with no events inside; then `kernel_steps` more
+    with an event pair around every kernel launch (timing level 3).  Events between
+    kernels of a few microseconds stretch the step, so they stay out of the timed region.
+    With autotune > 0 the library's V-cycle autotuner runs after the warm-up (that many
+    trial steps per candidate shape, state restored) and its choice is returned."""
     import torch
     from paper_1712_08494_amd import ek
     sim = ek.EKSim(cfg, inp)
@@ -129,38 +135,58 @@ def run_gpu(cfg, inp, steps, warmup, detail_steps=20, autotune=0, class_steps=50
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ob1 = sim.observables()
-    timing = {}
-    if class_steps:
-        sim.set_timing(1)
-        sim.step(class_steps)
-        timing = sim.timing()
-    if detail_steps:
-        sim.set_timing(2)
-        sim.step(detail_steps)
-        timing["smooth"] = sim.timing()["smooth"]
-    else:
-        timing["smooth"] = (0.0, 0)
+    kt = {}
+    if kernel_steps:
+        sim.set_timing(3)
+        sim.step(kernel_steps)
+        kt = sim.kernel_timing()
+        sim.set_timing(0)
     sim.close()
-    return t1 - t0, timing, ob0, ob1, tuned
+    return t1 - t0, kt, ob0, ob1, tuned
 
 
-def S_has_particles(inp):
-    return inp.particles is not None and len(inp.particles) > 0
+def kernel_table(kt, kernel_steps, N, s, tau_one, mask):
+    """Per-kernel device time per step, launches per step, mean launch time and, for the
+    kernels that carry algorithmic traffic, that traffic's rate."""
+    table = {}
+    for name, (ms, cnt) in kt.items():
+        if not cnt:
+            continue
+        row = {"us_per_step": round(1e3 * ms / kernel_steps, 1), "launches_per_step": round(cnt / kernel_steps, 2),
+               "us_per_launch": round(1e3 * ms / cnt, 2)}
+        b = algorithmic_bytes(name, s, tau_one, mask)
+        if b:
+            row["algorithmic_bytes_per_site"] = b
+            row["GBps"] = round(b * N / (ms / 1e3 / cnt) / 1e9, 1)
+        table[name] = row
+    return table
 
 
-def run_moment_state(workload, precision, n, steps, warmup, mlups_pop):
-    """The same workload with the tau = 1 moment state (density and u_e per site instead of
-    the populations): step rate, device memory, and a bitwise comparison with the
-    population path after a few steps from the same inputs."""
+def run_secondary(name, precision, n, steps, warmup):
+    """Step rate of another workload (no per-kernel timing)."""
+    cfg, inp = build_workload(name, precision, n)
+    log(f"gpu {precision}: {cfg.name}, {warmup} warm-up + {steps} timed steps")
+    dt, _, _, ob1, _ = run_gpu(cfg, inp, steps, warmup, kernel_steps=0)
+    return {"workload": f"{name} {cfg.nx}x{cfg.ny}x{cfg.nz}", "precision": precision,
+            "mlups": round(cfg.n_sites * steps / dt / 1e6, 2), "ms_per_step": round(1e3 * dt / steps, 4),
+            "poisson_iterations_last_solve": ob1["poisson_iters"]}
+
+
+def run_moment_state(workload, precision, n, steps, warmup):
+    """The tau = 1 moment state (density and u_e per site instead of the populations) on
+    a workload without particles: step rate against the population path, device memory,
+    and a bitwise comparison with the population path after a few steps."""
     import numpy as np
     from paper_1712_08494_amd import ek
+    out = {}
+    for ms in (False, True):
+        cfg, inp = build_workload(workload, precision, n)
+        cfg.moment_state = ms
+        log(f"gpu {'moment-state' if ms else 'population'} run, {cfg.name}")
+        dt, _, _, _, _ = run_gpu(cfg, inp, steps, warmup, kernel_steps=0)
+        out["moment_state" if ms else "populations"] = round(cfg.n_sites * steps / dt / 1e6, 2)
     cfg, inp = build_workload(workload, precision, n)
     cfg.moment_state = True
-    log("gpu moment-state run")
-    dt, _, _, _, _ = run_gpu(cfg, inp, steps, warmup, detail_steps=0, class_steps=0)
-    N = cfg.n_sites
-    mlups = N * steps / dt / 1e6
-    log(f"gpu moment state: {1e3 * dt / steps:.3f} ms/step")
     a = ek.EKSim(cfg, inp)
     cfg.moment_state = False
     b = ek.EKSim(cfg, inp)
@@ -170,8 +196,9 @@ def run_moment_state(workload, precision, n, steps, warmup, mlups_pop):
     same = all(np.array_equal(a.field(k), b.field(k)) for k in ("rho_a", "rho_b", "n_plus", "n_minus", "phi"))
     a.close()
     b.close()
-    return {"mlups": round(mlups, 2), "ms_per_step": round(1e3 * dt / steps, 4),
-            "speedup_over_populations": round(mlups / mlups_pop, 3),
+    return {"workload": f"{workload} {cfg.nx}x{cfg.ny}x{cfg.nz} {precision}", "mlups": out["moment_state"],
+            "mlups_populations": out["populations"],
+            "speedup_over_populations": round(out["moment_state"] / out["populations"], 3),
             "device_mib": round(bytes_ms / 2**20, 1), "device_mib_populations": round(bytes_pop / 2**20, 1),
             "bitwise_equal_to_populations_after_5_steps": bool(same)}
 
@@ -180,8 +207,8 @@ def run_fft_compare(n, steps, warmup):
     """The paper's lagged Fourier Poisson scheme against converged multigrid solves on a
     periodic charged droplet (n^3, radius 0.21 n, permittivity ratio 4, FP32): step rate of
     each, Poisson device time per step, and how far the lagged potential drifts from the
-    converged one.  (On the resolved colloids, permittivity ratio 8 at the sphere
-    surfaces, the lagged scheme diverges: see the design notes.)"""
+    converged one.  (On resolved colloids the lagged scheme diverges, and the library
+    refuses it there.)"""
     import numpy as np
     import torch
     from paper_1712_08494_amd import ek
@@ -214,59 +241,84 @@ def run_fft_compare(n, steps, warmup):
     return out
 
 
-def precision_error(workload, n, steps):
-    """The error the FP32/FP64 speedup is quoted at: the FP32 and FP64 paths from the same
-    inputs after `steps` steps, max relative difference of the fluid densities on fluid
-    sites and of the ion densities where present, and max |dphi| / max |phi|."""
+def field_errors(a, b):
+    """Max relative difference of the fluid and ion densities where b is non-zero, and
+    max |dphi| / max |phi|; a, b: objects with .field(name)."""
     import numpy as np
-    from paper_1712_08494_amd import ek
     out = {}
-    sims = {}
-    for prec in ("fp32", "fp64"):
-        cfg, inp = build_workload(workload, prec, n)
-        sims[prec] = ek.EKSim(cfg, inp)
-        sims[prec].step(steps)
-    a, b = sims["fp32"], sims["fp64"]
     for name in ("rho_a", "rho_b", "n_plus", "n_minus"):
         x, y = a.field(name), b.field(name)
         m = np.abs(y) > 0
         out[name] = float(f"{np.max(np.abs(x - y)[m] / np.abs(y)[m]):.3e}")
     px, py = a.field("phi"), b.field("phi")
     out["phi"] = float(f"{np.abs(px - py).max() / np.abs(py).max():.3e}")
-    out["steps"] = steps
-    for sim in sims.values():
-        sim.close()
     return out
 
 
-def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+def precision_error_vs_oracle(cfg, inp, steps):
+    """The error the FP32/FP64 speedup is quoted at: the GPU FP32 path and the GPU FP64
+    path against the FP64 CPU oracle, from the same inputs after `steps` steps."""
+    from dataclasses import replace
+    from oracle import oracle as orc
+    from paper_1712_08494_amd import ek
+    o = orc.Oracle(cfg, inp)
+    o.step(steps)
+    out = {"workload": f"{cfg.name}", "steps": steps}
+    for prec in ("fp32", "fp64"):
+        sim = ek.EKSim(replace(cfg, precision=prec), inp)
+        sim.step(steps)
+        out[prec] = field_errors(sim, o)
+        sim.close()
+    o.close()
+    return out
+
+
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count(), "model": model}
 
 
 def cpu_baseline(cfg, inp, target_s=20.0):
-    """Time the FP64 oracle on the same workload: one untimed step (the first solve after
-    set-up starts from a converged potential), then whole steps up to about target_s."""
+    """Time the FP64 oracle on a bounded sample of the workload with all host cores and
+    with one: one untimed step (the first solve after set-up starts from a converged
+    potential), then whole steps up to about target_s per run."""
     from oracle import oracle as orc
-    log("cpu baseline: oracle set-up")
-    o = orc.Oracle(cfg, inp)
-    threads = orc.num_threads()
-    o.step(1)
-    log("cpu baseline: timing")
-    t0 = time.perf_counter()
-    o.step(1)
-    per = time.perf_counter() - t0
-    steps = 1
-    extra = int(max(0, min(4, target_s / max(per, 1e-6) - 1)))
-    if extra:
+    res = {}
+    for threads in (0, 1):
+        log(f"cpu baseline: oracle set-up ({'all cores' if threads == 0 else '1 core'})")
+        o = orc.Oracle(cfg, inp, n_threads=threads)
+        used = orc.num_threads() if threads == 0 else 1
+        o.step(1)
         t0 = time.perf_counter()
-        o.step(extra)
-        per = (time.perf_counter() - t0 + per) / (extra + 1)
-        steps += extra
-    o.close()
-    log(f"cpu baseline: {per:.3f} s/step over {steps} step(s)")
-    return {"value": round(cfg.n_sites / per / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} step(s) of the same {cfg.nx}x{cfg.ny}x{cfg.nz} workload (after set-up and one "
-                      f"untimed step), FP64, Poisson CG to 1e-12, {threads} OpenMP threads"}
+        o.step(1)
+        per = time.perf_counter() - t0
+        steps = 1
+        extra = int(max(0, min(9, target_s / max(per, 1e-6) - 1)))
+        if extra:
+            t0 = time.perf_counter()
+            o.step(extra)
+            per = (time.perf_counter() - t0 + per) / (extra + 1)
+            steps += extra
+        o.close()
+        log(f"cpu baseline: {per:.3f} s/step over {steps} step(s) with {used} thread(s)")
+        res[used] = (per, steps)
+    all_threads = max(res)
+    per, steps = res[all_threads]
+    per1, steps1 = res[1]
+    return {"value": round(cfg.n_sites / per / 1e6, 4), "unit": "MLUPS", "cores": all_threads, "kind": "oracle",
+            "value_1core": round(cfg.n_sites / per1 / 1e6, 4), "host": cpu_info(),
+            "sample": f"{cfg.nx}x{cfg.ny}x{cfg.nz} box of the same workload ({cfg.name}: sphere density, "
+                      f"charges, salt, field as in the full box), FP64, Poisson CG to {cfg.poisson_tol_oracle:g}; "
+                      f"{steps} timed step(s) with {all_threads} OpenMP threads and {steps1} with 1, each after "
+                      f"set-up and one untimed step"}
 
 
 def run_batched(count, steps, cycles, seed=4):
@@ -425,34 +477,35 @@ def run_adjoint(n=96, steps=500, every=50, fd=True):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="walls_interface")
-    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="colloids")
+    ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--kernel-steps", type=int, default=20,
+                    help="steps after the timed region with an event pair around every kernel launch")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run used for the FP32/FP64 speedup")
+    ap.add_argument("--no-error", action="store_true", help="skip the FP32/FP64 error against the oracle")
+    ap.add_argument("--error-n", type=int, default=48, help="box of the error check (same sphere density)")
+    ap.add_argument("--error-steps", type=int, default=20)
+    ap.add_argument("--no-secondary", action="store_true", help="skip the walls/interface 128^3 legs")
     ap.add_argument("--no-moment-state", action="store_true", help="skip the tau = 1 moment-state run")
     ap.add_argument("--no-fft", action="store_true", help="skip the lagged Fourier Poisson comparison")
     ap.add_argument("--fft-n", type=int, default=128)
     ap.add_argument("--fft-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-n", type=int, default=64, help="box of the CPU sample (same sphere density)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-serial replica sweep")
     ap.add_argument("--batched-replicas", type=int, default=64)
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--batched-cycles", type=int, default=4)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode leg")
-    ap.add_argument("--detail-steps", type=int, default=20,
-                    help="steps after the timed region with per-smoothing-pass events")
-    ap.add_argument("--class-steps", type=int, default=50,
-                    help="steps after the timed region with an event pair per kernel class")
     ap.add_argument("--autotune", type=int, default=0,
                     help="after the warm-up, let the library pick the V-cycle shape (trial steps per candidate)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size three times (byte-counter scale)")
     args = ap.parse_args()
-    if args.class_steps < 1:
-        raise SystemExit("--class-steps must be at least 1")
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "decomposition is a design note, not an implemented path.", file=sys.stderr)
@@ -465,63 +518,72 @@ def main():
 
     cfg, inp = build_workload(args.workload, args.precision, args.n)
     log(f"gpu {args.precision}: {cfg.name}, {args.warmup} warm-up + {args.steps} timed steps")
-    dt, timing, ob0, ob1, tuned = run_gpu(cfg, inp, args.steps, args.warmup, args.detail_steps, args.autotune,
-                                          args.class_steps)
+    dt, kt, ob0, ob1, tuned = run_gpu(cfg, inp, args.steps, args.warmup, args.kernel_steps, args.autotune)
     if tuned:
         log(f"autotuned V-cycle: {tuned}")
     log(f"gpu {args.precision}: {1e3 * dt / args.steps:.3f} ms/step")
     N = cfg.n_sites
     mlups = N * args.steps / dt / 1e6
     s = 4 if args.precision == "fp32" else 8
-
-    # Dominant kernel by device time per step.  The lattice smoothing pass is timed per
-    # launch in the detail phase after the timed region (events between its short
-    # launches would distort the step time); the others over the timed region.
+    has_particles = inp.particles is not None and len(inp.particles) > 0
+    mask = 1 if (has_particles or cfg.walls_z) else 0
     tau_one = cfg.tau == 1.0
-    steps_of = {"fused": args.class_steps, "force": args.class_steps, "moments": args.class_steps,
-                "smooth": args.detail_steps}
-    cands = {k: timing[k] for k in steps_of if timing[k][1] and steps_of[k]}
-    per_step = {k: cands[k][0] / steps_of[k] for k in cands}
-    dom = max(per_step, key=per_step.get)
 
-    def rate(kernel):
-        ms, count = timing[kernel]
-        avg_s = ms / 1e3 / max(count, 1)
-        b = algorithmic_bytes(kernel, s, tau_one)
-        return b, avg_s, b * N / avg_s / 1e9
-
-    bpsite, avg_s, achieved = rate(dom)
-    kernel_table = {}
-    for k in ("moments", "poisson", "iter", "smooth", "force", "fused", "particle"):
-        tms, cnt = timing[k]
-        row = {"ms_total": round(tms, 3), "launches": int(cnt),
-               "us_per_launch": round(1e3 * tms / cnt, 3) if cnt else None}
-        if k in ("fused", "force", "moments", "smooth") and cnt:
-            b = algorithmic_bytes(k, s, tau_one)
-            row["bytes_per_site"] = b
-            row["GBps"] = round(b * N / (tms / 1e3 / cnt) / 1e9, 1)
-        kernel_table[k] = row
-    sweeps = (ob1["poisson_total"] - ob0["poisson_total"]) / args.steps
-
+    # the dominant kernel: largest device time per step among all kernels of the step
+    table = kernel_table(kt, args.kernel_steps, N, s, tau_one, mask)
+    dom = max(table, key=lambda k: table[k]["us_per_step"])
+    ms_dom, cnt_dom = kt[dom]
+    avg_s = ms_dom / 1e3 / cnt_dom
+    bpsite = algorithmic_bytes(dom, s, tau_one, mask)
+    achieved = bpsite * N / avg_s / 1e9
     if args.copy_calibration_mib:
         copy_calibration(args.copy_calibration_mib)
     traffic, traffic_src = measured_traffic(dom, args.workload, args.n, args.precision)
-    f_b, f_avg, f_ach = rate("fused")
-    f_traffic, f_src = measured_traffic("fused", args.workload, args.n, args.precision)
+
+    # executed lattice sweeps per step (two colour passes each) and the whole step's rate
+    passes = sum(kt[k][1] for k in ("k_sor", "k_sor_black_from", "k_mg_prolong_red_fine") if k in kt)
+    sweeps = passes / 2 / args.kernel_steps if args.kernel_steps else None
+    cycles = (ob1["poisson_total"] - ob0["poisson_total"]) / args.steps
+    step_b = step_bytes(s, mask) + (sweeps or 0.0) * sweep_bytes(s)
+    step_gbs = step_b * N * args.steps / dt / 1e9
+
+    drift = None
+    if has_particles:
+        d = [ob1[f"drift_{c}"] - ob0[f"drift_{c}"] for c in "xyz"]
+        v = [x / args.steps for x in d]
+        E = cfg.E_ext
+        drift = {"particles": len(inp.particles), "mean_displacement_over_timed_steps": d,
+                 "mean_velocity": v, "steps_since_init_at_end": ob1["steps"],
+                 "mean_displacement_since_init": [ob1[f"drift_{c}"] for c in "xyz"],
+                 "mobility_along_field": v[0] / E[0] if E[0] else None}
 
     fp64 = None
-    fp32_error = None
     if not args.no_fp64 and args.precision == "fp32":
         cfg64, inp64 = build_workload(args.workload, "fp64", args.n)
+        steps64 = max(10, args.steps // 2)
         log("gpu fp64 run for the FP32/FP64 speedup")
-        dt64, _, _, _, _ = run_gpu(cfg64, inp64, max(10, args.steps // 2), args.warmup, detail_steps=0, class_steps=0)
-        fp64 = N * max(10, args.steps // 2) / dt64 / 1e6
-        log(f"gpu fp64: {1e3 * dt64 / max(10, args.steps // 2):.3f} ms/step")
-        fp32_error = precision_error(args.workload, args.n, 50)
+        dt64, _, _, _, _ = run_gpu(cfg64, inp64, steps64, args.warmup, kernel_steps=0)
+        fp64 = N * steps64 / dt64 / 1e6
+        log(f"gpu fp64: {1e3 * dt64 / steps64:.3f} ms/step")
+
+    error = None
+    if not args.no_error and args.workload == "colloids":
+        # the same workload in a smaller box with the same sphere density, against the oracle
+        count = max(1, round(200 * (args.error_n / 256.0) ** 3))
+        cfg_e, inp_e = build_workload("colloids", "fp32", args.error_n, count=count)
+        log(f"error check: {cfg_e.name}, {args.error_steps} steps against the oracle")
+        error = precision_error_vs_oracle(cfg_e, inp_e, args.error_steps)
+
+    secondary = None
+    if not args.no_secondary:
+        secondary = {"walls_interface_128_fp32": run_secondary("walls_interface", "fp32", 128, 100, 10),
+                     "walls_interface_128_fp64": run_secondary("walls_interface", "fp64", 128, 50, 10)}
+        secondary["walls_interface_128_fp32_fp64_speedup"] = round(
+            secondary["walls_interface_128_fp32"]["mlups"] / secondary["walls_interface_128_fp64"]["mlups"], 3)
 
     moment = None
-    if not args.no_moment_state and cfg.tau == 1.0 and not S_has_particles(inp):
-        moment = run_moment_state(args.workload, args.precision, args.n, args.steps, args.warmup, mlups)
+    if not args.no_moment_state:
+        moment = run_moment_state("walls_interface", "fp32", 128, 100, 10)
 
     fft = None
     if not args.no_fft:
@@ -537,7 +599,12 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(cfg, inp, args.cpu_seconds)
+        if args.workload == "colloids":
+            count = max(1, round(200 * (args.cpu_n / 256.0) ** 3))
+            cfg_c, inp_c = build_workload("colloids", "fp64", args.cpu_n, count=count)
+        else:
+            cfg_c, inp_c = build_workload(args.workload, "fp64", args.cpu_n)
+        cpu = cpu_baseline(cfg_c, inp_c, args.cpu_seconds)
 
     out = {
         "metric": METRIC,
@@ -553,33 +620,32 @@ def main():
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz}", "sites": N,
-                   "precision": args.precision, "poisson_tol": cfg.poisson_tol,
+                   "particles": len(inp.particles) if has_particles else 0, "precision": args.precision,
+                   "field": list(cfg.E_ext), "poisson_tol": cfg.poisson_tol,
                    "poisson_solver": "multigrid" if ob1["poisson_mg_levels"] else "sor",
-                   "poisson_iterations_per_step": round(sweeps, 2),
+                   "poisson_v_cycles_per_step": round(cycles, 2),
                    "poisson_start_residual": ob1["poisson_rel0"], "multigrid_autotune": tuned},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": round(traffic) if traffic else None, "traffic_unit": "bytes per launch",
                      "traffic_bytes_per_site": round(traffic / N, 1) if traffic else None,
                      "traffic_source": os.path.relpath(traffic_src, ROOT) if traffic else traffic_src,
-                     "bytes_per_site": bpsite, "us_per_launch": round(avg_s * 1e6, 3),
-                     "timed_over": f"{args.class_steps} steps after the timed region, an event pair per kernel class"
-                     if dom != "smooth" else
-                     f"{args.detail_steps} steps after those, an event pair per group of back-to-back lattice passes"},
-        "roofline_fused": {"kernel": "fused", "achieved": round(f_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(f_ach / HBM_PEAK_GBS, 4), "bytes_per_site": f_b,
-                           "us_per_launch": round(f_avg * 1e6, 3),
-                           "traffic": round(f_traffic) if f_traffic else None,
-                           "traffic_source": os.path.relpath(f_src, ROOT) if f_traffic else f_src},
-        "device_us_per_step": {k: round(1e3 * v, 1) for k, v in per_step.items()},
-        "step_bytes_per_site": step_bytes(s),
-        "step_effective_GBps": round(step_bytes(s) * N * args.steps / dt / 1e9, 1),
-        "kernels": kernel_table,
-        "moment_state": moment,
-        "lagged_fourier_poisson": fft,
+                     "algorithmic_bytes_per_site": bpsite, "us_per_launch": round(avg_s * 1e6, 3),
+                     "launches_per_step": round(cnt_dom / args.kernel_steps, 2),
+                     "timed_over": f"{args.kernel_steps} steps after the timed region, an event pair per launch"},
+        "roofline_step": {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(step_gbs / HBM_PEAK_GBS, 4), "bytes_per_site_update": round(step_b, 1),
+                          "lattice_sweeps_per_step": round(sweeps, 2) if sweeps is not None else None,
+                          "definition": "(populations, ions and potential once each way, solid mask, and 24 B "
+                                        "(FP32) per executed lattice sweep of the Poisson solve) x MLUPS"},
+        "kernels": table,
+        "electrophoretic_drift": drift,
         "fp64_mlups": round(fp64, 2) if fp64 else None,
         "fp32_fp64_speedup": round(mlups / fp64, 3) if fp64 else None,
-        "fp32_error_vs_fp64": fp32_error,
+        "precision_error_vs_oracle": error,
+        "secondary": secondary,
+        "moment_state": moment,
+        "lagged_fourier_poisson": fft,
         "batched": batched,
         "adjoint": adjoint,
         "cpu_baseline": cpu,

@@ -97,6 +97,13 @@ typedef struct ek_params {
                                    values per site instead of 38 cross HBM.  Requires tau = 1 and no
                                    particles; not with ek_forward_ckpt / ek_adjoint or batches.
                                    ek_get_populations reconstructs the populations.  0: stored populations */
+    int32_t sweep_band;         /* workgroup order of the lattice stencil sweeps (force and fused passes): each
+                                   of the 8 XCDs sweeps its eighth of the z-planes in bands of sweep_band
+                                   consecutive workgroups (256 sites each) of a plane, through every plane of
+                                   its slab before the next band, so that the stencil's neighbour planes stay
+                                   in the XCD's L2.  0: bands of four x-rows; -1: whole planes in turn.  Used
+                                   when nx*ny is a multiple of 256, nz of 8 and the band divides a plane;
+                                   otherwise whole planes.  Results do not depend on it (bit for bit) */
 } ek_params;
 
 typedef struct ek_particle {
@@ -137,10 +144,39 @@ typedef struct ek_obs {
                             pair per group of back-to-back passes, count = passes */
 #define EK_T_COUNT 7
 
+/* Single kernels timed at timing level 3 (ek_kernel_name gives each one's name). */
+#define EK_K_MOMENTS 0
+#define EK_K_VIRTUAL 1
+#define EK_K_SOURCE_MEAN 2
+#define EK_K_EXTRAPOLATE 3
+#define EK_K_RESIDUAL 4
+#define EK_K_REDUCE 5
+#define EK_K_COARSEN 6           /* coarse-grid face coefficients, every level */
+#define EK_K_SOR 7               /* red-black colour pass on the lattice */
+#define EK_K_SOR_BLACK_FROM 8    /* black pass after the fused interpolation + red pass */
+#define EK_K_RESTRICT_FINE 9
+#define EK_K_RESTRICT 10
+#define EK_K_SMOOTH 11           /* colour pass on a launched coarse grid */
+#define EK_K_TAIL 12             /* single-workgroup solve of the two smallest grids */
+#define EK_K_PROLONG_RED_FINE 13
+#define EK_K_PROLONG_FINE 14
+#define EK_K_PROLONG 15
+#define EK_K_FINALIZE 16
+#define EK_K_FORCE 17
+#define EK_K_FUSED 18
+#define EK_K_PARTICLE 19         /* particle forces and integration */
+#define EK_K_LAGGED 20           /* a whole lagged Fourier solve (right-hand side, transforms, division) */
+#define EK_K_COUNT 21
+
 typedef struct ek_timing {
     double ms[EK_T_COUNT];    /* summed device time per class (HIP events) */
     int64_t count[EK_T_COUNT];/* launches (or solves for EK_T_POISSON) per class */
+    double kernel_ms[EK_K_COUNT];      /* timing level 3: summed device time per kernel */
+    int64_t kernel_count[EK_K_COUNT];  /* timing level 3: launches per kernel */
 } ek_timing;
+
+/* Name of kernel id k (EK_K_*), "" for other k.  Host-only. */
+const char* ek_kernel_name(int32_t k);
 
 /* Field ids for ek_get_field (one double per site, x fastest). */
 #define EK_F_RHO_A 0
@@ -158,6 +194,11 @@ typedef struct ek_timing {
 #define EK_F_EX 12    /* field E = -grad phi + E_ext of the current potential */
 #define EK_F_EY 13
 #define EK_F_EZ 14
+
+/* Minimum-image separation along a periodic axis of n sites (the particle geometry's
+   helper): d minus the whole periods n that bring it into [-n/2, n/2], taken off at once,
+   so that a non-finite d gives NaN.  Host-only, needs no GPU; NaN for n <= 0. */
+double ek_min_image(double d, int32_t n);
 
 /* D3Q19 velocity set used by ek_get_populations: c[19][3] and weights w[19]
    (Sec. II A, weights 1/3, 1/18, 1/36).  Returns 19. */
@@ -261,7 +302,8 @@ ek_status ek_device_bytes(const struct ek_ctx* ctx, size_t* bytes);
    2 classes plus the lattice-level red-black passes (EK_T_SMOOTH, one event pair per
    group of back-to-back passes; it adds events between small kernels and launches
    the multigrid cycle without its graph, so use it for per-launch figures, not for
-   step rates).
+   step rates), 3 an event pair around every kernel launch of a step (EK_K_*, in
+   kernel_ms / kernel_count; classes are not timed then; the cycle runs without its graph).
    Any call clears the accumulated times. */
 ek_status ek_set_timing(struct ek_ctx* ctx, int32_t enable);
 

@@ -13,6 +13,7 @@
 #include <hipfft/hipfft.h>
 
 #include "ek.h"
+#include "ek_device.h"
 #include "ek_internal.h"
 #include "ek_lattice.h"
 
@@ -112,6 +113,7 @@ struct ek_ctx {
     bool vc_split = false;  // layout the captured V-cycle graph works on
     int kring[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // V-cycles of the last own multigrid solves
     int kpos = 0;
+    int kcount = 0;  // entries of kring recorded (at most 8)
     void* tune_buf = nullptr;  // state copy of the autotuner (held only while it runs)
     // tau = 1 moment state instead of populations (ek_params.moment_state): two buffers of
     // 8 N values (step parity as the populations), the FP64 initial densities the first
@@ -133,6 +135,8 @@ struct ek_ctx {
     std::vector<hipEvent_t> pool;
     double tms[EK_T_COUNT] = {0};
     long long tcnt[EK_T_COUNT] = {0};
+    double kms[EK_K_COUNT] = {0};      // timing level 3: per kernel
+    long long kcnt[EK_K_COUNT] = {0};
     bool in_batch = false;  // owned by a batch: stepping goes through the batch
     // reverse mode (periodic FP64 contexts): checkpoints of the last checkpointed forward
     // run and the adjoint fields
@@ -145,7 +149,7 @@ struct ek_ctx {
         std::vector<int> ck_ws;          // adaptive warm start: order, steps since the probe
         std::vector<double> ck_rel0;     // its last start residuals of orders 2 and 3
         std::vector<int> ck_kring;       // cycles the last solves needed (8 per checkpoint) and
-        std::vector<int> ck_kpos;        // the next record's place
+        std::vector<int> ck_kpos;        // the next record's place + 8 x the records held
         double* seg = nullptr;      // K x kSegVals N doubles: the states of one segment
         int seg_cap = 0;
         double* buf = nullptr;      // adjoint fields (kAdjVals N doubles)
@@ -206,6 +210,8 @@ static void dfree(ek_ctx* c, void* ptr, size_t bytes) {
 // ------------------------------------------------------------------------------------
 // Timing (HIP events on the context's stream)
 // ------------------------------------------------------------------------------------
+constexpr int kKBase = 100;  // Timer classes from here on time single kernels (EK_K_*)
+
 static hipEvent_t get_event(ek_ctx* c) {
     if (!c->pool.empty()) {
         hipEvent_t e = c->pool.back();
@@ -223,8 +229,13 @@ static void resolve_timing(ek_ctx* c) {
     for (auto& r : c->recs) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, r.a, r.b);
-        c->tms[r.cls] += ms;
-        c->tcnt[r.cls] += r.count;
+        if (r.cls >= kKBase) {
+            c->kms[r.cls - kKBase] += ms;
+            c->kcnt[r.cls - kKBase] += r.count;
+        } else {
+            c->tms[r.cls] += ms;
+            c->tcnt[r.cls] += r.count;
+        }
         c->pool.push_back(r.a);
         c->pool.push_back(r.b);
     }
@@ -236,8 +247,15 @@ struct Timer {
     int cls, count;
     hipEvent_t a{};
     bool on;
+    // kernel classes at timing levels 1 and 2 (EK_T_SMOOTH only at 2); single kernels
+    // (ids kKBase + EK_K_*) only at level 3
+    static bool active(const ek_ctx* c, int cls) {
+        if (cls >= kKBase) return c->timing == 3;
+        if (c->timing == 3) return false;
+        return c->timing >= (cls == EK_T_SMOOTH ? 2 : 1);
+    }
     Timer(ek_ctx* c_, int cls_, int count_ = 1)
-        : c(c_), cls(cls_), count(count_), on(c_->timing >= (cls_ == EK_T_SMOOTH ? 2 : 1)) {
+        : c(c_), cls(cls_), count(count_), on(active(c_, cls_)) {
         if (on) {
             a = get_event(c);
             (void)hipEventRecord(a, c->st);
@@ -251,6 +269,9 @@ struct Timer {
         if (c->recs.size() > 4096) resolve_timing(c);
     }
 };
+
+// One kernel launch timed at timing level 3.
+#define EK_KT(id) Timer kt_##id##__(c, kKBase + (id))
 
 // ------------------------------------------------------------------------------------
 // Fields view for one precision
@@ -291,12 +312,7 @@ static Fields<T> fields(ek_ctx* c) {
 // Geometry (host, at set-up): wall layers, particle marking, solid fraction by sub-cell
 // counting, charge spreading, boundary lists (Sec. II E).
 // ------------------------------------------------------------------------------------
-static double wrap_dist(double d, int n) {
-    const double L = (double)n;
-    while (d > 0.5 * L) d -= L;
-    while (d < -0.5 * L) d += L;
-    return d;
-}
+static double wrap_dist(double d, int n) { return min_image(d, n); }
 
 struct HostGeom {
     std::vector<uint8_t> flags;
@@ -428,28 +444,37 @@ static ek_status build_geometry(ek_ctx* c, const ek_particle* parts, int np, Hos
 // ------------------------------------------------------------------------------------
 // Poisson solve with convergence control
 // ------------------------------------------------------------------------------------
-// The fewest V-cycles any of the last eight own multigrid solves needed (0 until eight are
-// recorded, or after a change of the cycle shape).
+// The fewest V-cycles any of the last (up to eight) own multigrid solves needed; 0 when none
+// is recorded (at set-up, or after a change of the cycle shape).
 static int cycles_floor(const ek_ctx* c) {
+    if (c->kcount == 0) return 0;
     int m = c->kring[0];
-    for (int k = 1; k < 8; ++k) m = std::min(m, c->kring[k]);
+    for (int k = 1; k < c->kcount; ++k) m = std::min(m, c->kring[k]);
     return m;
 }
 static void cycles_record(ek_ctx* c, int k) {
     c->kring[c->kpos] = k;
     c->kpos = (c->kpos + 1) % 8;
+    c->kcount = std::min(c->kcount + 1, 8);
 }
 static void cycles_forget(ek_ctx* c) {
     for (int k = 0; k < 8; ++k) c->kring[k] = 0;
     c->kpos = 0;
+    c->kcount = 0;
 }
 
 // F in site order (split false) and pack: the kernel also fills c->phis, c->qs.
 template <typename T>
 static ek_status check_residual(ek_ctx* c, const Fields<T>& F, bool split, bool pack, double& rr, double& ss) {
     const unsigned nres = residual_blocks(c->N);
-    launch_residual<T>(c->S, F, nres, split, pack ? c->phis : nullptr, pack ? (T*)c->qs : nullptr, c->st);
-    launch_reduce(c->red, nres, 3, nullptr, c->scal + 1, c->st);
+    {
+        EK_KT(EK_K_RESIDUAL);
+        launch_residual<T>(c->S, F, nres, split, pack ? c->phis : nullptr, pack ? (T*)c->qs : nullptr, c->st);
+    }
+    {
+        EK_KT(EK_K_REDUCE);
+        launch_reduce(c->red, nres, 3, nullptr, c->scal + 1, c->st);
+    }
     EK_HIP(hipMemcpyAsync(c->hscal, c->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, c->st));
     EK_HIP(hipStreamSynchronize(c->st));
     rr = c->hscal[1];
@@ -471,10 +496,13 @@ static void vcycle(ek_ctx* c, const Fields<T>& F, bool split) {
     // restriction into a launched coarse grid)
     auto smooth = [&](int g, int first = 0) {
         for (int color = first; color < 2; ++color) {
-            if (g == 0)
+            if (g == 0) {
+                EK_KT(EK_K_SOR);
                 launch_sor<T>(c->S, F, color, c->mg_omega, split, c->st);
-            else
+            } else {
+                EK_KT(EK_K_SMOOTH);
                 launch_mg_smooth(c->mg[g - 1], color, c->mg_omega, c->st);
+            }
         }
     };
     // the lattice sweeps of one leg run back to back: one event pair times the group
@@ -492,28 +520,43 @@ static void vcycle(ek_ctx* c, const Fields<T>& F, bool split) {
         else
             for (int s = 0; s < pre; ++s) smooth(g, s == 0 && red > 0.0 ? 1 : 0);
         const double r = g + 1 <= last_gpu ? red : 0.0;
-        if (g == 0)
+        if (g == 0) {
+            EK_KT(EK_K_RESTRICT_FINE);
             launch_mg_restrict_fine<T>(c->S, F, c->mg[0], split, r, c->st);
-        else
+        } else {
+            EK_KT(EK_K_RESTRICT);
             launch_mg_restrict(c->mg[g - 1], c->mg[g], r, c->st);
+        }
     }
-    launch_mg_tail(tail_mid ? c->mg[nl - 2] : c->mg[nl - 1], c->mg[nl - 1], tail_mid, c->mg_coarsest,
-                   c->mg_coarse_omega, c->mg_tail_pre, c->mg_tail_post, c->mg_omega, c->st);
+    {
+        EK_KT(EK_K_TAIL);
+        launch_mg_tail(tail_mid ? c->mg[nl - 2] : c->mg[nl - 1], c->mg[nl - 1], tail_mid, c->mg_coarsest,
+                       c->mg_coarse_omega, c->mg_tail_pre, c->mg_tail_post, c->mg_omega, c->st);
+    }
     for (int g = last_gpu; g >= 0; --g) {  // upward leg: interpolate from grid g+1, smooth grid g
         const int post = g == 0 ? c->mg_fine_post : c->mg_post;
         if (g == 0 && split && post >= 1) {
             // colour-split lattice: the interpolation takes the first red pass, and the black
             // pass reads the interpolated black values from c->blk
-            launch_mg_prolong_red_fine<T>(c->S, F, c->mg[0], c->mg_omega, c->blk, c->st);
+            {
+                EK_KT(EK_K_PROLONG_RED_FINE);
+                launch_mg_prolong_red_fine<T>(c->S, F, c->mg[0], c->mg_omega, c->blk, c->st);
+            }
             Timer tm(c, EK_T_SMOOTH, 2 * post - 1);
-            launch_sor_black_from<T>(c->S, F, c->mg_omega, c->blk, c->st);
+            {
+                EK_KT(EK_K_SOR_BLACK_FROM);
+                launch_sor_black_from<T>(c->S, F, c->mg_omega, c->blk, c->st);
+            }
             for (int s = 1; s < post; ++s) smooth(0);
             continue;
         }
-        if (g == 0)
+        if (g == 0) {
+            EK_KT(EK_K_PROLONG_FINE);
             launch_mg_prolong_fine<T>(c->S, F, c->mg[0], split, c->st);
-        else
+        } else {
+            EK_KT(EK_K_PROLONG);
             launch_mg_prolong(c->mg[g], c->mg[g - 1], c->st);
+        }
         if (g == 0)
             smooth_lattice(post);
         else
@@ -564,8 +607,14 @@ static ek_status run_cycles(ek_ctx* c, Fields<T>& F, bool split, int k) {
 // Coarse-level face coefficients for the current permittivity.
 template <typename T>
 static void mg_build(ek_ctx* c, const Fields<T>& F) {
-    launch_mg_coarsen_fine<T>(c->S, F, c->mg[0], c->st);
-    for (size_t l = 1; l < c->mg.size(); ++l) launch_mg_coarsen(c->mg[l - 1], c->mg[l], c->st);
+    {
+        EK_KT(EK_K_COARSEN);
+        launch_mg_coarsen_fine<T>(c->S, F, c->mg[0], c->st);
+    }
+    for (size_t l = 1; l < c->mg.size(); ++l) {
+        EK_KT(EK_K_COARSEN);
+        launch_mg_coarsen(c->mg[l - 1], c->mg[l], c->st);
+    }
 }
 
 // Requires q, eps and the source mean of the current state on the device.
@@ -599,8 +648,14 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
     bool built = false;
     if (k0 > 0) {
         const unsigned nres = residual_blocks(c->N);
-        launch_residual<T>(c->S, F, nres, false, split ? c->phis : nullptr, split ? (T*)c->qs : nullptr, c->st);
-        launch_reduce(c->red, nres, 3, nullptr, c->scal + 24, c->st);
+        {
+            EK_KT(EK_K_RESIDUAL);
+            launch_residual<T>(c->S, F, nres, false, split ? c->phis : nullptr, split ? (T*)c->qs : nullptr, c->st);
+        }
+        {
+            EK_KT(EK_K_REDUCE);
+            launch_reduce(c->red, nres, 3, nullptr, c->scal + 24, c->st);
+        }
         mg_build<T>(c, F);
         built = true;
         {
@@ -609,8 +664,14 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
         }
         EK_HIP(hipGetLastError());
         it = k0;
-        launch_residual<T>(c->S, FS, nres, split, nullptr, nullptr, c->st);
-        launch_reduce(c->red, nres, 3, nullptr, c->scal + 1, c->st);
+        {
+            EK_KT(EK_K_RESIDUAL);
+            launch_residual<T>(c->S, FS, nres, split, nullptr, nullptr, c->st);
+        }
+        {
+            EK_KT(EK_K_REDUCE);
+            launch_reduce(c->red, nres, 3, nullptr, c->scal + 1, c->st);
+        }
         EK_HIP(hipMemcpyAsync(c->hscal, c->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, c->st));
         EK_HIP(hipMemcpyAsync(c->hscal + 24, c->scal + 24, 3 * sizeof(double), hipMemcpyDeviceToHost, c->st));
         EK_HIP(hipStreamSynchronize(c->st));
@@ -626,6 +687,7 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
     double rel = 0.0;
     int need = 0;  // cycles this solve needed (for the next solves' k0)
     if (!(ss > 0.0)) {
+        EK_KT(EK_K_FINALIZE);
         launch_phi_finalize<T>(c->S, F, 1, nullptr, c->st);
     } else {
         const double target = tol * std::sqrt(ss);
@@ -664,8 +726,10 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
                 Timer ts(c, EK_T_ITER, k);
                 Timer tm(c, EK_T_SMOOTH, c->S.ncolor * k);  // the k sweeps run back to back
                 for (int s = 0; s < k; ++s)
-                    for (int color = 0; color < c->S.ncolor; ++color)
+                    for (int color = 0; color < c->S.ncolor; ++color) {
+                        EK_KT(EK_K_SOR);
                         launch_sor<T>(c->S, F, color, c->omega, false, c->st);
+                    }
             }
             EK_HIP(hipGetLastError());
             it += k;
@@ -674,7 +738,10 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
             update_rate(r, rn, k);
             r = rn;
         }
-        launch_phi_finalize<T>(c->S, F, 0, split ? c->phis : nullptr, c->st);
+        {
+            EK_KT(EK_K_FINALIZE);
+            launch_phi_finalize<T>(c->S, F, 0, split ? c->phis : nullptr, c->st);
+        }
         rel = r / std::sqrt(ss);
         if (r > target) status = EK_ENOCONV;
         // cycles needed: the first count at which the solve's mean decay per cycle reaches
@@ -702,8 +769,15 @@ template <typename T>
 static void moments_pass(ek_ctx* c) {
     Timer tm(c, EK_T_MOMENTS);
     Fields<T> F = fields<T>(c);
-    launch_moments<T>(c->S, F, c->nblk, c->st);
-    launch_virtual<T>(c->S, F, c->st);
+    {
+        EK_KT(EK_K_MOMENTS);
+        launch_moments<T>(c->S, F, c->nblk, c->st);
+    }
+    {
+        EK_KT(EK_K_VIRTUAL);
+        launch_virtual<T>(c->S, F, c->st);
+    }
+    EK_KT(EK_K_SOURCE_MEAN);
     launch_source_mean(c->S, c->red, c->nblk, c->scal, c->st);
 }
 
@@ -714,19 +788,21 @@ static ek_status step_rest(ek_ctx* c) {
     Fields<T> F = fields<T>(c);
     {
         Timer tm(c, EK_T_FORCE);
+        EK_KT(EK_K_FORCE);
         launch_force<T>(c->S, F, c->st);
     }
     {
         Timer tm(c, EK_T_FUSED);
+        EK_KT(EK_K_FUSED);
         launch_fused<T>(c->S, F, c->st);
     }
     if (c->np > 0) {
         Timer tm(c, EK_T_PARTICLE);
-        launch_particle_sum<T>(c->S, F, c->np, c->plink_off, c->plink_idx, c->psite_off, c->psite_idx, c->pF,
-                               c->st);
-        launch_particle_move(c->S, c->np, c->px[c->pcur], c->pv[c->pcur], c->prad, c->pF, c->px[c->pcur ^ 1],
-                             c->pv[c->pcur ^ 1], c->p.particle_rho, c->p.k_hertz, c->p.eta, c->p.move_particles,
-                             c->st);
+        EK_KT(EK_K_PARTICLE);
+        launch_particle_step<T>(c->S, F, c->np, c->plink_off, c->plink_idx, c->psite_off, c->psite_idx,
+                                c->px[c->pcur], c->pv[c->pcur], c->prad, c->pF, c->px[c->pcur ^ 1],
+                                c->pv[c->pcur ^ 1], c->p.particle_rho, c->p.k_hertz, c->p.eta, c->p.move_particles,
+                                c->st);
         c->pcur ^= 1;
     }
     EK_HIP(hipGetLastError());
@@ -741,6 +817,7 @@ static ek_status step_rest(ek_ctx* c) {
 template <typename T>
 static ek_status lagged_fourier(ek_ctx* c) {
     Timer tm(c, EK_T_POISSON);
+    EK_KT(EK_K_LAGGED);
     launch_lag_rhs<T>(c->S, fields<T>(c), c->fft_rhs, c->st);
     if (hipfftExecD2Z(c->fft_fwd, c->fft_rhs, (hipfftDoubleComplex*)c->fft_spec) != HIPFFT_SUCCESS)
         return fail(c, EK_EHIP, "hipfftExecD2Z failed");
@@ -774,7 +851,10 @@ static ek_status step_impl(ek_ctx* c, int nsteps) {
                 probe = true;
             }
         }
-        launch_phi_extrapolate(c->S, c->phi, c->phi_prev, c->phi_prev2, order, c->st);
+        {
+            EK_KT(EK_K_EXTRAPOLATE);
+            launch_phi_extrapolate(c->S, c->phi, c->phi_prev, c->phi_prev2, order, c->st);
+        }
         ek_status ps = poisson_solve<T>(c, c->p.poisson_tol, c->p.poisson_maxit, nullptr, nullptr);
         if (c->phi_history == 0 && c->steps >= 2) {
             c->rel0_of[order] = c->last_rel0;
@@ -809,6 +889,8 @@ extern "C" int32_t ek_lattice(int32_t* cvec, double* w) {
     }
     return kQ;
 }
+
+extern "C" double ek_min_image(double d, int32_t n) { return n > 0 ? min_image(d, n) : NAN; }
 
 static double omega_for(const ek_params& p) {
     const double pi = 3.14159265358979323846;
@@ -1049,6 +1131,11 @@ extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const doub
     if (!(p->eps_a > 0.0) || !(p->eps_b > 0.0) || !(p->eps_p > 0.0)) return fail(c, EK_EINVAL, "permittivities must be positive");
     if ((p->dmu[0] != 0.0 || p->dmu[1] != 0.0) && p->drho_a == 0.0) return fail(c, EK_EINVAL, "drho_a must be non-zero with solvation");
     if (n_parts < 0 || (n_parts > 0 && !parts)) return fail(c, EK_EINVAL, "bad particle array");
+    for (int j = 0; j < n_parts; ++j) {
+        bool ok = std::isfinite(parts[j].radius) && parts[j].radius > 0.0 && std::isfinite(parts[j].charge);
+        for (int k = 0; k < 3; ++k) ok = ok && std::isfinite(parts[j].x[k]) && std::isfinite(parts[j].v[k]);
+        if (!ok) return fail(c, EK_EINVAL, "particle " + std::to_string(j) + ": non-finite position, velocity or charge, or radius <= 0");
+    }
     if (p->poisson_maxit < 0 || !(p->poisson_tol > 0.0)) return fail(c, EK_EINVAL, "poisson_tol must be > 0, maxit >= 0");
     if (p->phi_history < 0 || p->phi_history > 3) return fail(c, EK_EINVAL, "phi_history must be in 0..3");
     c->phi_history = p->phi_history;
@@ -1071,6 +1158,21 @@ extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const doub
     S.inv_ny = 1.0 / S.ny;
     S.inv_nxy = 1.0 / S.nxy;
     S.inv_hx = S.nx >= 2 ? 1.0 / (S.nx / 2) : 0.0;
+    // banded workgroup order of the stencil sweeps (see site_banded): default bands of four
+    // x-rows, when every z-plane is a whole number of workgroups and nz splits over the 8 XCDs
+    if (p->sweep_band < -1) return fail(c, EK_EINVAL, "sweep_band must be >= -1");
+    S.band = 0;
+    S.plane_blocks = 0;
+    S.slab_planes = 0;
+    if (p->sweep_band != -1 && S.nxy % kBlock == 0 && S.nz % 8 == 0) {
+        const int pb = S.nxy / kBlock;
+        const int B = p->sweep_band > 0 ? p->sweep_band : std::max(1, 4 * S.nx / kBlock);
+        if (pb % B == 0) {
+            S.band = B;
+            S.plane_blocks = pb;
+            S.slab_planes = S.nz / 8;
+        }
+    }
     S.tau = p->tau;
     S.inv_tau = 1.0 / p->tau;
     S.G = p->G;
@@ -1097,6 +1199,11 @@ extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const doub
     if (p->poisson_solver < 0 || p->poisson_solver > 3) return fail(c, EK_EINVAL, "unknown poisson_solver");
     if (p->poisson_solver == EK_POISSON_FFT && p->walls_z)
         return fail(c, EK_EINVAL, "the lagged Fourier scheme needs a periodic lattice");
+    // The lagged scheme is a fixed-point iteration with one sweep per step; at the particle
+    // surfaces (eps_p / eps_f = 1/8 in the paper's colloids) its error amplification exceeds
+    // one and the potential diverges (on the CPU oracle as well), so it is not offered there.
+    if (p->poisson_solver == EK_POISSON_FFT && n_parts > 0)
+        return fail(c, EK_EINVAL, "the lagged Fourier scheme diverges at resolved particles; use EK_POISSON_MG or SOR");
     c->fft = p->poisson_solver == EK_POISSON_FFT;
     if (p->poisson_solver != EK_POISSON_SOR) {
         // Coarsen by two while every axis of the current level divides by 4 (so that the
@@ -1240,7 +1347,7 @@ static ek_status save_ck(ek_ctx* c, int slot) {
     c->adj.ck_rel0[2 * slot] = c->rel0_of[2];
     c->adj.ck_rel0[2 * slot + 1] = c->rel0_of[3];
     for (int k = 0; k < 8; ++k) c->adj.ck_kring[8 * slot + k] = c->kring[k];
-    c->adj.ck_kpos[slot] = c->kpos;
+    c->adj.ck_kpos[slot] = c->kpos + 8 * c->kcount;
     return EK_OK;
 }
 
@@ -1262,7 +1369,8 @@ static ek_status load_ck(ek_ctx* c, int slot) {
     c->rel0_of[2] = c->adj.ck_rel0[2 * slot];
     c->rel0_of[3] = c->adj.ck_rel0[2 * slot + 1];
     for (int k = 0; k < 8; ++k) c->kring[k] = c->adj.ck_kring[8 * slot + k];
-    c->kpos = c->adj.ck_kpos[slot];
+    c->kpos = c->adj.ck_kpos[slot] % 8;
+    c->kcount = c->adj.ck_kpos[slot] / 8;
     return EK_OK;
 }
 
@@ -1504,7 +1612,7 @@ struct HostState {
     int cur, pcur, ws_order, ws_since, last_iters, ms_first;
     double rate, rel0_of[4], last_rel, last_mean, last_rel0;
     long long steps, ptotal;
-    int kring[8], kpos;
+    int kring[8], kpos, kcount;
 };
 }  // namespace
 
@@ -1516,7 +1624,7 @@ static ek_status tune_copy(ek_ctx* c, bool save, HostState& h) {
     if (save) {
         h = HostState{c->cur, c->pcur, c->ws_order, c->ws_since, c->last_iters, c->ms_first ? 1 : 0, c->rate,
                       {0, 0, 0, 0}, c->last_rel, c->last_mean, c->last_rel0, c->steps, c->ptotal,
-                      {0, 0, 0, 0, 0, 0, 0, 0}, c->kpos};
+                      {0, 0, 0, 0, 0, 0, 0, 0}, c->kpos, c->kcount};
         for (int k = 0; k < 4; ++k) h.rel0_of[k] = c->rel0_of[k];
         for (int k = 0; k < 8; ++k) h.kring[k] = c->kring[k];
     } else {
@@ -1535,6 +1643,7 @@ static ek_status tune_copy(ek_ctx* c, bool save, HostState& h) {
         c->ptotal = h.ptotal;
         for (int k = 0; k < 8; ++k) c->kring[k] = h.kring[k];
         c->kpos = h.kpos;
+        c->kcount = h.kcount;
     }
     // populations of the current step, or the moment state (8 N values, in the first slot)
     void* dev[] = {c->moment_state ? c->ms[c->cur] : c->f[c->cur][0], c->moment_state ? nullptr : c->f[c->cur][1],
@@ -1577,18 +1686,27 @@ static ek_status autotune_impl(ek_ctx* c, int trial, int* best, double* ms_out) 
     // Two rounds over the candidates, each candidate's best round counts (clock and
     // thermal drift during the sweep hit every candidate alike).  Each trial: the saved
     // state, one untimed step that captures the cycle graph and estimates the cycle's
-    // convergence rate, the saved state again (keeping that rate), the timed steps.
+    // convergence rate, the saved state again (keeping that rate and the cycle count that
+    // step recorded, so the timed steps start from this shape's own cycle floor, not the
+    // one of the shape in place before the call), the timed steps.
     for (int round = 0; round < 2 && st == EK_OK; ++round)
         for (int k = 0; k < kNumCycleShapes && st == EK_OK; ++k) {
             apply_shape(c, kCycleShapes[k]);
             st = tune_copy(c, false, h);
             c->rate = -1.0;
+            cycles_forget(c);
             if (st == EK_OK) st = step_impl<T>(c, 1);
             if (st == EK_ENOCONV) st = EK_OK;
             const double rate = c->rate;
+            int kr[8];
+            for (int j = 0; j < 8; ++j) kr[j] = c->kring[j];
+            const int kp = c->kpos, kc = c->kcount;
             if (st == EK_OK) st = tune_copy(c, false, h);
             if (st != EK_OK) break;
             c->rate = rate;
+            for (int j = 0; j < 8; ++j) c->kring[j] = kr[j];
+            c->kpos = kp;
+            c->kcount = kc;
             (void)hipEventRecord(ev[0], c->st);
             st = step_impl<T>(c, trial);
             if (st == EK_ENOCONV) st = EK_OK;
@@ -1758,10 +1876,14 @@ extern "C" ek_status ek_device_bytes(const ek_ctx* c, size_t* bytes) {
 extern "C" ek_status ek_set_timing(ek_ctx* c, int32_t enable) {
     if (!c) return EK_EINVAL;
     resolve_timing(c);
-    c->timing = enable < 0 ? 0 : (enable > 2 ? 2 : enable);
+    c->timing = enable < 0 ? 0 : (enable > 3 ? 3 : enable);
     for (int k = 0; k < EK_T_COUNT; ++k) {
         c->tms[k] = 0.0;
         c->tcnt[k] = 0;
+    }
+    for (int k = 0; k < EK_K_COUNT; ++k) {
+        c->kms[k] = 0.0;
+        c->kcnt[k] = 0;
     }
     return EK_OK;
 }
@@ -1773,7 +1895,20 @@ extern "C" ek_status ek_get_timing(ek_ctx* c, ek_timing* out) {
         out->ms[k] = c->tms[k];
         out->count[k] = c->tcnt[k];
     }
+    for (int k = 0; k < EK_K_COUNT; ++k) {
+        out->kernel_ms[k] = c->kms[k];
+        out->kernel_count[k] = c->kcnt[k];
+    }
     return EK_OK;
+}
+
+extern "C" const char* ek_kernel_name(int32_t k) {
+    static const char* names[EK_K_COUNT] = {
+        "k_moments", "k_virtual", "k_source_mean", "k_phi_extrapolate", "k_residual", "k_reduce",
+        "k_mg_coarsen", "k_sor", "k_sor_black_from", "k_mg_restrict_fine", "k_mg_restrict", "k_mg_smooth",
+        "k_mg_tail", "k_mg_prolong_red_fine", "k_mg_prolong_fine", "k_mg_prolong", "k_phi_finalize", "k_force",
+        "k_fused", "k_particle_step", "lagged_fourier"};
+    return k >= 0 && k < EK_K_COUNT ? names[k] : "";
 }
 
 extern "C" ek_status ek_destroy(ek_ctx* c) {

@@ -17,6 +17,36 @@ __device__ __forceinline__ unsigned xcd_linear() {
     return lb * blockDim.x + threadIdx.x;
 }
 
+// The same XCD split for the stencil sweeps over the lattice, with the slab walked band by
+// band when S.band > 0: a band is S.band consecutive workgroups of one z-plane (a few x-rows),
+// taken in every plane of the slab before the next band starts.  The workgroups resident on
+// an XCD at any time then cover a few rows of many consecutive planes, so the z-neighbour
+// rows their stencils read were fetched by the workgroups just before them and still sit in
+// the XCD's L2.  In the plain order the resident workgroups cover whole planes, and at
+// 256 x 256 the neighbour planes of the stencil's arrays (256 KB per FP32 plane) exceed the
+// 4 MB L2.  Requires nz % 8 == 0 and whole planes of workgroups (checked by the host).
+__device__ __forceinline__ unsigned site_banded(const Scalars& S) {
+    const unsigned b = blockIdx.x;
+    const unsigned x8 = b & 7u, s = b >> 3;  // XCD and position in its sequence
+    if (S.band <= 0) return (x8 * (gridDim.x >> 3) + s) * blockDim.x + threadIdx.x;
+    const unsigned B = (unsigned)S.band, P = (unsigned)S.plane_blocks, nzs = (unsigned)S.slab_planes;
+    const unsigned per_band = nzs * B;
+    const unsigned band = s / per_band, rem = s - band * per_band;
+    const unsigned zz = rem / B, j = rem - zz * B;
+    const unsigned lb = (x8 * nzs + zz) * P + band * B + j;
+    return lb * blockDim.x + threadIdx.x;
+}
+
+// Minimum image of a separation along a periodic axis of length n: the whole periods that
+// stepping by n would remove are taken off at once, so the result equals the stepping loop
+// for every finite d and is NaN (not an endless loop) for a non-finite one.
+__host__ __device__ inline double min_image(double d, int n) {
+    const double L = (double)n;
+    if (d > 0.5 * L) d -= L * ceil((d - 0.5 * L) / L);
+    if (d < -0.5 * L) d += L * ceil((-0.5 * L - d) / L);
+    return d;
+}
+
 struct Nbr {
     int xm, xp, ym, yp, zm, zp;  // index offsets to the -1/+1 neighbour along each axis (periodic)
 };

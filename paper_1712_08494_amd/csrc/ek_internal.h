@@ -25,6 +25,10 @@ struct Scalars {
     unsigned ndomain; // sites in the Poisson domain
     int ncolor;       // colours of a lattice Gauss-Seidel sweep: 2, or 3 with an odd periodic y or z axis
     double inv_nx, inv_ny, inv_nxy, inv_hx;  // 1/nx, 1/ny, 1/(nx ny), 1/(nx/2): exact index division
+    // Banded workgroup order of the stencil sweeps (site_banded): workgroups of one z-plane
+    // (plane_blocks of them) are grouped in bands of `band`, and each XCD walks its slab of
+    // slab_planes planes band by band; band = 0 keeps the plain slab order.
+    int band, plane_blocks, slab_planes;
     double tau, inv_tau, G, rho0, D, beta;
     double kap_p, kap_m;   // s beta dmu+- / (2 drho_a)
     double G_p, G_m;       // s dmu+- / (drho_a c_s^2)
@@ -192,13 +196,13 @@ void launch_lag_table(double* tab, int nx, int ny, int nz, hipStream_t st);  // 
 void launch_lag_scale(double* spec, const double* tab, int nx, int ny, int nz, hipStream_t st);
 // populations of component c at time t of a moment-state context (FP64, 19 N, f not g)
 template <typename T> void launch_export_pop(const Scalars& S, const Fields<T>& F, int c, double* out, hipStream_t st);
+// one workgroup per particle: link momenta, q_c E over its sites, Hertz and lubrication
+// against every other particle, then symplectic Euler into xn, vn (pF receives the force)
 template <typename T>
-void launch_particle_sum(const Scalars& S, const Fields<T>& F, int np, const int32_t* link_off,
-                         const int32_t* link_idx, const int32_t* site_off, const int32_t* site_idx, double* pF,
-                         hipStream_t st);
-void launch_particle_move(const Scalars& S, int np, const double* x, const double* v, const double* r,
-                          const double* pF, double* xn, double* vn, double rho_p, double k_h, double eta, int move,
-                          hipStream_t st);
+void launch_particle_step(const Scalars& S, const Fields<T>& F, int np, const int32_t* link_off,
+                          const int32_t* link_idx, const int32_t* site_off, const int32_t* site_idx, const double* x,
+                          const double* v, const double* r, double* pF, double* xn, double* vn, double rho_p,
+                          double k_h, double eta, int move, hipStream_t st);
 template <typename T> void launch_observe(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
 template <typename T>
 void launch_init_pop_flags(const Scalars& S, T* f, const double* rho, double rref, const uint8_t* flags, hipStream_t st);

@@ -1796,7 +1796,7 @@ __device__ __forceinline__ void force_body(const Scalars& S, const Fields<T>& F,
 
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock, kForceOcc<T>) void k_force(Scalars S, Fields<T> F) {
-    force_body<T, G>(S, F, xcd_linear());
+    force_body<T, G>(S, F, site_banded(S));
 }
 
 template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hipStream_t st) {
@@ -1901,7 +1901,7 @@ __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F,
 
 template <typename T, int G, bool MS>
 __global__ __launch_bounds__(kBlock, kHotOcc<T>) void k_fused(Scalars S, Fields<T> F) {
-    fused_body<T, G, MS>(S, F, xcd_linear());
+    fused_body<T, G, MS>(S, F, site_banded(S));
 }
 
 template <typename T> void launch_fused(const Scalars& S, const Fields<T>& F, hipStream_t st) {
@@ -1920,69 +1920,39 @@ template <typename T> void launch_fused(const Scalars& S, const Fields<T>& F, hi
 }
 
 // ------------------------------------------------------------------------------------
-// Particles (Sec. II E): momentum from the particle's links plus q_c E over its sites,
-// one workgroup per particle, fixed-order sums.
+// Particles (Sec. II E), one workgroup per particle: the momentum handed over by the
+// particle's links, q_c E over its sites, the Hertz contact (+k_H delta^{3/2} n, repulsive)
+// and lubrication with every other particle, summed per thread and then in a fixed tree
+// order; then symplectic Euler (v, then x).  All read the positions and velocities of the
+// step's start and write the next buffers, so the particles are independent.
 // ------------------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_particle_sum(Scalars S, Fields<T> F, const int32_t* link_off,
-                                                         const int32_t* link_idx, const int32_t* site_off,
-                                                         const int32_t* site_idx, double* pF) {
-    const int p = blockIdx.x;
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int t = link_off[p] + threadIdx.x; t < link_off[p + 1]; t += blockDim.x) {
+__global__ __launch_bounds__(kBlock) void k_particle_step(Scalars S, Fields<T> F, int np, const int32_t* link_off,
+                                                          const int32_t* link_idx, const int32_t* site_off,
+                                                          const int32_t* site_idx, const double* __restrict__ x,
+                                                          const double* __restrict__ v, const double* __restrict__ rad,
+                                                          double* __restrict__ pF, double* __restrict__ xn,
+                                                          double* __restrict__ vn, double rho_p, double k_h, double eta,
+                                                          int move) {
+    const int a = blockIdx.x;
+    double f[3] = {0.0, 0.0, 0.0};
+    for (int t = link_off[a] + threadIdx.x; t < link_off[a + 1]; t += blockDim.x) {
         const double* rec = F.linkdp + (size_t)link_idx[t] * 6;
-        v[0] += rec[0] + rec[3];
-        v[1] += rec[1] + rec[4];
-        v[2] += rec[2] + rec[5];
+        f[0] += rec[0] + rec[3];
+        f[1] += rec[1] + rec[4];
+        f[2] += rec[2] + rec[5];
     }
-    for (int t = site_off[p] + threadIdx.x; t < site_off[p + 1]; t += blockDim.x) {
+    for (int t = site_off[a] + threadIdx.x; t < site_off[a + 1]; t += blockDim.x) {
         const unsigned i = (unsigned)site_idx[t];
-        int x, y, z;
-    site_xyz(i, S, x, y, z);
+        int sx, sy, sz;
+        site_xyz(i, S, sx, sy, sz);
         const double qv = (double)F.qc[i];
-        v[0] += qv * efield(0, x, y, z, F.phi, S);
-        v[1] += qv * efield(1, x, y, z, F.phi, S);
-        v[2] += qv * efield(2, x, y, z, F.phi, S);
+        f[0] += qv * efield(0, sx, sy, sz, F.phi, S);
+        f[1] += qv * efield(1, sx, sy, sz, F.phi, S);
+        f[2] += qv * efield(2, sx, sy, sz, F.phi, S);
     }
-    __shared__ double sm[3][kBlock];
-    for (int k = 0; k < 3; ++k) sm[k][threadIdx.x] = v[k];
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < 3; ++k) sm[k][threadIdx.x] += sm[k][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 3; ++k) pF[3 * p + k] = sm[k][0];
-}
-
-template <typename T>
-void launch_particle_sum(const Scalars& S, const Fields<T>& F, int np, const int32_t* link_off, const int32_t* link_idx,
-                         const int32_t* site_off, const int32_t* site_idx, double* pF, hipStream_t st) {
-    if (np <= 0) return;
-    hipLaunchKernelGGL(k_particle_sum<T>, dim3(np), dim3(kBlock), 0, st, S, F, link_off, link_idx, site_off, site_idx,
-                       pF);
-}
-
-// Minimum image of a separation along a periodic axis of length n: the number of periods a
-// loop would take off is computed directly, so a non-finite separation gives NaN instead of
-// a loop that never ends.
-__device__ __forceinline__ double min_image(double d, int n) {
-    const double L = (double)n;
-    if (d > 0.5 * L) d -= L * ceil((d - 0.5 * L) / L);
-    if (d < -0.5 * L) d += L * ceil((-0.5 * L - d) / L);
-    return d;
-}
-
-// Hertz contact (+k_H delta^{3/2} n, repulsive) and lubrication, then symplectic Euler.
-__global__ void k_particle_move(Scalars S, int np, const double* __restrict__ x, const double* __restrict__ v,
-                                const double* __restrict__ rad, double* __restrict__ pF, double* __restrict__ xn,
-                                double* __restrict__ vn, double rho_p, double k_h, double eta, int move) {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= np) return;
-    double F[3] = {pF[3 * a], pF[3 * a + 1], pF[3 * a + 2]};
     const int L[3] = {S.nx, S.ny, S.nz};
-    for (int b = 0; b < np; ++b) {
+    for (int b = threadIdx.x; b < np; b += blockDim.x) {
         if (b == a) continue;
         double dv[3], d2 = 0.0;
         for (int k = 0; k < 3; ++k) {
@@ -1990,12 +1960,12 @@ __global__ void k_particle_move(Scalars S, int np, const double* __restrict__ x,
             d2 += dv[k] * dv[k];
         }
         const double dist = sqrt(d2);
-        if (dist == 0.0) continue;
+        if (!(dist > 0.0)) continue;
         const double nh[3] = {dv[0] / dist, dv[1] / dist, dv[2] / dist};
         const double delta = rad[a] + rad[b] - dist;
         if (delta > 0.0) {
             const double fh = k_h * pow(delta, 1.5);
-            for (int k = 0; k < 3; ++k) F[k] += fh * nh[k];
+            for (int k = 0; k < 3; ++k) f[k] += fh * nh[k];
         }
         const double gap = dist - rad[a] - rad[b];
         if (gap < 2.0 / 3.0 && gap > 0.0) {
@@ -2003,24 +1973,37 @@ __global__ void k_particle_move(Scalars S, int np, const double* __restrict__ x,
             double nv = 0.0;
             for (int k = 0; k < 3; ++k) nv += nh[k] * (v[3 * a + k] - v[3 * b + k]);
             const double fl = -1.5 * M_PI * eta * rp * rp * nv * (1.0 / gap - 1.0);
-            for (int k = 0; k < 3; ++k) F[k] += fl * nh[k];
+            for (int k = 0; k < 3; ++k) f[k] += fl * nh[k];
         }
     }
-    const double m = rho_p * (4.0 / 3.0) * M_PI * rad[a] * rad[a] * rad[a];
-    for (int k = 0; k < 3; ++k) {
-        pF[3 * a + k] = F[k];
-        const double vv = move ? v[3 * a + k] + F[k] / m : v[3 * a + k];
-        vn[3 * a + k] = vv;
-        xn[3 * a + k] = move ? x[3 * a + k] + vv : x[3 * a + k];
+    __shared__ double sm[3][kBlock];
+    for (int k = 0; k < 3; ++k) sm[k][threadIdx.x] = f[k];
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 3; ++k) sm[k][threadIdx.x] += sm[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double m = rho_p * (4.0 / 3.0) * M_PI * rad[a] * rad[a] * rad[a];
+        for (int k = 0; k < 3; ++k) {
+            const double Fk = sm[k][0];
+            pF[3 * a + k] = Fk;
+            const double vv = move ? v[3 * a + k] + Fk / m : v[3 * a + k];
+            vn[3 * a + k] = vv;
+            xn[3 * a + k] = move ? x[3 * a + k] + vv : x[3 * a + k];
+        }
     }
 }
 
-void launch_particle_move(const Scalars& S, int np, const double* x, const double* v, const double* r,
-                          const double* pF, double* xn, double* vn, double rho_p, double k_h, double eta, int move,
-                          hipStream_t st) {
+template <typename T>
+void launch_particle_step(const Scalars& S, const Fields<T>& F, int np, const int32_t* link_off,
+                          const int32_t* link_idx, const int32_t* site_off, const int32_t* site_idx, const double* x,
+                          const double* v, const double* r, double* pF, double* xn, double* vn, double rho_p,
+                          double k_h, double eta, int move, hipStream_t st) {
     if (np <= 0) return;
-    hipLaunchKernelGGL(k_particle_move, dim3((np + 63) / 64), dim3(64), 0, st, S, np, x, v, r, const_cast<double*>(pF),
-                       xn, vn, rho_p, k_h, eta, move);
+    hipLaunchKernelGGL(k_particle_step<T>, dim3(np), dim3(kBlock), 0, st, S, F, np, link_off, link_idx, site_off,
+                       site_idx, x, v, r, pF, xn, vn, rho_p, k_h, eta, move);
 }
 
 // ------------------------------------------------------------------------------------
@@ -2207,8 +2190,9 @@ template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, 
     template void launch_force<T>(const Scalars&, const Fields<T>&, hipStream_t);                              \
     template void launch_fused<T>(const Scalars&, const Fields<T>&, hipStream_t);                              \
     template void launch_export_pop<T>(const Scalars&, const Fields<T>&, int, double*, hipStream_t);           \
-    template void launch_particle_sum<T>(const Scalars&, const Fields<T>&, int, const int32_t*, const int32_t*, \
-                                         const int32_t*, const int32_t*, double*, hipStream_t);                \
+    template void launch_particle_step<T>(const Scalars&, const Fields<T>&, int, const int32_t*, const int32_t*,  \
+                                          const int32_t*, const int32_t*, const double*, const double*, const double*, \
+                                          double*, double*, double*, double, double, double, int, hipStream_t);                \
     template void launch_observe<T>(const Scalars&, const Fields<T>&, unsigned, hipStream_t);                  \
     template void launch_init_ions<T>(const Scalars&, const Fields<T>&, T*, T*, const double*, const double*,  \
                                       hipStream_t);                                                             \

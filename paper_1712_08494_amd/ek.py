@@ -32,7 +32,7 @@ class EKParams(ctypes.Structure):
         ("E_ext", ctypes.c_double * 3), ("body_accel", ctypes.c_double * 3), ("sigma_wall", ctypes.c_double * 2),
         ("poisson_tol", ctypes.c_double), ("sor_omega", ctypes.c_double), ("particle_rho", ctypes.c_double),
         ("k_hertz", ctypes.c_double), ("eta", ctypes.c_double), ("phi_history", ctypes.c_int32),
-        ("moment_state", ctypes.c_int32),
+        ("moment_state", ctypes.c_int32), ("sweep_band", ctypes.c_int32),
     ]
 
 
@@ -51,11 +51,15 @@ class EKObs(ctypes.Structure):
     ]
 
 
+N_KERNELS = 21
+
+
 class EKTiming(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 7), ("count", ctypes.c_int64 * 7)]
+    _fields_ = [("ms", ctypes.c_double * 7), ("count", ctypes.c_int64 * 7),
+                ("kernel_ms", ctypes.c_double * N_KERNELS), ("kernel_count", ctypes.c_int64 * N_KERNELS)]
 
 
-EXPORTS = ["ek_lattice", "ek_init", "ek_step", "ek_poisson", "ek_observables", "ek_get_field",
+EXPORTS = ["ek_lattice", "ek_min_image", "ek_kernel_name", "ek_init", "ek_step", "ek_poisson", "ek_observables", "ek_get_field",
            "ek_get_populations", "ek_get_particles", "ek_device_bytes", "ek_set_timing", "ek_get_timing",
            "ek_destroy", "ek_status_str", "ek_last_error", "ek_batch_init", "ek_batch_step", "ek_batch_sync",
            "ek_batch_residuals", "ek_batch_replica", "ek_batch_destroy", "ek_batch_last_error",
@@ -87,6 +91,10 @@ def load(path=LIB_PATH):
     vp = ctypes.c_void_p
     L.ek_lattice.argtypes = [ctypes.POINTER(ctypes.c_int32), dp]
     L.ek_lattice.restype = ctypes.c_int32
+    L.ek_min_image.argtypes = [ctypes.c_double, ctypes.c_int32]
+    L.ek_min_image.restype = ctypes.c_double
+    L.ek_kernel_name.argtypes = [ctypes.c_int32]
+    L.ek_kernel_name.restype = ctypes.c_char_p
     L.ek_init.argtypes = [ctypes.POINTER(EKParams), dp, dp, dp, dp, ctypes.POINTER(EKParticle), ctypes.c_int32, vp,
                           ctypes.POINTER(vp)]
     L.ek_init.restype = ctypes.c_int32
@@ -198,6 +206,7 @@ def params_from_config(cfg):
     p.particle_rho, p.k_hertz, p.eta = cfg.particle_rho, cfg.k_hertz, cfg.eta
     p.phi_history = int(getattr(cfg, "phi_history", 0))
     p.moment_state = int(bool(getattr(cfg, "moment_state", False)))
+    p.sweep_band = int(getattr(cfg, "sweep_band", 0))
     return p
 
 
@@ -314,6 +323,13 @@ class EKSim:
         t = EKTiming()
         self._check(load().ek_get_timing(self._h, ctypes.byref(t)), "ek_get_timing")
         return {name: (t.ms[k], t.count[k]) for k, name in enumerate(TIMING_CLASSES)}
+
+    def kernel_timing(self):
+        """Per-kernel totals of timing level 3: {kernel name: (ms, launches)}."""
+        t = EKTiming()
+        L = load()
+        self._check(L.ek_get_timing(self._h, ctypes.byref(t)), "ek_get_timing")
+        return {L.ek_kernel_name(k).decode(): (t.kernel_ms[k], t.kernel_count[k]) for k in range(N_KERNELS)}
 
     def set_multigrid(self, fine_pre=1, fine_post=2, coarse_pre=1, coarse_post=2, tail_pre=3, tail_post=3,
                       coarsest=10, omega=1.2):

@@ -40,6 +40,7 @@ class EKConfig:
     eps_p: float = EPS_FLUID / 8.0   # relative permittivities 10 / 80, Sec. III D
     phi_history: int = 0             # Poisson warm start: 0 the library default
     moment_state: bool = False       # tau = 1 only: store density and u_e per site instead of populations
+    sweep_band: int = 0              # workgroup band of the stencil sweeps: 0 default, -1 plain order
     E_ext: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     body_accel: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     sigma_wall: Tuple[float, float] = (0.0, 0.0)

@@ -40,3 +40,63 @@ def test_status_strings():
     L = ek.load()
     assert L.ek_status_str(0) == b"ok"
     assert L.ek_status_str(ek.EK_ENOCONV).startswith(b"Poisson")
+
+
+def _stepping_min_image(d, n):
+    """Reference: step by whole periods while outside [-n/2, n/2] (finite d only)."""
+    L = float(n)
+    while d > 0.5 * L:
+        d -= L
+    while d < -0.5 * L:
+        d += L
+    return d
+
+
+def test_min_image_closed_form_equals_stepping():
+    """The particle geometry's minimum image takes whole periods off at once: equal to the
+    stepping loop for finite separations, NaN (not an endless loop) for non-finite ones."""
+    L = ek.load()
+    rng = np.random.default_rng(11)
+    for n in (1, 2, 7, 24, 255, 256, 1000):
+        ds = np.concatenate([rng.uniform(-3.5 * n, 3.5 * n, 4000), rng.uniform(-0.6 * n, 0.6 * n, 4000),
+                             np.array([0.5 * n, -0.5 * n, 1.5 * n, -1.5 * n, 0.0, n, -n, 2.5 * n, 1e-300]),
+                             np.nextafter(0.5 * n, np.inf) + np.arange(3) * n])
+        for d in ds:
+            assert L.ek_min_image(float(d), n) == _stepping_min_image(float(d), n), (d, n)
+    for bad in (np.inf, -np.inf, np.nan):
+        assert np.isnan(L.ek_min_image(bad, 64))
+
+
+def _init_status(cfg, inp):
+    """ek_init's status for a configuration that fails its argument checks, which run
+    before any device call (so this needs no GPU)."""
+    import ctypes
+    L = ek.load()
+    p = ek.params_from_config(cfg)
+    arr = (ek.EKParticle * len(inp.particles))()
+    for j, row in enumerate(inp.particles):
+        for k in range(3):
+            arr[j].x[k], arr[j].v[k] = row[k], row[3 + k]
+        arr[j].radius, arr[j].charge = row[6], row[7]
+    h = ctypes.c_void_p()
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (inp.rho_a, inp.rho_b, inp.n_plus, inp.n_minus)]
+    st = L.ek_init(ctypes.byref(p), *[ek._dp(x) for x in a], arr, len(inp.particles), None, ctypes.byref(h))
+    msg = L.ek_last_error(h).decode() if h else ""
+    L.ek_destroy(h)
+    return st, msg
+
+
+def test_init_rejects_non_finite_particles_and_fft_with_particles():
+    from paper_1712_08494_amd import workloads as wl
+    cfg = wl.EKConfig(16, 16, 16)
+    inp = wl.uniform(cfg)
+    for col, bad in ((0, np.inf), (1, np.nan), (4, np.inf), (6, np.nan), (7, np.inf), (6, -1.0)):
+        parts = np.array([[8.0, 8.0, 8.0, 0.0, 0.0, 0.0, 3.0, 0.1]])
+        parts[0, col] = bad
+        inp.particles = parts
+        st, msg = _init_status(cfg, inp)
+        assert st == ek.EK_EINVAL and "particle 0" in msg, (col, bad, msg)
+    inp.particles = np.array([[8.0, 8.0, 8.0, 0.0, 0.0, 0.0, 3.0, 0.1]])
+    cfg.poisson_solver = "fft"
+    st, msg = _init_status(cfg, inp)
+    assert st == ek.EK_EINVAL and "lagged Fourier" in msg, msg
