@@ -175,7 +175,8 @@ def run_secondary(name, precision, n, steps, warmup):
 def run_moment_state(workload, precision, n, steps, warmup):
     """The tau = 1 moment state (density and u_e per site instead of the populations) on
     a workload without particles: step rate against the population path, device memory,
-    and a bitwise comparison with the population path after a few steps."""
+    and a bitwise comparison after a few steps with the population path taking the same
+    (plain FP32) collision."""
     import numpy as np
     from paper_1712_08494_amd import ek
     out = {}
@@ -189,6 +190,7 @@ def run_moment_state(workload, precision, n, steps, warmup):
     cfg.moment_state = True
     a = ek.EKSim(cfg, inp)
     cfg.moment_state = False
+    cfg.fp32_plain_collision = True  # the moment state's collision: compared bit for bit
     b = ek.EKSim(cfg, inp)
     bytes_ms, bytes_pop = a.device_bytes(), b.device_bytes()
     a.step(5)

@@ -18,7 +18,8 @@
  *   - Lattice sites are indexed x fastest: i = x + nx * (y + ny * z).
  *   - Host arrays are double precision; they are borrowed for the duration of the
  *     call only and never retained.
- *   - Device memory of a context is allocated by ek_init and released by ek_destroy.
+ *   - Device memory of a context is allocated by ek_init and released by ek_destroy, or
+ *     carved from a workspace the caller owns (ek_workspace_bytes, ek_init_ws).
  *   - All work of a context is enqueued on the HIP stream given to ek_init (which may
  *     be a stream owned by the caller, e.g. PyTorch's current stream).
  *   - Calls return an ek_status; no exception or signal crosses the ABI.  On error,
@@ -104,6 +105,22 @@ typedef struct ek_params {
                                    in the XCD's L2.  0: bands of four x-rows; -1: whole planes in turn.  Used
                                    when nx*ny is a multiple of 256, nz of 8 and the band divides a plane;
                                    otherwise whole planes.  Results do not depend on it (bit for bit) */
+    int32_t poisson_cycles;     /* 0: each step's Poisson solve runs multigrid V-cycles until the relative
+                                   residual meets poisson_tol, which reads residuals back to the host (one or
+                                   two synchronisations per step).  1..64: each step runs exactly that many
+                                   V-cycles and reads nothing back, so ek_step only enqueues work; the start
+                                   and end residuals stay on the device and ek_observables reports them
+                                   (poisson_rel, poisson_rel0, and poisson_rel_max, the largest since its last
+                                   call).  The warm start is then linear in time unless phi_history is set.
+                                   Multigrid contexts only (EK_EINVAL otherwise).  ek_poisson and the solve of
+                                   ek_init always run to the tolerance */
+    int32_t fp32_plain_collision; /* FP32 populations: 0 (default) makes the collision conserve each site's
+                                   mass exactly: the moments pass sums the populations in FP64, and the rest
+                                   population takes the remainder of the other 18, stored as two floats (8 B
+                                   more per site and component).  At a steady state the FP32 roundings of a
+                                   plain collision repeat identically every step, and the mass then drifts
+                                   linearly (about 5e-9 per step on the walls/interface column).  1: the plain
+                                   FP32 collision.  FP64 and the tau = 1 moment state ignore it */
 } ek_params;
 
 typedef struct ek_particle {
@@ -131,6 +148,8 @@ typedef struct ek_obs {
     int32_t nonfinite;     /* 1 if a NaN or Inf was found in the populations or ions */
     int32_t negative_ions; /* number of sites with a negative ion density */
     double poisson_rel0;   /* relative residual of the starting guess of the last solve */
+    double poisson_rel_max;/* largest relative residual reached by the step solves since the previous
+                              ek_observables call (the tolerance is met when it is <= poisson_tol) */
 } ek_obs;
 
 /* Kernel classes timed when timing is on (ek_set_timing). */
@@ -222,11 +241,37 @@ ek_status ek_init(const ek_params* p, const double* rho_a, const double* rho_b, 
                   const double* n_minus, const ek_particle* parts, int32_t n_parts, void* stream,
                   struct ek_ctx** out);
 
-/* Advance nsteps full steps (moments, charge, Poisson, fluxes, forces, collide,
-   stream, particles).  Each solve starts from the potential extrapolated linearly in
-   time from the two previous steps.  Work is enqueued on the context's stream; the only
-   host synchronisation is the Poisson convergence test.  Returns EK_ENOCONV if any solve
-   stopped at maxit (the step is still taken with the last iterate). */
+/* Device memory that ek_init_ws needs for these parameters and particles (a pure host
+   computation: the particle geometry is built on the host to count boundary links; no
+   device call).  The layout is that of ek_init: populations, ions, moments, potentials,
+   multigrid levels, geometry and reduction scratch.  Errors: those of ek_init's argument
+   checks; EK_EINVAL for EK_POISSON_FFT (hipFFT plans hold a work area of their own). */
+ek_status ek_workspace_bytes(const ek_params* p, const ek_particle* parts, int32_t n_parts, size_t* bytes);
+
+/* As ek_init, but every device buffer of the context is carved from `workspace`, a device
+   allocation of ws_bytes >= ek_workspace_bytes(...) bytes owned by the caller (e.g. a torch
+   uint8 tensor), which must outlive the context; the library allocates no device memory for
+   it.  Buffers created by later calls (ek_forward_ckpt / ek_adjoint checkpoints, the
+   autotuner's state copy, a moment-state population export) still come from hipMalloc.
+   Errors: as ek_init; EK_ENOMEM if the workspace is too small; EK_EINVAL for a null
+   workspace or EK_POISSON_FFT. */
+ek_status ek_init_ws(const ek_params* p, const double* rho_a, const double* rho_b, const double* n_plus,
+                     const double* n_minus, const ek_particle* parts, int32_t n_parts, void* workspace,
+                     size_t ws_bytes, void* stream, struct ek_ctx** out);
+
+/* Advance nsteps full steps of the coupled method, every stage reading the state at time t
+   (Sec. II; the paper gives no order within a step): moments, pseudopotentials and virtual
+   densities (Sec. II A, II C, II E), charge and permittivity (eq. electric_potential, eq.
+   dielectric_constant), the Poisson solve (Sec. II D), the link fluxes and the ion update
+   (eq. nernst-planck-disc, eq. ionic-fluxes-disc-2), the Shan-Chen, solvation, friction and
+   Kelvin forces (eqs. shanChenForce, frictionforce, kelvin), the BGK collision with the
+   velocity shift (eq. BoltzmannBGKLattice), streaming with halfway bounce-back and momentum
+   exchange, and the particle update (Sec. II E).  Each solve starts from the potential
+   extrapolated in time as ek_params.phi_history says (default: adaptive, the order 2 or 3
+   whose last start residual was smaller).  Work is enqueued on the context's stream.  With
+   poisson_cycles = 0 the Poisson convergence test reads residuals back to the host; with
+   poisson_cycles > 0 nothing is read back and the call returns without waiting.  Returns
+   EK_ENOCONV if a solve stopped at maxit (the step is still taken with the last iterate). */
 ek_status ek_step(struct ek_ctx* ctx, int32_t nsteps);
 
 /* Solve the Poisson equation for the charge and permittivity of the current state
@@ -279,20 +324,30 @@ int32_t ek_autotune_candidates(int32_t* shapes, double* omegas);
    before the call is kept. */
 ek_status ek_autotune_multigrid(struct ek_ctx* ctx, int32_t trial_steps, int32_t* best, double* ms_per_step);
 
-/* FP64 totals and diagnostics of the current state (synchronises the stream).
-   Returns EK_ENONFINITE if populations or ion densities hold a NaN or Inf. */
-ek_status ek_observables(struct ek_ctx* ctx, ek_obs* out);
+/* FP64 totals and diagnostics of the current state (synchronises the stream): the
+   conserved sums of the method (fluid masses, ion numbers, charge, with the colloid charge
+   of Sec. II E; momentum), the largest velocity, the Poisson diagnostics of the last solves
+   and the mean particle drift.  The totals are sums in a fixed order, so they are
+   deterministic.  field_mask selects fields (bit k = field id k of ek_get_field, k <=
+   EK_F_EZ) that are also copied to host_fields, n_fields x nx*ny*nz doubles in increasing id
+   order; host_fields may be NULL when field_mask is 0.  Returns EK_ENONFINITE if populations
+   or ion densities hold a NaN or Inf (out and the fields are still written), EK_EINVAL for
+   mask bits beyond EK_F_EZ or a null host_fields. */
+ek_status ek_observables(struct ek_ctx* ctx, ek_obs* out, uint32_t field_mask, double* host_fields);
 
-/* Copy one field of the current state to host memory (nx*ny*nz doubles). */
+/* Copy one field of the current state to host memory (nx*ny*nz doubles): the fluid and ion
+   densities, potential, pre-force velocity (Sec. II A-D), charge and permittivity (eqs.
+   electric_potential, dielectric_constant), solid fraction and mask (Sec. II E) or the field
+   E = -grad phi + E_ext.  Synchronises. */
 ek_status ek_get_field(struct ek_ctx* ctx, int32_t field, double* host_out);
 
-/* Copy the populations of component comp (0 = a, 1 = b) to host memory as
+/* (Sec. II A) Copy the populations of component comp (0 = a, 1 = b) to host memory as
    19 * nx*ny*nz doubles, velocity-major in the order of ek_lattice.  FP32 contexts
    return f = deviation + w_d rho_ref. */
 ek_status ek_get_populations(struct ek_ctx* ctx, int32_t comp, double* host_out);
 
 /* Copy the particles to host memory as n_parts x 9 doubles: x(3), v(3) and the
-   force F(3) of the last step. */
+   force F(3) of the last step (Sec. II E: momentum exchange, q_c E, Hertz, lubrication). */
 ek_status ek_get_particles(struct ek_ctx* ctx, double* host_out);
 
 /* Device bytes held by the context. */

@@ -32,6 +32,14 @@ struct TimeRec {
 
 struct ek_ctx {
     ek_params p{};
+    // device memory: hipMalloc (ws_mode 0), or carved from the caller's workspace (2); 1 only
+    // adds up the sizes (ek_workspace_bytes)
+    char* ws = nullptr;
+    size_t ws_size = 0, ws_used = 0;
+    int ws_mode = 0;
+    bool split_layout = false;  // multigrid solves on colour-split copies of potential and charge
+    int fixed_cycles = 0;       // > 0: that many V-cycles per step, no host read-back (ek_params.poisson_cycles)
+    double rel_max = 0.0;       // largest relative residual of the solves since the last ek_observables
     hipStream_t st = nullptr;
     std::string err;
     Scalars S{};
@@ -128,6 +136,9 @@ struct ek_ctx {
     double* fft_tab = nullptr;  // per-axis eigenvalue parts (nx/2 + 1 + ny + nz doubles)
     void* ms[2] = {nullptr, nullptr};
     double* rho0 = nullptr;
+    // FP32 exact-mass collision (see Fields::rlo, Fields::mlo): 2 N floats each
+    void* rlo = nullptr;
+    void* mlo = nullptr;
     bool ms_first = false;
     // timing: 0 off, 1 kernel classes, 2 classes and every lattice-level smoothing pass
     int timing = 0;
@@ -180,6 +191,18 @@ static ek_status fail(ek_ctx* c, ek_status s, const std::string& msg) {
 
 static ek_status dalloc(ek_ctx* c, void** ptr, size_t bytes) {
     if (bytes == 0) bytes = 8;
+    if (c->ws_mode != 0) {  // measure (1) or carve the caller's workspace (2), in 256-byte aligned pieces
+        const uintptr_t base = (uintptr_t)c->ws;
+        const size_t off = (size_t)((((base + c->ws_used) + 255) & ~(uintptr_t)255) - base);
+        if (c->ws_mode == 2 && off + bytes > c->ws_size) {
+            c->err = "workspace of " + std::to_string(c->ws_size) + " bytes too small (ek_workspace_bytes)";
+            return EK_ENOMEM;
+        }
+        *ptr = c->ws_mode == 2 ? (void*)(c->ws + off) : nullptr;
+        c->ws_used = off + bytes;
+        c->bytes += bytes;
+        return EK_OK;
+    }
     hipError_t e = hipMalloc(ptr, bytes);
     if (e != hipSuccess) {
         c->err = "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e);
@@ -199,12 +222,12 @@ static ek_status dalloc(ek_ctx* c, void** ptr, size_t bytes) {
 static void dfree(ek_ctx* c, void* ptr, size_t bytes) {
     if (!ptr) return;
     for (size_t k = 0; k < c->allocs.size(); ++k)
-        if (c->allocs[k] == ptr) {
+        if (c->allocs[k] == ptr) {  // only buffers from hipMalloc (never a piece of a workspace)
             c->allocs.erase(c->allocs.begin() + (long)k);
-            break;
+            (void)hipFree(ptr);
+            c->bytes -= bytes;
+            return;
         }
-    (void)hipFree(ptr);
-    c->bytes -= bytes;
 }
 
 // ------------------------------------------------------------------------------------
@@ -305,6 +328,8 @@ static Fields<T> fields(ek_ctx* c) {
     F.msn = c->moment_state ? (T*)c->ms[c->cur ^ 1] : nullptr;
     F.rho0 = c->rho0;
     F.ms_first = c->ms_first ? 1 : 0;
+    F.rlo = (T*)c->rlo;
+    F.mlo = (T*)c->mlo;
     return F;
 }
 
@@ -409,6 +434,23 @@ static ek_status build_geometry(ek_ctx* c, const ek_particle* parts, int np, Hos
                 }
             }
     g.nlinks = nl;
+    // bit 3: the site or one of its six axis neighbours is partly covered (fluid fraction
+    // below 1).  A site with none of bits 0, 1 and 3 sees fluid fraction 1 and no solid
+    // around it, and the stencil passes take the plain path there.
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const size_t i = id(x, y, z);
+                bool part = g.psis[i] > 0.0;
+                for (int k = 0; k < 3 && !part; ++k)
+                    for (int sgn = -1; sgn <= 1 && !part; sgn += 2) {
+                        const size_t j = id(((x + (k == 0 ? sgn : 0)) % nx + nx) % nx,
+                                            ((y + (k == 1 ? sgn : 0)) % ny + ny) % ny,
+                                            ((z + (k == 2 ? sgn : 0)) % nz + nz) % nz);
+                        part = g.psis[j] > 0.0;
+                    }
+                if (part) g.flags[i] |= 8;
+            }
     if (np > 0) {
         // links grouped by particle (counting sort), in the order the fused kernel writes them
         std::vector<int32_t> lowner(nl > 0 ? nl : 1);
@@ -619,7 +661,7 @@ static void mg_build(ek_ctx* c, const Fields<T>& F) {
 
 // Requires q, eps and the source mean of the current state on the device.
 template <typename T>
-static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out, double* rel_out) {
+static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out, double* rel_out, bool fixed = false) {
     Timer tm(c, EK_T_POISSON);
     Fields<T> F = fields<T>(c);
     const bool use_mg = !c->mg.empty();
@@ -631,6 +673,45 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
     if (split) {
         FS.phi = c->phis;
         FS.q = (T*)c->qs;
+    }
+    if (fixed && use_mg && own) {
+        // A fixed number of V-cycles and no host read-back: the start and end residuals are
+        // reduced on the device, where ek_observables reads them (and the largest since its
+        // last call).  The step is then one stream of launches with no synchronisation.
+        const int k = c->fixed_cycles;
+        const unsigned nres = residual_blocks(c->N);
+        {
+            EK_KT(EK_K_RESIDUAL);
+            launch_residual<T>(c->S, F, nres, false, split ? c->phis : nullptr, split ? (T*)c->qs : nullptr, c->st);
+        }
+        {
+            EK_KT(EK_K_REDUCE);
+            launch_reduce(c->red, nres, 3, nullptr, c->scal + 24, c->st);
+        }
+        mg_build<T>(c, F);
+        {
+            Timer ts(c, EK_T_ITER, k);
+            EK_TRY(run_cycles<T>(c, FS, split, k));
+        }
+        {
+            EK_KT(EK_K_RESIDUAL);
+            launch_residual<T>(c->S, FS, nres, split, nullptr, nullptr, c->st);
+        }
+        {
+            EK_KT(EK_K_REDUCE);
+            launch_reduce(c->red, nres, 3, nullptr, c->scal + 1, c->st);
+        }
+        launch_track_residual(c->scal, c->st);
+        {
+            EK_KT(EK_K_FINALIZE);
+            launch_phi_finalize<T>(c->S, F, 0, split ? c->phis : nullptr, c->st);
+        }
+        EK_HIP(hipGetLastError());
+        c->last_iters = k;
+        c->ptotal += k;
+        if (iters_out) *iters_out = k;
+        if (rel_out) *rel_out = -1.0;
+        return EK_OK;
     }
     // the cycle rate: geometric mean over the last k cycles, kept on the slow side
     auto update_rate = [&](double r_old, double r_new, int k) {
@@ -758,6 +839,7 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
     if (own && use_mg) cycles_record(c, need);
     c->last_iters = it;
     c->last_rel = rel;
+    c->rel_max = std::max(c->rel_max, rel);
     c->ptotal += it;
     if (iters_out) *iters_out = it;
     if (rel_out) *rel_out = rel;
@@ -841,8 +923,10 @@ static ek_status step_impl(ek_ctx* c, int nsteps) {
             EK_TRY(step_rest<T>(c));
             continue;
         }
+        const bool fixed = c->fixed_cycles > 0;
         int order = c->phi_history;
         bool probe = false;
+        if (order == 0 && fixed) order = 2;  // the adaptive choice needs the start residuals on the host
         if (order == 0) {  // adaptive: keep the order with the smaller start residual, re-probe the other
             order = c->ws_order;
             const int other = 5 - c->ws_order;
@@ -855,8 +939,8 @@ static ek_status step_impl(ek_ctx* c, int nsteps) {
             EK_KT(EK_K_EXTRAPOLATE);
             launch_phi_extrapolate(c->S, c->phi, c->phi_prev, c->phi_prev2, order, c->st);
         }
-        ek_status ps = poisson_solve<T>(c, c->p.poisson_tol, c->p.poisson_maxit, nullptr, nullptr);
-        if (c->phi_history == 0 && c->steps >= 2) {
+        ek_status ps = poisson_solve<T>(c, c->p.poisson_tol, c->p.poisson_maxit, nullptr, nullptr, fixed);
+        if (c->phi_history == 0 && !fixed && c->steps >= 2) {
             c->rel0_of[order] = c->last_rel0;
             const int other = 5 - order;
             if (probe) {
@@ -918,21 +1002,88 @@ static double omega_for(const ek_params& p) {
     return 2.0 / (1.0 + std::sqrt(std::max(0.0, 1.0 - mu * mu)));
 }
 
+// Every device buffer of a context, in one place.  With c->ws_mode 0 each comes from
+// hipMalloc; with 1 the sizes are only added up (ek_workspace_bytes, no device call); with 2
+// they are carved from the caller's workspace.  Buffers created later (checkpoints, the
+// autotuner's state copy, a moment-state population export) always come from hipMalloc.
 template <typename T>
-static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, const double* n_plus,
-                           const double* n_minus, const ek_particle* parts, int np) {
+static ek_status allocate_all(ek_ctx* c, const HostGeom& g, int np) {
     const ek_params& p = c->p;
     const unsigned N = c->N;
-    HostGeom g;
-    EK_TRY(build_geometry(c, parts, np, g));
-    const bool colloids = np > 0;
-    c->S.colloids = colloids;
-    // Reference densities for the deviation storage, unless given.  A stored deviation
-    // rho - r carries a rounding error proportional to |rho - r|, so the relative error
-    // of rho scales with |rho - r| / rho.  Over the initial range [lo, hi] of a component
-    // the worst case of that ratio is smallest for the harmonic mean r = 2 lo hi / (lo + hi):
-    // near the mean for a nearly uniform fluid, near the minority value of a demixed one
-    // (where a plain mean would cost the minority phase two decades of precision).
+    const size_t es = sizeof(T);
+    for (int b = 0; b < 2; ++b)
+        for (int k = 0; k < 2; ++k) {
+            if (!c->moment_state) EK_TRY(dalloc(c, &c->f[b][k], (size_t)kQ * N * es));
+            EK_TRY(dalloc(c, &c->n[b][k], (size_t)N * es));
+        }
+    if (c->moment_state) {
+        for (int b = 0; b < 2; ++b) EK_TRY(dalloc(c, &c->ms[b], 8 * (size_t)N * es));
+        EK_TRY(dalloc(c, (void**)&c->rho0, 2 * (size_t)N * 8));
+    }
+    if (es == 4 && !c->moment_state && !p.fp32_plain_collision) {
+        EK_TRY(dalloc(c, &c->rlo, 2 * (size_t)N * es));
+        EK_TRY(dalloc(c, &c->mlo, 2 * (size_t)N * es));
+    }
+    EK_TRY(dalloc(c, &c->mom, 8 * (size_t)N * es));
+    EK_TRY(dalloc(c, &c->uph, 3 * (size_t)N * es));
+    EK_TRY(dalloc(c, &c->q, (size_t)N * es));
+    EK_TRY(dalloc(c, &c->eps, (size_t)N * es));
+    EK_TRY(dalloc(c, (void**)&c->phi, (size_t)N * 8));
+    EK_TRY(dalloc(c, (void**)&c->phi_prev, (size_t)N * 8));
+    EK_TRY(dalloc(c, (void**)&c->phi_prev2, (size_t)N * 8));
+    if (c->split_layout) {
+        EK_TRY(dalloc(c, (void**)&c->phis, (size_t)N * 8));
+        EK_TRY(dalloc(c, &c->qs, (size_t)N * es));
+        EK_TRY(dalloc(c, (void**)&c->blk, (size_t)(N / 2) * 8));
+    }
+    EK_TRY(dalloc(c, (void**)&c->red, (size_t)c->nblk * kRedSlots * 8));
+    EK_TRY(dalloc(c, (void**)&c->scal, 32 * 8));
+    EK_TRY(dalloc(c, (void**)&c->obs_max, 16 * sizeof(int)));
+    EK_TRY(dalloc(c, (void**)&c->stage, (size_t)N * 8));
+    EK_TRY(dalloc(c, (void**)&c->stage2, (size_t)N * 8));
+    for (auto& L : c->mg) {
+        EK_TRY(dalloc(c, (void**)&L.phi, (size_t)L.n * 8));
+        EK_TRY(dalloc(c, (void**)&L.s, (size_t)L.n * 8));
+        EK_TRY(dalloc(c, (void**)&L.ax, (size_t)L.n * 8));
+        EK_TRY(dalloc(c, (void**)&L.ay, (size_t)L.n * 8));
+        EK_TRY(dalloc(c, (void**)&L.az, (size_t)L.n * 8));
+    }
+    if (!g.vlist.empty()) EK_TRY(dalloc(c, (void**)&c->vlist, g.vlist.size() * 4));
+    if (np > 0) {
+        EK_TRY(dalloc(c, (void**)&c->flags, N));
+        EK_TRY(dalloc(c, &c->psif, (size_t)N * es));
+        EK_TRY(dalloc(c, &c->qc, (size_t)N * es));
+        EK_TRY(dalloc(c, (void**)&c->owner, (size_t)N * 4));
+        EK_TRY(dalloc(c, (void**)&c->linkbase, (size_t)N * 4));
+        EK_TRY(dalloc(c, (void**)&c->linkdp, (size_t)std::max(1LL, g.nlinks) * 6 * 8));
+        EK_TRY(dalloc(c, (void**)&c->plink_off, g.link_off.size() * 4));
+        EK_TRY(dalloc(c, (void**)&c->plink_idx, g.link_idx.size() * 4));
+        EK_TRY(dalloc(c, (void**)&c->psite_off, g.site_off.size() * 4));
+        EK_TRY(dalloc(c, (void**)&c->psite_idx, g.site_idx.size() * 4));
+        for (int b = 0; b < 2; ++b) {
+            EK_TRY(dalloc(c, (void**)&c->px[b], 3 * np * 8));
+            EK_TRY(dalloc(c, (void**)&c->pv[b], 3 * np * 8));
+        }
+        EK_TRY(dalloc(c, (void**)&c->prad, np * 8));
+        EK_TRY(dalloc(c, (void**)&c->pF, 3 * np * 8));
+    }
+    if (c->fft) {
+        EK_TRY(dalloc(c, (void**)&c->fft_rhs, (size_t)N * 8));
+        EK_TRY(dalloc(c, (void**)&c->fft_spec, (size_t)p.nz * p.ny * (p.nx / 2 + 1) * 16));
+        EK_TRY(dalloc(c, (void**)&c->fft_tab, (size_t)(p.nx / 2 + 1 + p.ny + p.nz) * 8));
+    }
+    return EK_OK;
+}
+
+// Reference densities of the FP32 deviation storage, unless given.  A stored deviation
+// rho - r carries a rounding error proportional to |rho - r|, so the relative error of rho
+// scales with |rho - r| / rho.  Over the initial range [lo, hi] of a component the worst case
+// of that ratio is smallest for the harmonic mean r = 2 lo hi / (lo + hi): near the mean for
+// a nearly uniform fluid, near the minority value of a demixed one (where a plain mean would
+// cost the minority phase two decades of precision).
+static ek_status reference_densities(ek_ctx* c, const HostGeom& g, const double* rho_a, const double* rho_b,
+                                     const double* n_plus, const double* n_minus) {
+    const unsigned N = c->N;
     for (int s = 0; s < 2; ++s) {
         const double* r = s == 0 ? rho_a : rho_b;
         double lo = INFINITY, hi = 0.0;
@@ -942,80 +1093,56 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
             lo = std::min(lo, r[i]);
             hi = std::max(hi, r[i]);
         }
-        c->S.rref[s] = p.rho_ref[s] > 0.0 ? p.rho_ref[s] : (hi > 0.0 ? 2.0 * lo * hi / (lo + hi) : 1.0);
+        c->S.rref[s] = c->p.rho_ref[s] > 0.0 ? c->p.rho_ref[s] : (hi > 0.0 ? 2.0 * lo * hi / (lo + hi) : 1.0);
     }
     for (unsigned i = 0; i < N; ++i)
         if (!std::isfinite(n_plus[i]) || !std::isfinite(n_minus[i])) return fail(c, EK_EINVAL, "ion densities must be finite");
+    return EK_OK;
+}
+
+template <typename T>
+static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, const double* n_plus,
+                           const double* n_minus, const ek_particle* parts, int np) {
+    const ek_params& p = c->p;
+    const unsigned N = c->N;
+    HostGeom g;
+    EK_TRY(build_geometry(c, parts, np, g));
+    const bool colloids = np > 0;
+    c->S.colloids = colloids;
+    EK_TRY(reference_densities(c, g, rho_a, rho_b, n_plus, n_minus));
+    EK_TRY(allocate_all<T>(c, g, np));
+    c->ws_mode = 0;  // later buffers come from hipMalloc
 
     const size_t es = sizeof(T);
-    for (int b = 0; b < 2; ++b)
-        for (int k = 0; k < 2; ++k) {
-            if (!c->moment_state) EK_TRY(dalloc(c, &c->f[b][k], (size_t)kQ * N * es));
-            EK_TRY(dalloc(c, &c->n[b][k], (size_t)N * es));
-        }
-    if (c->moment_state) {
-        for (int b = 0; b < 2; ++b) {
-            EK_TRY(dalloc(c, &c->ms[b], 8 * (size_t)N * es));
-            EK_HIP(hipMemsetAsync(c->ms[b], 0, 8 * (size_t)N * es, c->st));
-        }
-        EK_TRY(dalloc(c, (void**)&c->rho0, 2 * (size_t)N * 8));
-    }
-    EK_TRY(dalloc(c, &c->mom, 8 * (size_t)N * es));
-    EK_TRY(dalloc(c, &c->uph, 3 * (size_t)N * es));
-    EK_TRY(dalloc(c, &c->q, (size_t)N * es));
-    EK_TRY(dalloc(c, &c->eps, (size_t)N * es));
-    EK_TRY(dalloc(c, (void**)&c->phi, (size_t)N * 8));
-    EK_TRY(dalloc(c, (void**)&c->phi_prev, (size_t)N * 8));
-    EK_TRY(dalloc(c, (void**)&c->phi_prev2, (size_t)N * 8));
-    // EK_POISSON_SITE_ORDER=1 keeps the multigrid solves in site order (a diagnostic switch:
-    // the results are the same, bit for bit)
-    const char* site_order = std::getenv("EK_POISSON_SITE_ORDER");
-    if (!c->mg.empty() && !(site_order && std::atoi(site_order) != 0)) {
-        EK_TRY(dalloc(c, (void**)&c->phis, (size_t)N * 8));
-        EK_TRY(dalloc(c, &c->qs, (size_t)N * es));
-        EK_TRY(dalloc(c, (void**)&c->blk, (size_t)(N / 2) * 8));
-    }
+    if (c->moment_state)
+        for (int b = 0; b < 2; ++b) EK_HIP(hipMemsetAsync(c->ms[b], 0, 8 * (size_t)N * es, c->st));
     c->phi_own = c->phi;
     c->q_own = c->q;
-    EK_TRY(dalloc(c, (void**)&c->red, (size_t)c->nblk * kRedSlots * 8));
-    EK_TRY(dalloc(c, (void**)&c->scal, 32 * 8));
-    EK_TRY(dalloc(c, (void**)&c->obs_max, 16 * sizeof(int)));
-    EK_TRY(dalloc(c, (void**)&c->stage, (size_t)N * 8));
     EK_HIP(hipHostMalloc((void**)&c->hscal, 32 * sizeof(double), hipHostMallocDefault));
-    for (auto& L : c->mg) {
-        EK_TRY(dalloc(c, (void**)&L.phi, (size_t)L.n * 8));
-        EK_TRY(dalloc(c, (void**)&L.s, (size_t)L.n * 8));
-        EK_TRY(dalloc(c, (void**)&L.ax, (size_t)L.n * 8));
-        EK_TRY(dalloc(c, (void**)&L.ay, (size_t)L.n * 8));
-        EK_TRY(dalloc(c, (void**)&L.az, (size_t)L.n * 8));
-        EK_HIP(hipMemsetAsync(L.phi, 0, (size_t)L.n * 8, c->st));
-    }
+    for (auto& L : c->mg) EK_HIP(hipMemsetAsync(L.phi, 0, (size_t)L.n * 8, c->st));
     for (int b = 0; b < 2; ++b)
         for (int k = 0; k < 2; ++k) {
             if (c->f[b][k]) EK_HIP(hipMemsetAsync(c->f[b][k], 0, (size_t)kQ * N * es, c->st));
             EK_HIP(hipMemsetAsync(c->n[b][k], 0, (size_t)N * es, c->st));
         }
     EK_HIP(hipMemsetAsync(c->mom, 0, 8 * (size_t)N * es, c->st));
+    if (c->rlo) EK_HIP(hipMemsetAsync(c->rlo, 0, 2 * (size_t)N * es, c->st));
+    if (c->mlo) EK_HIP(hipMemsetAsync(c->mlo, 0, 2 * (size_t)N * es, c->st));
     EK_HIP(hipMemsetAsync(c->uph, 0, 3 * (size_t)N * es, c->st));
     EK_HIP(hipMemsetAsync(c->phi, 0, (size_t)N * 8, c->st));
     EK_HIP(hipMemsetAsync(c->scal, 0, 32 * 8, c->st));
     int hmax[16] = {0};
     hmax[8] = 1;
     EK_HIP(hipMemcpyAsync(c->obs_max, hmax, sizeof(hmax), hipMemcpyHostToDevice, c->st));
+    EK_HIP(hipStreamSynchronize(c->st));  // hmax is a stack array
 
     // geometry upload
     c->hflags = g.flags;
     c->hpsis = g.psis;
     c->nv = (int)g.vlist.size();
-    if (c->nv > 0) {
-        EK_TRY(dalloc(c, (void**)&c->vlist, g.vlist.size() * 4));
-        EK_HIP(hipMemcpyAsync(c->vlist, g.vlist.data(), g.vlist.size() * 4, hipMemcpyHostToDevice, c->st));
-    }
+    if (c->nv > 0) EK_HIP(hipMemcpyAsync(c->vlist, g.vlist.data(), g.vlist.size() * 4, hipMemcpyHostToDevice, c->st));
     if (colloids) {
-        EK_TRY(dalloc(c, (void**)&c->flags, N));
         EK_HIP(hipMemcpyAsync(c->flags, g.flags.data(), N, hipMemcpyHostToDevice, c->st));
-        EK_TRY(dalloc(c, &c->psif, (size_t)N * es));
-        EK_TRY(dalloc(c, &c->qc, (size_t)N * es));
         std::vector<double> tmp(N);
         for (unsigned i = 0; i < N; ++i) tmp[i] = 1.0 - g.psis[i];
         EK_HIP(hipMemcpyAsync(c->stage, tmp.data(), (size_t)N * 8, hipMemcpyHostToDevice, c->st));
@@ -1023,17 +1150,10 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
         EK_HIP(hipStreamSynchronize(c->st));
         EK_HIP(hipMemcpyAsync(c->stage, g.qc.data(), (size_t)N * 8, hipMemcpyHostToDevice, c->st));
         launch_upload<T>((T*)c->qc, c->stage, N, c->st);
-        EK_TRY(dalloc(c, (void**)&c->owner, (size_t)N * 4));
         EK_HIP(hipMemcpyAsync(c->owner, g.owner.data(), (size_t)N * 4, hipMemcpyHostToDevice, c->st));
-        EK_TRY(dalloc(c, (void**)&c->linkbase, (size_t)N * 4));
         EK_HIP(hipMemcpyAsync(c->linkbase, g.linkbase.data(), (size_t)N * 4, hipMemcpyHostToDevice, c->st));
         c->nlinks = g.nlinks;
-        EK_TRY(dalloc(c, (void**)&c->linkdp, (size_t)std::max(1LL, g.nlinks) * 6 * 8));
         EK_HIP(hipMemsetAsync(c->linkdp, 0, (size_t)std::max(1LL, g.nlinks) * 6 * 8, c->st));
-        EK_TRY(dalloc(c, (void**)&c->plink_off, g.link_off.size() * 4));
-        EK_TRY(dalloc(c, (void**)&c->plink_idx, g.link_idx.size() * 4));
-        EK_TRY(dalloc(c, (void**)&c->psite_off, g.site_off.size() * 4));
-        EK_TRY(dalloc(c, (void**)&c->psite_idx, g.site_idx.size() * 4));
         EK_HIP(hipMemcpyAsync(c->plink_off, g.link_off.data(), g.link_off.size() * 4, hipMemcpyHostToDevice, c->st));
         EK_HIP(hipMemcpyAsync(c->plink_idx, g.link_idx.data(), g.link_idx.size() * 4, hipMemcpyHostToDevice, c->st));
         EK_HIP(hipMemcpyAsync(c->psite_off, g.site_off.data(), g.site_off.size() * 4, hipMemcpyHostToDevice, c->st));
@@ -1051,14 +1171,10 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
         }
         c->px0 = hx;
         for (int b = 0; b < 2; ++b) {
-            EK_TRY(dalloc(c, (void**)&c->px[b], 3 * np * 8));
-            EK_TRY(dalloc(c, (void**)&c->pv[b], 3 * np * 8));
             EK_HIP(hipMemcpyAsync(c->px[b], hx.data(), 3 * np * 8, hipMemcpyHostToDevice, c->st));
             EK_HIP(hipMemcpyAsync(c->pv[b], hv.data(), 3 * np * 8, hipMemcpyHostToDevice, c->st));
         }
-        EK_TRY(dalloc(c, (void**)&c->prad, np * 8));
         EK_HIP(hipMemcpyAsync(c->prad, c->hrad.data(), np * 8, hipMemcpyHostToDevice, c->st));
-        EK_TRY(dalloc(c, (void**)&c->pF, 3 * np * 8));
         EK_HIP(hipMemsetAsync(c->pF, 0, 3 * np * 8, c->st));
         EK_HIP(hipStreamSynchronize(c->st));  // host staging vectors above end with this block
     }
@@ -1078,18 +1194,12 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     }
     EK_HIP(hipStreamSynchronize(c->st));
     // ions: stored as mean density and ionic charge (staging holds n+ then n-)
-    double* stage2 = nullptr;
-    EK_TRY(dalloc(c, (void**)&stage2, (size_t)N * 8));
     EK_HIP(hipMemcpyAsync(c->stage, n_plus, (size_t)N * 8, hipMemcpyHostToDevice, c->st));
-    EK_HIP(hipMemcpyAsync(stage2, n_minus, (size_t)N * 8, hipMemcpyHostToDevice, c->st));
-    launch_init_ions<T>(c->S, F, (T*)c->n[c->cur][0], (T*)c->n[c->cur][1], c->stage, stage2, c->st);
+    EK_HIP(hipMemcpyAsync(c->stage2, n_minus, (size_t)N * 8, hipMemcpyHostToDevice, c->st));
+    launch_init_ions<T>(c->S, F, (T*)c->n[c->cur][0], (T*)c->n[c->cur][1], c->stage, c->stage2, c->st);
     EK_HIP(hipStreamSynchronize(c->st));
-    c->stage2 = stage2;
     EK_HIP(hipGetLastError());
     if (c->fft) {
-        EK_TRY(dalloc(c, (void**)&c->fft_rhs, (size_t)N * 8));
-        EK_TRY(dalloc(c, (void**)&c->fft_spec, (size_t)p.nz * p.ny * (p.nx / 2 + 1) * 16));
-        EK_TRY(dalloc(c, (void**)&c->fft_tab, (size_t)(p.nx / 2 + 1 + p.ny + p.nz) * 8));
         launch_lag_table(c->fft_tab, p.nx, p.ny, p.nz, c->st);
         if (hipfftPlan3d(&c->fft_fwd, p.nz, p.ny, p.nx, HIPFFT_D2Z) != HIPFFT_SUCCESS ||
             hipfftPlan3d(&c->fft_inv, p.nz, p.ny, p.nx, HIPFFT_Z2D) != HIPFFT_SUCCESS ||
@@ -1103,19 +1213,16 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     EK_HIP(hipMemcpyAsync(c->phi_prev, c->phi, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
     EK_HIP(hipMemcpyAsync(c->phi_prev2, c->phi, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
     c->ptotal = 0;
+    c->rel_max = 0.0;
+    if (c->fixed_cycles) EK_HIP(hipMemsetAsync(c->scal + 28, 0, 8, c->st));
     return st;
 }
 
-extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const double* rho_b, const double* n_plus,
-                             const double* n_minus, const ek_particle* parts, int32_t n_parts, void* stream,
-                             ek_ctx** out) {
-    if (!out) return EK_EINVAL;
-    *out = nullptr;
-    ek_ctx* c = new ek_ctx();
-    *out = c;
-    if (!p || !rho_a || !rho_b || !n_plus || !n_minus) return fail(c, EK_EINVAL, "null argument");
+// Checks the parameters and sets up the context's scalars and multigrid levels: host work
+// only, no device call.
+static ek_status configure(ek_ctx* c, const ek_params* p, const ek_particle* parts, int32_t n_parts) {
+    if (!p) return fail(c, EK_EINVAL, "null parameters");
     c->p = *p;
-    c->st = (hipStream_t)stream;
     if (p->nx < 2 || (p->nx & 1) || p->ny < 1 || p->nz < 1) return fail(c, EK_EINVAL, "nx must be even and >= 2; ny, nz >= 1");
     if (p->walls_z && p->nz < 3) return fail(c, EK_EINVAL, "walls need nz >= 3");
     const double Nd = (double)p->nx * p->ny * p->nz;
@@ -1237,9 +1344,67 @@ extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const doub
             c->mg_coarse_omega = std::min(1.9, omega_for(q));
         }
     }
+    if (p->poisson_cycles < 0 || p->poisson_cycles > 64) return fail(c, EK_EINVAL, "poisson_cycles must be in 0..64");
+    if (p->fp32_plain_collision != 0 && p->fp32_plain_collision != 1)
+        return fail(c, EK_EINVAL, "fp32_plain_collision must be 0 or 1");
+    if (p->poisson_cycles > 0 && (c->mg.empty() || c->fft))
+        return fail(c, EK_EINVAL, "a fixed V-cycle count needs the multigrid solver");
+    c->fixed_cycles = p->poisson_cycles;
+    // EK_POISSON_SITE_ORDER=1 keeps the multigrid solves in site order (a diagnostic switch:
+    // the results are the same, bit for bit)
+    const char* site_order = std::getenv("EK_POISSON_SITE_ORDER");
+    c->split_layout = !c->mg.empty() && !(site_order && std::atoi(site_order) != 0);
     c->esz = p->precision == EK_FP32 ? 4 : 8;
-    if (p->precision == EK_FP32) return init_impl<float>(c, rho_a, rho_b, n_plus, n_minus, parts, n_parts);
+    return EK_OK;
+}
+
+static ek_status init_dispatch(ek_ctx* c, const double* rho_a, const double* rho_b, const double* n_plus,
+                               const double* n_minus, const ek_particle* parts, int32_t n_parts) {
+    if (!rho_a || !rho_b || !n_plus || !n_minus) return fail(c, EK_EINVAL, "null argument");
+    if (c->esz == 4) return init_impl<float>(c, rho_a, rho_b, n_plus, n_minus, parts, n_parts);
     return init_impl<double>(c, rho_a, rho_b, n_plus, n_minus, parts, n_parts);
+}
+
+extern "C" ek_status ek_init(const ek_params* p, const double* rho_a, const double* rho_b, const double* n_plus,
+                             const double* n_minus, const ek_particle* parts, int32_t n_parts, void* stream,
+                             ek_ctx** out) {
+    if (!out) return EK_EINVAL;
+    ek_ctx* c = new ek_ctx();
+    *out = c;
+    c->st = (hipStream_t)stream;
+    EK_TRY(configure(c, p, parts, n_parts));
+    return init_dispatch(c, rho_a, rho_b, n_plus, n_minus, parts, n_parts);
+}
+
+extern "C" ek_status ek_workspace_bytes(const ek_params* p, const ek_particle* parts, int32_t n_parts, size_t* bytes) {
+    if (!bytes) return EK_EINVAL;
+    *bytes = 0;
+    ek_ctx c;
+    EK_TRY(configure(&c, p, parts, n_parts));
+    if (c.fft) return EK_EINVAL;  // hipFFT's plans hold a work area of their own
+    HostGeom g;
+    c.N = (unsigned)((size_t)p->nx * p->ny * p->nz);
+    EK_TRY(build_geometry(&c, parts, n_parts, g));
+    c.ws_mode = 1;
+    EK_TRY(c.esz == 4 ? allocate_all<float>(&c, g, n_parts) : allocate_all<double>(&c, g, n_parts));
+    *bytes = c.ws_used + 256;  // room to align an arbitrary base address
+    return EK_OK;
+}
+
+extern "C" ek_status ek_init_ws(const ek_params* p, const double* rho_a, const double* rho_b, const double* n_plus,
+                                const double* n_minus, const ek_particle* parts, int32_t n_parts, void* workspace,
+                                size_t ws_bytes, void* stream, ek_ctx** out) {
+    if (!out) return EK_EINVAL;
+    ek_ctx* c = new ek_ctx();
+    *out = c;
+    c->st = (hipStream_t)stream;
+    if (!workspace) return fail(c, EK_EINVAL, "null workspace");
+    EK_TRY(configure(c, p, parts, n_parts));
+    if (c->fft) return fail(c, EK_EINVAL, "the lagged Fourier scheme needs hipFFT's own work area: use ek_init");
+    c->ws = (char*)workspace;
+    c->ws_size = ws_bytes;
+    c->ws_mode = 2;
+    return init_dispatch(c, rho_a, rho_b, n_plus, n_minus, parts, n_parts);
 }
 
 extern "C" ek_status ek_step(ek_ctx* c, int32_t nsteps) {
@@ -1272,7 +1437,7 @@ static ek_status observe_impl(ek_ctx* c, ek_obs* o) {
     Fields<T> F = fields<T>(c);
     launch_observe<T>(c->S, F, c->nblk, c->st);
     launch_reduce(c->red, c->nblk, 11, c->obs_max, c->scal + 8, c->st);
-    EK_HIP(hipMemcpyAsync(c->hscal, c->scal, 20 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    EK_HIP(hipMemcpyAsync(c->hscal, c->scal, 32 * sizeof(double), hipMemcpyDeviceToHost, c->st));
     EK_HIP(hipStreamSynchronize(c->st));
     const double* v = c->hscal + 8;
     std::memset(o, 0, sizeof(*o));
@@ -1290,6 +1455,15 @@ static ek_status observe_impl(ek_ctx* c, ek_obs* o) {
     o->source_mean = c->last_mean;
     o->poisson_rel = c->last_rel;
     o->poisson_rel0 = c->last_rel0;
+    o->poisson_rel_max = c->rel_max;
+    c->rel_max = 0.0;
+    if (c->fixed_cycles > 0 && c->steps > 0) {  // solves without host read-back keep their residuals on the device
+        o->source_mean = c->hscal[0];
+        o->poisson_rel = c->hscal[29];
+        o->poisson_rel0 = c->hscal[30];
+        o->poisson_rel_max = c->hscal[28];
+        EK_HIP(hipMemsetAsync(c->scal + 28, 0, 8, c->st));
+    }
     o->poisson_iters = c->last_iters;
     o->poisson_total = c->ptotal;
     o->poisson_mg_levels = c->mg.empty() ? 0 : (int32_t)c->mg.size() + 1;
@@ -1648,9 +1822,10 @@ static ek_status tune_copy(ek_ctx* c, bool save, HostState& h) {
     // populations of the current step, or the moment state (8 N values, in the first slot)
     void* dev[] = {c->moment_state ? c->ms[c->cur] : c->f[c->cur][0], c->moment_state ? nullptr : c->f[c->cur][1],
                    c->n[c->cur][0], c->n[c->cur][1], c->phi, c->phi_prev, c->phi_prev2,
-                   c->np ? c->px[c->pcur] : nullptr, c->np ? c->pv[c->pcur] : nullptr, c->np ? c->pF : nullptr};
-    const size_t len[] = {c->moment_state ? 8 * N * c->esz : pop, pop, ion, ion, N * 8, N * 8, N * 8, pb, pb, pb};
-    for (int k = 0; k < 10; ++k) {
+                   c->np ? c->px[c->pcur] : nullptr, c->np ? c->pv[c->pcur] : nullptr, c->np ? c->pF : nullptr, c->rlo};
+    const size_t len[] = {c->moment_state ? 8 * N * c->esz : pop, pop, ion, ion, N * 8, N * 8, N * 8, pb, pb, pb,
+                          c->rlo ? 2 * N * c->esz : 0};
+    for (int k = 0; k < 11; ++k) {
         if (!dev[k] || !len[k]) continue;
         if (save)
             EK_HIP(hipMemcpyAsync(b, dev[k], len[k], hipMemcpyDeviceToDevice, c->st));
@@ -1664,7 +1839,7 @@ static ek_status tune_copy(ek_ctx* c, bool save, HostState& h) {
 static size_t tune_bytes(const ek_ctx* c) {
     const size_t N = c->N, pb = (size_t)3 * c->np * 8;
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    return 2 * up(kQ * N * c->esz) + 2 * up(N * c->esz) + 3 * up(N * 8) + 3 * up(pb);
+    return 2 * up(kQ * N * c->esz) + 2 * up(N * c->esz) + 3 * up(N * 8) + 3 * up(pb) + (c->rlo ? up(2 * N * c->esz) : 0);
 }
 
 template <typename T>
@@ -1767,11 +1942,6 @@ extern "C" ek_status ek_autotune_multigrid(ek_ctx* c, int32_t trial_steps, int32
                        : autotune_impl<double>(c, trial_steps, best, ms_per_step);
 }
 
-extern "C" ek_status ek_observables(ek_ctx* c, ek_obs* out) {
-    if (!c || !c->phi) return EK_ESTATE;
-    if (!out) return fail(c, EK_EINVAL, "null output");
-    return c->esz == 4 ? observe_impl<float>(c, out) : observe_impl<double>(c, out);
-}
 
 template <typename T>
 static ek_status field_impl(ek_ctx* c, int which, double* host) {
@@ -1821,6 +1991,23 @@ extern "C" ek_status ek_get_field(ek_ctx* c, int32_t which, double* host_out) {
     return c->esz == 4 ? field_impl<float>(c, which, host_out) : field_impl<double>(c, which, host_out);
 }
 
+extern "C" ek_status ek_observables(ek_ctx* c, ek_obs* out, uint32_t field_mask, double* host_fields) {
+    if (!c || !c->phi) return EK_ESTATE;
+    if (!out) return fail(c, EK_EINVAL, "null output");
+    if (field_mask >> (EK_F_EZ + 1)) return fail(c, EK_EINVAL, "field_mask has bits beyond EK_F_EZ");
+    if (field_mask && !host_fields) return fail(c, EK_EINVAL, "null host_fields with a non-zero field_mask");
+    const ek_status st = c->esz == 4 ? observe_impl<float>(c, out) : observe_impl<double>(c, out);
+    if (st != EK_OK && st != EK_ENONFINITE) return st;
+    size_t slot = 0;
+    for (int k = 0; k <= EK_F_EZ; ++k)
+        if (field_mask & (1u << k)) {
+            EK_TRY(c->esz == 4 ? field_impl<float>(c, k, host_fields + slot * c->N)
+                               : field_impl<double>(c, k, host_fields + slot * c->N));
+            ++slot;
+        }
+    return st;
+}
+
 template <typename T>
 static ek_status pops_impl(ek_ctx* c, int comp, double* host) {
     const unsigned N = c->N;
@@ -1837,6 +2024,7 @@ static ek_status pops_impl(ek_ctx* c, int comp, double* host) {
     }
     for (int d = 0; d < kQ; ++d) {
         launch_to_double<T>((const T*)c->f[c->cur][comp] + (size_t)d * N, c->stage, N, weight(d) * c->S.rref[comp], c->st);
+        if (d == kRest && c->rlo) launch_add_lo<T>((const T*)c->rlo + (size_t)comp * N, c->stage, N, c->st);
         EK_HIP(hipMemcpyAsync(host + (size_t)d * N, c->stage, (size_t)N * 8, hipMemcpyDeviceToHost, c->st));
         EK_HIP(hipStreamSynchronize(c->st));
     }

@@ -51,7 +51,8 @@ struct Fields {
     T* q;               // charge density
     T* eps;             // permittivity
     double* phi;        // potential (double)
-    const uint8_t* flags;    // bit0 solid, bit1 fluid next to a solid, bit2 solid next to fluid
+    const uint8_t* flags;    // bit0 solid, bit1 fluid next to a solid, bit2 solid next to fluid,
+                             // bit3 the site or an axis neighbour partly covered
     const T* psif;           // fluid fraction
     const T* qc;             // particle charge per site
     const int32_t* owner;    // particle owning a site, -1 none
@@ -69,6 +70,12 @@ struct Fields {
     T* msn;
     const double* rho0;      // initial densities (2 N, FP64): the populations w_d rho0 before the first step
     int ms_first;            // 1 until the first step has written a moment state
+    // FP32 population contexts with the exact-mass collision (null otherwise): the low FP32
+    // part of each site's rest population (2 N, a then b; the stored rest value is the high
+    // part), and the part of each site's summed mass that the FP32 mass slot does not hold
+    // (2 N), from the moments pass to the collision
+    T* rlo;
+    T* mlo;
 };
 
 // One coarse level of the Poisson multigrid: cell-centred, periodic in all axes, with
@@ -204,6 +211,9 @@ void launch_particle_step(const Scalars& S, const Fields<T>& F, int np, const in
                           const double* v, const double* r, double* pF, double* xn, double* vn, double rho_p,
                           double k_h, double eta, int move, hipStream_t st);
 template <typename T> void launch_observe(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
+// the observables from a fixed grid of nblk workgroups (grid-stride), partial sums in red
+// device-side relative residuals of a solve without host read-back (scal[28..30])
+void launch_track_residual(double* scal, hipStream_t st);
 template <typename T>
 void launch_init_pop_flags(const Scalars& S, T* f, const double* rho, double rref, const uint8_t* flags, hipStream_t st);
 template <typename T>
@@ -212,6 +222,7 @@ void launch_init_ions(const Scalars& S, const Fields<T>& F, T* ion_s, T* ion_c, 
 template <typename T>
 void launch_ion_species(const T* ion_s, const T* ion_c, double* dst, unsigned n, double sign, hipStream_t st);
 template <typename T> void launch_to_double(const T* src, double* dst, unsigned n, double add, hipStream_t st);
+template <typename T> void launch_add_lo(const T* lo, double* dst, unsigned n, hipStream_t st);
 template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, int k, double* dst, hipStream_t st);
 template <typename T> void launch_upload(T* dst, const double* src, unsigned n, hipStream_t st);
 

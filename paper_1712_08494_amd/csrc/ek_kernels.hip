@@ -169,7 +169,7 @@ template <typename T>
 __device__ __forceinline__ T geq_dev(int d, T dr, T rs, T u0, T u1, T u2, T usq) {
 #pragma clang fp contract(off)
     const T cu = T(vx(d)) * u0 + T(vy(d)) * u1 + T(vz(d)) * u2;
-    return T(weight(d)) * (dr + rs * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq));
+    return T(storage_weight<T>(d)) * (dr + rs * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq));
 }
 
 // tau = 1 moment state.  At tau = 1 the post-collision populations of a site are the
@@ -215,7 +215,7 @@ __device__ __forceinline__ MsSite<T> ms_site(const Scalars& S, const Fields<T>& 
 template <typename T, int PM>
 __device__ __forceinline__ T arriving(const Scalars& S, const Fields<T>& F, int c, int d, unsigned i, int z,
                                       const Nbr& o, const MsSite<T>& own) {
-    if (PM == 2) return (T)(weight(d) * (F.rho0[(size_t)c * S.N + i] - S.rref[c]));
+    if (PM == 2) return (T)(storage_weight<T>(d) * (F.rho0[(size_t)c * S.N + i] - S.rref[c]));
     if (d != kRest) {
         const int od = opposite(d);
         const int zs = z - vz(d);
@@ -242,6 +242,11 @@ __device__ __forceinline__ double moments_body(const Scalars& S, const Fields<T>
         T da = T(-S.rref[0]), db = T(-S.rref[1]), ux = 0, uy = 0, uz = 0, pa = 0, pb = 0;
         if (!solid) {
             T sa = 0, sb = 0, mx = 0, my = 0, mz = 0;
+            // FP32 populations with the exact-mass rest population (F.rlo set): the mass is
+            // summed in FP64, where the 19 stored values and the rest population's low part
+            // add up exactly, and the part the FP32 mass slot cannot hold goes to F.mlo
+            const bool xm = sizeof(T) == 4 && PM == 0 && F.rlo != nullptr;
+            double sad = 0.0, sbd = 0.0;
             Nbr o{};
             MsSite<T> own0{}, own1{};
             if (PM == 1) {
@@ -259,6 +264,10 @@ __device__ __forceinline__ double moments_body(const Scalars& S, const Fields<T>
                                     : arriving<T, PM>(S, F, 1, d, i, z, o, own1);
                 sa += a;
                 sb += b;
+                if (xm) {
+                    sad += (double)a;
+                    sbd += (double)b;
+                }
                 const T s = a + b;
                 if (vx(d) > 0) mx += s;
                 if (vx(d) < 0) mx -= s;
@@ -266,6 +275,14 @@ __device__ __forceinline__ double moments_body(const Scalars& S, const Fields<T>
                 if (vy(d) < 0) my -= s;
                 if (vz(d) > 0) mz += s;
                 if (vz(d) < 0) mz -= s;
+            }
+            if (xm) {
+                sad += (double)F.rlo[i];
+                sbd += (double)F.rlo[(size_t)S.N + i];
+                sa = (T)sad;
+                sb = (T)sbd;
+                F.mlo[i] = (T)(sad - (double)sa);
+                F.mlo[(size_t)S.N + i] = (T)(sbd - (double)sb);
             }
             da = sa;
             db = sb;
@@ -1769,9 +1786,19 @@ __device__ __forceinline__ void site_forces(unsigned i, const Nbr& o, T ra, T rb
 // Total force and physical velocity u = u' + (Phi^a + Phi^b) / (2 rho) of every fluid
 // site (needed by the donor-cell ion advection of the neighbours).
 // ------------------------------------------------------------------------------------
+// With particles most sites have no solid D3Q19 neighbour and fluid fraction 1 on their
+// axis stencil (flag bits 0, 1 and 3 clear); there the particle path computes exactly what
+// the periodic path does (unit fractions, no bounce-back), so those sites take it and skip
+// the fraction and neighbour-flag loads.
+constexpr uint8_t kParticlePath = 1u | 2u | 8u;
+
 template <typename T, int G>
 __device__ __forceinline__ void force_body(const Scalars& S, const Fields<T>& F, unsigned i) {
     if (i >= S.N) return;
+    if (G == kColloids && (F.flags[i] & kParticlePath) == 0) {
+        force_body<T, kPeriodic>(S, F, i);
+        return;
+    }
     int x, y, z;
     site_xyz(i, S, x, y, z);
     const size_t N = S.N;
@@ -1822,6 +1849,10 @@ template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hi
 template <typename T, int G, bool MS = false>
 __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F, unsigned i) {
     if (i >= S.N) return;
+    if (G == kColloids && (F.flags[i] & kParticlePath) == 0) {
+        fused_body<T, kPeriodic, MS>(S, F, i);
+        return;
+    }
     int x, y, z;
     site_xyz(i, S, x, y, z);
     if (G == kWalls && (z == 0 || z == S.nz - 1)) return;  // wall layers hold no ions and no fluid
@@ -1861,6 +1892,13 @@ __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F,
         const T* fc = F.f[c];
         T* fo = F.fn[c];
         int lk = link;
+        // FP32 exact-mass collision: the post-collision populations must hold exactly the mass
+        // the moments pass summed (the FP32 slot plus F.mlo); the rest population takes the
+        // remainder of the other 18, kept as an FP32 pair (stored value + F.rlo).  Without it
+        // the FP32 rounding of a steady state repeats identically every step and the mass
+        // drifts linearly in time.
+        const bool xm = sizeof(T) == 4 && F.rlo != nullptr;
+        double other = 0.0;
 #pragma unroll
         for (int d = 0; d < kQ; ++d) {
             const T w = T(weight(d));
@@ -1869,6 +1907,10 @@ __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F,
             if (!tau1) {
                 const T g = __builtin_nontemporal_load(fc + (size_t)d * N + i);
                 gs = g - (g - geq) * T(S.inv_tau);
+            }
+            if (xm) {
+                if (d == kRest) continue;
+                other += (double)gs;
             }
             const unsigned j = i + offset_of(o, d);
             bool bounce = false;
@@ -1896,11 +1938,21 @@ __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F,
                 __builtin_nontemporal_store(gs, fo + (size_t)d * N + j);
             }
         }
+        if (xm) {
+            const double g0 = ((double)dr + (double)F.mlo[(size_t)c * N + i]) - other;
+            const T hi = (T)g0;
+            __builtin_nontemporal_store(hi, fo + (size_t)kRest * N + i);
+            F.rlo[(size_t)c * N + i] = (T)(g0 - (double)hi);
+        }
     }
 }
 
+// The particle variant holds both the particle path and the plain path: in FP32 it takes
+// three waves per SIMD, where it needs no scratch.
+template <typename T, int G> constexpr int kFusedOcc = (G == kColloids && sizeof(T) == 4) ? 3 : kHotOcc<T>;
+
 template <typename T, int G, bool MS>
-__global__ __launch_bounds__(kBlock, kHotOcc<T>) void k_fused(Scalars S, Fields<T> F) {
+__global__ __launch_bounds__(kBlock, (kFusedOcc<T, G>)) void k_fused(Scalars S, Fields<T> F) {
     fused_body<T, G, MS>(S, F, site_banded(S));
 }
 
@@ -2010,52 +2062,62 @@ void launch_particle_step(const Scalars& S, const Fields<T>& F, int np, const in
 // Observables: FP64 partial sums of mass, ions, charge, momentum; max |u|; counts of
 // non-finite values and negative ion densities.
 // ------------------------------------------------------------------------------------
+// The observables of one site, added into v: [0, 1] rho^a, rho^b (fluid sites), [2, 3] n+, n-,
+// [4] charge, [5..7] momentum, [8] |u| (the caller keeps the maximum), [9] non-finite
+// values, [10] negative ion densities.
+template <typename T, int PM>
+__device__ __forceinline__ void observe_site(const Scalars& S, const Fields<T>& F, unsigned i, double (&v)[11]) {
+#pragma clang fp contract(off)  // gathered populations rounded as stored ones (see moments_body)
+    int x, y, z;
+    site_xyz(i, S, x, y, z);
+    const double is_ = (double)F.n[0][i], ic_ = (double)F.n[1][i];
+    const double np_ = is_ + 0.5 * ic_, nm_ = is_ - 0.5 * ic_;
+    v[2] += np_;
+    v[3] += nm_;
+    v[4] += np_ - nm_ + (S.colloids ? (double)F.qc[i] : 0.0);
+    int bad = !isfinite(np_) || !isfinite(nm_);
+    v[10] += (np_ < 0.0) + (nm_ < 0.0);
+    if (!solid_at(i, z, S, F)) {
+        double sa = 0, sb = 0, m[3] = {0, 0, 0};
+        const Nbr o = make_nbr(x, y, z, S);
+        MsSite<T> own0{}, own1{};
+        if (PM == 1) {
+            own0 = ms_site<T>(S, F, 0, i);
+            own1 = ms_site<T>(S, F, 1, i);
+        }
+#pragma unroll
+        for (int d = 0; d < kQ; ++d) {
+            double a = PM == 0 ? (double)F.f[0][(size_t)d * S.N + i]
+                               : (double)arriving<T, PM>(S, F, 0, d, i, z, o, own0);
+            double b = PM == 0 ? (double)F.f[1][(size_t)d * S.N + i]
+                               : (double)arriving<T, PM>(S, F, 1, d, i, z, o, own1);
+            if (PM == 0 && d == kRest && F.rlo) {  // the rest population's low part
+                a = a + (double)F.rlo[i];
+                b = b + (double)F.rlo[(size_t)S.N + i];
+            }
+            bad |= !isfinite(a) || !isfinite(b);
+            sa += a;
+            sb += b;
+            m[0] += (a + b) * vx(d);
+            m[1] += (a + b) * vy(d);
+            m[2] += (a + b) * vz(d);
+        }
+        const double ra = S.rref[0] + sa, rb = S.rref[1] + sb;
+        v[0] += ra;
+        v[1] += rb;
+        v[5] += m[0];
+        v[6] += m[1];
+        v[7] += m[2];
+        v[8] = fmax(v[8], sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) / (ra + rb));
+    }
+    v[9] += bad;
+}
+
 template <typename T, int PM>
 __global__ __launch_bounds__(kBlock) void k_observe(Scalars S, Fields<T> F) {
-#pragma clang fp contract(off)  // gathered populations rounded as stored ones (see moments_body)
     const unsigned i = xcd_linear();
     double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (i < S.N) {
-        int x, y, z;
-        site_xyz(i, S, x, y, z);
-        const double is_ = (double)F.n[0][i], ic_ = (double)F.n[1][i];
-        const double np_ = is_ + 0.5 * ic_, nm_ = is_ - 0.5 * ic_;
-        v[2] = np_;
-        v[3] = nm_;
-        v[4] = np_ - nm_ + (S.colloids ? (double)F.qc[i] : 0.0);
-        int bad = !isfinite(np_) || !isfinite(nm_);
-        v[10] = (np_ < 0.0) + (nm_ < 0.0);
-        if (!solid_at(i, z, S, F)) {
-            double sa = 0, sb = 0, m[3] = {0, 0, 0};
-            const Nbr o = make_nbr(x, y, z, S);
-            MsSite<T> own0{}, own1{};
-            if (PM == 1) {
-                own0 = ms_site<T>(S, F, 0, i);
-                own1 = ms_site<T>(S, F, 1, i);
-            }
-#pragma unroll
-            for (int d = 0; d < kQ; ++d) {
-                const double a = PM == 0 ? (double)F.f[0][(size_t)d * S.N + i]
-                                         : (double)arriving<T, PM>(S, F, 0, d, i, z, o, own0);
-                const double b = PM == 0 ? (double)F.f[1][(size_t)d * S.N + i]
-                                         : (double)arriving<T, PM>(S, F, 1, d, i, z, o, own1);
-                bad |= !isfinite(a) || !isfinite(b);
-                sa += a;
-                sb += b;
-                m[0] += (a + b) * vx(d);
-                m[1] += (a + b) * vy(d);
-                m[2] += (a + b) * vz(d);
-            }
-            const double ra = S.rref[0] + sa, rb = S.rref[1] + sb;
-            v[0] = ra;
-            v[1] = rb;
-            v[5] = m[0];
-            v[6] = m[1];
-            v[7] = m[2];
-            v[8] = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) / (ra + rb);
-        }
-        v[9] = bad;
-    }
+    if (i < S.N) observe_site<T, PM>(S, F, i, v);
     const bool mx[11] = {false, false, false, false, false, false, false, false, true, false, false};
     block_reduce_store<11>(v, mx, F.red, blockIdx.x, gridDim.x);
 }
@@ -2068,6 +2130,22 @@ template <typename T> void launch_observe(const Scalars& S, const Fields<T>& F, 
         hipLaunchKernelGGL((k_observe<T, 1>), dim3(nblk), dim3(kBlock), 0, st, S, F);
     else
         hipLaunchKernelGGL((k_observe<T, 2>), dim3(nblk), dim3(kBlock), 0, st, S, F);
+}
+
+// Relative residuals of a solve run without a host read-back, kept on the device: the start
+// (scal[24], scal[25]) and end (scal[1], scal[2]) sums of squares give scal[30] and scal[29];
+// scal[28] keeps the largest end value since it was last cleared.
+__global__ void k_track_residual(double* scal) {
+    if (threadIdx.x != 0) return;
+    const double rel = scal[2] > 0.0 ? sqrt(scal[1] / scal[2]) : 0.0;
+    const double rel0 = scal[25] > 0.0 ? sqrt(scal[24] / scal[25]) : 0.0;
+    scal[29] = rel;
+    scal[30] = rel0;
+    scal[28] = fmax(scal[28], rel);
+}
+
+void launch_track_residual(double* scal, hipStream_t st) {
+    hipLaunchKernelGGL(k_track_residual, dim3(1), dim3(64), 0, st, scal);
 }
 
 // Populations of component c at time t (FP64, f_d = g_d + w_d rho_ref, velocity-major) of a
@@ -2097,6 +2175,17 @@ template <typename T> void launch_export_pop(const Scalars& S, const Fields<T>& 
         hipLaunchKernelGGL((k_export_pop<T, 2>), dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F, c, out);
 }
 
+// dst[i] += lo[i] (FP64): the low part of the FP32 rest population, added to its export.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_add_lo(const T* __restrict__ lo, double* __restrict__ dst, unsigned n) {
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = dst[i] + (double)lo[i];
+}
+
+template <typename T> void launch_add_lo(const T* lo, double* dst, unsigned n, hipStream_t st) {
+    hipLaunchKernelGGL(k_add_lo<T>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, lo, dst, n);
+}
+
 // ------------------------------------------------------------------------------------
 // Initialisation and export
 // ------------------------------------------------------------------------------------
@@ -2110,7 +2199,7 @@ __global__ __launch_bounds__(kBlock) void k_init_pop(Scalars S, T* f, const doub
     const bool solid = S.colloids ? (flags[i] & 1u) != 0 : wall_layer(z, S);
     const double dr = solid ? 0.0 : rho[i] - rref;
 #pragma unroll
-    for (int d = 0; d < kQ; ++d) f[(size_t)d * S.N + i] = (T)(weight(d) * dr);
+    for (int d = 0; d < kQ; ++d) f[(size_t)d * S.N + i] = (T)(storage_weight<T>(d) * dr);
 }
 
 // Ions are stored as the mean density s = (n+ + n-)/2 and the ionic charge c = n+ - n-
@@ -2194,6 +2283,7 @@ template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, 
                                           const int32_t*, const int32_t*, const double*, const double*, const double*, \
                                           double*, double*, double*, double, double, double, int, hipStream_t);                \
     template void launch_observe<T>(const Scalars&, const Fields<T>&, unsigned, hipStream_t);                  \
+    template void launch_add_lo<T>(const T*, double*, unsigned, hipStream_t);                  \
     template void launch_init_ions<T>(const Scalars&, const Fields<T>&, T*, T*, const double*, const double*,  \
                                       hipStream_t);                                                             \
     template void launch_ion_species<T>(const T*, const T*, double*, unsigned, double, hipStream_t);           \

@@ -31,4 +31,19 @@ __host__ __device__ constexpr double weight(int d) {
     return vsq(d) == 0 ? 1.0 / 3.0 : (vsq(d) == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
 
+// Weights of the equilibrium in the storage precision.  The collision sets each population
+// to w_d times the site's density deviation plus velocity terms, so the stored density
+// deviation is multiplied by the sum of the weights at every step.  The FP32 roundings of
+// 1/3, 1/18 and 1/36 sum to 1 + 1.5e-8, which would grow a deviation by 7.5e-5 over 5000
+// steps; these FP32 values sum to 1 exactly: w2 = 1864135 / 2^26 (1/36 to 6e-8), w1 = 2 w2,
+// w0 = 1 - 24 w2 = 2796203 / 2^23, each exact in FP32.  FP64 uses the exact fractions.
+__host__ __device__ constexpr double weight_fp32(int d) {
+    return vsq(d) == 0 ? 2796203.0 / 8388608.0 : (vsq(d) == 1 ? 1864135.0 / 33554432.0 : 1864135.0 / 67108864.0);
+}
+
+template <typename T>
+__host__ __device__ constexpr double storage_weight(int d) {
+    return sizeof(T) == 4 ? weight_fp32(d) : weight(d);
+}
+
 }  // namespace ek

@@ -32,7 +32,8 @@ class EKParams(ctypes.Structure):
         ("E_ext", ctypes.c_double * 3), ("body_accel", ctypes.c_double * 3), ("sigma_wall", ctypes.c_double * 2),
         ("poisson_tol", ctypes.c_double), ("sor_omega", ctypes.c_double), ("particle_rho", ctypes.c_double),
         ("k_hertz", ctypes.c_double), ("eta", ctypes.c_double), ("phi_history", ctypes.c_int32),
-        ("moment_state", ctypes.c_int32), ("sweep_band", ctypes.c_int32),
+        ("moment_state", ctypes.c_int32), ("sweep_band", ctypes.c_int32), ("poisson_cycles", ctypes.c_int32),
+        ("fp32_plain_collision", ctypes.c_int32),
     ]
 
 
@@ -48,6 +49,7 @@ class EKObs(ctypes.Structure):
         ("poisson_rel", ctypes.c_double), ("poisson_iters", ctypes.c_int64), ("poisson_total", ctypes.c_int64),
         ("poisson_mg_levels", ctypes.c_int32), ("steps", ctypes.c_int64), ("drift", ctypes.c_double * 3), ("pmomentum", ctypes.c_double * 3),
         ("nonfinite", ctypes.c_int32), ("negative_ions", ctypes.c_int32), ("poisson_rel0", ctypes.c_double),
+        ("poisson_rel_max", ctypes.c_double),
     ]
 
 
@@ -59,7 +61,7 @@ class EKTiming(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double * N_KERNELS), ("kernel_count", ctypes.c_int64 * N_KERNELS)]
 
 
-EXPORTS = ["ek_lattice", "ek_min_image", "ek_kernel_name", "ek_init", "ek_step", "ek_poisson", "ek_observables", "ek_get_field",
+EXPORTS = ["ek_lattice", "ek_min_image", "ek_kernel_name", "ek_workspace_bytes", "ek_init_ws", "ek_init", "ek_step", "ek_poisson", "ek_observables", "ek_get_field",
            "ek_get_populations", "ek_get_particles", "ek_device_bytes", "ek_set_timing", "ek_get_timing",
            "ek_destroy", "ek_status_str", "ek_last_error", "ek_batch_init", "ek_batch_step", "ek_batch_sync",
            "ek_batch_residuals", "ek_batch_replica", "ek_batch_destroy", "ek_batch_last_error",
@@ -102,7 +104,13 @@ def load(path=LIB_PATH):
     L.ek_step.restype = ctypes.c_int32
     L.ek_poisson.argtypes = [vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), dp]
     L.ek_poisson.restype = ctypes.c_int32
-    L.ek_observables.argtypes = [vp, ctypes.POINTER(EKObs)]
+    L.ek_workspace_bytes.argtypes = [ctypes.POINTER(EKParams), ctypes.POINTER(EKParticle), ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_size_t)]
+    L.ek_workspace_bytes.restype = ctypes.c_int32
+    L.ek_init_ws.argtypes = [ctypes.POINTER(EKParams), dp, dp, dp, dp, ctypes.POINTER(EKParticle), ctypes.c_int32,
+                             vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.ek_init_ws.restype = ctypes.c_int32
+    L.ek_observables.argtypes = [vp, ctypes.POINTER(EKObs), ctypes.c_uint32, dp]
     L.ek_observables.restype = ctypes.c_int32
     L.ek_get_field.argtypes = [vp, ctypes.c_int32, dp]
     L.ek_get_field.restype = ctypes.c_int32
@@ -207,6 +215,8 @@ def params_from_config(cfg):
     p.phi_history = int(getattr(cfg, "phi_history", 0))
     p.moment_state = int(bool(getattr(cfg, "moment_state", False)))
     p.sweep_band = int(getattr(cfg, "sweep_band", 0))
+    p.poisson_cycles = int(getattr(cfg, "poisson_cycles", 0))
+    p.fp32_plain_collision = int(bool(getattr(cfg, "fp32_plain_collision", False)))
     return p
 
 
@@ -219,7 +229,9 @@ def current_stream_handle():
 class EKSim:
     """A simulation context on the GPU.  Fields come back as (nz, ny, nx) float64 arrays."""
 
-    def __init__(self, cfg, inputs, stream=None, params=None):
+    def __init__(self, cfg, inputs, stream=None, params=None, workspace=False):
+        """workspace=True: the context's device memory is one torch uint8 tensor held by
+        this object (ek_workspace_bytes / ek_init_ws); otherwise the library allocates it."""
         L = load()
         self.cfg = cfg
         self.shape = (cfg.nz, cfg.ny, cfg.nx)
@@ -240,8 +252,19 @@ class EKSim:
             stream = current_stream_handle()
         self._stream = stream
         h = ctypes.c_void_p()
-        st = L.ek_init(ctypes.byref(self._p), _dp(ra), _dp(rb), _dp(npl), _dp(nmi),
-                       arr if self.np else None, self.np, stream, ctypes.byref(h))
+        self.workspace = None
+        if workspace:
+            import torch
+            nb = ctypes.c_size_t(0)
+            st = L.ek_workspace_bytes(ctypes.byref(self._p), arr if self.np else None, self.np, ctypes.byref(nb))
+            if st != EK_OK:
+                raise EKError(st, "ek_workspace_bytes")
+            self.workspace = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+            st = L.ek_init_ws(ctypes.byref(self._p), _dp(ra), _dp(rb), _dp(npl), _dp(nmi), arr if self.np else None,
+                              self.np, ctypes.c_void_p(self.workspace.data_ptr()), nb.value, stream, ctypes.byref(h))
+        else:
+            st = L.ek_init(ctypes.byref(self._p), _dp(ra), _dp(rb), _dp(npl), _dp(nmi),
+                           arr if self.np else None, self.np, stream, ctypes.byref(h))
         self._h = h
         if st != EK_OK:
             msg = self.last_error()
@@ -262,6 +285,7 @@ class EKSim:
         if getattr(self, "_h", None):
             load().ek_destroy(self._h)
             self._h = None
+        self.workspace = None  # after ek_destroy: the context no longer uses it
 
     def __del__(self):
         try:
@@ -279,11 +303,18 @@ class EKSim:
         self._check(st, "ek_poisson", (EK_ENOCONV,))
         return st, it.value, rel.value
 
-    def observables(self):
+    def observables(self, fields=()):
+        """FP64 totals and diagnostics; with field names, also those fields (ek_observables'
+        field mask) under the key "fields" as {name: (nz, ny, nx) array}."""
         o = EKObs()
-        st = load().ek_observables(self._h, ctypes.byref(o))
+        ids = sorted(FIELDS[f] for f in fields)
+        mask = 0
+        for k in ids:
+            mask |= 1 << k
+        buf = np.zeros(len(ids) * self.N) if ids else None
+        st = load().ek_observables(self._h, ctypes.byref(o), mask, _dp(buf) if ids else None)
         self._check(st, "ek_observables", (EK_ENONFINITE,))
-        return {
+        out = {
             "status": st,
             "sum_rho_a": o.sum_rho[0], "sum_rho_b": o.sum_rho[1], "sum_n_plus": o.sum_n[0],
             "sum_n_minus": o.sum_n[1], "sum_q": o.sum_q, "mom_x": o.momentum[0], "mom_y": o.momentum[1],
@@ -292,8 +323,12 @@ class EKSim:
             "poisson_mg_levels": o.poisson_mg_levels, "steps": o.steps,
             "drift_x": o.drift[0], "drift_y": o.drift[1], "drift_z": o.drift[2], "pmom_x": o.pmomentum[0],
             "pmom_y": o.pmomentum[1], "pmom_z": o.pmomentum[2], "nonfinite": o.nonfinite,
-            "negative_ions": o.negative_ions, "poisson_rel0": o.poisson_rel0,
+            "negative_ions": o.negative_ions, "poisson_rel0": o.poisson_rel0, "poisson_rel_max": o.poisson_rel_max,
         }
+        if ids:
+            names = {v: k for k, v in FIELDS.items()}
+            out["fields"] = {names[k]: buf[j * self.N:(j + 1) * self.N].reshape(self.shape) for j, k in enumerate(ids)}
+        return out
 
     def field(self, name):
         out = np.zeros(self.N)

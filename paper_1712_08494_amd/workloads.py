@@ -41,6 +41,8 @@ class EKConfig:
     phi_history: int = 0             # Poisson warm start: 0 the library default
     moment_state: bool = False       # tau = 1 only: store density and u_e per site instead of populations
     sweep_band: int = 0              # workgroup band of the stencil sweeps: 0 default, -1 plain order
+    poisson_cycles: int = 0          # > 0: that many V-cycles per step, no host read-back
+    fp32_plain_collision: bool = False  # FP32: the plain collision instead of the exact-mass one
     E_ext: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     body_accel: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     sigma_wall: Tuple[float, float] = (0.0, 0.0)

@@ -100,3 +100,36 @@ def test_init_rejects_non_finite_particles_and_fft_with_particles():
     cfg.poisson_solver = "fft"
     st, msg = _init_status(cfg, inp)
     assert st == ek.EK_EINVAL and "lagged Fourier" in msg, msg
+
+
+def test_workspace_bytes_is_a_host_computation():
+    """ek_workspace_bytes needs no GPU: it counts the buffers of the context's layout (the
+    particle geometry is built on the host for the boundary links)."""
+    import ctypes
+    from paper_1712_08494_amd import workloads as wl
+    L = ek.load()
+
+    def ws(cfg, parts=None):
+        p = ek.params_from_config(cfg)
+        n = 0 if parts is None else len(parts)
+        arr = (ek.EKParticle * max(n, 1))()
+        for j in range(n):
+            for k in range(3):
+                arr[j].x[k] = parts[j][k]
+            arr[j].radius, arr[j].charge = parts[j][6], parts[j][7]
+        b = ctypes.c_size_t(0)
+        st = L.ek_workspace_bytes(ctypes.byref(p), arr if n else None, n, ctypes.byref(b))
+        return st, b.value
+
+    st32, b32 = ws(wl.EKConfig(32, 32, 32, precision="fp32"))
+    st64, b64 = ws(wl.EKConfig(32, 32, 32, precision="fp64"))
+    assert st32 == 0 and st64 == 0
+    N = 32 ** 3
+    # two population buffers of 2 x 19 values per site, plus ions, moments and potentials
+    assert 2 * 2 * 19 * 4 * N < b32 < b64 and b64 > 2 * 2 * 19 * 8 * N
+    stp, bp = ws(wl.EKConfig(32, 32, 32, precision="fp32"), [[16.0, 16.0, 16.0, 0, 0, 0, 4.0, 0.5]])
+    assert stp == 0 and bp > b32  # the particle geometry adds per-site arrays and link records
+    stf, _ = ws(wl.EKConfig(32, 32, 32, poisson_solver="fft"))
+    assert stf == ek.EK_EINVAL
+    stb, _ = ws(wl.EKConfig(7, 4, 4))
+    assert stb == ek.EK_EINVAL

@@ -49,6 +49,8 @@ def _snapshot(sim):
 def test_moment_state_matches_populations(name, precision):
     cfg, inp = _case(name, precision)
     print(f"moment state vs populations: {name} {precision} {cfg.nx}x{cfg.ny}x{cfg.nz}", flush=True)
+    # the moment state takes the plain collision (no exact-mass rest population in FP32)
+    cfg.fp32_plain_collision = True
     pop = ek.EKSim(cfg, inp)
     cfg.moment_state = True
     ms = ek.EKSim(cfg, inp)
