@@ -335,6 +335,20 @@ ek_status ek_autotune_multigrid(struct ek_ctx* ctx, int32_t trial_steps, int32_t
    mask bits beyond EK_F_EZ or a null host_fields. */
 ek_status ek_observables(struct ek_ctx* ctx, ek_obs* out, uint32_t field_mask, double* host_fields);
 
+/* For callers that cannot allocate device memory or wait for the device (work captured in
+   a HIP graph, serving loops): the totals of ek_observables written to device memory,
+   enqueued on the context's stream without any host synchronisation or allocation.  d_out:
+   device pointer to 11 doubles: sum rho_a, sum rho_b (fluid sites), sum n+, sum n-, sum q,
+   momentum x, y, z, max |u|, count of non-finite values, count of negative ion densities.
+   The per-workgroup partial sums go to a file-scope device array of the library (128 KiB on
+   each GPU, held until the process ends; a fixed grid of at most 1024 workgroups strides over
+   any lattice size, so the partials use at most 88 KiB of it) instead of the context's
+   buffers.  The summation order differs from ek_observables' (the same values to FP64
+   rounding).  All calls on one GPU share that array: calls that may overlap (several
+   streams or threads) race and must be serialised by the caller.  Errors: EK_ESTATE,
+   EK_EINVAL (null d_out), EK_EHIP. */
+ek_status ek_observables_device(struct ek_ctx* ctx, double* d_out);
+
 /* Copy one field of the current state to host memory (nx*ny*nz doubles): the fluid and ion
    densities, potential, pre-force velocity (Sec. II A-D), charge and permittivity (eqs.
    electric_potential, dielectric_constant), solid fraction and mask (Sec. II E) or the field

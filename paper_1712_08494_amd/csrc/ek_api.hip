@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -40,6 +41,7 @@ struct ek_ctx {
     bool split_layout = false;  // multigrid solves on colour-split copies of potential and charge
     int fixed_cycles = 0;       // > 0: that many V-cycles per step, no host read-back (ek_params.poisson_cycles)
     double rel_max = 0.0;       // largest relative residual of the solves since the last ek_observables
+    double* obs_scratch = nullptr;  // this device's address of the library's observables scratch array
     hipStream_t st = nullptr;
     std::string err;
     Scalars S{};
@@ -1100,6 +1102,8 @@ static ek_status reference_densities(ek_ctx* c, const HostGeom& g, const double*
     return EK_OK;
 }
 
+static ek_status scratch_setup(ek_ctx* c);
+
 template <typename T>
 static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, const double* n_plus,
                            const double* n_minus, const ek_particle* parts, int np) {
@@ -1112,6 +1116,7 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     EK_TRY(reference_densities(c, g, rho_a, rho_b, n_plus, n_minus));
     EK_TRY(allocate_all<T>(c, g, np));
     c->ws_mode = 0;  // later buffers come from hipMalloc
+    EK_TRY(scratch_setup(c));
 
     const size_t es = sizeof(T);
     if (c->moment_state)
@@ -2006,6 +2011,52 @@ extern "C" ek_status ek_observables(ek_ctx* c, ek_obs* out, uint32_t field_mask,
             ++slot;
         }
     return st;
+}
+
+// The library's observables scratch: a file-scope device array, one copy on each GPU the
+// library runs on (held until the process ends).  Host code uses the address that
+// hipGetSymbolAddress returns on the current device (kept per device and per context), never
+// the array's name, which on the host is only a stand-in.  It holds the per-workgroup partial
+// sums of ek_observables_device: at most kObsScratchBlocks workgroups x 11 values.
+constexpr int kObsValues = 11;
+constexpr unsigned kObsScratchBlocks = 1024;
+constexpr size_t kScratchDoubles = 16384;  // 128 KiB
+static_assert(kObsScratchBlocks * kObsValues <= kScratchDoubles, "observables partials exceed the scratch array");
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// Once per device, with that device current: the device address of the scratch array.
+static ek_status scratch_setup(ek_ctx* c) {
+    int dev = 0;
+    EK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(c, EK_EINVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        EK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    c->obs_scratch = g_scratch_ptr[dev];
+    return EK_OK;
+}
+
+template <typename T>
+static ek_status observe_device_impl(ek_ctx* c, double* d_out) {
+    const unsigned nblk = std::min(site_blocks(c->N), kObsScratchBlocks);
+    if ((size_t)nblk * kObsValues > kScratchDoubles)
+        return fail(c, EK_EINVAL, "observables partials exceed the library's scratch array");
+    launch_observe_strided<T>(c->S, fields<T>(c), nblk, c->obs_scratch, c->st);
+    launch_reduce(c->obs_scratch, nblk, kObsValues, c->obs_max, d_out, c->st);
+    EK_HIP(hipGetLastError());
+    return EK_OK;
+}
+
+extern "C" ek_status ek_observables_device(ek_ctx* c, double* d_out) {
+    if (!c || !c->phi || !c->obs_scratch) return EK_ESTATE;
+    if (!d_out) return fail(c, EK_EINVAL, "null output");
+    return c->esz == 4 ? observe_device_impl<float>(c, d_out) : observe_device_impl<double>(c, d_out);
 }
 
 template <typename T>

@@ -212,6 +212,8 @@ void launch_particle_step(const Scalars& S, const Fields<T>& F, int np, const in
                           double k_h, double eta, int move, hipStream_t st);
 template <typename T> void launch_observe(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
 // the observables from a fixed grid of nblk workgroups (grid-stride), partial sums in red
+template <typename T>
+void launch_observe_strided(const Scalars& S, const Fields<T>& F, unsigned nblk, double* red, hipStream_t st);
 // device-side relative residuals of a solve without host read-back (scal[28..30])
 void launch_track_residual(double* scal, hipStream_t st);
 template <typename T>

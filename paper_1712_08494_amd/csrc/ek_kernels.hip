@@ -2122,6 +2122,17 @@ __global__ __launch_bounds__(kBlock) void k_observe(Scalars S, Fields<T> F) {
     block_reduce_store<11>(v, mx, F.red, blockIdx.x, gridDim.x);
 }
 
+// The same sums from a fixed grid of workgroups striding over the lattice, with the partial
+// sums in `red` (11 x gridDim.x doubles): the scratch does not grow with the lattice.
+template <typename T, int PM>
+__global__ __launch_bounds__(kBlock) void k_observe_strided(Scalars S, Fields<T> F, double* red) {
+    double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < S.N; i += gridDim.x * kBlock)
+        observe_site<T, PM>(S, F, i, v);
+    const bool mx[11] = {false, false, false, false, false, false, false, false, true, false, false};
+    block_reduce_store<11>(v, mx, red, blockIdx.x, gridDim.x);
+}
+
 template <typename T> void launch_observe(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st) {
     const int pm = pop_mode(F);
     if (pm == 0)
@@ -2130,6 +2141,17 @@ template <typename T> void launch_observe(const Scalars& S, const Fields<T>& F, 
         hipLaunchKernelGGL((k_observe<T, 1>), dim3(nblk), dim3(kBlock), 0, st, S, F);
     else
         hipLaunchKernelGGL((k_observe<T, 2>), dim3(nblk), dim3(kBlock), 0, st, S, F);
+}
+
+template <typename T>
+void launch_observe_strided(const Scalars& S, const Fields<T>& F, unsigned nblk, double* red, hipStream_t st) {
+    const int pm = pop_mode(F);
+    if (pm == 0)
+        hipLaunchKernelGGL((k_observe_strided<T, 0>), dim3(nblk), dim3(kBlock), 0, st, S, F, red);
+    else if (pm == 1)
+        hipLaunchKernelGGL((k_observe_strided<T, 1>), dim3(nblk), dim3(kBlock), 0, st, S, F, red);
+    else
+        hipLaunchKernelGGL((k_observe_strided<T, 2>), dim3(nblk), dim3(kBlock), 0, st, S, F, red);
 }
 
 // Relative residuals of a solve run without a host read-back, kept on the device: the start
@@ -2284,6 +2306,7 @@ template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, 
                                           double*, double*, double*, double, double, double, int, hipStream_t);                \
     template void launch_observe<T>(const Scalars&, const Fields<T>&, unsigned, hipStream_t);                  \
     template void launch_add_lo<T>(const T*, double*, unsigned, hipStream_t);                  \
+    template void launch_observe_strided<T>(const Scalars&, const Fields<T>&, unsigned, double*, hipStream_t);                  \
     template void launch_init_ions<T>(const Scalars&, const Fields<T>&, T*, T*, const double*, const double*,  \
                                       hipStream_t);                                                             \
     template void launch_ion_species<T>(const T*, const T*, double*, unsigned, double, hipStream_t);           \

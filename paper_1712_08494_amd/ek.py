@@ -61,7 +61,7 @@ class EKTiming(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double * N_KERNELS), ("kernel_count", ctypes.c_int64 * N_KERNELS)]
 
 
-EXPORTS = ["ek_lattice", "ek_min_image", "ek_kernel_name", "ek_workspace_bytes", "ek_init_ws", "ek_init", "ek_step", "ek_poisson", "ek_observables", "ek_get_field",
+EXPORTS = ["ek_lattice", "ek_min_image", "ek_kernel_name", "ek_workspace_bytes", "ek_init_ws", "ek_observables_device", "ek_init", "ek_step", "ek_poisson", "ek_observables", "ek_get_field",
            "ek_get_populations", "ek_get_particles", "ek_device_bytes", "ek_set_timing", "ek_get_timing",
            "ek_destroy", "ek_status_str", "ek_last_error", "ek_batch_init", "ek_batch_step", "ek_batch_sync",
            "ek_batch_residuals", "ek_batch_replica", "ek_batch_destroy", "ek_batch_last_error",
@@ -111,6 +111,8 @@ def load(path=LIB_PATH):
                              vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     L.ek_init_ws.restype = ctypes.c_int32
     L.ek_observables.argtypes = [vp, ctypes.POINTER(EKObs), ctypes.c_uint32, dp]
+    L.ek_observables_device.argtypes = [vp, vp]
+    L.ek_observables_device.restype = ctypes.c_int32
     L.ek_observables.restype = ctypes.c_int32
     L.ek_get_field.argtypes = [vp, ctypes.c_int32, dp]
     L.ek_get_field.restype = ctypes.c_int32
@@ -329,6 +331,15 @@ class EKSim:
             names = {v: k for k, v in FIELDS.items()}
             out["fields"] = {names[k]: buf[j * self.N:(j + 1) * self.N].reshape(self.shape) for j, k in enumerate(ids)}
         return out
+
+    def observables_device(self, out):
+        """The totals of observables() written by the library into `out`, a contiguous float64
+        GPU tensor of at least 11 values, on the context's stream, with no allocation and no
+        synchronisation (ek_observables_device)."""
+        import torch
+        if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() >= 11):
+            raise TypeError("out must be a contiguous float64 GPU tensor of at least 11 values")
+        self._check(load().ek_observables_device(self._h, ctypes.c_void_p(out.data_ptr())), "ek_observables_device")
 
     def field(self, name):
         out = np.zeros(self.N)
