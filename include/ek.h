@@ -121,6 +121,15 @@ typedef struct ek_params {
                                    plain collision repeat identically every step, and the mass then drifts
                                    linearly (about 5e-9 per step on the walls/interface column).  1: the plain
                                    FP32 collision.  FP64 and the tau = 1 moment state ignore it */
+    int32_t polarization;       /* 1: the external field also polarises the dielectric.  As printed (Sec. II D,
+                                   eq. electric_potential) the potential is sourced by the charge alone and
+                                   E = -grad phi + E_ext, so an ion-free dielectric feels no Kelvin force in a
+                                   uniform field.  With 1 the solve imposes Gauss's law on the total
+                                   displacement eps (-grad phi + E_ext) through every face: the source gains
+                                   -sum over the six faces of eps_face (E_ext . c_d).  Needed for the dielectric
+                                   droplet of Sec. III B.  Not with EK_POISSON_FFT, reverse mode, or walls with
+                                   E_ext[2] != 0 (the wall faces carry no displacement) (EK_EINVAL).
+                                   0 (default): the printed model */
 } ek_params;
 
 typedef struct ek_particle {

@@ -20,7 +20,9 @@
  *      virtual densities on solid sites next to fluid     (Sec. II E, Jansen et al.)
  *   2. charge and permittivity                            (Sec. II B eq. electric_potential,
  *                                                          eq. dielectric_constant; Sec. II E)
- *   3. variable-permittivity Poisson solve                (Sec. II D, eq. electric_potential)
+ *   3. variable-permittivity Poisson solve                (Sec. II D, eq. electric_potential;
+ *                                                          option: the polarisation source, a
+ *                                                          reading for Sec. III B, poisson_source)
  *   4. electric field E = -grad(phi) + E_ext              (Sec. II B)
  *   5. link fluxes and Nernst-Planck update               (Sec. II B eq. nernst-planck-disc,
  *                                                          upwind advection; Sec. II E
@@ -91,6 +93,7 @@ typedef struct {
     double poisson_tol;
     double particle_rho, k_hertz, eta;
     int32_t poisson_lagged;   /* 1: each step takes the lagged Fourier scheme of Sec. II D (periodic) */
+    int32_t polarization;     /* 1: the external field also polarises the dielectric (see poisson_source) */
 } or_params;
 
 typedef struct {
@@ -390,7 +393,15 @@ static void dom_shift(or_state* s, double* a, double by) {
     }
 }
 
-/* Source b with M phi = b, M = -A: b = q + wall charge in the adjacent layers, mean removed. */
+/* Source b with M phi = b, M = -A: b = q + wall charge in the adjacent layers, mean removed.
+   Reading (option `polarization`, off by default): as printed, the potential is sourced by
+   the charge alone and the field is E = -grad(phi) + E_ext, so an ion-free dielectric in a
+   uniform external field stays unpolarised and feels no Kelvin force.  The droplet
+   experiment of Sec. III B needs the field of the polarised medium.  With the option, Gauss's
+   law holds for the total displacement eps (-grad phi + E_ext) through every face:
+     sum_faces eps_f (phi_j - phi_i) = -(q_i - sum_faces eps_f (E_ext . c_d)),
+   i.e. the source gains -sum over the six faces of eps_f (E_ext . c_d) (zero where eps is
+   uniform; its sum over the domain vanishes). */
 static void poisson_source(or_state* s, double* b) {
     const or_params* p = &s->p;
     for (int64_t i = 0; i < s->N; ++i) b[i] = 0.0;
@@ -402,6 +413,14 @@ static void poisson_source(or_state* s, double* b) {
                 double v = s->q[i];
                 if (p->walls_z && z == 1) v += p->sigma_wall[0];
                 if (p->walls_z && z == p->nz - 2) v += p->sigma_wall[1];
+                if (p->polarization)
+                    for (int d = 1; d <= 6; ++d) {
+                        int zz = z + OC[d][2];
+                        if (p->walls_z && !in_domain(p, zz)) continue;
+                        int64_t j = IDX(p, wrap(x + OC[d][0], p->nx), wrap(y + OC[d][1], p->ny), wrap(zz, p->nz));
+                        double ef = 0.5 * (s->eps[i] + s->eps[j]);
+                        v -= ef * (p->E_ext[0] * OC[d][0] + p->E_ext[1] * OC[d][1] + p->E_ext[2] * OC[d][2]);
+                    }
                 b[i] = v;
             }
     }
@@ -870,6 +889,9 @@ or_state* or_create(const or_params* prm, const double* rho_a, const double* rho
                     const double* n_minus, const double* particles, int32_t n_particles) {
     lattice_setup();
     if (prm->poisson_lagged && prm->walls_z) return NULL; /* the lagged Fourier scheme is periodic */
+    if (prm->poisson_lagged && prm->polarization) return NULL; /* its right-hand side has no polarisation term */
+    /* with walls the wall faces carry no displacement, so a polarising field normal to them is undefined */
+    if (prm->polarization && prm->walls_z && prm->E_ext[2] != 0.0) return NULL;
     or_state* s = (or_state*)calloc(1, sizeof(or_state));
     s->p = *prm;
     set_threads(&s->p);

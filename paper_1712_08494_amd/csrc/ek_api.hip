@@ -1297,6 +1297,8 @@ static ek_status configure(ek_ctx* c, const ek_params* p, const ek_particle* par
     S.G_p = p->dmu[0] == 0.0 ? 0.0 : p->solvation_sign * p->dmu[0] / (p->drho_a * cs2);
     S.G_m = p->dmu[1] == 0.0 ? 0.0 : p->solvation_sign * p->dmu[1] / (p->drho_a * cs2);
     S.ion_sc = (S.G_p != 0.0 || S.G_m != 0.0);
+    if (p->polarization != 0 && p->polarization != 1) return fail(c, EK_EINVAL, "polarization must be 0 or 1");
+    S.polar = p->polarization;
     S.eps_a = p->eps_a;
     S.eps_b = p->eps_b;
     S.eps_p = p->eps_p;
@@ -1314,6 +1316,10 @@ static ek_status configure(ek_ctx* c, const ek_params* p, const ek_particle* par
     // The lagged scheme is a fixed-point iteration with one sweep per step; at the particle
     // surfaces (eps_p / eps_f = 1/8 in the paper's colloids) its error amplification exceeds
     // one and the potential diverges (on the CPU oracle as well), so it is not offered there.
+    if (p->poisson_solver == EK_POISSON_FFT && p->polarization)
+        return fail(c, EK_EINVAL, "the lagged Fourier scheme has no polarisation source");
+    if (p->polarization && p->walls_z && p->E_ext[2] != 0.0)
+        return fail(c, EK_EINVAL, "the wall faces carry no displacement: a polarising field normal to the walls is undefined");
     if (p->poisson_solver == EK_POISSON_FFT && n_parts > 0)
         return fail(c, EK_EINVAL, "the lagged Fourier scheme diverges at resolved particles; use EK_POISSON_MG or SOR");
     c->fft = p->poisson_solver == EK_POISSON_FFT;
@@ -1498,6 +1504,7 @@ static ek_status adj_check(ek_ctx* c) {
     if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: no reverse mode");
     if (c->esz != 8) return fail(c, EK_EINVAL, "reverse mode needs an FP64 context");
     if (c->S.walls || c->np > 0) return fail(c, EK_EINVAL, "reverse mode covers periodic lattices without particles");
+    if (c->S.polar) return fail(c, EK_EINVAL, "reverse mode does not cover the polarisation source");
     if (c->moment_state) return fail(c, EK_EINVAL, "reverse mode needs stored populations (moment_state = 0)");
     if (c->fft) return fail(c, EK_EINVAL, "reverse mode differentiates a converged Poisson solve, not the lagged one");
     return EK_OK;

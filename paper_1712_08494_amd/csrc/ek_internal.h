@@ -21,6 +21,7 @@ struct Scalars {
     int colloids;     // per-site geometry arrays present
     int kelvin;       // eps_a != eps_b: Kelvin force active
     int ion_sc;       // solvation Shan-Chen coupling active
+    int polar;        // the external field polarises the dielectric (Poisson source term)
     int z0, z1;       // Poisson domain in z (inclusive)
     unsigned ndomain; // sites in the Poisson domain
     int ncolor;       // colours of a lattice Gauss-Seidel sweep: 2, or 3 with an odd periodic y or z axis

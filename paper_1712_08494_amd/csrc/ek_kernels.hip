@@ -455,17 +455,20 @@ __device__ __forceinline__ void poisson_row_v(unsigned i, int x, int y, int z, c
     const double ei = (double)F.eps[i];
     diag = 0.0;
     offsum = 0.0;
+    double pol = 0.0;  // sum over the faces of eps_f (E_ext . c_d): the polarisation source
     if (S.nx > 1) {
         const unsigned a = i + (x == 0 ? S.nx - 1 : -1), b = i + (x == S.nx - 1 ? -(S.nx - 1) : 1);
         const double ea = 0.5 * (ei + (double)F.eps[a]), eb = 0.5 * (ei + (double)F.eps[b]);
         diag += ea + eb;
         offsum += ea * pv(a, nb, -1, 0, 0) + eb * pv(b, nb, 1, 0, 0);
+        pol += S.E_ext[0] * (eb - ea);
     }
     if (S.ny > 1) {
         const unsigned a = i + (y == 0 ? (S.ny - 1) * S.nx : -S.nx), b = i + (y == S.ny - 1 ? -(S.ny - 1) * S.nx : S.nx);
         const double ea = 0.5 * (ei + (double)F.eps[a]), eb = 0.5 * (ei + (double)F.eps[b]);
         diag += ea + eb;
         offsum += ea * pv(a, nb, 0, -1, 0) + eb * pv(b, nb, 0, 1, 0);
+        pol += S.E_ext[1] * (eb - ea);
     }
     if (S.nz > 1) {
         if (!(S.walls && z == S.z0)) {
@@ -473,17 +476,20 @@ __device__ __forceinline__ void poisson_row_v(unsigned i, int x, int y, int z, c
             const double ea = 0.5 * (ei + (double)F.eps[a]);
             diag += ea;
             offsum += ea * pv(a, nb, 0, 0, -1);
+            pol -= S.E_ext[2] * ea;
         }
         if (!(S.walls && z == S.z1)) {
             const unsigned b = i + (z == S.nz - 1 ? -(S.nz - 1) * S.nxy : S.nxy);
             const double eb = 0.5 * (ei + (double)F.eps[b]);
             diag += eb;
             offsum += eb * pv(b, nb, 0, 0, 1);
+            pol += S.E_ext[2] * eb;
         }
     }
     double s = (double)F.q[cidx<SP>(S, i, own)];
     if (S.walls && z == S.z0) s += S.sigma0;
     if (S.walls && z == S.z1) s += S.sigma1;
+    if (S.polar) s -= pol;
     src = s - F.scal[0];
 }
 
@@ -900,30 +906,35 @@ __device__ __forceinline__ void restrict_fine_body(const Scalars& S, const Field
                 const int z = zs[c];
                 if (z < S.z0 || z > S.z1) continue;
                 const double ei = (double)E[c][b][a];
-                double diag = 0.0, off = 0.0;
+                double diag = 0.0, off = 0.0, pol = 0.0;
                 {
                     const double ea = 0.5 * (ei + (double)E[c][b][a - 1]), eb = 0.5 * (ei + (double)E[c][b][a + 1]);
                     diag += ea + eb;
                     off += ea * P[c][b][a - 1] + eb * P[c][b][a + 1];
+                    pol += S.E_ext[0] * (eb - ea);
                 }
                 {
                     const double ea = 0.5 * (ei + (double)E[c][b - 1][a]), eb = 0.5 * (ei + (double)E[c][b + 1][a]);
                     diag += ea + eb;
                     off += ea * P[c][b - 1][a] + eb * P[c][b + 1][a];
+                    pol += S.E_ext[1] * (eb - ea);
                 }
                 if (!(S.walls && z == S.z0)) {
                     const double ea = 0.5 * (ei + (double)E[c - 1][b][a]);
                     diag += ea;
                     off += ea * P[c - 1][b][a];
+                    pol -= S.E_ext[2] * ea;
                 }
                 if (!(S.walls && z == S.z1)) {
                     const double eb = 0.5 * (ei + (double)E[c + 1][b][a]);
                     diag += eb;
                     off += eb * P[c + 1][b][a];
+                    pol += S.E_ext[2] * eb;
                 }
                 double src = (double)F.q[cidx<SP>(S, at(a, b, c), col(a, b, c))];
                 if (S.walls && z == S.z0) src += S.sigma0;
                 if (S.walls && z == S.z1) src += S.sigma1;
+                if (S.polar) src -= pol;
                 src -= mean;
                 sum += src + off - diag * P[c][b][a];
             }

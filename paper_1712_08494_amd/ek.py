@@ -33,7 +33,7 @@ class EKParams(ctypes.Structure):
         ("poisson_tol", ctypes.c_double), ("sor_omega", ctypes.c_double), ("particle_rho", ctypes.c_double),
         ("k_hertz", ctypes.c_double), ("eta", ctypes.c_double), ("phi_history", ctypes.c_int32),
         ("moment_state", ctypes.c_int32), ("sweep_band", ctypes.c_int32), ("poisson_cycles", ctypes.c_int32),
-        ("fp32_plain_collision", ctypes.c_int32),
+        ("fp32_plain_collision", ctypes.c_int32), ("polarization", ctypes.c_int32),
     ]
 
 
@@ -219,6 +219,7 @@ def params_from_config(cfg):
     p.sweep_band = int(getattr(cfg, "sweep_band", 0))
     p.poisson_cycles = int(getattr(cfg, "poisson_cycles", 0))
     p.fp32_plain_collision = int(bool(getattr(cfg, "fp32_plain_collision", False)))
+    p.polarization = int(bool(getattr(cfg, "polarization", False)))
     return p
 
 

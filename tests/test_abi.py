@@ -67,20 +67,21 @@ def test_min_image_closed_form_equals_stepping():
         assert np.isnan(L.ek_min_image(bad, 64))
 
 
-def _init_status(cfg, inp):
+def _init_status(cfg, inp, params=None):
     """ek_init's status for a configuration that fails its argument checks, which run
     before any device call (so this needs no GPU)."""
     import ctypes
     L = ek.load()
-    p = ek.params_from_config(cfg)
-    arr = (ek.EKParticle * len(inp.particles))()
-    for j, row in enumerate(inp.particles):
+    p = ek.params_from_config(cfg) if params is None else params
+    parts = inp.particles if inp.particles is not None else np.zeros((0, 8))
+    arr = (ek.EKParticle * len(parts))()
+    for j, row in enumerate(parts):
         for k in range(3):
             arr[j].x[k], arr[j].v[k] = row[k], row[3 + k]
         arr[j].radius, arr[j].charge = row[6], row[7]
     h = ctypes.c_void_p()
     a = [np.ascontiguousarray(x, dtype=np.float64) for x in (inp.rho_a, inp.rho_b, inp.n_plus, inp.n_minus)]
-    st = L.ek_init(ctypes.byref(p), *[ek._dp(x) for x in a], arr, len(inp.particles), None, ctypes.byref(h))
+    st = L.ek_init(ctypes.byref(p), *[ek._dp(x) for x in a], arr, len(parts), None, ctypes.byref(h))
     msg = L.ek_last_error(h).decode() if h else ""
     L.ek_destroy(h)
     return st, msg
@@ -100,6 +101,24 @@ def test_init_rejects_non_finite_particles_and_fft_with_particles():
     cfg.poisson_solver = "fft"
     st, msg = _init_status(cfg, inp)
     assert st == ek.EK_EINVAL and "lagged Fourier" in msg, msg
+
+
+def test_init_rejects_polarization_where_undefined():
+    """The polarisation source is refused with the lagged Fourier scheme (whose right-hand
+    side has no such term), with a field normal to walls (the wall faces carry no
+    displacement) and with a flag other than 0 or 1; checked before any device work."""
+    from paper_1712_08494_amd import workloads as wl
+    cfg = wl.EKConfig(16, 16, 16, polarization=True, E_ext=(0.0, 0.0, 1e-3), poisson_solver="fft")
+    st, msg = _init_status(cfg, wl.uniform(cfg))
+    assert st == ek.EK_EINVAL and "polarisation" in msg, msg
+    cfg = wl.EKConfig(16, 16, 16, walls_z=True, polarization=True, E_ext=(0.0, 0.0, 1e-3))
+    st, msg = _init_status(cfg, wl.uniform(cfg))
+    assert st == ek.EK_EINVAL and "normal to the walls" in msg, msg
+    cfg = wl.EKConfig(16, 16, 16, polarization=True)
+    p = ek.params_from_config(cfg)
+    p.polarization = 2
+    st, msg = _init_status(cfg, wl.uniform(cfg), params=p)
+    assert st == ek.EK_EINVAL and "polarization" in msg, msg
 
 
 def test_workspace_bytes_is_a_host_computation():

@@ -1,0 +1,58 @@
+"""GPU parity of the polarisation option (the Poisson source of the external field's
+displacement, a reading for the dielectric drop of Sec. III B) against the oracle: the
+ion-free quasi-2D drop with multigrid and with SOR, FP64 and FP32, and a 3-D drop with
+ions, where the multigrid runs on colour-split copies and coarse grids."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1712_08494_amd import ek
+from paper_1712_08494_amd import workloads as wl
+from tests.parity import compare, phi_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    ek.load()
+    torch.cuda.init()
+    yield
+
+
+@pytest.mark.parametrize("precision,solver", [("fp64", "mg"), ("fp32", "mg"), ("fp64", "sor")])
+def test_quasi2d_dielectric_drop(precision, solver):
+    cfg, inp = wl.dielectric_droplet(l=32, lx=4, chi=0.5, field=0.05, precision=precision)
+    cfg.poisson_solver = solver
+    cfg.poisson_tol = 1e-12
+    print(f"dielectric drop 4x32x32 {precision} {solver}, 20 steps", flush=True)
+    sim, o = ek.EKSim(cfg, inp), orc.Oracle(cfg, inp)
+    # the polarisation potential is there from the start
+    assert np.abs(o.field("phi")).max() > 1e-2
+    # FP32 keeps the permittivity in FP32 (relative rounding 6e-8)
+    assert phi_err(sim.field("phi"), o.field("phi")) < (1e-9 if precision == "fp64" else 1e-6)
+    sim.step(20)
+    o.step(20)
+    errs = compare(sim, o, precision, f"drop {precision} {solver}")
+    print(f"  errors {errs}", flush=True)
+    sim.close()
+    o.close()
+
+
+def test_3d_drop_with_ions_multigrid():
+    cfg, inp = wl.droplet(32, precision="fp64", field=2e-3)
+    cfg.polarization = True
+    cfg.eps_b = 0.5 * cfg.eps_a
+    cfg.poisson_tol = 1e-12
+    print("3-D drop 32^3 with ions, polarisation, fp64, 15 steps", flush=True)
+    sim, o = ek.EKSim(cfg, inp), orc.Oracle(cfg, inp)
+    assert sim.observables()["poisson_mg_levels"] >= 3
+    sim.step(15)
+    o.step(15)
+    errs = compare(sim, o, "fp64", "3-D drop")
+    print(f"  errors {errs}", flush=True)
+    sim.close()
+    o.close()
