@@ -295,6 +295,16 @@ ek_status ek_step(struct ek_ctx* ctx, int32_t nsteps);
    context keeps them in site order instead (a diagnostic: the results are bit-identical). */
 ek_status ek_poisson(struct ek_ctx* ctx, double tol, int32_t maxit, int32_t* iters, double* rel_res);
 
+/* Change the external field E_ext (3 doubles, lattice units) of a running context; it takes
+   effect from the next step.  The paper's drop experiments relax the fluid without a field
+   and then apply one, and let a deformed drop relax back after switching it off (Sec. III B);
+   restarting a context from its densities instead would reset the populations to
+   equilibrium.  The next Poisson solve starts from the potentials of the old field.  Reverse-
+   mode checkpoints taken before the change are dropped.  Errors: EK_ESTATE (no context, or
+   a replica of a batch), EK_EINVAL (null or non-finite field; a polarising field normal to
+   walls). */
+ek_status ek_set_field(struct ek_ctx* ctx, const double* E_ext);
+
 /* Shape of the multigrid V-cycle (contexts whose lattice the multigrid coarsens): red-black
    Gauss-Seidel sweeps before and after the coarse-grid correction on the lattice itself
    (fine_pre, fine_post), on the coarse grids smoothed by separate launches (coarse_pre,

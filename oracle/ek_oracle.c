@@ -692,7 +692,12 @@ static void advect_and_update_ions(or_state* s) {
 /* pseudopotentials count only on LB-fluid neighbours.                              */
 /* Friction (eq. frictionforce) from the discrete fluxes, half the sum over the six  */
 /* links of the site: F_fr = (1/(beta D)) (1/2) sum_{Q6} sum_+- J c_d.                */
-/* Kelvin (eq. kelvin), central form: F_K = -((eps_f - eps_bar)/4) sum_{Q6} E^2(i+d) c_d.*/
+/* Kelvin (Sec. II C), central form: F_K = +((eps_f - eps_bar)/4) sum_{Q6} E^2(i+d) c_d.   */
+/* Reading: eq. kelvin prints -(eps - eps_bar)/2 grad E^2, but the Landau form it is     */
+/* derived from, -E^2 grad(eps)/2 + grad(E^2 phi d eps/d phi)/2 with the permittivity law */
+/* (phi d eps/d phi = eps - eps_bar), gives +(eps - eps_bar)/2 grad E^2, and the discrete */
+/* total force of Sec. II E carries the plus sign.  The plus sign is taken: with it the  */
+/* dielectric drop of Sec. III B elongates along the field, as reported there.           */
 /* Reading: the non-Shan-Chen forces (and the body force rho g) are split between    */
 /* the components by mass fraction rho^s / rho.                                     */
 /* ------------------------------------------------------------------------------ */
@@ -729,7 +734,7 @@ static void compute_forces(or_state* s) {
                     int64_t up = IDX(p, wrap(x + (k == 0), p->nx), wrap(y + (k == 1), p->ny), wrap(z + (k == 2), p->nz));
                     double E2u = s->E[3 * up] * s->E[3 * up] + s->E[3 * up + 1] * s->E[3 * up + 1] + s->E[3 * up + 2] * s->E[3 * up + 2];
                     double E2m = s->E[3 * m] * s->E[3 * m] + s->E[3 * m + 1] * s->E[3 * m + 1] + s->E[3 * m + 2] * s->E[3 * m + 2];
-                    FK[k] = -0.25 * (s->epsf[i] - ebar) * (E2u - E2m);
+                    FK[k] = 0.25 * (s->epsf[i] - ebar) * (E2u - E2m);
                 }
                 double ra = s->rho[0][i], rb = s->rho[1][i], rt = ra + rb;
                 for (int k = 0; k < 3; ++k) {
@@ -1073,6 +1078,14 @@ void or_set_state(or_state* s, const double* fa, const double* fb, const double*
             }
     compute_moments(s);
     compute_charge_perm(s);
+}
+
+/* Change the external field between steps (the drop experiments of Sec. III B relax the
+   fluid before a field is applied).  Returns -1 where the field is undefined. */
+int or_set_field(or_state* s, const double* E_ext) {
+    if (s->p.polarization && s->p.walls_z && E_ext[2] != 0.0) return -1;
+    for (int k = 0; k < 3; ++k) s->p.E_ext[k] = E_ext[k];
+    return 0;
 }
 
 /* particles out: n x 9 doubles (x, y, z, vx, vy, vz, Fx, Fy, Fz of the last step) */

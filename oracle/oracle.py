@@ -83,6 +83,8 @@ def lib():
         L.or_get_field.restype = ctypes.c_int
         L.or_get_populations.argtypes = [ctypes.c_void_p, ctypes.c_int32, dp]
         L.or_set_state.argtypes = [ctypes.c_void_p, dp, dp, dp, dp, dp, dp]
+        L.or_set_field.argtypes = [ctypes.c_void_p, dp]
+        L.or_set_field.restype = ctypes.c_int
         L.or_get_particles.argtypes = [ctypes.c_void_p, dp]
         L.or_observables.argtypes = [ctypes.c_void_p, dp]
         L.or_lattice.argtypes = [ctypes.POINTER(ctypes.c_int32), dp]
@@ -205,6 +207,11 @@ class Oracle:
             parts = _c64(particles)
             pp = _dp(parts)
         lib().or_set_state(self._h, _dp(fa), _dp(fb), _dp(npl), _dp(nmi), _dp(ph), pp)
+
+    def set_field(self, E_ext):
+        e = _c64(np.asarray(E_ext, dtype=float).reshape(3))
+        if lib().or_set_field(self._h, _dp(e)) != 0:
+            raise ValueError("oracle: field undefined for this configuration")
 
     def particles(self):
         out = np.zeros((max(self.np, 1), 9))

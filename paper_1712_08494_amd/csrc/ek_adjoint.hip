@@ -11,7 +11,7 @@
 //   the physical velocity U = u' + (Phi^a + Phi^b) / (2 rho)
 //   Phi^a = -psi^a S^a + (rho^a / rho) F,  Phi^b = -psi^b G S^b + (rho^b / rho) F,
 //   S^a = sum_d w_d chi_a(i+d) c_d, S^b = sum_d w_d psi^a(i+d) c_d, chi_a = G psi^b + G+ n+ + G- n-,
-//   F = (1 / (2 beta D)) sum_{Q6} sum_+- J c_d - ((eps - eps_bar)/4) sum_{Q6} |E(i+d)|^2 c_d + rho g
+//   F = (1 / (2 beta D)) sum_{Q6} sum_+- J c_d + ((eps - eps_bar)/4) sum_{Q6} |E(i+d)|^2 c_d + rho g
 //   n(t+1) = n - sum_{Q6} (J + A),  f* = f - (f - f~(rho^s, u' + tau Phi^s / rho^s)) / tau,
 //   f(i + c_d, t+1) = f*_d(i)
 // The reverse step transposes these in the opposite order.  Gather form throughout (no
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_force(Scalars S, Fields<double> 
                 js += Jh + Jl;
             }
             dK[k] = efield_sq_at(hi, F.phi, S) - efield_sq_at(lo, F.phi, S);
-            Fr[k] = js / (2.0 * S.beta * S.D) - 0.25 * (ef - S.eps_bar) * dK[k] + rt * S.g_body[k];
+            Fr[k] = js / (2.0 * S.beta * S.D) + 0.25 * (ef - S.eps_bar) * dK[k] + rt * S.g_body[k];
         }
         double P[2][3];
         for (int k = 0; k < 3; ++k) {
@@ -207,8 +207,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_force(Scalars S, Fields<double> 
             red[1] += lP[1][k] * (-psb * sb[k]);
             lrho[0] += Fr[k] * rb * (lP[0][k] - lP[1][k]) / (rt * rt) + lF * S.g_body[k];
             lrho[1] += Fr[k] * ra * (lP[1][k] - lP[0][k]) / (rt * rt) + lF * S.g_body[k];
-            leps -= 0.25 * lF * dK[k];
-            red[0] += 0.25 * lF * dK[k];
+            leps += 0.25 * lF * dK[k];
+            red[0] -= 0.25 * lF * dK[k];
         }
         lrho[0] += lpsa * exp(-ra / S.rho0);
         lrho[1] += lpsb * exp(-rb / S.rho0);
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_links(Scalars S, Fields<double> 
                 lrho[0] -= lJ * S.D * kap[sp] * Ss;
             }
             // Kelvin force of the neighbours: F_K(i - e_k) reads +|E(i)|^2, F_K(i + e_k) reads -|E(i)|^2
-            kel += -0.25 * (F.eps[lo] - S.eps_bar) * aFl + 0.25 * (F.eps[hi] - S.eps_bar) * aFh;
+            kel += 0.25 * (F.eps[lo] - S.eps_bar) * aFl - 0.25 * (F.eps[hi] - S.eps_bar) * aFh;
         }
         for (int k = 0; k < 3; ++k) {
             lE[k] += 2.0 * efield(k, x, y, z, F.phi, S) * kel;

@@ -1772,6 +1772,20 @@ static void apply_shape(ek_ctx* c, const CycleShape& sh) {
     vcycle_graph_drop(c);  // the captured cycle has the old shape
 }
 
+extern "C" ek_status ek_set_field(ek_ctx* c, const double* E_ext) {
+    if (!c || !c->phi) return EK_ESTATE;
+    if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: its field is fixed by the batch");
+    if (!E_ext) return fail(c, EK_EINVAL, "null field");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(E_ext[k])) return fail(c, EK_EINVAL, "the field must be finite");
+    if (c->S.polar && c->S.walls && E_ext[2] != 0.0)
+        return fail(c, EK_EINVAL, "the wall faces carry no displacement: a polarising field normal to the walls is undefined");
+    for (int k = 0; k < 3; ++k) c->S.E_ext[k] = c->p.E_ext[k] = E_ext[k];
+    vcycle_graph_drop(c);  // the captured cycle holds the old field in its kernel arguments
+    c->adj.valid = false;  // checkpoints of a run with the old field cannot be recomputed
+    return EK_OK;
+}
+
 extern "C" ek_status ek_set_multigrid(ek_ctx* c, int32_t fine_pre, int32_t fine_post, int32_t coarse_pre,
                                       int32_t coarse_post, int32_t tail_pre, int32_t tail_post,
                                       int32_t coarsest_sweeps, double omega) {

@@ -1735,7 +1735,10 @@ __device__ __forceinline__ void site_links(unsigned i, int z, const Nbr& o, bool
 // Forces on both fluid components at fluid site i (Sec. II C):
 //   Phi^a = -psi^a sum_d w_d chi_a(i+d) c_d + (rho^a/rho) F,   chi_a = G psi^b + G_a+ n+ + G_a- n-
 //   Phi^b = -psi^b sum_d w_d G psi^a(i+d) c_d + (rho^b/rho) F
-//   F = (1/(2 beta D)) sum_{Q6} sum_+- J c_d  -  ((eps_f - eps_bar)/4) sum_{Q6} E^2(i+d) c_d  +  rho g
+//   F = (1/(2 beta D)) sum_{Q6} sum_+- J c_d  +  ((eps_f - eps_bar)/4) sum_{Q6} E^2(i+d) c_d  +  rho g
+// The Kelvin term takes the sign of the discrete total force of Sec. II E and of the Landau
+// form that eq. kelvin is derived from (+(eps - eps_bar)/2 grad E^2); eq. kelvin itself
+// prints a minus sign.
 template <typename T>
 __device__ __forceinline__ void site_forces(unsigned i, const Nbr& o, T ra, T rb, const T (&jsum)[3],
                                             const double (&El)[3], const double (&Eh)[3], const Scalars& S,
@@ -1778,7 +1781,7 @@ __device__ __forceinline__ void site_forces(unsigned i, const Nbr& o, T ra, T rb
         const double e2_my = sq(-0.5 * (pxmy - mxmy) + ex, El[1], -0.5 * (mypz - mymz) + ez);
         const double e2_pz = sq(-0.5 * (pxpz - mxpz) + ex, -0.5 * (pypz - mypz) + ey, Eh[2]);
         const double e2_mz = sq(-0.5 * (pxmz - mxmz) + ex, -0.5 * (pymz - mymz) + ey, El[2]);
-        const T fac = T(-0.25) * (eps_fluid<T>(ra, rb, S) - T(S.eps_bar));
+        const T fac = T(0.25) * (eps_fluid<T>(ra, rb, S) - T(S.eps_bar));
         FK[0] = fac * (T)(e2_px - e2_mx);
         FK[1] = fac * (T)(e2_py - e2_my);
         FK[2] = fac * (T)(e2_pz - e2_mz);

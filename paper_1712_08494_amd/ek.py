@@ -6,6 +6,7 @@ PyTorch supplies the HIP stream the context runs on (its current stream by defau
 """
 import ctypes
 import os
+from dataclasses import replace
 
 import numpy as np
 
@@ -65,7 +66,7 @@ EXPORTS = ["ek_lattice", "ek_min_image", "ek_kernel_name", "ek_workspace_bytes",
            "ek_get_populations", "ek_get_particles", "ek_device_bytes", "ek_set_timing", "ek_get_timing",
            "ek_destroy", "ek_status_str", "ek_last_error", "ek_batch_init", "ek_batch_step", "ek_batch_sync",
            "ek_batch_residuals", "ek_batch_replica", "ek_batch_destroy", "ek_batch_last_error",
-           "ek_forward_ckpt", "ek_adjoint", "ek_set_multigrid", "ek_autotune_candidates",
+           "ek_forward_ckpt", "ek_adjoint", "ek_set_field", "ek_set_multigrid", "ek_autotune_candidates",
            "ek_autotune_multigrid"]
 
 _lib = None
@@ -152,6 +153,8 @@ def load(path=LIB_PATH):
     L.ek_forward_ckpt.restype = ctypes.c_int32
     L.ek_adjoint.argtypes = [vp, vp, vp, dp, vp, vp]
     L.ek_adjoint.restype = ctypes.c_int32
+    L.ek_set_field.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.ek_set_field.restype = ctypes.c_int32
     L.ek_set_multigrid.argtypes = [vp] + [ctypes.c_int32] * 7 + [ctypes.c_double]
     L.ek_set_multigrid.restype = ctypes.c_int32
     L.ek_autotune_candidates.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
@@ -377,6 +380,12 @@ class EKSim:
         L = load()
         self._check(L.ek_get_timing(self._h, ctypes.byref(t)), "ek_get_timing")
         return {L.ek_kernel_name(k).decode(): (t.kernel_ms[k], t.kernel_count[k]) for k in range(N_KERNELS)}
+
+    def set_field(self, E_ext):
+        """Change the external field from the next step on (ek_set_field)."""
+        e = (ctypes.c_double * 3)(*[float(v) for v in E_ext])
+        self._check(load().ek_set_field(self._h, e), "ek_set_field")
+        self.cfg = replace(self.cfg, E_ext=tuple(float(v) for v in E_ext))
 
     def set_multigrid(self, fine_pre=1, fine_post=2, coarse_pre=1, coarse_post=2, tail_pre=3, tail_post=3,
                       coarsest=10, omega=1.2):

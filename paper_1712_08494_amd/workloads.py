@@ -273,12 +273,14 @@ def droplet(L, seed=4, precision="fp32", field=1e-4, salt=1e-3, G=3.6, dmu=-4.0,
     return cfg, EKInputs(rho_a, rho_b, n.copy(), n.copy())
 
 
-def dielectric_droplet(l=128, lx=4, radius=None, chi=0.5, field=0.05, precision="fp64", seed=6, width=2.0):
+def dielectric_droplet(l=128, lx=4, radius=None, chi=0.5, field=0.05, precision="fp64", seed=6, width=2.0,
+                       noise=1e-4):
     """The ion-free dielectric drop of Sec. III B: a quasi-two-dimensional periodic box
     lx x l x l, a cylinder of fluid b (radius l/4 unless given) along x in fluid a, the two
     bulk densities of the flat-interface calibration at G = 4.0, tanh profile of the given
-    width, rho noise 1e-4.  Permittivity contrast chi = (eps_a - eps_b) / (eps_a + eps_b)
-    with eps_a the fluid default; the field E_z polarises the dielectric."""
+    width, uniform rho noise of the given amplitude.  Permittivity contrast
+    chi = (eps_a - eps_b) / (eps_a + eps_b) with eps_a the fluid default; the field E_z
+    polarises the dielectric."""
     eps_b = EPS_FLUID * (1.0 - chi) / (1.0 + chi)
     cfg = EKConfig(lx, l, l, precision=precision, G=WALL_G, eps_a=EPS_FLUID, eps_b=eps_b, E_ext=(0.0, 0.0, field),
                    polarization=True, poisson_tol=1e-10, name=f"dielectric_droplet_{lx}x{l}x{l}")
@@ -288,8 +290,8 @@ def dielectric_droplet(l=128, lx=4, radius=None, chi=0.5, field=0.05, precision=
     d = np.hypot(y - l / 2 + 0.5, z - l / 2 + 0.5)
     R = l / 4.0 if radius is None else float(radius)
     inside = (0.5 * (1.0 - np.tanh((d - R) / width)))[:, :, None]
-    rho_a = WALL_RHO_MAJ + (WALL_RHO_MIN - WALL_RHO_MAJ) * inside + r.uniform(-1e-4, 1e-4, sh)
-    rho_b = WALL_RHO_MIN + (WALL_RHO_MAJ - WALL_RHO_MIN) * inside + r.uniform(-1e-4, 1e-4, sh)
+    rho_a = WALL_RHO_MAJ + (WALL_RHO_MIN - WALL_RHO_MAJ) * inside + r.uniform(-noise, noise, sh)
+    rho_b = WALL_RHO_MIN + (WALL_RHO_MAJ - WALL_RHO_MIN) * inside + r.uniform(-noise, noise, sh)
     zero = np.zeros(sh)
     return cfg, EKInputs(rho_a, rho_b, zero.copy(), zero.copy())
 

@@ -1,0 +1,118 @@
+"""The dielectric drop of Sec. III B against the small-deformation closed form
+(eq. droplet_deformation): delta_th = eps_a r_d chi^2 E_z^2 / (4 gamma).
+
+A quasi-two-dimensional periodic box 4 x 128 x 128 holds a cylinder of fluid b of radius
+32 in fluid a (G = 4.0, no ions, no noise).  It relaxes without a field for 2 x 10^4 steps;
+the field E_z is then switched on in the same context (ek_set_field, the polarisation
+source on) for 2.4 x 10^4 steps, after which the shape no longer changes.  As in the
+paper, the undeformed radius and the surface tension come from the relaxed state: the
+radius from the interface positions, gamma from the Young-Laplace law dp = gamma / r_d in
+two dimensions with the pressure of the Shan-Chen equation of state (eq. eqofstate) at the
+drop's centre and at the farthest point of the box.  The half-lengths a (along y) and b
+(along z) are the zero crossings of the concentration c = (rho_b - rho_a) / (rho_a + rho_b)
+along the two axes through the drop's centre, located by a tanh fit to the profile next to
+the interface; delta = (b - a) / (b + a).
+
+The paper finds agreement for fields below 0.1 and radii of at least 30 sites, and a
+normalised deformation independent of the field.  Measured here: delta / delta_th = 1.05
+(chi = 0.5, E_z = 0.1) and 0.93 / 0.94 (chi = 0.9, E_z = 0.05 / 0.1); the bound is 10 %.
+Without a field the drop stays round (|delta| ~ 2e-12).
+"""
+import numpy as np
+import pytest
+
+from paper_1712_08494_amd import ek
+from paper_1712_08494_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+L, RELAX, RUN = 128, 20000, 24000
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    ek.load()
+    torch.cuda.init()
+    yield
+
+
+def interface(profile, guess):
+    """Sub-lattice zero crossing of a concentration profile next to `guess` (tanh fit)."""
+    from scipy.optimize import curve_fit
+    s = np.arange(profile.size, dtype=float)
+    lo, hi = max(int(guess) - 6, 0), min(int(guess) + 7, profile.size)
+    f = lambda s, A, s0, w, B: A * np.tanh((s - s0) / w) + B
+    A0 = np.sign(profile[hi - 1] - profile[lo])
+    (A, s0, w, B), _ = curve_fit(f, s[lo:hi], profile[lo:hi], p0=[A0, guess, 2.0, 0.0], maxfev=20000)
+    return s0 + w * np.arctanh(-B / A)
+
+
+def shape(ra, rb):
+    """Half-lengths along y and z through the centre of fluid b, and the centre (y, z)."""
+    c = ((rb - ra) / (ra + rb)).mean(axis=2)     # (nz, ny): the box is uniform along x
+    n = c.shape[0]
+    w = np.clip(c, 0, None)
+    zc = (w.sum(axis=1) * np.arange(n)).sum() / w.sum()
+    yc = (w.sum(axis=0) * np.arange(n)).sum() / w.sum()
+
+    def row(a, t):
+        i = int(np.floor(t))
+        return (1 - (t - i)) * a[i] + (t - i) * a[i + 1]
+
+    cy, cz = row(c, zc), row(c.T, yc)
+    r0 = 0.25 * n
+    a = 0.5 * (interface(cy, yc + r0) - interface(cy, yc - r0))
+    b = 0.5 * (interface(cz, zc + r0) - interface(cz, zc - r0))
+    return a, b, (yc, zc)
+
+
+def pressure(ra, rb, G):
+    """Shan-Chen equation of state: p = cs^2 (rho_a + rho_b) + cs^2 G psi_a psi_b."""
+    psa, psb = 1.0 - np.exp(-ra), 1.0 - np.exp(-rb)
+    return (ra + rb) / 3.0 + G * psa * psb / 3.0
+
+
+def run(chi, E):
+    cfg, inp = wl.dielectric_droplet(l=L, lx=4, chi=chi, field=0.0, precision="fp64", noise=0.0)
+    cfg.poisson_tol = 1e-8
+    sim = ek.EKSim(cfg, inp)
+    sim.step(RELAX)
+    relaxed = (sim.field("rho_a"), sim.field("rho_b"))
+    sim.set_field((0.0, 0.0, E))
+    sim.step(RUN)
+    ob = sim.observables()
+    assert ob["nonfinite"] == 0
+    final = (sim.field("rho_a"), sim.field("rho_b"))
+    sim.close()
+    return cfg, relaxed, final
+
+
+def test_dielectric_drop_deformation_against_okonski():
+    cfg, relaxed, final = run(0.9, 0.0)
+    a0, b0, (yc, zc) = shape(*relaxed)
+    rd = 0.5 * (a0 + b0)
+    p = pressure(*relaxed, cfg.G).mean(axis=2)
+    iy, iz = int(round(yc)), int(round(zc))
+    dp = p[iz, iy] - p[(iz + L // 2) % L, (iy + L // 2) % L]
+    gamma = dp * rd
+    print(f"relaxed drop: r_d {rd:.4f}, dp {dp:.5e}, gamma {gamma:.5e}", flush=True)
+    assert abs(rd - 32.0) < 0.5 and gamma > 0
+    a, b, _ = shape(*final)
+    print(f"no field: delta {(b - a) / (b + a):.3e}", flush=True)
+    assert abs((b - a) / (b + a)) < 1e-6
+    ratios = {}
+    for chi, E in ((0.5, 0.1), (0.9, 0.05), (0.9, 0.1)):
+        cfg, _, final = run(chi, E)
+        a, b, _ = shape(*final)
+        delta = (b - a) / (b + a)
+        delta_th = cfg.eps_a * rd * chi * chi * E * E / (4.0 * gamma)
+        ratios[(chi, E)] = delta / delta_th
+        print(f"chi {chi} E_z {E}: a {a:.4f} b {b:.4f} delta {delta:.5e} delta_th {delta_th:.5e} "
+              f"ratio {delta / delta_th:.4f}", flush=True)
+        assert b > a                       # elongated along the field
+        assert abs(delta / delta_th - 1.0) < 0.10
+    # the normalised deformation does not depend on the field strength
+    assert abs(ratios[(0.9, 0.05)] / ratios[(0.9, 0.1)] - 1.0) < 0.03

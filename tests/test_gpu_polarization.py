@@ -56,3 +56,52 @@ def test_3d_drop_with_ions_multigrid():
     print(f"  errors {errs}", flush=True)
     sim.close()
     o.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_field_switched_on_between_steps(precision):
+    """ek_set_field: the drop relaxes 10 steps without a field, then takes one; the library
+    follows the oracle doing the same."""
+    cfg, inp = wl.dielectric_droplet(l=32, lx=4, chi=0.5, field=0.0, precision=precision)
+    cfg.poisson_tol = 1e-12
+    print(f"field switched on after 10 steps, {precision}", flush=True)
+    sim, o = ek.EKSim(cfg, inp), orc.Oracle(cfg, inp)
+    sim.step(10)
+    o.step(10)
+    assert np.abs(sim.field("phi")).max() < 1e-12
+    sim.set_field((0.0, 0.0, 0.05))
+    o.set_field((0.0, 0.0, 0.05))
+    sim.step(10)
+    o.step(10)
+    assert np.abs(o.field("phi")).max() > 1e-2
+    errs = compare(sim, o, precision, "field switched on")
+    print(f"  errors {errs}", flush=True)
+    sim.close()
+    o.close()
+
+
+def test_set_field_with_particles_and_rejections():
+    """A field change reaches the particle force (Q E) and the ion migration of the colloid
+    workload; a polarising field normal to walls is refused."""
+    cfg, inp = wl.colloids(shape=(32, 32, 32), count=4, radius=3.5, precision="fp64", seed=7, field=(0.0, 0.0, 0.0))
+    cfg.poisson_tol = 1e-12
+    print("colloids 32^3: field switched on after 5 steps", flush=True)
+    sim, o = ek.EKSim(cfg, inp), orc.Oracle(cfg, inp)
+    sim.step(5)
+    o.step(5)
+    for s in (sim, o):
+        s.set_field((1e-3, 0.0, 0.0))
+    sim.step(10)
+    o.step(10)
+    compare(sim, o, "fp64", "colloids field on")
+    pg, po = sim.particles(), o.particles()
+    assert np.abs(pg[:, 6:9] - po[:, 6:9]).max() <= 1e-8 * np.abs(po[:, 6:9]).max()
+    sim.close()
+    o.close()
+    cfg = wl.EKConfig(8, 8, 12, walls_z=True, G=0.0, polarization=True)
+    sim = ek.EKSim(cfg, wl.uniform(cfg, 0.5, 0.5, 0.0, 0.0))
+    with pytest.raises(RuntimeError, match="normal to the walls"):
+        sim.set_field((0.0, 0.0, 1e-3))
+    sim.set_field((1e-3, 0.0, 0.0))
+    sim.step(2)
+    sim.close()

@@ -4,7 +4,8 @@ does not come from the oracle's own code.
 
 - Virtual densities on solid sites (Sec. II E, after Jansen et al.): a uniform fluid next
   to a flat wall or a resting neutral sphere feels no Shan-Chen force and stays uniform.
-- Kelvin force (Sec. II C, eq. kelvin): -(eps - eps_bar)/2 grad E^2 in a dielectric column
+- Kelvin force (Sec. II C): +(eps - eps_bar)/2 grad E^2 (the sign of the Landau form and of the
+  discrete total force; eq. kelvin prints a minus) in a dielectric column
   between charged walls, against the continuum field D / eps(z).
 - Solvation coupling of fluid a to the ions (Sec. II C, eq. shanChenForce with
   G_a+- = dmu+- / (drho_a cs2)): the force -psi^a (dmu / drho_a) grad n on single modes.
@@ -74,7 +75,9 @@ def test_virtual_density_sphere_keeps_uniform_mixture_at_rest():
 # Kelvin force (Sec. II C, eq. kelvin).  Between walls carrying opposite surface charges
 # +-sigma and with no ions, the displacement is uniform, D = sigma, so E(z) = sigma /
 # eps(z) along z, and the Kelvin force density is
-#     F_K = -(eps - eps_bar)/2 d(E^2)/dz = (eps - eps_bar) sigma^2 eps'(z) / eps^3.
+#     F_K = +(eps - eps_bar)/2 d(E^2)/dz = -(eps - eps_bar) sigma^2 eps'(z) / eps^3
+# (the sign of the Landau form with the permittivity law and of the discrete total force;
+# eq. kelvin prints the opposite one).
 # With G = 0 and no ions it is the only force on the fluid.  The lattice value (central
 # differences, face permittivity the mean of the sites) agrees with it up to O(k^2) of
 # the profile's wavenumber; a flipped sign, a factor 1/2 for 1/4 in the central form, or
@@ -95,7 +98,7 @@ def test_kelvin_force_in_dielectric_column():
     eps = cfg.eps_a * ra + cfg.eps_b * (1.0 - ra)
     deps = -(cfg.eps_b - cfg.eps_a) * 0.35 * np.cos(np.pi * (z - 1.0) / (L - 1) * 1.5) * np.pi / (L - 1) * 1.5
     ebar = 0.5 * (cfg.eps_a + cfg.eps_b)
-    expect = (eps - ebar) * sig ** 2 * deps / eps ** 3
+    expect = -(eps - ebar) * sig ** 2 * deps / eps ** 3
     Fz = (o.field("Phi_a_z") + o.field("Phi_b_z"))[:, 0, 0]
     inner = slice(3, nz - 3)
     scale = np.abs(expect[inner]).max()
