@@ -102,9 +102,10 @@ typedef struct ek_params {
                                    of the 8 XCDs sweeps its eighth of the z-planes in bands of sweep_band
                                    consecutive workgroups (256 sites each) of a plane, through every plane of
                                    its slab before the next band, so that the stencil's neighbour planes stay
-                                   in the XCD's L2.  0: bands of four x-rows; -1: whole planes in turn.  Used
-                                   when nx*ny is a multiple of 256, nz of 8 and the band divides a plane;
-                                   otherwise whole planes.  Results do not depend on it (bit for bit) */
+                                   in the XCD's L2.  0 or -1: whole planes in turn (measured fastest since the
+                                   particle sites run in a kernel of their own).  Used when nx*ny is a multiple
+                                   of 256, nz of 8 and the band divides a plane; otherwise whole planes.
+                                   Results do not depend on it (bit for bit) */
     int32_t poisson_cycles;     /* 0: each step's Poisson solve runs multigrid V-cycles until the relative
                                    residual meets poisson_tol, which reads residuals back to the host (one or
                                    two synchronisations per step).  1..64: each step runs exactly that many

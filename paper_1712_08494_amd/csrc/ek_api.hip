@@ -74,6 +74,8 @@ struct ek_ctx {
     double* linkdp = nullptr;
     int32_t* vlist = nullptr;
     int nv = 0;
+    int32_t* plist = nullptr;  // sites of the particle path
+    int npl = 0;
     long long nlinks = 0;
     std::vector<uint8_t> hflags;   // host copy (solid marks for export)
     std::vector<double> hpsis;     // host copy of the solid fraction
@@ -323,6 +325,8 @@ static Fields<T> fields(ek_ctx* c) {
     F.linkdp = c->linkdp;
     F.vlist = c->vlist;
     F.nv = c->nv;
+    F.plist = c->plist;
+    F.npl = c->npl;
     F.pv = c->pv[c->pcur];
     F.red = c->red;
     F.scal = c->scal;
@@ -345,6 +349,7 @@ struct HostGeom {
     std::vector<uint8_t> flags;
     std::vector<double> psis, qc;
     std::vector<int32_t> owner, linkbase, vlist, link_off, link_idx, site_off, site_idx;
+    std::vector<int32_t> plist;  // sites with flag bits 0, 1 or 3 (the particle path), ascending
     long long nlinks = 0;
 };
 
@@ -453,6 +458,9 @@ static ek_status build_geometry(ek_ctx* c, const ek_particle* parts, int np, Hos
                     }
                 if (part) g.flags[i] |= 8;
             }
+    if (np > 0)
+        for (size_t i = 0; i < N; ++i)
+            if (g.flags[i] & (1 | 2 | 8)) g.plist.push_back((int32_t)i);
     if (np > 0) {
         // links grouped by particle (counting sort), in the order the fused kernel writes them
         std::vector<int32_t> lowner(nl > 0 ? nl : 1);
@@ -1051,6 +1059,7 @@ static ek_status allocate_all(ek_ctx* c, const HostGeom& g, int np) {
         EK_TRY(dalloc(c, (void**)&L.az, (size_t)L.n * 8));
     }
     if (!g.vlist.empty()) EK_TRY(dalloc(c, (void**)&c->vlist, g.vlist.size() * 4));
+    if (!g.plist.empty()) EK_TRY(dalloc(c, (void**)&c->plist, g.plist.size() * 4));
     if (np > 0) {
         EK_TRY(dalloc(c, (void**)&c->flags, N));
         EK_TRY(dalloc(c, &c->psif, (size_t)N * es));
@@ -1146,6 +1155,8 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     c->hpsis = g.psis;
     c->nv = (int)g.vlist.size();
     if (c->nv > 0) EK_HIP(hipMemcpyAsync(c->vlist, g.vlist.data(), g.vlist.size() * 4, hipMemcpyHostToDevice, c->st));
+    c->npl = (int)g.plist.size();
+    if (c->npl > 0) EK_HIP(hipMemcpyAsync(c->plist, g.plist.data(), g.plist.size() * 4, hipMemcpyHostToDevice, c->st));
     if (colloids) {
         EK_HIP(hipMemcpyAsync(c->flags, g.flags.data(), N, hipMemcpyHostToDevice, c->st));
         std::vector<double> tmp(N);
@@ -1270,15 +1281,15 @@ static ek_status configure(ek_ctx* c, const ek_params* p, const ek_particle* par
     S.inv_ny = 1.0 / S.ny;
     S.inv_nxy = 1.0 / S.nxy;
     S.inv_hx = S.nx >= 2 ? 1.0 / (S.nx / 2) : 0.0;
-    // banded workgroup order of the stencil sweeps (see site_banded): default bands of four
-    // x-rows, when every z-plane is a whole number of workgroups and nz splits over the 8 XCDs
+    // banded workgroup order of the stencil sweeps (see site_banded), on request only: when
+    // every z-plane is a whole number of workgroups and nz splits over the 8 XCDs
     if (p->sweep_band < -1) return fail(c, EK_EINVAL, "sweep_band must be >= -1");
     S.band = 0;
     S.plane_blocks = 0;
     S.slab_planes = 0;
-    if (p->sweep_band != -1 && S.nxy % kBlock == 0 && S.nz % 8 == 0) {
+    if (p->sweep_band > 0 && S.nxy % kBlock == 0 && S.nz % 8 == 0) {
         const int pb = S.nxy / kBlock;
-        const int B = p->sweep_band > 0 ? p->sweep_band : std::max(1, 4 * S.nx / kBlock);
+        const int B = p->sweep_band;
         if (pb % B == 0) {
             S.band = B;
             S.plane_blocks = pb;

@@ -61,6 +61,8 @@ struct Fields {
     double* linkdp;          // 6 doubles per particle link: (component, xyz) momentum handed over
     const int32_t* vlist;    // solid sites next to fluid (virtual densities)
     int nv;
+    const int32_t* plist;    // sites that take the particle path (flag bits 0, 1 or 3), ascending
+    int npl;
     const double* pv;        // particle velocities (3 per particle)
     double* red;             // reduction scratch
     double* scal;            // device scalars: [0] source mean, [1..3] rr, ss, sum phi

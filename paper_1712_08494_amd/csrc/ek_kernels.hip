@@ -1802,17 +1802,15 @@ __device__ __forceinline__ void site_forces(unsigned i, const Nbr& o, T ra, T rb
 // ------------------------------------------------------------------------------------
 // With particles most sites have no solid D3Q19 neighbour and fluid fraction 1 on their
 // axis stencil (flag bits 0, 1 and 3 clear); there the particle path computes exactly what
-// the periodic path does (unit fractions, no bounce-back), so those sites take it and skip
-// the fraction and neighbour-flag loads.
+// the periodic path does (unit fractions, no bounce-back).  Those sites run in the periodic
+// kernel, which skips the others; the others (about 1 % of the lattice at the 256^3
+// workload's sphere density) run in a second kernel over the list of their indices, so
+// the plain sites keep the periodic kernel's registers and occupancy.
 constexpr uint8_t kParticlePath = 1u | 2u | 8u;
 
 template <typename T, int G>
 __device__ __forceinline__ void force_body(const Scalars& S, const Fields<T>& F, unsigned i) {
     if (i >= S.N) return;
-    if (G == kColloids && (F.flags[i] & kParticlePath) == 0) {
-        force_body<T, kPeriodic>(S, F, i);
-        return;
-    }
     int x, y, z;
     site_xyz(i, S, x, y, z);
     const size_t N = S.N;
@@ -1835,16 +1833,32 @@ __device__ __forceinline__ void force_body(const Scalars& S, const Fields<T>& F,
     for (int k = 0; k < 3; ++k) F.uph[(size_t)k * N + i] = F.mom[(size_t)(5 + k) * N + i] + (Pa[k] + Pb[k]) / rt2;
 }
 
+// G = kColloids: the plain sites of a context with particles (the periodic path).
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock, kForceOcc<T>) void k_force(Scalars S, Fields<T> F) {
-    force_body<T, G>(S, F, site_banded(S));
+    const unsigned i = site_banded(S);
+    if (G == kColloids) {
+        if (i >= S.N || (F.flags[i] & kParticlePath) != 0) return;
+        force_body<T, kPeriodic>(S, F, i);
+    } else {
+        force_body<T, G>(S, F, i);
+    }
+}
+
+// The particle-path sites, from their list.
+template <typename T>
+__global__ __launch_bounds__(kBlock, kForceOcc<T>) void k_force_part(Scalars S, Fields<T> F) {
+    const unsigned t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < (unsigned)F.npl) force_body<T, kColloids>(S, F, (unsigned)F.plist[t]);
 }
 
 template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hipStream_t st) {
     const dim3 g(site_blocks(S.N)), b(kBlock);
-    if (S.colloids)
+    if (S.colloids) {
         hipLaunchKernelGGL((k_force<T, kColloids>), g, b, 0, st, S, F);
-    else if (S.walls)
+        if (F.npl > 0)
+            hipLaunchKernelGGL((k_force_part<T>), dim3(site_blocks((unsigned)F.npl)), b, 0, st, S, F);
+    } else if (S.walls)
         hipLaunchKernelGGL((k_force<T, kWalls>), g, b, 0, st, S, F);
     else
         hipLaunchKernelGGL((k_force<T, kPeriodic>), g, b, 0, st, S, F);
@@ -1863,10 +1877,6 @@ template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hi
 template <typename T, int G, bool MS = false>
 __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F, unsigned i) {
     if (i >= S.N) return;
-    if (G == kColloids && (F.flags[i] & kParticlePath) == 0) {
-        fused_body<T, kPeriodic, MS>(S, F, i);
-        return;
-    }
     int x, y, z;
     site_xyz(i, S, x, y, z);
     if (G == kWalls && (z == 0 || z == S.nz - 1)) return;  // wall layers hold no ions and no fluid
@@ -1961,21 +1971,36 @@ __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F,
     }
 }
 
-// The particle variant holds both the particle path and the plain path: in FP32 it takes
-// three waves per SIMD, where it needs no scratch.
-template <typename T, int G> constexpr int kFusedOcc = (G == kColloids && sizeof(T) == 4) ? 3 : kHotOcc<T>;
-
+// G = kColloids: the plain sites of a context with particles (the periodic path).
 template <typename T, int G, bool MS>
-__global__ __launch_bounds__(kBlock, (kFusedOcc<T, G>)) void k_fused(Scalars S, Fields<T> F) {
-    fused_body<T, G, MS>(S, F, site_banded(S));
+__global__ __launch_bounds__(kBlock, kHotOcc<T>) void k_fused(Scalars S, Fields<T> F) {
+    const unsigned i = site_banded(S);
+    if (G == kColloids) {
+        if (i >= S.N || (F.flags[i] & kParticlePath) != 0) return;
+        fused_body<T, kPeriodic, MS>(S, F, i);
+    } else {
+        fused_body<T, G, MS>(S, F, i);
+    }
+}
+
+// The particle-path sites, from their list: in FP32 three waves per SIMD, where the
+// exact-mass collision needs no scratch.
+template <typename T> constexpr int kPartOcc = sizeof(T) == 4 ? 3 : kHotOcc<T>;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock, kPartOcc<T>) void k_fused_part(Scalars S, Fields<T> F) {
+    const unsigned t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < (unsigned)F.npl) fused_body<T, kColloids, false>(S, F, (unsigned)F.plist[t]);
 }
 
 template <typename T> void launch_fused(const Scalars& S, const Fields<T>& F, hipStream_t st) {
     const dim3 g(site_blocks(S.N)), b(kBlock);
     const bool ms = F.ms != nullptr;  // a moment-state context writes it from the first step on
-    if (S.colloids)
+    if (S.colloids) {
         hipLaunchKernelGGL((k_fused<T, kColloids, false>), g, b, 0, st, S, F);
-    else if (S.walls && ms)
+        if (F.npl > 0)
+            hipLaunchKernelGGL((k_fused_part<T>), dim3(site_blocks((unsigned)F.npl)), b, 0, st, S, F);
+    } else if (S.walls && ms)
         hipLaunchKernelGGL((k_fused<T, kWalls, true>), g, b, 0, st, S, F);
     else if (S.walls)
         hipLaunchKernelGGL((k_fused<T, kWalls, false>), g, b, 0, st, S, F);

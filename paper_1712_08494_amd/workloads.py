@@ -40,7 +40,7 @@ class EKConfig:
     eps_p: float = EPS_FLUID / 8.0   # relative permittivities 10 / 80, Sec. III D
     phi_history: int = 0             # Poisson warm start: 0 the library default
     moment_state: bool = False       # tau = 1 only: store density and u_e per site instead of populations
-    sweep_band: int = 0              # workgroup band of the stencil sweeps: 0 default, -1 plain order
+    sweep_band: int = 0              # workgroup band of the stencil sweeps: 0 or -1 plain order
     poisson_cycles: int = 0          # > 0: that many V-cycles per step, no host read-back
     fp32_plain_collision: bool = False  # FP32: the plain collision instead of the exact-mass one
     polarization: bool = False       # the external field polarises the dielectric (Poisson source)
