@@ -94,6 +94,7 @@ typedef struct {
     double particle_rho, k_hertz, eta;
     int32_t poisson_lagged;   /* 1: each step takes the lagged Fourier scheme of Sec. II D (periodic) */
     int32_t polarization;     /* 1: the external field also polarises the dielectric (see poisson_source) */
+    int32_t reproject;        /* 1: moving particles are projected anew after every step (see reproject) */
 } or_params;
 
 typedef struct {
@@ -883,6 +884,114 @@ static void particle_update(or_state* s) {
 }
 
 /* ------------------------------------------------------------------------------ */
+/* Moving particles (Sec. II E): once the particles have moved, the projection is    */
+/* redone (solid mask, solid fraction, owner and charge per site, build_geometry)    */
+/* and the sites the move converts are handled:                                       */
+/*  - fluid -> solid (covered): the site's fluid momentum sum_s sum_d f^s_d c_d goes  */
+/*    to the covering particle and its populations are removed.  Reading: the        */
+/*    printed F_c carries a minus sign; conservation of momentum, which the text      */
+/*    states as the purpose, makes the particle's gain the fluid's loss.             */
+/*  - solid -> fluid (uncovered): populations f~(rho_bar^s, v) with v the velocity of */
+/*    the particle that covered the site and rho_bar^s the mean density of its D3Q19  */
+/*    neighbours that are fluid before and after the move (Reading: printed as a sum; */
+/*    the mean, as for the virtual densities).  The particle gives up the momentum of */
+/*    the new fluid, sum_s rho_bar^s v (Reading: the sign as for F_c).               */
+/* Ions live where the fluid fraction is positive (the partial-volume fluxes carry    */
+/* them into sites whose centre lies inside a particle).  Reading: the ion events are */
+/* therefore those of the fluid fraction: a site whose fraction drops to zero has its */
+/* ions shared equally among its axis (D3Q7) neighbours that keep a positive fraction */
+/* (the displacement is isotropic, the ions move on the axis links and equal shares   */
+/* keep them exactly); a site whose fraction rises from zero starts without ions,     */
+/* which it already holds.                                                            */
+/* The momentum transfers change the particle velocities at once (the same as adding */
+/* them to the next step's force in the symplectic update).                          */
+/* ------------------------------------------------------------------------------ */
+static void reproject(or_state* s) {
+    const or_params* p = &s->p;
+    int64_t N = s->N;
+    uint8_t* was_solid = (uint8_t*)malloc((size_t)N);
+    int32_t* was_owner = (int32_t*)malloc((size_t)N * sizeof(int32_t));
+    double* was_psif = (double*)malloc((size_t)N * sizeof(double));
+    memcpy(was_solid, s->solid, (size_t)N);
+    memcpy(was_owner, s->owner, (size_t)N * sizeof(int32_t));
+    memcpy(was_psif, s->psif, (size_t)N * sizeof(double));
+    build_geometry(s);
+    double* dP = (double*)calloc((size_t)(3 * (s->np > 0 ? s->np : 1)), sizeof(double));
+    double feq[OQ];
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                int64_t i = IDX(p, x, y, z);
+                if (!was_solid[i] && s->solid[i]) {
+                    int o = s->owner[i];
+                    for (int c = 0; c < 2; ++c)
+                        for (int d = 0; d < OQ; ++d) {
+                            double* fv = &s->f[c][(int64_t)d * N + i];
+                            if (o >= 0)
+                                for (int k = 0; k < 3; ++k) dP[3 * o + k] += *fv * OC[d][k];
+                            *fv = 0.0;
+                        }
+                }
+                if (was_psif[i] > 0.0 && s->psif[i] == 0.0) {
+                    int cnt = 0;
+                    for (int d = 1; d <= 6; ++d) {
+                        int zz = z + OC[d][2];
+                        if (p->walls_z && (zz < 0 || zz >= p->nz)) continue;
+                        int64_t j = IDX(p, wrap(x + OC[d][0], p->nx), wrap(y + OC[d][1], p->ny), wrap(zz, p->nz));
+                        if (s->psif[j] > 0.0) ++cnt;
+                    }
+                    for (int sp = 0; sp < 2 && cnt > 0; ++sp) {
+                        double share = s->n[sp][i] / cnt;
+                        for (int d = 1; d <= 6; ++d) {
+                            int zz = z + OC[d][2];
+                            if (p->walls_z && (zz < 0 || zz >= p->nz)) continue;
+                            int64_t j = IDX(p, wrap(x + OC[d][0], p->nx), wrap(y + OC[d][1], p->ny), wrap(zz, p->nz));
+                            if (s->psif[j] > 0.0) s->n[sp][j] += share;
+                        }
+                        s->n[sp][i] = 0.0;
+                    }
+                }
+            }
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                int64_t i = IDX(p, x, y, z);
+                if (!(was_solid[i] && !s->solid[i])) continue;
+                int o = was_owner[i];
+                double v[3] = {0, 0, 0};
+                if (o >= 0)
+                    for (int k = 0; k < 3; ++k) v[k] = s->pv[3 * o + k];
+                for (int c = 0; c < 2; ++c) {
+                    double acc = 0.0;
+                    int cnt = 0;
+                    for (int d = 1; d < OQ; ++d) {
+                        int zz = z + OC[d][2];
+                        if (p->walls_z && (zz < 0 || zz >= p->nz)) continue;
+                        int64_t j = IDX(p, wrap(x + OC[d][0], p->nx), wrap(y + OC[d][1], p->ny), wrap(zz, p->nz));
+                        if (was_solid[j] || s->solid[j]) continue;
+                        double r = 0.0;
+                        for (int e = 0; e < OQ; ++e) r += s->f[c][(int64_t)e * N + j];
+                        acc += r;
+                        ++cnt;
+                    }
+                    double rb = cnt > 0 ? acc / cnt : 0.0;
+                    or_equilibrium(rb, v, feq);
+                    for (int d = 0; d < OQ; ++d) s->f[c][(int64_t)d * N + i] = feq[d];
+                    if (o >= 0)
+                        for (int k = 0; k < 3; ++k) dP[3 * o + k] -= rb * v[k];
+                }
+            }
+    for (int j = 0; j < s->np; ++j) {
+        double m = p->particle_rho * (4.0 / 3.0) * M_PI * s->pr[j] * s->pr[j] * s->pr[j];
+        for (int k = 0; k < 3; ++k) s->pv[3 * j + k] += dP[3 * j + k] / m;
+    }
+    free(dP);
+    free(was_solid);
+    free(was_owner);
+    free(was_psif);
+}
+
+/* ------------------------------------------------------------------------------ */
 /* Public API                                                                       */
 /* ------------------------------------------------------------------------------ */
 static double* dalloc(int64_t n) { return (double*)calloc((size_t)n, sizeof(double)); }
@@ -897,6 +1006,7 @@ or_state* or_create(const or_params* prm, const double* rho_a, const double* rho
     if (prm->poisson_lagged && prm->polarization) return NULL; /* its right-hand side has no polarisation term */
     /* with walls the wall faces carry no displacement, so a polarising field normal to them is undefined */
     if (prm->polarization && prm->walls_z && prm->E_ext[2] != 0.0) return NULL;
+    if (prm->reproject && !prm->move_particles) return NULL; /* only moving particles are projected anew */
     or_state* s = (or_state*)calloc(1, sizeof(or_state));
     s->p = *prm;
     set_threads(&s->p);
@@ -979,6 +1089,7 @@ static int step_once(or_state* s) {
         double* t = s->f[c]; s->f[c] = s->fs[c]; s->fs[c] = t;
         t = s->n[c]; s->n[c] = s->nnew[c]; s->nnew[c] = t;
     }
+    if (s->p.reproject && s->np > 0) reproject(s);
     s->steps++;
     return st;
 }

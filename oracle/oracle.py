@@ -43,7 +43,7 @@ class OrParams(ctypes.Structure):
         ("E_ext", ctypes.c_double * 3), ("body_accel", ctypes.c_double * 3),
         ("sigma_wall", ctypes.c_double * 2), ("poisson_tol", ctypes.c_double),
         ("particle_rho", ctypes.c_double), ("k_hertz", ctypes.c_double), ("eta", ctypes.c_double),
-        ("poisson_lagged", ctypes.c_int32), ("polarization", ctypes.c_int32),
+        ("poisson_lagged", ctypes.c_int32), ("polarization", ctypes.c_int32), ("reproject", ctypes.c_int32),
     ]
 
 
@@ -139,6 +139,7 @@ def params_from_config(cfg, n_threads=0):
     p.particle_rho, p.k_hertz, p.eta = cfg.particle_rho, cfg.k_hertz, cfg.eta
     p.poisson_lagged = int(cfg.poisson_solver == "fft")
     p.polarization = int(bool(getattr(cfg, "polarization", False)))
+    p.reproject = int(bool(getattr(cfg, "reproject", False)))
     return p
 
 

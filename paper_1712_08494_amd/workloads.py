@@ -44,6 +44,7 @@ class EKConfig:
     poisson_cycles: int = 0          # > 0: that many V-cycles per step, no host read-back
     fp32_plain_collision: bool = False  # FP32: the plain collision instead of the exact-mass one
     polarization: bool = False       # the external field polarises the dielectric (Poisson source)
+    reproject: bool = False          # moving particles projected anew every step (cover / uncover)
     E_ext: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     body_accel: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     sigma_wall: Tuple[float, float] = (0.0, 0.0)
