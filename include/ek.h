@@ -131,6 +131,19 @@ typedef struct ek_params {
                                    droplet of Sec. III B.  Not with EK_POISSON_FFT, reverse mode, or walls with
                                    E_ext[2] != 0 (the wall faces carry no displacement) (EK_EINVAL).
                                    0 (default): the printed model */
+    int32_t reproject;          /* 1: moving particles are projected anew after every step (Sec. II E): solid
+                                   mask, solid fraction, owner and charge per site follow the particles; a
+                                   fluid site they cover hands its momentum to the particle, a site they
+                                   uncover gets the equilibrium at the mean density of its neighbours that
+                                   stay fluid, moving with the particle (which gives up that momentum), and
+                                   the ions of a site whose fluid fraction drops to zero are shared equally
+                                   among its axis neighbours that keep fluid.  Needs move_particles = 1,
+                                   every axis at least 2 ceil(max radius) + 9 sites long and a move below
+                                   one site per step; subsample at most 31; not with ek_autotune_multigrid.
+                                   The projection costs one workgroup per particle over a box of
+                                   (2 ceil(r) + 9)^3 sites and checks every other particle's box, so it
+                                   suits up to a few tens of particles.  0 (default): the mask set up by
+                                   ek_init stays (the particles may still move) */
 } ek_params;
 
 typedef struct ek_particle {
@@ -195,7 +208,8 @@ typedef struct ek_obs {
 #define EK_K_FUSED 18
 #define EK_K_PARTICLE 19         /* particle forces and integration */
 #define EK_K_LAGGED 20           /* a whole lagged Fourier solve (right-hand side, transforms, division) */
-#define EK_K_COUNT 21
+#define EK_K_REPROJECT 21        /* projection of moving particles after their step (reproject) */
+#define EK_K_COUNT 22
 
 typedef struct ek_timing {
     double ms[EK_T_COUNT];    /* summed device time per class (HIP events) */

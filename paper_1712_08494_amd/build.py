@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libek.so")
-SOURCES = ["ek_kernels.hip", "ek_adjoint.hip", "ek_fft.hip", "ek_api.hip"]
+SOURCES = ["ek_kernels.hip", "ek_particles.hip", "ek_adjoint.hip", "ek_fft.hip", "ek_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -87,6 +87,17 @@ struct ek_ctx {
     double* pF = nullptr;
     int pcur = 0;
     int32_t *plink_off = nullptr, *plink_idx = nullptr, *psite_off = nullptr, *psite_idx = nullptr;
+    // moving particles projected anew (ek_params.reproject): particle charges, the geometry
+    // copies and the work arrays of the projection (Reproj)
+    double* pQ = nullptr;
+    uint8_t* flags_old = nullptr;
+    int32_t* owner_old = nullptr;
+    void* psif_old = nullptr;
+    int32_t* rp_origin = nullptr;
+    int16_t* rp_cnt = nullptr;
+    uint8_t *rp_inside = nullptr, *rp_event = nullptr;
+    double *rp_evm = nullptr, *rp_ptot = nullptr;
+    void* rp_share = nullptr;
     std::vector<double> px0, hrad;
     // scratch
     double* red = nullptr;
@@ -322,7 +333,7 @@ static Fields<T> fields(ek_ctx* c) {
     F.qc = (const T*)c->qc;
     F.owner = c->owner;
     F.linkbase = c->linkbase;
-    F.linkdp = c->linkdp;
+    F.linkdp = c->S.reproject ? nullptr : c->linkdp;  // moving particles: no link lists
     F.vlist = c->vlist;
     F.nv = c->nv;
     F.plist = c->plist;
@@ -897,6 +908,18 @@ static ek_status step_rest(ek_ctx* c) {
                                 c->st);
         c->pcur ^= 1;
     }
+    if (c->S.reproject) {
+        Timer tm(c, EK_T_PARTICLE);
+        EK_KT(EK_K_REPROJECT);
+        const size_t N = c->N;
+        EK_HIP(hipMemcpyAsync(c->flags_old, c->flags, N, hipMemcpyDeviceToDevice, c->st));
+        EK_HIP(hipMemcpyAsync(c->owner_old, c->owner, N * 4, hipMemcpyDeviceToDevice, c->st));
+        EK_HIP(hipMemcpyAsync(c->psif_old, c->psif, N * c->esz, hipMemcpyDeviceToDevice, c->st));
+        Reproj<T> P{c->np, c->px[c->pcur], c->pv[c->pcur], c->prad, c->pQ, c->p.particle_rho, c->flags, c->owner,
+                    (T*)c->psif, (T*)c->qc, c->flags_old, c->owner_old, (const T*)c->psif_old, c->rp_origin,
+                    c->rp_cnt, c->rp_inside, c->rp_event, c->rp_evm, (T*)c->rp_share, c->rp_ptot};
+        launch_reproject<T>(c->S, F, P, c->st);
+    }
     EK_HIP(hipGetLastError());
     c->cur ^= 1;
     c->ms_first = false;  // a moment-state context now holds the state written by this step
@@ -1077,6 +1100,20 @@ static ek_status allocate_all(ek_ctx* c, const HostGeom& g, int np) {
         }
         EK_TRY(dalloc(c, (void**)&c->prad, np * 8));
         EK_TRY(dalloc(c, (void**)&c->pF, 3 * np * 8));
+        if (c->S.reproject) {
+            const size_t B3 = (size_t)c->S.rp_box * c->S.rp_box * c->S.rp_box;
+            EK_TRY(dalloc(c, (void**)&c->pQ, np * 8));
+            EK_TRY(dalloc(c, (void**)&c->flags_old, N));
+            EK_TRY(dalloc(c, (void**)&c->owner_old, (size_t)N * 4));
+            EK_TRY(dalloc(c, &c->psif_old, (size_t)N * es));
+            EK_TRY(dalloc(c, (void**)&c->rp_origin, 3 * np * 4));
+            EK_TRY(dalloc(c, (void**)&c->rp_cnt, np * B3 * 2));
+            EK_TRY(dalloc(c, (void**)&c->rp_inside, np * B3));
+            EK_TRY(dalloc(c, (void**)&c->rp_event, np * B3));
+            EK_TRY(dalloc(c, (void**)&c->rp_evm, 3 * np * B3 * 8));
+            EK_TRY(dalloc(c, &c->rp_share, (size_t)2 * N * es));
+            EK_TRY(dalloc(c, (void**)&c->rp_ptot, np * 8));
+        }
     }
     if (c->fft) {
         EK_TRY(dalloc(c, (void**)&c->fft_rhs, (size_t)N * 8));
@@ -1192,6 +1229,12 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
         }
         EK_HIP(hipMemcpyAsync(c->prad, c->hrad.data(), np * 8, hipMemcpyHostToDevice, c->st));
         EK_HIP(hipMemsetAsync(c->pF, 0, 3 * np * 8, c->st));
+        if (c->S.reproject) {
+            std::vector<double> hq(np);
+            for (int j = 0; j < np; ++j) hq[j] = parts[j].charge;
+            EK_HIP(hipMemcpyAsync(c->pQ, hq.data(), np * 8, hipMemcpyHostToDevice, c->st));
+            EK_HIP(hipStreamSynchronize(c->st));  // hq is a local vector
+        }
         EK_HIP(hipStreamSynchronize(c->st));  // host staging vectors above end with this block
     }
     EK_HIP(hipStreamSynchronize(c->st));
@@ -1281,6 +1324,24 @@ static ek_status configure(ek_ctx* c, const ek_params* p, const ek_particle* par
     S.inv_ny = 1.0 / S.ny;
     S.inv_nxy = 1.0 / S.nxy;
     S.inv_hx = S.nx >= 2 ? 1.0 / (S.nx / 2) : 0.0;
+    if (p->reproject != 0 && p->reproject != 1) return fail(c, EK_EINVAL, "reproject must be 0 or 1");
+    if (p->reproject && (n_parts == 0 || !p->move_particles))
+        return fail(c, EK_EINVAL, "reproject needs particles that move (move_particles = 1)");
+    S.reproject = p->reproject;
+    S.subs = p->subsample > 0 ? p->subsample : 8;
+    S.rp_half = S.rp_box = 0;
+    if (S.reproject) {
+        if (S.subs > 31) return fail(c, EK_EINVAL, "subsample must be at most 31 with reproject");
+        double rmax = 0.0;
+        for (int j = 0; j < n_parts; ++j) rmax = std::max(rmax, parts[j].radius);
+        // a site changes only within R + 1.87 of the new centre (a move below one site, sub-cell
+        // centres within sqrt(3)/2), its neighbour flags within one more; floor() of the centre
+        // loses up to one more site on the low side
+        S.rp_half = (int)std::ceil(rmax) + 4;
+        S.rp_box = 2 * S.rp_half + 1;
+        if (S.rp_box > p->nx || S.rp_box > p->ny || S.rp_box > p->nz)
+            return fail(c, EK_EINVAL, "reproject needs every axis at least 2 ceil(max radius) + 9 sites long");
+    }
     // banded workgroup order of the stencil sweeps (see site_banded), on request only: when
     // every z-plane is a whole number of workgroups and nz splits over the 8 XCDs
     if (p->sweep_band < -1) return fail(c, EK_EINVAL, "sweep_band must be >= -1");
@@ -1974,6 +2035,7 @@ extern "C" ek_status ek_autotune_multigrid(ek_ctx* c, int32_t trial_steps, int32
     if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: its cycle is fixed by the batch");
     if (c->mg.empty()) return fail(c, EK_EINVAL, "this lattice is solved by SOR: there is no V-cycle to tune");
     if (c->fft) return fail(c, EK_EINVAL, "the lagged Fourier scheme runs no V-cycles in its steps");
+    if (c->S.reproject) return fail(c, EK_EINVAL, "moving particles change the geometry, which the tuner does not restore");
     if (trial_steps < 1 || trial_steps > 1000) return fail(c, EK_EINVAL, "trial_steps must be in 1..1000");
     return c->esz == 4 ? autotune_impl<float>(c, trial_steps, best, ms_per_step)
                        : autotune_impl<double>(c, trial_steps, best, ms_per_step);
@@ -1984,6 +2046,15 @@ template <typename T>
 static ek_status field_impl(ek_ctx* c, int which, double* host) {
     const unsigned N = c->N;
     Fields<T> F = fields<T>(c);
+    if ((which == EK_F_PSI_S || which == EK_F_SOLID) && c->S.reproject) {  // the geometry moves: read it back
+        std::vector<uint8_t> fl(N);
+        std::vector<T> pf(N);
+        EK_HIP(hipMemcpyAsync(fl.data(), c->flags, N, hipMemcpyDeviceToHost, c->st));
+        EK_HIP(hipMemcpyAsync(pf.data(), c->psif, (size_t)N * sizeof(T), hipMemcpyDeviceToHost, c->st));
+        EK_HIP(hipStreamSynchronize(c->st));
+        for (unsigned i = 0; i < N; ++i) host[i] = which == EK_F_PSI_S ? 1.0 - (double)pf[i] : (double)(fl[i] & 1);
+        return EK_OK;
+    }
     if (which == EK_F_PSI_S || which == EK_F_SOLID) {
         for (unsigned i = 0; i < N; ++i) host[i] = which == EK_F_PSI_S ? c->hpsis[i] : (double)(c->hflags[i] & 1);
         return EK_OK;
@@ -2178,7 +2249,7 @@ extern "C" const char* ek_kernel_name(int32_t k) {
         "k_moments", "k_virtual", "k_source_mean", "k_phi_extrapolate", "k_residual", "k_reduce",
         "k_mg_coarsen", "k_sor", "k_sor_black_from", "k_mg_restrict_fine", "k_mg_restrict", "k_mg_smooth",
         "k_mg_tail", "k_mg_prolong_red_fine", "k_mg_prolong_fine", "k_mg_prolong", "k_phi_finalize", "k_force",
-        "k_fused", "k_particle_step", "lagged_fourier"};
+        "k_fused", "k_particle_step", "lagged_fourier", "k_reproject"};
     return k >= 0 && k < EK_K_COUNT ? names[k] : "";
 }
 

@@ -30,6 +30,10 @@ struct Scalars {
     // (plane_blocks of them) are grouped in bands of `band`, and each XCD walks its slab of
     // slab_planes planes band by band; band = 0 keeps the plain slab order.
     int band, plane_blocks, slab_planes;
+    // Moving particles projected anew every step (ek_params.reproject): sub-cells per axis
+    // of the solid fraction, and the half-width and side of the box of sites around a
+    // particle that a step's projection can change (rp_box = 2 rp_half + 1)
+    int reproject, subs, rp_half, rp_box;
     double tau, inv_tau, G, rho0, D, beta;
     double kap_p, kap_m;   // s beta dmu+- / (2 drho_a)
     double G_p, G_m;       // s dmu+- / (drho_a c_s^2)
@@ -214,6 +218,37 @@ void launch_particle_step(const Scalars& S, const Fields<T>& F, int np, const in
                           const double* v, const double* r, double* pF, double* xn, double* vn, double rho_p,
                           double k_h, double eta, int move, hipStream_t st);
 template <typename T> void launch_observe(const Scalars& S, const Fields<T>& F, unsigned nblk, hipStream_t st);
+
+// Projection of moving particles after their step (ek_params.reproject).  Work arrays: the
+// geometry of the step's start (flags, owner, fluid fraction), per particle and box site
+// the sub-cell count and centre test of the new position and the site's conversion, per
+// site the ion shares of a site whose fluid fraction drops to zero, per particle the box
+// origin and the summed solid fraction.
+template <typename T>
+struct Reproj {
+    int np;
+    const double* x;     // positions after the step (3 np)
+    double* v;           // velocities after the step (3 np); the conversions' impulses are added
+    const double* rad;   // radii
+    const double* Q;     // charges
+    double rho_p;        // particle mass density
+    uint8_t* flags;      // the context's geometry, updated in place
+    int32_t* owner;
+    T* psif;
+    T* qc;
+    const uint8_t* flags_old;  // copies taken before the projection
+    const int32_t* owner_old;
+    const T* psif_old;
+    int32_t* origin;     // 3 np: lowest lattice corner of each particle's box (not wrapped)
+    int16_t* cnt;        // np x box^3: sub-cells of the site inside the particle
+    uint8_t* inside;     // np x box^3: the site's centre strictly inside the particle
+    uint8_t* event;      // np x box^3: 1 covered, 2 uncovered (for the particle handling it)
+    double* evm;         // 3 x np x box^3: the particle's momentum change from that site
+    T* share;            // 2 N: ion shares (mean density, charge) of a site losing its fluid
+    double* ptot;        // np: summed solid fraction of each particle's sites
+};
+template <typename T>
+void launch_reproject(const Scalars& S, const Fields<T>& F, const Reproj<T>& P, hipStream_t st);
 // the observables from a fixed grid of nblk workgroups (grid-stride), partial sums in red
 template <typename T>
 void launch_observe_strided(const Scalars& S, const Fields<T>& F, unsigned nblk, double* red, hipStream_t st);

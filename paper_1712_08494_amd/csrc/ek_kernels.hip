@@ -350,11 +350,13 @@ template <typename T> void launch_moments(const Scalars& S, const Fields<T>& F, 
 // Virtual densities (Sec. II E, after Jansen et al.): a solid site with a fluid D3Q19
 // neighbour carries the mean density of its fluid neighbours, used only by the
 // Shan-Chen sums (and the permittivity of partly covered sites).
-template <typename T>
+// ALL: every solid site next to fluid (flag bit 2) instead of the list built at set-up
+// (moving particles change the mask).
+template <typename T, bool ALL>
 __global__ __launch_bounds__(kBlock) void k_virtual(Scalars S, Fields<T> F) {
     const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
-    if ((int)t >= F.nv) return;
-    const unsigned i = (unsigned)F.vlist[t];
+    if (ALL ? t >= S.N || !(F.flags[t] & 4u) : (int)t >= F.nv) return;
+    const unsigned i = ALL ? t : (unsigned)F.vlist[t];
     int x, y, z;
     site_xyz(i, S, x, y, z);
     const Nbr o = make_nbr(x, y, z, S);
@@ -385,8 +387,12 @@ __global__ __launch_bounds__(kBlock) void k_virtual(Scalars S, Fields<T> F) {
 }
 
 template <typename T> void launch_virtual(const Scalars& S, const Fields<T>& F, hipStream_t st) {
+    if (S.reproject) {
+        hipLaunchKernelGGL((k_virtual<T, true>), dim3(site_blocks(S.N)), dim3(kBlock), 0, st, S, F);
+        return;
+    }
     if (F.nv <= 0) return;
-    hipLaunchKernelGGL(k_virtual<T>, dim3((F.nv + kBlock - 1) / kBlock), dim3(kBlock), 0, st, S, F);
+    hipLaunchKernelGGL((k_virtual<T, false>), dim3((F.nv + kBlock - 1) / kBlock), dim3(kBlock), 0, st, S, F);
 }
 
 // Mean of the Poisson source over the domain: (sum q + wall charges) / sites.
@@ -1852,9 +1858,23 @@ __global__ __launch_bounds__(kBlock, kForceOcc<T>) void k_force_part(Scalars S, 
     if (t < (unsigned)F.npl) force_body<T, kColloids>(S, F, (unsigned)F.plist[t]);
 }
 
+// Every site, each taking its path by its flags (moving particles change which sites take
+// the particle path, so there is no list).
+template <typename T>
+__global__ __launch_bounds__(kBlock, kForceOcc<T>) void k_force_all(Scalars S, Fields<T> F) {
+    const unsigned i = site_banded(S);
+    if (i >= S.N) return;
+    if ((F.flags[i] & kParticlePath) == 0)
+        force_body<T, kPeriodic>(S, F, i);
+    else
+        force_body<T, kColloids>(S, F, i);
+}
+
 template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hipStream_t st) {
     const dim3 g(site_blocks(S.N)), b(kBlock);
-    if (S.colloids) {
+    if (S.reproject) {
+        hipLaunchKernelGGL(k_force_all<T>, g, b, 0, st, S, F);
+    } else if (S.colloids) {
         hipLaunchKernelGGL((k_force<T, kColloids>), g, b, 0, st, S, F);
         if (F.npl > 0)
             hipLaunchKernelGGL((k_force_part<T>), dim3(site_blocks((unsigned)F.npl)), b, 0, st, S, F);
@@ -1898,7 +1918,7 @@ __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F,
     site_forces<T>(i, o, ra, rb, jsum, El, Eh, S, F, F.phi, Pa, Pb);
 
     const bool near = G == kColloids ? (F.flags[i] & 2u) != 0 : (G == kWalls && (z == 1 || z == S.nz - 2));
-    const int link = (G == kColloids && near) ? F.linkbase[i] : 0;
+    const int link = (G == kColloids && near && F.linkdp) ? F.linkbase[i] : 0;
     const bool tau1 = S.tau == 1.0;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -1950,7 +1970,7 @@ __device__ __forceinline__ void fused_body(const Scalars& S, const Fields<T>& F,
                 }
                 const T corr = T(6) * w * rs * cv;
                 __builtin_nontemporal_store(gs - corr, fo + (size_t)opposite(d) * N + i);
-                if (own >= 0) {
+                if (own >= 0 && F.linkdp) {
                     const double dp = 2.0 * ((double)gs + weight(d) * S.rref[c]) - (double)corr;
                     double* rec = F.linkdp + (size_t)lk * 6 + 3 * c;
                     rec[0] = dp * vx(d);
@@ -1993,10 +2013,23 @@ __global__ __launch_bounds__(kBlock, kPartOcc<T>) void k_fused_part(Scalars S, F
     if (t < (unsigned)F.npl) fused_body<T, kColloids, false>(S, F, (unsigned)F.plist[t]);
 }
 
+// Every site, each taking its path by its flags (moving particles: no site list).
+template <typename T>
+__global__ __launch_bounds__(kBlock, kPartOcc<T>) void k_fused_all(Scalars S, Fields<T> F) {
+    const unsigned i = site_banded(S);
+    if (i >= S.N) return;
+    if ((F.flags[i] & kParticlePath) == 0)
+        fused_body<T, kPeriodic, false>(S, F, i);
+    else
+        fused_body<T, kColloids, false>(S, F, i);
+}
+
 template <typename T> void launch_fused(const Scalars& S, const Fields<T>& F, hipStream_t st) {
     const dim3 g(site_blocks(S.N)), b(kBlock);
     const bool ms = F.ms != nullptr;  // a moment-state context writes it from the first step on
-    if (S.colloids) {
+    if (S.reproject) {
+        hipLaunchKernelGGL(k_fused_all<T>, g, b, 0, st, S, F);
+    } else if (S.colloids) {
         hipLaunchKernelGGL((k_fused<T, kColloids, false>), g, b, 0, st, S, F);
         if (F.npl > 0)
             hipLaunchKernelGGL((k_fused_part<T>), dim3(site_blocks((unsigned)F.npl)), b, 0, st, S, F);
@@ -2027,20 +2060,57 @@ __global__ __launch_bounds__(kBlock) void k_particle_step(Scalars S, Fields<T> F
                                                           int move) {
     const int a = blockIdx.x;
     double f[3] = {0.0, 0.0, 0.0};
-    for (int t = link_off[a] + threadIdx.x; t < link_off[a + 1]; t += blockDim.x) {
-        const double* rec = F.linkdp + (size_t)link_idx[t] * 6;
-        f[0] += rec[0] + rec[3];
-        f[1] += rec[1] + rec[4];
-        f[2] += rec[2] + rec[5];
-    }
-    for (int t = site_off[a] + threadIdx.x; t < site_off[a + 1]; t += blockDim.x) {
-        const unsigned i = (unsigned)site_idx[t];
-        int sx, sy, sz;
-        site_xyz(i, S, sx, sy, sz);
-        const double qv = (double)F.qc[i];
-        f[0] += qv * efield(0, sx, sy, sz, F.phi, S);
-        f[1] += qv * efield(1, sx, sy, sz, F.phi, S);
-        f[2] += qv * efield(2, sx, sy, sz, F.phi, S);
+    if (S.reproject) {
+        // No link or site lists (the mask moves): the particle's box around its position at
+        // the step's start.  Each link from a fluid site i to a site of this particle
+        // returned f*_d - corr into i's opposite direction, so f*_d is recovered from it.
+        const int B = S.rp_box, B3 = B * B * B;
+        const int ox = (int)floor(x[3 * a]) - S.rp_half, oy = (int)floor(x[3 * a + 1]) - S.rp_half,
+                  oz = (int)floor(x[3 * a + 2]) - S.rp_half;
+        const size_t N = S.N;
+        for (int t = threadIdx.x; t < B3; t += blockDim.x) {
+            const int sx = wrapc(ox + t % B, S.nx), sy = wrapc(oy + (t / B) % B, S.ny), sz = wrapc(oz + t / (B * B), S.nz);
+            const unsigned i = (unsigned)sx + (unsigned)S.nx * ((unsigned)sy + (unsigned)S.ny * (unsigned)sz);
+            if (F.owner[i] == a) {
+                const double qv = (double)F.qc[i];
+                f[0] += qv * efield(0, sx, sy, sz, F.phi, S);
+                f[1] += qv * efield(1, sx, sy, sz, F.phi, S);
+                f[2] += qv * efield(2, sx, sy, sz, F.phi, S);
+            }
+            if (F.flags[i] & 1u) continue;
+            const Nbr o = make_nbr(sx, sy, sz, S);
+            for (int d = 0; d < kQ; ++d) {
+                if (d == kRest) continue;
+                const unsigned j = i + offset_of(o, d);
+                if (!(F.flags[j] & 1u) || F.owner[j] != a) continue;
+                const T cv = T(vx(d)) * T(v[3 * a]) + T(vy(d)) * T(v[3 * a + 1]) + T(vz(d)) * T(v[3 * a + 2]);
+                for (int c = 0; c < 2; ++c) {
+                    const T rs = T(S.rref[c]) + F.mom[(size_t)c * N + i];
+                    const T corr = T(6) * T(weight(d)) * rs * cv;
+                    const double gs = (double)F.fn[c][(size_t)opposite(d) * N + i] + (double)corr;
+                    const double dp = 2.0 * (gs + weight(d) * S.rref[c]) - (double)corr;
+                    f[0] += dp * vx(d);
+                    f[1] += dp * vy(d);
+                    f[2] += dp * vz(d);
+                }
+            }
+        }
+    } else {
+        for (int t = link_off[a] + threadIdx.x; t < link_off[a + 1]; t += blockDim.x) {
+            const double* rec = F.linkdp + (size_t)link_idx[t] * 6;
+            f[0] += rec[0] + rec[3];
+            f[1] += rec[1] + rec[4];
+            f[2] += rec[2] + rec[5];
+        }
+        for (int t = site_off[a] + threadIdx.x; t < site_off[a + 1]; t += blockDim.x) {
+            const unsigned i = (unsigned)site_idx[t];
+            int sx, sy, sz;
+            site_xyz(i, S, sx, sy, sz);
+            const double qv = (double)F.qc[i];
+            f[0] += qv * efield(0, sx, sy, sz, F.phi, S);
+            f[1] += qv * efield(1, sx, sy, sz, F.phi, S);
+            f[2] += qv * efield(2, sx, sy, sz, F.phi, S);
+        }
     }
     const int L[3] = {S.nx, S.ny, S.nz};
     for (int b = threadIdx.x; b < np; b += blockDim.x) {

@@ -34,7 +34,7 @@ class EKParams(ctypes.Structure):
         ("poisson_tol", ctypes.c_double), ("sor_omega", ctypes.c_double), ("particle_rho", ctypes.c_double),
         ("k_hertz", ctypes.c_double), ("eta", ctypes.c_double), ("phi_history", ctypes.c_int32),
         ("moment_state", ctypes.c_int32), ("sweep_band", ctypes.c_int32), ("poisson_cycles", ctypes.c_int32),
-        ("fp32_plain_collision", ctypes.c_int32), ("polarization", ctypes.c_int32),
+        ("fp32_plain_collision", ctypes.c_int32), ("polarization", ctypes.c_int32), ("reproject", ctypes.c_int32),
     ]
 
 
@@ -54,7 +54,7 @@ class EKObs(ctypes.Structure):
     ]
 
 
-N_KERNELS = 21
+N_KERNELS = 22
 
 
 class EKTiming(ctypes.Structure):
@@ -223,6 +223,7 @@ def params_from_config(cfg):
     p.poisson_cycles = int(getattr(cfg, "poisson_cycles", 0))
     p.fp32_plain_collision = int(bool(getattr(cfg, "fp32_plain_collision", False)))
     p.polarization = int(bool(getattr(cfg, "polarization", False)))
+    p.reproject = int(bool(getattr(cfg, "reproject", False)))
     return p
 
 

@@ -121,6 +121,25 @@ def test_init_rejects_polarization_where_undefined():
     assert st == ek.EK_EINVAL and "polarization" in msg, msg
 
 
+def test_init_rejects_reproject_where_unsupported():
+    """Projecting moving particles anew needs them to move, and every axis long enough for
+    the box of sites a step can change (2 ceil(r) + 9); checked before any device work."""
+    from paper_1712_08494_amd import workloads as wl
+    cfg = wl.EKConfig(28, 20, 20, reproject=True, move_particles=False)
+    inp = wl.uniform(cfg)
+    inp.particles = np.array([[7.3, 9.6, 7.9, 0.0, 0.0, 0.0, 3.5, 0.0]])
+    st, msg = _init_status(cfg, inp)
+    assert st == ek.EK_EINVAL and "move_particles" in msg, msg
+    cfg = wl.EKConfig(28, 20, 16, reproject=True)
+    inp = wl.uniform(cfg)
+    inp.particles = np.array([[7.3, 9.6, 7.9, 0.0, 0.0, 0.0, 3.5, 0.0]])
+    st, msg = _init_status(cfg, inp)
+    assert st == ek.EK_EINVAL and "axis" in msg, msg
+    cfg = wl.EKConfig(28, 20, 20, reproject=True)
+    st, msg = _init_status(cfg, wl.uniform(cfg))
+    assert st == ek.EK_EINVAL and "particles" in msg, msg
+
+
 def test_workspace_bytes_is_a_host_computation():
     """ek_workspace_bytes needs no GPU: it counts the buffers of the context's layout (the
     particle geometry is built on the host for the boundary links)."""
