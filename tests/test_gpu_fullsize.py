@@ -60,7 +60,8 @@ def test_colloids_256_properties():
 
 def test_batch_64_replicas_32cubed_vs_oracle():
     """The benchmark's replica sweep (64 droplets of 32^3, 48^3 and 64^3, FP32, 4 V-cycles per
-    step) for 5 steps; every 32^3 replica against its own FP64 oracle run."""
+    step) for 5 steps; every 32^3 replica and the first 48^3 and 64^3 replicas against their
+    own FP64 oracle runs."""
     reps = wl.replica_sweep(count=64, seed=4, precision="fp32")
     print(f"batch of 64 replicas ({sum(c.n_sites for c, _ in reps)} sites)", flush=True)
     b = ek.EKBatch([c for c, _ in reps], [i for _, i in reps], cycles=4)
@@ -71,12 +72,13 @@ def test_batch_64_replicas_32cubed_vs_oracle():
     assert np.all(last < 1e-5)
     small = [r for r, (c, _) in enumerate(reps) if c.nx == 32]
     assert len(small) >= 5
-    for r in small:
+    larger = [next(r for r, (c, _) in enumerate(reps) if c.nx == L) for L in (48, 64)]
+    for r in small + larger:
         cfg, inp = reps[r]
         o = orc.Oracle(cfg, inp)
         o.step(5)
         errs = compare(b.replica(r), o, "fp32", f"replica {r}")
-        print(f"  replica {r} (32^3, E {cfg.E_ext[2]:.1e}, G {cfg.G:.2f}): {errs}", flush=True)
+        print(f"  replica {r} ({cfg.nx}^3, E {cfg.E_ext[2]:.1e}, G {cfg.G:.2f}): {errs}", flush=True)
     b.close()
 
 
