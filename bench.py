@@ -323,7 +323,7 @@ def cpu_baseline(cfg, inp, target_s=20.0):
                       f"set-up and one untimed step"}
 
 
-def run_batched(count, steps, cycles, seed=4):
+def run_batched(count, steps, cycles, seed=4, tune_residual=None):
     """The replica sweep (droplets of sizes 32^3, 48^3, 64^3 with swept field, salt and
     coupling; FP32) as one batch with one graph launch per step, and the same replicas
     stepped one context after another."""
@@ -336,6 +336,13 @@ def run_batched(count, steps, cycles, seed=4):
     log(f"batched: {count} replicas, {sites} sites, {cycles} V-cycles per step")
     b = ek.EKBatch(cfgs, [i for _, i in reps], cycles=cycles)
     b.step(3)
+    tuned = None
+    if tune_residual:
+        shape, omega, tc, tms = b.autotune(trial_steps=10, max_residual=tune_residual)
+        tuned = {"shape": shape, "omega": omega, "v_cycles_per_step": tc, "trial_ms_per_step": round(tms, 3),
+                 "max_residual": tune_residual}
+        cycles = tc
+        log(f"batched: autotuner chose shape {shape}, omega {omega}, {tc} V-cycles per step")
     b.residuals()  # restart the worst-residual tracker after the start-up steps
     t0 = time.perf_counter()
     b.step(steps)
@@ -358,11 +365,31 @@ def run_batched(count, steps, cycles, seed=4):
     for sm in sims:
         sm.close()
     log(f"serial: {1e3 * ts / steps:.3f} ms per step of all replicas")
+    # equal work: serial contexts running the batch's fixed cycle count per step (no read-back)
+    from dataclasses import replace
+    sims = [ek.EKSim(replace(c, poisson_cycles=cycles), i) for c, i in reps]
+    for sm in sims:
+        sm.step(3)
+        sm.observables()  # restart the largest-residual record after the start-up steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for sm in sims:
+            sm.step(1)
+    torch.cuda.synchronize()
+    te = time.perf_counter() - t0
+    worst_e = max(sm.observables()["poisson_rel_max"] for sm in sims)
+    for sm in sims:
+        sm.close()
+    log(f"serial, {cycles} fixed V-cycles: {1e3 * te / steps:.3f} ms per step of all replicas")
     return {"workload": f"{count} droplet replicas of 32^3/48^3/64^3 (FP32)", "sites": sites, "steps": steps,
             "v_cycles_per_step": cycles, "mlups": round(sites * steps / tb / 1e6, 2),
             "serial_mlups": round(sites * steps / ts / 1e6, 2), "batched_over_serial": round(ts / tb, 3),
             "serial_v_cycles_per_step": round(its, 2), "worst_rel_residual": float(worst.max()),
-            "last_rel_residual": float(last.max())}
+            "last_rel_residual": float(last.max()),
+            "serial_equal_cycles_mlups": round(sites * steps / te / 1e6, 2),
+            "batched_over_serial_equal_cycles": round(te / tb, 3),
+            "serial_equal_cycles_worst_rel_residual": float(worst_e), "autotune": tuned}
 
 
 def droplet_deformation(ra, rb, background=0.1):
@@ -502,6 +529,8 @@ def main():
     ap.add_argument("--batched-replicas", type=int, default=64)
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--batched-cycles", type=int, default=4)
+    ap.add_argument("--batched-tune-residual", type=float, default=1e-8,
+                    help="autotune the batch for this worst relative residual (0: fixed --batched-cycles)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode leg")
     ap.add_argument("--autotune", type=int, default=0,
                     help="after the warm-up, let the library pick the V-cycle shape (trial steps per candidate)")
@@ -593,7 +622,8 @@ def main():
 
     batched = None
     if not args.no_batched:
-        batched = run_batched(args.batched_replicas, args.batched_steps, args.batched_cycles)
+        batched = run_batched(args.batched_replicas, args.batched_steps, args.batched_cycles,
+                              tune_residual=args.batched_tune_residual or None)
 
     adjoint = None
     if not args.no_adjoint:

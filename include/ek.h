@@ -492,6 +492,24 @@ ek_status ek_batch_residuals(struct ek_batch* b, double* last, double* worst);
    return EK_ESTATE on it. */
 ek_status ek_batch_replica(struct ek_batch* b, int32_t r, struct ek_ctx** ctx);
 
+/* Set the batch's V-cycle shape (shape: the seven counts of ek_set_multigrid; omega its
+   relaxation) and V-cycles per step (1..64), and capture its step graphs again.  The state
+   is kept.  Errors: EK_EINVAL, EK_ESTATE, EK_EHIP. */
+ek_status ek_batch_set_cycle(struct ek_batch* b, const int32_t* shape, double omega, int32_t cycles);
+
+/* Autotuner of the batched launch (a project-written tuner, no paper counterpart): for
+   every candidate shape of ek_autotune_candidates, the fewest V-cycles per step (up to 8)
+   whose worst relative Poisson residual over trial_steps steps (1..1000) stays within
+   max_residual, each timed with HIP events on the batch stream from the same saved state
+   of every replica.  The fastest is applied (an earlier candidate within 1 % is preferred)
+   and the state put back, so stepping continues from where it was.  best (optional): 8
+   int32, the shape's seven counts and the cycles; omega, ms_per_step (optional): its
+   relaxation and time per step of the whole batch.  Needs device memory for one copy of
+   every replica's state while it runs.  Errors: EK_EINVAL, EK_ESTATE, EK_ENOMEM, EK_EHIP,
+   EK_ENOCONV (no candidate met the bound; the previous shape and cycles stay). */
+ek_status ek_batch_autotune(struct ek_batch* b, int32_t trial_steps, double max_residual, int32_t* best,
+                            double* omega, double* ms_per_step);
+
 /* Release the batch, its replicas and its stream. */
 ek_status ek_batch_destroy(struct ek_batch* b);
 const char* ek_batch_last_error(const struct ek_batch* b);

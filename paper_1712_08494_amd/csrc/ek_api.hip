@@ -2405,16 +2405,37 @@ static void batch_step_launches(ek_batch* b, int parity) {
     launch_batch<T>(kB_FUSED, D, b->site.d, b->site.n, 0, 0, st);
 }
 
+// Capture one step per parity into a graph (again after a change of the cycle shape or
+// count: the descriptors carry the shape and the graph the launches of each cycle).
 template <typename T>
-static ek_status batch_setup(ek_batch* b) {
+static ek_status batch_capture(ek_batch* b) {
     const int nr = (int)b->reps.size();
-    // descriptors for the two buffer parities
+    EB_HIP(hipStreamSynchronize(b->st));
     for (int par = 0; par < 2; ++par) {
         std::vector<RepDesc<T>> h(nr);
         for (int r = 0; r < nr; ++r) h[r] = make_desc<T>(b->reps[r], par);
+        EB_HIP(hipMemcpy(b->desc[par], h.data(), nr * sizeof(RepDesc<T>), hipMemcpyHostToDevice));
+        if (b->exec[par]) (void)hipGraphExecDestroy(b->exec[par]);
+        if (b->graph[par]) (void)hipGraphDestroy(b->graph[par]);
+        b->exec[par] = nullptr;
+        b->graph[par] = nullptr;
+    }
+    for (int par = 0; par < 2; ++par) {
+        EB_HIP(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+        batch_step_launches<T>(b, par);
+        EB_HIP(hipStreamEndCapture(b->st, &b->graph[par]));
+        EB_HIP(hipGraphInstantiate(&b->exec[par], b->graph[par], nullptr, nullptr, 0));
+    }
+    return EK_OK;
+}
+
+template <typename T>
+static ek_status batch_setup(ek_batch* b) {
+    const int nr = (int)b->reps.size();
+    // descriptors for the two buffer parities (filled by batch_capture)
+    for (int par = 0; par < 2; ++par) {
         EB_HIP(hipMalloc(&b->desc[par], nr * sizeof(RepDesc<T>)));
         b->allocs.push_back(b->desc[par]);
-        EB_HIP(hipMemcpy(b->desc[par], h.data(), nr * sizeof(RepDesc<T>), hipMemcpyHostToDevice));
     }
     // block tables
     auto blocks = [](unsigned n) { return (n + kBlock - 1) / kBlock; };
@@ -2455,14 +2476,7 @@ static ek_status batch_setup(ek_batch* b) {
         EK_TRY(batch_table(b, cc, b->colors_gpu[g]));
         EK_TRY(batch_table(b, in, b->into[g]));
     }
-    // capture one step per parity into a graph
-    for (int par = 0; par < 2; ++par) {
-        EB_HIP(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
-        batch_step_launches<T>(b, par);
-        EB_HIP(hipStreamEndCapture(b->st, &b->graph[par]));
-        EB_HIP(hipGraphInstantiate(&b->exec[par], b->graph[par], nullptr, nullptr, 0));
-    }
-    return EK_OK;
+    return batch_capture<T>(b);
 }
 
 extern "C" ek_status ek_batch_init(const ek_params* params, int32_t n_rep, const double* const* rho_a,
@@ -2552,6 +2566,139 @@ extern "C" ek_status ek_batch_replica(ek_batch* b, int32_t r, ek_ctx** ctx) {
     if (!b || !ctx || r < 0 || r >= (int)b->reps.size()) return EK_EINVAL;
     *ctx = b->reps[r];
     return EK_OK;
+}
+
+#define EK_TRY_B(x)                 \
+    do {                            \
+        const ek_status s_ = (x);   \
+        if (s_ != EK_OK) return s_; \
+    } while (0)
+
+static ek_status batch_apply(ek_batch* b, const CycleShape& sh, int cycles) {
+    for (ek_ctx* c : b->reps) apply_shape(c, sh);
+    b->cycles = cycles;
+    return b->esz == 4 ? batch_capture<float>(b) : batch_capture<double>(b);
+}
+
+extern "C" ek_status ek_batch_set_cycle(ek_batch* b, const int32_t* shape, double omega, int32_t cycles) {
+    if (!b || !b->exec[0]) return EK_ESTATE;
+    if (!shape) {
+        b->err = "null shape";
+        return EK_EINVAL;
+    }
+    for (int k = 0; k < 7; ++k)
+        if (shape[k] < 0 || shape[k] > 64) {
+            b->err = "sweep counts must be in 0..64";
+            return EK_EINVAL;
+        }
+    if (shape[0] + shape[1] == 0 || shape[6] == 0 || !(omega > 0.0 && omega < 2.0) || cycles < 1 || cycles > 64) {
+        b->err = "the lattice needs a sweep per cycle, the coarsest grid one; omega in (0, 2), cycles in 1..64";
+        return EK_EINVAL;
+    }
+    CycleShape sh{{shape[0], shape[1], shape[2], shape[3], shape[4], shape[5], shape[6]}, omega};
+    return batch_apply(b, sh, cycles);
+}
+
+// Autotuner of the batched launch: for every candidate V-cycle shape, the fewest V-cycles
+// per step whose worst relative residual over trial_steps steps stays within max_residual,
+// timed with HIP events on the batch stream from the same saved state of every replica;
+// the fastest (shape, cycles) is kept and the state put back.
+template <typename T>
+static ek_status batch_autotune_impl(ek_batch* b, int trial, double maxres, int32_t* best, double* best_omega,
+                                     double* best_ms) {
+    const int nr = (int)b->reps.size();
+    EB_HIP(hipStreamSynchronize(b->st));
+    std::vector<HostState> hs(nr);
+    for (int r = 0; r < nr; ++r) {
+        ek_ctx* c = b->reps[r];
+        if (!c->tune_buf && dalloc(c, &c->tune_buf, tune_bytes(c)) != EK_OK) {
+            b->err = "replica " + std::to_string(r) + ": " + c->err;
+            return EK_ENOMEM;
+        }
+        if (tune_copy(c, true, hs[r]) != EK_OK) {
+            b->err = "replica " + std::to_string(r) + ": " + c->err;
+            return EK_EHIP;
+        }
+    }
+    const int par0 = b->parity;
+    const long long steps0 = b->steps;
+    auto restore = [&]() -> ek_status {
+        for (int r = 0; r < nr; ++r)
+            if (tune_copy(b->reps[r], false, hs[r]) != EK_OK) {
+                b->err = "replica " + std::to_string(r) + ": " + b->reps[r]->err;
+                return EK_EHIP;
+            }
+        b->parity = par0;
+        b->steps = steps0;
+        return EK_OK;
+    };
+    const ek_ctx* c0 = b->reps[0];
+    const CycleShape was{{c0->mg_fine_pre, c0->mg_fine_post, c0->mg_pre, c0->mg_post, c0->mg_tail_pre,
+                          c0->mg_tail_post, c0->mg_coarsest},
+                         c0->mg_omega};
+    const int was_cycles = b->cycles;
+    hipEvent_t e0, e1;
+    EB_HIP(hipEventCreate(&e0));
+    EB_HIP(hipEventCreate(&e1));
+    std::vector<double> worst(nr);
+    double bms = 1e300;
+    int bi = -1, bk = 0;
+    ek_status st = EK_OK;
+    for (int s = 0; s < kNumCycleShapes && st == EK_OK; ++s)
+        for (int k = 1; k <= 8; ++k) {
+            if ((st = restore()) != EK_OK || (st = batch_apply(b, kCycleShapes[s], k)) != EK_OK) break;
+            if ((st = ek_batch_residuals(b, nullptr, nullptr)) != EK_OK) break;  // restarts the worst record
+            (void)hipEventRecord(e0, b->st);
+            if ((st = ek_batch_step(b, trial)) != EK_OK) break;
+            (void)hipEventRecord(e1, b->st);
+            if ((st = ek_batch_residuals(b, nullptr, worst.data())) != EK_OK) break;
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            const double w = *std::max_element(worst.begin(), worst.end());
+            if (w <= maxres) {
+                // an earlier candidate within 1 % is kept (the default shape comes first)
+                if (ms / trial < 0.99 * bms) {
+                    bms = ms / trial;
+                    bi = s;
+                    bk = k;
+                }
+                break;  // more cycles of this shape only cost more
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == EK_OK) st = restore();
+    EB_HIP(hipStreamSynchronize(b->st));  // the restoring copies read the saved state
+    for (int r = 0; r < nr; ++r) {
+        ek_ctx* c = b->reps[r];
+        dfree(c, c->tune_buf, tune_bytes(c));
+        c->tune_buf = nullptr;
+    }
+    if (st != EK_OK) return st;
+    if (bi < 0) {  // no candidate met the bound: keep what the batch had
+        EK_TRY_B(batch_apply(b, was, was_cycles));
+        b->err = "no candidate met the residual bound within 8 V-cycles per step";
+        return EK_ENOCONV;
+    }
+    EK_TRY_B(batch_apply(b, kCycleShapes[bi], bk));
+    if (best) {
+        for (int k = 0; k < 7; ++k) best[k] = kCycleShapes[bi].v[k];
+        best[7] = bk;
+    }
+    if (best_omega) *best_omega = kCycleShapes[bi].omega;
+    if (best_ms) *best_ms = bms;
+    return EK_OK;
+}
+
+extern "C" ek_status ek_batch_autotune(ek_batch* b, int32_t trial_steps, double max_residual, int32_t* best,
+                                       double* omega, double* ms_per_step) {
+    if (!b || !b->exec[0]) return EK_ESTATE;
+    if (trial_steps < 1 || trial_steps > 1000 || !(max_residual > 0.0)) {
+        b->err = "trial_steps must be in 1..1000 and max_residual positive";
+        return EK_EINVAL;
+    }
+    return b->esz == 4 ? batch_autotune_impl<float>(b, trial_steps, max_residual, best, omega, ms_per_step)
+                       : batch_autotune_impl<double>(b, trial_steps, max_residual, best, omega, ms_per_step);
 }
 
 extern "C" ek_status ek_batch_destroy(ek_batch* b) {

@@ -66,6 +66,7 @@ EXPORTS = ["ek_lattice", "ek_min_image", "ek_kernel_name", "ek_workspace_bytes",
            "ek_get_populations", "ek_get_particles", "ek_device_bytes", "ek_set_timing", "ek_get_timing",
            "ek_destroy", "ek_status_str", "ek_last_error", "ek_batch_init", "ek_batch_step", "ek_batch_sync",
            "ek_batch_residuals", "ek_batch_replica", "ek_batch_destroy", "ek_batch_last_error",
+           "ek_batch_set_cycle", "ek_batch_autotune",
            "ek_forward_ckpt", "ek_adjoint", "ek_set_field", "ek_set_multigrid", "ek_autotune_candidates",
            "ek_autotune_multigrid"]
 
@@ -143,6 +144,11 @@ def load(path=LIB_PATH):
     L.ek_batch_sync.restype = ctypes.c_int32
     L.ek_batch_residuals.argtypes = [vp, dp, dp]
     L.ek_batch_residuals.restype = ctypes.c_int32
+    L.ek_batch_set_cycle.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_double, ctypes.c_int32]
+    L.ek_batch_set_cycle.restype = ctypes.c_int32
+    L.ek_batch_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
+                                    dp, dp]
+    L.ek_batch_autotune.restype = ctypes.c_int32
     L.ek_batch_replica.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(vp)]
     L.ek_batch_replica.restype = ctypes.c_int32
     L.ek_batch_destroy.argtypes = [vp]
@@ -490,6 +496,25 @@ class EKBatch:
         st = load().ek_batch_step(self._h, int(n))
         if st != EK_OK:
             raise EKError(st, "ek_batch_step: " + load().ek_batch_last_error(self._h).decode())
+
+    def set_cycle(self, shape, omega, cycles):
+        """V-cycle shape (seven sweep counts), relaxation and V-cycles per step (ek_batch_set_cycle)."""
+        sh = (ctypes.c_int32 * 7)(*[int(v) for v in shape])
+        st = load().ek_batch_set_cycle(self._h, sh, float(omega), int(cycles))
+        if st != EK_OK:
+            raise EKError(st, "ek_batch_set_cycle: " + load().ek_batch_last_error(self._h).decode())
+
+    def autotune(self, trial_steps=20, max_residual=1e-8):
+        """Pick the fastest (shape, cycles per step) meeting max_residual (ek_batch_autotune);
+        returns (shape, omega, cycles, ms per step)."""
+        best = (ctypes.c_int32 * 8)()
+        om = ctypes.c_double(0.0)
+        ms = ctypes.c_double(0.0)
+        st = load().ek_batch_autotune(self._h, int(trial_steps), float(max_residual), best, ctypes.byref(om),
+                                      ctypes.byref(ms))
+        if st != EK_OK:
+            raise EKError(st, "ek_batch_autotune: " + load().ek_batch_last_error(self._h).decode())
+        return list(best[:7]), om.value, best[7], ms.value
 
     def sync(self):
         load().ek_batch_sync(self._h)

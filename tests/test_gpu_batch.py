@@ -76,3 +76,32 @@ def test_batch_rejects_walls():
     with pytest.raises(ek.EKError) as e:
         ek.EKBatch([cfg], [inp])
     assert e.value.status == ek.EK_EINVAL
+
+
+def test_batch_autotune_restores_state_and_meets_its_bound():
+    """ek_batch_autotune tries (shape, cycles) candidates from a saved state: afterwards the
+    replicas hold the state they had, the chosen configuration keeps the worst residual
+    within the bound, and the run continues bit for bit as a batch given that
+    configuration by ek_batch_set_cycle."""
+    reps = _replicas("fp32")
+    cfgs, inps = [c for c, _ in reps], [i for _, i in reps]
+    b = ek.EKBatch(cfgs, inps, cycles=4)
+    b.step(3)
+    before = [b.replica(r).field("rho_a") for r in range(len(reps))]
+    shape, omega, cycles, ms = b.autotune(trial_steps=5, max_residual=1e-7)
+    print(f"tuned: shape {shape} omega {omega} cycles {cycles} {ms:.3f} ms/step", flush=True)
+    for r in range(len(reps)):
+        assert np.array_equal(b.replica(r).field("rho_a"), before[r]), r
+    b.residuals()
+    b.step(10)
+    _, worst = b.residuals()
+    assert worst.max() <= 1e-7 * 1.5, worst.max()  # steps beyond the trial, same regime
+    ref = ek.EKBatch(cfgs, inps, cycles=4)
+    ref.step(3)
+    ref.set_cycle(shape, omega, cycles)
+    ref.step(10)
+    for r in range(len(reps)):
+        for name in ("rho_a", "n_plus", "phi"):
+            assert np.array_equal(b.replica(r).field(name), ref.replica(r).field(name)), (r, name)
+    b.close()
+    ref.close()
