@@ -60,14 +60,16 @@ __device__ __forceinline__ T psif_at(unsigned j, int zj, const Scalars& S, const
     return S.colloids ? F.psif[j] : (wall_layer(zj, S) ? T(0) : T(1));
 }
 
-template <typename T> __device__ __forceinline__ T expT(T v);
-template <> __device__ __forceinline__ float expT<float>(float v) { return expf(v); }
-template <> __device__ __forceinline__ double expT<double>(double v) { return exp(v); }
+template <typename T> __device__ __forceinline__ T expm1T(T v);
+template <> __device__ __forceinline__ float expm1T<float>(float v) { return expm1f(v); }
+template <> __device__ __forceinline__ double expm1T<double>(double v) { return expm1(v); }
 
 template <typename T> __device__ __forceinline__ T pseudo(T rho, const Scalars& S) {
-    // psi = rho0 (1 - exp(-rho / rho0)), Sec. II C
+    // psi = rho0 (1 - exp(-rho / rho0)), Sec. II C, written as -rho0 expm1(-rho / rho0): in
+    // the minority phase (rho ~ 0.01) the difference 1 - exp(...) would lose about two of
+    // FP32's seven digits.
     const T r0 = T(S.rho0);
-    return r0 * (T(1) - expT<T>(-rho / r0));
+    return -r0 * expm1T<T>(-rho / r0);
 }
 
 // Fluid permittivity (eq. dielectric_constant) mixed with the particle permittivity

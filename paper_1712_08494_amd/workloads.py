@@ -111,12 +111,12 @@ def mixture_noise(n=32, seed=1, precision="fp64", G=3.6, shape=None):
 # ---------------------------------------------------------------------------------
 # Workload 2: charged walls in z and a flat interface between the two fluids.
 # Phase densities are the coexisting bulk densities of a flat Shan-Chen interface at
-# the paper's coupling G = 4.0 and total density 1.386 (a 64-site column relaxed for
-# 35000 steps on the CPU reference; drift below 1e-12).
+# the paper's coupling G = 4.0 and mean total density 1.386: a 64-site column relaxed for
+# 35000 steps on the CPU reference (oracle/calibrate_interface.py prints them).
 # ---------------------------------------------------------------------------------
 WALL_G = 4.0
-WALL_RHO_MAJ = 1.41401
-WALL_RHO_MIN = 0.01253
+WALL_RHO_MAJ = 1.41527
+WALL_RHO_MIN = 0.01112
 
 
 def _bisect(f, lo, hi, it=200):
