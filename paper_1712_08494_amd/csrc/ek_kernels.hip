@@ -454,47 +454,54 @@ __device__ __forceinline__ unsigned cidx(const Scalars& S, unsigned i, int color
 // The row with the neighbour potentials supplied by pv(j, colour, ox, oy, oz) for the
 // neighbour j at offset (ox, oy, oz); poisson_row reads them from F.phi.  Evaluated
 // without multiply-add contraction, so that callers supplying the neighbour values
-// differently (loaded, or interpolated on the fly) round the row identically.
+// differently (loaded, or interpolated on the fly) round the row identically.  Every
+// operand is fetched before the arithmetic: the faces that an axis of length 1 or a wall
+// leaves out are fetched too (their indices are lattice sites: the site itself, or a wall
+// layer) and then not used, so the loads carry no branches and issue together.
 template <typename T, bool SP, typename PV>
 __device__ __forceinline__ void poisson_row_v(unsigned i, int x, int y, int z, const Scalars& S, const Fields<T>& F,
                                               PV&& pv, double& diag, double& offsum, double& src) {
 #pragma clang fp contract(off)
     const int own = SP ? ((x + y + z) & 1) : 0, nb = own ^ 1;
+    const unsigned xa = i + (x == 0 ? S.nx - 1 : -1), xb = i + (x == S.nx - 1 ? -(S.nx - 1) : 1);
+    const unsigned ya = i + (y == 0 ? (S.ny - 1) * S.nx : -S.nx), yb = i + (y == S.ny - 1 ? -(S.ny - 1) * S.nx : S.nx);
+    const unsigned za = i + (z == 0 ? (S.nz - 1) * S.nxy : -S.nxy), zb = i + (z == S.nz - 1 ? -(S.nz - 1) * S.nxy : S.nxy);
     const double ei = (double)F.eps[i];
+    const double exa = (double)F.eps[xa], exb = (double)F.eps[xb], eya = (double)F.eps[ya], eyb = (double)F.eps[yb],
+                 eza = (double)F.eps[za], ezb = (double)F.eps[zb];
+    const double pxa = pv(xa, nb, -1, 0, 0), pxb = pv(xb, nb, 1, 0, 0), pya = pv(ya, nb, 0, -1, 0),
+                 pyb = pv(yb, nb, 0, 1, 0), pza = pv(za, nb, 0, 0, -1), pzb = pv(zb, nb, 0, 0, 1);
+    double s = (double)F.q[cidx<SP>(S, i, own)];
     diag = 0.0;
     offsum = 0.0;
     double pol = 0.0;  // sum over the faces of eps_f (E_ext . c_d): the polarisation source
-    if (S.nx > 1) {
-        const unsigned a = i + (x == 0 ? S.nx - 1 : -1), b = i + (x == S.nx - 1 ? -(S.nx - 1) : 1);
-        const double ea = 0.5 * (ei + (double)F.eps[a]), eb = 0.5 * (ei + (double)F.eps[b]);
+    // A face that is left out (an axis of length 1, a wall) is taken with a zero
+    // coefficient: adding +0 leaves every sum as it is, and the row has no branches, so the
+    // loads of consecutive rows can overlap.
+    {
+        const bool on = S.nx > 1;
+        const double ea = on ? 0.5 * (ei + exa) : 0.0, eb = on ? 0.5 * (ei + exb) : 0.0;
         diag += ea + eb;
-        offsum += ea * pv(a, nb, -1, 0, 0) + eb * pv(b, nb, 1, 0, 0);
+        offsum += ea * pxa + eb * pxb;
         pol += S.E_ext[0] * (eb - ea);
     }
-    if (S.ny > 1) {
-        const unsigned a = i + (y == 0 ? (S.ny - 1) * S.nx : -S.nx), b = i + (y == S.ny - 1 ? -(S.ny - 1) * S.nx : S.nx);
-        const double ea = 0.5 * (ei + (double)F.eps[a]), eb = 0.5 * (ei + (double)F.eps[b]);
+    {
+        const bool on = S.ny > 1;
+        const double ea = on ? 0.5 * (ei + eya) : 0.0, eb = on ? 0.5 * (ei + eyb) : 0.0;
         diag += ea + eb;
-        offsum += ea * pv(a, nb, 0, -1, 0) + eb * pv(b, nb, 0, 1, 0);
+        offsum += ea * pya + eb * pyb;
         pol += S.E_ext[1] * (eb - ea);
     }
-    if (S.nz > 1) {
-        if (!(S.walls && z == S.z0)) {
-            const unsigned a = i + (z == 0 ? (S.nz - 1) * S.nxy : -S.nxy);
-            const double ea = 0.5 * (ei + (double)F.eps[a]);
-            diag += ea;
-            offsum += ea * pv(a, nb, 0, 0, -1);
-            pol -= S.E_ext[2] * ea;
-        }
-        if (!(S.walls && z == S.z1)) {
-            const unsigned b = i + (z == S.nz - 1 ? -(S.nz - 1) * S.nxy : S.nxy);
-            const double eb = 0.5 * (ei + (double)F.eps[b]);
-            diag += eb;
-            offsum += eb * pv(b, nb, 0, 0, 1);
-            pol += S.E_ext[2] * eb;
-        }
+    {
+        const bool lo = S.nz > 1 && !(S.walls && z == S.z0), hi = S.nz > 1 && !(S.walls && z == S.z1);
+        const double ea = lo ? 0.5 * (ei + eza) : 0.0, eb = hi ? 0.5 * (ei + ezb) : 0.0;
+        diag += ea;
+        offsum += ea * pza;
+        pol -= S.E_ext[2] * ea;
+        diag += eb;
+        offsum += eb * pzb;
+        pol += S.E_ext[2] * eb;
     }
-    double s = (double)F.q[cidx<SP>(S, i, own)];
     if (S.walls && z == S.z0) s += S.sigma0;
     if (S.walls && z == S.z1) s += S.sigma1;
     if (S.polar) s -= pol;
@@ -554,16 +561,16 @@ __device__ __forceinline__ bool sor_site(const Scalars& S, const Fields<T>& F, u
         x = 2 * m + ((color + y + z) & 1);
         i = x + S.nx * (y + S.ny * z);
     }
+    o = cidx<SP>(S, i, color);
+    const double p = OWN ? own[i >> 1] : F.phi[o];
     double diag, offsum, src;
     poisson_row<T, SP>(i, x, y, z, S, F, diag, offsum, src);
-    o = cidx<SP>(S, i, color);
     if (diag <= 0.0) {  // an isolated site keeps its value (with OWN: the one in own)
         if (!OWN) return false;
-        v = own[i >> 1];
+        v = p;
         return true;
     }
     const double gs = (offsum + src) / diag;
-    const double p = OWN ? own[i >> 1] : F.phi[o];
     v = sor_update(p, gs, omega);
     return true;
 }
@@ -605,22 +612,22 @@ void launch_sor(const Scalars& S, const Fields<T>& F, int color, double omega, b
 }
 
 // Residual r = s + A phi: FP64 partial sums of r.r, s.s and phi over the domain.
+// The operands are fetched for a lattice site whether or not i lies in the domain (outside
+// it: a wall layer, or the last site past the end) and the sums take zeros there, so the
+// loads of the sites a thread handles carry no branches and can overlap.
 template <typename T, bool SP = false>
 __device__ __forceinline__ void residual_body(const Scalars& S, const Fields<T>& F, unsigned i, double (&v)[3]) {
-    v[0] = v[1] = v[2] = 0.0;
-    if (i < S.N) {
-        int x, y, z;
-        site_xyz(i, S, x, y, z);
-        if (z >= S.z0 && z <= S.z1) {
-            double diag, offsum, src;
-            poisson_row<T, SP>(i, x, y, z, S, F, diag, offsum, src);
-            const double p = F.phi[cidx<SP>(S, i, (x + y + z) & 1)];
-            const double res = src + offsum - diag * p;
-            v[0] = res * res;
-            v[1] = src * src;
-            v[2] = p;
-        }
-    }
+    const unsigned k = i < S.N ? i : S.N - 1;
+    int x, y, z;
+    site_xyz(k, S, x, y, z);
+    const bool in = i < S.N && z >= S.z0 && z <= S.z1;
+    const double p = F.phi[cidx<SP>(S, k, (x + y + z) & 1)];
+    double diag, offsum, src;
+    poisson_row<T, SP>(k, x, y, z, S, F, diag, offsum, src);
+    const double res = src + offsum - diag * p;
+    v[0] = in ? res * res : 0.0;
+    v[1] = in ? src * src : 0.0;
+    v[2] = in ? p : 0.0;
 }
 
 // Each thread takes kResSites sites, kBlock apart (a workgroup covers kResSites x kBlock
