@@ -43,6 +43,8 @@ def algorithmic_bytes(kernel, s, tau_one=True, mask=0):
         # one red-black colour pass over the lattice: half of a sweep's potential read +
         # write (16), charge (s) and permittivity (s)
         return (16 + 2 * s) / 2
+    if kernel == "k_sor_rb":     # a whole red-black sweep in one pass
+        return 16 + 2 * s
     return 0.0
 
 
@@ -573,6 +575,7 @@ def main():
 
     # executed lattice sweeps per step (two colour passes each) and the whole step's rate
     passes = sum(kt[k][1] for k in ("k_sor", "k_sor_black_from", "k_mg_prolong_red_fine") if k in kt)
+    passes += 2 * kt.get("k_sor_rb", (0.0, 0))[1]
     sweeps = passes / 2 / args.kernel_steps if args.kernel_steps else None
     cycles = (ob1["poisson_total"] - ob0["poisson_total"]) / args.steps
     step_b = step_bytes(s, mask) + (sweeps or 0.0) * sweep_bytes(s)

@@ -209,7 +209,8 @@ typedef struct ek_obs {
 #define EK_K_PARTICLE 19         /* particle forces and integration */
 #define EK_K_LAGGED 20           /* a whole lagged Fourier solve (right-hand side, transforms, division) */
 #define EK_K_REPROJECT 21        /* projection of moving particles after their step (reproject) */
-#define EK_K_COUNT 22
+#define EK_K_SOR_RB 22           /* one whole red-black lattice sweep in one pass (colour-split solves) */
+#define EK_K_COUNT 23
 
 typedef struct ek_timing {
     double ms[EK_T_COUNT];    /* summed device time per class (HIP events) */

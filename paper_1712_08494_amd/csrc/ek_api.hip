@@ -39,6 +39,7 @@ struct ek_ctx {
     size_t ws_size = 0, ws_used = 0;
     int ws_mode = 0;
     bool split_layout = false;  // multigrid solves on colour-split copies of potential and charge
+    bool one_pass = false;      // lattice sweeps of a colour-split solve in one pass (k_sor_rb) where it fits
     int fixed_cycles = 0;       // > 0: that many V-cycles per step, no host read-back (ek_params.poisson_cycles)
     double rel_max = 0.0;       // largest relative residual of the solves since the last ek_observables
     double* obs_scratch = nullptr;  // this device's address of the library's observables scratch array
@@ -551,13 +552,29 @@ static ek_status check_residual(ek_ctx* c, const Fields<T>& F, bool split, bool 
 // kernel (the coarsest solve, and the sweeps of the grid above it when small enough).
 // split: F holds the colour-split lattice potential and charge.
 template <typename T>
-static void vcycle(ek_ctx* c, const Fields<T>& F, bool split) {
+static void vcycle(ek_ctx* c, const Fields<T>& F0, bool split) {
     const int nl = (int)c->mg.size();
     const int tail_mid = (nl >= 2 && c->mg[nl - 2].n <= 4096 && c->mg[nl - 1].n <= 512) ? 1 : 0;
     const int last_gpu = nl - 1 - tail_mid;  // finest grid handled by the tail, minus one
+    // F.phi: the buffer that holds the lattice potential.  On colour-split fields a lattice
+    // sweep runs in one pass (k_sor_rb) from one buffer to the other (F0.phi, c->stage)
+    // where the kernel fits; an even number of such sweeps per cycle, so that the cycle
+    // ends in F0.phi, and the rest as two colour passes in place.
+    Fields<T> F = F0;
+    const bool rb = split && c->one_pass && sor_rb_fits(c->S);
+    int rb_left = rb ? c->mg_fine_pre + c->mg_fine_post - (c->mg_fine_post >= 1 ? 1 : 0) : 0;
+    rb_left -= rb_left & 1;
     // multigrid grids have even axes: two colours; first = 1 skips the red pass (taken by the
     // restriction into a launched coarse grid)
     auto smooth = [&](int g, int first = 0) {
+        if (g == 0 && first == 0 && rb_left > 0) {
+            double* to = F.phi == F0.phi ? c->stage : F0.phi;
+            EK_KT(EK_K_SOR_RB);
+            launch_sor_rb<T>(c->S, F, F.phi, to, c->mg_omega, c->st);
+            F.phi = to;
+            --rb_left;
+            return;
+        }
         for (int color = first; color < 2; ++color) {
             if (g == 0) {
                 EK_KT(EK_K_SOR);
@@ -1437,6 +1454,12 @@ static ek_status configure(ek_ctx* c, const ek_params* p, const ek_particle* par
     // the results are the same, bit for bit)
     const char* site_order = std::getenv("EK_POISSON_SITE_ORDER");
     c->split_layout = !c->mg.empty() && !(site_order && std::atoi(site_order) != 0);
+    // EK_POISSON_ONE_PASS=1 runs the lattice sweeps of colour-split solves in one pass
+    // (k_sor_rb) where it fits.  The results are the same, bit for bit; on gfx950 the two
+    // colour passes are faster (the one-pass kernel is bound by its FP64 rows, recomputed on
+    // the ring), so they are the default.
+    const char* one_pass = std::getenv("EK_POISSON_ONE_PASS");
+    c->one_pass = one_pass && std::atoi(one_pass) != 0;
     c->esz = p->precision == EK_FP32 ? 4 : 8;
     return EK_OK;
 }
@@ -2249,7 +2272,7 @@ extern "C" const char* ek_kernel_name(int32_t k) {
         "k_moments", "k_virtual", "k_source_mean", "k_phi_extrapolate", "k_residual", "k_reduce",
         "k_mg_coarsen", "k_sor", "k_sor_black_from", "k_mg_restrict_fine", "k_mg_restrict", "k_mg_smooth",
         "k_mg_tail", "k_mg_prolong_red_fine", "k_mg_prolong_fine", "k_mg_prolong", "k_phi_finalize", "k_force",
-        "k_fused", "k_particle_step", "lagged_fourier", "k_reproject"};
+        "k_fused", "k_particle_step", "lagged_fourier", "k_reproject", "k_sor_rb"};
     return k >= 0 && k < EK_K_COUNT ? names[k] : "";
 }
 

@@ -10,11 +10,13 @@ namespace ek {
 
 // Workgroups are dispatched round-robin over the 8 XCDs (XCD = blockIdx % 8).  Give XCD k
 // the contiguous block range [k * nb/8, (k+1) * nb/8) so its L2 holds a slab of planes.
+// The kernels that use it run kBlock threads per workgroup; the constant saves the load of
+// the workgroup size from the kernel's implicit arguments that blockDim.x costs.
 __device__ __forceinline__ unsigned xcd_linear() {
     const unsigned nb = gridDim.x;  // multiple of 8 (site_blocks)
     const unsigned b = blockIdx.x;
     const unsigned lb = (b & 7u) * (nb >> 3) + (b >> 3);
-    return lb * blockDim.x + threadIdx.x;
+    return lb * kBlock + threadIdx.x;
 }
 
 // The same XCD split for the stencil sweeps over the lattice, with the slab walked band by
@@ -28,13 +30,13 @@ __device__ __forceinline__ unsigned xcd_linear() {
 __device__ __forceinline__ unsigned site_banded(const Scalars& S) {
     const unsigned b = blockIdx.x;
     const unsigned x8 = b & 7u, s = b >> 3;  // XCD and position in its sequence
-    if (S.band <= 0) return (x8 * (gridDim.x >> 3) + s) * blockDim.x + threadIdx.x;
+    if (S.band <= 0) return (x8 * (gridDim.x >> 3) + s) * kBlock + threadIdx.x;
     const unsigned B = (unsigned)S.band, P = (unsigned)S.plane_blocks, nzs = (unsigned)S.slab_planes;
     const unsigned per_band = nzs * B;
     const unsigned band = s / per_band, rem = s - band * per_band;
     const unsigned zz = rem / B, j = rem - zz * B;
     const unsigned lb = (x8 * nzs + zz) * P + band * B + j;
-    return lb * blockDim.x + threadIdx.x;
+    return lb * kBlock + threadIdx.x;
 }
 
 // Minimum image of a separation along a periodic axis of length n: the whole periods that

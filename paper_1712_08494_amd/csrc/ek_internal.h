@@ -180,6 +180,12 @@ void launch_mg_prolong_red_fine(const Scalars& S, const Fields<T>& F, const MGLe
                                 hipStream_t st);
 template <typename T>
 void launch_sor_black_from(const Scalars& S, const Fields<T>& F, double omega, const double* blk, hipStream_t st);
+// One whole red-black sweep in one pass, colour-split fields from pin to pout (F.phi is not
+// read); only where sor_rb_fits(S).
+bool sor_rb_fits(const Scalars& S);
+template <typename T>
+void launch_sor_rb(const Scalars& S, const Fields<T>& F, const double* pin, double* pout, double omega,
+                   hipStream_t st);
 void launch_mg_prolong(const MGLevel& c, const MGLevel& f, hipStream_t st);
 void launch_mg_tail(const MGLevel& mid, const MGLevel& coarse, int has_mid, int iters, double omega, int mid_pre,
                     int mid_post, double mid_omega, hipStream_t st);

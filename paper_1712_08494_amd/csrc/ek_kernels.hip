@@ -356,7 +356,7 @@ template <typename T> void launch_moments(const Scalars& S, const Fields<T>& F, 
 // (moving particles change the mask).
 template <typename T, bool ALL>
 __global__ __launch_bounds__(kBlock) void k_virtual(Scalars S, Fields<T> F) {
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned t = blockIdx.x * kBlock + threadIdx.x;
     if (ALL ? t >= S.N || !(F.flags[t] & 4u) : (int)t >= F.nv) return;
     const unsigned i = ALL ? t : (unsigned)F.vlist[t];
     int x, y, z;
@@ -458,20 +458,22 @@ __device__ __forceinline__ unsigned cidx(const Scalars& S, unsigned i, int color
 // operand is fetched before the arithmetic: the faces that an axis of length 1 or a wall
 // leaves out are fetched too (their indices are lattice sites: the site itself, or a wall
 // layer) and then not used, so the loads carry no branches and issue together.
-template <typename T, bool SP, typename PV>
-__device__ __forceinline__ void poisson_row_v(unsigned i, int x, int y, int z, const Scalars& S, const Fields<T>& F,
-                                              PV&& pv, double& diag, double& offsum, double& src) {
+// The permittivities come from ev(j, ox, oy, oz) the same way and the charge from qv()
+// (poisson_row_v: from F.eps and F.q).
+template <typename T, bool SP, typename PV, typename EV, typename QV>
+__device__ __forceinline__ void poisson_row_ve(unsigned i, int x, int y, int z, const Scalars& S, const Fields<T>& F,
+                                               PV&& pv, EV&& ev, QV&& qv, double& diag, double& offsum, double& src) {
 #pragma clang fp contract(off)
     const int own = SP ? ((x + y + z) & 1) : 0, nb = own ^ 1;
     const unsigned xa = i + (x == 0 ? S.nx - 1 : -1), xb = i + (x == S.nx - 1 ? -(S.nx - 1) : 1);
     const unsigned ya = i + (y == 0 ? (S.ny - 1) * S.nx : -S.nx), yb = i + (y == S.ny - 1 ? -(S.ny - 1) * S.nx : S.nx);
     const unsigned za = i + (z == 0 ? (S.nz - 1) * S.nxy : -S.nxy), zb = i + (z == S.nz - 1 ? -(S.nz - 1) * S.nxy : S.nxy);
-    const double ei = (double)F.eps[i];
-    const double exa = (double)F.eps[xa], exb = (double)F.eps[xb], eya = (double)F.eps[ya], eyb = (double)F.eps[yb],
-                 eza = (double)F.eps[za], ezb = (double)F.eps[zb];
+    const double ei = ev(i, 0, 0, 0);
+    const double exa = ev(xa, -1, 0, 0), exb = ev(xb, 1, 0, 0), eya = ev(ya, 0, -1, 0), eyb = ev(yb, 0, 1, 0),
+                 eza = ev(za, 0, 0, -1), ezb = ev(zb, 0, 0, 1);
     const double pxa = pv(xa, nb, -1, 0, 0), pxb = pv(xb, nb, 1, 0, 0), pya = pv(ya, nb, 0, -1, 0),
                  pyb = pv(yb, nb, 0, 1, 0), pza = pv(za, nb, 0, 0, -1), pzb = pv(zb, nb, 0, 0, 1);
-    double s = (double)F.q[cidx<SP>(S, i, own)];
+    double s = qv();
     diag = 0.0;
     offsum = 0.0;
     double pol = 0.0;  // sum over the faces of eps_f (E_ext . c_d): the polarisation source
@@ -506,6 +508,14 @@ __device__ __forceinline__ void poisson_row_v(unsigned i, int x, int y, int z, c
     if (S.walls && z == S.z1) s += S.sigma1;
     if (S.polar) s -= pol;
     src = s - F.scal[0];
+}
+
+template <typename T, bool SP, typename PV>
+__device__ __forceinline__ void poisson_row_v(unsigned i, int x, int y, int z, const Scalars& S, const Fields<T>& F,
+                                              PV&& pv, double& diag, double& offsum, double& src) {
+    poisson_row_ve<T, SP>(
+        i, x, y, z, S, F, pv, [&](unsigned j, int, int, int) { return (double)F.eps[j]; },
+        [&]() { return (double)F.q[cidx<SP>(S, i, SP ? ((x + y + z) & 1) : 0)]; }, diag, offsum, src);
 }
 
 template <typename T, bool SP = false>
@@ -600,6 +610,188 @@ template <typename T>
 void launch_sor_black_from(const Scalars& S, const Fields<T>& F, double omega, const double* blk, hipStream_t st) {
     const unsigned n = (unsigned)(S.nx / 2) * S.ny * (S.z1 - S.z0 + 1);
     hipLaunchKernelGGL(k_sor_black_from<T>, dim3(site_blocks(n)), dim3(kBlock), 0, st, S, F, omega, blk);
+}
+
+// One whole red-black sweep in one pass over colour-split fields, from pin to pout.  A
+// workgroup owns a tile of kRbTX x kRbTY sites over a range of planes and marches up
+// through them, holding three planes of the old potential, four of the permittivity and
+// three of new red values in LDS.  At plane k it computes the red update of plane k on the
+// tile and a one-site ring around it, then the black update of plane k - 1 on the tile.
+// The red update reads only old black values, the black update only new red ones, both
+// from LDS, so the result is the one the two colour passes give, bit for bit: the same
+// rows, in the same operand order.  The ring's red values are computed again by the
+// neighbouring tiles, which need them too; the second buffer keeps the old values that
+// other workgroups still read.  Two colour passes move 2 x 18 B/site in FP32 (each
+// re-reads the charge and permittivity of both colours); this pass 24 B/site.  With walls
+// the wall layers are copied, so that every value a row of the next pass reads is set.
+constexpr int kRbTX = 64, kRbTY = 4, kRbLX = kRbTX + 4, kRbLY = kRbTY + 4, kRbP = kRbLX * kRbLY;
+constexpr int kRbRed = (kRbTX + 2) / 2 * (kRbTY + 2);  // red sites of the tile and its ring, per plane
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sor_rb(Scalars S, Fields<T> F, const double* __restrict__ pin,
+                                                  double* __restrict__ pout, double omega, int zc, unsigned nwork) {
+    static_assert(kRbTX * kRbTY == kBlock && kRbRed <= kBlock, "one tile site and one ring red site per thread");
+    constexpr int kLoads = (kRbP + kBlock - 1) / kBlock;  // LDS positions per thread and plane
+    constexpr int kHalfRow = kRbTX / 2, kRingRow = (kRbTX + 2) / 2;
+    __shared__ double sphi[3][kRbP];  // old potential, planes k - 1, k, k + 1
+    __shared__ T seps[4][kRbP];       // permittivity, planes k - 2 .. k + 1
+    __shared__ double sred[3][kRbP];  // new red values, planes k - 2, k - 1, k (tile and ring)
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned w = (b & 7u) * (nb >> 3) + (b >> 3);  // XCD-contiguous ranges of tiles
+    if (w >= nwork) return;
+    const unsigned ntx = (unsigned)S.nx / kRbTX, nty = (unsigned)S.ny / kRbTY;
+    const unsigned tx = w % ntx, rest = w / ntx, ty = rest % nty, chunk = rest / nty;
+    const int x0 = (int)tx * kRbTX, y0 = (int)ty * kRbTY;
+    const int zs = S.z0 + (int)chunk * zc, ze = min(zs + zc, S.z1 + 1);  // planes [zs, ze)
+    const int t = threadIdx.x;
+    const unsigned nx = (unsigned)S.nx, nxy = (unsigned)S.nxy, half = (unsigned)S.N >> 1;
+    // a plane index k in [zs - 2, ze + 1] that is a lattice plane (with walls: 0 .. nz - 1)
+    auto inside = [&](int k) { return !S.walls || (k >= 0 && k < S.nz); };
+    auto zplane = [&](int k) { return S.walls ? min(max(k, 0), S.nz - 1) : wrapc(k, S.nz); };
+    auto s3 = [&](int k) { return (k - zs + 3) % 3; };  // k >= zs - 2
+    auto s4 = [&](int k) { return (k - zs + 4) % 4; };
+    // colour-split index of the site at in-plane offset xy (x + nx y, colour parity c of
+    // x + y) in plane z
+    auto split = [&](unsigned xy, int c, int z) {
+        const unsigned i = xy + nxy * (unsigned)z;
+        return (((c + z) & 1) ? half : 0u) + (i >> 1);
+    };
+    // The thread's LDS positions of a plane (in-plane offsets and parities are the same in
+    // every plane).  The next plane's potential and permittivity go to registers one step
+    // ahead and into LDS at the next step, so their loads overlap a step's arithmetic.
+    unsigned f_xy[kLoads];
+    int f_c[kLoads];
+#pragma unroll
+    for (int j = 0; j < kLoads; ++j) {
+        const int p = min(t + j * kBlock, kRbP - 1);
+        const int ly = p / kRbLX, lx = p - ly * kRbLX;
+        const int x = wrapc(x0 - 2 + lx, S.nx), y = wrapc(y0 - 2 + ly, S.ny);
+        f_xy[j] = (unsigned)x + nx * (unsigned)y;
+        f_c[j] = (x + y) & 1;
+    }
+    double rphi[kLoads];
+    T reps[kLoads];
+    auto fetch = [&](int k) {
+        const int zz = zplane(k);
+#pragma unroll
+        for (int j = 0; j < kLoads; ++j) {
+            rphi[j] = pin[split(f_xy[j], f_c[j], zz)];
+            reps[j] = F.eps[f_xy[j] + nxy * (unsigned)zz];
+        }
+    };
+    auto commit = [&](int k) {
+        if (!inside(k)) return;  // not a plane: never read
+        double* dp = sphi[s3(k)];
+        T* de = seps[s4(k)];
+#pragma unroll
+        for (int j = 0; j < kLoads; ++j) {
+            const int p = t + j * kBlock;
+            if (p < kRbP) {
+                dp[p] = rphi[j];
+                de[p] = reps[j];
+            }
+        }
+    };
+    // The thread's red site of the tile and ring (t < kRbRed), and its tile site: the black
+    // sites of the tile for t < kBlock / 2, the red ones for the others.  Both depend on the
+    // parity of the plane: [0] even planes, [1] odd.
+    int r_x[2], r_p[2], r_y = 0;
+    unsigned r_xy[2];
+    int b_x[2], b_p[2], b_y;
+    unsigned b_xy[2];
+    {
+        const int ly = 1 + t / kRingRow, m = t - (ly - 1) * kRingRow;
+        r_y = wrapc(y0 - 2 + ly, S.ny);
+        const int u = t & (kBlock / 2 - 1), r = u / kHalfRow, mb = u - r * kHalfRow;
+        b_y = y0 + r;
+        const int want = t < kBlock / 2 ? 1 : 0;  // colour of the tile site
+#pragma unroll
+        for (int pz = 0; pz < 2; ++pz) {
+            const int lx = 1 + ((r_y + pz + 1) & 1) + 2 * m;  // x + y + z even (x0 is even)
+            r_x[pz] = wrapc(x0 - 2 + lx, S.nx);
+            r_p[pz] = ly * kRbLX + lx;
+            r_xy[pz] = (unsigned)r_x[pz] + nx * (unsigned)r_y;
+            const int bx = 2 * mb + ((b_y + pz + want) & 1);  // x + y + z has the wanted parity
+            b_x[pz] = x0 + bx;
+            b_p[pz] = (2 + r) * kRbLX + 2 + bx;
+            b_xy[pz] = (unsigned)b_x[pz] + nx * (unsigned)b_y;
+        }
+    }
+    const bool black = t < kBlock / 2;
+    // charges, one step ahead: of the red site of plane k and of the black tile site of plane k - 1
+    auto q_red = [&](int k) {
+        const int zz = zplane(k), pz = zz & 1;
+        return t < kRbRed ? F.q[(r_xy[pz] + nxy * (unsigned)zz) >> 1] : T(0);  // red: the first half
+    };
+    auto q_black = [&](int k) {
+        const int zz = zplane(k), pz = zz & 1;
+        return black ? F.q[half + ((b_xy[pz] + nxy * (unsigned)zz) >> 1)] : T(0);
+    };
+    // the row at LDS position p of plane k with neighbour potentials from plane ring v
+    auto update = [&](const double (*v)[kRbP], int p, int k, int x, int y, int zz, T q) {
+        double diag, offsum, src;
+        poisson_row_ve<T, true>(
+            0u, x, y, zz, S, F, [&](unsigned, int, int ox, int oy, int oz) { return v[s3(k + oz)][p + ox + oy * kRbLX]; },
+            [&](unsigned, int ox, int oy, int oz) { return (double)seps[s4(k + oz)][p + ox + oy * kRbLX]; },
+            [&]() { return (double)q; }, diag, offsum, src);
+        const double old = sphi[s3(k)][p];
+        return diag > 0.0 ? sor_update(old, (offsum + src) / diag, omega) : old;  // an isolated site keeps its value
+    };
+    fetch(zs - 2);
+    commit(zs - 2);
+    fetch(zs - 1);
+    commit(zs - 1);
+    fetch(zs);
+    commit(zs);
+    fetch(zs + 1);
+    T qr = q_red(zs - 1), qb = T(0);
+    for (int k = zs - 1; k <= ze; ++k) {
+        if (k >= zs) {
+            commit(k + 1);
+            if (k + 2 <= ze + 1) fetch(k + 2);
+        }
+        const T qr_next = q_red(min(k + 1, ze)), qb_next = q_black(k);
+        __syncthreads();
+        const int zz = zplane(k), pz = zz & 1;
+        if (t < kRbRed) {  // red site of plane k in the tile or its ring
+            const bool wall = S.walls && (k < S.z0 || k > S.z1);
+            const int p = r_p[pz];
+            sred[s3(k)][p] = wall ? sphi[s3(k)][p] : update(sphi, p, k, r_x[pz], r_y, zz, qr);
+        }
+        __syncthreads();
+        const int kb = k - 1;
+        if (kb >= zs) {  // plane kb: black update, and the red values of the tile
+            const int zb = zplane(kb), pb = zb & 1, p = b_p[pb];
+            const unsigned o = (black ? half : 0u) + ((b_xy[pb] + nxy * (unsigned)zb) >> 1);
+            pout[o] = black ? update(sred, p, kb, b_x[pb], b_y, zb, qb) : sred[s3(kb)][p];
+        }
+        if (S.walls && ((k == zs - 1 && zs == S.z0) || (k == ze && ze == S.z1 + 1))) {  // a wall layer
+            const int p = b_p[pz];
+            pout[(black ? half : 0u) + ((b_xy[pz] + nxy * (unsigned)zz) >> 1)] = sphi[s3(k)][p];
+        }
+        __syncthreads();
+        qr = qr_next;
+        qb = qb_next;
+    }
+}
+
+// Whether k_sor_rb covers the lattice: two colours, whole tiles in x and y, and enough
+// planes for its LDS window.
+bool sor_rb_fits(const Scalars& S) {
+    return S.ncolor == 2 && S.nx % kRbTX == 0 && S.ny % kRbTY == 0 && S.nz >= 8 && S.z1 - S.z0 + 1 >= 4;
+}
+
+template <typename T>
+void launch_sor_rb(const Scalars& S, const Fields<T>& F, const double* pin, double* pout, double omega,
+                   hipStream_t st) {
+    const int nzd = S.z1 - S.z0 + 1;
+    const unsigned tiles = (unsigned)(S.nx / kRbTX) * (unsigned)(S.ny / kRbTY);
+    // planes per workgroup: about 2048 workgroups, at least 8 planes each (the window's
+    // two extra planes cost little against them)
+    const int zc = std::max(8, (int)((tiles * (unsigned)nzd + 2047) / 2048));
+    const unsigned chunks = (unsigned)((nzd + zc - 1) / zc), nwork = tiles * chunks;
+    const unsigned nblk = (nwork + 7) / 8 * 8;  // whole XCD rounds; the extra workgroups return
+    hipLaunchKernelGGL(k_sor_rb<T>, dim3(nblk), dim3(kBlock), 0, st, S, F, pin, pout, omega, zc, nwork);
 }
 
 template <typename T>
@@ -2437,7 +2629,8 @@ template <typename T> void launch_field_e(const Scalars& S, const Fields<T>& F, 
     template void launch_mg_prolong_fine<T>(const Scalars&, const Fields<T>&, const MGLevel&, bool, hipStream_t); \
     template void launch_mg_prolong_red_fine<T>(const Scalars&, const Fields<T>&, const MGLevel&, double, double*, \
                                                 hipStream_t);                                                      \
-    template void launch_sor_black_from<T>(const Scalars&, const Fields<T>&, double, const double*, hipStream_t);
+    template void launch_sor_black_from<T>(const Scalars&, const Fields<T>&, double, const double*, hipStream_t); \
+    template void launch_sor_rb<T>(const Scalars&, const Fields<T>&, const double*, double*, double, hipStream_t);
 
 EK_INST(float)
 EK_INST(double)

@@ -54,7 +54,7 @@ class EKObs(ctypes.Structure):
     ]
 
 
-N_KERNELS = 22
+N_KERNELS = 23
 
 
 class EKTiming(ctypes.Structure):

@@ -330,6 +330,47 @@ def test_colour_split_solve_is_bit_identical_to_site_order(case, shape, monkeypa
     b.close()
 
 
+@pytest.mark.parametrize("case,shape", [("walls_fp32", None), ("walls_fp64", (2, 1, 1, 3, 3, 3, 10)),
+                                        ("walls_fp32", (2, 2, 1, 2, 3, 3, 10)), ("colloids_fp32", None),
+                                        ("mixture_fp64", None)])
+def test_one_pass_sweep_is_bit_identical_to_two_passes(case, shape, monkeypatch):
+    """With EK_POISSON_ONE_PASS=1 a lattice sweep of the V-cycle on colour-split fields runs
+    in one pass (k_sor_rb: a z-marching tile with the planes in LDS, writing to a second
+    buffer); by default it runs as the two colour passes in place.  The rows are the same
+    arithmetic in the same order, so the states agree bit for bit, iteration counts
+    included.  Shapes: the default (two one-pass sweeps per cycle), two sweeps before the
+    correction and none after the fused one, and an odd count (two in one pass, the last
+    in two)."""
+    if case == "colloids_fp32":
+        cfg, inp = wl.colloids(shape=(64, 64, 64), count=12, radius=4.0, precision="fp32", seed=11)
+    elif case == "mixture_fp64":
+        cfg, inp = wl.mixture_noise(shape=(64, 32, 32), precision="fp64")
+    else:
+        cfg, inp = wl.walls_interface(shape=(128, 16, 32) if shape else (64, 64, 64), precision=case.split("_")[1])
+    _announce(f"one-pass vs two-pass lattice sweeps: {case} {shape or 'default shape'}")
+    monkeypatch.setenv("EK_POISSON_ONE_PASS", "1")
+    a = ek.EKSim(cfg, inp)
+    monkeypatch.delenv("EK_POISSON_ONE_PASS")
+    b = ek.EKSim(cfg, inp)
+    if shape is not None:
+        for sim in (a, b):
+            sim.set_multigrid(*shape, omega=1.15)
+    a.step(3)
+    b.step(3)
+    for sim in (a, b):
+        sim.set_timing(3)
+    a.step(5)
+    b.step(5)
+    ka, kb = a.kernel_timing(), b.kernel_timing()
+    assert ka["k_sor_rb"][1] > 0 and kb["k_sor_rb"][1] == 0, (ka["k_sor_rb"], kb["k_sor_rb"])
+    for k in ("phi", "rho_a", "rho_b", "n_plus", "n_minus", "ux"):
+        assert np.array_equal(a.field(k), b.field(k)), k
+    oa, ob = a.observables(), b.observables()
+    assert oa["poisson_total"] == ob["poisson_total"] > 0
+    a.close()
+    b.close()
+
+
 def test_cycle_control_meets_tolerance_every_step():
     """The multigrid solve launches the cycles recent solves needed before it reads back the
     start residual; every step must still end below the tolerance, and the count it records
