@@ -46,7 +46,8 @@ def test_autotune_restores_state_and_applies_shape(name):
     print("  " + ", ".join(f"{c}: {t:.3f} ms" for c, t in zip(cands, ms)) + f"  -> {best}", flush=True)
     assert 0 <= best < len(cands)
     assert all(np.isfinite(t) and t > 0 for t in ms)
-    assert ms[best] == min(ms)
+    # the fastest shape, unless an earlier candidate (the default first) is within 1 % of it
+    assert best == next(k for k, t in enumerate(ms) if t <= 1.01 * min(ms))
     for x, y in zip(before, _state(a)):
         assert np.array_equal(x, y)
     o1 = a.observables()
