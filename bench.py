@@ -469,6 +469,34 @@ def run_adjoint(n=96, steps=500, every=50, fd=True):
            "D": float(D.detach()), "fwd_ms": round(1e3 * t_fwd, 1), "fwd_plain_ms": round(1e3 * t_plain, 1),
            "bwd_ms": round(1e3 * t_bwd, 1), "bwd_fwd_ratio": round(t_bwd / t_fwd, 3),
            "grad": {k: float(v) for k, v in g.items()}}
+    # the same workload from an FP32 context: FP32 forward run, FP64 sweep over segments
+    # restarted from its checkpoints
+    cfg32 = replace(cfg, precision="fp32")
+    s32 = ek.EKSim(cfg32, inp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s32.forward_checkpointed(steps, every)
+    torch.cuda.synchronize()
+    t_fwd32 = time.perf_counter() - t0
+    ra32 = torch.from_numpy(s32.field("rho_a")).to(dev).requires_grad_(True)
+    rb32 = torch.from_numpy(s32.field("rho_b")).to(dev).requires_grad_(True)
+    D32 = droplet_deformation(ra32, rb32)
+    D32.backward()
+    adj32 = torch.zeros((2, 19, N), dtype=torch.float64, device=dev)
+    for comp, t in ((0, ra32), (1, rb32)):
+        if t.grad is not None:
+            adj32[comp] = t.grad.reshape(1, N)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grad32, _, _ = s32.adjoint(adj32, adj_n, initial=False)
+    torch.cuda.synchronize()
+    t_bwd32 = time.perf_counter() - t0
+    s32.close()
+    g32 = {"E_z": grad32["E_ext"][2], "eps_ratio": grad32["eps_b"] * cfg.eps_a, "G": grad32["G"]}
+    log(f"adjoint FP32: forward {t_fwd32:.2f} s, backward {t_bwd32:.2f} s")
+    out["fp32"] = {"D": float(D32.detach()), "fwd_ms": round(1e3 * t_fwd32, 1), "bwd_ms": round(1e3 * t_bwd32, 1),
+                   "grad": {k: float(v) for k, v in g32.items()},
+                   "grad_rel_diff_to_fp64": {k: abs(g32[k] - g[k]) / abs(g[k]) for k in g}}
     if fd:
         def D_at(**kw):
             s2 = ek.EKSim(replace(cfg, **kw), inp)

@@ -428,7 +428,13 @@ const char* ek_last_error(const struct ek_ctx* ctx);
  * Shan-Chen, ion-solvation, friction and Kelvin forces, the link fluxes with donor-cell
  * advection, the central-difference field and the Poisson equation, whose potential is
  * the implicit solution: its adjoint is one more solve with the same symmetric operator).
- * FP64 contexts on periodic lattices without particles only (EK_EINVAL otherwise).
+ * Periodic lattices without particles only (EK_EINVAL otherwise).  The transposed
+ * passes are FP64.  An FP32 context runs its own forward steps; its checkpoints are its
+ * states widened to FP64 in an FP64 twin context (built from the same parameters and
+ * fields at each ek_forward_ckpt, same stream), which recomputes every segment in FP64
+ * and reverses it: the gradient of the FP64 step linearised along segments restarted
+ * from the FP32 trajectory.  The twin is held until the next ek_forward_ckpt or
+ * ek_destroy and adds an FP64 context's memory.
  * --------------------------------------------------------------------------------- */
 
 /* Advance nsteps steps (as ek_step) keeping a device checkpoint of the state every

@@ -183,6 +183,7 @@ struct ek_ctx {
         double* gred = nullptr;     // gradient partials per workgroup
         bool valid = false;
     } adj;
+    ek_ctx* shadow = nullptr;  // FP64 twin holding the checkpoints of an FP32 context's reverse mode
 };
 
 // Checkpoint: populations of a and b (2 x 19 N), stored ions (2 N), the potential and the
@@ -1592,12 +1593,16 @@ static ek_status observe_impl(ek_ctx* c, ek_obs* o) {
 }
 
 // ------------------------------------------------------------------------------------
-// Reverse mode: checkpointed forward run and the adjoint sweep (periodic FP64 contexts).
+// Reverse mode: checkpointed forward run and the adjoint sweep (periodic contexts).  The
+// transposed passes are FP64.  An FP32 context runs its forward steps itself; its
+// checkpoints are its states widened to FP64 in an FP64 twin (c->shadow, built from the
+// same parameters at each checkpointed run), whose sweep recomputes every segment in FP64
+// from them and reverses it.  The gradient is then the FP64 map's, linearised along
+// segments that restart from the FP32 trajectory at every checkpoint.
 // ------------------------------------------------------------------------------------
 static ek_status adj_check(ek_ctx* c) {
     if (!c || !c->phi) return EK_ESTATE;
     if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: no reverse mode");
-    if (c->esz != 8) return fail(c, EK_EINVAL, "reverse mode needs an FP64 context");
     if (c->S.walls || c->np > 0) return fail(c, EK_EINVAL, "reverse mode covers periodic lattices without particles");
     if (c->S.polar) return fail(c, EK_EINVAL, "reverse mode does not cover the polarisation source");
     if (c->moment_state) return fail(c, EK_EINVAL, "reverse mode needs stored populations (moment_state = 0)");
@@ -1655,9 +1660,125 @@ static ek_status load_ck(ek_ctx* c, int slot) {
     return EK_OK;
 }
 
+// The FP64 twin of an FP32 context, built afresh from its current parameters (the field
+// included) and fields, with the same V-cycle shape.
+static ek_status shadow_make(ek_ctx* c) {
+    if (c->shadow) (void)ek_destroy(c->shadow);
+    c->shadow = nullptr;
+    const size_t N = c->N;
+    std::vector<double> ra(N), rb(N), np(N), nm(N);
+    EK_TRY(ek_get_field(c, EK_F_RHO_A, ra.data()));
+    EK_TRY(ek_get_field(c, EK_F_RHO_B, rb.data()));
+    EK_TRY(ek_get_field(c, EK_F_N_PLUS, np.data()));
+    EK_TRY(ek_get_field(c, EK_F_N_MINUS, nm.data()));
+    ek_params p64 = c->p;
+    p64.precision = EK_FP64;
+    ek_ctx* sh = nullptr;
+    const ek_status st = ek_init(&p64, ra.data(), rb.data(), np.data(), nm.data(), nullptr, 0, (void*)c->st, &sh);
+    if (st != EK_OK) {
+        const std::string m = sh ? sh->err : std::string();
+        if (sh) (void)ek_destroy(sh);
+        return fail(c, st, "the FP64 twin for reverse mode: " + m);
+    }
+    sh->mg_fine_pre = c->mg_fine_pre;
+    sh->mg_fine_post = c->mg_fine_post;
+    sh->mg_pre = c->mg_pre;
+    sh->mg_post = c->mg_post;
+    sh->mg_tail_pre = c->mg_tail_pre;
+    sh->mg_tail_post = c->mg_tail_post;
+    sh->mg_coarsest = c->mg_coarsest;
+    sh->mg_omega = c->mg_omega;
+    c->shadow = sh;
+    return EK_OK;
+}
+
+// The FP32 context's state widened into its twin: populations (deviations re-referenced to
+// the twin's rho_ref, the rest population with its low part), ions, the potential and its
+// two predecessors, and the host control state of the solver.
+static ek_status shadow_sync(ek_ctx* c) {
+    ek_ctx* sh = c->shadow;
+    const unsigned N = c->N;
+    for (int comp = 0; comp < 2; ++comp)
+        for (int d = 0; d < kQ; ++d) {
+            double* dst = (double*)sh->f[sh->cur][comp] + (size_t)d * N;
+            launch_to_double<float>((const float*)c->f[c->cur][comp] + (size_t)d * N, dst, N,
+                                    weight(d) * (c->S.rref[comp] - sh->S.rref[comp]), c->st);
+            if (d == kRest && c->rlo) launch_add_lo<float>((const float*)c->rlo + (size_t)comp * N, dst, N, c->st);
+        }
+    for (int k = 0; k < 2; ++k)
+        launch_to_double<float>((const float*)c->n[c->cur][k], (double*)sh->n[sh->cur][k], N, 0.0, c->st);
+    EK_HIP(hipGetLastError());
+    EK_TRY(copy_d(c, sh->phi, c->phi, N));
+    EK_TRY(copy_d(c, sh->phi_prev, c->phi_prev, N));
+    EK_TRY(copy_d(c, sh->phi_prev2, c->phi_prev2, N));
+    sh->rate = c->rate;
+    sh->steps = c->steps;
+    sh->ptotal = c->ptotal;
+    sh->ws_order = c->ws_order;
+    sh->ws_since = c->ws_since;
+    sh->rel0_of[2] = c->rel0_of[2];
+    sh->rel0_of[3] = c->rel0_of[3];
+    for (int k = 0; k < 8; ++k) sh->kring[k] = c->kring[k];
+    sh->kpos = c->kpos;
+    sh->kcount = c->kcount;
+    return EK_OK;
+}
+
+// Room for `need` checkpoints and their host records.
+static ek_status ck_alloc(ek_ctx* c, size_t need) {
+    auto& A = c->adj;
+    const size_t N = c->N;
+    if (A.ck_cap < need) {
+        dfree(c, A.ck, A.ck_cap * kCkVals * N * sizeof(double));
+        A.ck = nullptr;
+        A.ck_cap = 0;
+        EK_TRY(dalloc(c, (void**)&A.ck, need * kCkVals * N * sizeof(double)));
+        A.ck_cap = need;
+    }
+    A.ck_rate.assign(need, 0.0);
+    A.ck_steps.assign(need, 0);
+    A.ck_ptotal.assign(need, 0);
+    A.ck_ws.assign(2 * need, 0);
+    A.ck_rel0.assign(2 * need, 0.0);
+    A.ck_kring.assign(8 * need, 0);
+    A.ck_kpos.assign(need, 0);
+    A.valid = false;
+    return EK_OK;
+}
+
+static ek_status forward_ckpt_fp32(ek_ctx* c, int nsteps, int every) {
+    const int nseg = (nsteps + every - 1) / every;
+    c->adj.valid = false;
+    EK_TRY(shadow_make(c));
+    ek_ctx* sh = c->shadow;
+    auto twin = [&](ek_status st) {  // a failure of the twin, reported on the context
+        if (st != EK_OK && st != EK_ENOCONV) c->err = "FP64 twin: " + sh->err;
+        return st;
+    };
+    EK_TRY(twin(ck_alloc(sh, (size_t)nseg + 1)));
+    ek_status worst = EK_OK;
+    for (int g = 0; g < nseg; ++g) {
+        EK_TRY(shadow_sync(c));
+        EK_TRY(twin(save_ck(sh, g)));
+        const ek_status st = step_impl<float>(c, std::min(every, nsteps - g * every));
+        if (st == EK_ENOCONV)
+            worst = st;
+        else if (st != EK_OK)
+            return st;
+    }
+    EK_TRY(shadow_sync(c));
+    EK_TRY(twin(save_ck(sh, nseg)));
+    sh->adj.T = c->adj.T = nsteps;
+    sh->adj.K = c->adj.K = every;
+    sh->adj.nck = c->adj.nck = nseg + 1;
+    sh->adj.valid = c->adj.valid = true;
+    return worst;
+}
+
 extern "C" ek_status ek_forward_ckpt(ek_ctx* c, int32_t nsteps, int32_t every) {
     EK_TRY(adj_check(c));
     if (nsteps < 1 || every < 1) return fail(c, EK_EINVAL, "nsteps and every must be >= 1");
+    if (c->esz == 4) return forward_ckpt_fp32(c, nsteps, every);
     auto& A = c->adj;
     const int nseg = (nsteps + every - 1) / every;
     const size_t need = (size_t)nseg + 1;
@@ -1700,6 +1821,11 @@ extern "C" ek_status ek_adjoint(ek_ctx* c, const double* adj_f, const double* ad
     auto& A = c->adj;
     if (!A.valid) return fail(c, EK_ESTATE, "no checkpointed forward run (ek_forward_ckpt) to reverse");
     if (!adj_f || !adj_n || !grad) return fail(c, EK_EINVAL, "adj_f, adj_n and grad are required");
+    if (c->esz == 4) {  // the FP64 twin holds the checkpoints and runs the sweep
+        const ek_status st = ek_adjoint(c->shadow, adj_f, adj_n, grad, adj_f0, adj_n0);
+        if (st != EK_OK && st != EK_ENOCONV) c->err = "FP64 twin: " + c->shadow->err;
+        return st;
+    }
     const size_t N = c->N;
     if (A.seg_cap < A.K) {
         dfree(c, A.seg, (size_t)A.seg_cap * kSegVals * N * sizeof(double));
@@ -2279,6 +2405,7 @@ extern "C" const char* ek_kernel_name(int32_t k) {
 extern "C" ek_status ek_destroy(ek_ctx* c) {
     if (!c) return EK_OK;
     if (c->in_batch) return fail(c, EK_ESTATE, "replica of a batch: released by ek_batch_destroy");
+    if (c->shadow) (void)ek_destroy(c->shadow);
     if (c->phi) (void)hipStreamSynchronize(c->st);
     resolve_timing(c);
     vcycle_graph_drop(c);

@@ -538,16 +538,17 @@ def _ek_run_function():
 
     class EKRun(torch.autograd.Function):
         """T steps of the method as a differentiable function of (E_z, eps_b / eps_a, G).
-        forward(params, cfg, inputs, nsteps, every) runs a checkpointed forward pass of an
-        FP64 periodic context built from cfg with those three parameters replaced, and
-        returns the fluid densities rho^a, rho^b at the end as (nz, ny, nx) GPU tensors;
-        backward runs the library's adjoint sweep."""
+        forward(params, cfg, inputs, nsteps, every) runs a checkpointed forward pass of a
+        periodic context built from cfg (in its precision) with those three parameters
+        replaced, and returns the fluid densities rho^a, rho^b at the end as (nz, ny, nx)
+        GPU tensors; backward runs the library's adjoint sweep (FP64; for an FP32 context
+        along segments restarted from its FP32 checkpoints)."""
 
         @staticmethod
         def forward(ctx, params, cfg, inputs, nsteps, every):
             from dataclasses import replace
             ez, ratio, G = (float(v) for v in params.detach().cpu().tolist())
-            c2 = replace(cfg, E_ext=(cfg.E_ext[0], cfg.E_ext[1], ez), eps_b=ratio * cfg.eps_a, G=G, precision="fp64")
+            c2 = replace(cfg, E_ext=(cfg.E_ext[0], cfg.E_ext[1], ez), eps_b=ratio * cfg.eps_a, G=G)
             sim = EKSim(c2, inputs)
             sim.forward_checkpointed(nsteps, every)
             ctx.sim, ctx.eps_a = sim, cfg.eps_a

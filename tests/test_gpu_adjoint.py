@@ -159,16 +159,20 @@ def _droplet(n, field):
     return cfg, inp
 
 
-def test_droplet_deformation_gradient_vs_oracle():
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_droplet_deformation_gradient_vs_oracle(precision):
     """dD/d(E_z, eps_b/eps_a, G) of a charged droplet (permittivity ratio 4) after 32
     steps: the adjoint through the autograd wrapper against central differences of the
     FP64 oracle.  Over so few steps the deformation responds weakly to the field, so the
     field is 1e-2 (the full-size run uses 5e-4 over 500 steps), and a uniform drift keeps
     the outer fluid off the upwind switch of the donor-cell advection at u = 0, where
-    finite differences are not derivatives."""
+    finite differences are not derivatives.  FP32: the forward run is FP32 and the sweep
+    reverses FP64 segments restarted from its checkpoints; the bound is 1e-3 (1e-5 in
+    FP64), D itself within 1e-5 of the oracle."""
     import torch
     n, T, K = 16, 32, 8
     cfg, inp = _droplet(n, 1e-2)
+    cfg.precision = precision
     cfg.body_accel = (1e-3, 8e-4, 6e-4)
     print(f"droplet {n}^3, {T} steps: adjoint vs oracle finite differences", flush=True)
     p0 = np.array([cfg.E_ext[2], cfg.eps_b / cfg.eps_a, cfg.G])
@@ -194,8 +198,8 @@ def test_droplet_deformation_gradient_vs_oracle():
 
     D0 = oracle_D(p0)
     Dv = float(D.detach())
-    print(f"  D = {Dv:.12e} (library), {D0:.12e} (oracle)", flush=True)
-    assert abs(D0 - Dv) < 1e-8 * abs(D0) + 1e-12, (D0, Dv)
+    print(f"  D = {Dv:.12e} (library, {precision}), {D0:.12e} (oracle)", flush=True)
+    assert abs(D0 - Dv) < (1e-8 if precision == "fp64" else 1e-5) * abs(D0) + 1e-12, (D0, Dv)
     for k, name in enumerate(("E_z", "eps_b/eps_a", "G")):
         fds = []
         for rel_h in (1e-4, 1e-3):
@@ -207,7 +211,7 @@ def test_droplet_deformation_gradient_vs_oracle():
         rels = [abs(g[k] - fd) / abs(fd) for fd in fds]
         print(f"  dD/d{name}: adjoint {g[k]:.10e}  oracle FD (h 1e-4) {fds[0]:.10e} rel {rels[0]:.2e}, "
               f"(h 1e-3) {fds[1]:.10e} rel {rels[1]:.2e}", flush=True)
-        assert min(rels) < 1e-5, (name, g[k], fds)
+        assert min(rels) < (1e-5 if precision == "fp64" else 1e-3), (name, g[k], fds)
 
 
 def test_adjoint_rejects_unsupported():
@@ -218,12 +222,13 @@ def test_adjoint_rejects_unsupported():
         sim.forward_checkpointed(2, 1)
     assert e.value.status == ek.EK_EINVAL
     sim.close()
-    cfg, inp = _case("bgk", n=8)
     cfg.precision = "fp32"
     sim = ek.EKSim(cfg, inp)
-    with pytest.raises(ek.EKError):
+    with pytest.raises(ek.EKError) as e:
         sim.forward_checkpointed(2, 1)
+    assert e.value.status == ek.EK_EINVAL
     sim.close()
+    cfg, inp = _case("bgk", n=8)
     cfg.precision = "fp64"
     sim = ek.EKSim(cfg, inp)
     z = torch.zeros(2 * 19 * cfg.n_sites, dtype=torch.float64, device="cuda")
