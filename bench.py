@@ -207,6 +207,38 @@ def run_moment_state(workload, precision, n, steps, warmup):
             "bitwise_equal_to_populations_after_5_steps": bool(same)}
 
 
+def run_moving(n, steps, warmup, speed=0.05):
+    """The colloid workload with its spheres projected anew after every step (reproject),
+    each launched at `speed` lattice units per step in a random direction so that sites are
+    covered and uncovered throughout: step rate, the projection's device time per step, and
+    the sites whose solid mark changed, against the same spheres kept on the set-up mask."""
+    import numpy as np
+    from paper_1712_08494_amd import ek
+    res = {}
+    for rp in (False, True):
+        cfg, inp = build_workload("colloids", "fp32", n)
+        cfg.reproject = rp
+        r = np.random.Generator(np.random.PCG64(17))
+        v = r.normal(size=(inp.particles.shape[0], 3))
+        inp.particles[:, 3:6] = speed * v / np.linalg.norm(v, axis=1, keepdims=True)
+        log(f"gpu moving spheres, {cfg.name}, reproject {rp}")
+        sim = ek.EKSim(cfg, inp)
+        solid0 = sim.field("solid")
+        sim.close()
+        dt, kt, _, _, _ = run_gpu(cfg, inp, steps, warmup, kernel_steps=5)
+        key = "reproject" if rp else "set_up_mask"
+        res[key] = {"mlups": round(cfg.n_sites * steps / dt / 1e6, 2), "ms_per_step": round(1e3 * dt / steps, 4)}
+        if rp:
+            ms, cnt = kt.get("k_reproject", (0.0, 0))
+            res[key]["k_reproject_us_per_step"] = round(1e3 * ms / 5, 1) if cnt else None
+            sim = ek.EKSim(cfg, inp)
+            sim.step(warmup + steps)
+            res[key]["sites_converted_over_run"] = int(np.sum(sim.field("solid") != solid0))
+            sim.close()
+    count = inp.particles.shape[0]
+    return {"workload": f"colloids {n}x{n}x{n}, {count} spheres moving at {speed} per step, FP32", **res}
+
+
 def run_fft_compare(n, steps, warmup):
     """The paper's lagged Fourier Poisson scheme against converged multigrid solves on a
     periodic charged droplet (n^3, radius 0.21 n, permittivity ratio 4, FP32): step rate of
@@ -549,6 +581,7 @@ def main():
     ap.add_argument("--error-steps", type=int, default=20)
     ap.add_argument("--no-secondary", action="store_true", help="skip the walls/interface 128^3 legs")
     ap.add_argument("--no-moment-state", action="store_true", help="skip the tau = 1 moment-state run")
+    ap.add_argument("--no-moving", action="store_true", help="skip the moving-colloid (reproject) comparison")
     ap.add_argument("--no-fft", action="store_true", help="skip the lagged Fourier Poisson comparison")
     ap.add_argument("--fft-n", type=int, default=128)
     ap.add_argument("--fft-steps", type=int, default=50)
@@ -647,6 +680,10 @@ def main():
     if not args.no_moment_state:
         moment = run_moment_state("walls_interface", "fp32", 128, 100, 10)
 
+    moving = None
+    if not args.no_moving:
+        moving = run_moving(args.n, 30, 5)
+
     fft = None
     if not args.no_fft:
         fft = run_fft_compare(args.fft_n, args.fft_steps, 5)
@@ -708,6 +745,7 @@ def main():
         "precision_error_vs_oracle": error,
         "secondary": secondary,
         "moment_state": moment,
+        "moving_colloids": moving,
         "lagged_fourier_poisson": fft,
         "batched": batched,
         "adjoint": adjoint,

@@ -76,7 +76,8 @@ struct ek_ctx {
     int32_t* vlist = nullptr;
     int nv = 0;
     int32_t* plist = nullptr;  // sites of the particle path
-    int npl = 0;
+    int npl = 0;               // their number; with moving particles the list's capacity
+    int32_t* npl_dev = nullptr;  // moving particles: the list's length, rebuilt on the device every step
     long long nlinks = 0;
     std::vector<uint8_t> hflags;   // host copy (solid marks for export)
     std::vector<double> hpsis;     // host copy of the solid fraction
@@ -95,6 +96,7 @@ struct ek_ctx {
     int32_t* owner_old = nullptr;
     void* psif_old = nullptr;
     int32_t* rp_origin = nullptr;
+    int32_t *rp_nb = nullptr, *rp_nnb = nullptr;  // particles whose projection boxes meet
     int16_t* rp_cnt = nullptr;
     uint8_t *rp_inside = nullptr, *rp_event = nullptr;
     double *rp_evm = nullptr, *rp_ptot = nullptr;
@@ -340,6 +342,7 @@ static Fields<T> fields(ek_ctx* c) {
     F.nv = c->nv;
     F.plist = c->plist;
     F.npl = c->npl;
+    F.npl_dev = c->S.reproject ? c->npl_dev : nullptr;
     F.pv = c->pv[c->pcur];
     F.red = c->red;
     F.scal = c->scal;
@@ -935,7 +938,8 @@ static ek_status step_rest(ek_ctx* c) {
         EK_HIP(hipMemcpyAsync(c->psif_old, c->psif, N * c->esz, hipMemcpyDeviceToDevice, c->st));
         Reproj<T> P{c->np, c->px[c->pcur], c->pv[c->pcur], c->prad, c->pQ, c->p.particle_rho, c->flags, c->owner,
                     (T*)c->psif, (T*)c->qc, c->flags_old, c->owner_old, (const T*)c->psif_old, c->rp_origin,
-                    c->rp_cnt, c->rp_inside, c->rp_event, c->rp_evm, (T*)c->rp_share, c->rp_ptot};
+                    c->rp_cnt, c->rp_inside, c->rp_event, c->rp_evm, (T*)c->rp_share, c->rp_ptot, c->rp_nb, c->rp_nnb,
+                    c->plist, c->npl_dev};
         launch_reproject<T>(c->S, F, P, c->st);
     }
     EK_HIP(hipGetLastError());
@@ -1100,7 +1104,14 @@ static ek_status allocate_all(ek_ctx* c, const HostGeom& g, int np) {
         EK_TRY(dalloc(c, (void**)&L.az, (size_t)L.n * 8));
     }
     if (!g.vlist.empty()) EK_TRY(dalloc(c, (void**)&c->vlist, g.vlist.size() * 4));
-    if (!g.plist.empty()) EK_TRY(dalloc(c, (void**)&c->plist, g.plist.size() * 4));
+    if (c->S.reproject) {  // room for every box site (the particle-path sites all lie in the boxes)
+        const size_t B3 = (size_t)c->S.rp_box * c->S.rp_box * c->S.rp_box;
+        const size_t cap = std::max(g.plist.size(), std::min((size_t)N, (size_t)np * B3));
+        EK_TRY(dalloc(c, (void**)&c->plist, cap * 4));
+        EK_TRY(dalloc(c, (void**)&c->npl_dev, 4));
+    } else if (!g.plist.empty()) {
+        EK_TRY(dalloc(c, (void**)&c->plist, g.plist.size() * 4));
+    }
     if (np > 0) {
         EK_TRY(dalloc(c, (void**)&c->flags, N));
         EK_TRY(dalloc(c, &c->psif, (size_t)N * es));
@@ -1125,6 +1136,8 @@ static ek_status allocate_all(ek_ctx* c, const HostGeom& g, int np) {
             EK_TRY(dalloc(c, (void**)&c->owner_old, (size_t)N * 4));
             EK_TRY(dalloc(c, &c->psif_old, (size_t)N * es));
             EK_TRY(dalloc(c, (void**)&c->rp_origin, 3 * np * 4));
+            EK_TRY(dalloc(c, (void**)&c->rp_nb, np * np * 4));
+            EK_TRY(dalloc(c, (void**)&c->rp_nnb, np * 4));
             EK_TRY(dalloc(c, (void**)&c->rp_cnt, np * B3 * 2));
             EK_TRY(dalloc(c, (void**)&c->rp_inside, np * B3));
             EK_TRY(dalloc(c, (void**)&c->rp_event, np * B3));
@@ -1212,6 +1225,12 @@ static ek_status init_impl(ek_ctx* c, const double* rho_a, const double* rho_b, 
     if (c->nv > 0) EK_HIP(hipMemcpyAsync(c->vlist, g.vlist.data(), g.vlist.size() * 4, hipMemcpyHostToDevice, c->st));
     c->npl = (int)g.plist.size();
     if (c->npl > 0) EK_HIP(hipMemcpyAsync(c->plist, g.plist.data(), g.plist.size() * 4, hipMemcpyHostToDevice, c->st));
+    if (c->S.reproject) {
+        const int32_t n0 = c->npl;
+        EK_HIP(hipMemcpy(c->npl_dev, &n0, 4, hipMemcpyHostToDevice));
+        const size_t B3 = (size_t)c->S.rp_box * c->S.rp_box * c->S.rp_box;
+        c->npl = (int)std::max(g.plist.size(), std::min((size_t)N, (size_t)np * B3));  // launch size
+    }
     if (colloids) {
         EK_HIP(hipMemcpyAsync(c->flags, g.flags.data(), N, hipMemcpyHostToDevice, c->st));
         std::vector<double> tmp(N);

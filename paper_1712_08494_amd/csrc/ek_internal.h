@@ -65,8 +65,10 @@ struct Fields {
     double* linkdp;          // 6 doubles per particle link: (component, xyz) momentum handed over
     const int32_t* vlist;    // solid sites next to fluid (virtual densities)
     int nv;
-    const int32_t* plist;    // sites that take the particle path (flag bits 0, 1 or 3), ascending
-    int npl;
+    const int32_t* plist;    // sites that take the particle path (flag bits 0, 1 or 3), ascending; with
+                             // moving particles rebuilt on the device after every projection, unordered
+    int npl;                 // its length, or with npl_dev its capacity
+    const int32_t* npl_dev;  // device-held length (moving particles), or null
     const double* pv;        // particle velocities (3 per particle)
     double* red;             // reduction scratch
     double* scal;            // device scalars: [0] source mean, [1..3] rr, ss, sum phi
@@ -252,6 +254,10 @@ struct Reproj {
     double* evm;         // 3 x np x box^3: the particle's momentum change from that site
     T* share;            // 2 N: ion shares (mean density, charge) of a site losing its fluid
     double* ptot;        // np: summed solid fraction of each particle's sites
+    int32_t* nb;         // np x np: per particle, the particles whose boxes meet its box, ascending (itself included)
+    int32_t* nnb;        // np: how many
+    int32_t* plist;      // the context's particle-path list, rebuilt from the boxes
+    int32_t* npl;        // its length (device)
 };
 template <typename T>
 void launch_reproject(const Scalars& S, const Fields<T>& F, const Reproj<T>& P, hipStream_t st);

@@ -2056,26 +2056,13 @@ __global__ __launch_bounds__(kBlock, kForceOcc<T>) void k_force(Scalars S, Field
 template <typename T>
 __global__ __launch_bounds__(kBlock, kForceOcc<T>) void k_force_part(Scalars S, Fields<T> F) {
     const unsigned t = blockIdx.x * kBlock + threadIdx.x;
-    if (t < (unsigned)F.npl) force_body<T, kColloids>(S, F, (unsigned)F.plist[t]);
-}
-
-// Every site, each taking its path by its flags (moving particles change which sites take
-// the particle path, so there is no list).
-template <typename T>
-__global__ __launch_bounds__(kBlock, kForceOcc<T>) void k_force_all(Scalars S, Fields<T> F) {
-    const unsigned i = site_banded(S);
-    if (i >= S.N) return;
-    if ((F.flags[i] & kParticlePath) == 0)
-        force_body<T, kPeriodic>(S, F, i);
-    else
-        force_body<T, kColloids>(S, F, i);
+    const unsigned n = F.npl_dev ? (unsigned)*F.npl_dev : (unsigned)F.npl;
+    if (t < n) force_body<T, kColloids>(S, F, (unsigned)F.plist[t]);
 }
 
 template <typename T> void launch_force(const Scalars& S, const Fields<T>& F, hipStream_t st) {
     const dim3 g(site_blocks(S.N)), b(kBlock);
-    if (S.reproject) {
-        hipLaunchKernelGGL(k_force_all<T>, g, b, 0, st, S, F);
-    } else if (S.colloids) {
+    if (S.colloids) {  // with moving particles the list is sized by its capacity and read on the device
         hipLaunchKernelGGL((k_force<T, kColloids>), g, b, 0, st, S, F);
         if (F.npl > 0)
             hipLaunchKernelGGL((k_force_part<T>), dim3(site_blocks((unsigned)F.npl)), b, 0, st, S, F);
@@ -2211,26 +2198,14 @@ template <typename T> constexpr int kPartOcc = sizeof(T) == 4 ? 3 : kHotOcc<T>;
 template <typename T>
 __global__ __launch_bounds__(kBlock, kPartOcc<T>) void k_fused_part(Scalars S, Fields<T> F) {
     const unsigned t = blockIdx.x * kBlock + threadIdx.x;
-    if (t < (unsigned)F.npl) fused_body<T, kColloids, false>(S, F, (unsigned)F.plist[t]);
-}
-
-// Every site, each taking its path by its flags (moving particles: no site list).
-template <typename T>
-__global__ __launch_bounds__(kBlock, kPartOcc<T>) void k_fused_all(Scalars S, Fields<T> F) {
-    const unsigned i = site_banded(S);
-    if (i >= S.N) return;
-    if ((F.flags[i] & kParticlePath) == 0)
-        fused_body<T, kPeriodic, false>(S, F, i);
-    else
-        fused_body<T, kColloids, false>(S, F, i);
+    const unsigned n = F.npl_dev ? (unsigned)*F.npl_dev : (unsigned)F.npl;
+    if (t < n) fused_body<T, kColloids, false>(S, F, (unsigned)F.plist[t]);
 }
 
 template <typename T> void launch_fused(const Scalars& S, const Fields<T>& F, hipStream_t st) {
     const dim3 g(site_blocks(S.N)), b(kBlock);
     const bool ms = F.ms != nullptr;  // a moment-state context writes it from the first step on
-    if (S.reproject) {
-        hipLaunchKernelGGL(k_fused_all<T>, g, b, 0, st, S, F);
-    } else if (S.colloids) {
+    if (S.colloids) {  // with moving particles the list is sized by its capacity and read on the device
         hipLaunchKernelGGL((k_fused<T, kColloids, false>), g, b, 0, st, S, F);
         if (F.npl > 0)
             hipLaunchKernelGGL((k_fused_part<T>), dim3(site_blocks((unsigned)F.npl)), b, 0, st, S, F);

@@ -14,14 +14,14 @@
 //
 // Layout.  Every particle owns a box of rp_box^3 sites centred on its new position, wide
 // enough to hold every site whose geometry the step can change (the move is below one site
-// per step) and their neighbours.  One workgroup per particle walks its box; sites in
-// several boxes are resolved from all boxes alike (the owner is the lowest particle index
-// with a covered sub-cell, a site is solid if its centre is inside any particle), so every
-// workgroup writes the same values there.  Each conversion is handled by exactly one
-// workgroup (the new owner for a covered site, the old owner for an uncovered one), and
-// per-site work that adds (ion shares, charge) by the lowest-indexed particle whose box
-// holds the site.  Per-particle sums run in a fixed tree order, so results are
-// deterministic.
+// per step) and their neighbours.  A few workgroups per particle walk its box, one thread
+// per box site; sites in several boxes are resolved from all boxes that meet (the owner is
+// the lowest particle index with a covered sub-cell, a site is solid if its centre is
+// inside any particle), so every thread writes the same values there.  Each conversion is
+// handled by exactly one thread (of the new owner's box for a covered site, of the old
+// owner's for an uncovered one), and per-site work that adds (ion shares, charge) by the
+// lowest-indexed particle whose box holds the site.  Per-particle sums run in one
+// workgroup per particle in a fixed tree order, so results are deterministic.
 #include "ek_device.h"
 
 namespace ek {
@@ -55,11 +55,25 @@ __device__ __forceinline__ int box_index(const Scalars& S, const int32_t* origin
     return ox + B * (oy + B * oz);
 }
 
-// The lowest particle index whose box holds the site.
-__device__ __forceinline__ int first_box(const Scalars& S, const int32_t* origin, int np, int x, int y, int z) {
-    for (int j = 0; j < np; ++j)
-        if (box_index(S, origin, j, x, y, z) >= 0) return j;
-    return np;
+// Whether the boxes of particles a and j share a site: along every axis the circular
+// distance between their lowest corners is below the box side.
+__device__ __forceinline__ bool boxes_meet(const Scalars& S, const int32_t* origin, int a, int j) {
+    const int n[3] = {S.nx, S.ny, S.nz};
+    for (int k = 0; k < 3; ++k) {
+        const int d = ((origin[3 * a + k] - origin[3 * j + k]) % n[k] + n[k]) % n[k];
+        if (d >= S.rp_box && n[k] - d >= S.rp_box) return false;
+    }
+    return true;
+}
+
+// The lowest particle index whose box holds the site (x, y, z) of particle a's box: every
+// such box meets a's box, so only those (ascending in P.nb) are scanned.
+template <typename T>
+__device__ __forceinline__ int first_box(const Scalars& S, const Reproj<T>& P, int a, int x, int y, int z) {
+    const int32_t* nb = P.nb + (size_t)a * P.np;
+    for (int m = 0; m < P.nnb[a]; ++m)
+        if (box_index(S, P.origin, nb[m], x, y, z) >= 0) return nb[m];
+    return P.np;
 }
 
 __device__ __forceinline__ bool wall_layer(const Scalars& S, int z) { return S.walls && (z == 0 || z == S.nz - 1); }
@@ -85,15 +99,13 @@ __global__ __launch_bounds__(kBlock) void k_rp_mark(Scalars S, Reproj<T> P) {
 #pragma clang fp contract(off)
     const int a = blockIdx.x;
     const double X = P.x[3 * a], Y = P.x[3 * a + 1], Z = P.x[3 * a + 2], R = P.rad[a];
-    if (threadIdx.x == 0) {
-        P.origin[3 * a] = (int)floor(X) - S.rp_half;
-        P.origin[3 * a + 1] = (int)floor(Y) - S.rp_half;
-        P.origin[3 * a + 2] = (int)floor(Z) - S.rp_half;
-    }
-    __syncthreads();
+    // every workgroup of the particle derives the box corner; the first one stores it
+    const int32_t org[3] = {(int)floor(X) - S.rp_half, (int)floor(Y) - S.rp_half, (int)floor(Z) - S.rp_half};
+    if (blockIdx.y == 0 && threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) P.origin[3 * a + k] = org[k];
     const int B3 = S.rp_box * S.rp_box * S.rp_box, h = S.subs;
-    for (int t = threadIdx.x; t < B3; t += blockDim.x) {
-        const BoxSite s = box_site(S, P.origin, a, t);
+    for (int t = blockIdx.y * kBlock + threadIdx.x; t < B3; t += kBlock * gridDim.y) {
+        const BoxSite s = box_site(S, org, 0, t);
         const double dx = min_image((double)s.x - X, S.nx), dy = min_image((double)s.y - Y, S.ny),
                      dz = min_image((double)s.z - Z, S.nz);
         const double d2 = dx * dx + dy * dy + dz * dz;
@@ -120,6 +132,19 @@ __global__ __launch_bounds__(kBlock) void k_rp_mark(Scalars S, Reproj<T> P) {
     }
 }
 
+// Pass 1b: for each particle, the particles whose boxes meet its own, in ascending order.
+// Only they can hold a site of its box, so the later passes scan them instead of every box.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rp_pairs(Scalars S, Reproj<T> P) {
+    const int a = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    if (a == 0) *P.npl = 0;  // the particle-path list is rebuilt by k_rp_list
+    int m = 0;
+    for (int j = 0; j < P.np; ++j)
+        if (boxes_meet(S, P.origin, a, j)) P.nb[(size_t)a * P.np + m++] = j;
+    P.nnb[a] = m;
+}
+
 // Pass 2: the new solid mark, owner and fluid fraction of every box site, from all boxes.
 // Wall layers keep theirs.  Bits 1-3 of the flags are recomputed in pass 5.
 template <typename T>
@@ -127,12 +152,14 @@ __global__ __launch_bounds__(kBlock) void k_rp_resolve(Scalars S, Reproj<T> P) {
     const int a = blockIdx.x;
     const int B3 = S.rp_box * S.rp_box * S.rp_box;
     const double cells = (double)S.subs * S.subs * S.subs;
-    for (int t = threadIdx.x; t < B3; t += blockDim.x) {
+    for (int t = blockIdx.y * kBlock + threadIdx.x; t < B3; t += kBlock * gridDim.y) {
         const BoxSite s = box_site(S, P.origin, a, t);
         if (wall_layer(S, s.z)) continue;
         int own = -1, c = 0;
         uint8_t solid = 0;
-        for (int j = 0; j < P.np; ++j) {
+        const int32_t* nb = P.nb + (size_t)a * P.np;
+        for (int m = 0; m < P.nnb[a]; ++m) {  // ascending: the lowest covering index owns the site
+            const int j = nb[m];
             const int tj = box_index(S, P.origin, j, s.x, s.y, s.z);
             if (tj < 0) continue;
             const size_t k = (size_t)j * B3 + tj;
@@ -155,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_rp_convert(Scalars S, Fields<T> F, R
     const int a = blockIdx.x;
     const int B3 = S.rp_box * S.rp_box * S.rp_box;
     const size_t N = S.N;
-    for (int t = threadIdx.x; t < B3; t += blockDim.x) {
+    for (int t = blockIdx.y * kBlock + threadIdx.x; t < B3; t += kBlock * gridDim.y) {
         const BoxSite s = box_site(S, P.origin, a, t);
         const size_t k = (size_t)a * B3 + t;
         P.event[k] = 0;
@@ -232,9 +259,9 @@ __global__ __launch_bounds__(kBlock) void k_rp_ions(Scalars S, Fields<T> F, Repr
     const int a = blockIdx.x;
     const int B3 = S.rp_box * S.rp_box * S.rp_box;
     const size_t N = S.N;
-    for (int t = threadIdx.x; t < B3; t += blockDim.x) {
+    for (int t = blockIdx.y * kBlock + threadIdx.x; t < B3; t += kBlock * gridDim.y) {
         const BoxSite s = box_site(S, P.origin, a, t);
-        if (wall_layer(S, s.z) || first_box(S, P.origin, P.np, s.x, s.y, s.z) != a) continue;
+        if (wall_layer(S, s.z) || first_box(S, P, a, s.x, s.y, s.z) != a) continue;
         const unsigned i = s.i;
         const Nbr o = make_nbr(s.x, s.y, s.z, S);
         auto gives = [&](unsigned j, int zj) {
@@ -308,9 +335,9 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rp_finish(Scalars S, Reproj<T> P) {
     const int a = blockIdx.x;
     const int B3 = S.rp_box * S.rp_box * S.rp_box;
-    for (int t = threadIdx.x; t < B3; t += blockDim.x) {
+    for (int t = blockIdx.y * kBlock + threadIdx.x; t < B3; t += kBlock * gridDim.y) {
         const BoxSite s = box_site(S, P.origin, a, t);
-        if (first_box(S, P.origin, P.np, s.x, s.y, s.z) != a) continue;
+        if (first_box(S, P, a, s.x, s.y, s.z) != a) continue;
         const unsigned i = s.i;
         const int own = P.owner[i];
         const double psis = 1.0 - (double)P.psif[i];
@@ -329,16 +356,36 @@ __global__ __launch_bounds__(kBlock) void k_rp_finish(Scalars S, Reproj<T> P) {
     }
 }
 
+// Pass 7: the particle-path sites (flag bits 0, 1 or 3), gathered from the boxes (each
+// site by the lowest-indexed box that holds it) into the context's list, in no particular
+// order: every such site lies in a box (a box reaches four sites beyond its sphere), and
+// the list kernels handle each listed site by itself.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rp_list(Scalars S, Reproj<T> P) {
+    const int a = blockIdx.x;
+    const int B3 = S.rp_box * S.rp_box * S.rp_box;
+    for (int t = blockIdx.y * kBlock + threadIdx.x; t < B3; t += kBlock * gridDim.y) {
+        const BoxSite s = box_site(S, P.origin, a, t);
+        if ((P.flags[s.i] & (1u | 2u | 8u)) == 0 || first_box(S, P, a, s.x, s.y, s.z) != a) continue;
+        P.plist[atomicAdd(P.npl, 1)] = (int32_t)s.i;
+    }
+}
+
 template <typename T>
 void launch_reproject(const Scalars& S, const Fields<T>& F, const Reproj<T>& P, hipStream_t st) {
     if (P.np <= 0) return;
-    const dim3 g(P.np), b(kBlock);
-    hipLaunchKernelGGL(k_rp_mark<T>, g, b, 0, st, S, P);
-    hipLaunchKernelGGL(k_rp_resolve<T>, g, b, 0, st, S, P);
-    hipLaunchKernelGGL(k_rp_convert<T>, g, b, 0, st, S, F, P);
-    hipLaunchKernelGGL(k_rp_ions<T>, g, b, 0, st, S, F, P);
+    // the per-site passes split each box over a few workgroups (one per particle would
+    // leave most of the chip idle with a few hundred particles); the per-particle sums keep one
+    const int B3 = S.rp_box * S.rp_box * S.rp_box;
+    const dim3 g(P.np), gs(P.np, std::min(8, (B3 + 4 * kBlock - 1) / (4 * kBlock))), b(kBlock);
+    hipLaunchKernelGGL(k_rp_mark<T>, gs, b, 0, st, S, P);
+    hipLaunchKernelGGL(k_rp_pairs<T>, g, dim3(64), 0, st, S, P);
+    hipLaunchKernelGGL(k_rp_resolve<T>, gs, b, 0, st, S, P);
+    hipLaunchKernelGGL(k_rp_convert<T>, gs, b, 0, st, S, F, P);
+    hipLaunchKernelGGL(k_rp_ions<T>, gs, b, 0, st, S, F, P);
     hipLaunchKernelGGL(k_rp_sum<T>, g, b, 0, st, S, P);
-    hipLaunchKernelGGL(k_rp_finish<T>, g, b, 0, st, S, P);
+    hipLaunchKernelGGL(k_rp_finish<T>, gs, b, 0, st, S, P);
+    hipLaunchKernelGGL(k_rp_list<T>, gs, b, 0, st, S, P);
 }
 
 template void launch_reproject<float>(const Scalars&, const Fields<float>&, const Reproj<float>&, hipStream_t);

@@ -173,3 +173,44 @@ def test_cfg5_dG_difference_quotients_converge_to_the_adjoint():
         print(f"  relative step {r:.0e}: FD {fd:.6e}, adjoint {g:.6e}, rel {rel[r]:.2e}", flush=True)
     assert rel[1e-4] > 0.1                       # the quotient across many branch flips
     assert max(rel[1e-5], rel[1e-6], rel[1e-7]) < 1e-2
+
+
+def test_colloids_256_moving_reprojected():
+    """The 256^3 colloid workload with its spheres projected anew every step (reproject),
+    each sphere launched at 0.05 lattice units per step (slowed by the fluid's drag, it
+    moves up to about one site in 30 steps) so that it covers and uncovers many sites.  The ion totals are conserved (a
+    covered site's ions go to its fluid neighbours), the solid volume follows the spheres,
+    nothing turns non-finite or negative, and two runs agree bit for bit."""
+    cfg, inp = wl.colloids(n=256, precision="fp32")
+    cfg.reproject = True
+    r = np.random.Generator(np.random.PCG64(17))
+    v = r.normal(size=(inp.particles.shape[0], 3))
+    inp.particles[:, 3:6] = 0.05 * v / np.linalg.norm(v, axis=1, keepdims=True)
+    print(f"colloids 256^3, {inp.particles.shape[0]} spheres moving at 0.05, reprojected, FP32, 30 steps", flush=True)
+    vol = (4.0 / 3.0 * np.pi * inp.particles[:, 6] ** 3).sum()
+    runs = []
+    for rep in range(2):
+        sim = ek.EKSim(cfg, inp)
+        o0 = sim.observables()
+        solid0 = sim.field("solid")
+        sim.step(30)
+        o = sim.observables()
+        solid = sim.field("solid")
+        moved = int(np.sum(solid != solid0))
+        print(f"  sites whose solid mark changed: {moved}", flush=True)
+        assert moved > 1000
+        for k in ("sum_n_plus", "sum_n_minus"):
+            assert abs(o[k] - o0[k]) <= 1e-5 * abs(o0[k]), (k, o0[k], o[k])
+        assert o["nonfinite"] == 0 and o["negative_ions"] == 0
+        psis = sim.field("psi_s")
+        assert abs(psis.sum() - vol) < 0.03 * vol, (psis.sum(), vol)
+        p = sim.particles()
+        d = p[:, 0:3] - inp.particles[:, 0:3]
+        d -= np.array([cfg.nx, cfg.ny, cfg.nz]) * np.round(d / np.array([cfg.nx, cfg.ny, cfg.nz]))
+        dist = np.linalg.norm(d, axis=1)
+        print(f"  displacement: mean {dist.mean():.3f}, max {dist.max():.3f} sites", flush=True)
+        assert np.all(np.isfinite(p)) and dist.max() > 0.5  # slowed by the fluid's drag
+        runs.append((sim.field("n_plus"), sim.field("rho_a"), sim.field("phi"), p))
+        sim.close()
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
