@@ -454,7 +454,8 @@ ek_status ek_forward_ckpt(struct ek_ctx* ctx, int32_t nsteps, int32_t every);
    state at the start of the run.  Each segment of `every` steps is recomputed from its
    checkpoint (device memory `every` x 41 N doubles) and reversed step by step; every
    reverse step solves the adjoint Poisson equation to the context's Poisson tolerance.
-   On return the context holds the state at the end of the run again.  Synchronises.
+   On return the context holds the state at the end of the run again (an FP32 context
+   never leaves it: its FP64 twin does the recomputing).  Synchronises.
    Errors: EK_ESTATE (no checkpointed run), EK_EINVAL, EK_ENOMEM, EK_ENOCONV (an
    adjoint solve stopped at maxit; the gradient is still returned). */
 ek_status ek_adjoint(struct ek_ctx* ctx, const double* adj_f, const double* adj_n, double* grad, double* adj_f0,
