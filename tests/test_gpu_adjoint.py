@@ -236,6 +236,15 @@ def test_adjoint_rejects_unsupported():
         sim.adjoint(z, torch.zeros(2 * cfg.n_sites, dtype=torch.float64, device="cuda"))
     assert e.value.status == ek.EK_ESTATE
     sim.close()
+    # an FP32 context's checkpoints (held by its FP64 twin) are dropped with a new field
+    cfg.precision = "fp32"
+    sim = ek.EKSim(cfg, inp)
+    sim.forward_checkpointed(2, 1)
+    sim.set_field((0.0, 0.0, 1e-3))
+    with pytest.raises(ek.EKError) as e:
+        sim.adjoint(z, torch.zeros(2 * cfg.n_sites, dtype=torch.float64, device="cuda"))
+    assert e.value.status == ek.EK_ESTATE
+    sim.close()
 
 
 def test_recompute_is_exact_across_checkpoint_intervals():
