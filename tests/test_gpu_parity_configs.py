@@ -119,7 +119,8 @@ def _closed_form_deviation(cfg, ra_z, npl, nmi):
     fl = (z >= 1) & (z <= nz - 2)
     far = (np.abs(z - zi) > 5) & fl
     deep = (np.abs(z - zi) > 3 / kap) & fl
-    rel = np.maximum(np.abs(npl - ep) / ep, np.abs(nmi - em) / em)
+    rel = np.zeros(nz)                    # the wall layers (z = 0, nz - 1) hold no ions
+    rel[fl] = np.maximum(np.abs(npl[fl] - ep[fl]) / ep[fl], np.abs(nmi[fl] - em[fl]) / em[fl])
     return float(rel[far].max()), float(rel[deep].max())
 
 
