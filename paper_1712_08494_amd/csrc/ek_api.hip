@@ -125,8 +125,9 @@ struct ek_ctx {
     double mg_omega = 1.2;  // relaxation of the smoothing sweeps (1: Gauss-Seidel)
     // One V-cycle captured as a HIP graph and replayed for each cycle of a solve (one host
     // call instead of ~40 launches).  It is captured with the context's own charge and
-    // potential buffers and used only while they are the ones in place; per-sweep timing
-    // (level 2) and a changed cycle shape fall back to direct launches / a new capture.
+    // potential buffers (or their colour-split copies) and used only while they are the ones
+    // in place; per-sweep timing (level 2) and a changed cycle shape fall back to direct
+    // launches / a new capture.
     hipStream_t cap_st = nullptr;
     hipGraph_t vc_graph = nullptr;
     hipGraphExec_t vc_exec = nullptr;
@@ -135,6 +136,10 @@ struct ek_ctx {
     void* qs = nullptr;
     double* blk = nullptr;   // black values between the fused interpolation + red pass and the black pass
     double* phi_own = nullptr;
+    // Set by the reverse sweep around its adjoint solve: the adjoint potential and its
+    // source stand in for phi and q, and the solve runs like one of the own potential
+    // (colour-split copies, the captured cycle, the cycle-count floor of its own history).
+    bool adj_solve = false;
     bool vc_off = false;
     bool vc_split = false;  // layout the captured V-cycle graph works on
     int kring[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // V-cycles of the last own multigrid solves
@@ -192,7 +197,7 @@ struct ek_ctx {
 // two previous potentials (the warm start of the next solve).  Segment state: populations, ions
 // and the potential solved in that step.  Adjoint fields: dL/df (two parities x two
 // components x 19 N), dL/dn (two parities x 2 N) and the intermediates of AdjFields.
-constexpr size_t kCkVals = 2 * kQ + 5, kSegVals = 2 * kQ + 3, kAdjVals = 4 * kQ + 4 + 6 + 3 + 3 + 2 + 3 + 2 + 1 + 1 + 1;
+constexpr size_t kCkVals = 2 * kQ + 5, kSegVals = 2 * kQ + 3, kAdjVals = 4 * kQ + 4 + 6 + 3 + 3 + 2 + 3 + 2 + 1 + 1 + 1 + 2;
 
 #define EK_HIP(call)                                                                             \
     do {                                                                                         \
@@ -655,12 +660,17 @@ static void vcycle_graph_drop(ek_ctx* c) {
     c->vc_graph = nullptr;
 }
 
+// A solve of the context's own potential and charge, or the reverse sweep's adjoint solve.
+static bool own_solve(const ek_ctx* c) {
+    return (c->phi == c->phi_own && c->q == c->q_own) || c->adj_solve;
+}
+
 // k V-cycles: graph replays when possible, direct launches otherwise.  The graph is
 // captured (and replayed) only for the context's own potential and charge, in the layout
 // (colour-split or site order) it was captured with.
 template <typename T>
 static ek_status run_cycles(ek_ctx* c, Fields<T>& F, bool split, int k) {
-    const bool own = c->phi == c->phi_own && c->q == c->q_own;
+    const bool own = own_solve(c);
     if (own && c->vc_exec && c->vc_split != split) vcycle_graph_drop(c);  // other solves launch directly
     if (c->timing < 2 && own && !c->vc_off && !c->vc_exec) {
         if (!c->cap_st) EK_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
@@ -707,7 +717,7 @@ static ek_status poisson_solve(ek_ctx* c, double tol, int maxit, int* iters_out,
     Timer tm(c, EK_T_POISSON);
     Fields<T> F = fields<T>(c);
     const bool use_mg = !c->mg.empty();
-    const bool own = c->phi == c->phi_own && c->q == c->q_own;
+    const bool own = own_solve(c);
     // a multigrid solve of the context's own potential runs on colour-split copies of the
     // potential and charge; the gauge kernel writes the result back in site order
     const bool split = c->phis && use_mg && own;
@@ -1881,16 +1891,32 @@ extern "C" ek_status ek_adjoint(ek_ctx* c, const double* adj_f, const double* ad
     AF.aeps = p; p += N;
     AF.rhs = p; p += N;
     double* mu = p; p += N;
+    double* mu1 = p; p += N;  // the adjoint potentials of the two reverse steps before
+    double* mu2 = p; p += N;
     AF.mu = mu;
     AF.gred = A.gred;
 
     EK_HIP(hipMemsetAsync(A.gred, 0, (size_t)c->nblk * kRedSlots * sizeof(double), c->st));
-    EK_HIP(hipMemsetAsync(mu, 0, N * sizeof(double), c->st));
+    EK_HIP(hipMemsetAsync(mu, 0, 3 * N * sizeof(double), c->st));  // mu, mu1, mu2
     EK_TRY(copy_d(c, lf[0][0], adj_f, kQ * N));
     EK_TRY(copy_d(c, lf[0][1], adj_f + kQ * N, kQ * N));
     EK_TRY(copy_d(c, ln[0][0], adj_n, N));
     EK_TRY(copy_d(c, ln[0][1], adj_n + N, N));
     const double rate_fwd = c->rate;
+    // The adjoint solves keep a cycle rate and cycle counts of their own, carried from one
+    // reverse step to the next across segments (each recomputed segment starts from its
+    // checkpoint's), so the sweep does not depend on the checkpoint interval.
+    struct {
+        double rate;
+        int kring[8], kpos, kcount;
+    } hadj = {rate_fwd, {0, 0, 0, 0, 0, 0, 0, 0}, 0, 0};
+    auto swap_hist = [&]() {
+        std::swap(c->rate, hadj.rate);
+        for (int k = 0; k < 8; ++k) std::swap(c->kring[k], hadj.kring[k]);
+        std::swap(c->kpos, hadj.kpos);
+        std::swap(c->kcount, hadj.kcount);
+    };
+    int nadj = 0;  // adjoint solves so far
     int la = 0;
     ek_status worst = EK_OK;
     double g[kAdjSlots];
@@ -1939,12 +1965,23 @@ extern "C" ek_status ek_adjoint(ek_ctx* c, const double* adj_f, const double* ad
                 launch_source_mean(c->S, c->red, c->nblk, c->scal, c->st);
                 EK_HIP(hipGetLastError());
                 // adjoint Poisson equation M mu = dL/dphi with the same solver: the source and
-                // the unknown are swapped in for the charge and the potential
+                // the unknown are swapped in for the charge and the potential.  Warm start: mu
+                // varies smoothly from one reverse step to the next, so the start is extrapolated
+                // in time from the solutions known so far (quadratic once there are three).
+                {
+                    EK_KT(EK_K_EXTRAPOLATE);
+                    launch_phi_extrapolate(c->S, mu, mu1, mu2, nadj >= 3 ? 3 : (nadj >= 2 ? 2 : 1), c->st);
+                }
+                ++nadj;
                 void* q_fwd = c->q;
                 double* phi_fwd = c->phi;
                 c->q = AF.rhs;
                 c->phi = mu;
+                c->adj_solve = true;
+                swap_hist();
                 const ek_status ps = poisson_solve<double>(c, c->p.poisson_tol, c->p.poisson_maxit, nullptr, nullptr);
+                swap_hist();
+                c->adj_solve = false;
                 c->q = q_fwd;
                 c->phi = phi_fwd;
                 if (ps == EK_ENOCONV)
@@ -1970,6 +2007,7 @@ extern "C" ek_status ek_adjoint(ek_ctx* c, const double* adj_f, const double* ad
         return EK_OK;
     };
     const ek_status sst = sweep();
+    c->adj_solve = false;
     // leave the context at the end of the forward run, also after a failed sweep
     const ek_status lst = load_ck(c, A.nck - 1);
     c->rate = rate_fwd;
