@@ -447,11 +447,14 @@ def droplet_deformation(ra, rb, background=0.1):
     return (b - a) / (b + a)
 
 
-def run_adjoint(n=96, steps=500, every=50, fd=True):
+def run_adjoint(n=96, steps=500, every=50, fd=True, tune=100):
     """Reverse mode on the differentiation workload: a charged droplet (radius 20 in a
     periodic 96^3 box, permittivity ratio 4, E_z = 5e-4, FP64), 500 steps with a
     checkpoint every 50, and the gradient of its deformation with respect to (E_z,
-    eps_b/eps_a, G) by the adjoint sweep, next to central differences of GPU runs."""
+    eps_b/eps_a, G) by the adjoint sweep, next to central differences of GPU runs.
+    With tune > 0 the V-cycle autotuner first picks the shape for this workload (that many
+    trial steps per candidate, after 20 steps from the initial state); every timed run,
+    forward and reverse, uses it."""
     import torch
     from dataclasses import replace
     from paper_1712_08494_amd import ek
@@ -461,17 +464,34 @@ def run_adjoint(n=96, steps=500, every=50, fd=True):
     cfg.poisson_tol = 1e-10
     N = cfg.n_sites
     log(f"adjoint: droplet {n}^3, {steps} steps, checkpoints every {every}")
-    sim = ek.EKSim(cfg, inp)
+    shape, tuned = None, None
+    if tune:
+        st = ek.EKSim(cfg, inp)
+        st.step(20)
+        best, cands, ms = st.autotune_multigrid(tune)
+        st.close()
+        shape = cands[best]
+        tuned = {"shape": list(shape[0]), "omega": shape[1], "ms_per_step": round(ms[best], 4),
+                 "default_ms_per_step": round(ms[0], 4)}
+        log(f"adjoint: autotuned V-cycle {shape} ({ms[best]:.3f} ms/step, default {ms[0]:.3f})")
+
+    def new_sim(c):
+        s = ek.EKSim(c, inp)
+        if shape is not None:
+            s.set_multigrid(*shape[0], omega=shape[1])
+        return s
+
+    sim = new_sim(cfg)
     sim.step(2)
     sim.close()  # warm the library and the allocator
-    sim = ek.EKSim(cfg, inp)
+    sim = new_sim(cfg)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     sim.close()
-    sim = ek.EKSim(cfg, inp)
+    sim = new_sim(cfg)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.forward_checkpointed(steps, every)
@@ -500,11 +520,11 @@ def run_adjoint(n=96, steps=500, every=50, fd=True):
            "objective": "deformation (b - a)/(b + a) from second moments of the b excess",
            "D": float(D.detach()), "fwd_ms": round(1e3 * t_fwd, 1), "fwd_plain_ms": round(1e3 * t_plain, 1),
            "bwd_ms": round(1e3 * t_bwd, 1), "bwd_fwd_ratio": round(t_bwd / t_fwd, 3),
-           "grad": {k: float(v) for k, v in g.items()}}
+           "grad": {k: float(v) for k, v in g.items()}, "multigrid_autotune": tuned}
     # the same workload from an FP32 context: FP32 forward run, FP64 sweep over segments
     # restarted from its checkpoints
     cfg32 = replace(cfg, precision="fp32")
-    s32 = ek.EKSim(cfg32, inp)
+    s32 = new_sim(cfg32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s32.forward_checkpointed(steps, every)
