@@ -615,8 +615,9 @@ def main():
     ap.add_argument("--batched-tune-residual", type=float, default=1e-8,
                     help="autotune the batch for this worst relative residual (0: fixed --batched-cycles)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode leg")
-    ap.add_argument("--autotune", type=int, default=0,
-                    help="after the warm-up, let the library pick the V-cycle shape (trial steps per candidate)")
+    ap.add_argument("--autotune", type=int, default=100,
+                    help="after the warm-up of the headline run and of its FP64 twin, let the library pick the "
+                         "V-cycle shape (trial steps per candidate; 0: the default shape)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size three times (byte-counter scale)")
     args = ap.parse_args()
@@ -672,12 +673,12 @@ def main():
                  "mean_displacement_since_init": [ob1[f"drift_{c}"] for c in "xyz"],
                  "mobility_along_field": v[0] / E[0] if E[0] else None}
 
-    fp64 = None
+    fp64, tuned64 = None, None
     if not args.no_fp64 and args.precision == "fp32":
         cfg64, inp64 = build_workload(args.workload, "fp64", args.n)
         steps64 = max(10, args.steps // 2)
         log("gpu fp64 run for the FP32/FP64 speedup")
-        dt64, _, _, _, _ = run_gpu(cfg64, inp64, steps64, args.warmup, kernel_steps=0)
+        dt64, _, _, _, tuned64 = run_gpu(cfg64, inp64, steps64, args.warmup, kernel_steps=0, autotune=args.autotune)
         fp64 = N * steps64 / dt64 / 1e6
         log(f"gpu fp64: {1e3 * dt64 / steps64:.3f} ms/step")
 
@@ -762,6 +763,7 @@ def main():
         "electrophoretic_drift": drift,
         "fp64_mlups": round(fp64, 2) if fp64 else None,
         "fp32_fp64_speedup": round(mlups / fp64, 3) if fp64 else None,
+        "fp64_multigrid_autotune": tuned64,
         "precision_error_vs_oracle": error,
         "secondary": secondary,
         "moment_state": moment,
