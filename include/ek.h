@@ -453,7 +453,9 @@ ek_status ek_forward_ckpt(struct ek_ctx* ctx, int32_t nsteps, int32_t every);
    adj_f0, adj_n0 (device, optional, NULL to skip): the same sensitivities for the
    state at the start of the run.  Each segment of `every` steps is recomputed from its
    checkpoint (device memory `every` x 41 N doubles) and reversed step by step; every
-   reverse step solves the adjoint Poisson equation to the context's Poisson tolerance.
+   reverse step solves the adjoint Poisson equation to the context's Poisson tolerance
+   (same solver and V-cycle shape, started from the adjoint potentials of the previous
+   reverse steps extrapolated in time).
    On return the context holds the state at the end of the run again (an FP32 context
    never leaves it: its FP64 twin does the recomputing).  Synchronises.
    Errors: EK_ESTATE (no checkpointed run), EK_EINVAL, EK_ENOMEM, EK_ENOCONV (an
